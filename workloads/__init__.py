@@ -1,0 +1,343 @@
+"""Seeded synthetic workloads for the two-phase Cahn-Hilliard Navier-Stokes step.
+
+This module is shared by the CPU oracle, the GPU tests and the benchmark.  It
+holds only problem *definitions* (grid, physical parameters, step count) and
+initial-condition generators; none of the time-step arithmetic lives here.
+
+Conventions
+-----------
+* Non-dimensionalisation follows the paper's governing-equations section: the
+  "+" fluid is the reference, so rho_plus = eta_plus = 1 and the mixture maps
+  are rho(phi) = alpha*phi + beta, eta(phi) = gamma*phi + xi.
+* phi = +1 is the carrier fluid, phi = -1 the drop / bubble.
+* Arrays are numpy float64, C order, x fastest: shape (ny, nx) in 2D and
+  (nz, ny, nx) in 3D.  Face arrays of axis a have the same shape as the cell
+  arrays; entry c holds the face between cell c - e_a and cell c.  On a walled
+  axis the entry with index 0 along that axis is the wall face (always zero for
+  the normal velocity) and the opposite wall face is not stored.
+* Interface profiles use the flat equilibrium of the double-well energy,
+  phi = tanh(d / (sqrt(2) Cn)), with d the signed distance (positive in the
+  carrier).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+PERIODIC = "periodic"
+WALL = "wall"
+
+
+@dataclasses.dataclass
+class Props:
+    """Physical and numerical parameters of one problem (non-dimensional).
+
+    rho_minus / eta_minus are the density / viscosity of the phi=-1 fluid
+    relative to the phi=+1 fluid.  inv_Fr = 0 switches gravity off.
+    Pe is the Peclet number; the mobility m(phi) is 1.
+    """
+
+    rho_minus: float = 1.0
+    eta_minus: float = 1.0
+    Re: float = 10.0
+    We: float = 1.0
+    Cn: float = 0.05
+    Pe: float = 1000.0
+    inv_Fr: float = 0.0
+    dt: float = 1e-4
+    S: float = 2.0
+    # linear-solver controls (relative residual, iteration cap)
+    rtol_ch: float = 1e-13
+    rtol_mom: float = 1e-13
+    rtol_p: float = 1e-12
+    max_iter: int = 200
+
+    def copy(self, **kw) -> "Props":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclasses.dataclass
+class Problem:
+    name: str
+    n: Tuple[int, ...]          # cells per axis (nx, ny[, nz])
+    h: float
+    bc: Tuple[str, ...]         # per axis: PERIODIC or WALL
+    props: Props
+    steps: int
+    init: str                   # initial-condition recipe name
+    init_args: Dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        return tuple(reversed(self.n))
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def periodic(self) -> Tuple[bool, ...]:
+        return tuple(b == PERIODIC for b in self.bc)
+
+
+# ---------------------------------------------------------------------------
+# coordinates
+# ---------------------------------------------------------------------------
+
+def cell_centres(n: Tuple[int, ...], h: float) -> List[np.ndarray]:
+    """Cell-centre coordinates x_a = (i_a + 1/2) h broadcast to the cell shape."""
+    dim = len(n)
+    shape = tuple(reversed(n))
+    out = []
+    for a in range(dim):
+        c = (np.arange(n[a], dtype=np.float64) + 0.5) * h
+        sh = [1] * dim
+        sh[dim - 1 - a] = n[a]
+        out.append(np.broadcast_to(c.reshape(sh), shape).copy())
+    return out
+
+
+def _min_image(d: np.ndarray, L: float, periodic: bool) -> np.ndarray:
+    if not periodic:
+        return d
+    return d - L * np.round(d / L)
+
+
+def interface(d: np.ndarray, Cn: float) -> np.ndarray:
+    """Equilibrium profile phi = tanh(d / (sqrt 2 Cn)); d > 0 in the carrier."""
+    return np.tanh(d / (math.sqrt(2.0) * Cn))
+
+
+# ---------------------------------------------------------------------------
+# initial conditions
+# ---------------------------------------------------------------------------
+
+def phi_drop(p: Problem, centre, radius) -> np.ndarray:
+    X = cell_centres(p.n, p.h)
+    r2 = np.zeros(p.shape)
+    for a in range(p.dim):
+        d = _min_image(X[a] - centre[a], p.n[a] * p.h, p.periodic[a])
+        r2 += d * d
+    return interface(np.sqrt(r2) - radius, p.props.Cn)
+
+
+def phi_ellipse(p: Problem, centre, semi_axes) -> np.ndarray:
+    """Axis-aligned ellipse; d = F/|grad F| with F = sqrt(sum (x_a/s_a)^2) - 1."""
+    X = cell_centres(p.n, p.h)
+    q = np.zeros(p.shape)
+    g = np.zeros(p.shape)
+    for a in range(p.dim):
+        d = _min_image(X[a] - centre[a], p.n[a] * p.h, p.periodic[a])
+        q += (d / semi_axes[a]) ** 2
+        g += (d / semi_axes[a] ** 2) ** 2
+    rad = np.sqrt(q)
+    grad = np.sqrt(g) / np.maximum(rad, 1e-300)
+    dist = np.where(rad > 0, (rad - 1.0) / np.maximum(grad, 1e-300), -min(semi_axes))
+    return interface(dist, p.props.Cn)
+
+
+def phi_slab(p: Problem, height: float) -> np.ndarray:
+    """Flat interface at y = height, carrier (phi=+1) below."""
+    X = cell_centres(p.n, p.h)
+    return interface(height - X[1], p.props.Cn)
+
+
+def phi_spinodal(p: Problem, seed: int, amp: float = 0.05) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return amp * rng.uniform(-1.0, 1.0, size=p.shape)
+
+
+def velocity_streamfunction(p: Problem, seed: int, amp: float, kmax: int = 2) -> List[np.ndarray]:
+    """Discretely divergence-free MAC velocity from a seeded 2D streamfunction.
+
+    psi lives on cell corners (i h, j h); u_x(face i,j) = (psi(i,j+1) - psi(i,j))/h,
+    u_y(face i,j) = -(psi(i+1,j) - psi(i,j))/h.  On walled axes psi is
+    multiplied by a profile that vanishes (with zero slope) on the walls, so
+    the normal velocity is zero there.  Scaled so that max|u| = amp.
+    """
+    assert p.dim == 2
+    rng = np.random.default_rng(seed)
+    nx, ny = p.n
+    Lx, Ly = nx * p.h, ny * p.h
+    xs = np.arange(nx + 1) * p.h
+    ys = np.arange(ny + 1) * p.h
+    Xc, Yc = np.meshgrid(xs, ys)  # (ny+1, nx+1)
+    psi = np.zeros_like(Xc)
+    for kx in range(0, kmax + 1):
+        for ky in range(0, kmax + 1):
+            if kx == 0 and ky == 0:
+                continue
+            ph = rng.uniform(0, 2 * np.pi, size=2)
+            amp_k = rng.normal()
+            fx = np.cos(2 * np.pi * kx * Xc / Lx + ph[0]) if p.periodic[0] else np.cos(np.pi * kx * Xc / Lx)
+            fy = np.cos(2 * np.pi * ky * Yc / Ly + ph[1]) if p.periodic[1] else np.cos(np.pi * ky * Yc / Ly)
+            psi += amp_k * fx * fy
+    if not p.periodic[0]:
+        psi *= np.sin(np.pi * Xc / Lx) ** 2
+    if not p.periodic[1]:
+        psi *= np.sin(np.pi * Yc / Ly) ** 2
+    ux = (psi[1:, :nx] - psi[:ny, :nx]) / p.h
+    uy = -(psi[:ny, 1:] - psi[:ny, :nx]) / p.h
+    if not p.periodic[0]:
+        ux[:, 0] = 0.0
+    if not p.periodic[1]:
+        uy[0, :] = 0.0
+    m = max(np.abs(ux).max(), np.abs(uy).max())
+    return [ux * (amp / m), uy * (amp / m)]
+
+
+def velocity_potential3d(p: Problem, seed: int, amp: float, kmax2: int = 4) -> List[np.ndarray]:
+    """Discretely divergence-free 3D MAC velocity u = curl_h A (all-periodic grid).
+
+    A_x, A_y, A_z live on cell edges; Fourier modes 1 <= |k|^2 <= kmax2 with
+    seeded phases and amplitudes.  Scaled so that max|u| = amp.
+    """
+    assert p.dim == 3 and all(p.periodic)
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = p.n
+    h = p.h
+    L = [nx * h, ny * h, nz * h]
+    idx = [np.arange(n_) for n_ in (nx, ny, nz)]
+    # coordinates: index i -> i*h (lower corner) or (i+1/2)h (centre)
+    def coord(a, centred):
+        return (idx[a] + (0.5 if centred else 0.0)) * h
+    # A_x at (x centred, y corner, z corner) etc.
+    comps = []
+    for a in range(3):
+        cen = [b == a for b in range(3)]
+        Xs = np.meshgrid(coord(2, cen[2]), coord(1, cen[1]), coord(0, cen[0]), indexing="ij")
+        Z, Y, X = Xs
+        A = np.zeros((nz, ny, nx))
+        for kx in range(-2, 3):
+            for ky in range(-2, 3):
+                for kz in range(-2, 3):
+                    k2 = kx * kx + ky * ky + kz * kz
+                    if k2 < 1 or k2 > kmax2:
+                        continue
+                    ph = rng.uniform(0, 2 * np.pi)
+                    c = rng.normal()
+                    A += c * np.cos(2 * np.pi * (kx * X / L[0] + ky * Y / L[1] + kz * Z / L[2]) + ph)
+        comps.append(A)
+    Ax, Ay, Az = comps
+
+    def dplus(q, a):  # forward difference along axis a (numpy axis 2-a), periodic
+        return (np.roll(q, -1, axis=2 - a) - q) / h
+
+    # u_x at x-face (corner in x, centred in y,z) = dAz/dy - dAy/dz
+    ux = dplus(Az, 1) - dplus(Ay, 2)
+    uy = dplus(Ax, 2) - dplus(Az, 0)
+    uz = dplus(Ay, 0) - dplus(Ax, 1)
+    m = max(np.abs(ux).max(), np.abs(uy).max(), np.abs(uz).max())
+    return [ux * (amp / m), uy * (amp / m), uz * (amp / m)]
+
+
+def initial_state(p: Problem) -> Dict[str, object]:
+    """Return {'phi': cells, 'u': [faces per axis], 'p': cells} in float64."""
+    a = p.init_args
+    if p.init == "drop":
+        phi = phi_drop(p, a["centre"], a["radius"])
+    elif p.init == "ellipse":
+        phi = phi_ellipse(p, a["centre"], a["semi_axes"])
+    elif p.init == "slab":
+        phi = phi_slab(p, a["height"])
+    elif p.init == "spinodal":
+        phi = phi_spinodal(p, a.get("seed", 0), a.get("amp", 0.05))
+    elif p.init == "const":
+        phi = np.full(p.shape, float(a.get("value", 1.0)))
+    else:
+        raise ValueError(f"unknown initial condition {p.init!r}")
+    if a.get("velocity") == "stream":
+        u = velocity_streamfunction(p, a.get("vseed", 1), a.get("vamp", 1e-2))
+    elif a.get("velocity") == "potential3d":
+        u = velocity_potential3d(p, a.get("vseed", 1), a.get("vamp", 1e-2))
+    else:
+        u = [np.zeros(p.shape) for _ in range(p.dim)]
+    return {"phi": np.ascontiguousarray(phi, dtype=np.float64),
+            "u": [np.ascontiguousarray(x, dtype=np.float64) for x in u],
+            "p": np.zeros(p.shape)}
+
+
+# ---------------------------------------------------------------------------
+# named problems
+# ---------------------------------------------------------------------------
+
+def static_drop(n: int = 64, steps: int = 100, **kw) -> Problem:
+    """Static drop: unit periodic box, R = 0.25 centred, density and viscosity
+    ratio 10 (carrier heavier), sigma = 1 (We = 1), Cn = 1.5 h, mobility 1e-3
+    (Pe = 1/(M sigma) = 1000), Re = 10, no gravity, dt = 1e-4, u0 = 0."""
+    h = 1.0 / n
+    pr = Props(rho_minus=0.1, eta_minus=0.1, Re=10.0, We=1.0, Cn=1.5 * h,
+               Pe=1000.0, inv_Fr=0.0, dt=1e-4)
+    pr = pr.copy(**kw)
+    return Problem("static_drop_%d" % n, (n, n), h, (PERIODIC, PERIODIC), pr, steps,
+                   "drop", {"centre": (0.5, 0.5), "radius": 0.25})
+
+
+def rising_bubble(nx: int = 256, steps: int = 2000, **kw) -> Problem:
+    """Rising bubble: non-dimensional box [0,2] x [0,4] (bubble diameter 1),
+    nx x 2nx cells, periodic sides, no-slip top and bottom.  Bubble radius 0.5
+    at (1,1); rho_-/rho_+ = 1e-3, eta_-/eta_+ = 1e-2; We = Eo = 10, Re = Ar = 35,
+    Fr = 1 with gravity along -y; Cn = 1.5 h; 1/Pe = 3 Cn^2; dt = 2.5e-4."""
+    h = 2.0 / nx
+    Cn = 1.5 * h
+    pr = Props(rho_minus=1e-3, eta_minus=1e-2, Re=35.0, We=10.0, Cn=Cn,
+               Pe=1.0 / (3.0 * Cn * Cn), inv_Fr=1.0, dt=2.5e-4)
+    pr = pr.copy(**kw)
+    return Problem("rising_bubble_%dx%d" % (nx, 2 * nx), (nx, 2 * nx), h, (PERIODIC, WALL),
+                   pr, steps, "drop", {"centre": (1.0, 1.0), "radius": 0.5})
+
+
+def adjoint_drop(n: int = 128, steps: int = 400, sigma: float = 1.0, mobility: float = 1e-3, **kw) -> Problem:
+    """Oscillating drop: unit periodic box, initial ellipse with semi-axes
+    0.3 (x) / 0.2 (y), ratios 10/10, Re = 10, Cn = 1.5 h, dt = 1e-4.
+    Surface tension sigma and mobility M enter as We = 1/sigma, Pe = 1/(M sigma)."""
+    h = 1.0 / n
+    pr = Props(rho_minus=0.1, eta_minus=0.1, Re=10.0, We=1.0 / sigma, Cn=1.5 * h,
+               Pe=1.0 / (mobility * sigma), inv_Fr=0.0, dt=1e-4)
+    pr = pr.copy(**kw)
+    return Problem("adjoint_drop_%d" % n, (n, n), h, (PERIODIC, PERIODIC), pr, steps,
+                   "ellipse", {"centre": (0.5, 0.5), "semi_axes": (0.3, 0.2)})
+
+
+def flat_interface(nx: int = 32, ny: int = 32, steps: int = 100, gravity: bool = True, **kw) -> Problem:
+    """Flat interface at rest: x periodic, y walls, heavy carrier below."""
+    h = 1.0 / nx
+    pr = Props(rho_minus=0.1, eta_minus=0.1, Re=10.0, We=1.0, Cn=1.5 * h, Pe=1000.0,
+               inv_Fr=1.0 if gravity else 0.0, dt=1e-4)
+    pr = pr.copy(**kw)
+    return Problem("flat_%dx%d" % (nx, ny), (nx, ny), h, (PERIODIC, WALL), pr, steps,
+                   "slab", {"height": 0.5 * ny * h})
+
+
+def spinodal(n: int = 32, seed: int = 7, steps: int = 1000, bc=(PERIODIC, PERIODIC), **kw) -> Problem:
+    h = 1.0 / n
+    pr = Props(rho_minus=0.1, eta_minus=0.1, Re=10.0, We=1.0, Cn=1.5 * h, Pe=1000.0, dt=1e-4)
+    pr = pr.copy(**kw)
+    return Problem("spinodal_%d" % n, (n,) * len(bc), h, tuple(bc), pr, steps,
+                   "spinodal", {"seed": seed, "amp": 0.05})
+
+
+def drop3d(n: int = 32, steps: int = 10, **kw) -> Problem:
+    """3D periodic drop with a divergence-free random velocity perturbation."""
+    h = 1.0 / n
+    pr = Props(rho_minus=0.1, eta_minus=0.1, Re=10.0, We=1.0, Cn=1.5 * h, Pe=1000.0, dt=1e-4)
+    pr = pr.copy(**kw)
+    return Problem("drop3d_%d" % n, (n, n, n), h, (PERIODIC,) * 3, pr, steps, "drop",
+                   {"centre": (0.5, 0.5, 0.5), "radius": 0.25, "velocity": "potential3d",
+                    "vseed": 3, "vamp": 1e-2})
+
+
+def problem_by_name(name: str) -> Problem:
+    table = {
+        "static_drop": static_drop,
+        "rising_bubble": rising_bubble,
+        "adjoint_drop": adjoint_drop,
+    }
+    return table[name]()
