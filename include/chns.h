@@ -1,0 +1,198 @@
+/*
+ * chns.h -- C ABI of the MI355X (gfx950) time-step library for the two-phase
+ * Cahn-Hilliard Navier-Stokes (CHNS) model of Khanwale et al., "A fully-coupled
+ * framework for solving Cahn-Hilliard Navier-Stokes equations: second-order,
+ * energy-stable numerical methods on adaptive octree based meshes"
+ * (arXiv 2009.06628).
+ *
+ * Model (paper, governing-equations section): phase field phi in [-1, 1],
+ * chemical potential mu = psi'(phi) - Cn^2 lap(phi) with psi = (phi^2-1)^2/4,
+ * mixture density rho = alpha phi + beta and viscosity eta = gamma phi + xi
+ * built from the pulled-back phi* = clamp(phi, -1, 1) (remark on the
+ * pull-back), thermodynamically consistent flux
+ * J = (rho_- - rho_+)/(2 rho_+ Cn) grad mu, momentum with the Korteweg
+ * stress, pressure (1/We) grad p, viscosity (1/Re) div(eta grad v) and
+ * gravity rho g_hat / Fr with g_hat = (0,-1,0), solenoidal velocity.
+ * Non-dimensional groups Pe, Re, We, Cn, Fr as defined there; mobility 1.
+ *
+ * Discretisation (a split step on a uniform MAC grid; the paper's own
+ * Crank-Nicolson / FEM / Newton layout is not used): the library advances
+ *   S1  explicit CH stage with the advective flux u A(phi),
+ *   S2  (I - dt kM S L + dt kM Cn^2 L L) phihat = r, kM = 1/(Pe Cn), S = stabiliser,
+ *   S3  mu^{n+1} = psi'(phi^n) + S (phihat - phi^n) - Cn^2 L phihat,
+ *   S4  phi^{n+1} = phi^n - dt D(u A(phi^n) - kM G mu^{n+1})  (mass conserving),
+ *   S5  J = -(alpha/Cn) G mu^{n+1},  m = A(alpha phi^n + beta) u^n + J / Pe,
+ *   S6  rho^{n+1}, eta^{n+1} from clamp(phi^{n+1}),
+ *   S7  per axis a:  (rho_f^{n+1}/dt) u*_a - (1/Re) div(eta grad u*_a)
+ *         = ((rho_f^{n+1}+rho_f^n)/(2dt)) u_a^n - N_a(m, u^n)
+ *           - (1/(We Cn)) A_a(phi^n) G_a mu^{n+1} + rho_f^{n+1} g_hat_a / Fr,
+ *       N_a the skew-symmetric advection of the appendix remark,
+ *   S8  -D(rho_f^{-1} G p) = -(We/dt) D u*,  mean(p) = 0,
+ *   S9  u^{n+1} = u* - (dt/We) rho_f^{-1} G p.
+ * Every linear system is solved matrix-free by multigrid-preconditioned
+ * conjugate gradients on the device.
+ *
+ * Data layout (device memory, float64, row-major, x fastest):
+ *   cell arrays   idx = i + nx*(j + ny*k), nx*ny*nz entries (nz = 1 in 2D);
+ *   face arrays   one per axis a, same shape as the cell arrays; entry c is
+ *                 the face between cell c - e_a and cell c.  On a walled axis
+ *                 the entry with index 0 along that axis is the wall face
+ *                 (its normal velocity is 0) and the opposite wall face is
+ *                 not stored.
+ *
+ * Ownership: every device array (state, workspace) belongs to the caller.
+ * The library keeps raw pointers and small host metadata, never allocates
+ * device memory, and runs all work on the stream given at creation.  Handles
+ * are not thread-safe; distinct handles are independent.
+ *
+ * Errors: functions return CHNS_OK (0), the warning CHNS_ENOCONV (> 0: the
+ * call completed but a linear solve stopped at max_iter), or a negative code.
+ * After a negative code the outputs of that call are unspecified.
+ * chns_last_error() returns a message for the most recent failure on the
+ * calling thread.
+ */
+#ifndef CHNS_H
+#define CHNS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CHNS_OK = 0,
+    CHNS_ENOCONV = 1,      /* warning: a solve hit max_iter; see stats      */
+    CHNS_EINVAL = -1,      /* bad argument or unsupported grid              */
+    CHNS_ENOMEM = -2,      /* workspace smaller than chns_workspace_size    */
+    CHNS_EDEVICE = -3,     /* HIP runtime error (message in last_error)     */
+    CHNS_ENONFINITE = -4   /* NaN / Inf detected in a residual              */
+};
+
+enum { CHNS_BC_PERIODIC = 0, CHNS_BC_WALL = 1 };
+enum { CHNS_FP64 = 0, CHNS_FP32_REFINE = 1 };
+
+/* Grid description.  dim = 2 or 3; n[a] cells along axis a (n[2] ignored in
+ * 2D); h the uniform cell size; bc[a] per axis: periodic, or no-slip /
+ * no-flux walls on both ends (paper: boundary conditions of the
+ * mass-conservation proposition).  precision selects the arithmetic of the
+ * linear solves (CHNS_FP64, or FP32 multigrid sweeps under an FP64 outer
+ * refinement).  nphases must be 2.
+ * Supported sizes: every n[a] >= 2 and even, and repeated halving of all axes
+ * while they stay even must reach a grid of at most 512 cells.            */
+typedef struct {
+    int dim;
+    int n[3];
+    double h;
+    int bc[3];
+    int precision;
+    int nphases;
+} chns_grid_desc;
+
+/* Physical and numerical parameters (non-dimensional; the phi = +1 fluid is
+ * the reference, rho_+ = eta_+ = 1).  inv_Fr = 1/Fr, 0 disables gravity.
+ * dt the time step, S the CH stabiliser (S >= 1 keeps the CH sub-step energy
+ * stable for |phi| <= 1).  rtol_* are relative residual tolerances
+ * ||b - Ax||_2 <= rtol ||b||_2 of the CH, momentum and pressure solves;
+ * max_iter caps every PCG solve.                                         */
+typedef struct {
+    double rho_minus, eta_minus;
+    double Re, We, Cn, Pe, inv_Fr;
+    double dt, S;
+    double rtol_ch, rtol_mom, rtol_p;
+    int max_iter;
+    int reserved;
+} chns_props;
+
+/* Caller-owned device pointers of the state.  phi, p, mu: cell arrays;
+ * u[a]: face arrays (u[2] unused in 2D).  chns_step reads phi, u, p and
+ * overwrites them with the new state; mu receives mu^{n+1}.             */
+typedef struct {
+    void *phi;
+    void *u[3];
+    void *p;
+    void *mu;
+} chns_state;
+
+/* Host-side statistics of the last step of a chns_step call.            */
+typedef struct {
+    int iters_ch, iters_mom[3], iters_p;
+    int unconverged;            /* bit 0: CH, bits 1..3: momentum, bit 4: p */
+    double res_ch, res_mom[3], res_p;   /* final relative residuals        */
+    double mass_plus, mass_minus;       /* sum (1 +- phi)/2 h^d            */
+    double energy;                      /* discrete total energy           */
+    double umax, divmax;                /* max |u|, max |D u|              */
+} chns_step_stats;
+
+typedef struct {
+    int iters;
+    double rel_res;
+} chns_solve_stats;
+
+/* Bytes of device workspace that chns_create_grid needs for this grid
+ * (field buffers, multigrid hierarchy, coarse-grid inverse, reduction
+ * scratch).  Returns CHNS_EINVAL for an unsupported description.         */
+int chns_workspace_size(const chns_grid_desc *desc, size_t *bytes);
+
+/* Create a handle.  workspace: device memory of at least
+ * chns_workspace_size bytes, 256-byte aligned, owned by the caller and kept
+ * alive until chns_destroy_grid.  hip_stream: a hipStream_t (NULL = default
+ * stream).  No device memory is allocated here or later.                 */
+int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes,
+                     void *hip_stream, struct chns_grid **out);
+
+/* Set / change the parameters (host struct, copied).  Must be called before
+ * the first chns_step.  Rebuilds the constant CH multigrid hierarchy.     */
+int chns_set_properties(struct chns_grid *g, const chns_props *props);
+
+/* Advance the state nsteps time steps (S1..S9 each) in place on the grid's
+ * stream.  If stats is not NULL the call synchronises the stream and fills
+ * it (solver statistics of the last step, diagnostics of the final state).
+ * Returns CHNS_ENOCONV if any solve of any step hit max_iter.            */
+int chns_step(struct chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats);
+
+/* Stand-alone pressure solve of S8:  -D(rho_f^{-1} G p) = rhs, mean(p) = 0,
+ * with rho a cell array of densities (rho_f = face averages, used as is)
+ * and rhs a cell array (projected to mean zero internally; not modified).
+ * p (cell array) is the initial guess on entry and the solution on exit.  */
+int chns_solve_pressure(struct chns_grid *g, const void *rho, const void *rhs, void *p,
+                        double rtol, int max_iter, chns_solve_stats *stats);
+
+/* Apply the pressure operator of S8: y = -D(rho_f^{-1} G x) with rho_f the
+ * face averages of the cell density rho (no pull-back).  x, y: cell arrays.
+ * Synchronises the stream.  Used to check the stencil kernel on its own.  */
+int chns_apply_pressure_operator(struct chns_grid *g, const void *rho, const void *x, void *y);
+
+/* Per-kernel timing.  chns_set_timing(g, 1) creates a host-side pool of
+ * hipEvents (no device memory), resets the counters and makes every later
+ * chns_step / chns_solve_pressure bracket each kernel launch with an event
+ * pair; chns_set_timing(g, 0) stops it.  chns_get_timing copies one record
+ * per kernel class that ran (at most max records; *count receives the number
+ * of classes): launches, summed kernel time in ms (hipEventElapsedTime) and
+ * summed algorithmic bytes (each array a launch reads or writes counted
+ * once).  Timing adds host work per launch; measure throughput without it. */
+typedef struct {
+    char name[24];
+    int launches;
+    double ms;
+    double bytes;
+} chns_kernel_timing;
+
+int chns_set_timing(struct chns_grid *g, int enable);
+int chns_get_timing(struct chns_grid *g, chns_kernel_timing *out, int max, int *count);
+
+/* Release the handle (host metadata only; device memory is the caller's). */
+int chns_destroy_grid(struct chns_grid *g);
+
+/* Static text for an error code.                                          */
+const char *chns_error_string(int code);
+
+/* Copy the calling thread's most recent error message into buf (always
+ * NUL-terminated when len > 0); returns its full length.                  */
+int chns_last_error(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHNS_H */

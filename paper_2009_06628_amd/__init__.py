@@ -1,0 +1,262 @@
+"""MI355X-native split time step of the two-phase Cahn-Hilliard Navier-Stokes
+model (Khanwale et al., arXiv 2009.06628) -- Python binding.
+
+The binding only marshals arguments: every step of the path runs in the HIP
+kernels of libchns.so (built in-tree by ``paper_2009_06628_amd.build``).
+PyTorch supplies device memory and the stream.  There is no CPU fallback: if
+the library or a GPU is missing, every entry point raises.
+
+Names follow the C ABI in include/chns.h: create_grid / set_properties /
+step / solve_pressure (plus workspace_size and apply_pressure_operator).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchns.so")
+
+CHNS_OK, CHNS_ENOCONV, CHNS_EINVAL, CHNS_ENOMEM, CHNS_EDEVICE, CHNS_ENONFINITE = 0, 1, -1, -2, -3, -4
+CHNS_BC_PERIODIC, CHNS_BC_WALL = 0, 1
+CHNS_FP64, CHNS_FP32_REFINE = 0, 1
+
+
+class chns_grid_desc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("bc", ctypes.c_int * 3), ("precision", ctypes.c_int), ("nphases", ctypes.c_int)]
+
+
+class chns_props(ctypes.Structure):
+    _fields_ = [("rho_minus", ctypes.c_double), ("eta_minus", ctypes.c_double),
+                ("Re", ctypes.c_double), ("We", ctypes.c_double), ("Cn", ctypes.c_double),
+                ("Pe", ctypes.c_double), ("inv_Fr", ctypes.c_double),
+                ("dt", ctypes.c_double), ("S", ctypes.c_double),
+                ("rtol_ch", ctypes.c_double), ("rtol_mom", ctypes.c_double), ("rtol_p", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+class chns_state(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_void_p), ("u", ctypes.c_void_p * 3), ("p", ctypes.c_void_p),
+                ("mu", ctypes.c_void_p)]
+
+
+class chns_step_stats(ctypes.Structure):
+    _fields_ = [("iters_ch", ctypes.c_int), ("iters_mom", ctypes.c_int * 3), ("iters_p", ctypes.c_int),
+                ("unconverged", ctypes.c_int),
+                ("res_ch", ctypes.c_double), ("res_mom", ctypes.c_double * 3), ("res_p", ctypes.c_double),
+                ("mass_plus", ctypes.c_double), ("mass_minus", ctypes.c_double),
+                ("energy", ctypes.c_double), ("umax", ctypes.c_double), ("divmax", ctypes.c_double)]
+
+
+class chns_kernel_timing(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+class chns_solve_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rel_res", ctypes.c_double)]
+
+
+EXPORTS = {
+    "chns_workspace_size": (ctypes.c_int, [ctypes.POINTER(chns_grid_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "chns_create_grid": (ctypes.c_int, [ctypes.POINTER(chns_grid_desc), ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "chns_set_properties": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_props)]),
+    "chns_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.c_int,
+                                 ctypes.POINTER(chns_step_stats)]),
+    "chns_solve_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_double, ctypes.c_int, ctypes.POINTER(chns_solve_stats)]),
+    "chns_apply_pressure_operator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                    ctypes.c_void_p]),
+    "chns_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "chns_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_kernel_timing), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int)]),
+    "chns_destroy_grid": (ctypes.c_int, [ctypes.c_void_p]),
+    "chns_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "chns_last_error": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
+}
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libchns.so (no GPU needed to load).  Raises if it is not built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2009_06628_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+class CHNSError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = load_library()
+        buf = ctypes.create_string_buffer(1024)
+        lib.chns_last_error(buf, 1024)
+        super().__init__(f"{where}: {lib.chns_error_string(code).decode()} ({code}): {buf.value.decode()}")
+        self.code = code
+
+
+def _check(code: int, where: str, allow_noconv: bool = False) -> int:
+    if code == CHNS_OK or (code == CHNS_ENOCONV and allow_noconv):
+        return code
+    raise CHNSError(code, where)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2009_06628_amd needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _ptr(t, dtype=None) -> int:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    if t.dtype != torch.float64:
+        raise ValueError("expected float64")
+    return t.data_ptr()
+
+
+def make_desc(n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64) -> chns_grid_desc:
+    d = chns_grid_desc()
+    d.dim = len(n)
+    for a in range(3):
+        d.n[a] = int(n[a]) if a < len(n) else 1
+        d.bc[a] = (CHNS_BC_WALL if bc[a] == "wall" else CHNS_BC_PERIODIC) if a < len(n) else 0
+    d.h = float(h)
+    d.precision = precision
+    d.nphases = 2
+    return d
+
+
+def workspace_size(n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64) -> int:
+    lib = load_library()
+    d = make_desc(n, h, bc, precision)
+    out = ctypes.c_size_t(0)
+    _check(lib.chns_workspace_size(ctypes.byref(d), ctypes.byref(out)), "chns_workspace_size")
+    return out.value
+
+
+class Grid:
+    """Handle of one uniform grid (create_grid); owns its workspace tensor."""
+
+    def __init__(self, n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64,
+                 device: str = "cuda", stream=None):
+        torch = _torch()
+        lib = load_library()
+        self.n = tuple(int(x) for x in n)
+        self.dim = len(self.n)
+        self.shape = tuple(reversed(self.n))
+        self.h = float(h)
+        self.bc = tuple(bc)
+        self.device = torch.device(device)
+        self._desc = make_desc(self.n, h, bc, precision)
+        nbytes = workspace_size(self.n, h, bc, precision)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        _check(lib.chns_create_grid(ctypes.byref(self._desc), ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
+               "chns_create_grid")
+        self._h = handle
+        self._lib = lib
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.chns_destroy_grid(h)
+            self._h = None
+
+    # -- set_properties ------------------------------------------------------
+    def set_properties(self, props) -> None:
+        p = chns_props()
+        for name, _ in chns_props._fields_:
+            if name == "reserved":
+                continue
+            setattr(p, name, getattr(props, name))
+        _check(self._lib.chns_set_properties(self._h, ctypes.byref(p)), "chns_set_properties")
+
+    # -- state ---------------------------------------------------------------
+    def new_state(self, init: Optional[Dict] = None) -> Dict:
+        """Allocate a device state (float64) and fill it from numpy arrays."""
+        torch = _torch()
+        z = lambda: torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+        st = {"phi": z(), "u": [z() for _ in range(self.dim)], "p": z(), "mu": z()}
+        if init is not None:
+            st["phi"].copy_(torch.as_tensor(init["phi"]))
+            for a in range(self.dim):
+                st["u"][a].copy_(torch.as_tensor(init["u"][a]))
+            if "p" in init:
+                st["p"].copy_(torch.as_tensor(init["p"]))
+        return st
+
+    def _cstate(self, st: Dict) -> chns_state:
+        cs = chns_state()
+        cs.phi = _ptr(st["phi"])
+        for a in range(3):
+            cs.u[a] = _ptr(st["u"][a]) if a < self.dim else None
+        cs.p = _ptr(st["p"])
+        cs.mu = _ptr(st["mu"])
+        return cs
+
+    # -- step ----------------------------------------------------------------
+    def step(self, st: Dict, nsteps: int = 1, stats: bool = True, allow_noconv: bool = False) -> Optional[Dict]:
+        cs = self._cstate(st)
+        out = chns_step_stats()
+        rc = self._lib.chns_step(self._h, ctypes.byref(cs), int(nsteps), ctypes.byref(out) if stats else None)
+        _check(rc, "chns_step", allow_noconv)
+        if not stats:
+            return None
+        return {
+            "iters_ch": out.iters_ch, "iters_mom": list(out.iters_mom)[: self.dim], "iters_p": out.iters_p,
+            "unconverged": out.unconverged, "res_ch": out.res_ch, "res_mom": list(out.res_mom)[: self.dim],
+            "res_p": out.res_p, "mass_plus": out.mass_plus, "mass_minus": out.mass_minus,
+            "energy": out.energy, "umax": out.umax, "divmax": out.divmax, "rc": rc,
+        }
+
+    # -- solve_pressure --------------------------------------------------------
+    def solve_pressure(self, rho, rhs, p, rtol: float = 1e-12, max_iter: int = 200) -> Dict:
+        out = chns_solve_stats()
+        rc = self._lib.chns_solve_pressure(self._h, ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(_ptr(rhs)),
+                                           ctypes.c_void_p(_ptr(p)), float(rtol), int(max_iter), ctypes.byref(out))
+        _check(rc, "chns_solve_pressure", allow_noconv=True)
+        return {"iters": out.iters, "rel_res": out.rel_res, "rc": rc}
+
+    # -- per-kernel timing ------------------------------------------------------
+    def set_timing(self, enable: bool) -> None:
+        _check(self._lib.chns_set_timing(self._h, 1 if enable else 0), "chns_set_timing")
+
+    def get_timing(self) -> List[Dict]:
+        arr = (chns_kernel_timing * 64)()
+        cnt = ctypes.c_int(0)
+        _check(self._lib.chns_get_timing(self._h, arr, 64, ctypes.byref(cnt)), "chns_get_timing")
+        return [{"name": arr[i].name.decode(), "launches": arr[i].launches, "ms": arr[i].ms,
+                 "bytes": arr[i].bytes} for i in range(cnt.value)]
+
+    def apply_pressure_operator(self, rho, x, y) -> None:
+        _check(self._lib.chns_apply_pressure_operator(self._h, ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(_ptr(x)),
+                                                      ctypes.c_void_p(_ptr(y))), "chns_apply_pressure_operator")
+
+
+def create_grid(n, h, bc, precision=CHNS_FP64, device="cuda", stream=None) -> Grid:
+    return Grid(n, h, bc, precision, device, stream)
+
+
+def grid_for_problem(problem, precision=CHNS_FP64, device="cuda") -> Grid:
+    """Grid + properties for a workloads.Problem."""
+    g = Grid(problem.n, problem.h, problem.bc, precision, device)
+    g.set_properties(problem.props)
+    return g

@@ -1,0 +1,530 @@
+// C ABI of libchns: argument checking, workspace layout, and the per-step
+// sequence S1..S9 on the handle's stream.  No device memory is allocated:
+// every buffer is carved out of the caller's workspace.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.h"
+#include "solvers.h"
+#include "step.h"
+
+using namespace chns;
+
+static thread_local std::string g_err;
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+// ---------------------------------------------------------------------------
+namespace chns {
+thread_local Prof *g_prof = nullptr;
+
+static const char *kNames[K_NCLASS] = {"ch_rhs",   "mu",          "phi_update",   "mom_setup", "p_setup",
+                                       "project",  "smooth",      "residual",     "restrict",  "prolong",
+                                       "coarse_solve", "mg_setup", "pcg_apply",   "pcg_update", "pcg_dot",
+                                       "pcg_init", "mean",        "diag"};
+
+const char *kclass_name(int c) { return (c >= 0 && c < K_NCLASS) ? kNames[c] : "?"; }
+
+void prof_begin(int cls, double bytes, hipStream_t st) {
+    Prof *P = g_prof;
+    if (P->n == P->cap) prof_flush();
+    (void)hipEventRecord(P->ev[2 * P->n], st);
+    P->cls[P->n] = cls;
+    P->bytes[P->n] = bytes;
+}
+
+void prof_end(hipStream_t st) {
+    Prof *P = g_prof;
+    (void)hipEventRecord(P->ev[2 * P->n + 1], st);
+    P->n++;
+}
+
+int prof_flush() {
+    Prof *P = g_prof;
+    if (!P || P->n == 0) return 0;
+    if (hipEventSynchronize(P->ev[2 * P->n - 1]) != hipSuccess) return -1;
+    for (int i = 0; i < P->n; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, P->ev[2 * i], P->ev[2 * i + 1]) != hipSuccess) return -1;
+        P->ms[P->cls[i]] += ms;
+        P->launches[P->cls[i]] += 1;
+        P->total_bytes[P->cls[i]] += P->bytes[i];
+    }
+    P->n = 0;
+    return 0;
+}
+}  // namespace chns
+
+namespace {
+// Installs the handle's profiler for the duration of an API call.
+struct ProfScope {
+    explicit ProfScope(chns_grid *g) { g_prof = (g && g->prof.enabled) ? &g->prof : nullptr; }
+    ~ProfScope() {
+        prof_flush();
+        g_prof = nullptr;
+    }
+};
+}  // namespace
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(CHNS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
+
+struct Plan {
+    int dim;
+    int nlev;
+    Geo lev[kMaxLev];
+};
+
+int make_plan(const chns_grid_desc *d, Plan &P) {
+    if (!d) return fail(CHNS_EINVAL, "grid description is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(CHNS_EINVAL, "dim must be 2 or 3");
+    if (d->nphases != 2) return fail(CHNS_EINVAL, "only nphases = 2 is supported");
+    if (d->precision != CHNS_FP64) return fail(CHNS_EINVAL, "precision form not available in this build");
+    if (!(d->h > 0.0) || !std::isfinite(d->h)) return fail(CHNS_EINVAL, "h must be positive and finite");
+    Geo g;
+    g.N = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (a < d->dim) {
+            if (d->n[a] < 2) return fail(CHNS_EINVAL, "every n[a] must be >= 2");
+            if (d->bc[a] != CHNS_BC_PERIODIC && d->bc[a] != CHNS_BC_WALL) return fail(CHNS_EINVAL, "bad bc");
+            g.n[a] = d->n[a];
+            g.per[a] = d->bc[a] == CHNS_BC_PERIODIC;
+        } else {
+            g.n[a] = 1;
+            g.per[a] = 1;
+        }
+        g.N *= g.n[a];
+    }
+    if (g.N > (1LL << 34)) return fail(CHNS_EINVAL, "grid too large");
+    P.dim = d->dim;
+    P.nlev = 1;
+    P.lev[0] = g;
+    for (;;) {
+        const Geo &f = P.lev[P.nlev - 1];
+        if (f.N <= 64 || P.nlev == kMaxLev) break;
+        bool ok = true;
+        for (int a = 0; a < d->dim; ++a)
+            if ((f.n[a] & 1) || f.n[a] / 2 < 2) ok = false;
+        if (!ok) break;
+        Geo c = f;
+        c.N = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (a < d->dim) c.n[a] = f.n[a] / 2;
+            c.N *= c.n[a];
+        }
+        P.lev[P.nlev++] = c;
+    }
+    if (P.lev[P.nlev - 1].N > kMaxCoarse) {
+        char buf[256];
+        snprintf(buf, sizeof buf,
+                 "unsupported grid: coarsening by 2 stops at %lld cells (> %d); choose sizes with more factors of 2",
+                 (long long)P.lev[P.nlev - 1].N, kMaxCoarse);
+        return fail(CHNS_EINVAL, buf);
+    }
+    return CHNS_OK;
+}
+
+// Bump allocator over the workspace (base == nullptr: sizing pass).
+struct Bump {
+    char *base;
+    size_t off;
+    template <typename T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+template <typename T>
+void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
+    S.nlev = P.nlev;
+    S.singular = singular;
+    S.ncoarse = (int)P.lev[P.nlev - 1].N;
+    for (int l = 0; l < P.nlev; ++l) {
+        Level<T> &L = S.lev[l];
+        L.g = P.lev[l];
+        const size_t n = (size_t)L.g.N;
+        L.s = B.take<T>(n);
+        for (int b = 0; b < 3; ++b) L.cs[b] = b < P.dim ? B.take<T>(n) : nullptr;
+        L.r = B.take<T>(n);
+        L.x = l ? B.take<T>(n) : nullptr;
+        L.b = l ? B.take<T>(n) : nullptr;
+    }
+    S.Ainv = B.take<T>((size_t)S.ncoarse * S.ncoarse);
+    S.aug = nullptr;
+}
+
+void layout(Bump &B, const Plan &P, chns_grid *g) {
+    const size_t N = (size_t)P.lev[0].N;
+    g->phi_new = B.take<double>(N);
+    g->phihat = B.take<double>(N);
+    g->rch = B.take<double>(N);
+    for (int a = 0; a < 3; ++a) g->ustar[a] = a < P.dim ? B.take<double>(N) : nullptr;
+    g->rhs = B.take<double>(N);
+    g->vr = B.take<double>(N);
+    g->vz = B.take<double>(N);
+    g->vp0 = B.take<double>(N);
+    g->vp1 = B.take<double>(N);
+    g->vq = B.take<double>(N);
+    g->vt = B.take<double>(N);
+    carve_slot(B, P, g->ch, 0);
+    carve_slot(B, P, g->mom, 0);
+    carve_slot(B, P, g->pres, 1);
+    const int nc = g->ch.ncoarse;
+    double *aug = B.take<double>((size_t)nc * 2 * nc);
+    g->ch.aug = g->mom.aug = g->pres.aug = aug;
+    g->red.part0 = B.take<double>(kMaxBlocks);
+    g->red.part1 = B.take<double>(kMaxBlocks);
+    g->red.part2 = B.take<double>(kMaxBlocks);
+    g->diag = B.take<double>(8 * (size_t)kMaxBlocks + 16);
+    g->red.counter = B.take<unsigned int>(64);
+    g->red.scal = B.take<Scal>(1);
+}
+
+StepConst step_const(const chns_grid *g) {
+    const chns_props &p = g->props;
+    StepConst k;
+    k.h = g->h;
+    k.ih = 1.0 / g->h;
+    k.ih2 = k.ih * k.ih;
+    k.dt = p.dt;
+    k.S = p.S;
+    k.Cn = p.Cn;
+    k.Pe = p.Pe;
+    k.kM = 1.0 / (p.Pe * p.Cn);
+    k.alpha = (1.0 - p.rho_minus) / 2.0;
+    k.beta = (1.0 + p.rho_minus) / 2.0;
+    k.gamma = (1.0 - p.eta_minus) / 2.0;
+    k.xi = (1.0 + p.eta_minus) / 2.0;
+    k.inv_Re = 1.0 / p.Re;
+    k.inv_We = 1.0 / p.We;
+    k.We = p.We;
+    k.inv_Fr = p.inv_Fr;
+    return k;
+}
+
+PcgVecs<double> vecs(chns_grid *g) { return PcgVecs<double>{g->vr, g->vz, g->vp0, g->vp1, g->vq, g->vt}; }
+
+int next_predict(int last) { return last < 1 ? 1 : last; }
+
+int check_solve(const SolveOut &o, const char *what) {
+    if (o.nonfinite) return fail(CHNS_ENONFINITE, std::string("non-finite residual in the ") + what + " solve");
+    return CHNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chns_workspace_size(const chns_grid_desc *desc, size_t *bytes) {
+    if (!bytes) return fail(CHNS_EINVAL, "bytes is NULL");
+    Plan P;
+    int rc = make_plan(desc, P);
+    if (rc) return rc;
+    chns_grid tmp;
+    Bump B{nullptr, 0};
+    layout(B, P, &tmp);
+    *bytes = B.off + 256;
+    return CHNS_OK;
+}
+
+int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, void *hip_stream, chns_grid **out) {
+    if (!out) return fail(CHNS_EINVAL, "out is NULL");
+    *out = nullptr;
+    Plan P;
+    int rc = make_plan(desc, P);
+    if (rc) return rc;
+    size_t need = 0;
+    chns_workspace_size(desc, &need);
+    if (!workspace) return fail(CHNS_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(CHNS_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < need) return fail(CHNS_ENOMEM, "workspace smaller than chns_workspace_size");
+    chns_grid *g = new (std::nothrow) chns_grid();
+    if (!g) return fail(CHNS_ENOMEM, "host allocation failed");
+    g->desc = *desc;
+    g->props_set = 0;
+    g->stream = (hipStream_t)hip_stream;
+    g->geo = P.lev[0];
+    g->dim = P.dim;
+    g->h = desc->h;
+    g->ws = workspace;
+    g->ws_bytes = bytes;
+    Bump B{(char *)workspace, 0};
+    layout(B, P, g);
+    for (int k = 0; k < 6; ++k) g->last_iters[k] = 4;
+    memset(&g->last, 0, sizeof g->last);
+    hipError_t e = hipMemsetAsync(g->red.counter, 0, 64 * sizeof(unsigned int), g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(g->red.scal, 0, sizeof(Scal), g->stream);
+    if (e != hipSuccess) {
+        delete g;
+        return fail(CHNS_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return CHNS_OK;
+}
+
+int chns_set_properties(chns_grid *g, const chns_props *p) {
+    if (!g || !p) return fail(CHNS_EINVAL, "NULL argument");
+    const double pos[] = {p->rho_minus, p->eta_minus, p->Re, p->We, p->Cn, p->Pe, p->dt};
+    for (double v : pos)
+        if (!(v > 0.0) || !std::isfinite(v))
+            return fail(CHNS_EINVAL, "rho_minus, eta_minus, Re, We, Cn, Pe, dt must be positive and finite");
+    if (!(p->S >= 0.0) || !std::isfinite(p->inv_Fr)) return fail(CHNS_EINVAL, "S must be >= 0, inv_Fr finite");
+    if (!(p->rtol_ch > 0.0) || !(p->rtol_mom > 0.0) || !(p->rtol_p > 0.0))
+        return fail(CHNS_EINVAL, "tolerances must be positive");
+    if (p->max_iter < 1) return fail(CHNS_EINVAL, "max_iter must be >= 1");
+    g->props = *p;
+    g->props_set = 1;
+    const StepConst k = step_const(g);
+    const double cb = p->dt * k.kM * p->Cn * p->Cn;
+    double *cs[3] = {g->ch.lev[0].cs[0], g->ch.lev[0].cs[1], g->ch.lev[0].cs[2]};
+    launch_fill_ch(g->dim, g->geo, std::sqrt(cb) * k.ih2, g->ch.lev[0].s, cs, g->stream);
+    mg_setup(g->ch, g->dim, g->stream);
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+}
+
+int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) {
+    if (!g || !st) return fail(CHNS_EINVAL, "NULL argument");
+    if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
+    if (nsteps < 0) return fail(CHNS_EINVAL, "nsteps must be >= 0");
+    if (!st->phi || !st->p || !st->mu) return fail(CHNS_EINVAL, "state pointer is NULL");
+    for (int a = 0; a < g->dim; ++a)
+        if (!st->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
+    ProfScope prof_scope(g);
+    const int dim = g->dim;
+    const Geo &geo = g->geo;
+    const StepConst k = step_const(g);
+    const chns_props &p = g->props;
+    hipStream_t s = g->stream;
+    double *phi = (double *)st->phi, *mu = (double *)st->mu, *pr = (double *)st->p;
+    double *u[3] = {(double *)st->u[0], (double *)st->u[1], dim == 3 ? (double *)st->u[2] : nullptr};
+    const double *uc[3] = {u[0], u[1], u[2]};
+    const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
+    PcgVecs<double> v = vecs(g);
+    const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
+    int unconv_any = 0;
+    chns_step_stats last;
+    memset(&last, 0, sizeof last);
+    for (int n = 0; n < nsteps; ++n) {
+        SolveOut o;
+        memset(&last, 0, sizeof last);
+        // S1, S2
+        launch_ch_rhs(dim, geo, k, phi, uc, g->rch, g->phihat, s);
+        HIPCHK(pcg_solve(g->ch, dim, OP_CH, ch, (const double *)g->rch, g->phihat, p.rtol_ch, p.max_iter,
+                         next_predict(g->last_iters[0]), g->red, v, s, &o));
+        if (int rc = check_solve(o, "Cahn-Hilliard")) return rc;
+        g->last_iters[0] = o.iters;
+        last.iters_ch = o.iters;
+        last.res_ch = o.rel_res;
+        last.unconverged |= o.unconverged ? 1 : 0;
+        // S3, S4
+        launch_mu(dim, geo, k, phi, g->phihat, mu, s);
+        launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);
+        // S5..S7
+        for (int a = 0; a < dim; ++a) {
+            Level<double> &L0 = g->mom.lev[0];
+            double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, g->rhs, g->ustar[a], s);
+            mg_setup(g->mom, dim, s);
+            HIPCHK(pcg_solve(g->mom, dim, OP_SLOT, ch, (const double *)g->rhs, g->ustar[a], p.rtol_mom, p.max_iter,
+                             next_predict(g->last_iters[1 + a]), g->red, v, s, &o));
+            if (int rc = check_solve(o, "momentum")) return rc;
+            g->last_iters[1 + a] = o.iters;
+            last.iters_mom[a] = o.iters;
+            last.res_mom[a] = o.rel_res;
+            last.unconverged |= o.unconverged ? (2 << a) : 0;
+        }
+        // S8
+        {
+            Level<double> &L0 = g->pres.lev[0];
+            double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+            launch_p_setup(dim, geo, k, g->phi_new, usc, L0.s, cs, g->rhs, s);
+            remove_mean(geo, g->rhs, g->red, s);
+            mg_setup(g->pres, dim, s);
+            HIPCHK(pcg_solve(g->pres, dim, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, p.max_iter,
+                             next_predict(g->last_iters[4]), g->red, v, s, &o));
+            if (int rc = check_solve(o, "pressure")) return rc;
+            g->last_iters[4] = o.iters;
+            last.iters_p = o.iters;
+            last.res_p = o.rel_res;
+            last.unconverged |= o.unconverged ? 16 : 0;
+            remove_mean(geo, pr, g->red, s);
+        }
+        // S9
+        launch_project(dim, geo, k, g->phi_new, usc, pr, phi, u, s);
+        HIPCHK(hipGetLastError());
+        unconv_any |= last.unconverged;
+    }
+    if (stats) {
+        launch_diagnostics(dim, geo, k, phi, uc, g->diag, g->red.counter, g->diag + 8 * kMaxBlocks, s);
+        double h8[8];
+        HIPCHK(hipMemcpyAsync(h8, g->diag + 8 * kMaxBlocks, sizeof h8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double hd = std::pow(g->h, dim);
+        last.mass_plus = h8[0] * hd;
+        last.mass_minus = h8[1] * hd;
+        const double kin = h8[2] * hd;
+        const double fre = (h8[3] * hd + 0.5 * p.Cn * p.Cn * h8[4] * hd) / (p.Cn * p.We);
+        const double grav = p.inv_Fr * h8[5] * hd;
+        last.energy = kin + fre + grav;
+        last.umax = h8[6];
+        last.divmax = h8[7];
+        *stats = last;
+    }
+    g->last = last;
+    if (unconv_any) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "unconverged solves (bit 0 CH, 1..3 momentum, 4 pressure): mask %d", unconv_any);
+        g_err = buf;
+        return CHNS_ENOCONV;
+    }
+    return CHNS_OK;
+}
+
+int chns_solve_pressure(chns_grid *g, const void *rho, const void *rhs, void *p, double rtol, int max_iter,
+                        chns_solve_stats *stats) {
+    if (!g || !rho || !rhs || !p) return fail(CHNS_EINVAL, "NULL argument");
+    if (!(rtol > 0.0) || max_iter < 1) return fail(CHNS_EINVAL, "rtol must be > 0 and max_iter >= 1");
+    ProfScope prof_scope(g);
+    const int dim = g->dim;
+    hipStream_t s = g->stream;
+    Level<double> &L0 = g->pres.lev[0];
+    double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+    launch_p_coef_from_rho(dim, g->geo, 1.0 / (g->h * g->h), (const double *)rho, L0.s, cs, s);
+    HIPCHK(hipMemcpyAsync(g->rhs, rhs, sizeof(double) * g->geo.N, hipMemcpyDeviceToDevice, s));
+    remove_mean(g->geo, g->rhs, g->red, s);
+    mg_setup(g->pres, dim, s);
+    PcgVecs<double> v = vecs(g);
+    SolveOut o;
+    HIPCHK(pcg_solve(g->pres, dim, OP_SLOT, ChOp{0, 0, 0}, (const double *)g->rhs, (double *)p, rtol, max_iter,
+                     next_predict(g->last_iters[5]), g->red, v, s, &o));
+    if (int rc = check_solve(o, "pressure")) return rc;
+    g->last_iters[5] = o.iters;
+    remove_mean(g->geo, (double *)p, g->red, s);
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats) {
+        stats->iters = o.iters;
+        stats->rel_res = o.rel_res;
+    }
+    return o.unconverged ? CHNS_ENOCONV : CHNS_OK;
+}
+
+int chns_apply_pressure_operator(chns_grid *g, const void *rho, const void *x, void *y) {
+    if (!g || !rho || !x || !y) return fail(CHNS_EINVAL, "NULL argument");
+    Level<double> &L0 = g->pres.lev[0];
+    double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+    launch_p_coef_from_rho(g->dim, g->geo, 1.0 / (g->h * g->h), (const double *)rho, L0.s, cs, g->stream);
+    slot_apply(g->pres, g->dim, (const double *)x, (double *)y, g->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return CHNS_OK;
+}
+
+static void prof_release(Prof &P) {
+    if (P.ev) {
+        for (int i = 0; i < 2 * P.cap; ++i) (void)hipEventDestroy(P.ev[i]);
+    }
+    delete[] P.ev;
+    delete[] P.cls;
+    delete[] P.bytes;
+    P.ev = nullptr;
+    P.cls = nullptr;
+    P.bytes = nullptr;
+    P.cap = 0;
+}
+
+int chns_set_timing(chns_grid *g, int enable) {
+    if (!g) return fail(CHNS_EINVAL, "NULL handle");
+    Prof &P = g->prof;
+    if (enable && !P.ev) {
+        const int cap = 4096;
+        P.ev = new (std::nothrow) hipEvent_t[2 * cap];
+        P.cls = new (std::nothrow) int[cap];
+        P.bytes = new (std::nothrow) double[cap];
+        if (!P.ev || !P.cls || !P.bytes) {
+            prof_release(P);
+            return fail(CHNS_ENOMEM, "host allocation failed");
+        }
+        for (int i = 0; i < 2 * cap; ++i) {
+            hipError_t e = hipEventCreate(&P.ev[i]);
+            if (e != hipSuccess) {
+                P.cap = i / 2;
+                prof_release(P);
+                return fail(CHNS_EDEVICE, std::string("hipEventCreate: ") + hipGetErrorString(e));
+            }
+        }
+        P.cap = cap;
+    }
+    P.enabled = enable ? 1 : 0;
+    P.n = 0;
+    for (int c = 0; c < K_NCLASS; ++c) {
+        P.launches[c] = 0;
+        P.ms[c] = 0.0;
+        P.total_bytes[c] = 0.0;
+    }
+    return CHNS_OK;
+}
+
+int chns_get_timing(chns_grid *g, chns_kernel_timing *out, int max, int *count) {
+    if (!g || !count) return fail(CHNS_EINVAL, "NULL argument");
+    const Prof &P = g->prof;
+    int n = 0;
+    for (int c = 0; c < K_NCLASS; ++c) {
+        if (!P.launches[c]) continue;
+        if (out && n < max) {
+            memset(&out[n], 0, sizeof out[n]);
+            strncpy(out[n].name, kclass_name(c), sizeof out[n].name - 1);
+            out[n].launches = P.launches[c];
+            out[n].ms = P.ms[c];
+            out[n].bytes = P.total_bytes[c];
+        }
+        ++n;
+    }
+    *count = n;
+    return CHNS_OK;
+}
+
+int chns_destroy_grid(chns_grid *g) {
+    if (g) prof_release(g->prof);
+    delete g;
+    return CHNS_OK;
+}
+
+const char *chns_error_string(int code) {
+    switch (code) {
+        case CHNS_OK: return "success";
+        case CHNS_ENOCONV: return "a linear solve reached max_iter before the tolerance";
+        case CHNS_EINVAL: return "invalid argument or unsupported grid";
+        case CHNS_ENOMEM: return "workspace too small";
+        case CHNS_EDEVICE: return "HIP runtime error";
+        case CHNS_ENONFINITE: return "non-finite value in a residual";
+        default: return "unknown error code";
+    }
+}
+
+int chns_last_error(char *buf, size_t len) {
+    if (buf && len > 0) {
+        size_t n = g_err.size() < len - 1 ? g_err.size() : len - 1;
+        memcpy(buf, g_err.data(), n);
+        buf[n] = '\0';
+    }
+    return (int)g_err.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,222 @@
+// Internal definitions shared by the HIP translation units of libchns.
+// Grid geometry, neighbour indexing on the uniform MAC grid, deterministic
+// block reductions and the handle layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/chns.h"
+
+namespace chns {
+
+constexpr int kMaxLev = 16;
+constexpr int kMaxCoarse = 512;     // cells of the coarsest (dense) level
+constexpr int kBlock = 256;         // threads per block of the linear kernels
+constexpr int kMaxBlocks = 4096;    // grid-stride cap (fixes reduction order)
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+struct Geo {
+    int n[3];      // cells per axis (n[2] = 1 in 2D)
+    int per[3];    // 1: periodic, 0: walled (Neumann-type at both ends)
+    long long N;   // total cells
+};
+
+__host__ __device__ inline long long stride_of(const Geo &g, int a) {
+    return a == 0 ? 1LL : (a == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
+}
+
+__device__ inline void cell_coords(const Geo &g, long long c, int &i, int &j, int &k) {
+    i = (int)(c % g.n[0]);
+    long long t = c / g.n[0];
+    j = (int)(t % g.n[1]);
+    k = (int)(t / g.n[1]);
+}
+
+// Index of c - e_a (wrapping on periodic axes); -1 outside a walled axis.
+__device__ inline long long nb_lo(const Geo &g, long long c, int ia, int a) {
+    const long long s = stride_of(g, a);
+    if (ia > 0) return c - s;
+    return g.per[a] ? c + (long long)(g.n[a] - 1) * s : -1;
+}
+// Index of c + e_a; -1 outside a walled axis.
+__device__ inline long long nb_hi(const Geo &g, long long c, int ia, int a) {
+    const long long s = stride_of(g, a);
+    if (ia < g.n[a] - 1) return c + s;
+    return g.per[a] ? c - (long long)(g.n[a] - 1) * s : -1;
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+inline int grid_for(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (int)(b > kMaxBlocks ? kMaxBlocks : b);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions: fixed element -> block mapping (grid-stride with
+// a fixed grid), wave shuffles then LDS inside the block, and a fixed-order
+// sum over the block partials done by the last block to finish.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, kWave));
+    return v;
+}
+
+// Sum over the block; result valid in thread 0.  lds: >= blockDim/64 doubles.
+__device__ inline double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) r += lds[k];
+    return r;
+}
+__device__ inline double block_max(double v, double *lds) {
+    v = wave_max(v);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) r = fmax(r, lds[k]);
+    return r;
+}
+
+// Returns true in every thread of the block that finished last.  Thread 0
+// must have written this block's partials before the call.
+__device__ inline bool last_block(unsigned int *counter) {
+    __shared__ int am_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = atomicAdd(counter, 1u);
+        am_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (am_last) __threadfence();
+    return am_last != 0;
+}
+
+// Sum of nparts partials in a fixed order (block-wide); result in thread 0.
+__device__ inline double sum_partials(const double *part, int nparts, double *lds) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) v += ((volatile const double *)part)[k];
+    return block_sum(v, lds);
+}
+
+// ---------------------------------------------------------------------------
+// PCG scalar block (device memory)
+// ---------------------------------------------------------------------------
+struct Scal {
+    double rz, pq, rr, bb, alpha, beta, rtol2, sum0, sum1, zmean;
+    int done, iter, max_iter, nonfinite;
+    int unconverged, pad0, pad1, pad2;
+};
+
+// ---------------------------------------------------------------------------
+// multigrid operator slot:  A x = s x - sum_b D_b(cs_b G_b x) h^2,
+// i.e. (A x)_c = s_c x_c + sum_b [cs_b(c) (x_c - x_{c-e_b}) + cs_b(c+e_b) (x_c - x_{c+e_b})]
+// with cs_b pre-divided by the squared level spacing; walled axes carry no
+// boundary term (Neumann type), Dirichlet contributions are folded into s.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Level {
+    Geo g;
+    T *s;
+    T *cs[3];
+    T *x, *b, *r;   // level >= 1 own x, b; every level owns r
+};
+
+template <typename T>
+struct Slot {
+    int nlev;
+    int singular;
+    int ncoarse;
+    Level<T> lev[kMaxLev];
+    T *Ainv;        // coarsest-level inverse, ncoarse x ncoarse
+    T *aug;         // scratch for the inverse, ncoarse x 2 ncoarse
+};
+
+// Reduction scratch shared by all solves of a handle.
+struct Red {
+    double *part0, *part1, *part2;   // kMaxBlocks partials each
+    unsigned int *counter;     // last-block counters (several)
+    Scal *scal;                // device scalars
+};
+
+// ---------------------------------------------------------------------------
+// optional per-kernel timing (hipEvent pairs around every launch, grouped by
+// kernel class, with the algorithmic bytes of each launch)
+// ---------------------------------------------------------------------------
+enum KClass {
+    K_CH_RHS = 0, K_MU, K_PHI_UPDATE, K_MOM_SETUP, K_P_SETUP, K_PROJECT,
+    K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE, K_MG_SETUP,
+    K_PCG_APPLY, K_PCG_UPDATE, K_PCG_DOT, K_PCG_INIT, K_MEAN, K_DIAG,
+    K_NCLASS
+};
+
+struct Prof {
+    int enabled;
+    int cap, n;                  // event pairs in the pool / in use
+    hipEvent_t *ev;              // 2 * cap events
+    int *cls;
+    double *bytes;
+    int launches[K_NCLASS];
+    double ms[K_NCLASS];
+    double total_bytes[K_NCLASS];
+};
+
+extern thread_local Prof *g_prof;
+void prof_begin(int cls, double bytes, hipStream_t st);
+void prof_end(hipStream_t st);
+int prof_flush();                // synchronise and accumulate; 0 on success
+const char *kclass_name(int cls);
+
+}  // namespace chns
+
+// Launch with optional timing: cls = KClass, bytes = algorithmic bytes.
+#define TLAUNCH(cls, bytes, kern, grid, block, st, ...)                                   \
+    do {                                                                                  \
+        if (chns::g_prof) chns::prof_begin((cls), (double)(bytes), (st));                 \
+        hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                        \
+        if (chns::g_prof) chns::prof_end(st);                                             \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+struct chns_grid {
+    chns_grid_desc desc;
+    chns_props props;
+    int props_set;
+    hipStream_t stream;
+    chns::Geo geo;
+    int dim;
+    double h;
+    // state-independent workspace buffers (double, N cells each)
+    double *phi_new, *phihat, *rch, *ustar[3], *rhs;
+    double *vr, *vz, *vp0, *vp1, *vq, *vt;   // PCG vectors
+    chns::Slot<double> ch, mom, pres;
+    chns::Red red;
+    double *diag;                            // diagnostics scratch
+    int last_iters[6];                       // iteration-count predictions
+    chns_step_stats last;
+    chns::Prof prof;
+    void *ws;
+    size_t ws_bytes;
+};

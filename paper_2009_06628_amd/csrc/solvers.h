@@ -1,0 +1,54 @@
+// Host-side entry points of the multigrid-preconditioned CG machinery.
+#pragma once
+#include "common.h"
+
+namespace chns {
+
+enum OpKind { OP_SLOT = 0, OP_CH = 1 };
+
+template <typename T>
+struct PcgVecs {
+    T *r, *z, *p0, *p1, *q, *t;
+};
+
+struct SolveOut {
+    int iters;
+    double rel_res;
+    int unconverged;
+    int nonfinite;
+};
+
+// Constant-coefficient CH operator M = I - a L + b L L and its
+// preconditioner operator I + c(-L), c = sqrt(b).
+struct ChOp {
+    double a, b, ih2;   // M = I - a L + b L L, ih2 = 1/h^2
+};
+
+// Coarsen the slot's level-0 coefficients onto every level and invert the
+// coarsest operator (deterministic, on the stream).
+template <typename T>
+void mg_setup(Slot<T> &S, int dim, hipStream_t st);
+
+// One symmetric V(1,1) cycle with red-black Gauss-Seidel: x0 ~ A^{-1} b0.
+template <typename T>
+void mg_vcycle(Slot<T> &S, int dim, const T *b0, T *x0, const int *done, hipStream_t st);
+
+// PCG on A x = b (A = slot operator, or the CH operator preconditioned by
+// two V-cycles of the slot).  x is the initial guess on entry.  predict is
+// the number of iterations launched before the first host check.
+// Returns hipSuccess or the first HIP error.
+template <typename T>
+hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x, double rtol,
+                     int max_iter, int predict, Red &red, PcgVecs<T> &v, hipStream_t st,
+                     SolveOut *out);
+
+// Subtract the mean of a cell array (deterministic).  Used for the
+// singular pressure system (right-hand side, then the solution gauge).
+template <typename T>
+void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st);
+
+// Apply the slot operator at level 0: y = A x (tests / residual checks).
+template <typename T>
+void slot_apply(Slot<T> &S, int dim, const T *x, T *y, hipStream_t st);
+
+}  // namespace chns

@@ -1,0 +1,45 @@
+// Host launchers of the time-step kernels (S1..S9 and diagnostics).
+#pragma once
+#include "common.h"
+
+namespace chns {
+
+// Constants of one step, derived from chns_props on the host.
+struct StepConst {
+    double h, ih, ih2;
+    double dt, S, Cn, Pe, kM;          // kM = 1/(Pe Cn)
+    double alpha, beta, gamma, xi;     // mixture maps
+    double inv_Re, inv_We, We, inv_Fr;
+};
+
+// S1: r = phi - dt D(u A phi) + dt kM L(psi'(phi) - S phi); phihat = phi.
+void launch_ch_rhs(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
+                   double *r, double *phihat, hipStream_t st);
+// S3: mu = psi'(phi) + S (phihat - phi) - Cn^2 L phihat.
+void launch_mu(int dim, const Geo &g, const StepConst &k, const double *phi, const double *phihat, double *mu,
+               hipStream_t st);
+// S4: phi_new = phi - dt D(u A phi - kM G mu).
+void launch_phi_update(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
+                       const double *mu, double *phi_new, hipStream_t st);
+// S5-S7 set-up for component a: level-0 coefficients of the momentum slot,
+// right-hand side, and initial guess ustar_a = u_a.
+void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const double *phi, const double *phi_new,
+                      const double *mu, const double *const u[3], double *s, double *const cs[3], double *rhs,
+                      double *ustar, hipStream_t st);
+// S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new) and
+// rhs = -(We/dt) D ustar.
+void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
+                    double *s, double *const cs[3], double *rhs, hipStream_t st);
+// Pressure coefficients from a given cell density (stand-alone solve).
+void launch_p_coef_from_rho(int dim, const Geo &g, double ih2, const double *rho, double *s, double *const cs[3],
+                            hipStream_t st);
+// S9: u = ustar - (dt/We) G p / rho_f; phi = phi_new.
+void launch_project(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
+                    const double *p, double *phi, double *const u[3], hipStream_t st);
+// CH slot level-0 coefficients: s = 1, cs = c / h^2.
+void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *const cs[3], hipStream_t st);
+// Diagnostics into out[0..6] = mass+, mass-, kinetic, free, gravity, umax, divmax.
+void launch_diagnostics(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
+                        double *part, unsigned int *counter, double *out, hipStream_t st);
+
+}  // namespace chns

@@ -1,0 +1,72 @@
+"""C-ABI library checks that need no GPU: it loads, exports every function
+declared in include/chns.h, and rejects bad descriptions before touching the
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2009_06628_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "chns.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(chns_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load_library()
+    names = declared_functions()
+    assert "chns_step" in names and "chns_solve_pressure" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(P.EXPORTS) >= set(names)
+
+
+def test_error_strings():
+    lib = P.load_library()
+    for code in (0, 1, -1, -2, -3, -4):
+        assert lib.chns_error_string(code)
+
+
+@pytest.mark.parametrize("n,bc", [((64, 64), ("periodic", "periodic")), ((256, 512), ("periodic", "wall")),
+                                  ((96, 96), ("periodic", "periodic")), ((128, 128, 128), ("periodic",) * 3),
+                                  ((20, 20), ("wall", "wall"))])
+def test_workspace_size_supported(n, bc):
+    b = P.workspace_size(n, 1.0 / n[0], bc)
+    cells = 1
+    for x in n:
+        cells *= x
+    assert b > 8 * cells * 10
+
+
+@pytest.mark.parametrize("n", [(50, 50), (1, 8), (0, 0), (100, 100)])
+def test_workspace_size_rejects_unsupported(n):
+    with pytest.raises(P.CHNSError) as ei:
+        P.workspace_size(n, 0.1, ("periodic", "periodic"))
+    assert ei.value.code == P.CHNS_EINVAL
+
+
+def test_create_rejects_small_workspace_before_device_use():
+    lib = P.load_library()
+    d = P.make_desc((64, 64), 1 / 64, ("periodic", "periodic"))
+    h = ctypes.c_void_p()
+    rc = lib.chns_create_grid(ctypes.byref(d), ctypes.c_void_p(4096), ctypes.c_size_t(1024), None, ctypes.byref(h))
+    assert rc == P.CHNS_ENOMEM
+    rc = lib.chns_create_grid(ctypes.byref(d), ctypes.c_void_p(4097), ctypes.c_size_t(1 << 30), None, ctypes.byref(h))
+    assert rc == P.CHNS_EINVAL
+    d.dim = 4
+    rc = lib.chns_create_grid(ctypes.byref(d), ctypes.c_void_p(4096), ctypes.c_size_t(1 << 30), None, ctypes.byref(h))
+    assert rc == P.CHNS_EINVAL
+
+
+def test_binding_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        P.create_grid((64, 64), 1 / 64, ("periodic", "periodic"))

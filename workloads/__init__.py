@@ -50,10 +50,10 @@ class Props:
     dt: float = 1e-4
     S: float = 2.0
     # linear-solver controls (relative residual, iteration cap)
-    rtol_ch: float = 1e-13
+    rtol_ch: float = 1e-15
     rtol_mom: float = 1e-13
     rtol_p: float = 1e-12
-    max_iter: int = 200
+    max_iter: int = 300
 
     def copy(self, **kw) -> "Props":
         return dataclasses.replace(self, **kw)
