@@ -153,6 +153,7 @@ struct Bump {
 template <typename T>
 void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
     S.nlev = P.nlev;
+    S.lsb = 0;
     S.singular = singular;
     S.ncoarse = (int)P.lev[P.nlev - 1].N;
     for (int l = 0; l < P.nlev; ++l) {
@@ -161,11 +162,12 @@ void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
         const size_t n = (size_t)L.g.N;
         L.s = B.take<T>(n);
         for (int b = 0; b < 3; ++b) L.cs[b] = b < P.dim ? B.take<T>(n) : nullptr;
+        L.invd = B.take<T>(n);
         L.r = B.take<T>(n);
         L.x = l ? B.take<T>(n) : nullptr;
         L.b = l ? B.take<T>(n) : nullptr;
     }
-    S.Ainv = B.take<T>((size_t)S.ncoarse * S.ncoarse);
+    S.Ainv = B.take<double>((size_t)S.ncoarse * S.ncoarse);
     S.aug = nullptr;
 }
 
@@ -186,7 +188,7 @@ void layout(Bump &B, const Plan &P, chns_grid *g) {
     carve_slot(B, P, g->mom, 0);
     carve_slot(B, P, g->pres, 1);
     const int nc = g->ch.ncoarse;
-    double *aug = B.take<double>((size_t)nc * 2 * nc);
+    double *aug = nc > kLdsInverse ? B.take<double>((size_t)nc * nc) : nullptr;
     g->ch.aug = g->mom.aug = g->pres.aug = aug;
     g->red.part0 = B.take<double>(kMaxBlocks);
     g->red.part1 = B.take<double>(kMaxBlocks);

@@ -16,6 +16,8 @@ constexpr int kMaxCoarse = 512;     // cells of the coarsest (dense) level
 constexpr int kBlock = 256;         // threads per block of the linear kernels
 constexpr int kMaxBlocks = 4096;    // grid-stride cap (fixes reduction order)
 constexpr int kWave = 64;
+constexpr int kLdsInverse = 64;     // coarsest sizes inverted in LDS
+constexpr int kSBThreads = 1024;    // single-workgroup coarse-level kernels
 
 // ---------------------------------------------------------------------------
 // geometry
@@ -112,6 +114,17 @@ __device__ inline bool last_block(unsigned int *counter) {
     return am_last != 0;
 }
 
+// Sum over the block; result returned to every thread.
+__device__ inline double block_sum_all(double v, double *lds) {
+    double r = block_sum(v, lds);
+    __syncthreads();
+    if (threadIdx.x == 0) lds[0] = r;
+    __syncthreads();
+    r = lds[0];
+    __syncthreads();
+    return r;
+}
+
 // Sum of nparts partials in a fixed order (block-wide); result in thread 0.
 __device__ inline double sum_partials(const double *part, int nparts, double *lds) {
     double v = 0.0;
@@ -139,17 +152,20 @@ struct Level {
     Geo g;
     T *s;
     T *cs[3];
-    T *x, *b, *r;   // level >= 1 own x, b; every level owns r
+    T *invd;        // 1 / A_cc
+    T *x, *b, *r;   // level >= 1 own x, b; every level owns r (also the
+                    // scratch of the fused prolongation + smoothing pass)
 };
 
 template <typename T>
 struct Slot {
     int nlev;
+    int lsb;        // first level handled by the single-workgroup kernel
     int singular;
     int ncoarse;
     Level<T> lev[kMaxLev];
-    T *Ainv;        // coarsest-level inverse, ncoarse x ncoarse
-    T *aug;         // scratch for the inverse, ncoarse x 2 ncoarse
+    double *Ainv;   // coarsest-level inverse, ncoarse x ncoarse (FP64)
+    double *aug;    // scratch for the inverse when ncoarse > kLdsInverse
 };
 
 // Reduction scratch shared by all solves of a handle.

@@ -1,227 +1,339 @@
 // Matrix-free multigrid-preconditioned conjugate gradients on the uniform
 // grid (gfx950).  The elliptic solver is not fixed by the paper (its coupled
-// system goes to Krylov solvers with ASM / algebraic multigrid
-// preconditioners); this is a geometric cell-centred multigrid:
+// system goes to Krylov solvers with ASM / algebraic-multigrid
+// preconditioners, and it names matrix-free multigrid as future work); this
+// is a geometric cell-centred multigrid:
 //   * operator       (A x)_c = s_c x_c + sum_b cs_b(c)(x_c - x_{c-e_b})
 //                                       + cs_b(c+e_b)(x_c - x_{c+e_b}),
-//   * smoother       red-black Gauss-Seidel, pre (red, black), post (black,
-//                    red): the V-cycle is a symmetric positive definite
-//                    preconditioner;
+//   * smoother       red-black Gauss-Seidel; pre-smoothing (red, black) from
+//                    a zero guess, post-smoothing (black, red): the V-cycle is
+//                    a symmetric positive definite preconditioner;
 //   * transfers      cell-centred bilinear / trilinear prolongation P and
 //                    full-weighting restriction R = P^T / 2^d;
 //   * coarse levels  re-discretised: s averaged over children, face
 //                    coefficients averaged over the fine faces of a coarse
 //                    face and divided by 4 (spacing doubles);
-//   * coarsest       explicit inverse (Gauss-Jordan, one workgroup), with a
-//                    rank-one shift tau 1 1^T for the singular pressure
-//                    operator;
-//   * reductions     deterministic: fixed grid-stride partition, wave
-//                    shuffles, fixed-order final sum by the last block.
-// PCG scalars stay on the device; every iteration kernel returns at once
-// when the device-side "done" flag is set, so the host launches iterations
-// in chunks and checks the flag once per chunk.
+//   * coarsest       explicit FP64 inverse (Gauss-Jordan in one workgroup)
+//                    with a rank-one shift tau 1 1^T for the singular
+//                    pressure operator.
+// Launch structure: levels with more than kSBCells cells use one grid-wide
+// kernel per pass (5 per level: fused zero-guess pre-smoothing, residual,
+// restriction, fused prolongation + black sweep, red sweep); all smaller
+// levels run inside ONE single-workgroup kernel, which removes the launch
+// latency that otherwise dominates the coarse levels.
+// Reductions are deterministic and fence-free: per-block partials from a
+// fixed grid-stride partition, summed in a fixed order either by a
+// one-workgroup finalize kernel or redundantly by every block of the kernel
+// that consumes them.  PCG scalars live on the device; every iteration
+// kernel returns at once when the device "done" flag is set, so the host
+// launches iterations in chunks and checks the flag once per chunk.
+#include <cstdlib>
+
 #include "solvers.h"
 
 namespace chns {
 
+// Levels at or below this many cells run in the single-workgroup kernel
+// (default; the CHNS_SB_CELLS environment variable overrides it at set-up).
+constexpr long long kSBCellsDefault = 2048;
+
+static long long sb_cells() {
+    static long long v = -1;
+    if (v < 0) {
+        const char *e = getenv("CHNS_SB_CELLS");
+        v = e ? atoll(e) : kSBCellsDefault;
+        if (v < 1) v = 1;
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------------------
-// stencil helpers
+// per-cell building blocks (shared by the grid-wide and single-block kernels)
 // ---------------------------------------------------------------------------
+template <int DIM>
+__device__ inline void coords_of(const Geo &g, long long c, int ia[3]) {
+    cell_coords(g, c, ia[0], ia[1], ia[2]);
+}
+
+// (A x)_c
 template <typename T, int DIM>
-__device__ inline void op_at(const Level<T> &L, const T *__restrict__ x, long long c, int i, int j, int k,
-                             double &Ax, double &diag, double &offsum) {
-    // Ax = (A x)_c, diag = A_cc, offsum = sum of cs * x_nb (for Gauss-Seidel)
+__device__ inline double apply_at(const Level<T> &L, const T *__restrict__ x, long long c, const int ia[3]) {
     const Geo &g = L.g;
     const double xc = (double)x[c];
-    double d = (double)L.s[c];
-    double off = 0.0;
-    const int ia[3] = {i, j, k};
+    double acc = (double)L.s[c] * xc;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        long long lo = nb_lo(g, c, ia[b], b);
-        long long hi = nb_hi(g, c, ia[b], b);
-        if (lo >= 0) {
-            double w = (double)L.cs[b][c];
-            d += w;
-            off += w * (double)x[lo];
-        }
-        if (hi >= 0) {
-            double w = (double)L.cs[b][hi];
-            d += w;
-            off += w * (double)x[hi];
-        }
+        const long long lo = nb_lo(g, c, ia[b], b);
+        const long long hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) acc += (double)L.cs[b][c] * (xc - (double)x[lo]);
+        if (hi >= 0) acc += (double)L.cs[b][hi] * (xc - (double)x[hi]);
     }
-    diag = d;
-    offsum = off;
-    Ax = d * xc - off;
+    return acc;
 }
 
-// ---------------------------------------------------------------------------
-// V-cycle kernels
-// ---------------------------------------------------------------------------
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_rbgs(Level<T> L, const T *__restrict__ b, T *__restrict__ x,
-                                                 int color, int zero_init, const int *__restrict__ done) {
-    if (*done) return;
-    const Geo g = L.g;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        const int col = (i + j + k) & 1;
-        if (zero_init) {
-            if (col != color) {
-                x[c] = (T)0;
-                continue;
-            }
-            double d = (double)L.s[c];
-            const int ia[3] = {i, j, k};
+// sum_b cs * x_nb over the neighbours (x given by a functor)
+template <typename T, int DIM, typename F>
+__device__ inline double offsum_at(const Level<T> &L, long long c, const int ia[3], F xv) {
+    const Geo &g = L.g;
+    double acc = 0.0;
 #pragma unroll
-            for (int bb = 0; bb < DIM; ++bb) {
-                if (nb_lo(g, c, ia[bb], bb) >= 0) d += (double)L.cs[bb][c];
-                long long hi = nb_hi(g, c, ia[bb], bb);
-                if (hi >= 0) d += (double)L.cs[bb][hi];
-            }
-            x[c] = (T)((double)b[c] / d);
-            continue;
-        }
-        if (col != color) continue;
-        double Ax, d, off;
-        op_at<T, DIM>(L, x, c, i, j, k, Ax, d, off);
-        x[c] = (T)(((double)b[c] + off) / d);
+    for (int b = 0; b < DIM; ++b) {
+        const long long lo = nb_lo(g, c, ia[b], b);
+        const long long hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) acc += (double)L.cs[b][c] * xv(lo);
+        if (hi >= 0) acc += (double)L.cs[b][hi] * xv(hi);
+    }
+    return acc;
+}
+
+template <typename T, int DIM>
+__device__ inline void invd_cell(const Level<T> &L, long long c) {
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    double d = (double)L.s[c];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        if (nb_lo(L.g, c, ia[b], b) >= 0) d += (double)L.cs[b][c];
+        const long long hi = nb_hi(L.g, c, ia[b], b);
+        if (hi >= 0) d += (double)L.cs[b][hi];
+    }
+    L.invd[c] = (T)(1.0 / d);
+}
+
+// zero-guess pre-smoothing: red x = b / d, black from those red values
+template <typename T, int DIM>
+__device__ inline void presmooth_cell(const Level<T> &L, const T *__restrict__ b, T *__restrict__ x, long long c) {
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    const int col = (ia[0] + ia[1] + ia[2]) & 1;
+    if (col == 0) {
+        x[c] = (T)((double)b[c] * (double)L.invd[c]);
+    } else {
+        auto red = [&](long long e) { return (double)b[e] * (double)L.invd[e]; };
+        x[c] = (T)(((double)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (double)L.invd[c]);
     }
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_residual(Level<T> L, const T *__restrict__ b, const T *__restrict__ x,
-                                                     T *__restrict__ r, const int *__restrict__ done) {
-    if (*done) return;
-    const Geo g = L.g;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        double Ax, d, off;
-        op_at<T, DIM>(L, x, c, i, j, k, Ax, d, off);
-        r[c] = (T)((double)b[c] - Ax);
-    }
+__device__ inline void residual_cell(const Level<T> &L, const T *__restrict__ b, const T *__restrict__ x,
+                                     long long c) {
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    L.r[c] = (T)((double)b[c] - apply_at<T, DIM>(L, x, c, ia));
 }
 
-// Per-axis weights of the cell-centred linear prolongation: fine cell f
-// takes 3/4 of its parent f/2 and 1/4 of the coarse neighbour on its side
-// (f even: parent - 1, f odd: parent + 1); past a walled boundary the
-// neighbour is replaced by the parent (weight 1).
-__device__ inline void prolong_axis(int f, int nc, int per, int &c0, double &w0, int &c1, double &w1) {
+// cell-centred linear prolongation along one axis: fine f takes 3/4 of its
+// parent f/2 and 1/4 of the coarse neighbour on its side; past a wall the
+// neighbour is the parent itself (weight 1 in total)
+__device__ inline void pro_axis(int f, int nc, int per, int &c0, int &c1, double &w0, double &w1) {
     const int p = f >> 1;
     int q = (f & 1) ? p + 1 : p - 1;
     c0 = p;
     if (q < 0 || q >= nc) {
         if (per) {
-            q = (q + nc) % nc;
+            q = q < 0 ? nc - 1 : 0;
         } else {
-            w0 = 1.0;
             c1 = p;
+            w0 = 1.0;
             w1 = 0.0;
             return;
         }
     }
-    w0 = 0.75;
     c1 = q;
+    w0 = 0.75;
     w1 = 0.25;
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gf, Geo gc, const T *__restrict__ xc, T *__restrict__ xf,
-                                                        const int *__restrict__ done) {
-    if (*done) return;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < gf.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(gf, c, i, j, k);
-        int ci[3][2];
-        double wi[3][2];
-        const int fi[3] = {i, j, k};
+__device__ inline double prolong_at(const Geo &gf, const Geo &gc, const T *__restrict__ xc, const int fi[3]) {
+    int c0[3], c1[3];
+    double w0[3], w1[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a < DIM) {
-                prolong_axis(fi[a], gc.n[a], gc.per[a], ci[a][0], wi[a][0], ci[a][1], wi[a][1]);
-            } else {
-                ci[a][0] = ci[a][1] = 0;
-                wi[a][0] = 1.0;
-                wi[a][1] = 0.0;
-            }
+    for (int a = 0; a < 3; ++a) {
+        if (a < DIM) {
+            pro_axis(fi[a], gc.n[a], gc.per[a], c0[a], c1[a], w0[a], w1[a]);
+        } else {
+            c0[a] = c1[a] = 0;
+            w0[a] = 1.0;
+            w1[a] = 0.0;
         }
-        double v = 0.0;
+    }
+    const long long nx = gc.n[0], nxy = (long long)gc.n[0] * gc.n[1];
+    double v = 0.0;
 #pragma unroll
-        for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz) {
+        const long long kz = (dz ? c1[2] : c0[2]) * nxy;
+        const double wz = dz ? w1[2] : w0[2];
 #pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
+        for (int dy = 0; dy < 2; ++dy) {
+            const long long ky = kz + (dy ? c1[1] : c0[1]) * nx;
+            const double wyz = wz * (dy ? w1[1] : w0[1]);
+            v += wyz * (w0[0] * (double)xc[ky + c0[0]] + w1[0] * (double)xc[ky + c1[0]]);
+        }
+    }
+    return v;
+}
+
+// full weighting along one axis: the four fine cells 2I-1 .. 2I+2 with
+// weights (1,3,3,1)/8; at a wall the missing outer cell's weight moves to the
+// adjacent child (4,3,1)/8 -- exactly the transpose of pro_axis / 2.  Always
+// four taps (an absent one gets weight 0 and a valid index) so that the
+// loads of a fully unrolled stencil issue together.
+__device__ inline void res_axis(int I, int nc, int nf, int per, int f[4], double w[4]) {
+    const bool lo = (I > 0) || per, hi = (I < nc - 1) || per;
+    f[0] = I > 0 ? 2 * I - 1 : (per ? nf - 1 : 0);
+    w[0] = lo ? 0.125 : 0.0;
+    f[1] = 2 * I;
+    w[1] = lo ? 0.375 : 0.5;
+    f[2] = 2 * I + 1;
+    w[2] = hi ? 0.375 : 0.5;
+    f[3] = I < nc - 1 ? 2 * I + 2 : (per ? 0 : nf - 1);
+    w[3] = hi ? 0.125 : 0.0;
+}
+
+template <typename T, int DIM>
+__device__ inline void restrict_cell(const Geo &gf, const Geo &gc, const T *__restrict__ rf, T *__restrict__ bc,
+                                     long long c) {
+    int I[3];
+    coords_of<DIM>(gc, c, I);
+    int fx[4], fy[4], fz[4];
+    double wx[4], wy[4], wz[4];
+    res_axis(I[0], gc.n[0], gf.n[0], gc.per[0], fx, wx);
+    res_axis(I[1], gc.n[1], gf.n[1], gc.per[1], fy, wy);
+    if (DIM == 3) res_axis(I[2], gc.n[2], gf.n[2], gc.per[2], fz, wz);
+    const long long nx = gf.n[0], nxy = (long long)gf.n[0] * gf.n[1];
+    double v = 0.0;
 #pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    const double w = wi[0][dx] * wi[1][dy] * wi[2][dz];
-                    const long long idx = ci[0][dx] + (long long)gc.n[0] * (ci[1][dy] + (long long)gc.n[1] * ci[2][dz]);
-                    v += w * (double)xc[idx];
-                }
-        xf[c] = (T)((double)xf[c] + v);
+    for (int a = 0; a < (DIM == 3 ? 4 : 1); ++a) {
+        const long long kz = DIM == 3 ? fz[a] * nxy : 0;
+        const double wza = DIM == 3 ? wz[a] : 1.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const long long row = kz + fy[q] * nx;
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s += wx[e] * (double)rf[row + fx[e]];
+            v += (wy[q] * wza) * s;
+        }
+    }
+    bc[c] = (T)v;
+}
+
+// fused prolongation + black sweep: writes tmp = {red: x + P e, black:
+// GS update from those red values}; x is left untouched
+template <typename T, int DIM>
+__device__ inline void prolong_black_cell(const Level<T> &L, const Geo &gc, const T *__restrict__ xc,
+                                          const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ tmp,
+                                          long long c) {
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    const int col = (ia[0] + ia[1] + ia[2]) & 1;
+    if (col == 0) {
+        tmp[c] = (T)((double)x[c] + prolong_at<T, DIM>(L.g, gc, xc, ia));
+    } else {
+        auto red = [&](long long e) {
+            int ie[3];
+            coords_of<DIM>(L.g, e, ie);
+            return (double)x[e] + prolong_at<T, DIM>(L.g, gc, xc, ie);
+        };
+        tmp[c] = (T)(((double)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (double)L.invd[c]);
     }
 }
 
-// R = P^T / 2^d: coarse cell I gathers the fine cells whose prolongation
-// stencil contains I (children 2I, 2I+1 and the outer neighbours 2I-1, 2I+2).
-__device__ inline int restrict_axis(int I, int nc, int nf, int per, int *fidx, double *w) {
-    int m = 0;
-    for (int f = 2 * I - 1; f <= 2 * I + 2; ++f) {
-        int ff = f;
-        if (ff < 0 || ff >= nf) {
-            if (!per) continue;
-            ff = (ff + nf) % nf;
-        }
-        int c0, c1;
-        double w0, w1;
-        prolong_axis(ff, nc, per, c0, w0, c1, w1);
-        double wt = 0.0;
-        if (c0 == I) wt += w0;
-        if (c1 == I) wt += w1;
-        if (wt != 0.0) {
-            fidx[m] = ff;
-            w[m] = wt;
-            ++m;
-        }
+// red sweep from tmp: x = {red: GS update from black tmp values, black: tmp}
+template <typename T, int DIM>
+__device__ inline void red_from_tmp_cell(const Level<T> &L, const T *__restrict__ b, const T *__restrict__ tmp,
+                                         T *__restrict__ x, long long c) {
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    const int col = (ia[0] + ia[1] + ia[2]) & 1;
+    if (col == 1) {
+        x[c] = tmp[c];
+    } else {
+        auto blk = [&](long long e) { return (double)tmp[e]; };
+        x[c] = (T)(((double)b[c] + offsum_at<T, DIM>(L, c, ia, blk)) * (double)L.invd[c]);
     }
-    return m;
+}
+
+template <typename T, int DIM>
+__device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, long long c) {
+    int I[3];
+    coords_of<DIM>(C.g, c, I);
+    const Geo &gf = F.g;
+    double s = 0.0;
+    double cs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int d3[3] = {dx, dy, dz};
+                const long long f =
+                    (2 * I[0] + dx) + (long long)gf.n[0] * ((2 * I[1] + dy) + (long long)gf.n[1] * (2 * I[2] + dz));
+                s += (double)F.s[f];
+#pragma unroll
+                for (int b = 0; b < DIM; ++b)
+                    if (d3[b] == 0) cs[b] += (double)F.cs[b][f];   // fine faces on the coarse lower b-face
+            }
+    constexpr double nchild = (DIM == 3) ? 8.0 : 4.0;
+    C.s[c] = (T)(s / nchild);
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) C.cs[b][c] = (T)(cs[b] / (nchild * 0.5) * 0.25);
+}
+
+// ---------------------------------------------------------------------------
+// grid-wide V-cycle kernels (one pass each)
+// ---------------------------------------------------------------------------
+#define GRID_LOOP(N) \
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < (N); c += (long long)gridDim.x * blockDim.x)
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_presmooth(Level<T> L, const T *__restrict__ b, T *__restrict__ x,
+                                                      const int *__restrict__ done) {
+    if (*done) return;
+    GRID_LOOP(L.g.N) presmooth_cell<T, DIM>(L, b, x, c);
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_residual(Level<T> L, const T *__restrict__ b, const T *__restrict__ x,
+                                                     const int *__restrict__ done) {
+    if (*done) return;
+    GRID_LOOP(L.g.N) residual_cell<T, DIM>(L, b, x, c);
 }
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock) k_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ bc,
                                                      const int *__restrict__ done) {
     if (*done) return;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < gc.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int I, J, K;
-        cell_coords(gc, c, I, J, K);
-        int fx[4], fy[4], fz[4];
-        double wx[4], wy[4], wz[4];
-        const int mx = restrict_axis(I, gc.n[0], gf.n[0], gc.per[0], fx, wx);
-        const int my = restrict_axis(J, gc.n[1], gf.n[1], gc.per[1], fy, wy);
-        int mz = 1;
-        fz[0] = 0;
-        wz[0] = 1.0;
-        if (DIM == 3) mz = restrict_axis(K, gc.n[2], gf.n[2], gc.per[2], fz, wz);
-        double v = 0.0;
-        for (int a = 0; a < mz; ++a)
-            for (int bq = 0; bq < my; ++bq) {
-                const long long row = (long long)gf.n[0] * (fy[bq] + (long long)gf.n[1] * fz[a]);
-                const double wyz = wy[bq] * wz[a];
-                for (int e = 0; e < mx; ++e) v += wx[e] * wyz * (double)rf[row + fx[e]];
-            }
-        bc[c] = (T)(v * (DIM == 3 ? 0.125 : 0.25));
-    }
+    GRID_LOOP(gc.N) restrict_cell<T, DIM>(gf, gc, rf, bc, c);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024) k_coarse_solve(int n, const double *__restrict__ Ainv, const T *__restrict__ b,
-                                                       T *__restrict__ x, const int *__restrict__ done) {
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_prolong_black(Level<T> L, Geo gc, const T *__restrict__ xc,
+                                                          const T *__restrict__ b, const T *__restrict__ x,
+                                                          T *__restrict__ tmp, const int *__restrict__ done) {
     if (*done) return;
+    GRID_LOOP(L.g.N) prolong_black_cell<T, DIM>(L, gc, xc, b, x, tmp, c);
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_red_from_tmp(Level<T> L, const T *__restrict__ b,
+                                                         const T *__restrict__ tmp, T *__restrict__ x,
+                                                         const int *__restrict__ done) {
+    if (*done) return;
+    GRID_LOOP(L.g.N) red_from_tmp_cell<T, DIM>(L, b, tmp, x, c);
+}
+
+// ---------------------------------------------------------------------------
+// single-workgroup kernels for the small levels
+// ---------------------------------------------------------------------------
+#define BLOCK_LOOP(N) for (long long c = threadIdx.x; c < (N); c += blockDim.x)
+
+// x = Ainv b on the coarsest level (FP64 matrix, block-wide)
+template <typename T>
+__device__ inline void coarse_solve_block(int n, const double *__restrict__ Ainv, const T *__restrict__ b,
+                                          T *__restrict__ x) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         double v = 0.0;
         const double *row = Ainv + (long long)i * n;
@@ -230,450 +342,435 @@ __global__ void __launch_bounds__(1024) k_coarse_solve(int n, const double *__re
     }
 }
 
-// ---------------------------------------------------------------------------
-// set-up kernels
-// ---------------------------------------------------------------------------
+// V-cycle over levels [l0, nlev) in one workgroup.  b0 / x0 are the
+// right-hand side / result of level l0 (they replace its own arrays).
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_coarsen(Level<T> F, Level<T> C) {
-    const Geo gf = F.g, gc = C.g;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < gc.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int I, J, K;
-        cell_coords(gc, c, I, J, K);
-        const int I3[3] = {I, J, K};
-        double s = 0.0;
-        double cs[3] = {0.0, 0.0, 0.0};
-        for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dx = 0; dx < 2; ++dx) {
-                    const int d3[3] = {dx, dy, dz};
-                    const long long f = (2 * I + dx) + (long long)gf.n[0] * ((2 * J + dy) + (long long)gf.n[1] * (2 * K + dz));
-                    s += (double)F.s[f];
-#pragma unroll
-                    for (int b = 0; b < DIM; ++b)
-                        if (d3[b] == 0) cs[b] += (double)F.cs[b][f];   // fine faces on the coarse lower b-face
-                }
-        (void)I3;
-        const double nchild = (DIM == 3) ? 8.0 : 4.0;
-        C.s[c] = (T)(s / nchild);
-#pragma unroll
-        for (int b = 0; b < DIM; ++b) C.cs[b][c] = (T)(cs[b] / (nchild * 0.5) * 0.25);
+__global__ void __launch_bounds__(kSBThreads) k_vcycle_block(Slot<T> S, int l0, const T *__restrict__ b0,
+                                                             T *__restrict__ x0, const int *__restrict__ done) {
+    if (*done) return;
+    const int L = S.nlev;
+    for (int l = l0; l < L - 1; ++l) {
+        const Level<T> &lv = S.lev[l];
+        const T *b = l == l0 ? b0 : lv.b;
+        T *x = l == l0 ? x0 : lv.x;
+        BLOCK_LOOP(lv.g.N) presmooth_cell<T, DIM>(lv, b, x, c);
+        __syncthreads();
+        BLOCK_LOOP(lv.g.N) residual_cell<T, DIM>(lv, b, x, c);
+        __syncthreads();
+        BLOCK_LOOP(S.lev[l + 1].g.N) restrict_cell<T, DIM>(lv.g, S.lev[l + 1].g, lv.r, S.lev[l + 1].b, c);
+        __syncthreads();
+    }
+    {
+        const Level<T> &lc = S.lev[L - 1];
+        coarse_solve_block<T>((int)lc.g.N, S.Ainv, L - 1 == l0 ? b0 : lc.b, L - 1 == l0 ? x0 : lc.x);
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= l0; --l) {
+        const Level<T> &lv = S.lev[l];
+        const T *b = l == l0 ? b0 : lv.b;
+        T *x = l == l0 ? x0 : lv.x;
+        BLOCK_LOOP(lv.g.N) prolong_black_cell<T, DIM>(lv, S.lev[l + 1].g, S.lev[l + 1].x, b, x, lv.r, c);
+        __syncthreads();
+        BLOCK_LOOP(lv.g.N) red_from_tmp_cell<T, DIM>(lv, b, lv.r, x, c);
+        __syncthreads();
     }
 }
 
-// Assemble the coarsest operator densely into aug = [A | I] and invert it
-// by Gauss-Jordan elimination (SPD: no pivoting), one workgroup.
+// In-place Gauss-Jordan inversion of the n x n SPD matrix held in A (no
+// pivoting), block-wide; f is a scratch row of n doubles.
+__device__ inline void gauss_jordan_inplace(double *A, int n, double *f, double *piv) {
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        if (threadIdx.x == 0) *piv = 1.0 / A[k * n + k];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) f[i] = A[i * n + k];
+        __syncthreads();
+        const double p = *piv;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) A[k * n + j] = (j == k) ? p : A[k * n + j] * p;
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            if (i == k) continue;
+            const double fi = f[i];
+            A[e] = (j == k) ? -fi * p : A[e] - fi * A[k * n + j];
+        }
+    }
+    __syncthreads();
+}
+
+// Set-up of the small levels in one workgroup: coarsen from level
+// max(l0,1) - 1 downwards, inverse diagonals, then the coarsest inverse.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(1024) k_dense_inverse(Level<T> L, int singular, double *__restrict__ aug,
-                                                        double *__restrict__ Ainv) {
-    const Geo g = L.g;
-    const int n = (int)g.N;
-    const int w = 2 * n;
+__global__ void __launch_bounds__(kSBThreads) k_setup_block(Slot<T> S, int l0) {
+    __shared__ double A[kLdsInverse * kLdsInverse];
     __shared__ double f[kMaxCoarse];
-    __shared__ double red[1024 / kWave];
-    __shared__ double sh_piv, sh_tau;
-    for (long long e = threadIdx.x; e < (long long)n * w; e += blockDim.x) aug[e] = 0.0;
+    __shared__ double red[kSBThreads / kWave];
+    __shared__ double piv;
+    const int L = S.nlev;
+    if (l0 == 0) {
+        BLOCK_LOOP(S.lev[0].g.N) invd_cell<T, DIM>(S.lev[0], c);
+        __syncthreads();
+    }
+    for (int l = (l0 > 1 ? l0 : 1); l < L; ++l) {
+        BLOCK_LOOP(S.lev[l].g.N) coarsen_cell<T, DIM>(S.lev[l - 1], S.lev[l], c);
+        __syncthreads();
+        BLOCK_LOOP(S.lev[l].g.N) invd_cell<T, DIM>(S.lev[l], c);
+        __syncthreads();
+    }
+    // dense coarsest operator
+    const Level<T> &C = S.lev[L - 1];
+    const int n = (int)C.g.N;
+    double *M = n <= kLdsInverse ? A : S.aug;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = 0.0;
     __syncthreads();
     double dsum = 0.0;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        const int ia[3] = {i, j, k};
-        double d = (double)L.s[c];
+        int ia[3];
+        coords_of<DIM>(C.g, c, ia);
+        double d = (double)C.s[c];
         for (int b = 0; b < DIM; ++b) {
-            long long lo = nb_lo(g, c, ia[b], b);
-            long long hi = nb_hi(g, c, ia[b], b);
+            const long long lo = nb_lo(C.g, c, ia[b], b);
+            const long long hi = nb_hi(C.g, c, ia[b], b);
             if (lo >= 0) {
-                double cw = (double)L.cs[b][c];
-                d += cw;
-                aug[(long long)c * w + lo] -= cw;
+                const double w = (double)C.cs[b][c];
+                d += w;
+                M[c * n + lo] -= w;
             }
             if (hi >= 0) {
-                double cw = (double)L.cs[b][hi];
-                d += cw;
-                aug[(long long)c * w + hi] -= cw;
+                const double w = (double)C.cs[b][hi];
+                d += w;
+                M[c * n + hi] -= w;
             }
         }
-        aug[(long long)c * w + c] += d;
-        aug[(long long)c * w + n + c] = 1.0;
+        M[c * n + c] += d;
         dsum += d;
     }
-    double tot = block_sum(dsum, red);
-    if (threadIdx.x == 0) sh_tau = singular ? (tot / n) / n : 0.0;
-    __syncthreads();
-    if (singular) {
-        const double tau = sh_tau;
-        for (long long e = threadIdx.x; e < (long long)n * n; e += blockDim.x) aug[(e / n) * w + (e % n)] += tau;
+    const double tot = block_sum_all(dsum, red);
+    if (S.singular) {
+        const double tau = (tot / n) / n;
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] += tau;
     }
-    for (int kk = 0; kk < n; ++kk) {
-        __syncthreads();
-        if (threadIdx.x == 0) sh_piv = 1.0 / aug[(long long)kk * w + kk];
-        for (int i = threadIdx.x; i < n; i += blockDim.x) f[i] = aug[(long long)i * w + kk];
-        __syncthreads();
-        const double pinv = sh_piv;
-        for (int jj = threadIdx.x; jj < w; jj += blockDim.x) aug[(long long)kk * w + jj] *= pinv;
-        __syncthreads();
-        for (long long e = threadIdx.x; e < (long long)n * w; e += blockDim.x) {
-            const int i = (int)(e / w), jj = (int)(e % w);
-            if (i != kk) aug[e] -= f[i] * aug[(long long)kk * w + jj];
-        }
-    }
-    __syncthreads();
-    for (long long e = threadIdx.x; e < (long long)n * n; e += blockDim.x)
-        Ainv[e] = aug[(e / n) * w + n + (e % n)];
+    gauss_jordan_inplace(M, n, f, &piv);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) S.Ainv[e] = M[e];
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_invd(Level<T> L) {
+    GRID_LOOP(L.g.N) invd_cell<T, DIM>(L, c);
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_coarsen(Level<T> F, Level<T> C) {
+    GRID_LOOP(C.g.N) coarsen_cell<T, DIM>(F, C, c);
 }
 
 // ---------------------------------------------------------------------------
 // PCG kernels
 // ---------------------------------------------------------------------------
 
-// Lap(x) at c for the CH operator (unit-spacing coefficients cs = 1/h^2 in
-// every direction, walled axes Neumann).  x given by a functor.
+// fixed-order sum of partials, returned to every thread of the block
+__device__ inline double sum_parts_all(const double *__restrict__ part, int nparts, double *lds) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) v += part[k];
+    return block_sum_all(v, lds);
+}
+
+// Lap(x) at c for the CH operator (walled axes Neumann), x given by a functor
 template <int DIM, typename F>
-__device__ inline double lap_at(const Geo &g, long long c, int i, int j, int k, double ih2, F val) {
-    const int ia[3] = {i, j, k};
+__device__ inline double lap_at(const Geo &g, long long c, const int ia[3], double ih2, F val) {
     const double xc = val(c);
     double acc = 0.0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        long long lo = nb_lo(g, c, ia[b], b);
-        long long hi = nb_hi(g, c, ia[b], b);
+        const long long lo = nb_lo(g, c, ia[b], b);
+        const long long hi = nb_hi(g, c, ia[b], b);
         if (lo >= 0) acc += val(lo) - xc;
         if (hi >= 0) acc += val(hi) - xc;
     }
     return acc * ih2;
 }
 
-// first: p_new = z, otherwise p_new = z + beta p_old; then q = A p_new
-// (slot operator), partial p.q; the last block sets alpha = rz / pq.
+// p_new = (z - zmean) + beta p_old (beta = 0: p_new = z - zmean);
+// q = A p_new (slot operator); partial p.q
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const T *__restrict__ z, const T *__restrict__ pold,
-                                                           T *__restrict__ pnew, T *__restrict__ q, Scal *sc,
-                                                           double *part, unsigned int *counter) {
+__global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const T *__restrict__ z,
+                                                           const T *__restrict__ pold, T *__restrict__ pnew,
+                                                           T *__restrict__ q, const Scal *__restrict__ sc,
+                                                           double *__restrict__ part) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
-    const double beta = sc->beta;
-    const double zm = sc->zmean;
-    const Geo g = L.g;
+    const double beta = sc->beta, zm = sc->zmean;
+    auto pv = [&](long long e) { return ((double)z[e] - zm) + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
     double acc = 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        const int ia[3] = {i, j, k};
-        const double pc = ((double)z[c] - zm) + (beta != 0.0 ? beta * (double)pold[c] : 0.0);
-        double d = (double)L.s[c];
-        double off = 0.0;
+    GRID_LOOP(L.g.N) {
+        int ia[3];
+        coords_of<DIM>(L.g, c, ia);
+        const double pc = pv(c);
+        double qc = (double)L.s[c] * pc;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            long long lo = nb_lo(g, c, ia[b], b);
-            long long hi = nb_hi(g, c, ia[b], b);
-            if (lo >= 0) {
-                double w = (double)L.cs[b][c];
-                d += w;
-                off += w * (((double)z[lo] - zm) + (beta != 0.0 ? beta * (double)pold[lo] : 0.0));
-            }
-            if (hi >= 0) {
-                double w = (double)L.cs[b][hi];
-                d += w;
-                off += w * (((double)z[hi] - zm) + (beta != 0.0 ? beta * (double)pold[hi] : 0.0));
-            }
+            const long long lo = nb_lo(L.g, c, ia[b], b);
+            const long long hi = nb_hi(L.g, c, ia[b], b);
+            if (lo >= 0) qc += (double)L.cs[b][c] * (pc - pv(lo));
+            if (hi >= 0) qc += (double)L.cs[b][hi] * (pc - pv(hi));
         }
-        const double qc = d * pc - off;
         pnew[c] = (T)pc;
         q[c] = (T)qc;
         acc += pc * qc;
     }
-    double s = block_sum(acc, lds);
+    const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(counter)) {
-        double tot = sum_partials(part, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            sc->pq = tot;
-            sc->alpha = (tot != 0.0) ? sc->rz / tot : 0.0;
-            *counter = 0;
-        }
-    }
 }
 
 // CH operator, first half: p_new = z + beta p_old, t = L p_new.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const T *__restrict__ z, const T *__restrict__ pold,
-                                                       T *__restrict__ pnew, T *__restrict__ t, const Scal *sc) {
+__global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const T *__restrict__ z,
+                                                       const T *__restrict__ pold, T *__restrict__ pnew,
+                                                       T *__restrict__ t, const Scal *__restrict__ sc) {
     if (sc->done) return;
     const double beta = sc->beta;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        auto val = [&](long long e) { return (double)z[e] + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
-        pnew[c] = (T)val(c);
-        t[c] = (T)lap_at<DIM>(g, c, i, j, k, ih2, val);
+    auto pv = [&](long long e) { return (double)z[e] + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
+    GRID_LOOP(g.N) {
+        int ia[3];
+        coords_of<DIM>(g, c, ia);
+        pnew[c] = (T)pv(c);
+        t[c] = (T)lap_at<DIM>(g, c, ia, ih2, pv);
     }
 }
 
-// CH operator, second half: q = p - a t + b L t; partial p.q, alpha.
+// CH operator, second half: q = p - a t + b L t; partial p.q.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_pcg_ch_apply(Geo g, double ih2, double ca, double cb, const T *__restrict__ p,
-                                                         const T *__restrict__ t, T *__restrict__ q, Scal *sc,
-                                                         double *part, unsigned int *counter) {
+__global__ void __launch_bounds__(kBlock) k_pcg_ch_apply(Geo g, double ih2, double ca, double cb,
+                                                         const T *__restrict__ p, const T *__restrict__ t,
+                                                         T *__restrict__ q, const Scal *__restrict__ sc,
+                                                         double *__restrict__ part) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
+    auto tv = [&](long long e) { return (double)t[e]; };
     double acc = 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        auto val = [&](long long e) { return (double)t[e]; };
+    GRID_LOOP(g.N) {
+        int ia[3];
+        coords_of<DIM>(g, c, ia);
         const double pc = (double)p[c];
-        const double qc = pc - ca * (double)t[c] + cb * lap_at<DIM>(g, c, i, j, k, ih2, val);
+        const double qc = pc - ca * (double)t[c] + cb * lap_at<DIM>(g, c, ia, ih2, tv);
         q[c] = (T)qc;
         acc += pc * qc;
     }
-    double s = block_sum(acc, lds);
+    const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(counter)) {
-        double tot = sum_partials(part, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            sc->pq = tot;
-            sc->alpha = (tot != 0.0) ? sc->rz / tot : 0.0;
-            *counter = 0;
-        }
-    }
 }
 
-// x += alpha p, r -= alpha q, partial r.r; the last block tests convergence.
+// alpha = rz / sum(part_pq) (every block, same order); x += alpha p;
+// r -= alpha q; partial r.r
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pcg_update(long long N, const T *__restrict__ p, const T *__restrict__ q,
-                                                       T *__restrict__ x, T *__restrict__ r, Scal *sc, double *part,
-                                                       unsigned int *counter) {
+                                                       T *__restrict__ x, T *__restrict__ r, Scal *sc,
+                                                       const double *__restrict__ part_pq, int nparts,
+                                                       double *__restrict__ part_rr) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
-    const double alpha = sc->alpha;
+    const double pq = sum_parts_all(part_pq, nparts, lds);
+    const double alpha = pq != 0.0 ? sc->rz / pq : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = alpha;
+    }
     double acc = 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+    GRID_LOOP(N) {
         x[c] = (T)((double)x[c] + alpha * (double)p[c]);
         const double rc = (double)r[c] - alpha * (double)q[c];
         r[c] = (T)rc;
         acc += rc * rc;
     }
-    double s = block_sum(acc, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(counter)) {
-        double tot = sum_partials(part, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            sc->rr = tot;
-            sc->iter += 1;
-            if (!isfinite(tot)) {
-                sc->nonfinite = 1;
-                sc->done = 1;
-            } else if (tot <= sc->rtol2 * sc->bb) {
-                sc->done = 1;
-            } else if (sc->iter >= sc->max_iter) {
-                sc->unconverged = 1;
-                sc->done = 1;
-            }
-            *counter = 0;
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// one workgroup: rr = sum(part_rr); iteration count; convergence flag
+__global__ void __launch_bounds__(kBlock) k_pcg_fin_rr(Scal *sc, const double *__restrict__ part_rr, int nparts) {
+    if (sc->done) return;
+    __shared__ double lds[kBlock / kWave];
+    const double rr = sum_parts_all(part_rr, nparts, lds);
+    if (threadIdx.x == 0) {
+        sc->rr = rr;
+        sc->iter += 1;
+        if (!isfinite(rr)) {
+            sc->nonfinite = 1;
+            sc->done = 1;
+        } else if (rr <= sc->rtol2 * sc->bb) {
+            sc->done = 1;
+        } else if (sc->iter >= sc->max_iter) {
+            sc->unconverged = 1;
+            sc->done = 1;
         }
     }
 }
 
-// rz_new = r.(z - zmean); beta = rz_new / rz (0 on the first call); rz = rz_new.
-// For a singular (pure Neumann / periodic) operator the preconditioned vector
-// is projected onto the range: zmean = mean(z), otherwise zmean = 0.  The
-// V-cycle amplifies the constant mode, and without the projection rounding
-// noise in that mode destroys the conjugacy of the search directions.
+// partials of r.z, sum z, sum r
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_rz(long long N, const T *__restrict__ r, const T *__restrict__ z, Scal *sc,
-                                                   double *part0, double *part1, double *part2, unsigned int *counter,
-                                                   int first, int singular) {
+__global__ void __launch_bounds__(kBlock) k_pcg_rz(long long N, const T *__restrict__ r, const T *__restrict__ z,
+                                                   const Scal *__restrict__ sc, double *__restrict__ p0,
+                                                   double *__restrict__ p1, double *__restrict__ p2, int singular) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
     double arz = 0.0, az = 0.0, ar = 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+    GRID_LOOP(N) {
         const double rc = (double)r[c], zc = (double)z[c];
         arz += rc * zc;
         az += zc;
         ar += rc;
     }
-    double s0 = block_sum(arz, lds);
-    double s1 = singular ? block_sum(az, lds) : 0.0;
-    double s2 = singular ? block_sum(ar, lds) : 0.0;
+    const double s0 = block_sum(arz, lds);
+    const double s1 = singular ? block_sum(az, lds) : 0.0;
+    const double s2 = singular ? block_sum(ar, lds) : 0.0;
     if (threadIdx.x == 0) {
-        part0[blockIdx.x] = s0;
-        part1[blockIdx.x] = s1;
-        part2[blockIdx.x] = s2;
+        p0[blockIdx.x] = s0;
+        p1[blockIdx.x] = s1;
+        p2[blockIdx.x] = s2;
     }
-    if (last_block(counter)) {
-        double trz = sum_partials(part0, gridDim.x, lds);
-        double tz = singular ? sum_partials(part1, gridDim.x, lds) : 0.0;
-        double tr = singular ? sum_partials(part2, gridDim.x, lds) : 0.0;
-        if (threadIdx.x == 0) {
-            const double zm = singular ? tz / (double)N : 0.0;
-            const double rz = trz - zm * tr;
-            sc->zmean = zm;
-            sc->beta = (first || sc->rz == 0.0) ? 0.0 : rz / sc->rz;
-            sc->rz = rz;
-            if (!isfinite(rz)) {
-                sc->nonfinite = 1;
-                sc->done = 1;
-            }
-            *counter = 0;
+}
+
+// One workgroup: rz_new = r.(z - zmean), beta = rz_new / rz (0 on the first
+// call).  For a singular (pure Neumann / periodic) operator the
+// preconditioned vector is projected onto the range: zmean = mean(z),
+// otherwise 0.  The V-cycle amplifies the constant mode, and without the
+// projection rounding noise in that mode destroys the conjugacy of the
+// search directions.
+__global__ void __launch_bounds__(kBlock) k_pcg_fin_rz(Scal *sc, const double *__restrict__ p0,
+                                                       const double *__restrict__ p1, const double *__restrict__ p2,
+                                                       int nparts, long long N, int first, int singular) {
+    if (sc->done) return;
+    __shared__ double lds[kBlock / kWave];
+    const double trz = sum_parts_all(p0, nparts, lds);
+    const double tz = singular ? sum_parts_all(p1, nparts, lds) : 0.0;
+    const double tr = singular ? sum_parts_all(p2, nparts, lds) : 0.0;
+    if (threadIdx.x == 0) {
+        const double zm = singular ? tz / (double)N : 0.0;
+        const double rz = trz - zm * tr;
+        sc->zmean = zm;
+        sc->beta = (first || sc->rz == 0.0) ? 0.0 : rz / sc->rz;
+        sc->rz = rz;
+        if (!isfinite(rz)) {
+            sc->nonfinite = 1;
+            sc->done = 1;
         }
     }
 }
 
-// r = b - A x (slot operator), partials b.b and r.r; initialises the scalars.
+// r = b - A x (slot operator); partials of b.b and r.r
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_pcg_init_slot(Level<T> L, const T *__restrict__ b, const T *__restrict__ x,
-                                                          T *__restrict__ r, Scal *sc, double *part0, double *part1,
-                                                          unsigned int *counter, double rtol, int max_iter) {
+__global__ void __launch_bounds__(kBlock) k_pcg_init_slot(Level<T> L, const T *__restrict__ b,
+                                                          const T *__restrict__ x, T *__restrict__ r,
+                                                          double *__restrict__ p0, double *__restrict__ p1) {
     __shared__ double lds[kBlock / kWave];
-    const Geo g = L.g;
     double bb = 0.0, rr = 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        double Ax, d, off;
-        op_at<T, DIM>(L, x, c, i, j, k, Ax, d, off);
+    GRID_LOOP(L.g.N) {
+        int ia[3];
+        coords_of<DIM>(L.g, c, ia);
         const double bc = (double)b[c];
-        const double rc = bc - Ax;
+        const double rc = bc - apply_at<T, DIM>(L, x, c, ia);
         r[c] = (T)rc;
         bb += bc * bc;
         rr += rc * rc;
     }
-    double s0 = block_sum(bb, lds);
-    double s1 = block_sum(rr, lds);
+    const double s0 = block_sum(bb, lds);
+    const double s1 = block_sum(rr, lds);
     if (threadIdx.x == 0) {
-        part0[blockIdx.x] = s0;
-        part1[blockIdx.x] = s1;
-    }
-    if (last_block(counter)) {
-        double tb = sum_partials(part0, gridDim.x, lds);
-        double tr = sum_partials(part1, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            sc->bb = tb > tr ? tb : tr;
-            sc->rr = tr;
-            sc->rtol2 = rtol * rtol;
-            sc->iter = 0;
-            sc->max_iter = max_iter;
-            sc->unconverged = 0;
-            sc->nonfinite = 0;
-            sc->beta = 0.0;
-            sc->rz = 0.0;
-            sc->zmean = 0.0;
-            sc->done = 0;
-            if (!isfinite(tr) || !isfinite(tb)) {
-                sc->nonfinite = 1;
-                sc->done = 1;
-            } else if (tr <= sc->rtol2 * sc->bb) {
-                sc->done = 1;
-            }
-            *counter = 0;
-        }
-    }
-}
-
-// CH init: t = L x computed first by k_ch_lap_plain; r = b - (x - a t + b L t).
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_ch_lap_plain(Geo g, double ih2, const T *__restrict__ x, T *__restrict__ t) {
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        auto val = [&](long long e) { return (double)x[e]; };
-        t[c] = (T)lap_at<DIM>(g, c, i, j, k, ih2, val);
+        p0[blockIdx.x] = s0;
+        p1[blockIdx.x] = s1;
     }
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_pcg_init_ch(Geo g, double ih2, double ca, double cb, const T *__restrict__ b,
-                                                        const T *__restrict__ x, const T *__restrict__ t, T *__restrict__ r,
-                                                        Scal *sc, double *part0, double *part1, unsigned int *counter,
-                                                        double rtol, int max_iter) {
+__global__ void __launch_bounds__(kBlock) k_ch_lap_plain(Geo g, double ih2, const T *__restrict__ x,
+                                                         T *__restrict__ t) {
+    auto xv = [&](long long e) { return (double)x[e]; };
+    GRID_LOOP(g.N) {
+        int ia[3];
+        coords_of<DIM>(g, c, ia);
+        t[c] = (T)lap_at<DIM>(g, c, ia, ih2, xv);
+    }
+}
+
+// CH: r = b - (x - a t + b L t) with t = L x; partials b.b, r.r
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_pcg_init_ch(Geo g, double ih2, double ca, double cb,
+                                                        const T *__restrict__ b, const T *__restrict__ x,
+                                                        const T *__restrict__ t, T *__restrict__ r,
+                                                        double *__restrict__ p0, double *__restrict__ p1) {
     __shared__ double lds[kBlock / kWave];
+    auto tv = [&](long long e) { return (double)t[e]; };
     double bb = 0.0, rr = 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        auto val = [&](long long e) { return (double)t[e]; };
-        const double Mx = (double)x[c] - ca * (double)t[c] + cb * lap_at<DIM>(g, c, i, j, k, ih2, val);
+    GRID_LOOP(g.N) {
+        int ia[3];
+        coords_of<DIM>(g, c, ia);
+        const double Mx = (double)x[c] - ca * (double)t[c] + cb * lap_at<DIM>(g, c, ia, ih2, tv);
         const double bc = (double)b[c];
         const double rc = bc - Mx;
         r[c] = (T)rc;
         bb += bc * bc;
         rr += rc * rc;
     }
-    double s0 = block_sum(bb, lds);
-    double s1 = block_sum(rr, lds);
+    const double s0 = block_sum(bb, lds);
+    const double s1 = block_sum(rr, lds);
     if (threadIdx.x == 0) {
-        part0[blockIdx.x] = s0;
-        part1[blockIdx.x] = s1;
+        p0[blockIdx.x] = s0;
+        p1[blockIdx.x] = s1;
     }
-    if (last_block(counter)) {
-        double tb = sum_partials(part0, gridDim.x, lds);
-        double tr = sum_partials(part1, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            sc->bb = tb > tr ? tb : tr;
-            sc->rr = tr;
-            sc->rtol2 = rtol * rtol;
-            sc->iter = 0;
-            sc->max_iter = max_iter;
-            sc->unconverged = 0;
-            sc->nonfinite = 0;
-            sc->beta = 0.0;
-            sc->rz = 0.0;
-            sc->zmean = 0.0;
-            sc->done = 0;
-            if (!isfinite(tr) || !isfinite(tb)) {
-                sc->nonfinite = 1;
-                sc->done = 1;
-            } else if (tr <= sc->rtol2 * sc->bb) {
-                sc->done = 1;
-            }
-            *counter = 0;
+}
+
+// one workgroup: initialise the scalars from the b.b and r0.r0 partials
+__global__ void __launch_bounds__(kBlock) k_pcg_fin_init(Scal *sc, const double *__restrict__ p0,
+                                                         const double *__restrict__ p1, int nparts, double rtol,
+                                                         int max_iter) {
+    __shared__ double lds[kBlock / kWave];
+    const double tb = sum_parts_all(p0, nparts, lds);
+    const double tr = sum_parts_all(p1, nparts, lds);
+    if (threadIdx.x == 0) {
+        sc->bb = tb > tr ? tb : tr;
+        sc->rr = tr;
+        sc->rtol2 = rtol * rtol;
+        sc->iter = 0;
+        sc->max_iter = max_iter;
+        sc->unconverged = 0;
+        sc->nonfinite = 0;
+        sc->beta = 0.0;
+        sc->rz = 0.0;
+        sc->zmean = 0.0;
+        sc->alpha = 0.0;
+        sc->done = 0;
+        if (!isfinite(tr) || !isfinite(tb)) {
+            sc->nonfinite = 1;
+            sc->done = 1;
+        } else if (tr <= sc->rtol2 * sc->bb) {
+            sc->done = 1;
         }
     }
 }
 
-// mean removal: partial sums, then subtract (two kernels, deterministic)
+// mean removal: partial sums, then every block sums them and subtracts
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sum(long long N, const T *__restrict__ x, double *part, unsigned int *counter,
-                                                double *out) {
+__global__ void __launch_bounds__(kBlock) k_sum(long long N, const T *__restrict__ x, double *__restrict__ part) {
     __shared__ double lds[kBlock / kWave];
     double acc = 0.0;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x)
-        acc += (double)x[c];
-    double s = block_sum(acc, lds);
+    GRID_LOOP(N) acc += (double)x[c];
+    const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
-    if (last_block(counter)) {
-        double tot = sum_partials(part, gridDim.x, lds);
-        if (threadIdx.x == 0) {
-            *out = tot;
-            *counter = 0;
-        }
-    }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sub_mean(long long N, T *__restrict__ x, const double *__restrict__ sum) {
-    const double m = *sum / (double)N;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x)
-        x[c] = (T)((double)x[c] - m);
+__global__ void __launch_bounds__(kBlock) k_sub_mean(long long N, T *__restrict__ x, const double *__restrict__ part,
+                                                     int nparts) {
+    __shared__ double lds[kBlock / kWave];
+    const double m = sum_parts_all(part, nparts, lds) / (double)N;
+    GRID_LOOP(N) x[c] = (T)((double)x[c] - m);
 }
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock) k_slot_apply(Level<T> L, const T *__restrict__ x, T *__restrict__ y) {
-    const Geo g = L.g;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < g.N;
-         c += (long long)gridDim.x * blockDim.x) {
-        int i, j, k;
-        cell_coords(g, c, i, j, k);
-        double Ax, d, off;
-        op_at<T, DIM>(L, x, c, i, j, k, Ax, d, off);
-        y[c] = (T)Ax;
+    GRID_LOOP(L.g.N) {
+        int ia[3];
+        coords_of<DIM>(L.g, c, ia);
+        y[c] = (T)apply_at<T, DIM>(L, x, c, ia);
     }
 }
 
@@ -681,16 +778,32 @@ __global__ void __launch_bounds__(kBlock) k_slot_apply(Level<T> L, const T *__re
 // host drivers
 // ---------------------------------------------------------------------------
 #define LAUNCH(cls, bytes, kern, n, st, ...) TLAUNCH(cls, bytes, kern, dim3(grid_for(n)), dim3(kBlock), st, __VA_ARGS__)
+#define LAUNCH1(cls, bytes, kern, threads, st, ...) TLAUNCH(cls, bytes, kern, dim3(1), dim3(threads), st, __VA_ARGS__)
+
+// First level handled by the single-workgroup kernel.
+template <typename T>
+static int single_block_level(const Slot<T> &S) {
+    int l = 0;
+    const long long lim = sb_cells();
+    while (l < S.nlev - 1 && S.lev[l].g.N > lim) ++l;
+    return l;
+}
 
 template <typename T, int DIM>
 static void mg_setup_d(Slot<T> &S, hipStream_t st) {
     constexpr double W = sizeof(T);
-    for (int l = 0; l + 1 < S.nlev; ++l)
-        LAUNCH(K_MG_SETUP, W * (1 + DIM) * (S.lev[l].g.N + S.lev[l + 1].g.N), (k_coarsen<T, DIM>), S.lev[l + 1].g.N, st,
-               S.lev[l], S.lev[l + 1]);
-    const Level<T> &C = S.lev[S.nlev - 1];
-    TLAUNCH(K_MG_SETUP, 8.0 * 3.0 * C.g.N * C.g.N, (k_dense_inverse<T, DIM>), dim3(1), dim3(1024), st, C, S.singular,
-            (double *)S.aug, (double *)S.Ainv);
+    S.lsb = single_block_level(S);
+    const int lsb = S.lsb;
+    if (lsb > 0) LAUNCH(K_MG_SETUP, W * (2 + DIM) * S.lev[0].g.N, (k_invd<T, DIM>), S.lev[0].g.N, st, S.lev[0]);
+    for (int l = 1; l < lsb; ++l) {
+        LAUNCH(K_MG_SETUP, W * (1 + DIM) * (S.lev[l - 1].g.N + S.lev[l].g.N), (k_coarsen<T, DIM>), S.lev[l].g.N, st,
+               S.lev[l - 1], S.lev[l]);
+        LAUNCH(K_MG_SETUP, W * (2 + DIM) * S.lev[l].g.N, (k_invd<T, DIM>), S.lev[l].g.N, st, S.lev[l]);
+    }
+    double bytes = 0.0;
+    for (int l = lsb; l < S.nlev; ++l) bytes += W * (2 + 2 * DIM) * S.lev[l].g.N;
+    bytes += 8.0 * S.ncoarse * S.ncoarse;
+    LAUNCH1(K_MG_SETUP, bytes, (k_setup_block<T, DIM>), kSBThreads, st, S, lsb);
 }
 
 template <typename T>
@@ -704,34 +817,32 @@ void mg_setup(Slot<T> &S, int dim, hipStream_t st) {
 template <typename T, int DIM>
 static void vcycle_d(Slot<T> &S, const T *b0, T *x0, const int *done, hipStream_t st) {
     constexpr double W = sizeof(T);
-    const int L = S.nlev;
-    for (int l = 0; l < L - 1; ++l) {
+    const int lsb = S.lsb;
+    for (int l = 0; l < lsb; ++l) {
         Level<T> &lv = S.lev[l];
         const T *b = l == 0 ? b0 : lv.b;
         T *x = l == 0 ? x0 : lv.x;
-        const long long N = lv.g.N;
-        LAUNCH(K_SMOOTH, W * (3 + DIM) * N, (k_rbgs<T, DIM>), N, st, lv, b, x, 0, 1, done);
-        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N, (k_rbgs<T, DIM>), N, st, lv, b, x, 1, 0, done);
-        LAUNCH(K_RESIDUAL, W * (4 + DIM) * N, (k_residual<T, DIM>), N, st, lv, b, (const T *)x, lv.r, done);
-        LAUNCH(K_RESTRICT, W * (N + S.lev[l + 1].g.N), (k_restrict<T, DIM>), S.lev[l + 1].g.N, st, lv.g, S.lev[l + 1].g,
-               (const T *)lv.r, S.lev[l + 1].b, done);
+        const long long N = lv.g.N, Nc = S.lev[l + 1].g.N;
+        LAUNCH(K_SMOOTH, W * (2 + DIM) * N, (k_presmooth<T, DIM>), N, st, lv, b, x, done);
+        LAUNCH(K_RESIDUAL, W * (4 + DIM) * N, (k_residual<T, DIM>), N, st, lv, b, (const T *)x, done);
+        LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict<T, DIM>), Nc, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
+               S.lev[l + 1].b, done);
     }
     {
-        Level<T> &lc = S.lev[L - 1];
-        const T *b = L == 1 ? b0 : lc.b;
-        T *x = L == 1 ? x0 : lc.x;
-        TLAUNCH(K_COARSE_SOLVE, 8.0 * lc.g.N * lc.g.N + W * 2.0 * lc.g.N, (k_coarse_solve<T>), dim3(1), dim3(1024), st,
-                (int)lc.g.N, (const double *)S.Ainv, b, x, done);
+        double bytes = 8.0 * S.ncoarse * S.ncoarse;
+        for (int l = lsb; l < S.nlev; ++l) bytes += W * 12.0 * S.lev[l].g.N;
+        const T *b = lsb == 0 ? b0 : S.lev[lsb].b;
+        T *x = lsb == 0 ? x0 : S.lev[lsb].x;
+        LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, DIM>), kSBThreads, st, S, lsb, b, x, done);
     }
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = lsb - 1; l >= 0; --l) {
         Level<T> &lv = S.lev[l];
         const T *b = l == 0 ? b0 : lv.b;
         T *x = l == 0 ? x0 : lv.x;
-        const long long N = lv.g.N;
-        LAUNCH(K_PROLONG, W * (2 * N + S.lev[l + 1].g.N), (k_prolong_add<T, DIM>), N, st, lv.g, S.lev[l + 1].g,
-               (const T *)S.lev[l + 1].x, x, done);
-        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N, (k_rbgs<T, DIM>), N, st, lv, b, x, 1, 0, done);
-        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N, (k_rbgs<T, DIM>), N, st, lv, b, x, 0, 0, done);
+        const long long N = lv.g.N, Nc = S.lev[l + 1].g.N;
+        LAUNCH(K_PROLONG, W * ((4 + DIM) * N + Nc), (k_prolong_black<T, DIM>), N, st, lv, S.lev[l + 1].g,
+               (const T *)S.lev[l + 1].x, b, (const T *)x, lv.r, done);
+        LAUNCH(K_SMOOTH, W * (4 + DIM) * N, (k_red_from_tmp<T, DIM>), N, st, lv, b, (const T *)lv.r, x, done);
     }
 }
 
@@ -761,19 +872,24 @@ static hipError_t pcg_d(Slot<T> &S, OpKind kind, ChOp ch, const T *b, T *x, doub
     const Level<T> &L0 = S.lev[0];
     const Geo g = L0.g;
     const long long N = g.N;
+    const int nb = grid_for(N);
     Scal *sc = red.scal;
     const int *done = &sc->done;
     if (kind == OP_SLOT) {
-        LAUNCH(K_PCG_INIT, W * (4 + DIM) * N, (k_pcg_init_slot<T, DIM>), N, st, L0, b, (const T *)x, v.r, sc, red.part0,
-               red.part1, red.counter, rtol, max_iter);
+        LAUNCH(K_PCG_INIT, W * (4 + DIM) * N, (k_pcg_init_slot<T, DIM>), N, st, L0, b, (const T *)x, v.r, red.part0,
+               red.part1);
     } else {
         LAUNCH(K_PCG_INIT, W * 2 * N, (k_ch_lap_plain<T, DIM>), N, st, g, ch.ih2, (const T *)x, v.t);
         LAUNCH(K_PCG_INIT, W * 4 * N, (k_pcg_init_ch<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, b, (const T *)x,
-               (const T *)v.t, v.r, sc, red.part0, red.part1, red.counter, rtol, max_iter);
+               (const T *)v.t, v.r, red.part0, red.part1);
     }
+    LAUNCH1(K_PCG_INIT, 16.0 * nb, (k_pcg_fin_init), kBlock, st, sc, (const double *)red.part0,
+            (const double *)red.part1, nb, rtol, max_iter);
     precond_d<T, DIM>(S, kind, v.r, v.z, v.t, done, st);
-    LAUNCH(K_PCG_DOT, W * 2 * N, (k_pcg_rz<T>), N, st, N, (const T *)v.r, (const T *)v.z, sc, red.part0, red.part1,
-           red.part2, red.counter, 1, S.singular);
+    LAUNCH(K_PCG_DOT, W * 2 * N, (k_pcg_rz<T>), N, st, N, (const T *)v.r, (const T *)v.z, (const Scal *)sc, red.part0,
+           red.part1, red.part2, S.singular);
+    LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
+            (const double *)red.part1, (const double *)red.part2, nb, N, 1, S.singular);
     int launched = 0;
     int chunk = predict < 1 ? 1 : predict;
     Scal hs;
@@ -785,18 +901,21 @@ static hipError_t pcg_d(Slot<T> &S, OpKind kind, ChOp ch, const T *b, T *x, doub
             T *pold = (k & 1) ? v.p0 : v.p1;
             if (kind == OP_SLOT) {
                 LAUNCH(K_PCG_APPLY, W * (5 + DIM) * N, (k_pcg_apply_slot<T, DIM>), N, st, L0, (const T *)v.z,
-                       (const T *)pold, pnew, v.q, sc, red.part0, red.counter);
+                       (const T *)pold, pnew, v.q, (const Scal *)sc, red.part0);
             } else {
-                LAUNCH(K_PCG_APPLY, W * 4 * N, (k_pcg_ch_lap<T, DIM>), N, st, g, ch.ih2, (const T *)v.z, (const T *)pold,
-                       pnew, v.t, (const Scal *)sc);
+                LAUNCH(K_PCG_APPLY, W * 4 * N, (k_pcg_ch_lap<T, DIM>), N, st, g, ch.ih2, (const T *)v.z,
+                       (const T *)pold, pnew, v.t, (const Scal *)sc);
                 LAUNCH(K_PCG_APPLY, W * 3 * N, (k_pcg_ch_apply<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, (const T *)pnew,
-                       (const T *)v.t, v.q, sc, red.part0, red.counter);
+                       (const T *)v.t, v.q, (const Scal *)sc, red.part0);
             }
             LAUNCH(K_PCG_UPDATE, W * 6 * N, (k_pcg_update<T>), N, st, N, (const T *)pnew, (const T *)v.q, x, v.r, sc,
-                   red.part0, red.counter);
+                   (const double *)red.part0, nb, red.part1);
+            LAUNCH1(K_PCG_UPDATE, 8.0 * nb, (k_pcg_fin_rr), kBlock, st, sc, (const double *)red.part1, nb);
             precond_d<T, DIM>(S, kind, v.r, v.z, v.t, done, st);
-            LAUNCH(K_PCG_DOT, W * 2 * N, (k_pcg_rz<T>), N, st, N, (const T *)v.r, (const T *)v.z, sc, red.part0, red.part1,
-                   red.part2, red.counter, 0, S.singular);
+            LAUNCH(K_PCG_DOT, W * 2 * N, (k_pcg_rz<T>), N, st, N, (const T *)v.r, (const T *)v.z, (const Scal *)sc,
+                   red.part0, red.part1, red.part2, S.singular);
+            LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
+                    (const double *)red.part1, (const double *)red.part2, nb, N, 0, S.singular);
         }
         launched += chunk;
         hipError_t e = hipMemcpyAsync(&hs, sc, sizeof(Scal), hipMemcpyDeviceToHost, st);
@@ -823,10 +942,9 @@ hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x
 
 template <typename T>
 void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st) {
-    constexpr double W = sizeof(T);
-    (void)W;
-    LAUNCH(K_MEAN, sizeof(T) * g.N, (k_sum<T>), g.N, st, g.N, (const T *)x, red.part0, red.counter, &red.scal->sum0);
-    LAUNCH(K_MEAN, 2.0 * sizeof(T) * g.N, (k_sub_mean<T>), g.N, st, g.N, x, (const double *)&red.scal->sum0);
+    const int nb = grid_for(g.N);
+    LAUNCH(K_MEAN, sizeof(T) * g.N, (k_sum<T>), g.N, st, g.N, (const T *)x, red.part0);
+    LAUNCH(K_MEAN, 2.0 * sizeof(T) * g.N, (k_sub_mean<T>), g.N, st, g.N, x, (const double *)red.part0, nb);
 }
 
 template <typename T>
