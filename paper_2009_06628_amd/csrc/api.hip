@@ -92,7 +92,7 @@ int make_plan(const chns_grid_desc *d, Plan &P) {
     if (!d) return fail(CHNS_EINVAL, "grid description is NULL");
     if (d->dim != 2 && d->dim != 3) return fail(CHNS_EINVAL, "dim must be 2 or 3");
     if (d->nphases != 2) return fail(CHNS_EINVAL, "only nphases = 2 is supported");
-    if (d->precision != CHNS_FP64) return fail(CHNS_EINVAL, "precision form not available in this build");
+    if (d->precision != CHNS_FP64 && d->precision != CHNS_FP32_REFINE) return fail(CHNS_EINVAL, "bad precision");
     if (!(d->h > 0.0) || !std::isfinite(d->h)) return fail(CHNS_EINVAL, "h must be positive and finite");
     Geo g;
     g.N = 1;
@@ -108,7 +108,7 @@ int make_plan(const chns_grid_desc *d, Plan &P) {
         }
         g.N *= g.n[a];
     }
-    if (g.N > (1LL << 34)) return fail(CHNS_EINVAL, "grid too large");
+    if (g.N >= (1LL << 31) - 1) return fail(CHNS_EINVAL, "grid too large (kernels index cells with 32-bit integers)");
     P.dim = d->dim;
     P.nlev = 1;
     P.lev[0] = g;
@@ -171,7 +171,7 @@ void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
     S.aug = nullptr;
 }
 
-void layout(Bump &B, const Plan &P, chns_grid *g) {
+void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     const size_t N = (size_t)P.lev[0].N;
     g->phi_new = B.take<double>(N);
     g->phihat = B.take<double>(N);
@@ -190,6 +190,17 @@ void layout(Bump &B, const Plan &P, chns_grid *g) {
     const int nc = g->ch.ncoarse;
     double *aug = nc > kLdsInverse ? B.take<double>((size_t)nc * nc) : nullptr;
     g->ch.aug = g->mom.aug = g->pres.aug = aug;
+    g->prec = prec;
+    if (prec == CHNS_FP32_REFINE) {
+        carve_slot(B, P, g->ch32, 0);
+        carve_slot(B, P, g->mom32, 0);
+        carve_slot(B, P, g->pres32, 1);
+        g->ch32.aug = g->mom32.aug = g->pres32.aug = aug;
+        g->f_z = B.take<float>(N);
+        g->f_t = B.take<float>(N);
+    } else {
+        g->f_z = g->f_t = nullptr;
+    }
     g->red.part0 = B.take<double>(kMaxBlocks);
     g->red.part1 = B.take<double>(kMaxBlocks);
     g->red.part2 = B.take<double>(kMaxBlocks);
@@ -224,6 +235,32 @@ PcgVecs<double> vecs(chns_grid *g) { return PcgVecs<double>{g->vr, g->vz, g->vp0
 
 int next_predict(int last) { return last < 1 ? 1 : last; }
 
+// One linear solve in the handle's precision form.  which: 0 CH (constant
+// hierarchy, set up by chns_set_properties), 1 momentum, 2 pressure (their
+// level-0 coefficients were just written by the set-up kernels).  pidx
+// indexes the iteration predictions.
+hipError_t run_solve(chns_grid *g, int which, OpKind kind, ChOp ch, const double *b, double *x, double rtol,
+                     int pidx, SolveOut *o) {
+    Slot<double> &S64 = which == 0 ? g->ch : (which == 1 ? g->mom : g->pres);
+    hipStream_t s = g->stream;
+    PcgVecs<double> v = vecs(g);
+    if (g->prec == CHNS_FP64) {
+        if (which != 0) mg_setup(S64, g->dim, s);
+        hipError_t e = pcg_solve(S64, g->dim, kind, ch, b, x, rtol, g->props.max_iter, next_predict(g->last_iters[pidx]),
+                                 g->red, v, s, o);
+        g->last_iters[pidx] = o->iters;
+        return e;
+    }
+    Slot<float> &S32 = which == 0 ? g->ch32 : (which == 1 ? g->mom32 : g->pres32);
+    if (which != 0) {
+        convert_level0(S64, S32, g->dim, s);
+        mg_setup(S32, g->dim, s);
+    }
+    const PcgVecs2<double, float> v2{v.r, v.p0, v.p1, v.q, v.t, g->f_z, g->f_t};
+    return refine_solve(S64, S32, g->dim, kind, ch, b, x, rtol, g->props.max_iter, &g->last_inner[pidx], g->red, v2, s,
+                        o);
+}
+
 int check_solve(const SolveOut &o, const char *what) {
     if (o.nonfinite) return fail(CHNS_ENONFINITE, std::string("non-finite residual in the ") + what + " solve");
     return CHNS_OK;
@@ -240,7 +277,7 @@ int chns_workspace_size(const chns_grid_desc *desc, size_t *bytes) {
     if (rc) return rc;
     chns_grid tmp;
     Bump B{nullptr, 0};
-    layout(B, P, &tmp);
+    layout(B, P, &tmp, desc->precision);
     *bytes = B.off + 256;
     return CHNS_OK;
 }
@@ -267,8 +304,8 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     g->ws = workspace;
     g->ws_bytes = bytes;
     Bump B{(char *)workspace, 0};
-    layout(B, P, g);
-    for (int k = 0; k < 6; ++k) g->last_iters[k] = 4;
+    layout(B, P, g, desc->precision);
+    for (int k = 0; k < 6; ++k) g->last_iters[k] = g->last_inner[k] = 4;
     memset(&g->last, 0, sizeof g->last);
     hipError_t e = hipMemsetAsync(g->red.counter, 0, 64 * sizeof(unsigned int), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->red.scal, 0, sizeof(Scal), g->stream);
@@ -297,6 +334,10 @@ int chns_set_properties(chns_grid *g, const chns_props *p) {
     double *cs[3] = {g->ch.lev[0].cs[0], g->ch.lev[0].cs[1], g->ch.lev[0].cs[2]};
     launch_fill_ch(g->dim, g->geo, std::sqrt(cb) * k.ih2, g->ch.lev[0].s, cs, g->stream);
     mg_setup(g->ch, g->dim, g->stream);
+    if (g->prec == CHNS_FP32_REFINE) {
+        convert_level0(g->ch, g->ch32, g->dim, g->stream);
+        mg_setup(g->ch32, g->dim, g->stream);
+    }
     HIPCHK(hipGetLastError());
     return CHNS_OK;
 }
@@ -328,10 +369,8 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
         memset(&last, 0, sizeof last);
         // S1, S2
         launch_ch_rhs(dim, geo, k, phi, uc, g->rch, g->phihat, s);
-        HIPCHK(pcg_solve(g->ch, dim, OP_CH, ch, (const double *)g->rch, g->phihat, p.rtol_ch, p.max_iter,
-                         next_predict(g->last_iters[0]), g->red, v, s, &o));
+        HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)g->rch, g->phihat, p.rtol_ch, 0, &o));
         if (int rc = check_solve(o, "Cahn-Hilliard")) return rc;
-        g->last_iters[0] = o.iters;
         last.iters_ch = o.iters;
         last.res_ch = o.rel_res;
         last.unconverged |= o.unconverged ? 1 : 0;
@@ -343,11 +382,8 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
             Level<double> &L0 = g->mom.lev[0];
             double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
             launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, g->rhs, g->ustar[a], s);
-            mg_setup(g->mom, dim, s);
-            HIPCHK(pcg_solve(g->mom, dim, OP_SLOT, ch, (const double *)g->rhs, g->ustar[a], p.rtol_mom, p.max_iter,
-                             next_predict(g->last_iters[1 + a]), g->red, v, s, &o));
+            HIPCHK(run_solve(g, 1, OP_SLOT, ch, (const double *)g->rhs, g->ustar[a], p.rtol_mom, 1 + a, &o));
             if (int rc = check_solve(o, "momentum")) return rc;
-            g->last_iters[1 + a] = o.iters;
             last.iters_mom[a] = o.iters;
             last.res_mom[a] = o.rel_res;
             last.unconverged |= o.unconverged ? (2 << a) : 0;
@@ -358,11 +394,8 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
             double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
             launch_p_setup(dim, geo, k, g->phi_new, usc, L0.s, cs, g->rhs, s);
             remove_mean(geo, g->rhs, g->red, s);
-            mg_setup(g->pres, dim, s);
-            HIPCHK(pcg_solve(g->pres, dim, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, p.max_iter,
-                             next_predict(g->last_iters[4]), g->red, v, s, &o));
+            HIPCHK(run_solve(g, 2, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
             if (int rc = check_solve(o, "pressure")) return rc;
-            g->last_iters[4] = o.iters;
             last.iters_p = o.iters;
             last.res_p = o.rel_res;
             last.unconverged |= o.unconverged ? 16 : 0;
@@ -411,13 +444,13 @@ int chns_solve_pressure(chns_grid *g, const void *rho, const void *rhs, void *p,
     launch_p_coef_from_rho(dim, g->geo, 1.0 / (g->h * g->h), (const double *)rho, L0.s, cs, s);
     HIPCHK(hipMemcpyAsync(g->rhs, rhs, sizeof(double) * g->geo.N, hipMemcpyDeviceToDevice, s));
     remove_mean(g->geo, g->rhs, g->red, s);
-    mg_setup(g->pres, dim, s);
-    PcgVecs<double> v = vecs(g);
     SolveOut o;
-    HIPCHK(pcg_solve(g->pres, dim, OP_SLOT, ChOp{0, 0, 0}, (const double *)g->rhs, (double *)p, rtol, max_iter,
-                     next_predict(g->last_iters[5]), g->red, v, s, &o));
+    const int saved = g->props.max_iter;
+    g->props.max_iter = max_iter;
+    hipError_t e = run_solve(g, 2, OP_SLOT, ChOp{0, 0, 0}, (const double *)g->rhs, (double *)p, rtol, 5, &o);
+    g->props.max_iter = saved;
+    HIPCHK(e);
     if (int rc = check_solve(o, "pressure")) return rc;
-    g->last_iters[5] = o.iters;
     remove_mean(g->geo, (double *)p, g->red, s);
     HIPCHK(hipStreamSynchronize(s));
     if (stats) {

@@ -28,28 +28,41 @@ struct Geo {
     long long N;   // total cells
 };
 
-__host__ __device__ inline long long stride_of(const Geo &g, int a) {
-    return a == 0 ? 1LL : (a == 1 ? (long long)g.n[0] : (long long)g.n[0] * g.n[1]);
+// Kernels index cells with 32-bit integers (grids are limited to < 2^31
+// cells); coordinates come from unsigned 32-bit divisions.
+__host__ __device__ inline int stride_of(const Geo &g, int a) {
+    return a == 0 ? 1 : (a == 1 ? g.n[0] : g.n[0] * g.n[1]);
 }
 
-__device__ inline void cell_coords(const Geo &g, long long c, int &i, int &j, int &k) {
-    i = (int)(c % g.n[0]);
-    long long t = c / g.n[0];
-    j = (int)(t % g.n[1]);
-    k = (int)(t / g.n[1]);
+__device__ inline void cell_coords(const Geo &g, int c, int &i, int &j, int &k) {
+    const unsigned uc = (unsigned)c, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];
+    const unsigned t = uc / n0;
+    i = (int)(uc - t * n0);
+    const unsigned kk = t / n1;
+    j = (int)(t - kk * n1);
+    k = (int)kk;
+}
+
+// 2D: one division (the row index is j)
+__device__ inline void cell_coords2(const Geo &g, int c, int &i, int &j, int &k) {
+    const unsigned uc = (unsigned)c, n0 = (unsigned)g.n[0];
+    const unsigned t = uc / n0;
+    i = (int)(uc - t * n0);
+    j = (int)t;
+    k = 0;
 }
 
 // Index of c - e_a (wrapping on periodic axes); -1 outside a walled axis.
-__device__ inline long long nb_lo(const Geo &g, long long c, int ia, int a) {
-    const long long s = stride_of(g, a);
+__device__ inline int nb_lo(const Geo &g, int c, int ia, int a) {
+    const int s = stride_of(g, a);
     if (ia > 0) return c - s;
-    return g.per[a] ? c + (long long)(g.n[a] - 1) * s : -1;
+    return g.per[a] ? c + (g.n[a] - 1) * s : -1;
 }
 // Index of c + e_a; -1 outside a walled axis.
-__device__ inline long long nb_hi(const Geo &g, long long c, int ia, int a) {
-    const long long s = stride_of(g, a);
+__device__ inline int nb_hi(const Geo &g, int c, int ia, int a) {
+    const int s = stride_of(g, a);
     if (ia < g.n[a] - 1) return c + s;
-    return g.per[a] ? c - (long long)(g.n[a] - 1) * s : -1;
+    return g.per[a] ? c - (g.n[a] - 1) * s : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -228,6 +241,11 @@ struct chns_grid {
     double *phi_new, *phihat, *rch, *ustar[3], *rhs;
     double *vr, *vz, *vp0, *vp1, *vq, *vt;   // PCG vectors
     chns::Slot<double> ch, mom, pres;
+    // precision form (FP32 inner solves under FP64 refinement)
+    int prec;
+    chns::Slot<float> ch32, mom32, pres32;
+    float *f_z, *f_t;   // FP32 preconditioned vector and V-cycle scratch
+    int last_inner[6];
     chns::Red red;
     double *diag;                            // diagnostics scratch
     int last_iters[6];                       // iteration-count predictions

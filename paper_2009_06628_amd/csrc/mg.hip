@@ -35,10 +35,10 @@ namespace chns {
 
 // Levels at or below this many cells run in the single-workgroup kernel
 // (default; the CHNS_SB_CELLS environment variable overrides it at set-up).
-constexpr long long kSBCellsDefault = 2048;
+constexpr int kSBCellsDefault = 2048;
 
-static long long sb_cells() {
-    static long long v = -1;
+static int sb_cells() {
+    static int v = -1;
     if (v < 0) {
         const char *e = getenv("CHNS_SB_CELLS");
         v = e ? atoll(e) : kSBCellsDefault;
@@ -51,81 +51,90 @@ static long long sb_cells() {
 // per-cell building blocks (shared by the grid-wide and single-block kernels)
 // ---------------------------------------------------------------------------
 template <int DIM>
-__device__ inline void coords_of(const Geo &g, long long c, int ia[3]) {
-    cell_coords(g, c, ia[0], ia[1], ia[2]);
+__device__ inline void coords_of(const Geo &g, int c, int ia[3]) {
+    if (DIM == 2)
+        cell_coords2(g, c, ia[0], ia[1], ia[2]);
+    else
+        cell_coords(g, c, ia[0], ia[1], ia[2]);
 }
 
 // (A x)_c
 template <typename T, int DIM>
-__device__ inline double apply_at(const Level<T> &L, const T *__restrict__ x, long long c, const int ia[3]) {
+__device__ inline T apply_at(const Level<T> &L, const T *__restrict__ x, int c, const int ia[3]) {
+    using R = T;
     const Geo &g = L.g;
-    const double xc = (double)x[c];
-    double acc = (double)L.s[c] * xc;
+    const R xc = (R)x[c];
+    R acc = (R)L.s[c] * xc;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        const long long lo = nb_lo(g, c, ia[b], b);
-        const long long hi = nb_hi(g, c, ia[b], b);
-        if (lo >= 0) acc += (double)L.cs[b][c] * (xc - (double)x[lo]);
-        if (hi >= 0) acc += (double)L.cs[b][hi] * (xc - (double)x[hi]);
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) acc += (R)L.cs[b][c] * (xc - (R)x[lo]);
+        if (hi >= 0) acc += (R)L.cs[b][hi] * (xc - (R)x[hi]);
     }
     return acc;
 }
 
 // sum_b cs * x_nb over the neighbours (x given by a functor)
 template <typename T, int DIM, typename F>
-__device__ inline double offsum_at(const Level<T> &L, long long c, const int ia[3], F xv) {
+__device__ inline T offsum_at(const Level<T> &L, int c, const int ia[3], F xv) {
+    using R = T;
     const Geo &g = L.g;
-    double acc = 0.0;
+    R acc = 0.0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        const long long lo = nb_lo(g, c, ia[b], b);
-        const long long hi = nb_hi(g, c, ia[b], b);
-        if (lo >= 0) acc += (double)L.cs[b][c] * xv(lo);
-        if (hi >= 0) acc += (double)L.cs[b][hi] * xv(hi);
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) acc += (R)L.cs[b][c] * xv(lo);
+        if (hi >= 0) acc += (R)L.cs[b][hi] * xv(hi);
     }
     return acc;
 }
 
 template <typename T, int DIM>
-__device__ inline void invd_cell(const Level<T> &L, long long c) {
+__device__ inline void invd_cell(const Level<T> &L, int c) {
+    using R = T;
     int ia[3];
     coords_of<DIM>(L.g, c, ia);
-    double d = (double)L.s[c];
+    R d = (R)L.s[c];
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        if (nb_lo(L.g, c, ia[b], b) >= 0) d += (double)L.cs[b][c];
-        const long long hi = nb_hi(L.g, c, ia[b], b);
-        if (hi >= 0) d += (double)L.cs[b][hi];
+        if (nb_lo(L.g, c, ia[b], b) >= 0) d += (R)L.cs[b][c];
+        const int hi = nb_hi(L.g, c, ia[b], b);
+        if (hi >= 0) d += (R)L.cs[b][hi];
     }
-    L.invd[c] = (T)(1.0 / d);
+    L.invd[c] = (T)((R)1 / d);
 }
 
 // zero-guess pre-smoothing: red x = b / d, black from those red values
-template <typename T, int DIM>
-__device__ inline void presmooth_cell(const Level<T> &L, const T *__restrict__ b, T *__restrict__ x, long long c) {
+template <typename T, typename TB, int DIM>
+__device__ inline void presmooth_cell(const Level<T> &L, const TB *__restrict__ b, T *__restrict__ x, int c) {
+    using R = T;
     int ia[3];
     coords_of<DIM>(L.g, c, ia);
     const int col = (ia[0] + ia[1] + ia[2]) & 1;
     if (col == 0) {
-        x[c] = (T)((double)b[c] * (double)L.invd[c]);
+        x[c] = (T)((R)b[c] * (R)L.invd[c]);
     } else {
-        auto red = [&](long long e) { return (double)b[e] * (double)L.invd[e]; };
-        x[c] = (T)(((double)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (double)L.invd[c]);
+        auto red = [&](int e) { return (R)b[e] * (R)L.invd[e]; };
+        x[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (R)L.invd[c]);
     }
 }
 
-template <typename T, int DIM>
-__device__ inline void residual_cell(const Level<T> &L, const T *__restrict__ b, const T *__restrict__ x,
-                                     long long c) {
+template <typename T, typename TB, int DIM>
+__device__ inline void residual_cell(const Level<T> &L, const TB *__restrict__ b, const T *__restrict__ x,
+                                     int c) {
+    using R = T;
     int ia[3];
     coords_of<DIM>(L.g, c, ia);
-    L.r[c] = (T)((double)b[c] - apply_at<T, DIM>(L, x, c, ia));
+    L.r[c] = (T)((R)b[c] - apply_at<T, DIM>(L, x, c, ia));
 }
 
 // cell-centred linear prolongation along one axis: fine f takes 3/4 of its
 // parent f/2 and 1/4 of the coarse neighbour on its side; past a wall the
 // neighbour is the parent itself (weight 1 in total)
-__device__ inline void pro_axis(int f, int nc, int per, int &c0, int &c1, double &w0, double &w1) {
+template <typename R>
+__device__ inline void pro_axis(int f, int nc, int per, int &c0, int &c1, R &w0, R &w1) {
     const int p = f >> 1;
     int q = (f & 1) ? p + 1 : p - 1;
     c0 = p;
@@ -134,41 +143,42 @@ __device__ inline void pro_axis(int f, int nc, int per, int &c0, int &c1, double
             q = q < 0 ? nc - 1 : 0;
         } else {
             c1 = p;
-            w0 = 1.0;
-            w1 = 0.0;
+            w0 = (R)1;
+            w1 = (R)0;
             return;
         }
     }
     c1 = q;
-    w0 = 0.75;
-    w1 = 0.25;
+    w0 = (R)0.75;
+    w1 = (R)0.25;
 }
 
 template <typename T, int DIM>
-__device__ inline double prolong_at(const Geo &gf, const Geo &gc, const T *__restrict__ xc, const int fi[3]) {
+__device__ inline T prolong_at(const Geo &gf, const Geo &gc, const T *__restrict__ xc, const int fi[3]) {
+    using R = T;
     int c0[3], c1[3];
-    double w0[3], w1[3];
+    R w0[3], w1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (a < DIM) {
-            pro_axis(fi[a], gc.n[a], gc.per[a], c0[a], c1[a], w0[a], w1[a]);
+            pro_axis<R>(fi[a], gc.n[a], gc.per[a], c0[a], c1[a], w0[a], w1[a]);
         } else {
             c0[a] = c1[a] = 0;
             w0[a] = 1.0;
             w1[a] = 0.0;
         }
     }
-    const long long nx = gc.n[0], nxy = (long long)gc.n[0] * gc.n[1];
-    double v = 0.0;
+    const int nx = gc.n[0], nxy = (int)gc.n[0] * gc.n[1];
+    R v = 0.0;
 #pragma unroll
     for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz) {
-        const long long kz = (dz ? c1[2] : c0[2]) * nxy;
-        const double wz = dz ? w1[2] : w0[2];
+        const int kz = (dz ? c1[2] : c0[2]) * nxy;
+        const R wz = dz ? w1[2] : w0[2];
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
-            const long long ky = kz + (dy ? c1[1] : c0[1]) * nx;
-            const double wyz = wz * (dy ? w1[1] : w0[1]);
-            v += wyz * (w0[0] * (double)xc[ky + c0[0]] + w1[0] * (double)xc[ky + c1[0]]);
+            const int ky = kz + (dy ? c1[1] : c0[1]) * nx;
+            const R wyz = wz * (dy ? w1[1] : w0[1]);
+            v += wyz * (w0[0] * (R)xc[ky + c0[0]] + w1[0] * (R)xc[ky + c1[0]]);
         }
     }
     return v;
@@ -179,40 +189,42 @@ __device__ inline double prolong_at(const Geo &gf, const Geo &gc, const T *__res
 // adjacent child (4,3,1)/8 -- exactly the transpose of pro_axis / 2.  Always
 // four taps (an absent one gets weight 0 and a valid index) so that the
 // loads of a fully unrolled stencil issue together.
-__device__ inline void res_axis(int I, int nc, int nf, int per, int f[4], double w[4]) {
+template <typename R>
+__device__ inline void res_axis(int I, int nc, int nf, int per, int f[4], R w[4]) {
     const bool lo = (I > 0) || per, hi = (I < nc - 1) || per;
     f[0] = I > 0 ? 2 * I - 1 : (per ? nf - 1 : 0);
-    w[0] = lo ? 0.125 : 0.0;
+    w[0] = lo ? (R)0.125 : (R)0;
     f[1] = 2 * I;
-    w[1] = lo ? 0.375 : 0.5;
+    w[1] = lo ? (R)0.375 : (R)0.5;
     f[2] = 2 * I + 1;
-    w[2] = hi ? 0.375 : 0.5;
+    w[2] = hi ? (R)0.375 : (R)0.5;
     f[3] = I < nc - 1 ? 2 * I + 2 : (per ? 0 : nf - 1);
-    w[3] = hi ? 0.125 : 0.0;
+    w[3] = hi ? (R)0.125 : (R)0;
 }
 
 template <typename T, int DIM>
 __device__ inline void restrict_cell(const Geo &gf, const Geo &gc, const T *__restrict__ rf, T *__restrict__ bc,
-                                     long long c) {
+                                     int c) {
+    using R = T;
     int I[3];
     coords_of<DIM>(gc, c, I);
     int fx[4], fy[4], fz[4];
-    double wx[4], wy[4], wz[4];
-    res_axis(I[0], gc.n[0], gf.n[0], gc.per[0], fx, wx);
-    res_axis(I[1], gc.n[1], gf.n[1], gc.per[1], fy, wy);
-    if (DIM == 3) res_axis(I[2], gc.n[2], gf.n[2], gc.per[2], fz, wz);
-    const long long nx = gf.n[0], nxy = (long long)gf.n[0] * gf.n[1];
-    double v = 0.0;
+    R wx[4], wy[4], wz[4];
+    res_axis<R>(I[0], gc.n[0], gf.n[0], gc.per[0], fx, wx);
+    res_axis<R>(I[1], gc.n[1], gf.n[1], gc.per[1], fy, wy);
+    if (DIM == 3) res_axis<R>(I[2], gc.n[2], gf.n[2], gc.per[2], fz, wz);
+    const int nx = gf.n[0], nxy = (int)gf.n[0] * gf.n[1];
+    R v = 0.0;
 #pragma unroll
     for (int a = 0; a < (DIM == 3 ? 4 : 1); ++a) {
-        const long long kz = DIM == 3 ? fz[a] * nxy : 0;
-        const double wza = DIM == 3 ? wz[a] : 1.0;
+        const int kz = DIM == 3 ? fz[a] * nxy : 0;
+        const R wza = DIM == 3 ? wz[a] : 1.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const long long row = kz + fy[q] * nx;
-            double s = 0.0;
+            const int row = kz + fy[q] * nx;
+            R s = 0.0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) s += wx[e] * (double)rf[row + fx[e]];
+            for (int e = 0; e < 4; ++e) s += wx[e] * (R)rf[row + fx[e]];
             v += (wy[q] * wza) * s;
         }
     }
@@ -221,42 +233,44 @@ __device__ inline void restrict_cell(const Geo &gf, const Geo &gc, const T *__re
 
 // fused prolongation + black sweep: writes tmp = {red: x + P e, black:
 // GS update from those red values}; x is left untouched
-template <typename T, int DIM>
+template <typename T, typename TB, int DIM>
 __device__ inline void prolong_black_cell(const Level<T> &L, const Geo &gc, const T *__restrict__ xc,
-                                          const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ tmp,
-                                          long long c) {
+                                          const TB *__restrict__ b, const T *__restrict__ x, T *__restrict__ tmp,
+                                          int c) {
+    using R = T;
     int ia[3];
     coords_of<DIM>(L.g, c, ia);
     const int col = (ia[0] + ia[1] + ia[2]) & 1;
     if (col == 0) {
-        tmp[c] = (T)((double)x[c] + prolong_at<T, DIM>(L.g, gc, xc, ia));
+        tmp[c] = (T)((R)x[c] + prolong_at<T, DIM>(L.g, gc, xc, ia));
     } else {
-        auto red = [&](long long e) {
+        auto red = [&](int e) {
             int ie[3];
             coords_of<DIM>(L.g, e, ie);
-            return (double)x[e] + prolong_at<T, DIM>(L.g, gc, xc, ie);
+            return (R)x[e] + prolong_at<T, DIM>(L.g, gc, xc, ie);
         };
-        tmp[c] = (T)(((double)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (double)L.invd[c]);
+        tmp[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (R)L.invd[c]);
     }
 }
 
 // red sweep from tmp: x = {red: GS update from black tmp values, black: tmp}
-template <typename T, int DIM>
-__device__ inline void red_from_tmp_cell(const Level<T> &L, const T *__restrict__ b, const T *__restrict__ tmp,
-                                         T *__restrict__ x, long long c) {
+template <typename T, typename TB, int DIM>
+__device__ inline void red_from_tmp_cell(const Level<T> &L, const TB *__restrict__ b, const T *__restrict__ tmp,
+                                         T *__restrict__ x, int c) {
+    using R = T;
     int ia[3];
     coords_of<DIM>(L.g, c, ia);
     const int col = (ia[0] + ia[1] + ia[2]) & 1;
     if (col == 1) {
         x[c] = tmp[c];
     } else {
-        auto blk = [&](long long e) { return (double)tmp[e]; };
-        x[c] = (T)(((double)b[c] + offsum_at<T, DIM>(L, c, ia, blk)) * (double)L.invd[c]);
+        auto blk = [&](int e) { return (R)tmp[e]; };
+        x[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, blk)) * (R)L.invd[c]);
     }
 }
 
 template <typename T, int DIM>
-__device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, long long c) {
+__device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, int c) {
     int I[3];
     coords_of<DIM>(C.g, c, I);
     const Geo &gf = F.g;
@@ -269,8 +283,8 @@ __device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, long l
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
                 const int d3[3] = {dx, dy, dz};
-                const long long f =
-                    (2 * I[0] + dx) + (long long)gf.n[0] * ((2 * I[1] + dy) + (long long)gf.n[1] * (2 * I[2] + dz));
+                const int f =
+                    (2 * I[0] + dx) + (int)gf.n[0] * ((2 * I[1] + dy) + (int)gf.n[1] * (2 * I[2] + dz));
                 s += (double)F.s[f];
 #pragma unroll
                 for (int b = 0; b < DIM; ++b)
@@ -286,20 +300,20 @@ __device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, long l
 // grid-wide V-cycle kernels (one pass each)
 // ---------------------------------------------------------------------------
 #define GRID_LOOP(N) \
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < (N); c += (long long)gridDim.x * blockDim.x)
+    for (int c = (int)(blockIdx.x * blockDim.x + threadIdx.x); c < (int)(N); c += (int)(gridDim.x * blockDim.x))
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_presmooth(Level<T> L, const T *__restrict__ b, T *__restrict__ x,
+template <typename T, typename TB, int DIM>
+__global__ void __launch_bounds__(kBlock) k_presmooth(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,
                                                       const int *__restrict__ done) {
     if (*done) return;
-    GRID_LOOP(L.g.N) presmooth_cell<T, DIM>(L, b, x, c);
+    GRID_LOOP(L.g.N) presmooth_cell<T, TB, DIM>(L, b, x, c);
 }
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_residual(Level<T> L, const T *__restrict__ b, const T *__restrict__ x,
+template <typename T, typename TB, int DIM>
+__global__ void __launch_bounds__(kBlock) k_residual(Level<T> L, const TB *__restrict__ b, const T *__restrict__ x,
                                                      const int *__restrict__ done) {
     if (*done) return;
-    GRID_LOOP(L.g.N) residual_cell<T, DIM>(L, b, x, c);
+    GRID_LOOP(L.g.N) residual_cell<T, TB, DIM>(L, b, x, c);
 }
 
 template <typename T, int DIM>
@@ -309,71 +323,77 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo gf, Geo gc, const T *__
     GRID_LOOP(gc.N) restrict_cell<T, DIM>(gf, gc, rf, bc, c);
 }
 
-template <typename T, int DIM>
+template <typename T, typename TB, int DIM>
 __global__ void __launch_bounds__(kBlock) k_prolong_black(Level<T> L, Geo gc, const T *__restrict__ xc,
-                                                          const T *__restrict__ b, const T *__restrict__ x,
+                                                          const TB *__restrict__ b, const T *__restrict__ x,
                                                           T *__restrict__ tmp, const int *__restrict__ done) {
     if (*done) return;
-    GRID_LOOP(L.g.N) prolong_black_cell<T, DIM>(L, gc, xc, b, x, tmp, c);
+    GRID_LOOP(L.g.N) prolong_black_cell<T, TB, DIM>(L, gc, xc, b, x, tmp, c);
 }
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_red_from_tmp(Level<T> L, const T *__restrict__ b,
+template <typename T, typename TB, int DIM>
+__global__ void __launch_bounds__(kBlock) k_red_from_tmp(Level<T> L, const TB *__restrict__ b,
                                                          const T *__restrict__ tmp, T *__restrict__ x,
                                                          const int *__restrict__ done) {
     if (*done) return;
-    GRID_LOOP(L.g.N) red_from_tmp_cell<T, DIM>(L, b, tmp, x, c);
+    GRID_LOOP(L.g.N) red_from_tmp_cell<T, TB, DIM>(L, b, tmp, x, c);
 }
 
 // ---------------------------------------------------------------------------
 // single-workgroup kernels for the small levels
 // ---------------------------------------------------------------------------
-#define BLOCK_LOOP(N) for (long long c = threadIdx.x; c < (N); c += blockDim.x)
+#define BLOCK_LOOP(N) for (int c = (int)threadIdx.x; c < (int)(N); c += (int)blockDim.x)
 
 // x = Ainv b on the coarsest level (FP64 matrix, block-wide)
-template <typename T>
-__device__ inline void coarse_solve_block(int n, const double *__restrict__ Ainv, const T *__restrict__ b,
+template <typename T, typename TB>
+__device__ inline void coarse_solve_block(int n, const double *__restrict__ Ainv, const TB *__restrict__ b,
                                           T *__restrict__ x) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         double v = 0.0;
-        const double *row = Ainv + (long long)i * n;
+        const double *row = Ainv + i * n;
         for (int j = 0; j < n; ++j) v += row[j] * (double)b[j];
         x[i] = (T)v;
     }
 }
 
+template <typename T, typename TB, int DIM>
+__device__ inline void block_down(const Slot<T> &S, int l, const TB *__restrict__ b, T *__restrict__ x) {
+    const Level<T> &lv = S.lev[l];
+    BLOCK_LOOP(lv.g.N) presmooth_cell<T, TB, DIM>(lv, b, x, c);
+    __syncthreads();
+    BLOCK_LOOP(lv.g.N) residual_cell<T, TB, DIM>(lv, b, x, c);
+    __syncthreads();
+    BLOCK_LOOP(S.lev[l + 1].g.N) restrict_cell<T, DIM>(lv.g, S.lev[l + 1].g, lv.r, S.lev[l + 1].b, c);
+    __syncthreads();
+}
+
+template <typename T, typename TB, int DIM>
+__device__ inline void block_up(const Slot<T> &S, int l, const TB *__restrict__ b, T *__restrict__ x) {
+    const Level<T> &lv = S.lev[l];
+    BLOCK_LOOP(lv.g.N) prolong_black_cell<T, TB, DIM>(lv, S.lev[l + 1].g, S.lev[l + 1].x, b, x, lv.r, c);
+    __syncthreads();
+    BLOCK_LOOP(lv.g.N) red_from_tmp_cell<T, TB, DIM>(lv, b, lv.r, x, c);
+    __syncthreads();
+}
+
 // V-cycle over levels [l0, nlev) in one workgroup.  b0 / x0 are the
-// right-hand side / result of level l0 (they replace its own arrays).
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kSBThreads) k_vcycle_block(Slot<T> S, int l0, const T *__restrict__ b0,
+// right-hand side / result of level l0 (they replace its own arrays; b0 may
+// be stored in another precision).
+template <typename T, typename TB, int DIM>
+__global__ void __launch_bounds__(kSBThreads) k_vcycle_block(Slot<T> S, int l0, const TB *__restrict__ b0,
                                                              T *__restrict__ x0, const int *__restrict__ done) {
     if (*done) return;
     const int L = S.nlev;
-    for (int l = l0; l < L - 1; ++l) {
-        const Level<T> &lv = S.lev[l];
-        const T *b = l == l0 ? b0 : lv.b;
-        T *x = l == l0 ? x0 : lv.x;
-        BLOCK_LOOP(lv.g.N) presmooth_cell<T, DIM>(lv, b, x, c);
-        __syncthreads();
-        BLOCK_LOOP(lv.g.N) residual_cell<T, DIM>(lv, b, x, c);
-        __syncthreads();
-        BLOCK_LOOP(S.lev[l + 1].g.N) restrict_cell<T, DIM>(lv.g, S.lev[l + 1].g, lv.r, S.lev[l + 1].b, c);
-        __syncthreads();
+    if (l0 == L - 1) {
+        coarse_solve_block<T, TB>((int)S.lev[L - 1].g.N, S.Ainv, b0, x0);
+        return;
     }
-    {
-        const Level<T> &lc = S.lev[L - 1];
-        coarse_solve_block<T>((int)lc.g.N, S.Ainv, L - 1 == l0 ? b0 : lc.b, L - 1 == l0 ? x0 : lc.x);
-        __syncthreads();
-    }
-    for (int l = L - 2; l >= l0; --l) {
-        const Level<T> &lv = S.lev[l];
-        const T *b = l == l0 ? b0 : lv.b;
-        T *x = l == l0 ? x0 : lv.x;
-        BLOCK_LOOP(lv.g.N) prolong_black_cell<T, DIM>(lv, S.lev[l + 1].g, S.lev[l + 1].x, b, x, lv.r, c);
-        __syncthreads();
-        BLOCK_LOOP(lv.g.N) red_from_tmp_cell<T, DIM>(lv, b, lv.r, x, c);
-        __syncthreads();
-    }
+    block_down<T, TB, DIM>(S, l0, b0, x0);
+    for (int l = l0 + 1; l < L - 1; ++l) block_down<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x);
+    coarse_solve_block<T, T>((int)S.lev[L - 1].g.N, S.Ainv, S.lev[L - 1].b, S.lev[L - 1].x);
+    __syncthreads();
+    for (int l = L - 2; l > l0; --l) block_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x);
+    block_up<T, TB, DIM>(S, l0, b0, x0);
 }
 
 // In-place Gauss-Jordan inversion of the n x n SPD matrix held in A (no
@@ -428,8 +448,8 @@ __global__ void __launch_bounds__(kSBThreads) k_setup_block(Slot<T> S, int l0) {
         coords_of<DIM>(C.g, c, ia);
         double d = (double)C.s[c];
         for (int b = 0; b < DIM; ++b) {
-            const long long lo = nb_lo(C.g, c, ia[b], b);
-            const long long hi = nb_hi(C.g, c, ia[b], b);
+            const int lo = nb_lo(C.g, c, ia[b], b);
+            const int hi = nb_hi(C.g, c, ia[b], b);
             if (lo >= 0) {
                 const double w = (double)C.cs[b][c];
                 d += w;
@@ -476,13 +496,13 @@ __device__ inline double sum_parts_all(const double *__restrict__ part, int npar
 
 // Lap(x) at c for the CH operator (walled axes Neumann), x given by a functor
 template <int DIM, typename F>
-__device__ inline double lap_at(const Geo &g, long long c, const int ia[3], double ih2, F val) {
+__device__ inline double lap_at(const Geo &g, int c, const int ia[3], double ih2, F val) {
     const double xc = val(c);
     double acc = 0.0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
-        const long long lo = nb_lo(g, c, ia[b], b);
-        const long long hi = nb_hi(g, c, ia[b], b);
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
         if (lo >= 0) acc += val(lo) - xc;
         if (hi >= 0) acc += val(hi) - xc;
     }
@@ -491,15 +511,15 @@ __device__ inline double lap_at(const Geo &g, long long c, const int ia[3], doub
 
 // p_new = (z - zmean) + beta p_old (beta = 0: p_new = z - zmean);
 // q = A p_new (slot operator); partial p.q
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const T *__restrict__ z,
+template <typename T, typename TZ, int DIM>
+__global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ *__restrict__ z,
                                                            const T *__restrict__ pold, T *__restrict__ pnew,
                                                            T *__restrict__ q, const Scal *__restrict__ sc,
                                                            double *__restrict__ part) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
     const double beta = sc->beta, zm = sc->zmean;
-    auto pv = [&](long long e) { return ((double)z[e] - zm) + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
+    auto pv = [&](int e) { return ((double)z[e] - zm) + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
     double acc = 0.0;
     GRID_LOOP(L.g.N) {
         int ia[3];
@@ -508,8 +528,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const T *
         double qc = (double)L.s[c] * pc;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            const long long lo = nb_lo(L.g, c, ia[b], b);
-            const long long hi = nb_hi(L.g, c, ia[b], b);
+            const int lo = nb_lo(L.g, c, ia[b], b);
+            const int hi = nb_hi(L.g, c, ia[b], b);
             if (lo >= 0) qc += (double)L.cs[b][c] * (pc - pv(lo));
             if (hi >= 0) qc += (double)L.cs[b][hi] * (pc - pv(hi));
         }
@@ -522,13 +542,13 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const T *
 }
 
 // CH operator, first half: p_new = z + beta p_old, t = L p_new.
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const T *__restrict__ z,
+template <typename T, typename TZ, int DIM>
+__global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const TZ *__restrict__ z,
                                                        const T *__restrict__ pold, T *__restrict__ pnew,
                                                        T *__restrict__ t, const Scal *__restrict__ sc) {
     if (sc->done) return;
     const double beta = sc->beta;
-    auto pv = [&](long long e) { return (double)z[e] + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
+    auto pv = [&](int e) { return (double)z[e] + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
     GRID_LOOP(g.N) {
         int ia[3];
         coords_of<DIM>(g, c, ia);
@@ -545,7 +565,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_ch_apply(Geo g, double ih2, doub
                                                          double *__restrict__ part) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
-    auto tv = [&](long long e) { return (double)t[e]; };
+    auto tv = [&](int e) { return (double)t[e]; };
     double acc = 0.0;
     GRID_LOOP(g.N) {
         int ia[3];
@@ -562,7 +582,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_ch_apply(Geo g, double ih2, doub
 // alpha = rz / sum(part_pq) (every block, same order); x += alpha p;
 // r -= alpha q; partial r.r
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_update(long long N, const T *__restrict__ p, const T *__restrict__ q,
+__global__ void __launch_bounds__(kBlock) k_pcg_update(int N, const T *__restrict__ p, const T *__restrict__ q,
                                                        T *__restrict__ x, T *__restrict__ r, Scal *sc,
                                                        const double *__restrict__ part_pq, int nparts,
                                                        double *__restrict__ part_rr) {
@@ -606,8 +626,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_fin_rr(Scal *sc, const double *_
 }
 
 // partials of r.z, sum z, sum r
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_pcg_rz(long long N, const T *__restrict__ r, const T *__restrict__ z,
+template <typename T, typename TZ>
+__global__ void __launch_bounds__(kBlock) k_pcg_rz(int N, const T *__restrict__ r, const TZ *__restrict__ z,
                                                    const Scal *__restrict__ sc, double *__restrict__ p0,
                                                    double *__restrict__ p1, double *__restrict__ p2, int singular) {
     if (sc->done) return;
@@ -637,7 +657,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rz(long long N, const T *__restr
 // search directions.
 __global__ void __launch_bounds__(kBlock) k_pcg_fin_rz(Scal *sc, const double *__restrict__ p0,
                                                        const double *__restrict__ p1, const double *__restrict__ p2,
-                                                       int nparts, long long N, int first, int singular) {
+                                                       int nparts, int N, int first, int singular) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
     const double trz = sum_parts_all(p0, nparts, lds);
@@ -680,10 +700,30 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init_slot(Level<T> L, const T *_
     }
 }
 
+// zero initial guess: x = 0, r = b; partials of b.b (twice)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pcg_init_zero(int N, const T *__restrict__ b, T *__restrict__ x,
+                                                          T *__restrict__ r, double *__restrict__ p0,
+                                                          double *__restrict__ p1) {
+    __shared__ double lds[kBlock / kWave];
+    double bb = 0.0;
+    GRID_LOOP(N) {
+        const T bc = b[c];
+        x[c] = (T)0;
+        r[c] = bc;
+        bb += (double)bc * (double)bc;
+    }
+    const double s0 = block_sum(bb, lds);
+    if (threadIdx.x == 0) {
+        p0[blockIdx.x] = s0;
+        p1[blockIdx.x] = s0;
+    }
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kBlock) k_ch_lap_plain(Geo g, double ih2, const T *__restrict__ x,
                                                          T *__restrict__ t) {
-    auto xv = [&](long long e) { return (double)x[e]; };
+    auto xv = [&](int e) { return (double)x[e]; };
     GRID_LOOP(g.N) {
         int ia[3];
         coords_of<DIM>(g, c, ia);
@@ -698,7 +738,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init_ch(Geo g, double ih2, doubl
                                                         const T *__restrict__ t, T *__restrict__ r,
                                                         double *__restrict__ p0, double *__restrict__ p1) {
     __shared__ double lds[kBlock / kWave];
-    auto tv = [&](long long e) { return (double)t[e]; };
+    auto tv = [&](int e) { return (double)t[e]; };
     double bb = 0.0, rr = 0.0;
     GRID_LOOP(g.N) {
         int ia[3];
@@ -749,7 +789,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_fin_init(Scal *sc, const double 
 
 // mean removal: partial sums, then every block sums them and subtracts
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sum(long long N, const T *__restrict__ x, double *__restrict__ part) {
+__global__ void __launch_bounds__(kBlock) k_sum(int N, const T *__restrict__ x, double *__restrict__ part) {
     __shared__ double lds[kBlock / kWave];
     double acc = 0.0;
     GRID_LOOP(N) acc += (double)x[c];
@@ -758,7 +798,7 @@ __global__ void __launch_bounds__(kBlock) k_sum(long long N, const T *__restrict
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_sub_mean(long long N, T *__restrict__ x, const double *__restrict__ part,
+__global__ void __launch_bounds__(kBlock) k_sub_mean(int N, T *__restrict__ x, const double *__restrict__ part,
                                                      int nparts) {
     __shared__ double lds[kBlock / kWave];
     const double m = sum_parts_all(part, nparts, lds) / (double)N;
@@ -784,7 +824,7 @@ __global__ void __launch_bounds__(kBlock) k_slot_apply(Level<T> L, const T *__re
 template <typename T>
 static int single_block_level(const Slot<T> &S) {
     int l = 0;
-    const long long lim = sb_cells();
+    const int lim = sb_cells();
     while (l < S.nlev - 1 && S.lev[l].g.N > lim) ++l;
     return l;
 }
@@ -814,68 +854,93 @@ void mg_setup(Slot<T> &S, int dim, hipStream_t st) {
         mg_setup_d<T, 3>(S, st);
 }
 
-template <typename T, int DIM>
-static void vcycle_d(Slot<T> &S, const T *b0, T *x0, const int *done, hipStream_t st) {
+template <typename T, typename TB, int DIM>
+static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st) {
+    constexpr double W = sizeof(T);
+    Level<T> &lv = S.lev[l];
+    const int N = (int)lv.g.N, Nc = (int)S.lev[l + 1].g.N;
+    const double WB = sizeof(TB) - W;   // extra bytes of a wider right-hand side
+    LAUNCH(K_SMOOTH, W * (2 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
+    LAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual<T, TB, DIM>), N, st, lv, b, (const T *)x, done);
+    LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict<T, DIM>), Nc, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
+           S.lev[l + 1].b, done);
+}
+
+template <typename T, typename TB, int DIM>
+static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st) {
+    constexpr double W = sizeof(T);
+    Level<T> &lv = S.lev[l];
+    const int N = (int)lv.g.N, Nc = (int)S.lev[l + 1].g.N;
+    const double WB = sizeof(TB) - W;
+    LAUNCH(K_PROLONG, W * ((4 + DIM) * N + Nc) + WB * N, (k_prolong_black<T, TB, DIM>), N, st, lv, S.lev[l + 1].g,
+           (const T *)S.lev[l + 1].x, b, (const T *)x, lv.r, done);
+    LAUNCH(K_SMOOTH, W * (4 + DIM) * N + WB * N, (k_red_from_tmp<T, TB, DIM>), N, st, lv, b, (const T *)lv.r, x,
+           done);
+}
+
+// One V-cycle of slot S: x0 ~ A^{-1} b0 (b0 may be stored in another
+// precision than the hierarchy).
+template <typename T, typename TB, int DIM>
+static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream_t st) {
     constexpr double W = sizeof(T);
     const int lsb = S.lsb;
-    for (int l = 0; l < lsb; ++l) {
-        Level<T> &lv = S.lev[l];
-        const T *b = l == 0 ? b0 : lv.b;
-        T *x = l == 0 ? x0 : lv.x;
-        const long long N = lv.g.N, Nc = S.lev[l + 1].g.N;
-        LAUNCH(K_SMOOTH, W * (2 + DIM) * N, (k_presmooth<T, DIM>), N, st, lv, b, x, done);
-        LAUNCH(K_RESIDUAL, W * (4 + DIM) * N, (k_residual<T, DIM>), N, st, lv, b, (const T *)x, done);
-        LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict<T, DIM>), Nc, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
-               S.lev[l + 1].b, done);
+    if (lsb > 0) {
+        vcycle_down<T, TB, DIM>(S, 0, b0, x0, done, st);
+        for (int l = 1; l < lsb; ++l) vcycle_down<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
     }
     {
         double bytes = 8.0 * S.ncoarse * S.ncoarse;
         for (int l = lsb; l < S.nlev; ++l) bytes += W * 12.0 * S.lev[l].g.N;
-        const T *b = lsb == 0 ? b0 : S.lev[lsb].b;
-        T *x = lsb == 0 ? x0 : S.lev[lsb].x;
-        LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, DIM>), kSBThreads, st, S, lsb, b, x, done);
+        if (lsb == 0)
+            LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, TB, DIM>), kSBThreads, st, S, 0, b0, x0, done);
+        else
+            LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, T, DIM>), kSBThreads, st, S, lsb,
+                    (const T *)S.lev[lsb].b, S.lev[lsb].x, done);
     }
-    for (int l = lsb - 1; l >= 0; --l) {
-        Level<T> &lv = S.lev[l];
-        const T *b = l == 0 ? b0 : lv.b;
-        T *x = l == 0 ? x0 : lv.x;
-        const long long N = lv.g.N, Nc = S.lev[l + 1].g.N;
-        LAUNCH(K_PROLONG, W * ((4 + DIM) * N + Nc), (k_prolong_black<T, DIM>), N, st, lv, S.lev[l + 1].g,
-               (const T *)S.lev[l + 1].x, b, (const T *)x, lv.r, done);
-        LAUNCH(K_SMOOTH, W * (4 + DIM) * N, (k_red_from_tmp<T, DIM>), N, st, lv, b, (const T *)lv.r, x, done);
+    if (lsb > 0) {
+        for (int l = lsb - 1; l >= 1; --l) vcycle_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
+        vcycle_up<T, TB, DIM>(S, 0, b0, x0, done, st);
     }
 }
 
 template <typename T>
 void mg_vcycle(Slot<T> &S, int dim, const T *b0, T *x0, const int *done, hipStream_t st) {
     if (dim == 2)
-        vcycle_d<T, 2>(S, b0, x0, done, st);
+        vcycle_d<T, T, 2>(S, b0, x0, done, st);
     else
-        vcycle_d<T, 3>(S, b0, x0, done, st);
+        vcycle_d<T, T, 3>(S, b0, x0, done, st);
 }
 
-template <typename T, int DIM>
-static void precond_d(Slot<T> &S, OpKind kind, const T *r, T *z, T *tmp, const int *done, hipStream_t st) {
+// Preconditioner z = B r with the hierarchy SP (precision TP); r in T.
+template <typename T, typename TP, int DIM>
+static void precond_d(Slot<TP> &SP, OpKind kind, const T *r, TP *z, TP *w, const int *done, hipStream_t st) {
     if (kind == OP_CH) {
         // M ~ (I - c L)^2 with c = sqrt(b): two V-cycles of the slot operator
-        vcycle_d<T, DIM>(S, r, tmp, done, st);
-        vcycle_d<T, DIM>(S, tmp, z, done, st);
+        vcycle_d<TP, T, DIM>(SP, r, w, done, st);
+        vcycle_d<TP, TP, DIM>(SP, w, z, done, st);
     } else {
-        vcycle_d<T, DIM>(S, r, z, done, st);
+        vcycle_d<TP, T, DIM>(SP, r, z, done, st);
     }
 }
 
-template <typename T, int DIM>
-static hipError_t pcg_d(Slot<T> &S, OpKind kind, ChOp ch, const T *b, T *x, double rtol, int max_iter, int predict,
-                        Red &red, PcgVecs<T> &v, hipStream_t st, SolveOut *out) {
+// PCG in precision T (operator SA level 0, vectors, updates) preconditioned
+// by V-cycles of the hierarchy SP in precision TP.
+template <typename T, typename TP, int DIM>
+static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T *b, T *x, double rtol, int max_iter,
+                        int predict, Red &red, const PcgVecs2<T, TP> &v, hipStream_t st, SolveOut *out,
+                        int zero_guess, int check_init = 0) {
     constexpr double W = sizeof(T);
-    const Level<T> &L0 = S.lev[0];
+    constexpr double WP = sizeof(TP);
+    const Level<T> &L0 = SA.lev[0];
     const Geo g = L0.g;
-    const long long N = g.N;
+    const int N = (int)g.N;
     const int nb = grid_for(N);
+    const int singular = SP.singular;
     Scal *sc = red.scal;
     const int *done = &sc->done;
-    if (kind == OP_SLOT) {
+    if (zero_guess) {
+        LAUNCH(K_PCG_INIT, W * 3 * N, (k_pcg_init_zero<T>), N, st, N, b, x, v.r, red.part0, red.part1);
+    } else if (kind == OP_SLOT) {
         LAUNCH(K_PCG_INIT, W * (4 + DIM) * N, (k_pcg_init_slot<T, DIM>), N, st, L0, b, (const T *)x, v.r, red.part0,
                red.part1);
     } else {
@@ -885,14 +950,30 @@ static hipError_t pcg_d(Slot<T> &S, OpKind kind, ChOp ch, const T *b, T *x, doub
     }
     LAUNCH1(K_PCG_INIT, 16.0 * nb, (k_pcg_fin_init), kBlock, st, sc, (const double *)red.part0,
             (const double *)red.part1, nb, rtol, max_iter);
-    precond_d<T, DIM>(S, kind, v.r, v.z, v.t, done, st);
-    LAUNCH(K_PCG_DOT, W * 2 * N, (k_pcg_rz<T>), N, st, N, (const T *)v.r, (const T *)v.z, (const Scal *)sc, red.part0,
-           red.part1, red.part2, S.singular);
+    Scal hs;
+    if (check_init) {
+        // refinement round: return at once if the true residual already meets
+        // the tolerance (no V-cycle or early-exit launches are queued)
+        hipError_t e = hipMemcpyAsync(&hs, sc, sizeof(Scal), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (hs.done) {
+            if (out) {
+                out->iters = 0;
+                out->rel_res = hs.bb > 0.0 ? sqrt(hs.rr / hs.bb) : 0.0;
+                out->unconverged = 0;
+                out->nonfinite = hs.nonfinite;
+            }
+            return hipGetLastError();
+        }
+    }
+    precond_d<T, TP, DIM>(SP, kind, v.r, v.z, v.w, done, st);
+    LAUNCH(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z, (const Scal *)sc,
+           red.part0, red.part1, red.part2, singular);
     LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
-            (const double *)red.part1, (const double *)red.part2, nb, N, 1, S.singular);
+            (const double *)red.part1, (const double *)red.part2, nb, N, 1, singular);
     int launched = 0;
     int chunk = predict < 1 ? 1 : predict;
-    Scal hs;
     for (;;) {
         if (chunk > max_iter - launched) chunk = max_iter - launched;
         for (int it = 0; it < chunk; ++it) {
@@ -900,10 +981,10 @@ static hipError_t pcg_d(Slot<T> &S, OpKind kind, ChOp ch, const T *b, T *x, doub
             T *pnew = (k & 1) ? v.p1 : v.p0;
             T *pold = (k & 1) ? v.p0 : v.p1;
             if (kind == OP_SLOT) {
-                LAUNCH(K_PCG_APPLY, W * (5 + DIM) * N, (k_pcg_apply_slot<T, DIM>), N, st, L0, (const T *)v.z,
-                       (const T *)pold, pnew, v.q, (const Scal *)sc, red.part0);
+                LAUNCH(K_PCG_APPLY, W * (4 + DIM) * N + WP * N, (k_pcg_apply_slot<T, TP, DIM>), N, st, L0,
+                       (const TP *)v.z, (const T *)pold, pnew, v.q, (const Scal *)sc, red.part0);
             } else {
-                LAUNCH(K_PCG_APPLY, W * 4 * N, (k_pcg_ch_lap<T, DIM>), N, st, g, ch.ih2, (const T *)v.z,
+                LAUNCH(K_PCG_APPLY, W * 3 * N + WP * N, (k_pcg_ch_lap<T, TP, DIM>), N, st, g, ch.ih2, (const TP *)v.z,
                        (const T *)pold, pnew, v.t, (const Scal *)sc);
                 LAUNCH(K_PCG_APPLY, W * 3 * N, (k_pcg_ch_apply<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, (const T *)pnew,
                        (const T *)v.t, v.q, (const Scal *)sc, red.part0);
@@ -911,11 +992,11 @@ static hipError_t pcg_d(Slot<T> &S, OpKind kind, ChOp ch, const T *b, T *x, doub
             LAUNCH(K_PCG_UPDATE, W * 6 * N, (k_pcg_update<T>), N, st, N, (const T *)pnew, (const T *)v.q, x, v.r, sc,
                    (const double *)red.part0, nb, red.part1);
             LAUNCH1(K_PCG_UPDATE, 8.0 * nb, (k_pcg_fin_rr), kBlock, st, sc, (const double *)red.part1, nb);
-            precond_d<T, DIM>(S, kind, v.r, v.z, v.t, done, st);
-            LAUNCH(K_PCG_DOT, W * 2 * N, (k_pcg_rz<T>), N, st, N, (const T *)v.r, (const T *)v.z, (const Scal *)sc,
-                   red.part0, red.part1, red.part2, S.singular);
+            precond_d<T, TP, DIM>(SP, kind, v.r, v.z, v.w, done, st);
+            LAUNCH(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
+                   (const Scal *)sc, red.part0, red.part1, red.part2, singular);
             LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
-                    (const double *)red.part1, (const double *)red.part2, nb, N, 0, S.singular);
+                    (const double *)red.part1, (const double *)red.part2, nb, N, 0, singular);
         }
         launched += chunk;
         hipError_t e = hipMemcpyAsync(&hs, sc, sizeof(Scal), hipMemcpyDeviceToHost, st);
@@ -935,16 +1016,80 @@ static hipError_t pcg_d(Slot<T> &S, OpKind kind, ChOp ch, const T *b, T *x, doub
 
 template <typename T>
 hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x, double rtol, int max_iter,
-                     int predict, Red &red, PcgVecs<T> &v, hipStream_t st, SolveOut *out) {
-    if (dim == 2) return pcg_d<T, 2>(S, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out);
-    return pcg_d<T, 3>(S, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out);
+                     int predict, Red &red, PcgVecs<T> &v, hipStream_t st, SolveOut *out, int zero_guess) {
+    const PcgVecs2<T, T> v2{v.r, v.p0, v.p1, v.q, v.t, v.z, v.t};
+    if (dim == 2) return pcg_d<T, T, 2>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess);
+    return pcg_d<T, T, 3>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess);
+}
+
+// ---------------------------------------------------------------------------
+// precision form: FP32 multigrid-preconditioned CG inside an FP64 iterative
+// refinement.  The outer loop computes the residual r = b - A x in FP64 with
+// the FP64 level-0 coefficients, solves A e = r in FP32 (FP32 vectors,
+// coefficients and sweeps; FP64 dot products and coarse inverse) and adds e
+// in FP64, until ||r||_2 <= rtol max(||b||_2, ||r_0||_2) as in the FP64 form.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_conv_coef(Level<double> A, Level<float> B) {
+    GRID_LOOP(A.g.N) {
+        B.s[c] = (float)A.s[c];
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) B.cs[b][c] = (float)A.cs[b][c];
+    }
+}
+
+void convert_level0(const Slot<double> &A, Slot<float> &B, int dim, hipStream_t st) {
+    const int N = A.lev[0].g.N;
+    const double bytes = (8.0 + 4.0) * (1 + dim) * N;
+    if (dim == 2)
+        LAUNCH(K_MG_SETUP, bytes, (k_conv_coef<2>), N, st, A.lev[0], B.lev[0]);
+    else
+        LAUNCH(K_MG_SETUP, bytes, (k_conv_coef<3>), N, st, A.lev[0], B.lev[0]);
+}
+
+template <int DIM>
+static hipError_t refine_d(Slot<double> &S64, Slot<float> &S32, OpKind kind, ChOp ch, const double *b, double *x,
+                           double rtol, int max_iter, int *predict, Red &red, const PcgVecs2<double, float> &v,
+                           hipStream_t st, SolveOut *out) {
+    // Rounds of FP64 PCG with the FP32 V-cycle preconditioner, each started
+    // from the current x: its initial residual is the true FP64 residual
+    // b - A x, so the loop ends when that residual meets the tolerance
+    // (a round that converges at its initial residual).
+    int total = 0;
+    SolveOut o;
+    o.iters = 0;
+    o.rel_res = 0.0;
+    o.unconverged = 1;
+    o.nonfinite = 0;
+    for (int round = 0; round < kMaxRefine && total < max_iter; ++round) {
+        hipError_t e = pcg_d<double, float, DIM>(S64, S32, kind, ch, b, x, rtol, max_iter - total,
+                                                 round == 0 ? *predict : 2, red, v, st, &o, 0, round > 0);
+        if (e != hipSuccess) return e;
+        total += o.iters;
+        if (o.nonfinite) break;
+        if (o.iters > 0 && round == 0) *predict = o.iters;
+        if (o.iters == 0 && !o.unconverged) break;   // true residual already within tolerance
+    }
+    if (out) {
+        *out = o;
+        out->iters = total;
+    }
+    return hipGetLastError();
+}
+
+hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kind, ChOp ch, const double *b,
+                        double *x, double rtol, int max_iter, int *predict, Red &red,
+                        const PcgVecs2<double, float> &v, hipStream_t st, SolveOut *out) {
+    if (dim == 2) return refine_d<2>(S64, S32, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out);
+    return refine_d<3>(S64, S32, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out);
 }
 
 template <typename T>
 void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st) {
-    const int nb = grid_for(g.N);
-    LAUNCH(K_MEAN, sizeof(T) * g.N, (k_sum<T>), g.N, st, g.N, (const T *)x, red.part0);
-    LAUNCH(K_MEAN, 2.0 * sizeof(T) * g.N, (k_sub_mean<T>), g.N, st, g.N, x, (const double *)red.part0, nb);
+    const int N = (int)g.N;
+    const int nb = grid_for(N);
+    LAUNCH(K_MEAN, sizeof(T) * N, (k_sum<T>), N, st, N, (const T *)x, red.part0);
+    LAUNCH(K_MEAN, 2.0 * sizeof(T) * N, (k_sub_mean<T>), N, st, N, x, (const double *)red.part0, nb);
 }
 
 template <typename T>
@@ -958,7 +1103,10 @@ void slot_apply(Slot<T> &S, int dim, const T *x, T *y, hipStream_t st) {
 template void mg_setup<double>(Slot<double> &, int, hipStream_t);
 template void mg_vcycle<double>(Slot<double> &, int, const double *, double *, const int *, hipStream_t);
 template hipError_t pcg_solve<double>(Slot<double> &, int, OpKind, ChOp, const double *, double *, double, int, int,
-                                      Red &, PcgVecs<double> &, hipStream_t, SolveOut *);
+                                      Red &, PcgVecs<double> &, hipStream_t, SolveOut *, int);
+template void mg_setup<float>(Slot<float> &, int, hipStream_t);
+template hipError_t pcg_solve<float>(Slot<float> &, int, OpKind, ChOp, const float *, float *, double, int, int,
+                                     Red &, PcgVecs<float> &, hipStream_t, SolveOut *, int);
 template void remove_mean<double>(const Geo &, double *, Red &, hipStream_t);
 template void slot_apply<double>(Slot<double> &, int, const double *, double *, hipStream_t);
 

@@ -11,6 +11,14 @@ struct PcgVecs {
     T *r, *z, *p0, *p1, *q, *t;
 };
 
+// PCG vectors in precision T with the preconditioned vector z and the
+// preconditioner's scratch w in precision TP.
+template <typename T, typename TP>
+struct PcgVecs2 {
+    T *r, *p0, *p1, *q, *t;
+    TP *z, *w;
+};
+
 struct SolveOut {
     int iters;
     double rel_res;
@@ -40,7 +48,20 @@ void mg_vcycle(Slot<T> &S, int dim, const T *b0, T *x0, const int *done, hipStre
 template <typename T>
 hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x, double rtol,
                      int max_iter, int predict, Red &red, PcgVecs<T> &v, hipStream_t st,
-                     SolveOut *out);
+                     SolveOut *out, int zero_guess = 0);
+
+// Precision form: FP64 conjugate gradients (residual recurrence, updates and
+// dot products in FP64) preconditioned by FP32 V-cycles (FP32 coefficients,
+// smoother sweeps and transfers; FP64 coarsest inverse), wrapped in FP64
+// iterative refinement: rounds restart from the current x with the true
+// FP64 residual until it meets the tolerance.  S64 supplies the FP64
+// level-0 operator, S32 the FP32 hierarchy (level-0 coefficients converted by
+// convert_level0 and coarsened by mg_setup<float> beforehand).
+constexpr int kMaxRefine = 4;
+void convert_level0(const Slot<double> &A, Slot<float> &B, int dim, hipStream_t st);
+hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kind, ChOp ch, const double *b,
+                        double *x, double rtol, int max_iter, int *predict, Red &red,
+                        const PcgVecs2<double, float> &v, hipStream_t st, SolveOut *out);
 
 // Subtract the mean of a cell array (deterministic).  Used for the
 // singular pressure system (right-hand side, then the solution gauge).

@@ -24,7 +24,7 @@ __device__ inline double dpsi(double p) { return p * p * p - p; }
 __device__ inline double pullback(double p) { return fabs(p) <= 1.0 ? p : copysign(1.0, p); }
 
 #define CELL_LOOP(N) \
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < (N); c += (long long)gridDim.x * blockDim.x)
+    for (int c = (int)(blockIdx.x * blockDim.x + threadIdx.x); c < (int)(N); c += (int)(gridDim.x * blockDim.x))
 
 // ---------------------------------------------------------------------------
 // S1
@@ -34,15 +34,15 @@ __global__ void __launch_bounds__(kBlock) k_ch_rhs(Geo g, StepConst k, const dou
                                                    double *__restrict__ r, double *__restrict__ phihat) {
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
         const double pc = phi[c];
         const double gc = dpsi(pc) - k.S * pc;
         double div = 0.0, lap = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const long long lo = nb_lo(g, c, ia[a], a);
-            const long long hi = nb_hi(g, c, ia[a], a);
+            const int lo = nb_lo(g, c, ia[a], a);
+            const int hi = nb_hi(g, c, ia[a], a);
             double flo = 0.0, fhi = 0.0;
             if (lo >= 0) {
                 const double pl = phi[lo];
@@ -69,14 +69,14 @@ __global__ void __launch_bounds__(kBlock) k_mu(Geo g, StepConst k, const double 
                                                const double *__restrict__ ph, double *__restrict__ mu) {
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
         const double xc = ph[c];
         double lap = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const long long lo = nb_lo(g, c, ia[a], a);
-            const long long hi = nb_hi(g, c, ia[a], a);
+            const int lo = nb_lo(g, c, ia[a], a);
+            const int hi = nb_hi(g, c, ia[a], a);
             if (lo >= 0) lap += ph[lo] - xc;
             if (hi >= 0) lap += ph[hi] - xc;
         }
@@ -98,14 +98,14 @@ __global__ void __launch_bounds__(kBlock) k_phi_update(Geo g, StepConst k, const
                                                        const double *__restrict__ mu, double *__restrict__ phin) {
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
         const double pc = phi[c], mc = mu[c];
         double div = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const long long lo = nb_lo(g, c, ia[a], a);
-            const long long hi = nb_hi(g, c, ia[a], a);
+            const int lo = nb_lo(g, c, ia[a], a);
+            const int hi = nb_hi(g, c, ia[a], a);
             const double flo = lo >= 0 ? phi_face_flux(k, u.a[a][c], phi[lo], pc, mu[lo], mc) : 0.0;
             const double fhi = hi >= 0 ? phi_face_flux(k, u.a[a][hi], pc, phi[hi], mc, mu[hi]) : 0.0;
             div += fhi - flo;
@@ -122,10 +122,10 @@ __global__ void __launch_bounds__(kBlock) k_phi_update(Geo g, StepConst k, const
 // b (index ib of f along b), zero on wall faces.
 template <int DIM>
 __device__ inline double mflux(const Geo &g, const StepConst &k, const double *__restrict__ phi,
-                               const double *__restrict__ mu, const double *__restrict__ ub, int b, long long f, int ib) {
+                               const double *__restrict__ mu, const double *__restrict__ ub, int b, int f, int ib) {
     if (f < 0) return 0.0;                       // unstored upper wall face
     if (!g.per[b] && ib == 0) return 0.0;        // stored wall face
-    const long long lo = nb_lo(g, f, ib, b);
+    const int lo = nb_lo(g, f, ib, b);
     const double rl = k.alpha * phi[f] + k.beta, rlo = k.alpha * phi[lo] + k.beta;
     return (0.5 * (rl + rlo)) * ub[f] - (k.alpha / (k.Cn * k.Pe)) * ((mu[f] - mu[lo]) * k.ih);
 }
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
     const double rvis = k.inv_Re * k.ih2;
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
         const double *ua = u.a[a];
         if (!g.per[a] && ia[a] == 0) {
@@ -153,8 +153,8 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
             ustar[c] = 0.0;
             continue;
         }
-        const long long cam = nb_lo(g, c, ia[a], a);   // cell c - e_a
-        auto eta_of = [&](long long e) { return k.gamma * pullback(phin[e]) + k.xi; };
+        const int cam = nb_lo(g, c, ia[a], a);   // cell c - e_a
+        auto eta_of = [&](int e) { return k.gamma * pullback(phin[e]) + k.xi; };
         const double rf_new = 0.5 * ((k.alpha * pullback(phin[c]) + k.beta) + (k.alpha * pullback(phin[cam]) + k.beta));
         const double rf_old = 0.5 * ((k.alpha * pullback(phi[c]) + k.beta) + (k.alpha * pullback(phi[cam]) + k.beta));
         const double e_c = eta_of(c), e_am = eta_of(cam);
@@ -162,8 +162,8 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
         double nadv = 0.0;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            const long long lo = nb_lo(g, c, ia[b], b);
-            const long long hi = nb_hi(g, c, ia[b], b);
+            const int lo = nb_lo(g, c, ia[b], b);
+            const int hi = nb_hi(g, c, ia[b], b);
             if (b == a) {
                 // viscous coupling through the cell centres c - e_a (lower) and c (upper)
                 double w = e_am * rvis;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
             } else {
                 // viscous coupling through the edge between faces c - e_b and c
                 if (lo >= 0) {
-                    const long long lam = nb_lo(g, lo, ia[a], a);   // c - e_b - e_a
+                    const int lam = nb_lo(g, lo, ia[a], a);   // c - e_b - e_a
                     const double ee = 0.25 * (((e_c + e_am) + eta_of(lo)) + eta_of(lam));
                     cs.a[b][c] = (!g.per[b] && ia[b] == 0) ? 0.0 : ee * rvis;
                 } else {
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
                 // skew advection, b != a
                 const int ibn = wrap_next(ia[b], g.n[b]);
                 const double mph = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[b], b, hi, ibn) : 0.0;
-                const long long hiam = hi >= 0 ? nb_lo(g, hi, ia[a], a) : -1;   // c + e_b - e_a
+                const int hiam = hi >= 0 ? nb_lo(g, hi, ia[a], a) : -1;   // c + e_b - e_a
                 const double mpha = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[b], b, hiam, ibn) : 0.0;
                 const double mp = 0.5 * (mph + mpha);
                 const double mm = 0.5 * (mflux<DIM>(g, k, phi, mu, u.a[b], b, c, ia[b]) +
@@ -224,14 +224,14 @@ __global__ void __launch_bounds__(kBlock) k_p_setup(Geo g, StepConst k, const do
                                                     double *__restrict__ s, W3 cs, double *__restrict__ rhs) {
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
         const double rc = k.alpha * pullback(phin[c]) + k.beta;
         double div = 0.0;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            const long long lo = nb_lo(g, c, ia[b], b);
-            const long long hi = nb_hi(g, c, ia[b], b);
+            const int lo = nb_lo(g, c, ia[b], b);
+            const int hi = nb_hi(g, c, ia[b], b);
             if (lo >= 0) {
                 const double rl = k.alpha * pullback(phin[lo]) + k.beta;
                 cs.a[b][c] = 1.0 / (0.5 * (rc + rl)) * k.ih2;
@@ -252,11 +252,11 @@ __global__ void __launch_bounds__(kBlock) k_p_coef_rho(Geo g, double ih2, const 
                                                        double *__restrict__ s, W3 cs) {
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {
-            const long long lo = nb_lo(g, c, ia[b], b);
+            const int lo = nb_lo(g, c, ia[b], b);
             cs.a[b][c] = lo >= 0 ? 1.0 / (0.5 * (rho[c] + rho[lo])) * ih2 : 0.0;
         }
         s[c] = 0.0;
@@ -271,13 +271,13 @@ __global__ void __launch_bounds__(kBlock) k_project(Geo g, StepConst k, const do
                                                     const double *__restrict__ p, double *__restrict__ phi, W3 u) {
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
         const double pn = phin[c];
         const double rc = k.alpha * pullback(pn) + k.beta;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const long long lo = nb_lo(g, c, ia[a], a);
+            const int lo = nb_lo(g, c, ia[a], a);
             double v = 0.0;
             if (lo >= 0) {
                 const double rf = 0.5 * (rc + (k.alpha * pullback(phin[lo]) + k.beta));
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, StepConst k, const doubl
     double acc[kNDiag] = {0, 0, 0, 0, 0, 0, 0, 0};
     CELL_LOOP(g.N) {
         int i, j, kk;
-        cell_coords(g, c, i, j, kk);
+        if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
         const int ia[3] = {i, j, kk};
         const double pc = phi[c];
         const double rc = k.alpha * pullback(pc) + k.beta;
@@ -321,8 +321,8 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, StepConst k, const doubl
         double div = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const long long lo = nb_lo(g, c, ia[a], a);
-            const long long hi = nb_hi(g, c, ia[a], a);
+            const int lo = nb_lo(g, c, ia[a], a);
+            const int hi = nb_hi(g, c, ia[a], a);
             const double uc = u.a[a][c];
             if (lo >= 0) {
                 const double rf = 0.5 * (rc + (k.alpha * pullback(phi[lo]) + k.beta));

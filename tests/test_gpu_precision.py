@@ -1,0 +1,118 @@
+"""Precision form (FP32 multigrid sweeps and smoothers inside an FP64
+iterative refinement; FP64 dot products, coarse solves and residuals) against
+the FP64 oracle and the FP64 GPU path.  Target: within 1e-5 of the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import MACGrid, Params, step as ostep, diagnostics
+from oracle import chns as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def relerr(a, b):
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def run(prob, steps, precision):
+    import paper_2009_06628_amd as P
+    g = P.grid_for_problem(prob, precision=precision)
+    st = g.new_state(W.initial_state(prob))
+    stats = g.step(st, steps)
+    torch.cuda.synchronize()
+    return g, st, stats
+
+
+def errs(sg, so, dim):
+    e = {"phi": relerr(to_np(sg["phi"]), so["phi"])}
+    for a in range(dim):
+        e["u%d" % a] = relerr(to_np(sg["u"][a]), so["u"][a])
+    pg = to_np(sg["p"])
+    e["p"] = relerr(pg - pg.mean(), so["p"] - so["p"].mean())
+    print("errors", {k: "%.2e" % v for k, v in e.items()}, flush=True)
+    return e
+
+
+def test_precision_form_static_drop_vs_oracle():
+    import paper_2009_06628_amd as P
+    prob = W.static_drop(64, steps=100)
+    _, sg, stats = run(prob, 100, P.CHNS_FP32_REFINE)
+    og = MACGrid(prob.n, prob.h, prob.periodic)
+    prm = Params.from_props(prob.props)
+    so = W.initial_state(prob)
+    for _ in range(100):
+        so = ostep(og, so, prm)
+    e = errs(sg, so, 2)
+    assert max(e.values()) <= 1e-5
+    d0 = diagnostics(og, W.initial_state(prob), prm)
+    assert abs(stats["mass_minus"] - d0["mass_minus"]) / d0["mass_minus"] <= 1e-12
+
+
+def test_precision_form_bubble_vs_oracle():
+    import paper_2009_06628_amd as P
+    prob = W.rising_bubble(64, steps=50)
+    _, sg, stats = run(prob, 50, P.CHNS_FP32_REFINE)
+    og = MACGrid(prob.n, prob.h, prob.periodic)
+    prm = Params.from_props(prob.props)
+    so = W.initial_state(prob)
+    for _ in range(50):
+        so = ostep(og, so, prm)
+    print("stats", stats, flush=True)
+    e = errs(sg, so, 2)
+    assert max(e.values()) <= 1e-5
+
+
+def test_precision_form_drops3d_vs_oracle():
+    import paper_2009_06628_amd as P
+    prob = W.drops3d(32, steps=5)
+    _, sg, stats = run(prob, 5, P.CHNS_FP32_REFINE)
+    og = MACGrid(prob.n, prob.h, prob.periodic)
+    prm = Params.from_props(prob.props)
+    so = W.initial_state(prob)
+    for _ in range(5):
+        so = ostep(og, so, prm)
+    e = errs(sg, so, 3)
+    assert max(e.values()) <= 1e-5
+
+
+def test_precision_form_drops3d_128_vs_fp64():
+    """Full 128^3 drop configuration, precision form at its own (looser)
+    tolerances vs the FP64 GPU path at the parity tolerances after 10 steps
+    (the oracle is too slow at this size): within 1e-5, mass to 1e-12."""
+    import paper_2009_06628_amd as P
+    prob = W.drops3d(128, steps=10)
+    _, s64, st64 = run(prob, 10, P.CHNS_FP64)
+    prob32 = W.drops3d(128, steps=10, **W.PRECISION_FORM_TOLERANCES)
+    _, s32, st32 = run(prob32, 10, P.CHNS_FP32_REFINE)
+    so = {"phi": to_np(s64["phi"]), "u": [to_np(x) for x in s64["u"]], "p": to_np(s64["p"])}
+    e = errs(s32, so, 3)
+    assert max(e.values()) <= 1e-5
+    assert abs(st32["mass_minus"] - st64["mass_minus"]) <= 1e-12 * st64["mass_minus"]
+
+
+def test_precision_form_solve_pressure():
+    import paper_2009_06628_amd as P
+    n, per = (64, 128), (True, False)
+    og = MACGrid(n, 1.0 / 64, per)
+    X = og.coords()
+    r = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 1.0) ** 2)
+    phi = np.tanh((r - 0.25) / (math.sqrt(2) * 2 * og.h))
+    rho = 0.5 * (1 - 1e-3) * phi + 0.5 * (1 + 1e-3)
+    rhs = np.random.default_rng(3).normal(size=og.shape)
+    rhs -= rhs.mean()
+    ref = O.pressure_solve(og, [og.avg(rho, a) for a in range(2)], rhs)
+    g = P.create_grid(n, 1.0 / 64, ["periodic", "wall"], precision=P.CHNS_FP32_REFINE)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    p = dev(np.zeros(og.shape))
+    out = g.solve_pressure(dev(rho), dev(rhs), p, rtol=1e-12, max_iter=400)
+    print("refined pressure solve", out, flush=True)
+    assert out["rc"] == 0
+    assert relerr(to_np(p), ref) <= 1e-9
