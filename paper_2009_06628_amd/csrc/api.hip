@@ -28,17 +28,13 @@ static const char *kNames[K_NCLASS] = {"ch_rhs",   "mu",          "phi_update", 
 
 const char *kclass_name(int c) { return (c >= 0 && c < K_NCLASS) ? kNames[c] : "?"; }
 
-void prof_begin(int cls, double bytes, hipStream_t st) {
+void prof_slot(int cls, double bytes, hipEvent_t *e0, hipEvent_t *e1) {
     Prof *P = g_prof;
     if (P->n == P->cap) prof_flush();
-    (void)hipEventRecord(P->ev[2 * P->n], st);
+    *e0 = P->ev[2 * P->n];
+    *e1 = P->ev[2 * P->n + 1];
     P->cls[P->n] = cls;
     P->bytes[P->n] = bytes;
-}
-
-void prof_end(hipStream_t st) {
-    Prof *P = g_prof;
-    (void)hipEventRecord(P->ev[2 * P->n + 1], st);
     P->n++;
 }
 

@@ -3,6 +3,7 @@
 // block reductions and the handle layout.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
@@ -68,6 +69,14 @@ __device__ inline int nb_hi(const Geo &g, int c, int ia, int a) {
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 1024;    // blocks of kernels that write partials
+
+inline int grid_red(long long n) {
+    long long b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (int)(b > kRedBlocks ? kRedBlocks : b);
+}
+
 inline int grid_for(long long n) {
     long long b = (n + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
@@ -211,19 +220,25 @@ struct Prof {
 };
 
 extern thread_local Prof *g_prof;
-void prof_begin(int cls, double bytes, hipStream_t st);
-void prof_end(hipStream_t st);
+void prof_slot(int cls, double bytes, hipEvent_t *e0, hipEvent_t *e1);
 int prof_flush();                // synchronise and accumulate; 0 on success
 const char *kclass_name(int cls);
 
 }  // namespace chns
 
 // Launch with optional timing: cls = KClass, bytes = algorithmic bytes.
+// In timing mode the start / stop events are recorded by the dispatch itself
+// (hipExtLaunchKernelGGL), so their difference is the kernel's execution time
+// without the gaps between launches.
 #define TLAUNCH(cls, bytes, kern, grid, block, st, ...)                                   \
     do {                                                                                  \
-        if (chns::g_prof) chns::prof_begin((cls), (double)(bytes), (st));                 \
-        hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                        \
-        if (chns::g_prof) chns::prof_end(st);                                             \
+        if (chns::g_prof) {                                                               \
+            hipEvent_t e0_, e1_;                                                          \
+            chns::prof_slot((cls), (double)(bytes), &e0_, &e1_);                          \
+            hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0_, e1_, 0, __VA_ARGS__);    \
+        } else {                                                                          \
+            hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                    \
+        }                                                                                 \
     } while (0)
 
 // ---------------------------------------------------------------------------

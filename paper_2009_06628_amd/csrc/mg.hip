@@ -269,6 +269,17 @@ __device__ inline void red_from_tmp_cell(const Level<T> &L, const TB *__restrict
     }
 }
 
+// in-place Gauss-Seidel update of one colour (neighbours have the other colour)
+template <typename T, typename TB, int DIM>
+__device__ inline void gs_color_cell(const Level<T> &L, const TB *__restrict__ b, T *__restrict__ x, int color, int c) {
+    using R = T;
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    if (((ia[0] + ia[1] + ia[2]) & 1) != color) return;
+    auto xv = [&](int e) { return (R)x[e]; };
+    x[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, xv)) * (R)L.invd[c]);
+}
+
 template <typename T, int DIM>
 __device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, int c) {
     int I[3];
@@ -337,6 +348,26 @@ __global__ void __launch_bounds__(kBlock) k_red_from_tmp(Level<T> L, const TB *_
                                                          const int *__restrict__ done) {
     if (*done) return;
     GRID_LOOP(L.g.N) red_from_tmp_cell<T, TB, DIM>(L, b, tmp, x, c);
+}
+
+// 3D fine levels: separate prolongation and colour sweeps (the fused pass
+// would interpolate each red neighbour of a black cell again: 48 coarse loads)
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gf, Geo gc, const T *__restrict__ xc, T *__restrict__ x,
+                                                        const int *__restrict__ done) {
+    if (*done) return;
+    GRID_LOOP(gf.N) {
+        int ia[3];
+        coords_of<DIM>(gf, c, ia);
+        x[c] = (T)((T)x[c] + prolong_at<T, DIM>(gf, gc, xc, ia));
+    }
+}
+
+template <typename T, typename TB, int DIM>
+__global__ void __launch_bounds__(kBlock) k_gs_color(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,
+                                                     int color, const int *__restrict__ done) {
+    if (*done) return;
+    GRID_LOOP(L.g.N) gs_color_cell<T, TB, DIM>(L, b, x, color, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -819,6 +850,8 @@ __global__ void __launch_bounds__(kBlock) k_slot_apply(Level<T> L, const T *__re
 // ---------------------------------------------------------------------------
 #define LAUNCH(cls, bytes, kern, n, st, ...) TLAUNCH(cls, bytes, kern, dim3(grid_for(n)), dim3(kBlock), st, __VA_ARGS__)
 #define LAUNCH1(cls, bytes, kern, threads, st, ...) TLAUNCH(cls, bytes, kern, dim3(1), dim3(threads), st, __VA_ARGS__)
+// kernels that produce per-block partials use at most kRedBlocks blocks
+#define LAUNCHR(cls, bytes, kern, n, st, ...) TLAUNCH(cls, bytes, kern, dim3(grid_red(n)), dim3(kBlock), st, __VA_ARGS__)
 
 // First level handled by the single-workgroup kernel.
 template <typename T>
@@ -872,6 +905,13 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
     Level<T> &lv = S.lev[l];
     const int N = (int)lv.g.N, Nc = (int)S.lev[l + 1].g.N;
     const double WB = sizeof(TB) - W;
+    if (DIM == 3) {
+        LAUNCH(K_PROLONG, W * (2 * N + Nc), (k_prolong_add<T, DIM>), N, st, lv.g, S.lev[l + 1].g,
+               (const T *)S.lev[l + 1].x, x, done);
+        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 1, done);
+        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 0, done);
+        return;
+    }
     LAUNCH(K_PROLONG, W * ((4 + DIM) * N + Nc) + WB * N, (k_prolong_black<T, TB, DIM>), N, st, lv, S.lev[l + 1].g,
            (const T *)S.lev[l + 1].x, b, (const T *)x, lv.r, done);
     LAUNCH(K_SMOOTH, W * (4 + DIM) * N + WB * N, (k_red_from_tmp<T, TB, DIM>), N, st, lv, b, (const T *)lv.r, x,
@@ -934,18 +974,18 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
     const Level<T> &L0 = SA.lev[0];
     const Geo g = L0.g;
     const int N = (int)g.N;
-    const int nb = grid_for(N);
+    const int nb = grid_red(N);
     const int singular = SP.singular;
     Scal *sc = red.scal;
     const int *done = &sc->done;
     if (zero_guess) {
-        LAUNCH(K_PCG_INIT, W * 3 * N, (k_pcg_init_zero<T>), N, st, N, b, x, v.r, red.part0, red.part1);
+        LAUNCHR(K_PCG_INIT, W * 3 * N, (k_pcg_init_zero<T>), N, st, N, b, x, v.r, red.part0, red.part1);
     } else if (kind == OP_SLOT) {
-        LAUNCH(K_PCG_INIT, W * (4 + DIM) * N, (k_pcg_init_slot<T, DIM>), N, st, L0, b, (const T *)x, v.r, red.part0,
+        LAUNCHR(K_PCG_INIT, W * (4 + DIM) * N, (k_pcg_init_slot<T, DIM>), N, st, L0, b, (const T *)x, v.r, red.part0,
                red.part1);
     } else {
         LAUNCH(K_PCG_INIT, W * 2 * N, (k_ch_lap_plain<T, DIM>), N, st, g, ch.ih2, (const T *)x, v.t);
-        LAUNCH(K_PCG_INIT, W * 4 * N, (k_pcg_init_ch<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, b, (const T *)x,
+        LAUNCHR(K_PCG_INIT, W * 4 * N, (k_pcg_init_ch<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, b, (const T *)x,
                (const T *)v.t, v.r, red.part0, red.part1);
     }
     LAUNCH1(K_PCG_INIT, 16.0 * nb, (k_pcg_fin_init), kBlock, st, sc, (const double *)red.part0,
@@ -968,7 +1008,7 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
         }
     }
     precond_d<T, TP, DIM>(SP, kind, v.r, v.z, v.w, done, st);
-    LAUNCH(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z, (const Scal *)sc,
+    LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z, (const Scal *)sc,
            red.part0, red.part1, red.part2, singular);
     LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
             (const double *)red.part1, (const double *)red.part2, nb, N, 1, singular);
@@ -981,19 +1021,19 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
             T *pnew = (k & 1) ? v.p1 : v.p0;
             T *pold = (k & 1) ? v.p0 : v.p1;
             if (kind == OP_SLOT) {
-                LAUNCH(K_PCG_APPLY, W * (4 + DIM) * N + WP * N, (k_pcg_apply_slot<T, TP, DIM>), N, st, L0,
+                LAUNCHR(K_PCG_APPLY, W * (4 + DIM) * N + WP * N, (k_pcg_apply_slot<T, TP, DIM>), N, st, L0,
                        (const TP *)v.z, (const T *)pold, pnew, v.q, (const Scal *)sc, red.part0);
             } else {
                 LAUNCH(K_PCG_APPLY, W * 3 * N + WP * N, (k_pcg_ch_lap<T, TP, DIM>), N, st, g, ch.ih2, (const TP *)v.z,
                        (const T *)pold, pnew, v.t, (const Scal *)sc);
-                LAUNCH(K_PCG_APPLY, W * 3 * N, (k_pcg_ch_apply<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, (const T *)pnew,
+                LAUNCHR(K_PCG_APPLY, W * 3 * N, (k_pcg_ch_apply<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, (const T *)pnew,
                        (const T *)v.t, v.q, (const Scal *)sc, red.part0);
             }
-            LAUNCH(K_PCG_UPDATE, W * 6 * N, (k_pcg_update<T>), N, st, N, (const T *)pnew, (const T *)v.q, x, v.r, sc,
+            LAUNCHR(K_PCG_UPDATE, W * 6 * N, (k_pcg_update<T>), N, st, N, (const T *)pnew, (const T *)v.q, x, v.r, sc,
                    (const double *)red.part0, nb, red.part1);
             LAUNCH1(K_PCG_UPDATE, 8.0 * nb, (k_pcg_fin_rr), kBlock, st, sc, (const double *)red.part1, nb);
             precond_d<T, TP, DIM>(SP, kind, v.r, v.z, v.w, done, st);
-            LAUNCH(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
+            LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
                    (const Scal *)sc, red.part0, red.part1, red.part2, singular);
             LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
                     (const double *)red.part1, (const double *)red.part2, nb, N, 0, singular);
@@ -1087,9 +1127,9 @@ hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kin
 template <typename T>
 void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st) {
     const int N = (int)g.N;
-    const int nb = grid_for(N);
-    LAUNCH(K_MEAN, sizeof(T) * N, (k_sum<T>), N, st, N, (const T *)x, red.part0);
-    LAUNCH(K_MEAN, 2.0 * sizeof(T) * N, (k_sub_mean<T>), N, st, N, x, (const double *)red.part0, nb);
+    const int nb = grid_red(N);
+    LAUNCHR(K_MEAN, sizeof(T) * N, (k_sum<T>), N, st, N, (const T *)x, red.part0);
+    LAUNCHR(K_MEAN, 2.0 * sizeof(T) * N, (k_sub_mean<T>), N, st, N, x, (const double *)red.part0, nb);
 }
 
 template <typename T>
