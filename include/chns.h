@@ -163,6 +163,42 @@ int chns_solve_pressure(struct chns_grid *g, const void *rho, const void *rhs, v
  * Synchronises the stream.  Used to check the stencil kernel on its own.  */
 int chns_apply_pressure_operator(struct chns_grid *g, const void *rho, const void *x, void *y);
 
+/* ---- discrete adjoint -------------------------------------------------
+ * Reverse-mode derivative of one call of the step map S1..S9 (the split
+ * scheme of the paper's time discretisation, including the pull-back of phi
+ * in the density and viscosity maps, the consistent flux J and the
+ * potential-form surface tension), for losses of the final phi and u.
+ * The adjoint needs its own workspace (caller-owned device memory, 256-byte
+ * aligned, size from chns_adjoint_workspace_size), attached once per handle.
+ */
+int chns_adjoint_workspace_size(const chns_grid_desc *desc, size_t *bytes);
+int chns_attach_adjoint_workspace(struct chns_grid *g, void *workspace, size_t bytes);
+
+/* Adjoint variables: device pointers with the state's layout (phi a cell
+ * array, u[a] face arrays; u[2] unused in 2D).  Entries of u on wall faces
+ * are ignored on input and written as 0.                                   */
+typedef struct {
+    void *phi;
+    void *u[3];
+} chns_adj;
+
+/* One reverse step.  fwd: the state (phi^k, u^k, and p^{k-1}, the pressure
+ * initial guess the forward step used) at the start of forward step k; it
+ * is read only: the call recomputes S1..S8 of that step into the adjoint
+ * workspace.  lam_in: dL/d(phi^{k+1}, u^{k+1}); lam_out receives
+ * dL/d(phi^k, u^k).  lam_out may be the same arrays as lam_in (in place),
+ * but must not otherwise overlap them or fwd.  The three adjoint elliptic
+ * solves (pressure, momentum per component, CH) use the forward operators,
+ * which are symmetric, with the forward tolerances.  If grad_params (host,
+ * 2 doubles) is not NULL it ACCUMULATES this step's parameter derivatives:
+ * grad_params[0] += dL/dsigma, grad_params[1] += dL/dM, for the surface
+ * tension sigma = 1/We and the mobility M = We/Pe at fixed Re, Cn, ratios
+ * (so k_M = 1/(Pe Cn) = M sigma / Cn; u^{k+1} does not depend on We through
+ * the projection); this synchronises the stream.  Returns CHNS_ENOCONV if a
+ * forward or adjoint solve hit max_iter.                                   */
+int chns_adjoint_step(struct chns_grid *g, const chns_state *fwd, const chns_adj *lam_in, chns_adj *lam_out,
+                      double grad_params[2]);
+
 /* Per-kernel timing.  chns_set_timing(g, 1) creates a host-side pool of
  * hipEvents (no device memory), resets the counters and makes every later
  * chns_step / chns_solve_pressure bracket each kernel launch with an event

@@ -7,7 +7,9 @@ PyTorch supplies device memory and the stream.  There is no CPU fallback: if
 the library or a GPU is missing, every entry point raises.
 
 Names follow the C ABI in include/chns.h: create_grid / set_properties /
-step / solve_pressure (plus workspace_size and apply_pressure_operator).
+step / solve_pressure / adjoint_step (plus workspace_size,
+apply_pressure_operator and the timing calls).  The differentiable rollout
+(torch.autograd.Function with checkpointing) is in ``.adjoint``.
 """
 from __future__ import annotations
 
@@ -55,6 +57,10 @@ class chns_kernel_timing(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
+class chns_adj(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_void_p), ("u", ctypes.c_void_p * 3)]
+
+
 class chns_solve_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("rel_res", ctypes.c_double)]
 
@@ -70,6 +76,10 @@ EXPORTS = {
                                            ctypes.c_double, ctypes.c_int, ctypes.POINTER(chns_solve_stats)]),
     "chns_apply_pressure_operator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                     ctypes.c_void_p]),
+    "chns_adjoint_workspace_size": (ctypes.c_int, [ctypes.POINTER(chns_grid_desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "chns_attach_adjoint_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "chns_adjoint_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.POINTER(chns_adj),
+                                         ctypes.POINTER(chns_adj), ctypes.POINTER(ctypes.c_double)]),
     "chns_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "chns_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_kernel_timing), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int)]),
@@ -234,6 +244,46 @@ class Grid:
                                            ctypes.c_void_p(_ptr(p)), float(rtol), int(max_iter), ctypes.byref(out))
         _check(rc, "chns_solve_pressure", allow_noconv=True)
         return {"iters": out.iters, "rel_res": out.rel_res, "rc": rc}
+
+    # -- adjoint_step ------------------------------------------------------------
+    def attach_adjoint(self) -> None:
+        """Allocate and attach the adjoint workspace (once per handle)."""
+        if getattr(self, "adj_workspace", None) is not None:
+            return
+        torch = _torch()
+        out = ctypes.c_size_t(0)
+        _check(self._lib.chns_adjoint_workspace_size(ctypes.byref(self._desc), ctypes.byref(out)),
+               "chns_adjoint_workspace_size")
+        nbytes = out.value
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (ws.data_ptr() + 255) & ~255
+        _check(self._lib.chns_attach_adjoint_workspace(self._h, ctypes.c_void_p(aligned), ctypes.c_size_t(nbytes)),
+               "chns_attach_adjoint_workspace")
+        self.adj_workspace = ws
+
+    def _cadj(self, lam: Dict) -> chns_adj:
+        ca = chns_adj()
+        ca.phi = _ptr(lam["phi"])
+        for a in range(3):
+            ca.u[a] = _ptr(lam["u"][a]) if a < self.dim else None
+        return ca
+
+    def adjoint_step(self, fwd: Dict, lam_in: Dict, lam_out: Dict, grad=None, allow_noconv: bool = False) -> int:
+        """One reverse step (chns_adjoint_step).  fwd: state dict at the start of
+        the forward step (phi, u, p; mu unused); lam_in / lam_out: dicts with
+        phi and u (may be the same dict).  grad: optional ctypes double[2]
+        accumulating dL/dsigma, dL/dM."""
+        if getattr(self, "adj_workspace", None) is None:
+            self.attach_adjoint()
+        cs = chns_state()
+        cs.phi = _ptr(fwd["phi"])
+        for a in range(3):
+            cs.u[a] = _ptr(fwd["u"][a]) if a < self.dim else None
+        cs.p = _ptr(fwd["p"])
+        cs.mu = None
+        li, lo = self._cadj(lam_in), self._cadj(lam_out)
+        rc = self._lib.chns_adjoint_step(self._h, ctypes.byref(cs), ctypes.byref(li), ctypes.byref(lo), grad)
+        return _check(rc, "chns_adjoint_step", allow_noconv)
 
     # -- per-kernel timing ------------------------------------------------------
     def set_timing(self, enable: bool) -> None:

@@ -10,6 +10,7 @@
 #include "common.h"
 #include "solvers.h"
 #include "step.h"
+#include "adjoint.h"
 
 using namespace chns;
 
@@ -24,7 +25,7 @@ thread_local Prof *g_prof = nullptr;
 static const char *kNames[K_NCLASS] = {"ch_rhs",   "mu",          "phi_update",   "mom_setup", "p_setup",
                                        "project",  "smooth",      "residual",     "restrict",  "prolong",
                                        "coarse_solve", "mg_setup", "pcg_apply",   "pcg_update", "pcg_dot",
-                                       "pcg_init", "mean",        "diag"};
+                                       "pcg_init", "mean",        "diag",        "adjoint"};
 
 const char *kclass_name(int c) { return (c >= 0 && c < K_NCLASS) ? kNames[c] : "?"; }
 
@@ -262,6 +263,69 @@ int check_solve(const SolveOut &o, const char *what) {
     return CHNS_OK;
 }
 
+// S1..S8 of one step from (phi, u) with the pressure initial guess in pr:
+// phihat, mu, phi_new, ustar and p; solver statistics into last.
+int forward_core(chns_grid *g, const double *phi, const double *const uc[3], double *mu, double *pr,
+                 chns_step_stats &last) {
+    const int dim = g->dim;
+    const Geo &geo = g->geo;
+    const StepConst k = step_const(g);
+    const chns_props &p = g->props;
+    hipStream_t s = g->stream;
+    const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
+    const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
+    SolveOut o;
+    memset(&last, 0, sizeof last);
+    // S1, S2
+    launch_ch_rhs(dim, geo, k, phi, uc, g->rch, g->phihat, s);
+    HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)g->rch, g->phihat, p.rtol_ch, 0, &o));
+    if (int rc = check_solve(o, "Cahn-Hilliard")) return rc;
+    last.iters_ch = o.iters;
+    last.res_ch = o.rel_res;
+    last.unconverged |= o.unconverged ? 1 : 0;
+    // S3, S4
+    launch_mu(dim, geo, k, phi, g->phihat, mu, s);
+    launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);
+    // S5..S7
+    for (int a = 0; a < dim; ++a) {
+        Level<double> &L0 = g->mom.lev[0];
+        double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+        launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, g->rhs, g->ustar[a], s);
+        HIPCHK(run_solve(g, 1, OP_SLOT, ch, (const double *)g->rhs, g->ustar[a], p.rtol_mom, 1 + a, &o));
+        if (int rc = check_solve(o, "momentum")) return rc;
+        last.iters_mom[a] = o.iters;
+        last.res_mom[a] = o.rel_res;
+        last.unconverged |= o.unconverged ? (2 << a) : 0;
+    }
+    // S8
+    Level<double> &L0 = g->pres.lev[0];
+    double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+    launch_p_setup(dim, geo, k, g->phi_new, usc, L0.s, cs, g->rhs, s);
+    remove_mean(geo, g->rhs, g->red, s);
+    HIPCHK(run_solve(g, 2, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
+    if (int rc = check_solve(o, "pressure")) return rc;
+    last.iters_p = o.iters;
+    last.res_p = o.rel_res;
+    last.unconverged |= o.unconverged ? 16 : 0;
+    remove_mean(geo, pr, g->red, s);
+    return CHNS_OK;
+}
+
+// Adjoint workspace: the forward recomputation's p and mu, the cell and
+// face adjoints, and the parameter partials.
+void layout_adjoint(Bump &B, const Geo &geo, int dim, AdjBufs &A) {
+    const size_t N = (size_t)geo.N;
+    double **cells[] = {&A.p_t, &A.mu_t, &A.pbar, &A.zeta, &A.etab, &A.pbt, &A.mub,
+                        &A.chr, &A.omega, &A.lphi, &A.sbar};
+    for (double **c : cells) *c = B.take<double>(N);
+    double **faces[] = {A.usb, A.rfnb, A.rfob, A.aphib, A.gmub, A.mb, A.nu, A.csb};
+    for (double **f : faces)
+        for (int a = 0; a < 3; ++a) f[a] = a < dim ? B.take<double>(N) : nullptr;
+    for (int a = 0; a < 3; ++a) A.Fb[a] = A.usb[a];
+    A.gpart = B.take<double>((size_t)kAdjRegions * kRedBlocks);
+    A.gout = B.take<double>(4);
+}
+
 }  // namespace
 
 extern "C" {
@@ -301,7 +365,8 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     g->ws_bytes = bytes;
     Bump B{(char *)workspace, 0};
     layout(B, P, g, desc->precision);
-    for (int k = 0; k < 6; ++k) g->last_iters[k] = g->last_inner[k] = 4;
+    for (int k = 0; k < 12; ++k) g->last_iters[k] = g->last_inner[k] = 4;
+    g->adj_ready = 0;
     memset(&g->last, 0, sizeof g->last);
     hipError_t e = hipMemsetAsync(g->red.counter, 0, 64 * sizeof(unsigned int), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->red.scal, 0, sizeof(Scal), g->stream);
@@ -355,48 +420,11 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     double *u[3] = {(double *)st->u[0], (double *)st->u[1], dim == 3 ? (double *)st->u[2] : nullptr};
     const double *uc[3] = {u[0], u[1], u[2]};
     const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
-    PcgVecs<double> v = vecs(g);
-    const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
     int unconv_any = 0;
     chns_step_stats last;
     memset(&last, 0, sizeof last);
     for (int n = 0; n < nsteps; ++n) {
-        SolveOut o;
-        memset(&last, 0, sizeof last);
-        // S1, S2
-        launch_ch_rhs(dim, geo, k, phi, uc, g->rch, g->phihat, s);
-        HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)g->rch, g->phihat, p.rtol_ch, 0, &o));
-        if (int rc = check_solve(o, "Cahn-Hilliard")) return rc;
-        last.iters_ch = o.iters;
-        last.res_ch = o.rel_res;
-        last.unconverged |= o.unconverged ? 1 : 0;
-        // S3, S4
-        launch_mu(dim, geo, k, phi, g->phihat, mu, s);
-        launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);
-        // S5..S7
-        for (int a = 0; a < dim; ++a) {
-            Level<double> &L0 = g->mom.lev[0];
-            double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, g->rhs, g->ustar[a], s);
-            HIPCHK(run_solve(g, 1, OP_SLOT, ch, (const double *)g->rhs, g->ustar[a], p.rtol_mom, 1 + a, &o));
-            if (int rc = check_solve(o, "momentum")) return rc;
-            last.iters_mom[a] = o.iters;
-            last.res_mom[a] = o.rel_res;
-            last.unconverged |= o.unconverged ? (2 << a) : 0;
-        }
-        // S8
-        {
-            Level<double> &L0 = g->pres.lev[0];
-            double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-            launch_p_setup(dim, geo, k, g->phi_new, usc, L0.s, cs, g->rhs, s);
-            remove_mean(geo, g->rhs, g->red, s);
-            HIPCHK(run_solve(g, 2, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
-            if (int rc = check_solve(o, "pressure")) return rc;
-            last.iters_p = o.iters;
-            last.res_p = o.rel_res;
-            last.unconverged |= o.unconverged ? 16 : 0;
-            remove_mean(geo, pr, g->red, s);
-        }
+        if (int rc = forward_core(g, phi, uc, mu, pr, last)) return rc;
         // S9
         launch_project(dim, geo, k, g->phi_new, usc, pr, phi, u, s);
         HIPCHK(hipGetLastError());
@@ -422,6 +450,112 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     if (unconv_any) {
         char buf[256];
         snprintf(buf, sizeof buf, "unconverged solves (bit 0 CH, 1..3 momentum, 4 pressure): mask %d", unconv_any);
+        g_err = buf;
+        return CHNS_ENOCONV;
+    }
+    return CHNS_OK;
+}
+
+int chns_adjoint_workspace_size(const chns_grid_desc *desc, size_t *bytes) {
+    if (!bytes) return fail(CHNS_EINVAL, "bytes is NULL");
+    Plan P;
+    int rc = make_plan(desc, P);
+    if (rc) return rc;
+    AdjBufs A;
+    Bump B{nullptr, 0};
+    layout_adjoint(B, P.lev[0], P.dim, A);
+    *bytes = B.off + 256;
+    return CHNS_OK;
+}
+
+int chns_attach_adjoint_workspace(chns_grid *g, void *workspace, size_t bytes) {
+    if (!g) return fail(CHNS_EINVAL, "NULL handle");
+    if (!workspace) return fail(CHNS_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(CHNS_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    if (int rc = chns_adjoint_workspace_size(&g->desc, &need)) return rc;
+    if (bytes < need) return fail(CHNS_ENOMEM, "adjoint workspace smaller than chns_adjoint_workspace_size");
+    Bump B{(char *)workspace, 0};
+    layout_adjoint(B, g->geo, g->dim, g->adj);
+    g->adj_ready = 1;
+    return CHNS_OK;
+}
+
+int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_in, chns_adj *lam_out,
+                      double grad_params[2]) {
+    if (!g || !fwd || !lam_in || !lam_out) return fail(CHNS_EINVAL, "NULL argument");
+    if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
+    if (!g->adj_ready) return fail(CHNS_EINVAL, "chns_attach_adjoint_workspace must be called first");
+    if (!fwd->phi || !fwd->p || !lam_in->phi || !lam_out->phi) return fail(CHNS_EINVAL, "state pointer is NULL");
+    for (int a = 0; a < g->dim; ++a)
+        if (!fwd->u[a] || !lam_in->u[a] || !lam_out->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
+    ProfScope prof_scope(g);
+    const int dim = g->dim;
+    const Geo &geo = g->geo;
+    const StepConst k = step_const(g);
+    const chns_props &p = g->props;
+    hipStream_t s = g->stream;
+    AdjBufs &A = g->adj;
+    const double *phi = (const double *)fwd->phi;
+    const double *uc[3] = {(const double *)fwd->u[0], (const double *)fwd->u[1],
+                           dim == 3 ? (const double *)fwd->u[2] : nullptr};
+    const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
+    const double *ubar[3] = {(const double *)lam_in->u[0], (const double *)lam_in->u[1],
+                             dim == 3 ? (const double *)lam_in->u[2] : nullptr};
+    double *uout[3] = {(double *)lam_out->u[0], (double *)lam_out->u[1], dim == 3 ? (double *)lam_out->u[2] : nullptr};
+    const double *phibar_in = (const double *)lam_in->phi;
+    double *phibar_out = (double *)lam_out->phi;
+    const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
+
+    // Forward recomputation of S1..S8 from the stored state (the pressure
+    // solve starts from the stored p, as the original step did).
+    HIPCHK(hipMemcpyAsync(A.p_t, fwd->p, sizeof(double) * geo.N, hipMemcpyDeviceToDevice, s));
+    chns_step_stats last;
+    memset(&last, 0, sizeof last);
+    if (int rc = forward_core(g, phi, uc, A.mu_t, A.p_t, last)) return rc;
+    int unconv = last.unconverged;
+
+    SolveOut o;
+    // reverse of S9 and S8: adjoint pressure solve (the pressure slot still
+    // holds the operator of the recomputed step)
+    adj_p_rhs(dim, geo, k, g->phi_new, ubar, A.pbar, A.zeta, s);
+    remove_mean(geo, A.pbar, g->red, s);
+    HIPCHK(run_solve(g, 2, OP_SLOT, ch, (const double *)A.pbar, A.zeta, p.rtol_p, 10, &o));
+    if (int rc = check_solve(o, "adjoint pressure")) return rc;
+    unconv |= o.unconverged ? 16 : 0;
+    remove_mean(geo, A.zeta, g->red, s);
+    adj_proj_faces(dim, geo, k, g->phi_new, A.p_t, A.zeta, ubar, A, uout, s);
+    // reverse of S7..S5, one velocity component at a time
+    for (int a = 0; a < dim; ++a) {
+        Level<double> &L0 = g->mom.lev[0];
+        double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+        launch_mom_setup(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, L0.s, cs, g->rhs, g->ustar[a], s, 1);
+        HIPCHK(run_solve(g, 1, OP_SLOT, ch, (const double *)A.usb[a], A.nu[a], p.rtol_mom, 7 + a, &o));
+        if (int rc = check_solve(o, "adjoint momentum")) return rc;
+        unconv |= o.unconverged ? (2 << a) : 0;
+        adj_mom(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, usc, A, uout, s);
+    }
+    // reverse of the density / viscosity maps, S4 and S3
+    adj_rho_flux_mu(dim, geo, k, phi, g->phi_new, A.mu_t, uc, phibar_in, A, uout, phibar_out, s);
+    // reverse of S2 (adjoint CH solve) and S1
+    adj_ch_rhs(dim, geo, k, g->phihat, A, s);
+    HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)A.chr, A.omega, p.rtol_ch, 6, &o));
+    if (int rc = check_solve(o, "adjoint Cahn-Hilliard")) return rc;
+    unconv |= o.unconverged ? 1 : 0;
+    adj_ch_post(dim, geo, k, phi, uc, A, uout, phibar_out, s);
+    HIPCHK(hipGetLastError());
+    if (grad_params) {
+        adj_params(dim, geo, k, A, A.gout, s);
+        double gh[4];
+        HIPCHK(hipMemcpyAsync(gh, A.gout, sizeof gh, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        grad_params[0] += gh[0];
+        grad_params[1] += gh[1];
+    }
+    if (unconv) {
+        char buf[256];
+        snprintf(buf, sizeof buf,
+                 "unconverged solves in the adjoint step (bit 0 CH, 1..3 momentum, 4 pressure): mask %d", unconv);
         g_err = buf;
         return CHNS_ENOCONV;
     }

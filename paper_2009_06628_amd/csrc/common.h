@@ -204,7 +204,7 @@ struct Red {
 enum KClass {
     K_CH_RHS = 0, K_MU, K_PHI_UPDATE, K_MOM_SETUP, K_P_SETUP, K_PROJECT,
     K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE, K_MG_SETUP,
-    K_PCG_APPLY, K_PCG_UPDATE, K_PCG_DOT, K_PCG_INIT, K_MEAN, K_DIAG,
+    K_PCG_APPLY, K_PCG_UPDATE, K_PCG_DOT, K_PCG_INIT, K_MEAN, K_DIAG, K_ADJOINT,
     K_NCLASS
 };
 
@@ -242,6 +242,22 @@ const char *kclass_name(int cls);
     } while (0)
 
 // ---------------------------------------------------------------------------
+// device buffers of the discrete adjoint (carved from the adjoint workspace)
+// ---------------------------------------------------------------------------
+namespace chns {
+constexpr int kAdjRegions = 6;   // partial sums: 0..2 dL/dk, 3..5 dL/ds_t (one per axis)
+
+struct AdjBufs {
+    double *p_t, *mu_t;                                   // forward recomputation
+    double *pbar, *zeta, *etab, *pbt, *mub, *chr, *omega, *lphi, *sbar;   // cells
+    double *usb[3], *rfnb[3], *rfob[3], *aphib[3], *gmub[3], *mb[3], *nu[3], *csb[3];   // faces
+    double *Fb[3];     // aliases usb (dead after the momentum adjoint solves)
+    double *gpart;     // kAdjRegions x kRedBlocks partials
+    double *gout;      // 4 doubles: this step's parameter derivatives
+};
+}  // namespace chns
+
+// ---------------------------------------------------------------------------
 // the handle
 // ---------------------------------------------------------------------------
 struct chns_grid {
@@ -260,10 +276,12 @@ struct chns_grid {
     int prec;
     chns::Slot<float> ch32, mom32, pres32;
     float *f_z, *f_t;   // FP32 preconditioned vector and V-cycle scratch
-    int last_inner[6];
+    int last_inner[12];
     chns::Red red;
     double *diag;                            // diagnostics scratch
-    int last_iters[6];                       // iteration-count predictions
+    int last_iters[12];                      // iteration-count predictions
+    int adj_ready;                           // adjoint workspace attached
+    chns::AdjBufs adj;
     chns_step_stats last;
     chns::Prof prof;
     void *ws;

@@ -25,7 +25,7 @@ void launch_phi_update(int dim, const Geo &g, const StepConst &k, const double *
 // right-hand side, and initial guess ustar_a = u_a.
 void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const double *phi, const double *phi_new,
                       const double *mu, const double *const u[3], double *s, double *const cs[3], double *rhs,
-                      double *ustar, hipStream_t st);
+                      double *ustar, hipStream_t st, int coef_only = 0);
 // S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new) and
 // rhs = -(We/dt) D ustar.
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],

@@ -9,22 +9,9 @@
 // flux J = (rho_- - rho_+)/(2 rho_+ Cn) grad mu, skew-symmetric advection
 // (appendix remark), surface tension in the potential form phi grad mu /
 // (We Cn) (lemma on the weak equivalence of the forcing), gravity along -y.
-#include "step.h"
+#include "stepdev.h"
 
 namespace chns {
-
-struct U3 {
-    const double *a[3];
-};
-struct W3 {
-    double *a[3];
-};
-
-__device__ inline double dpsi(double p) { return p * p * p - p; }
-__device__ inline double pullback(double p) { return fabs(p) <= 1.0 ? p : copysign(1.0, p); }
-
-#define CELL_LOOP(N) \
-    for (int c = (int)(blockIdx.x * blockDim.x + threadIdx.x); c < (int)(N); c += (int)(gridDim.x * blockDim.x))
 
 // ---------------------------------------------------------------------------
 // S1
@@ -118,26 +105,11 @@ __global__ void __launch_bounds__(kBlock) k_phi_update(Geo g, StepConst k, const
 // S5-S7 set-up for component a
 // ---------------------------------------------------------------------------
 
-// Mass flux m_b = A_b(alpha phi + beta) u_b + J_b / Pe on the face f of axis
-// b (index ib of f along b), zero on wall faces.
-template <int DIM>
-__device__ inline double mflux(const Geo &g, const StepConst &k, const double *__restrict__ phi,
-                               const double *__restrict__ mu, const double *__restrict__ ub, int b, int f, int ib) {
-    if (f < 0) return 0.0;                       // unstored upper wall face
-    if (!g.per[b] && ib == 0) return 0.0;        // stored wall face
-    const int lo = nb_lo(g, f, ib, b);
-    const double rl = k.alpha * phi[f] + k.beta, rlo = k.alpha * phi[lo] + k.beta;
-    return (0.5 * (rl + rlo)) * ub[f] - (k.alpha / (k.Cn * k.Pe)) * ((mu[f] - mu[lo]) * k.ih);
-}
-
-__device__ inline int wrap_next(int ib, int n) { return ib + 1 < n ? ib + 1 : 0; }
-__device__ inline int wrap_prev(int ib, int n) { return ib > 0 ? ib - 1 : n - 1; }
-
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a, const double *__restrict__ phi,
                                                       const double *__restrict__ phin, const double *__restrict__ mu,
                                                       U3 u, double *__restrict__ s, W3 cs, double *__restrict__ rhs,
-                                                      double *__restrict__ ustar) {
+                                                      double *__restrict__ ustar, int coef_only) {
     const double rvis = k.inv_Re * k.ih2;
     CELL_LOOP(g.N) {
         int i, j, kk;
@@ -149,8 +121,10 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
             s[c] = 1.0;
 #pragma unroll
             for (int b = 0; b < DIM; ++b) cs.a[b][c] = 0.0;
-            rhs[c] = 0.0;
-            ustar[c] = 0.0;
+            if (!coef_only) {
+                rhs[c] = 0.0;
+                ustar[c] = 0.0;
+            }
             continue;
         }
         const int cam = nb_lo(g, c, ia[a], a);   // cell c - e_a
@@ -211,8 +185,10 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
         double f = (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
         if (a == 1 && k.inv_Fr != 0.0) f -= rf_new * k.inv_Fr;     // g_hat = (0, -1, 0)
         s[c] = sd;
-        rhs[c] = f;
-        ustar[c] = ua[c];
+        if (!coef_only) {
+            rhs[c] = f;
+            ustar[c] = ua[c];
+        }
     }
 }
 
@@ -368,8 +344,6 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, StepConst k, const doubl
             LAUNCH(cls, bytes_, (kern<3>), n, st, __VA_ARGS__);                 \
     } while (0)
 
-static U3 mk_u3(const double *const u[3]) { return U3{{u[0], u[1], u[2]}}; }
-static W3 mk_w3(double *const u[3]) { return W3{{u[0], u[1], u[2]}}; }
 
 void launch_ch_rhs(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3], double *r,
                    double *phihat, hipStream_t st) {
@@ -385,8 +359,9 @@ void launch_phi_update(int dim, const Geo &g, const StepConst &k, const double *
 }
 void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const double *phi, const double *phi_new,
                       const double *mu, const double *const u[3], double *s, double *const cs[3], double *rhs,
-                      double *ustar, hipStream_t st) {
-    DISPATCH(K_MOM_SETUP, 6 + 2 * dim, dim, k_mom_setup, g.N, st, g, k, a, phi, phi_new, mu, mk_u3(u), s, mk_w3(cs), rhs, ustar);
+                      double *ustar, hipStream_t st, int coef_only) {
+    DISPATCH(K_MOM_SETUP, 6 + 2 * dim, dim, k_mom_setup, g.N, st, g, k, a, phi, phi_new, mu, mk_u3(u), s, mk_w3(cs), rhs,
+             ustar, coef_only);
 }
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
                     double *s, double *const cs[3], double *rhs, hipStream_t st) {

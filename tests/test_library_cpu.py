@@ -70,3 +70,20 @@ def test_binding_fails_loudly_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         P.create_grid((64, 64), 1 / 64, ("periodic", "periodic"))
+
+
+@pytest.mark.parametrize("n,bc", [((128, 128), ("periodic", "periodic")), ((16, 16, 16), ("wall", "wall", "periodic"))])
+def test_adjoint_workspace_size(n, bc):
+    lib = P.load_library()
+    d = P.make_desc(n, 1.0 / n[0], bc)
+    out = ctypes.c_size_t(0)
+    assert lib.chns_adjoint_workspace_size(ctypes.byref(d), ctypes.byref(out)) == P.CHNS_OK
+    cells = 1
+    for x in n:
+        cells *= x
+    dim = len(n)
+    # 11 cell arrays and 8 face arrays per axis, plus partials
+    assert out.value >= 8 * cells * (11 + 8 * dim)
+    d.dim = 5
+    assert lib.chns_adjoint_workspace_size(ctypes.byref(d), ctypes.byref(out)) == P.CHNS_EINVAL
+    assert lib.chns_adjoint_step(None, None, None, None, None) == P.CHNS_EINVAL
