@@ -199,6 +199,74 @@ typedef struct {
 int chns_adjoint_step(struct chns_grid *g, const chns_state *fwd, const chns_adj *lam_in, chns_adj *lam_out,
                       double grad_params[2]);
 
+/* ---- batched ensemble -------------------------------------------------
+ * Many independent problems of uneven size (same dim and precision) advanced
+ * together: one persistent kernel per time step in which each workgroup
+ * takes whole problems from a longest-first queue and runs S1..S9 for them,
+ * with the solver loops on the device.  nsteps launches can be captured once
+ * into a hipGraph and replayed.  The state of all problems is packed back to
+ * back: problem i occupies cells [offsets[i], offsets[i+1]) of each packed
+ * array (its own layout inside, as for a single grid).                    */
+struct chns_batch;
+
+/* Per-problem statistics of one chns_batch_step call.                    */
+typedef struct {
+    int iters_ch, iters_mom[3], iters_p;  /* last step                              */
+    int flags;        /* OR over the call: bit 0 CH, bits 1..3 momentum, bit 4
+                         pressure unconverged; bit 5 non-finite residual        */
+    int steps;        /* steps taken in the call                                */
+    int pad;
+    long long total_iters;               /* PCG iterations of all solves       */
+    double res_ch, res_mom[3], res_p;    /* last step's relative residuals     */
+} chns_batch_stats;
+
+#define CHNS_MAX_TUNING 16
+/* Autotuner result: the chosen workgroup size (block) and workgroup count
+ * (grid) with its time per step, and every candidate that was timed.      */
+typedef struct {
+    int block, grid;
+    double ms_per_step;
+    int ncand;
+    int cand_block[CHNS_MAX_TUNING], cand_grid[CHNS_MAX_TUNING];
+    double cand_ms[CHNS_MAX_TUNING];
+} chns_batch_tuning;
+
+/* Workspace bytes for count problems (descs[i] as for a single grid).     */
+int chns_batch_workspace_size(int count, const chns_grid_desc *descs, size_t *bytes);
+
+/* Create a batch: descs[count], props[count] (copied), caller-owned device
+ * workspace (256-byte aligned).  hip_stream: the caller's stream; the batch
+ * runs on an internal non-blocking stream ordered after it and before any
+ * later work on it.  Builds the constant CH hierarchies (synchronises).
+ * No device memory is allocated here or later.                            */
+int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *props, void *workspace,
+                      size_t bytes, void *hip_stream, struct chns_batch **out);
+
+/* Packed-layout offsets (count + 1 entries, in cells; host array).       */
+int chns_batch_offsets(struct chns_batch *b, long long *offsets);
+
+/* Advance every problem nsteps steps in place.  packed: device pointers to
+ * the packed arrays.  use_graph != 0 captures the nsteps launches into a
+ * hipGraph on the first call and replays it while nsteps, the pointers and
+ * the launch shape stay the same.  stats (host, count entries) or NULL; if
+ * given the call synchronises and returns CHNS_ENOCONV / CHNS_ENONFINITE
+ * when any problem's solve reported it.                                    */
+int chns_batch_step(struct chns_batch *b, const chns_state *packed, int nsteps, int use_graph,
+                    chns_batch_stats *stats);
+
+/* Set the launch shape: block = threads per workgroup (64..512, multiple of
+ * 64), grid = number of persistent workgroups (>= 1).                      */
+int chns_batch_set_launch(struct chns_batch *b, int block, int grid);
+
+/* Time steps_per_trial steps for each candidate launch shape, keep the
+ * fastest, and restore the packed state (bitwise) afterwards.  Synchronises.
+ * result (host) may be NULL.                                              */
+int chns_batch_autotune(struct chns_batch *b, const chns_state *packed, int steps_per_trial,
+                        chns_batch_tuning *result);
+
+/* Release the batch (host metadata, stream, events, graph).               */
+int chns_destroy_batch(struct chns_batch *b);
+
 /* Per-kernel timing.  chns_set_timing(g, 1) creates a host-side pool of
  * hipEvents (no device memory), resets the counters and makes every later
  * chns_step / chns_solve_pressure bracket each kernel launch with an event

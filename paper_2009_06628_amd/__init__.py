@@ -61,6 +61,22 @@ class chns_adj(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_void_p), ("u", ctypes.c_void_p * 3)]
 
 
+class chns_batch_stats(ctypes.Structure):
+    _fields_ = [("iters_ch", ctypes.c_int), ("iters_mom", ctypes.c_int * 3), ("iters_p", ctypes.c_int),
+                ("flags", ctypes.c_int), ("steps", ctypes.c_int), ("pad", ctypes.c_int),
+                ("total_iters", ctypes.c_longlong),
+                ("res_ch", ctypes.c_double), ("res_mom", ctypes.c_double * 3), ("res_p", ctypes.c_double)]
+
+
+CHNS_MAX_TUNING = 16
+
+
+class chns_batch_tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("grid", ctypes.c_int), ("ms_per_step", ctypes.c_double),
+                ("ncand", ctypes.c_int), ("cand_block", ctypes.c_int * CHNS_MAX_TUNING),
+                ("cand_grid", ctypes.c_int * CHNS_MAX_TUNING), ("cand_ms", ctypes.c_double * CHNS_MAX_TUNING)]
+
+
 class chns_solve_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("rel_res", ctypes.c_double)]
 
@@ -80,6 +96,18 @@ EXPORTS = {
     "chns_attach_adjoint_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "chns_adjoint_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.POINTER(chns_adj),
                                          ctypes.POINTER(chns_adj), ctypes.POINTER(ctypes.c_double)]),
+    "chns_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(chns_grid_desc),
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "chns_create_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(chns_grid_desc), ctypes.POINTER(chns_props),
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "chns_batch_offsets": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_longlong)]),
+    "chns_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(chns_batch_stats)]),
+    "chns_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "chns_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.c_int,
+                                           ctypes.POINTER(chns_batch_tuning)]),
+    "chns_destroy_batch": (ctypes.c_int, [ctypes.c_void_p]),
     "chns_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "chns_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_kernel_timing), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int)]),
@@ -299,6 +327,121 @@ class Grid:
     def apply_pressure_operator(self, rho, x, y) -> None:
         _check(self._lib.chns_apply_pressure_operator(self._h, ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(_ptr(x)),
                                                       ctypes.c_void_p(_ptr(y))), "chns_apply_pressure_operator")
+
+
+def _props_struct(props) -> chns_props:
+    p = chns_props()
+    for name, _ in chns_props._fields_:
+        if name == "reserved":
+            continue
+        setattr(p, name, getattr(props, name))
+    return p
+
+
+class Batch:
+    """Batched ensemble (chns_create_batch / chns_batch_step): problems of
+    uneven size packed back to back, advanced by one persistent kernel per
+    step.  problems: objects with n, h, bc, props (e.g. workloads.Problem)."""
+
+    def __init__(self, problems, precision: int = CHNS_FP64, device: str = "cuda", stream=None):
+        torch = _torch()
+        lib = load_library()
+        self._lib = lib
+        self.count = len(problems)
+        self.dim = len(problems[0].n)
+        self.device = torch.device(device)
+        self.shapes = [tuple(reversed(tuple(int(x) for x in p.n))) for p in problems]
+        descs = (chns_grid_desc * self.count)()
+        props = (chns_props * self.count)()
+        for i, p in enumerate(problems):
+            descs[i] = make_desc(p.n, p.h, p.bc, precision)
+            props[i] = _props_struct(p.props)
+        self._descs, self._props = descs, props
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.chns_batch_workspace_size(self.count, descs, ctypes.byref(nbytes)), "chns_batch_workspace_size")
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        _check(lib.chns_create_batch(self.count, descs, props, ctypes.c_void_p(aligned), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)),
+               "chns_create_batch")
+        self._h = handle
+        offs = (ctypes.c_longlong * (self.count + 1))()
+        _check(lib.chns_batch_offsets(handle, offs), "chns_batch_offsets")
+        self.offsets = [int(offs[i]) for i in range(self.count + 1)]
+        self.total_cells = self.offsets[-1]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.chns_destroy_batch(h)
+            self._h = None
+
+    def new_state(self, inits=None) -> Dict:
+        """Packed device state; inits: list of per-problem dicts (numpy)."""
+        torch = _torch()
+        z = lambda: torch.zeros(self.total_cells, dtype=torch.float64, device=self.device)
+        st = {"phi": z(), "u": [z() for _ in range(self.dim)], "p": z(), "mu": z()}
+        if inits is not None:
+            import numpy as np
+            host = {"phi": np.zeros(self.total_cells), "u": [np.zeros(self.total_cells) for _ in range(self.dim)],
+                    "p": np.zeros(self.total_cells)}
+            for i, ini in enumerate(inits):
+                a, b = self.offsets[i], self.offsets[i + 1]
+                host["phi"][a:b] = np.asarray(ini["phi"]).ravel()
+                for d in range(self.dim):
+                    host["u"][d][a:b] = np.asarray(ini["u"][d]).ravel()
+                if "p" in ini:
+                    host["p"][a:b] = np.asarray(ini["p"]).ravel()
+            st["phi"].copy_(torch.as_tensor(host["phi"]))
+            for d in range(self.dim):
+                st["u"][d].copy_(torch.as_tensor(host["u"][d]))
+            st["p"].copy_(torch.as_tensor(host["p"]))
+        return st
+
+    def view(self, st: Dict, i: int) -> Dict:
+        """Views of problem i's arrays in a packed state (cell / face shape)."""
+        a, b = self.offsets[i], self.offsets[i + 1]
+        sh = self.shapes[i]
+        return {"phi": st["phi"][a:b].view(sh), "u": [x[a:b].view(sh) for x in st["u"]],
+                "p": st["p"][a:b].view(sh), "mu": st["mu"][a:b].view(sh)}
+
+    def _cstate(self, st: Dict) -> chns_state:
+        cs = chns_state()
+        cs.phi = _ptr(st["phi"])
+        for a in range(3):
+            cs.u[a] = _ptr(st["u"][a]) if a < self.dim else None
+        cs.p = _ptr(st["p"])
+        cs.mu = _ptr(st["mu"])
+        return cs
+
+    def step(self, st: Dict, nsteps: int = 1, use_graph: bool = False, stats: bool = True,
+             allow_noconv: bool = False):
+        cs = self._cstate(st)
+        arr = (chns_batch_stats * self.count)() if stats else None
+        rc = self._lib.chns_batch_step(self._h, ctypes.byref(cs), int(nsteps), 1 if use_graph else 0, arr)
+        _check(rc, "chns_batch_step", allow_noconv)
+        if not stats:
+            return None
+        return [{"iters_ch": s.iters_ch, "iters_mom": list(s.iters_mom)[: self.dim], "iters_p": s.iters_p,
+                 "flags": s.flags, "steps": s.steps, "total_iters": s.total_iters, "res_ch": s.res_ch,
+                 "res_mom": list(s.res_mom)[: self.dim], "res_p": s.res_p} for s in arr]
+
+    def set_launch(self, block: int, grid: int) -> None:
+        _check(self._lib.chns_batch_set_launch(self._h, int(block), int(grid)), "chns_batch_set_launch")
+
+    def autotune(self, st: Dict, steps_per_trial: int = 1) -> Dict:
+        cs = self._cstate(st)
+        r = chns_batch_tuning()
+        _check(self._lib.chns_batch_autotune(self._h, ctypes.byref(cs), int(steps_per_trial), ctypes.byref(r)),
+               "chns_batch_autotune")
+        return {"block": r.block, "grid": r.grid, "ms_per_step": r.ms_per_step,
+                "candidates": [(r.cand_block[i], r.cand_grid[i], r.cand_ms[i]) for i in range(r.ncand)]}
+
+
+def create_batch(problems, precision=CHNS_FP64, device="cuda", stream=None) -> Batch:
+    return Batch(problems, precision, device, stream)
 
 
 def create_grid(n, h, bc, precision=CHNS_FP64, device="cuda", stream=None) -> Grid:

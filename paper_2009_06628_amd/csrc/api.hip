@@ -11,6 +11,7 @@
 #include "solvers.h"
 #include "step.h"
 #include "adjoint.h"
+#include "plan.h"
 
 using namespace chns;
 
@@ -71,19 +72,41 @@ static int fail(int code, const std::string &msg) {
     return code;
 }
 
-#define HIPCHK(expr)                                                                                     \
-    do {                                                                                                 \
-        hipError_t e_ = (expr);                                                                          \
-        if (e_ != hipSuccess) return fail(CHNS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+namespace chns {
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
 
-namespace {
+StepConst step_const_of(const chns_props &p, double h) {
+    StepConst k;
+    k.h = h;
+    k.ih = 1.0 / h;
+    k.ih2 = k.ih * k.ih;
+    k.dt = p.dt;
+    k.S = p.S;
+    k.Cn = p.Cn;
+    k.Pe = p.Pe;
+    k.kM = 1.0 / (p.Pe * p.Cn);
+    k.alpha = (1.0 - p.rho_minus) / 2.0;
+    k.beta = (1.0 + p.rho_minus) / 2.0;
+    k.gamma = (1.0 - p.eta_minus) / 2.0;
+    k.xi = (1.0 + p.eta_minus) / 2.0;
+    k.inv_Re = 1.0 / p.Re;
+    k.inv_We = 1.0 / p.We;
+    k.We = p.We;
+    k.inv_Fr = p.inv_Fr;
+    return k;
+}
 
-struct Plan {
-    int dim;
-    int nlev;
-    Geo lev[kMaxLev];
-};
+int check_props(const chns_props *p) {
+    const double pos[] = {p->rho_minus, p->eta_minus, p->Re, p->We, p->Cn, p->Pe, p->dt};
+    for (double v : pos)
+        if (!(v > 0.0) || !std::isfinite(v))
+            return fail(CHNS_EINVAL, "rho_minus, eta_minus, Re, We, Cn, Pe, dt must be positive and finite");
+    if (!(p->S >= 0.0) || !std::isfinite(p->inv_Fr)) return fail(CHNS_EINVAL, "S must be >= 0, inv_Fr finite");
+    if (!(p->rtol_ch > 0.0) || !(p->rtol_mom > 0.0) || !(p->rtol_p > 0.0))
+        return fail(CHNS_EINVAL, "tolerances must be positive");
+    if (p->max_iter < 1) return fail(CHNS_EINVAL, "max_iter must be >= 1");
+    return CHNS_OK;
+}
 
 int make_plan(const chns_grid_desc *d, Plan &P) {
     if (!d) return fail(CHNS_EINVAL, "grid description is NULL");
@@ -134,39 +157,16 @@ int make_plan(const chns_grid_desc *d, Plan &P) {
     return CHNS_OK;
 }
 
-// Bump allocator over the workspace (base == nullptr: sizing pass).
-struct Bump {
-    char *base;
-    size_t off;
-    template <typename T>
-    T *take(size_t count) {
-        off = (off + 255) & ~(size_t)255;
-        T *p = base ? (T *)(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
-};
+}  // namespace chns
 
-template <typename T>
-void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
-    S.nlev = P.nlev;
-    S.lsb = 0;
-    S.singular = singular;
-    S.ncoarse = (int)P.lev[P.nlev - 1].N;
-    for (int l = 0; l < P.nlev; ++l) {
-        Level<T> &L = S.lev[l];
-        L.g = P.lev[l];
-        const size_t n = (size_t)L.g.N;
-        L.s = B.take<T>(n);
-        for (int b = 0; b < 3; ++b) L.cs[b] = b < P.dim ? B.take<T>(n) : nullptr;
-        L.invd = B.take<T>(n);
-        L.r = B.take<T>(n);
-        L.x = l ? B.take<T>(n) : nullptr;
-        L.b = l ? B.take<T>(n) : nullptr;
-    }
-    S.Ainv = B.take<double>((size_t)S.ncoarse * S.ncoarse);
-    S.aug = nullptr;
-}
+
+#define HIPCHK(expr)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) return fail(CHNS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+namespace {
 
 void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     const size_t N = (size_t)P.lev[0].N;
@@ -206,27 +206,7 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     g->red.scal = B.take<Scal>(1);
 }
 
-StepConst step_const(const chns_grid *g) {
-    const chns_props &p = g->props;
-    StepConst k;
-    k.h = g->h;
-    k.ih = 1.0 / g->h;
-    k.ih2 = k.ih * k.ih;
-    k.dt = p.dt;
-    k.S = p.S;
-    k.Cn = p.Cn;
-    k.Pe = p.Pe;
-    k.kM = 1.0 / (p.Pe * p.Cn);
-    k.alpha = (1.0 - p.rho_minus) / 2.0;
-    k.beta = (1.0 + p.rho_minus) / 2.0;
-    k.gamma = (1.0 - p.eta_minus) / 2.0;
-    k.xi = (1.0 + p.eta_minus) / 2.0;
-    k.inv_Re = 1.0 / p.Re;
-    k.inv_We = 1.0 / p.We;
-    k.We = p.We;
-    k.inv_Fr = p.inv_Fr;
-    return k;
-}
+StepConst step_const(const chns_grid *g) { return step_const_of(g->props, g->h); }
 
 PcgVecs<double> vecs(chns_grid *g) { return PcgVecs<double>{g->vr, g->vz, g->vp0, g->vp1, g->vq, g->vt}; }
 
@@ -380,14 +360,7 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
 
 int chns_set_properties(chns_grid *g, const chns_props *p) {
     if (!g || !p) return fail(CHNS_EINVAL, "NULL argument");
-    const double pos[] = {p->rho_minus, p->eta_minus, p->Re, p->We, p->Cn, p->Pe, p->dt};
-    for (double v : pos)
-        if (!(v > 0.0) || !std::isfinite(v))
-            return fail(CHNS_EINVAL, "rho_minus, eta_minus, Re, We, Cn, Pe, dt must be positive and finite");
-    if (!(p->S >= 0.0) || !std::isfinite(p->inv_Fr)) return fail(CHNS_EINVAL, "S must be >= 0, inv_Fr finite");
-    if (!(p->rtol_ch > 0.0) || !(p->rtol_mom > 0.0) || !(p->rtol_p > 0.0))
-        return fail(CHNS_EINVAL, "tolerances must be positive");
-    if (p->max_iter < 1) return fail(CHNS_EINVAL, "max_iter must be >= 1");
+    if (int rc = check_props(p)) return rc;
     g->props = *p;
     g->props_set = 1;
     const StepConst k = step_const(g);

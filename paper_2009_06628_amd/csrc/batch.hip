@@ -1,0 +1,813 @@
+// Batched ensemble (gfx950): many independent problems of uneven size, each
+// advanced through the whole split step S1..S9 by ONE workgroup inside a
+// persistent kernel.  One launch per time step:
+//   * workgroups pull problems from a device queue in longest-first order
+//     (largest cell count first), so the makespan stays close to the mean
+//     load; there is no synchronisation between workgroups;
+//   * inside a problem every sweep is a workgroup-stride loop followed by a
+//     workgroup barrier; the three kinds of linear solves run the same
+//     preconditioned CG as the single-grid path (FP64 vectors and
+//     reductions, the V-cycle in FP64 or, in the precision form, FP32 with an
+//     FP64 true-residual refinement), with their convergence loops on the
+//     device, so a step has data-independent control flow on the host and
+//     nsteps launches are captured once into a hipGraph and replayed;
+//   * per-cell arithmetic is shared with the single-grid kernels, so a batched
+//     problem matches its own single-grid run up to the order of the sums.
+// Workgroup size and workgroup count are chosen by chns_batch_autotune.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mgdev.h"
+#include "plan.h"
+#include "solvers.h"
+#include "stepdev.h"
+
+namespace chns {
+
+// ---------------------------------------------------------------------------
+// device tables
+// ---------------------------------------------------------------------------
+template <typename TP>
+struct BatchProb {
+    Geo g;
+    StepConst k;
+    ChOp ch;
+    double rtol_ch, rtol_mom, rtol_p;
+    int max_iter;
+    long long off;                         // first cell in the packed state arrays
+    double *phi_new, *phihat, *rch, *ustar[3], *rhs;
+    double *r, *p0, *p1, *q, *t;           // CG vectors (FP64)
+    TP *z, *w;                             // preconditioned vector, V-cycle scratch
+    Level<double> op;                      // FP64 level-0 operator of the momentum / pressure solves
+    Slot<TP> chs, mom, pres;               // CH hierarchy; momentum and pressure share arrays
+};
+
+struct BatchState {
+    double *phi, *u[3], *p, *mu;
+};
+
+// Solve outcome inside a workgroup.
+struct PcgRes {
+    int iters;
+    double rel;
+    int unconv, nonfinite;
+};
+
+constexpr int kBatchMaxThreads = 512;
+
+// r.z (with the singular projection), returned to every thread
+template <typename TP>
+__device__ inline double rz_block(int N, const double *__restrict__ r, const TP *__restrict__ z, int singular,
+                                  double *red, double &zm) {
+    double arz = 0.0, az = 0.0, ar = 0.0;
+    BLOCK_LOOP(N) {
+        const double rc = r[c], zc = (double)z[c];
+        arz += rc * zc;
+        az += zc;
+        ar += rc;
+    }
+    const double trz = block_sum_all(arz, red);
+    const double tz = singular ? block_sum_all(az, red) : 0.0;
+    const double tr = singular ? block_sum_all(ar, red) : 0.0;
+    zm = singular ? tz / (double)N : 0.0;
+    return trz - zm * tr;
+}
+
+template <typename TP, int DIM>
+__device__ __attribute__((noinline)) void precond_block(int kind, const Slot<TP> &SP, const double *r, TP *z, TP *w) {
+    if (kind == OP_CH) {
+        vcycle_block_dev<TP, double, DIM>(SP, 0, r, w);
+        vcycle_block_dev<TP, TP, DIM>(SP, 0, w, z);
+    } else {
+        vcycle_block_dev<TP, double, DIM>(SP, 0, r, z);
+    }
+}
+
+// Preconditioned CG on A x = b inside one workgroup; x holds the initial
+// guess.  kind OP_SLOT: A = P.op (variable coefficients); OP_CH: the
+// constant CH operator.  With an FP32 hierarchy the solve restarts from the
+// FP64 true residual until it meets the tolerance (at most kMaxRefine
+// rounds).  Ends with a workgroup barrier.
+template <typename TP, int DIM>
+__device__ __attribute__((noinline)) PcgRes pcg_block(const BatchProb<TP> &P, int kind, const Slot<TP> &SP, int singular,
+                            const double *__restrict__ b, double *__restrict__ x, double rtol, int max_iter,
+                            double *red) {
+    const Geo &g = P.g;
+    const int N = (int)g.N;
+    const ChOp ch = P.ch;
+    double *r = P.r, *q = P.q, *t = P.t;
+    TP *z = P.z, *w = P.w;
+    const double rtol2 = rtol * rtol;
+    const int rounds = sizeof(TP) < sizeof(double) ? kMaxRefine : 1;
+    PcgRes out{0, 0.0, 0, 0};
+    for (int round = 0; round < rounds; ++round) {
+        // r = b - A x
+        double bb = 0.0, rr = 0.0;
+        if (kind == OP_CH) {
+            auto xv = [&](int e) { return x[e]; };
+            BLOCK_LOOP(N) {
+                int ia[3];
+                coords_of<DIM>(g, c, ia);
+                t[c] = lap_at<DIM>(g, c, ia, ch.ih2, xv);
+            }
+            __syncthreads();
+            auto tv = [&](int e) { return t[e]; };
+            BLOCK_LOOP(N) {
+                int ia[3];
+                coords_of<DIM>(g, c, ia);
+                const double Mx = x[c] - ch.a * t[c] + ch.b * lap_at<DIM>(g, c, ia, ch.ih2, tv);
+                const double bc = b[c], rc = bc - Mx;
+                r[c] = rc;
+                bb += bc * bc;
+                rr += rc * rc;
+            }
+        } else {
+            BLOCK_LOOP(N) {
+                int ia[3];
+                coords_of<DIM>(g, c, ia);
+                const double bc = b[c], rc = bc - apply_at<double, DIM>(P.op, x, c, ia);
+                r[c] = rc;
+                bb += bc * bc;
+                rr += rc * rc;
+            }
+        }
+        const double tb = block_sum_all(bb, red);
+        double rrt = block_sum_all(rr, red);
+        const double bref = tb > rrt ? tb : rrt;
+        if (!isfinite(tb) || !isfinite(rrt)) {
+            out.nonfinite = 1;
+            return out;
+        }
+        out.rel = bref > 0.0 ? sqrt(rrt / bref) : 0.0;
+        if (rrt <= rtol2 * bref) {
+            out.unconv = 0;
+            return out;
+        }
+        // PCG from here
+        precond_block<TP, DIM>(kind, SP, r, z, w);
+        double zm = 0.0;
+        double rz = rz_block<TP>(N, r, z, singular, red, zm);
+        double beta = 0.0;
+        double *pnew = P.p0, *pold = P.p1;
+        int it = 0;
+        out.unconv = 1;
+        for (;;) {
+            auto pv = [&](int e) { return ((double)z[e] - zm) + (beta != 0.0 ? beta * pold[e] : 0.0); };
+            double pq = 0.0;
+            if (kind == OP_CH) {
+                BLOCK_LOOP(N) {
+                    int ia[3];
+                    coords_of<DIM>(g, c, ia);
+                    pnew[c] = pv(c);
+                    t[c] = lap_at<DIM>(g, c, ia, ch.ih2, pv);
+                }
+                __syncthreads();
+                auto tv = [&](int e) { return t[e]; };
+                BLOCK_LOOP(N) {
+                    int ia[3];
+                    coords_of<DIM>(g, c, ia);
+                    const double pc = pnew[c];
+                    const double qc = pc - ch.a * t[c] + ch.b * lap_at<DIM>(g, c, ia, ch.ih2, tv);
+                    q[c] = qc;
+                    pq += pc * qc;
+                }
+            } else {
+                const Level<double> &L = P.op;
+                BLOCK_LOOP(N) {
+                    int ia[3];
+                    coords_of<DIM>(g, c, ia);
+                    const double pc = pv(c);
+                    double qc = L.s[c] * pc;
+#pragma unroll
+                    for (int bx = 0; bx < DIM; ++bx) {
+                        const int lo = nb_lo(g, c, ia[bx], bx);
+                        const int hi = nb_hi(g, c, ia[bx], bx);
+                        if (lo >= 0) qc += L.cs[bx][c] * (pc - pv(lo));
+                        if (hi >= 0) qc += L.cs[bx][hi] * (pc - pv(hi));
+                    }
+                    pnew[c] = pc;
+                    q[c] = qc;
+                    pq += pc * qc;
+                }
+            }
+            pq = block_sum_all(pq, red);
+            const double alpha = pq != 0.0 ? rz / pq : 0.0;
+            rr = 0.0;
+            BLOCK_LOOP(N) {
+                x[c] += alpha * pnew[c];
+                const double rc = r[c] - alpha * q[c];
+                r[c] = rc;
+                rr += rc * rc;
+            }
+            rrt = block_sum_all(rr, red);
+            ++it;
+            out.rel = bref > 0.0 ? sqrt(rrt / bref) : 0.0;
+            if (!isfinite(rrt)) {
+                out.nonfinite = 1;
+                out.iters += it;
+                return out;
+            }
+            if (rrt <= rtol2 * bref) {
+                out.unconv = 0;
+                break;
+            }
+            if (it >= max_iter) break;
+            precond_block<TP, DIM>(kind, SP, r, z, w);
+            const double rzn = rz_block<TP>(N, r, z, singular, red, zm);
+            if (!isfinite(rzn)) {
+                out.nonfinite = 1;
+                out.iters += it;
+                return out;
+            }
+            beta = rz == 0.0 ? 0.0 : rzn / rz;
+            rz = rzn;
+            double *tmp = pnew;
+            pnew = pold;
+            pold = tmp;
+        }
+        out.iters += it;
+        if (out.unconv) return out;
+        // FP64 rounds are final; the precision form re-checks the true residual
+    }
+    return out;
+}
+
+__device__ inline void remove_mean_block(int N, double *x, double *red) {
+    double acc = 0.0;
+    BLOCK_LOOP(N) acc += x[c];
+    const double m = block_sum_all(acc, red) / (double)N;
+    BLOCK_LOOP(N) x[c] -= m;
+    __syncthreads();
+}
+
+// Level-0 coefficients of a variable slot from the FP64 operator, then the
+// hierarchy (inverse diagonals, coarse levels, coarsest inverse).
+template <typename TP, int DIM>
+__device__ __attribute__((noinline)) void prepare_slot(const BatchProb<TP> &P, const Slot<TP> &S, SetupLds &sh) {
+    if (sizeof(TP) < sizeof(double)) {
+        const Level<TP> &L0 = S.lev[0];
+        BLOCK_LOOP(P.g.N) {
+            L0.s[c] = (TP)P.op.s[c];
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) L0.cs[b][c] = (TP)P.op.cs[b][c];
+        }
+        __syncthreads();
+    }
+    setup_block_dev<TP, DIM>(S, 0, sh);
+}
+
+// Statistics of one solve (written by thread 0 into the problem's record).
+__device__ inline void record(PcgRes o, int bit, int *iters, double *res, int &flags, long long &total) {
+    if (threadIdx.x == 0) {
+        *iters = o.iters;
+        *res = o.rel;
+    }
+    total += o.iters;
+    if (o.unconv) flags |= 1 << bit;
+    if (o.nonfinite) flags |= 1 << 5;
+}
+
+// S1..S9 of one problem by the calling workgroup.
+template <typename TP, int DIM>
+__device__ void batch_problem_step(const BatchProb<TP> &P, const BatchState &st, chns_batch_stats *S,
+                                   SetupLds &sh, double *red) {
+    const Geo &g = P.g;
+    const int N = (int)g.N;
+    const StepConst &k = P.k;
+    double *phi = st.phi + P.off, *mu = st.mu + P.off, *pr = st.p + P.off;
+    const U3 uc{{st.u[0] + P.off, st.u[1] + P.off, DIM == 3 ? st.u[2] + P.off : nullptr}};
+    const W3 uw{{st.u[0] + P.off, st.u[1] + P.off, DIM == 3 ? st.u[2] + P.off : nullptr}};
+    const U3 usc{{P.ustar[0], P.ustar[1], P.ustar[2]}};
+    const W3 opcs{{P.op.cs[0], P.op.cs[1], P.op.cs[2]}};
+    int flags = 0;
+    long long total = 0;
+    // S1, S2
+    BLOCK_LOOP(N) ch_rhs_cell<DIM>(g, k, phi, uc, P.rch, P.phihat, c);
+    __syncthreads();
+    PcgRes o = pcg_block<TP, DIM>(P, OP_CH, P.chs, 0, P.rch, P.phihat, P.rtol_ch, P.max_iter, red);
+    record(o, 0, &S->iters_ch, &S->res_ch, flags, total);
+    // S3, S4
+    BLOCK_LOOP(N) mu_cell<DIM>(g, k, phi, P.phihat, mu, c);
+    __syncthreads();
+    BLOCK_LOOP(N) phi_update_cell<DIM>(g, k, phi, uc, mu, P.phi_new, c);
+    __syncthreads();
+    // S5..S7
+    for (int a = 0; a < DIM; ++a) {
+        BLOCK_LOOP(N) mom_setup_cell<DIM>(g, k, a, phi, P.phi_new, mu, uc, P.op.s, opcs, P.rhs, P.ustar[a], 0, c);
+        __syncthreads();
+        prepare_slot<TP, DIM>(P, P.mom, sh);
+        o = pcg_block<TP, DIM>(P, OP_SLOT, P.mom, 0, P.rhs, P.ustar[a], P.rtol_mom, P.max_iter, red);
+        record(o, 1 + a, &S->iters_mom[a], &S->res_mom[a], flags, total);
+    }
+    // S8
+    BLOCK_LOOP(N) p_setup_cell<DIM>(g, k, P.phi_new, usc, P.op.s, opcs, P.rhs, c);
+    __syncthreads();
+    remove_mean_block(N, P.rhs, red);
+    prepare_slot<TP, DIM>(P, P.pres, sh);
+    o = pcg_block<TP, DIM>(P, OP_SLOT, P.pres, 1, P.rhs, pr, P.rtol_p, P.max_iter, red);
+    record(o, 4, &S->iters_p, &S->res_p, flags, total);
+    remove_mean_block(N, pr, red);
+    // S9
+    BLOCK_LOOP(N) project_cell<DIM>(g, k, P.phi_new, usc, pr, phi, uw, c);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S->flags |= flags;
+        S->total_iters += total;
+        S->steps += 1;
+    }
+}
+
+// One time step of every problem.  Workgroups take problems from the queue
+// (order[] lists them longest first) until it is empty.
+template <typename TP, int DIM>
+__global__ void __launch_bounds__(kBatchMaxThreads) k_batch_step(const BatchProb<TP> *__restrict__ probs,
+                                                                 const int *__restrict__ order, int nprob,
+                                                                 unsigned int *queue, BatchState st,
+                                                                 chns_batch_stats *stats) {
+    __shared__ SetupLds sh;
+    __shared__ double red[kBatchMaxThreads / kWave];
+    __shared__ int s_t;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_t = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        // uniform across the workgroup: keep the problem index (and so every
+        // table load below) in scalar registers
+        const int t = __builtin_amdgcn_readfirstlane(s_t);
+        if (t >= nprob) break;
+        const int i = __builtin_amdgcn_readfirstlane(order[t]);
+        batch_problem_step<TP, DIM>(probs[i], st, stats + i, sh, red);
+    }
+}
+
+// Constant CH hierarchy of every problem (one workgroup per problem).
+template <typename TP, int DIM>
+__global__ void __launch_bounds__(kBatchMaxThreads) k_batch_init(const BatchProb<TP> *__restrict__ probs, int nprob) {
+    __shared__ SetupLds sh;
+    for (int i = blockIdx.x; i < nprob; i += gridDim.x) {
+        const BatchProb<TP> &P = probs[i];
+        const Level<TP> &L0 = P.chs.lev[0];
+        const double csv = sqrt(P.ch.b) * P.ch.ih2;
+        BLOCK_LOOP(P.g.N) {
+            L0.s[c] = (TP)1.0;
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) L0.cs[b][c] = (TP)csv;
+        }
+        __syncthreads();
+        setup_block_dev<TP, DIM>(P.chs, 0, sh);
+    }
+}
+
+__global__ void k_batch_reset_queue(unsigned int *queue) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) queue[0] = 0u;
+}
+
+__global__ void k_batch_reset_stats(chns_batch_stats *stats, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        chns_batch_stats z = {};
+        stats[i] = z;
+    }
+}
+
+}  // namespace chns
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+using namespace chns;
+
+struct chns_batch {
+    int count, dim, prec;
+    hipStream_t user_stream, stream;
+    hipEvent_t ev_in, ev_out;
+    void *d_probs;
+    int *d_order;
+    unsigned int *d_queue;
+    chns_batch_stats *d_stats;
+    double *backup;
+    std::vector<long long> offsets;   // count + 1
+    std::vector<int> order;
+    long long total_cells;
+    int block, grid;                  // launch shape
+    // captured graph of the last chns_batch_step call with use_graph
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int g_steps, g_block, g_grid;
+    BatchState g_state;
+};
+
+namespace {
+
+#define BHIPCHK(expr)                                                                                         \
+    do {                                                                                                      \
+        hipError_t e_ = (expr);                                                                               \
+        if (e_ != hipSuccess) return set_error(CHNS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename TP>
+size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *props, std::vector<BatchProb<TP>> *host,
+                    chns_batch *b) {
+    // tables first
+    void *probs = B.take<BatchProb<TP>>((size_t)count);
+    int *order = B.take<int>((size_t)count);
+    unsigned int *queue = B.take<unsigned int>(64);
+    chns_batch_stats *stats = B.take<chns_batch_stats>((size_t)count);
+    long long tot = 0;
+    for (int i = 0; i < count; ++i) tot += plans[i].lev[0].N;
+    const int dim = plans[0].dim;
+    double *backup = B.take<double>((size_t)tot * (3 + dim));
+    if (b) {
+        b->d_probs = probs;
+        b->d_order = order;
+        b->d_queue = queue;
+        b->d_stats = stats;
+        b->backup = backup;
+    }
+    long long off = 0;
+    for (int i = 0; i < count; ++i) {
+        const Plan &P = plans[i];
+        const size_t N = (size_t)P.lev[0].N;
+        BatchProb<TP> Q;
+        memset(&Q, 0, sizeof Q);
+        Q.g = P.lev[0];
+        Q.off = off;
+        off += (long long)N;
+        Q.phi_new = B.take<double>(N);
+        Q.phihat = B.take<double>(N);
+        Q.rch = B.take<double>(N);
+        for (int a = 0; a < 3; ++a) Q.ustar[a] = a < dim ? B.take<double>(N) : nullptr;
+        Q.rhs = B.take<double>(N);
+        Q.r = B.take<double>(N);
+        Q.p0 = B.take<double>(N);
+        Q.p1 = B.take<double>(N);
+        Q.q = B.take<double>(N);
+        Q.t = B.take<double>(N);
+        Q.z = B.take<TP>(N);
+        Q.w = B.take<TP>(N);
+        carve_slot(B, P, Q.chs, 0);
+        carve_slot(B, P, Q.mom, 0);
+        Q.pres = Q.mom;
+        Q.pres.singular = 1;
+        const int nc = Q.mom.ncoarse;
+        double *aug = nc > kLdsInverse ? B.take<double>((size_t)nc * nc) : nullptr;
+        Q.chs.aug = Q.mom.aug = Q.pres.aug = aug;
+        Q.op.g = Q.g;
+        if (sizeof(TP) == sizeof(double)) {
+            const Level<TP> &L0 = Q.mom.lev[0];
+            Q.op.s = (double *)L0.s;
+            for (int a = 0; a < 3; ++a) Q.op.cs[a] = (double *)L0.cs[a];
+            Q.op.invd = (double *)L0.invd;
+            Q.op.r = (double *)L0.r;
+        } else {
+            Q.op.s = B.take<double>(N);
+            for (int a = 0; a < 3; ++a) Q.op.cs[a] = a < dim ? B.take<double>(N) : nullptr;
+        }
+        if (host) {   // step constants and CH operator are filled in by the caller
+            const chns_props &p = props[i];
+            Q.rtol_ch = p.rtol_ch;
+            Q.rtol_mom = p.rtol_mom;
+            Q.rtol_p = p.rtol_p;
+            Q.max_iter = p.max_iter;
+            host->push_back(Q);
+        }
+    }
+    if (b) b->total_cells = tot;
+    return B.off;
+}
+
+int check_descs(int count, const chns_grid_desc *descs, std::vector<Plan> &plans) {
+    if (count < 1) return set_error(CHNS_EINVAL, "count must be >= 1");
+    if (!descs) return set_error(CHNS_EINVAL, "descs is NULL");
+    plans.resize(count);
+    for (int i = 0; i < count; ++i) {
+        if (int rc = make_plan(&descs[i], plans[i])) return rc;
+        if (descs[i].dim != descs[0].dim || descs[i].precision != descs[0].precision)
+            return set_error(CHNS_EINVAL, "every problem of a batch must have the same dim and precision");
+    }
+    return CHNS_OK;
+}
+
+template <typename TP>
+size_t batch_bytes(int count, const std::vector<Plan> &plans) {
+    Bump B{nullptr, 0};
+    return layout_batch<TP>(B, count, plans.data(), nullptr, nullptr, nullptr) + 256;
+}
+
+template <typename TP, int DIM>
+void launch_step(chns_batch *b, const BatchState &st, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset_queue, dim3(1), dim3(64), 0, s, b->d_queue);
+    hipLaunchKernelGGL((k_batch_step<TP, DIM>), dim3(b->grid), dim3(b->block), 0, s,
+                       (const BatchProb<TP> *)b->d_probs, (const int *)b->d_order, b->count, b->d_queue, st,
+                       b->d_stats);
+}
+
+void launch_steps(chns_batch *b, const BatchState &st, int nsteps, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_stats, b->count);
+    for (int n = 0; n < nsteps; ++n) {
+        if (b->prec == CHNS_FP64) {
+            if (b->dim == 2) launch_step<double, 2>(b, st, s); else launch_step<double, 3>(b, st, s);
+        } else {
+            if (b->dim == 2) launch_step<float, 2>(b, st, s); else launch_step<float, 3>(b, st, s);
+        }
+    }
+}
+
+void drop_graph(chns_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->g_steps = -1;
+}
+
+int state_of(chns_batch *b, const chns_state *packed, BatchState &st) {
+    if (!packed || !packed->phi || !packed->p || !packed->mu) return set_error(CHNS_EINVAL, "state pointer is NULL");
+    for (int a = 0; a < b->dim; ++a)
+        if (!packed->u[a]) return set_error(CHNS_EINVAL, "velocity pointer is NULL");
+    st.phi = (double *)packed->phi;
+    st.p = (double *)packed->p;
+    st.mu = (double *)packed->mu;
+    for (int a = 0; a < 3; ++a) st.u[a] = a < b->dim ? (double *)packed->u[a] : nullptr;
+    return CHNS_OK;
+}
+
+bool same_state(const BatchState &x, const BatchState &y) {
+    return x.phi == y.phi && x.p == y.p && x.mu == y.mu && x.u[0] == y.u[0] && x.u[1] == y.u[1] && x.u[2] == y.u[2];
+}
+
+// Run nsteps on the batch's own stream (ordered after the caller's stream).
+int run_steps(chns_batch *b, const BatchState &st, int nsteps, int use_graph) {
+    BHIPCHK(hipEventRecord(b->ev_in, b->user_stream));
+    BHIPCHK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    if (use_graph && nsteps > 0) {
+        if (!(b->exec && b->g_steps == nsteps && b->g_block == b->block && b->g_grid == b->grid &&
+              same_state(b->g_state, st))) {
+            drop_graph(b);
+            BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            launch_steps(b, st, nsteps, b->stream);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &gr);
+            if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            b->graph = gr;
+            e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                drop_graph(b);
+                return set_error(CHNS_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            b->g_steps = nsteps;
+            b->g_block = b->block;
+            b->g_grid = b->grid;
+            b->g_state = st;
+        }
+        BHIPCHK(hipGraphLaunch(b->exec, b->stream));
+    } else {
+        launch_steps(b, st, nsteps, b->stream);
+    }
+    BHIPCHK(hipGetLastError());
+    BHIPCHK(hipEventRecord(b->ev_out, b->stream));
+    BHIPCHK(hipStreamWaitEvent(b->user_stream, b->ev_out, 0));
+    return CHNS_OK;
+}
+
+int copy_state(chns_batch *b, const BatchState &st, int to_backup, hipStream_t s) {
+    const size_t n = (size_t)b->total_cells * sizeof(double);
+    double *fields[6] = {st.phi, st.p, st.mu, st.u[0], st.u[1], st.u[2]};
+    const int nf = 3 + b->dim;
+    for (int f = 0; f < nf; ++f) {
+        double *bk = b->backup + (size_t)f * b->total_cells;
+        BHIPCHK(hipMemcpyAsync(to_backup ? bk : fields[f], to_backup ? fields[f] : bk, n, hipMemcpyDeviceToDevice, s));
+    }
+    return CHNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int chns_batch_workspace_size(int count, const chns_grid_desc *descs, size_t *bytes) {
+    if (!bytes) return set_error(CHNS_EINVAL, "bytes is NULL");
+    std::vector<Plan> plans;
+    if (int rc = check_descs(count, descs, plans)) return rc;
+    *bytes = descs[0].precision == CHNS_FP64 ? batch_bytes<double>(count, plans) : batch_bytes<float>(count, plans);
+    return CHNS_OK;
+}
+
+int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *props, void *workspace, size_t bytes,
+                      void *hip_stream, chns_batch **out) {
+    if (!out) return set_error(CHNS_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::vector<Plan> plans;
+    if (int rc = check_descs(count, descs, plans)) return rc;
+    if (!props) return set_error(CHNS_EINVAL, "props is NULL");
+    for (int i = 0; i < count; ++i)
+        if (int rc = check_props(&props[i])) return rc;
+    if (!workspace) return set_error(CHNS_EINVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return set_error(CHNS_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    chns_batch_workspace_size(count, descs, &need);
+    if (bytes < need) return set_error(CHNS_ENOMEM, "workspace smaller than chns_batch_workspace_size");
+    chns_batch *b = new (std::nothrow) chns_batch();
+    if (!b) return set_error(CHNS_ENOMEM, "host allocation failed");
+    b->count = count;
+    b->dim = descs[0].dim;
+    b->prec = descs[0].precision;
+    b->user_stream = (hipStream_t)hip_stream;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->g_steps = -1;
+    b->block = 256;
+    b->grid = count;
+    Bump B{(char *)workspace, 0};
+    std::vector<char> host_table;
+    size_t entry = 0;
+    auto fill = [&](auto tag) {
+        using TP = decltype(tag);
+        std::vector<BatchProb<TP>> h;
+        h.reserve(count);
+        layout_batch<TP>(B, count, plans.data(), props, &h, b);
+        for (int i = 0; i < count; ++i) {
+            h[i].k = step_const_of(props[i], descs[i].h);
+            const StepConst &k = h[i].k;
+            h[i].ch = ChOp{props[i].dt * k.kM * props[i].S, props[i].dt * k.kM * props[i].Cn * props[i].Cn, k.ih2};
+        }
+        entry = sizeof(BatchProb<TP>);
+        host_table.resize(entry * count);
+        memcpy(host_table.data(), h.data(), entry * count);
+    };
+    if (b->prec == CHNS_FP64) fill(double()); else fill(float());
+    b->offsets.resize(count + 1);
+    b->offsets[0] = 0;
+    for (int i = 0; i < count; ++i) b->offsets[i + 1] = b->offsets[i] + plans[i].lev[0].N;
+    // longest first (stable: equal sizes keep their index order)
+    b->order.resize(count);
+    for (int i = 0; i < count; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return plans[x].lev[0].N > plans[y].lev[0].N; });
+    auto cleanup = [&](int rc) {
+        if (b->stream) (void)hipStreamDestroy(b->stream);
+        if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+        if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+        delete b;
+        return rc;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemcpy(b->d_probs, host_table.data(), entry * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_order, b->order.data(), sizeof(int) * count, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(set_error(CHNS_EDEVICE, std::string("batch set-up: ") + hipGetErrorString(e)));
+    const int ginit = count < 4096 ? count : 4096;
+    if (b->prec == CHNS_FP64) {
+        if (b->dim == 2)
+            hipLaunchKernelGGL((k_batch_init<double, 2>), dim3(ginit), dim3(kBatchMaxThreads), 0, b->stream,
+                               (const BatchProb<double> *)b->d_probs, count);
+        else
+            hipLaunchKernelGGL((k_batch_init<double, 3>), dim3(ginit), dim3(kBatchMaxThreads), 0, b->stream,
+                               (const BatchProb<double> *)b->d_probs, count);
+    } else {
+        if (b->dim == 2)
+            hipLaunchKernelGGL((k_batch_init<float, 2>), dim3(ginit), dim3(kBatchMaxThreads), 0, b->stream,
+                               (const BatchProb<float> *)b->d_probs, count);
+        else
+            hipLaunchKernelGGL((k_batch_init<float, 3>), dim3(ginit), dim3(kBatchMaxThreads), 0, b->stream,
+                               (const BatchProb<float> *)b->d_probs, count);
+    }
+    hipLaunchKernelGGL(k_batch_reset_stats, dim3((count + 255) / 256), dim3(256), 0, b->stream, b->d_stats, count);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return cleanup(set_error(CHNS_EDEVICE, std::string("batch init: ") + hipGetErrorString(e)));
+    *out = b;
+    return CHNS_OK;
+}
+
+int chns_batch_offsets(chns_batch *b, long long *offsets) {
+    if (!b || !offsets) return set_error(CHNS_EINVAL, "NULL argument");
+    for (int i = 0; i <= b->count; ++i) offsets[i] = b->offsets[i];
+    return CHNS_OK;
+}
+
+int chns_batch_step(chns_batch *b, const chns_state *packed, int nsteps, int use_graph, chns_batch_stats *stats) {
+    if (!b) return set_error(CHNS_EINVAL, "NULL handle");
+    if (nsteps < 0) return set_error(CHNS_EINVAL, "nsteps must be >= 0");
+    BatchState st;
+    if (int rc = state_of(b, packed, st)) return rc;
+    if (int rc = run_steps(b, st, nsteps, use_graph)) return rc;
+    if (!stats) return CHNS_OK;
+    BHIPCHK(hipMemcpyAsync(stats, b->d_stats, sizeof(chns_batch_stats) * b->count, hipMemcpyDeviceToHost, b->stream));
+    BHIPCHK(hipStreamSynchronize(b->stream));
+    int flags = 0;
+    for (int i = 0; i < b->count; ++i) flags |= stats[i].flags;
+    if (flags & 32) return set_error(CHNS_ENONFINITE, "non-finite residual in a batched solve");
+    if (flags) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "unconverged batched solves (bit 0 CH, 1..3 momentum, 4 pressure): mask %d", flags);
+        return set_error(CHNS_ENOCONV, buf);
+    }
+    return CHNS_OK;
+}
+
+int chns_batch_set_launch(chns_batch *b, int block, int grid) {
+    if (!b) return set_error(CHNS_EINVAL, "NULL handle");
+    if (block < kWave || block > kBatchMaxThreads || block % kWave) return set_error(CHNS_EINVAL, "bad block size");
+    if (grid < 1) return set_error(CHNS_EINVAL, "grid must be >= 1");
+    b->block = block;
+    b->grid = grid;
+    return CHNS_OK;
+}
+
+int chns_batch_autotune(chns_batch *b, const chns_state *packed, int steps_per_trial, chns_batch_tuning *result) {
+    if (!b) return set_error(CHNS_EINVAL, "NULL handle");
+    if (steps_per_trial < 1) return set_error(CHNS_EINVAL, "steps_per_trial must be >= 1");
+    BatchState st;
+    if (int rc = state_of(b, packed, st)) return rc;
+    // candidates: workgroup size x workgroup count
+    const int blocks[3] = {128, 256, 512};
+    std::vector<int> grids;
+    for (int m : {1, 2, 4}) {
+        const int gsz = std::min(b->count, 256 * m);
+        if (std::find(grids.begin(), grids.end(), gsz) == grids.end()) grids.push_back(gsz);
+    }
+    if (std::find(grids.begin(), grids.end(), b->count) == grids.end()) grids.push_back(b->count);
+    chns_batch_tuning res;
+    memset(&res, 0, sizeof res);
+    hipEvent_t e0, e1;
+    BHIPCHK(hipEventCreate(&e0));
+    BHIPCHK(hipEventCreate(&e1));
+    const int saved_block = b->block, saved_grid = b->grid;
+    BHIPCHK(hipEventRecord(b->ev_in, b->user_stream));
+    BHIPCHK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    int rc = copy_state(b, st, 1, b->stream);
+    double best = 1e300;
+    int first = 1;
+    for (int bl : blocks) {
+        for (int gr : grids) {
+            if (rc) break;
+            if (res.ncand >= CHNS_MAX_TUNING) break;
+            b->block = bl;
+            b->grid = gr;
+            if (first) {   // warm-up (code objects, caches)
+                launch_steps(b, st, 1, b->stream);
+                if ((rc = copy_state(b, st, 0, b->stream))) break;
+                first = 0;
+            }
+            hipEventRecord(e0, b->stream);
+            launch_steps(b, st, steps_per_trial, b->stream);
+            hipEventRecord(e1, b->stream);
+            hipError_t e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = set_error(CHNS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+                break;
+            }
+            const double per = ms / steps_per_trial;
+            res.cand_block[res.ncand] = bl;
+            res.cand_grid[res.ncand] = gr;
+            res.cand_ms[res.ncand] = per;
+            res.ncand++;
+            if (per < best) {
+                best = per;
+                res.block = bl;
+                res.grid = gr;
+                res.ms_per_step = per;
+            }
+            if ((rc = copy_state(b, st, 0, b->stream))) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc && hipStreamSynchronize(b->stream) != hipSuccess) rc = set_error(CHNS_EDEVICE, "autotune sync failed");
+    if (rc) {
+        b->block = saved_block;
+        b->grid = saved_grid;
+        return rc;
+    }
+    b->block = res.block;
+    b->grid = res.grid;
+    drop_graph(b);
+    hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, b->stream, b->d_stats,
+                       b->count);
+    BHIPCHK(hipEventRecord(b->ev_out, b->stream));
+    BHIPCHK(hipStreamWaitEvent(b->user_stream, b->ev_out, 0));
+    if (result) *result = res;
+    return CHNS_OK;
+}
+
+int chns_destroy_batch(chns_batch *b) {
+    if (!b) return CHNS_OK;
+    drop_graph(b);
+    if (b->stream) {
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipStreamDestroy(b->stream);
+    }
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    delete b;
+    return CHNS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,431 @@
+// Device building blocks of the multigrid: per-cell operator, smoother and
+// transfer bodies, the workgroup-level V-cycle and hierarchy set-up, and the
+// Laplacian of the CH operator.  Shared by the grid-wide kernels (one pass
+// per launch), the single-workgroup coarse-level kernels and the batched
+// workgroup-per-problem step.
+#pragma once
+#include "common.h"
+
+namespace chns {
+
+// ---------------------------------------------------------------------------
+// per-cell building blocks (shared by the grid-wide and single-block kernels)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ inline void coords_of(const Geo &g, int c, int ia[3]) {
+    if (DIM == 2)
+        cell_coords2(g, c, ia[0], ia[1], ia[2]);
+    else
+        cell_coords(g, c, ia[0], ia[1], ia[2]);
+}
+
+// (A x)_c
+template <typename T, int DIM>
+__device__ inline T apply_at(const Level<T> &L, const T *__restrict__ x, int c, const int ia[3]) {
+    using R = T;
+    const Geo &g = L.g;
+    const R xc = (R)x[c];
+    R acc = (R)L.s[c] * xc;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) acc += (R)L.cs[b][c] * (xc - (R)x[lo]);
+        if (hi >= 0) acc += (R)L.cs[b][hi] * (xc - (R)x[hi]);
+    }
+    return acc;
+}
+
+// sum_b cs * x_nb over the neighbours (x given by a functor)
+template <typename T, int DIM, typename F>
+__device__ inline T offsum_at(const Level<T> &L, int c, const int ia[3], F xv) {
+    using R = T;
+    const Geo &g = L.g;
+    R acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) acc += (R)L.cs[b][c] * xv(lo);
+        if (hi >= 0) acc += (R)L.cs[b][hi] * xv(hi);
+    }
+    return acc;
+}
+
+template <typename T, int DIM>
+__device__ inline void invd_cell(const Level<T> &L, int c) {
+    using R = T;
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    R d = (R)L.s[c];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        if (nb_lo(L.g, c, ia[b], b) >= 0) d += (R)L.cs[b][c];
+        const int hi = nb_hi(L.g, c, ia[b], b);
+        if (hi >= 0) d += (R)L.cs[b][hi];
+    }
+    L.invd[c] = (T)((R)1 / d);
+}
+
+// zero-guess pre-smoothing: red x = b / d, black from those red values
+template <typename T, typename TB, int DIM>
+__device__ inline void presmooth_cell(const Level<T> &L, const TB *__restrict__ b, T *__restrict__ x, int c) {
+    using R = T;
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    const int col = (ia[0] + ia[1] + ia[2]) & 1;
+    if (col == 0) {
+        x[c] = (T)((R)b[c] * (R)L.invd[c]);
+    } else {
+        auto red = [&](int e) { return (R)b[e] * (R)L.invd[e]; };
+        x[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (R)L.invd[c]);
+    }
+}
+
+template <typename T, typename TB, int DIM>
+__device__ inline void residual_cell(const Level<T> &L, const TB *__restrict__ b, const T *__restrict__ x,
+                                     int c) {
+    using R = T;
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    L.r[c] = (T)((R)b[c] - apply_at<T, DIM>(L, x, c, ia));
+}
+
+// cell-centred linear prolongation along one axis: fine f takes 3/4 of its
+// parent f/2 and 1/4 of the coarse neighbour on its side; past a wall the
+// neighbour is the parent itself (weight 1 in total)
+template <typename R>
+__device__ inline void pro_axis(int f, int nc, int per, int &c0, int &c1, R &w0, R &w1) {
+    const int p = f >> 1;
+    int q = (f & 1) ? p + 1 : p - 1;
+    c0 = p;
+    if (q < 0 || q >= nc) {
+        if (per) {
+            q = q < 0 ? nc - 1 : 0;
+        } else {
+            c1 = p;
+            w0 = (R)1;
+            w1 = (R)0;
+            return;
+        }
+    }
+    c1 = q;
+    w0 = (R)0.75;
+    w1 = (R)0.25;
+}
+
+template <typename T, int DIM>
+__device__ inline T prolong_at(const Geo &gf, const Geo &gc, const T *__restrict__ xc, const int fi[3]) {
+    using R = T;
+    int c0[3], c1[3];
+    R w0[3], w1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < DIM) {
+            pro_axis<R>(fi[a], gc.n[a], gc.per[a], c0[a], c1[a], w0[a], w1[a]);
+        } else {
+            c0[a] = c1[a] = 0;
+            w0[a] = 1.0;
+            w1[a] = 0.0;
+        }
+    }
+    const int nx = gc.n[0], nxy = (int)gc.n[0] * gc.n[1];
+    R v = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz) {
+        const int kz = (dz ? c1[2] : c0[2]) * nxy;
+        const R wz = dz ? w1[2] : w0[2];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int ky = kz + (dy ? c1[1] : c0[1]) * nx;
+            const R wyz = wz * (dy ? w1[1] : w0[1]);
+            v += wyz * (w0[0] * (R)xc[ky + c0[0]] + w1[0] * (R)xc[ky + c1[0]]);
+        }
+    }
+    return v;
+}
+
+// full weighting along one axis: the four fine cells 2I-1 .. 2I+2 with
+// weights (1,3,3,1)/8; at a wall the missing outer cell's weight moves to the
+// adjacent child (4,3,1)/8 -- exactly the transpose of pro_axis / 2.  Always
+// four taps (an absent one gets weight 0 and a valid index) so that the
+// loads of a fully unrolled stencil issue together.
+template <typename R>
+__device__ inline void res_axis(int I, int nc, int nf, int per, int f[4], R w[4]) {
+    const bool lo = (I > 0) || per, hi = (I < nc - 1) || per;
+    f[0] = I > 0 ? 2 * I - 1 : (per ? nf - 1 : 0);
+    w[0] = lo ? (R)0.125 : (R)0;
+    f[1] = 2 * I;
+    w[1] = lo ? (R)0.375 : (R)0.5;
+    f[2] = 2 * I + 1;
+    w[2] = hi ? (R)0.375 : (R)0.5;
+    f[3] = I < nc - 1 ? 2 * I + 2 : (per ? 0 : nf - 1);
+    w[3] = hi ? (R)0.125 : (R)0;
+}
+
+template <typename T, int DIM>
+__device__ inline void restrict_cell(const Geo &gf, const Geo &gc, const T *__restrict__ rf, T *__restrict__ bc,
+                                     int c) {
+    using R = T;
+    int I[3];
+    coords_of<DIM>(gc, c, I);
+    int fx[4], fy[4], fz[4];
+    R wx[4], wy[4], wz[4];
+    res_axis<R>(I[0], gc.n[0], gf.n[0], gc.per[0], fx, wx);
+    res_axis<R>(I[1], gc.n[1], gf.n[1], gc.per[1], fy, wy);
+    if (DIM == 3) res_axis<R>(I[2], gc.n[2], gf.n[2], gc.per[2], fz, wz);
+    const int nx = gf.n[0], nxy = (int)gf.n[0] * gf.n[1];
+    R v = 0.0;
+#pragma unroll
+    for (int a = 0; a < (DIM == 3 ? 4 : 1); ++a) {
+        const int kz = DIM == 3 ? fz[a] * nxy : 0;
+        const R wza = DIM == 3 ? wz[a] : 1.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = kz + fy[q] * nx;
+            R s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s += wx[e] * (R)rf[row + fx[e]];
+            v += (wy[q] * wza) * s;
+        }
+    }
+    bc[c] = (T)v;
+}
+
+// fused prolongation + black sweep: writes tmp = {red: x + P e, black:
+// GS update from those red values}; x is left untouched
+template <typename T, typename TB, int DIM>
+__device__ inline void prolong_black_cell(const Level<T> &L, const Geo &gc, const T *__restrict__ xc,
+                                          const TB *__restrict__ b, const T *__restrict__ x, T *__restrict__ tmp,
+                                          int c) {
+    using R = T;
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    const int col = (ia[0] + ia[1] + ia[2]) & 1;
+    if (col == 0) {
+        tmp[c] = (T)((R)x[c] + prolong_at<T, DIM>(L.g, gc, xc, ia));
+    } else {
+        auto red = [&](int e) {
+            int ie[3];
+            coords_of<DIM>(L.g, e, ie);
+            return (R)x[e] + prolong_at<T, DIM>(L.g, gc, xc, ie);
+        };
+        tmp[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, red)) * (R)L.invd[c]);
+    }
+}
+
+// red sweep from tmp: x = {red: GS update from black tmp values, black: tmp}
+template <typename T, typename TB, int DIM>
+__device__ inline void red_from_tmp_cell(const Level<T> &L, const TB *__restrict__ b, const T *__restrict__ tmp,
+                                         T *__restrict__ x, int c) {
+    using R = T;
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    const int col = (ia[0] + ia[1] + ia[2]) & 1;
+    if (col == 1) {
+        x[c] = tmp[c];
+    } else {
+        auto blk = [&](int e) { return (R)tmp[e]; };
+        x[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, blk)) * (R)L.invd[c]);
+    }
+}
+
+// in-place Gauss-Seidel update of one colour (neighbours have the other colour)
+template <typename T, typename TB, int DIM>
+__device__ inline void gs_color_cell(const Level<T> &L, const TB *__restrict__ b, T *__restrict__ x, int color, int c) {
+    using R = T;
+    int ia[3];
+    coords_of<DIM>(L.g, c, ia);
+    if (((ia[0] + ia[1] + ia[2]) & 1) != color) return;
+    auto xv = [&](int e) { return (R)x[e]; };
+    x[c] = (T)(((R)b[c] + offsum_at<T, DIM>(L, c, ia, xv)) * (R)L.invd[c]);
+}
+
+template <typename T, int DIM>
+__device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, int c) {
+    int I[3];
+    coords_of<DIM>(C.g, c, I);
+    const Geo &gf = F.g;
+    double s = 0.0;
+    double cs[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int d3[3] = {dx, dy, dz};
+                const int f =
+                    (2 * I[0] + dx) + (int)gf.n[0] * ((2 * I[1] + dy) + (int)gf.n[1] * (2 * I[2] + dz));
+                s += (double)F.s[f];
+#pragma unroll
+                for (int b = 0; b < DIM; ++b)
+                    if (d3[b] == 0) cs[b] += (double)F.cs[b][f];   // fine faces on the coarse lower b-face
+            }
+    constexpr double nchild = (DIM == 3) ? 8.0 : 4.0;
+    C.s[c] = (T)(s / nchild);
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) C.cs[b][c] = (T)(cs[b] / (nchild * 0.5) * 0.25);
+}
+
+
+// ---------------------------------------------------------------------------
+// single-workgroup kernels for the small levels
+// ---------------------------------------------------------------------------
+#define BLOCK_LOOP(N) for (int c = (int)threadIdx.x; c < (int)(N); c += (int)blockDim.x)
+
+// x = Ainv b on the coarsest level (FP64 matrix, block-wide)
+template <typename T, typename TB>
+__device__ inline void coarse_solve_block(int n, const double *__restrict__ Ainv, const TB *__restrict__ b,
+                                          T *__restrict__ x) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = 0.0;
+        const double *row = Ainv + i * n;
+        for (int j = 0; j < n; ++j) v += row[j] * (double)b[j];
+        x[i] = (T)v;
+    }
+}
+
+template <typename T, typename TB, int DIM>
+__device__ inline void block_down(const Slot<T> &S, int l, const TB *__restrict__ b, T *__restrict__ x) {
+    const Level<T> &lv = S.lev[l];
+    BLOCK_LOOP(lv.g.N) presmooth_cell<T, TB, DIM>(lv, b, x, c);
+    __syncthreads();
+    BLOCK_LOOP(lv.g.N) residual_cell<T, TB, DIM>(lv, b, x, c);
+    __syncthreads();
+    BLOCK_LOOP(S.lev[l + 1].g.N) restrict_cell<T, DIM>(lv.g, S.lev[l + 1].g, lv.r, S.lev[l + 1].b, c);
+    __syncthreads();
+}
+
+template <typename T, typename TB, int DIM>
+__device__ inline void block_up(const Slot<T> &S, int l, const TB *__restrict__ b, T *__restrict__ x) {
+    const Level<T> &lv = S.lev[l];
+    BLOCK_LOOP(lv.g.N) prolong_black_cell<T, TB, DIM>(lv, S.lev[l + 1].g, S.lev[l + 1].x, b, x, lv.r, c);
+    __syncthreads();
+    BLOCK_LOOP(lv.g.N) red_from_tmp_cell<T, TB, DIM>(lv, b, lv.r, x, c);
+    __syncthreads();
+}
+
+// V-cycle over levels [l0, nlev) in one workgroup.  b0 / x0 are the
+// right-hand side / result of level l0 (they replace its own arrays; b0 may
+// be stored in another precision).  Ends with a workgroup barrier.
+template <typename T, typename TB, int DIM>
+__device__ inline void vcycle_block_dev(const Slot<T> &S, int l0, const TB *__restrict__ b0, T *__restrict__ x0) {
+    const int L = S.nlev;
+    if (l0 == L - 1) {
+        coarse_solve_block<T, TB>((int)S.lev[L - 1].g.N, S.Ainv, b0, x0);
+        __syncthreads();
+        return;
+    }
+    block_down<T, TB, DIM>(S, l0, b0, x0);
+    for (int l = l0 + 1; l < L - 1; ++l) block_down<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x);
+    coarse_solve_block<T, T>((int)S.lev[L - 1].g.N, S.Ainv, S.lev[L - 1].b, S.lev[L - 1].x);
+    __syncthreads();
+    for (int l = L - 2; l > l0; --l) block_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x);
+    block_up<T, TB, DIM>(S, l0, b0, x0);
+}
+
+// In-place Gauss-Jordan inversion of the n x n SPD matrix held in A (no
+// pivoting), block-wide; f is a scratch row of n doubles.
+__device__ inline void gauss_jordan_inplace(double *A, int n, double *f, double *piv) {
+    for (int k = 0; k < n; ++k) {
+        __syncthreads();
+        if (threadIdx.x == 0) *piv = 1.0 / A[k * n + k];
+        for (int i = threadIdx.x; i < n; i += blockDim.x) f[i] = A[i * n + k];
+        __syncthreads();
+        const double p = *piv;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) A[k * n + j] = (j == k) ? p : A[k * n + j] * p;
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e % n;
+            if (i == k) continue;
+            const double fi = f[i];
+            A[e] = (j == k) ? -fi * p : A[e] - fi * A[k * n + j];
+        }
+    }
+    __syncthreads();
+}
+
+// LDS of the set-up: the coarsest matrix when it has at most kLdsInverse
+// cells, a scratch row, reduction slots and the pivot.
+struct SetupLds {
+    double A[kLdsInverse * kLdsInverse];
+    double f[kMaxCoarse];
+    double red[kSBThreads / kWave];
+    double piv;
+};
+
+// Set-up of the small levels in one workgroup: coarsen from level
+// max(l0,1) - 1 downwards, inverse diagonals, then the coarsest inverse
+// (in LDS when it has at most kLdsInverse cells, else in S.aug).  Ends with
+// a workgroup barrier.
+template <typename T, int DIM>
+__device__ inline void setup_block_dev(const Slot<T> &S, int l0, SetupLds &sh) {
+    double *A = sh.A, *f = sh.f, *red = sh.red;
+    double &piv = sh.piv;
+    const int L = S.nlev;
+    if (l0 == 0) {
+        BLOCK_LOOP(S.lev[0].g.N) invd_cell<T, DIM>(S.lev[0], c);
+        __syncthreads();
+    }
+    for (int l = (l0 > 1 ? l0 : 1); l < L; ++l) {
+        BLOCK_LOOP(S.lev[l].g.N) coarsen_cell<T, DIM>(S.lev[l - 1], S.lev[l], c);
+        __syncthreads();
+        BLOCK_LOOP(S.lev[l].g.N) invd_cell<T, DIM>(S.lev[l], c);
+        __syncthreads();
+    }
+    // dense coarsest operator
+    const Level<T> &C = S.lev[L - 1];
+    const int n = (int)C.g.N;
+    double *M = n <= kLdsInverse ? A : S.aug;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = 0.0;
+    __syncthreads();
+    double dsum = 0.0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int ia[3];
+        coords_of<DIM>(C.g, c, ia);
+        double d = (double)C.s[c];
+        for (int b = 0; b < DIM; ++b) {
+            const int lo = nb_lo(C.g, c, ia[b], b);
+            const int hi = nb_hi(C.g, c, ia[b], b);
+            if (lo >= 0) {
+                const double w = (double)C.cs[b][c];
+                d += w;
+                M[c * n + lo] -= w;
+            }
+            if (hi >= 0) {
+                const double w = (double)C.cs[b][hi];
+                d += w;
+                M[c * n + hi] -= w;
+            }
+        }
+        M[c * n + c] += d;
+        dsum += d;
+    }
+    const double tot = block_sum_all(dsum, red);
+    if (S.singular) {
+        const double tau = (tot / n) / n;
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] += tau;
+    }
+    gauss_jordan_inplace(M, n, f, &piv);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) S.Ainv[e] = M[e];
+    __syncthreads();
+}
+
+
+// Lap(x) at c for the CH operator (walled axes Neumann), x given by a functor
+template <int DIM, typename F>
+__device__ inline double lap_at(const Geo &g, int c, const int ia[3], double ih2, F val) {
+    const double xc = val(c);
+    double acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) acc += val(lo) - xc;
+        if (hi >= 0) acc += val(hi) - xc;
+    }
+    return acc * ih2;
+}
+
+}  // namespace chns

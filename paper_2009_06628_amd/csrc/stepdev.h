@@ -45,5 +45,222 @@ __device__ inline double mflux(const Geo &g, const StepConst &k, const double *_
 __device__ inline int wrap_next(int ib, int n) { return ib + 1 < n ? ib + 1 : 0; }
 __device__ inline int wrap_prev(int ib, int n) { return ib > 0 ? ib - 1 : n - 1; }
 
+// ---------------------------------------------------------------------------
+// per-cell bodies of the step (shared by the grid-wide kernels and the
+// workgroup-per-problem batched kernel)
+// ---------------------------------------------------------------------------
+
+// S1: r = phi - dt D(u A phi) + dt kM L(psi'(phi) - S phi); phihat = phi
+template <int DIM>
+__device__ inline void ch_rhs_cell(const Geo &g, const StepConst &k, const double *__restrict__ phi, const U3 &u,
+                                   double *__restrict__ r, double *__restrict__ phihat, int c) {
+    int i, j, kk;
+    if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
+    const int ia[3] = {i, j, kk};
+    const double pc = phi[c];
+    const double gc = dpsi(pc) - k.S * pc;
+    double div = 0.0, lap = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int lo = nb_lo(g, c, ia[a], a);
+        const int hi = nb_hi(g, c, ia[a], a);
+        double flo = 0.0, fhi = 0.0;
+        if (lo >= 0) {
+            const double pl = phi[lo];
+            flo = u.a[a][c] * (0.5 * (pl + pc));
+            lap += (dpsi(pl) - k.S * pl) - gc;
+        }
+        if (hi >= 0) {
+            const double ph = phi[hi];
+            fhi = u.a[a][hi] * (0.5 * (pc + ph));
+            lap += (dpsi(ph) - k.S * ph) - gc;
+        }
+        div += fhi - flo;
+    }
+    r[c] = pc - k.dt * (div * k.ih) + k.dt * k.kM * (lap * k.ih2);
+    phihat[c] = pc;
+}
+
+// S3: mu = psi'(phi) + S (phihat - phi) - Cn^2 L phihat
+template <int DIM>
+__device__ inline void mu_cell(const Geo &g, const StepConst &k, const double *__restrict__ phi,
+                               const double *__restrict__ ph, double *__restrict__ mu, int c) {
+    int i, j, kk;
+    if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
+    const int ia[3] = {i, j, kk};
+    const double xc = ph[c];
+    double lap = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int lo = nb_lo(g, c, ia[a], a);
+        const int hi = nb_hi(g, c, ia[a], a);
+        if (lo >= 0) lap += ph[lo] - xc;
+        if (hi >= 0) lap += ph[hi] - xc;
+    }
+    const double pc = phi[c];
+    mu[c] = dpsi(pc) + k.S * (xc - pc) - k.Cn * k.Cn * (lap * k.ih2);
+}
+
+// S4: flux-form update; both cells of a face evaluate its flux with the same
+// operands in the same order, so sum(phi) telescopes to round-off.
+__device__ inline double phi_face_flux(const StepConst &k, double uf, double pl, double pu, double ml, double mu_) {
+    return uf * (0.5 * (pl + pu)) - k.kM * ((mu_ - ml) * k.ih);
+}
+
+template <int DIM>
+__device__ inline void phi_update_cell(const Geo &g, const StepConst &k, const double *__restrict__ phi, const U3 &u,
+                                       const double *__restrict__ mu, double *__restrict__ phin, int c) {
+    int i, j, kk;
+    if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
+    const int ia[3] = {i, j, kk};
+    const double pc = phi[c], mc = mu[c];
+    double div = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int lo = nb_lo(g, c, ia[a], a);
+        const int hi = nb_hi(g, c, ia[a], a);
+        const double flo = lo >= 0 ? phi_face_flux(k, u.a[a][c], phi[lo], pc, mu[lo], mc) : 0.0;
+        const double fhi = hi >= 0 ? phi_face_flux(k, u.a[a][hi], pc, phi[hi], mc, mu[hi]) : 0.0;
+        div += fhi - flo;
+    }
+    phin[c] = pc - k.dt * (div * k.ih);
+}
+
+// S5-S7 set-up for component a: level-0 coefficients of the momentum operator,
+// right-hand side, initial guess ustar_a = u_a
+template <int DIM>
+__device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, const double *__restrict__ phi,
+                                      const double *__restrict__ phin, const double *__restrict__ mu, const U3 &u,
+                                      double *__restrict__ s, const W3 &cs, double *__restrict__ rhs,
+                                      double *__restrict__ ustar, int coef_only, int c) {
+    const double rvis = k.inv_Re * k.ih2;
+    int i, j, kk;
+    if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
+    const int ia[3] = {i, j, kk};
+    const double *ua = u.a[a];
+    if (!g.per[a] && ia[a] == 0) {
+        // wall face of a walled axis: decoupled identity row, u = 0
+        s[c] = 1.0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) cs.a[b][c] = 0.0;
+        if (!coef_only) {
+            rhs[c] = 0.0;
+            ustar[c] = 0.0;
+        }
+        return;
+    }
+    const int cam = nb_lo(g, c, ia[a], a);   // cell c - e_a
+    auto eta_of = [&](int e) { return k.gamma * pullback(phin[e]) + k.xi; };
+    const double rf_new = 0.5 * ((k.alpha * pullback(phin[c]) + k.beta) + (k.alpha * pullback(phin[cam]) + k.beta));
+    const double rf_old = 0.5 * ((k.alpha * pullback(phi[c]) + k.beta) + (k.alpha * pullback(phi[cam]) + k.beta));
+    const double e_c = eta_of(c), e_am = eta_of(cam);
+    double sd = rf_new / k.dt;
+    double nadv = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
+        if (b == a) {
+            // viscous coupling through the cell centres c - e_a (lower) and c (upper)
+            double w = e_am * rvis;
+            if (!g.per[a] && ia[a] == 1) {
+                sd += w;        // neighbour is the wall face (u = 0)
+                w = 0.0;
+            }
+            if (!g.per[a] && ia[a] == g.n[a] - 1) sd += e_c * rvis;   // upper wall face
+            cs.a[b][c] = w;
+            // skew advection, b == a
+            const double m_c = mflux<DIM>(g, k, phi, mu, u.a[a], a, c, ia[a]);
+            const double m_hi = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[a], a, hi, wrap_next(ia[a], g.n[a])) : 0.0;
+            const double m_lo = mflux<DIM>(g, k, phi, mu, u.a[a], a, lo, wrap_prev(ia[a], g.n[a]));
+            const double mp = 0.5 * (m_c + m_hi), mm = 0.5 * (m_lo + m_c);
+            const double up = hi >= 0 ? ua[hi] : 0.0;
+            const double um = (!g.per[a] && ia[a] == 1) ? 0.0 : ua[lo];   // wall face
+            nadv += mp * up - mm * um;
+        } else {
+            // viscous coupling through the edge between faces c - e_b and c
+            if (lo >= 0) {
+                const int lam = nb_lo(g, lo, ia[a], a);   // c - e_b - e_a
+                const double ee = 0.25 * (((e_c + e_am) + eta_of(lo)) + eta_of(lam));
+                cs.a[b][c] = (!g.per[b] && ia[b] == 0) ? 0.0 : ee * rvis;
+            } else {
+                cs.a[b][c] = 0.0;
+            }
+            if (!g.per[b] && ia[b] == 0) sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
+            if (!g.per[b] && ia[b] == g.n[b] - 1) sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
+            // skew advection, b != a
+            const int ibn = wrap_next(ia[b], g.n[b]);
+            const double mph = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[b], b, hi, ibn) : 0.0;
+            const int hiam = hi >= 0 ? nb_lo(g, hi, ia[a], a) : -1;   // c + e_b - e_a
+            const double mpha = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[b], b, hiam, ibn) : 0.0;
+            const double mp = 0.5 * (mph + mpha);
+            const double mm = 0.5 * (mflux<DIM>(g, k, phi, mu, u.a[b], b, c, ia[b]) +
+                                     mflux<DIM>(g, k, phi, mu, u.a[b], b, cam, ia[b]));
+            const double uc = ua[c];
+            const double up = hi >= 0 ? ua[hi] : -uc;
+            const double um = lo >= 0 ? ua[lo] : -uc;
+            nadv += mp * up - mm * um;
+        }
+    }
+    nadv *= 0.5 * k.ih;
+    const double st = (k.inv_We / k.Cn) * (0.5 * (phi[c] + phi[cam])) * ((mu[c] - mu[cam]) * k.ih);
+    double f = (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
+    if (a == 1 && k.inv_Fr != 0.0) f -= rf_new * k.inv_Fr;     // g_hat = (0, -1, 0)
+    s[c] = sd;
+    if (!coef_only) {
+        rhs[c] = f;
+        ustar[c] = ua[c];
+    }
+}
+
+// S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new),
+// rhs = -(We/dt) D ustar
+template <int DIM>
+__device__ inline void p_setup_cell(const Geo &g, const StepConst &k, const double *__restrict__ phin, const U3 &us,
+                                    double *__restrict__ s, const W3 &cs, double *__restrict__ rhs, int c) {
+    int i, j, kk;
+    if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
+    const int ia[3] = {i, j, kk};
+    const double rc = k.alpha * pullback(phin[c]) + k.beta;
+    double div = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const int lo = nb_lo(g, c, ia[b], b);
+        const int hi = nb_hi(g, c, ia[b], b);
+        if (lo >= 0) {
+            const double rl = k.alpha * pullback(phin[lo]) + k.beta;
+            cs.a[b][c] = 1.0 / (0.5 * (rc + rl)) * k.ih2;
+        } else {
+            cs.a[b][c] = 0.0;
+        }
+        const double flo = lo >= 0 ? us.a[b][c] : 0.0;
+        const double fhi = hi >= 0 ? us.a[b][hi] : 0.0;
+        div += fhi - flo;
+    }
+    s[c] = 0.0;
+    rhs[c] = -(k.We / k.dt) * (div * k.ih);
+}
+
+// S9: u = ustar - (dt/We) G p / rho_f; phi = phi_new
+template <int DIM>
+__device__ inline void project_cell(const Geo &g, const StepConst &k, const double *__restrict__ phin, const U3 &us,
+                                    const double *__restrict__ p, double *__restrict__ phi, const W3 &u, int c) {
+    int i, j, kk;
+    if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
+    const int ia[3] = {i, j, kk};
+    const double pn = phin[c];
+    const double rc = k.alpha * pullback(pn) + k.beta;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const int lo = nb_lo(g, c, ia[a], a);
+        double v = 0.0;
+        if (lo >= 0) {
+            const double rf = 0.5 * (rc + (k.alpha * pullback(phin[lo]) + k.beta));
+            v = us.a[a][c] - (k.dt * k.inv_We) * ((p[c] - p[lo]) * k.ih) / rf;
+        }
+        u.a[a][c] = v;
+    }
+    phi[c] = pn;
+}
 
 }  // namespace chns

@@ -1,0 +1,198 @@
+"""Batched ensemble (chns_create_batch / chns_batch_step) on the GPU.
+
+* every batched problem matches its own single-grid run (FP64, 20 steps,
+  three problems of each size 64 .. 256) to 1e-10 relative;
+* small batches (2D periodic and walled, 3D) match the FP64 oracle to 1e-9;
+* the precision form stays within 1e-5 of the FP64 batch;
+* a captured hipGraph replays bit for bit like eager launches, several times,
+  with unrelated device work in between;
+* the autotuner restores the state bit for bit and every launch shape gives
+  the same answer up to the order of the sums;
+* phase masses are conserved per problem.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import MACGrid, Params, step as ostep
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    import paper_2009_06628_amd as P
+    return P
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def compare(bv, ref, dim, tol, what):
+    errs = {"phi": relerr(to_np(bv["phi"]), ref["phi"])}
+    for a in range(dim):
+        scale = max(np.abs(ref["u"][a]).max(), 1e-300)
+        errs["u%d" % a] = float(np.abs(to_np(bv["u"][a]) - ref["u"][a]).max() / scale)
+    pb, pr = to_np(bv["p"]), np.asarray(ref["p"])
+    errs["p"] = relerr(pb - pb.mean(), pr - pr.mean())
+    print(what, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (what, k, v, tol)
+
+
+def single_grid_run(prob, steps, precision=0):
+    P = _lib()
+    g = P.grid_for_problem(prob, precision)
+    st = g.new_state(W.initial_state(prob))
+    g.step(st, steps)
+    return {"phi": to_np(st["phi"]), "u": [to_np(x) for x in st["u"]], "p": to_np(st["p"])}
+
+
+def batch_run(probs, steps, precision=0, use_graph=False):
+    P = _lib()
+    b = P.create_batch(probs, precision)
+    st = b.new_state([W.initial_state(p) for p in probs])
+    stats = b.step(st, steps, use_graph=use_graph)
+    torch.cuda.synchronize()
+    return b, st, stats
+
+
+def test_batch_matches_single_grid_fp64():
+    probs = W.ensemble_stratified(per_size=3, steps=20)
+    print("batch vs single grid:", [p.n[0] for p in probs], flush=True)
+    b, st, stats = batch_run(probs, 20)
+    print("iterations (last step) of the first problem of each size:",
+          [(probs[i].n[0], stats[i]["iters_ch"], stats[i]["iters_mom"], stats[i]["iters_p"])
+           for i in range(0, len(probs), 3)], flush=True)
+    for i, p in enumerate(probs):
+        assert stats[i]["steps"] == 20 and stats[i]["flags"] == 0
+        ref = single_grid_run(p, 20)
+        compare(b.view(st, i), ref, 2, 1e-10, "problem %d (%d^2)" % (i, p.n[0]))
+
+
+def _oracle(prob, steps):
+    g = MACGrid(prob.n, prob.h, prob.periodic)
+    prm = Params.from_props(prob.props)
+    s = W.initial_state(prob)
+    for _ in range(steps):
+        s = ostep(g, s, prm)
+    return s
+
+
+def test_batch_matches_oracle_2d():
+    probs = [W.oscillating_drop(16, (0.3, 0.22), 10.0, 5.0, steps=10),
+             W.oscillating_drop(24, (0.25, 0.2), 300.0, 30.0, steps=10),
+             W.oscillating_drop(32, (0.22, 0.28), 1.0, 1.0, steps=10),
+             W.rising_bubble(16, steps=10)]
+    probs[3].init_args = dict(probs[3].init_args, velocity="stream", vseed=6, vamp=0.1)
+    print("batch vs oracle 2D:", [p.n for p in probs], flush=True)
+    b, st, stats = batch_run(probs, 10)
+    for i, p in enumerate(probs):
+        compare(b.view(st, i), _oracle(p, 10), 2, 1e-9, "problem %d %s" % (i, p.n))
+
+
+def test_batch_matches_oracle_3d():
+    probs = [W.drop3d(16, steps=3), W.drop3d(8, steps=3)]
+    print("batch vs oracle 3D:", [p.n for p in probs], flush=True)
+    b, st, stats = batch_run(probs, 3)
+    for i, p in enumerate(probs):
+        compare(b.view(st, i), _oracle(p, 3), 3, 1e-9, "problem %d %s" % (i, p.n))
+
+
+def test_batch_precision_form_within_1e5():
+    P = _lib()
+    probs = W.ensemble_stratified(per_size=3, steps=20, **W.PRECISION_FORM_TOLERANCES)
+    print("batch precision form vs FP64 batch", flush=True)
+    b64, s64, _ = batch_run(probs, 20, P.CHNS_FP64)
+    b32, s32, stats = batch_run(probs, 20, P.CHNS_FP32_REFINE)
+    for i, p in enumerate(probs):
+        v = b64.view(s64, i)
+        ref = {"phi": to_np(v["phi"]), "u": [to_np(x) for x in v["u"]], "p": to_np(v["p"])}
+        compare(b32.view(s32, i), ref, 2, 1e-5, "problem %d (%d^2) fp32+refine" % (i, p.n[0]))
+
+
+def test_batch_graph_replays_match_eager():
+    P = _lib()
+    probs = [W.oscillating_drop(n, (0.25, 0.21), 50.0, 7.0, steps=5) for n in (32, 48, 64, 96, 64, 32)]
+    inits = [W.initial_state(p) for p in probs]
+    print("graph replay vs eager", flush=True)
+    b = P.create_batch(probs)
+    st = b.new_state(inits)
+    b.step(st, 5, use_graph=False)
+    eager = {"phi": st["phi"].clone(), "u": [x.clone() for x in st["u"]], "p": st["p"].clone()}
+    junk = torch.randn(1 << 20, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        fresh = b.new_state(inits)
+        for k in ("phi", "p"):
+            st[k].copy_(fresh[k])
+        for a in range(2):
+            st["u"][a].copy_(fresh["u"][a])
+        stats = b.step(st, 5, use_graph=True)
+        torch.cuda.synchronize()
+        assert all(s["steps"] == 5 for s in stats)
+        assert torch.equal(st["phi"], eager["phi"]) and torch.equal(st["p"], eager["p"]), rep
+        for a in range(2):
+            assert torch.equal(st["u"][a], eager["u"][a]), rep
+        junk.mul_(1.0001).add_(0.5)           # unrelated eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_batch_autotune_restores_state_and_shapes_agree():
+    P = _lib()
+    probs = W.ensemble(count=24, seed=9, steps=3)
+    inits = [W.initial_state(p) for p in probs]
+    print("autotune on 24 problems", flush=True)
+    b = P.create_batch(probs)
+    st = b.new_state(inits)
+    before = {k: st[k].clone() for k in ("phi", "p")}
+    res = b.autotune(st, 1)
+    torch.cuda.synchronize()
+    print("autotune:", res, flush=True)
+    assert res["block"] in (128, 256, 512) and res["grid"] >= 1 and len(res["candidates"]) >= 3
+    for k in ("phi", "p"):
+        assert torch.equal(st[k], before[k])
+    outs = []
+    for block, grid in ((128, 5), (512, 24), (256, 13)):
+        s = b.new_state(inits)
+        b.set_launch(block, grid)
+        b.step(s, 3)
+        outs.append(s)
+    for o in outs[1:]:
+        assert relerr(to_np(o["phi"]), to_np(outs[0]["phi"])) <= 1e-12
+        assert relerr(to_np(o["u"][0]), to_np(outs[0]["u"][0])) <= 1e-9
+
+
+def test_batch_mass_conservation():
+    probs = W.ensemble(count=10, seed=5, sizes=(32, 64, 96), steps=20)
+    b, st, stats = batch_run(probs, 20)
+    for i, p in enumerate(probs):
+        phi0 = W.initial_state(p)["phi"]
+        phi = to_np(b.view(st, i)["phi"])
+        m0, m1 = (1 + phi0).sum(), (1 + phi).sum()
+        rel = abs(m1 - m0) / m0
+        assert rel <= 1e-12, (i, rel)
+
+
+def test_batch_argument_errors():
+    P = _lib()
+    import ctypes
+    lib = P.load_library()
+    descs = (P.chns_grid_desc * 2)()
+    descs[0] = P.make_desc((32, 32), 1 / 32, ("periodic", "periodic"))
+    descs[1] = P.make_desc((16, 16, 16), 1 / 16, ("periodic",) * 3)
+    n = ctypes.c_size_t(0)
+    assert lib.chns_batch_workspace_size(2, descs, ctypes.byref(n)) == P.CHNS_EINVAL
+    assert lib.chns_batch_workspace_size(0, descs, ctypes.byref(n)) == P.CHNS_EINVAL
+    probs = [W.oscillating_drop(32, (0.25, 0.25), 2.0, 2.0, steps=1)]
+    b = P.create_batch(probs)
+    with pytest.raises(P.CHNSError):
+        b.set_launch(1000, 4)
+    with pytest.raises(P.CHNSError):
+        b.set_launch(256, 0)

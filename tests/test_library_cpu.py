@@ -87,3 +87,23 @@ def test_adjoint_workspace_size(n, bc):
     d.dim = 5
     assert lib.chns_adjoint_workspace_size(ctypes.byref(d), ctypes.byref(out)) == P.CHNS_EINVAL
     assert lib.chns_adjoint_step(None, None, None, None, None) == P.CHNS_EINVAL
+
+
+def test_batch_workspace_size_and_validation():
+    lib = P.load_library()
+    descs = (P.chns_grid_desc * 3)()
+    for i, n in enumerate((64, 96, 256)):
+        descs[i] = P.make_desc((n, n), 1.0 / n, ("periodic", "periodic"))
+    out = ctypes.c_size_t(0)
+    assert lib.chns_batch_workspace_size(3, descs, ctypes.byref(out)) == P.CHNS_OK
+    cells = 64 * 64 + 96 * 96 + 256 * 256
+    assert out.value >= 8 * cells * 20
+    descs[1].precision = P.CHNS_FP32_REFINE      # mixed precision is rejected
+    assert lib.chns_batch_workspace_size(3, descs, ctypes.byref(out)) == P.CHNS_EINVAL
+    descs[1].precision = P.CHNS_FP64
+    descs[2].n[0] = 50                           # unsupported size
+    assert lib.chns_batch_workspace_size(3, descs, ctypes.byref(out)) == P.CHNS_EINVAL
+    h = ctypes.c_void_p()
+    props = (P.chns_props * 3)()
+    assert lib.chns_create_batch(3, descs, props, ctypes.c_void_p(4096), ctypes.c_size_t(1 << 30), None,
+                                 ctypes.byref(h)) == P.CHNS_EINVAL

@@ -395,6 +395,48 @@ def drops3d(n: int = 128, steps: int = 500, seed: int = 3, count: int = 16, **kw
                     "velocity": "potential3d", "vseed": seed + 100, "vamp": 1e-2})
 
 
+def oscillating_drop(n: int, semi_axes, rho_ratio: float, eta_ratio: float, sigma: float = 1.0,
+                     mobility: float = 1e-3, steps: int = 200, name: Optional[str] = None, **kw) -> Problem:
+    """One member of the batched ensemble: unit periodic box, centred
+    axis-aligned ellipse, density / viscosity ratios rho_+/rho_- and
+    eta_+/eta_-, Re = 10, Cn = 1.5 h, We = 1/sigma, Pe = 1/(M sigma), and the
+    capillary time-step bound dt = min(1e-4, 1/2 sqrt((rho_+ + rho_-) h^3 / (2 pi sigma)))."""
+    h = 1.0 / n
+    rho_minus = 1.0 / rho_ratio
+    dt = min(1e-4, 0.5 * math.sqrt((1.0 + rho_minus) * h ** 3 / (2.0 * math.pi * sigma)))
+    pr = Props(rho_minus=rho_minus, eta_minus=1.0 / eta_ratio, Re=10.0, We=1.0 / sigma, Cn=1.5 * h,
+               Pe=1.0 / (mobility * sigma), inv_Fr=0.0, dt=dt)
+    pr = pr.copy(**kw)
+    return Problem(name or "osc_drop_%d" % n, (n, n), h, (PERIODIC, PERIODIC), pr, steps,
+                   "ellipse", {"centre": (0.5, 0.5), "semi_axes": tuple(semi_axes)})
+
+
+def ensemble(count: int = 512, seed: int = 4, sizes=(64, 96, 128, 192, 256), steps: int = 200,
+             **kw) -> List[Problem]:
+    """Batched ensemble of oscillating drops: n ~ U(sizes), semi-axes
+    U[0.2, 0.3] each, rho_+/rho_- ~ logU[1, 1000], eta_+/eta_- ~ logU[1, 100]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        ax = rng.uniform(0.2, 0.3, size=2)
+        rr = float(np.exp(rng.uniform(0.0, math.log(1000.0))))
+        er = float(np.exp(rng.uniform(0.0, math.log(100.0))))
+        out.append(oscillating_drop(n, ax, rr, er, steps=steps, name="ens%d_%d" % (i, n), **kw))
+    return out
+
+
+def ensemble_stratified(per_size: int = 3, seed: int = 4, sizes=(64, 96, 128, 192, 256), steps: int = 20,
+                        **kw) -> List[Problem]:
+    """A few members of every size (parity tests of the batched form): the
+    first per_size members of each size drawn from the ensemble's generator."""
+    pool = ensemble(count=64 * len(sizes) * per_size, seed=seed, sizes=sizes, steps=steps, **kw)
+    out = []
+    for n in sizes:
+        out += [p for p in pool if p.n[0] == n][:per_size]
+    return out
+
+
 # Solver tolerances of the precision form (FP32 multigrid under FP64
 # refinement): its budget is 1e-5 relative to the FP64 oracle, so the solves
 # stop at these looser relative residuals (measured error ~2e-7).
