@@ -186,8 +186,11 @@ __device__ __attribute__((noinline)) PcgRes pcg_block(const BatchProb<TP> &P, in
                     for (int bx = 0; bx < DIM; ++bx) {
                         const int lo = nb_lo(g, c, ia[bx], bx);
                         const int hi = nb_hi(g, c, ia[bx], bx);
-                        if (lo >= 0) qc += L.cs[bx][c] * (pc - pv(lo));
-                        if (hi >= 0) qc += L.cs[bx][hi] * (pc - pv(hi));
+                        const int l = lo >= 0 ? lo : c, h = hi >= 0 ? hi : c;
+                        const double vl = pv(l), vh = pv(h);
+                        const double wl = L.cs[bx][c], wh = L.cs[bx][h];
+                        qc += (lo >= 0 ? wl : 0.0) * (pc - vl);
+                        qc += (hi >= 0 ? wh : 0.0) * (pc - vh);
                     }
                     pnew[c] = pc;
                     q[c] = qc;

@@ -19,6 +19,11 @@ __device__ inline void coords_of(const Geo &g, int c, int ia[3]) {
         cell_coords(g, c, ia[0], ia[1], ia[2]);
 }
 
+// Neighbour stencils are branch-free: a missing neighbour (outside a walled
+// axis) is replaced by the cell itself with weight 0, so every load of a
+// stencil is unconditional and can be issued together (adding 0 leaves the
+// sums unchanged).
+
 // (A x)_c
 template <typename T, int DIM>
 __device__ inline T apply_at(const Level<T> &L, const T *__restrict__ x, int c, const int ia[3]) {
@@ -30,8 +35,11 @@ __device__ inline T apply_at(const Level<T> &L, const T *__restrict__ x, int c, 
     for (int b = 0; b < DIM; ++b) {
         const int lo = nb_lo(g, c, ia[b], b);
         const int hi = nb_hi(g, c, ia[b], b);
-        if (lo >= 0) acc += (R)L.cs[b][c] * (xc - (R)x[lo]);
-        if (hi >= 0) acc += (R)L.cs[b][hi] * (xc - (R)x[hi]);
+        const int l = lo >= 0 ? lo : c, h = hi >= 0 ? hi : c;
+        const R xl = (R)x[l], xh = (R)x[h];
+        const R wl = (R)L.cs[b][c], wh = (R)L.cs[b][h];
+        acc += (lo >= 0 ? wl : (R)0) * (xc - xl);
+        acc += (hi >= 0 ? wh : (R)0) * (xc - xh);
     }
     return acc;
 }
@@ -46,8 +54,11 @@ __device__ inline T offsum_at(const Level<T> &L, int c, const int ia[3], F xv) {
     for (int b = 0; b < DIM; ++b) {
         const int lo = nb_lo(g, c, ia[b], b);
         const int hi = nb_hi(g, c, ia[b], b);
-        if (lo >= 0) acc += (R)L.cs[b][c] * xv(lo);
-        if (hi >= 0) acc += (R)L.cs[b][hi] * xv(hi);
+        const int l = lo >= 0 ? lo : c, h = hi >= 0 ? hi : c;
+        const R vl = xv(l), vh = xv(h);
+        const R wl = (R)L.cs[b][c], wh = (R)L.cs[b][h];
+        acc += (lo >= 0 ? wl : (R)0) * vl;
+        acc += (hi >= 0 ? wh : (R)0) * vh;
     }
     return acc;
 }
@@ -414,6 +425,7 @@ __device__ inline void setup_block_dev(const Slot<T> &S, int l0, SetupLds &sh) {
 
 
 // Lap(x) at c for the CH operator (walled axes Neumann), x given by a functor
+// (branch-free like apply_at)
 template <int DIM, typename F>
 __device__ inline double lap_at(const Geo &g, int c, const int ia[3], double ih2, F val) {
     const double xc = val(c);
@@ -422,8 +434,9 @@ __device__ inline double lap_at(const Geo &g, int c, const int ia[3], double ih2
     for (int b = 0; b < DIM; ++b) {
         const int lo = nb_lo(g, c, ia[b], b);
         const int hi = nb_hi(g, c, ia[b], b);
-        if (lo >= 0) acc += val(lo) - xc;
-        if (hi >= 0) acc += val(hi) - xc;
+        const double vl = val(lo >= 0 ? lo : c), vh = val(hi >= 0 ? hi : c);
+        acc += lo >= 0 ? vl - xc : 0.0;
+        acc += hi >= 0 ? vh - xc : 0.0;
     }
     return acc * ih2;
 }
