@@ -8,6 +8,16 @@ A step is one full pass S1..S9 (CH solve, momentum predictor, pressure
 projection).  Inputs are synthetic (seeded tanh bubble, fluid at rest) and
 already resident in device memory when the timed region starts.
 
+Secondary measurements (key "secondary", each on its own workload, skipped
+with --no-extras):
+  precision_form  3D periodic drops (128^3, 16 drops, ratios 100): FP64 vs
+                  FP32 multigrid under FP64 refinement, throughput ratio and
+                  the state difference after the timed steps
+  batched         ensemble of 512 oscillating drops (64^2 .. 256^2), FP32 +
+                  refinement, autotuned launch shape, hipGraph-captured steps
+  adjoint         oscillating drop 128^2, FP64: backward (checkpoint every 20
+                  steps, segment recompute, adjoint steps) vs forward time
+
 Prints one JSON line:
   value         grid cell-updates/s = cells * steps / wall-time of the timed
                 region (host-side clock after a device synchronisation on
@@ -44,7 +54,96 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extra-steps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def bench_precision_form(P, W, steps):
+    """3D drops: FP64 vs FP32+refinement on the same input."""
+    import torch
+    prob = W.drops3d(128, steps=steps, **W.PRECISION_FORM_TOLERANCES)
+    init = W.initial_state(prob)
+    out = {"workload": "drops3d_128^3", "cells": prob.cells, "steps": steps}
+    states = {}
+    for name, prec in (("fp64", P.CHNS_FP64), ("fp32_refine", P.CHNS_FP32_REFINE)):
+        g = P.grid_for_problem(prob, prec, device="cuda:0")
+        st = g.new_state(init)
+        g.step(st, 2, stats=False)
+        _sync()
+        t0 = time.perf_counter()
+        g.step(st, steps, stats=False)
+        _sync()
+        dt = time.perf_counter() - t0
+        out[name] = {"value": round(prob.cells * steps / dt, 1), "ms_per_step": round(dt / steps * 1e3, 3)}
+        states[name] = st
+        del g
+    out["speedup"] = round(out["fp32_refine"]["value"] / out["fp64"]["value"], 3)
+    a, b = states["fp32_refine"], states["fp64"]
+    err = float((a["phi"] - b["phi"]).abs().max() / b["phi"].abs().max())
+    for d in range(3):
+        err = max(err, float((a["u"][d] - b["u"][d]).abs().max() / b["u"][d].abs().max().clamp_min(1e-300)))
+    out["max_rel_diff_vs_fp64"] = err
+    out["tolerances"] = W.PRECISION_FORM_TOLERANCES
+    return out
+
+
+def bench_batched(P, W, steps):
+    """Batched ensemble: 512 problems, FP32 + refinement, graph-captured."""
+    probs = W.ensemble(count=512, seed=4, steps=200, **W.PRECISION_FORM_TOLERANCES)
+    b = P.create_batch(probs, P.CHNS_FP32_REFINE, device="cuda:0")
+    st = b.new_state([W.initial_state(p) for p in probs])
+    tune = b.autotune(st, 1)
+    b.step(st, steps, use_graph=True, stats=False)     # capture + first replay (warm-up)
+    _sync()
+    t0 = time.perf_counter()
+    stats = b.step(st, steps, use_graph=True, stats=True)
+    dt = time.perf_counter() - t0
+    tot = sum(s["total_iters"] for s in stats)
+    return {"workload": "ensemble_512_oscillating_drops_fp32_refine", "problems": len(probs),
+            "cells": b.total_cells, "steps": steps, "value": round(b.total_cells * steps / dt, 1),
+            "ms_per_step": round(dt / steps * 1e3, 3), "graph": True,
+            "launch": {"block": tune["block"], "grid": tune["grid"]},
+            "autotune_ms_per_step": {"%dx%d" % (c[0], c[1]): round(c[2], 2) for c in tune["candidates"]},
+            "pcg_iterations_per_problem_step": round(tot / (len(probs) * steps), 2),
+            "unconverged": sum(1 for s in stats if s["flags"])}
+
+
+def bench_adjoint(P, W):
+    """Oscillating drop 128^2: 40 forward steps vs the checkpointed backward."""
+    import torch
+    from paper_2009_06628_amd.adjoint import rollout
+    steps = 40
+    prob = W.adjoint_drop(128, steps=steps)
+    init = W.initial_state(prob)
+    g = P.create_grid(prob.n, prob.h, prob.bc, device="cuda:0")
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda:0")
+    u0 = [dev(x) for x in init["u"]]
+    with torch.no_grad():
+        target = rollout(g, prob.props, dev(init["phi"]), u0, 1.0, 1e-3, steps)[0].clone()
+    phi0 = dev(init["phi"]).requires_grad_(True)
+    sigma = torch.tensor(1.1, dtype=torch.float64, requires_grad=True)
+    mob = torch.tensor(1.2e-3, dtype=torch.float64, requires_grad=True)
+    _sync()
+    t0 = time.perf_counter()
+    out = rollout(g, prob.props, phi0, u0, sigma, mob, steps, checkpoint_every=20)
+    loss = 0.5 * g.h ** 2 * ((out[0] - target) ** 2).sum()
+    _sync()
+    t1 = time.perf_counter()
+    loss.backward()
+    _sync()
+    t2 = time.perf_counter()
+    return {"workload": "oscillating_drop_128^2_fp64", "steps": steps, "checkpoint_every": 20,
+            "forward_ms": round((t1 - t0) * 1e3, 2), "backward_ms": round((t2 - t1) * 1e3, 2),
+            "adjoint_over_forward": round((t2 - t1) / (t1 - t0), 3),
+            "dL_dsigma": float(sigma.grad), "dL_dM": float(mob.grad)}
 
 
 def cpu_baseline(prob, steps):
@@ -80,6 +179,14 @@ def main():
 
     import paper_2009_06628_amd as P
     import workloads as W
+
+    if args.calibrate_copy:
+        # reference kernel for the HBM byte counters: reads and writes 256 MiB
+        a = torch.empty(32 << 20, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     prob = W.rising_bubble(256, steps=2000)
     g = P.grid_for_problem(prob, device="cuda:0")
@@ -122,6 +229,16 @@ def main():
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         cpu = cpu_baseline(prob, args.cpu_steps)
 
+    secondary = None
+    if not args.no_extras:
+        del g, st
+        torch.cuda.empty_cache()
+        secondary = {"precision_form": bench_precision_form(P, W, args.extra_steps)}
+        torch.cuda.empty_cache()
+        secondary["batched"] = bench_batched(P, W, args.extra_steps)
+        torch.cuda.empty_cache()
+        secondary["adjoint"] = bench_adjoint(P, W)
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4),
@@ -134,6 +251,7 @@ def main():
                    "mass_minus": stats["mass_minus"], "energy": stats["energy"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "secondary": secondary,
     }
     if kernels is not None:
         out["kernels"] = [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),
