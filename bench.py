@@ -61,6 +61,23 @@ def parse():
     return ap.parse_args()
 
 
+def recorded_traffic(kernel_class):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a
+    plain copy of known size); None if the record is for another kernel or the
+    kernel's sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+        if rec.get("kernel_class") != kernel_class:
+            return None
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])).hexdigest()
+        return rec["traffic_bytes_per_launch"] if h == rec["sources_sha256"] else None
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -219,7 +236,7 @@ def main():
         dom = max(kernels, key=lambda r: r["ms"])
         achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": recorded_traffic(dom["name"]),
                 "kernel": dom["name"], "avg_us": round(dom["ms"] * 1e3 / dom["launches"], 3),
                 "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
                 "launches_per_step": round(dom["launches"] / args.profile_steps, 1),
