@@ -71,16 +71,31 @@ __device__ inline int nb_hi(const Geo &g, int c, int ia, int a) {
 // ---------------------------------------------------------------------------
 constexpr int kRedBlocks = 1024;    // blocks of kernels that write partials
 
+// Grids are rounded up to a multiple of the 8 XCDs so that xcd_block()
+// below is a bijection.
 inline int grid_red(long long n) {
     long long b = (n + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
-    return (int)(b > kRedBlocks ? kRedBlocks : b);
+    if (b > kRedBlocks) b = kRedBlocks;
+    if (b > 8) b = (b + 7) & ~7LL;
+    return (int)b;
 }
 
 inline int grid_for(long long n) {
     long long b = (n + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
-    return (int)(b > kMaxBlocks ? kMaxBlocks : b);
+    if (b > kMaxBlocks) b = kMaxBlocks;
+    if (b > 8) b = (b + 7) & ~7LL;
+    return (int)b;
+}
+
+// Logical block index for grid-stride sweeps.  Workgroups are dispatched
+// round-robin over the 8 XCDs, each with its own L2; renumbering them so
+// that XCD k sweeps one contiguous 1/8 of the cells keeps a cell's y / z
+// neighbour rows in the same L2 as the cell.
+__device__ inline int xcd_block() {
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+    return (nb & 7) ? b : (b & 7) * (nb >> 3) + (b >> 3);
 }
 
 // ---------------------------------------------------------------------------

@@ -52,7 +52,7 @@ static int sb_cells() {
 // grid-wide V-cycle kernels (one pass each)
 // ---------------------------------------------------------------------------
 #define GRID_LOOP(N) \
-    for (int c = (int)(blockIdx.x * blockDim.x + threadIdx.x); c < (int)(N); c += (int)(gridDim.x * blockDim.x))
+    for (int c = xcd_block() * (int)blockDim.x + (int)threadIdx.x; c < (int)(N); c += (int)(gridDim.x * blockDim.x))
 
 template <typename T, typename TB, int DIM>
 __global__ void __launch_bounds__(kBlock) k_presmooth(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,

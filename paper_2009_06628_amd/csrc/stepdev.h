@@ -20,7 +20,7 @@ __device__ inline double pullback(double p) { return fabs(p) <= 1.0 ? p : copysi
 __device__ inline double dpullback(double p) { return fabs(p) < 1.0 ? 1.0 : 0.0; }
 
 #define CELL_LOOP(N) \
-    for (int c = (int)(blockIdx.x * blockDim.x + threadIdx.x); c < (int)(N); c += (int)(gridDim.x * blockDim.x))
+    for (int c = xcd_block() * (int)blockDim.x + (int)threadIdx.x; c < (int)(N); c += (int)(gridDim.x * blockDim.x))
 
 template <int DIM>
 __device__ inline void cc(const Geo &g, int c, int &i, int &j, int &k) {
