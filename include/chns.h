@@ -220,14 +220,30 @@ typedef struct {
     double res_ch, res_mom[3], res_p;    /* last step's relative residuals     */
 } chns_batch_stats;
 
+/* Two forms of the batched step:
+ *  CHNS_BATCH_PERSISTENT  one persistent kernel per step; each workgroup
+ *                         takes whole problems (largest first) and runs S1..S9
+ *                         with its solver loops on the device;
+ *  CHNS_BATCH_TILED       one launch per sweep over the cells of all problems,
+ *                         cut into tiles of tile_cells cells (a 256-thread
+ *                         workgroup per tile); per-problem solver scalars, the
+ *                         small multigrid levels one workgroup per problem.  A
+ *                         captured (graph) step launches a fixed number of CG
+ *                         iterations per solve (the budgets); eager steps run
+ *                         every solve to convergence with host checks.       */
+enum { CHNS_BATCH_PERSISTENT = 0, CHNS_BATCH_TILED = 1 };
+
 #define CHNS_MAX_TUNING 16
-/* Autotuner result: the chosen workgroup size (block) and workgroup count
- * (grid) with its time per step, and every candidate that was timed.      */
+/* Autotuner result: the chosen form, its launch shape (persistent: block
+ * threads per workgroup, grid workgroups; tiled: tile_cells) and time per
+ * step, the graph iteration budgets, and every candidate that was timed
+ * (cand_block holds tile_cells for tiled candidates).                     */
 typedef struct {
-    int block, grid;
+    int mode, block, grid, tile_cells;
     double ms_per_step;
+    int budget_ch, budget_mom, budget_p;
     int ncand;
-    int cand_block[CHNS_MAX_TUNING], cand_grid[CHNS_MAX_TUNING];
+    int cand_mode[CHNS_MAX_TUNING], cand_block[CHNS_MAX_TUNING], cand_grid[CHNS_MAX_TUNING];
     double cand_ms[CHNS_MAX_TUNING];
 } chns_batch_tuning;
 
@@ -254,13 +270,22 @@ int chns_batch_offsets(struct chns_batch *b, long long *offsets);
 int chns_batch_step(struct chns_batch *b, const chns_state *packed, int nsteps, int use_graph,
                     chns_batch_stats *stats);
 
-/* Set the launch shape: block = threads per workgroup (64..512, multiple of
- * 64), grid = number of persistent workgroups (>= 1).                      */
+/* Persistent form with block threads per workgroup (64..512, multiple of
+ * 64) and grid persistent workgroups (>= 1).                              */
 int chns_batch_set_launch(struct chns_batch *b, int block, int grid);
 
-/* Time steps_per_trial steps for each candidate launch shape, keep the
- * fastest, and restore the packed state (bitwise) afterwards.  Synchronises.
- * result (host) may be NULL.                                              */
+/* Tiled form with tile_cells cells per tile (multiple of 256; uploads the
+ * tile lists, synchronous).                                               */
+int chns_batch_set_tiled(struct chns_batch *b, int tile_cells);
+
+/* CG iterations a captured tiled step launches per solve (CH, each momentum
+ * component, pressure); a problem that needs more is reported unconverged.
+ * The autotuner sets them from the iterations it observed.               */
+int chns_batch_set_budget(struct chns_batch *b, int iters_ch, int iters_mom, int iters_p);
+
+/* Time steps_per_trial steps for each candidate form and launch shape, keep
+ * the fastest, set the graph budgets, and restore the packed state
+ * (bitwise) afterwards.  Synchronises.  result (host) may be NULL.        */
 int chns_batch_autotune(struct chns_batch *b, const chns_state *packed, int steps_per_trial,
                         chns_batch_tuning *result);
 

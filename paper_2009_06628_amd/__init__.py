@@ -71,9 +71,15 @@ class chns_batch_stats(ctypes.Structure):
 CHNS_MAX_TUNING = 16
 
 
+CHNS_BATCH_PERSISTENT, CHNS_BATCH_TILED = 0, 1
+
+
 class chns_batch_tuning(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int), ("grid", ctypes.c_int), ("ms_per_step", ctypes.c_double),
-                ("ncand", ctypes.c_int), ("cand_block", ctypes.c_int * CHNS_MAX_TUNING),
+    _fields_ = [("mode", ctypes.c_int), ("block", ctypes.c_int), ("grid", ctypes.c_int), ("tile_cells", ctypes.c_int),
+                ("ms_per_step", ctypes.c_double),
+                ("budget_ch", ctypes.c_int), ("budget_mom", ctypes.c_int), ("budget_p", ctypes.c_int),
+                ("ncand", ctypes.c_int), ("cand_mode", ctypes.c_int * CHNS_MAX_TUNING),
+                ("cand_block", ctypes.c_int * CHNS_MAX_TUNING),
                 ("cand_grid", ctypes.c_int * CHNS_MAX_TUNING), ("cand_ms", ctypes.c_double * CHNS_MAX_TUNING)]
 
 
@@ -105,6 +111,8 @@ EXPORTS = {
     "chns_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(chns_batch_stats)]),
     "chns_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "chns_batch_set_tiled": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "chns_batch_set_budget": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "chns_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.c_int,
                                            ctypes.POINTER(chns_batch_tuning)]),
     "chns_destroy_batch": (ctypes.c_int, [ctypes.c_void_p]),
@@ -429,15 +437,26 @@ class Batch:
                  "res_mom": list(s.res_mom)[: self.dim], "res_p": s.res_p} for s in arr]
 
     def set_launch(self, block: int, grid: int) -> None:
+        """Persistent form: block threads per workgroup, grid workgroups."""
         _check(self._lib.chns_batch_set_launch(self._h, int(block), int(grid)), "chns_batch_set_launch")
+
+    def set_tiled(self, tile_cells: int = 1024) -> None:
+        """Tiled form: one launch per sweep over all problems, tile_cells per tile."""
+        _check(self._lib.chns_batch_set_tiled(self._h, int(tile_cells)), "chns_batch_set_tiled")
+
+    def set_budget(self, ch: int, mom: int, p: int) -> None:
+        _check(self._lib.chns_batch_set_budget(self._h, int(ch), int(mom), int(p)), "chns_batch_set_budget")
 
     def autotune(self, st: Dict, steps_per_trial: int = 1) -> Dict:
         cs = self._cstate(st)
         r = chns_batch_tuning()
         _check(self._lib.chns_batch_autotune(self._h, ctypes.byref(cs), int(steps_per_trial), ctypes.byref(r)),
                "chns_batch_autotune")
-        return {"block": r.block, "grid": r.grid, "ms_per_step": r.ms_per_step,
-                "candidates": [(r.cand_block[i], r.cand_grid[i], r.cand_ms[i]) for i in range(r.ncand)]}
+        name = {CHNS_BATCH_PERSISTENT: "persistent", CHNS_BATCH_TILED: "tiled"}
+        return {"mode": name[r.mode], "block": r.block, "grid": r.grid, "tile_cells": r.tile_cells,
+                "ms_per_step": r.ms_per_step, "budgets": (r.budget_ch, r.budget_mom, r.budget_p),
+                "candidates": [(name[r.cand_mode[i]], r.cand_block[i], r.cand_grid[i], r.cand_ms[i])
+                               for i in range(r.ncand)]}
 
 
 def create_batch(problems, precision=CHNS_FP64, device="cuda", stream=None) -> Batch:

@@ -21,34 +21,13 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "mgdev.h"
 #include "plan.h"
 #include "solvers.h"
 #include "stepdev.h"
 
 namespace chns {
-
-// ---------------------------------------------------------------------------
-// device tables
-// ---------------------------------------------------------------------------
-template <typename TP>
-struct BatchProb {
-    Geo g;
-    StepConst k;
-    ChOp ch;
-    double rtol_ch, rtol_mom, rtol_p;
-    int max_iter;
-    long long off;                         // first cell in the packed state arrays
-    double *phi_new, *phihat, *rch, *ustar[3], *rhs;
-    double *r, *p0, *p1, *q, *t;           // CG vectors (FP64)
-    TP *z, *w;                             // preconditioned vector, V-cycle scratch
-    Level<double> op;                      // FP64 level-0 operator of the momentum / pressure solves
-    Slot<TP> chs, mom, pres;               // CH hierarchy; momentum and pressure share arrays
-};
-
-struct BatchState {
-    double *phi, *u[3], *p, *mu;
-};
 
 // Solve outcome inside a workgroup.
 struct PcgRes {
@@ -58,6 +37,7 @@ struct PcgRes {
 };
 
 constexpr int kBatchMaxThreads = 512;
+constexpr int kBatchSBCells = 2048;   // tiled form: levels at or below this run in one workgroup
 
 // r.z (with the singular projection), returned to every thread
 template <typename TP>
@@ -383,26 +363,6 @@ __global__ void k_batch_reset_stats(chns_batch_stats *stats, int n) {
 // ---------------------------------------------------------------------------
 using namespace chns;
 
-struct chns_batch {
-    int count, dim, prec;
-    hipStream_t user_stream, stream;
-    hipEvent_t ev_in, ev_out;
-    void *d_probs;
-    int *d_order;
-    unsigned int *d_queue;
-    chns_batch_stats *d_stats;
-    double *backup;
-    std::vector<long long> offsets;   // count + 1
-    std::vector<int> order;
-    long long total_cells;
-    int block, grid;                  // launch shape
-    // captured graph of the last chns_batch_step call with use_graph
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-    int g_steps, g_block, g_grid;
-    BatchState g_state;
-};
-
 namespace {
 
 #define BHIPCHK(expr)                                                                                         \
@@ -423,12 +383,35 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
     for (int i = 0; i < count; ++i) tot += plans[i].lev[0].N;
     const int dim = plans[0].dim;
     double *backup = B.take<double>((size_t)tot * (3 + dim));
+    // tiled form: per-problem scalars, tile lists (capacity for the smallest
+    // tile), per-tile partial sums
+    Scal *scal = B.take<Scal>((size_t)count);
+    int *active = B.take<int>(64);
+    BTile *tiles[kMaxLev];
+    size_t cap[kMaxLev];
+    for (int l = 0; l < kMaxLev; ++l) {
+        size_t n = 8;
+        for (int i = 0; i < count; ++i)
+            if (l < plans[i].nlev) n += (size_t)((plans[i].lev[l].N + kTileBlock - 1) / kTileBlock);
+        cap[l] = n + 8;
+        tiles[l] = B.take<BTile>(cap[l]);
+    }
+    double *tp0 = B.take<double>(cap[0]), *tp1 = B.take<double>(cap[0]), *tp2 = B.take<double>(cap[0]);
     if (b) {
         b->d_probs = probs;
         b->d_order = order;
         b->d_queue = queue;
         b->d_stats = stats;
         b->backup = backup;
+        b->d_scal = scal;
+        b->d_active = active;
+        for (int l = 0; l < kMaxLev; ++l) {
+            b->d_tiles[l] = tiles[l];
+            b->tile_cap[l] = cap[l];
+        }
+        b->tpart0 = tp0;
+        b->tpart1 = tp1;
+        b->tpart2 = tp2;
     }
     long long off = 0;
     for (int i = 0; i < count; ++i) {
@@ -469,6 +452,12 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
             Q.op.s = B.take<double>(N);
             for (int a = 0; a < 3; ++a) Q.op.cs[a] = a < dim ? B.take<double>(N) : nullptr;
         }
+        Q.sc = scal ? scal + i : nullptr;
+        {
+            int lsb = 0;   // first level with at most kSBCells cells (single-workgroup part)
+            while (lsb < P.nlev - 1 && P.lev[lsb].N > kBatchSBCells) ++lsb;
+            Q.lsb = lsb;
+        }
         if (host) {   // step constants and CH operator are filled in by the caller
             const chns_props &p = props[i];
             Q.rtol_ch = p.rtol_ch;
@@ -508,8 +497,9 @@ void launch_step(chns_batch *b, const BatchState &st, hipStream_t s) {
                        b->d_stats);
 }
 
-void launch_steps(chns_batch *b, const BatchState &st, int nsteps, hipStream_t s) {
+int launch_steps(chns_batch *b, const BatchState &st, int nsteps, hipStream_t s, int graph) {
     hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_stats, b->count);
+    if (b->mode == CHNS_BATCH_TILED) return tiled_steps(b, st, nsteps, graph, s, b->d_stats);
     for (int n = 0; n < nsteps; ++n) {
         if (b->prec == CHNS_FP64) {
             if (b->dim == 2) launch_step<double, 2>(b, st, s); else launch_step<double, 3>(b, st, s);
@@ -517,6 +507,7 @@ void launch_steps(chns_batch *b, const BatchState &st, int nsteps, hipStream_t s
             if (b->dim == 2) launch_step<float, 2>(b, st, s); else launch_step<float, 3>(b, st, s);
         }
     }
+    return CHNS_OK;
 }
 
 void drop_graph(chns_batch *b) {
@@ -548,12 +539,16 @@ int run_steps(chns_batch *b, const BatchState &st, int nsteps, int use_graph) {
     BHIPCHK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
     if (use_graph && nsteps > 0) {
         if (!(b->exec && b->g_steps == nsteps && b->g_block == b->block && b->g_grid == b->grid &&
-              same_state(b->g_state, st))) {
+              b->g_mode == b->mode && b->g_tile == b->tile_cells && same_state(b->g_state, st))) {
             drop_graph(b);
             BHIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            launch_steps(b, st, nsteps, b->stream);
+            const int rc = launch_steps(b, st, nsteps, b->stream, 1);
             hipGraph_t gr = nullptr;
             hipError_t e = hipStreamEndCapture(b->stream, &gr);
+            if (rc) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc;
+            }
             if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
             b->graph = gr;
             e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
@@ -564,11 +559,13 @@ int run_steps(chns_batch *b, const BatchState &st, int nsteps, int use_graph) {
             b->g_steps = nsteps;
             b->g_block = b->block;
             b->g_grid = b->grid;
+            b->g_mode = b->mode;
+            b->g_tile = b->tile_cells;
             b->g_state = st;
         }
         BHIPCHK(hipGraphLaunch(b->exec, b->stream));
     } else {
-        launch_steps(b, st, nsteps, b->stream);
+        if (int rc = launch_steps(b, st, nsteps, b->stream, 0)) return rc;
     }
     BHIPCHK(hipGetLastError());
     BHIPCHK(hipEventRecord(b->ev_out, b->stream));
@@ -624,6 +621,27 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     b->g_steps = -1;
     b->block = 256;
     b->grid = count;
+    b->mode = CHNS_BATCH_PERSISTENT;
+    b->tile_cells = 1024;
+    b->budget[0] = 30;
+    b->budget[1] = 30;
+    b->budget[2] = 60;
+    b->last_iters[0] = b->last_iters[1] = b->last_iters[2] = 0;
+    b->nlev.resize(count);
+    b->lsb.resize(count);
+    b->nlev_max = 0;
+    b->lg = 0;
+    for (int l = 0; l < kMaxLev; ++l) b->ncells[l].assign(count, 0);
+    for (int i = 0; i < count; ++i) {
+        const Plan &P = plans[i];
+        b->nlev[i] = P.nlev;
+        int lsb = 0;
+        while (lsb < P.nlev - 1 && P.lev[lsb].N > kBatchSBCells) ++lsb;
+        b->lsb[i] = lsb;
+        b->nlev_max = std::max(b->nlev_max, P.nlev);
+        b->lg = std::max(b->lg, lsb);
+        for (int l = 0; l < P.nlev; ++l) b->ncells[l][i] = P.lev[l].N;
+    }
     Bump B{(char *)workspace, 0};
     std::vector<char> host_table;
     size_t entry = 0;
@@ -662,7 +680,9 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemcpy(b->d_probs, host_table.data(), entry * count, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->d_order, b->order.data(), sizeof(int) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_scal, 0, sizeof(Scal) * count);
     if (e != hipSuccess) return cleanup(set_error(CHNS_EDEVICE, std::string("batch set-up: ") + hipGetErrorString(e)));
+    if (int rc = tiled_build(b, b->tile_cells)) return cleanup(rc);
     const int ginit = count < 4096 ? count : 4096;
     if (b->prec == CHNS_FP64) {
         if (b->dim == 2)
@@ -717,8 +737,28 @@ int chns_batch_set_launch(chns_batch *b, int block, int grid) {
     if (!b) return set_error(CHNS_EINVAL, "NULL handle");
     if (block < kWave || block > kBatchMaxThreads || block % kWave) return set_error(CHNS_EINVAL, "bad block size");
     if (grid < 1) return set_error(CHNS_EINVAL, "grid must be >= 1");
+    b->mode = CHNS_BATCH_PERSISTENT;
     b->block = block;
     b->grid = grid;
+    return CHNS_OK;
+}
+
+int chns_batch_set_tiled(chns_batch *b, int tile_cells) {
+    if (!b) return set_error(CHNS_EINVAL, "NULL handle");
+    if (tile_cells < kTileBlock || tile_cells % kTileBlock || tile_cells > (1 << 20))
+        return set_error(CHNS_EINVAL, "tile_cells must be a multiple of 256 in [256, 2^20]");
+    if (b->tile_cells != tile_cells)
+        if (int rc = tiled_build(b, tile_cells)) return rc;
+    b->mode = CHNS_BATCH_TILED;
+    return CHNS_OK;
+}
+
+int chns_batch_set_budget(chns_batch *b, int iters_ch, int iters_mom, int iters_p) {
+    if (!b) return set_error(CHNS_EINVAL, "NULL handle");
+    if (iters_ch < 1 || iters_mom < 1 || iters_p < 1) return set_error(CHNS_EINVAL, "budgets must be >= 1");
+    b->budget[0] = iters_ch;
+    b->budget[1] = iters_mom;
+    b->budget[2] = iters_p;
     return CHNS_OK;
 }
 
@@ -727,70 +767,97 @@ int chns_batch_autotune(chns_batch *b, const chns_state *packed, int steps_per_t
     if (steps_per_trial < 1) return set_error(CHNS_EINVAL, "steps_per_trial must be >= 1");
     BatchState st;
     if (int rc = state_of(b, packed, st)) return rc;
-    // candidates: workgroup size x workgroup count
-    const int blocks[3] = {128, 256, 512};
-    std::vector<int> grids;
-    for (int m : {1, 2, 4}) {
-        const int gsz = std::min(b->count, 256 * m);
-        if (std::find(grids.begin(), grids.end(), gsz) == grids.end()) grids.push_back(gsz);
-    }
-    if (std::find(grids.begin(), grids.end(), b->count) == grids.end()) grids.push_back(b->count);
+    // candidates: persistent form (threads per workgroup x workgroups) and
+    // tiled form (cells per tile)
+    struct Cand {
+        int mode, a, g;
+    };
+    std::vector<Cand> cands;
+    for (int bl : {256, 512})
+        for (int gr : {std::min(b->count, 256), b->count}) {
+            bool dup = false;
+            for (const Cand &c : cands) dup |= c.mode == CHNS_BATCH_PERSISTENT && c.a == bl && c.g == gr;
+            if (!dup) cands.push_back({CHNS_BATCH_PERSISTENT, bl, gr});
+        }
+    for (int tc : {512, 1024, 2048, 4096}) cands.push_back({CHNS_BATCH_TILED, tc, 0});
     chns_batch_tuning res;
     memset(&res, 0, sizeof res);
     hipEvent_t e0, e1;
     BHIPCHK(hipEventCreate(&e0));
     BHIPCHK(hipEventCreate(&e1));
-    const int saved_block = b->block, saved_grid = b->grid;
+    const int saved_mode = b->mode, saved_block = b->block, saved_grid = b->grid, saved_tile = b->tile_cells;
     BHIPCHK(hipEventRecord(b->ev_in, b->user_stream));
     BHIPCHK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
     int rc = copy_state(b, st, 1, b->stream);
     double best = 1e300;
-    int first = 1;
-    for (int bl : blocks) {
-        for (int gr : grids) {
-            if (rc) break;
-            if (res.ncand >= CHNS_MAX_TUNING) break;
-            b->block = bl;
-            b->grid = gr;
-            if (first) {   // warm-up (code objects, caches)
-                launch_steps(b, st, 1, b->stream);
-                if ((rc = copy_state(b, st, 0, b->stream))) break;
-                first = 0;
-            }
-            hipEventRecord(e0, b->stream);
-            launch_steps(b, st, steps_per_trial, b->stream);
-            hipEventRecord(e1, b->stream);
-            hipError_t e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                rc = set_error(CHNS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
-                break;
-            }
-            const double per = ms / steps_per_trial;
-            res.cand_block[res.ncand] = bl;
-            res.cand_grid[res.ncand] = gr;
-            res.cand_ms[res.ncand] = per;
-            res.ncand++;
-            if (per < best) {
-                best = per;
-                res.block = bl;
-                res.grid = gr;
-                res.ms_per_step = per;
-            }
-            if ((rc = copy_state(b, st, 0, b->stream))) break;
+    int most[3] = {0, 0, 0};
+    for (const Cand &c : cands) {
+        if (rc || res.ncand >= CHNS_MAX_TUNING) break;
+        if (c.mode == CHNS_BATCH_TILED) {
+            if ((rc = tiled_build(b, c.a))) break;
+            b->mode = CHNS_BATCH_TILED;
+        } else {
+            b->mode = CHNS_BATCH_PERSISTENT;
+            b->block = c.a;
+            b->grid = c.g;
         }
+        // warm-up step (code objects, caches, the tiled form's chunk sizes)
+        if ((rc = launch_steps(b, st, 1, b->stream, 0))) break;
+        if ((rc = copy_state(b, st, 0, b->stream))) break;
+        (void)hipEventRecord(e0, b->stream);
+        if ((rc = launch_steps(b, st, steps_per_trial, b->stream, 0))) break;
+        (void)hipEventRecord(e1, b->stream);
+        hipError_t e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = set_error(CHNS_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            break;
+        }
+        if (c.mode == CHNS_BATCH_TILED)
+            for (int k = 0; k < 3; ++k) most[k] = std::max(most[k], b->last_iters[k]);
+        const double per = ms / steps_per_trial;
+        res.cand_mode[res.ncand] = c.mode;
+        res.cand_block[res.ncand] = c.a;
+        res.cand_grid[res.ncand] = c.g;
+        res.cand_ms[res.ncand] = per;
+        res.ncand++;
+        if (per < best) {
+            best = per;
+            res.mode = c.mode;
+            res.block = c.mode == CHNS_BATCH_TILED ? kTileBlock : c.a;
+            res.grid = c.g;
+            res.tile_cells = c.mode == CHNS_BATCH_TILED ? c.a : 0;
+            res.ms_per_step = per;
+        }
+        if ((rc = copy_state(b, st, 0, b->stream))) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (!rc && hipStreamSynchronize(b->stream) != hipSuccess) rc = set_error(CHNS_EDEVICE, "autotune sync failed");
     if (rc) {
+        b->mode = saved_mode;
         b->block = saved_block;
         b->grid = saved_grid;
+        (void)tiled_build(b, saved_tile);
         return rc;
     }
-    b->block = res.block;
-    b->grid = res.grid;
+    // graph budgets of the tiled form: the most iterations any problem
+    // needed in the trials, with a margin
+    for (int k = 0; k < 3; ++k)
+        if (most[k] > 0) b->budget[k] = most[k] + most[k] / 4 + 2;
+    res.budget_ch = b->budget[0];
+    res.budget_mom = b->budget[1];
+    res.budget_p = b->budget[2];
+    if (res.mode == CHNS_BATCH_TILED) {
+        if ((rc = tiled_build(b, res.tile_cells))) return rc;
+        b->mode = CHNS_BATCH_TILED;
+    } else {
+        if ((rc = tiled_build(b, saved_tile))) return rc;
+        b->mode = CHNS_BATCH_PERSISTENT;
+        b->block = res.block;
+        b->grid = res.grid;
+    }
     drop_graph(b);
     hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, b->stream, b->d_stats,
                        b->count);

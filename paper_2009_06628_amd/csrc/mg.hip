@@ -501,7 +501,7 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
     Level<T> &lv = S.lev[l];
     const int N = (int)lv.g.N, Nc = (int)S.lev[l + 1].g.N;
     const double WB = sizeof(TB) - W;   // extra bytes of a wider right-hand side
-    LAUNCH(K_SMOOTH, W * (2 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
+    LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
     LAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual<T, TB, DIM>), N, st, lv, b, (const T *)x, done);
     LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict<T, DIM>), Nc, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
            S.lev[l + 1].b, done);

@@ -55,19 +55,25 @@ def single_grid_run(prob, steps, precision=0):
     return {"phi": to_np(st["phi"]), "u": [to_np(x) for x in st["u"]], "p": to_np(st["p"])}
 
 
-def batch_run(probs, steps, precision=0, use_graph=False):
+def batch_run(probs, steps, precision=0, use_graph=False, form="persistent"):
     P = _lib()
     b = P.create_batch(probs, precision)
+    if form == "tiled":
+        b.set_tiled(512)
     st = b.new_state([W.initial_state(p) for p in probs])
     stats = b.step(st, steps, use_graph=use_graph)
     torch.cuda.synchronize()
     return b, st, stats
 
 
-def test_batch_matches_single_grid_fp64():
+FORMS = ["persistent", "tiled"]
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_matches_single_grid_fp64(form):
     probs = W.ensemble_stratified(per_size=3, steps=20)
-    print("batch vs single grid:", [p.n[0] for p in probs], flush=True)
-    b, st, stats = batch_run(probs, 20)
+    print("batch (%s) vs single grid:" % form, [p.n[0] for p in probs], flush=True)
+    b, st, stats = batch_run(probs, 20, form=form)
     print("iterations (last step) of the first problem of each size:",
           [(probs[i].n[0], stats[i]["iters_ch"], stats[i]["iters_mom"], stats[i]["iters_p"])
            for i in range(0, len(probs), 3)], flush=True)
@@ -86,44 +92,54 @@ def _oracle(prob, steps):
     return s
 
 
-def test_batch_matches_oracle_2d():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_matches_oracle_2d(form):
     probs = [W.oscillating_drop(16, (0.3, 0.22), 10.0, 5.0, steps=10),
              W.oscillating_drop(24, (0.25, 0.2), 300.0, 30.0, steps=10),
              W.oscillating_drop(32, (0.22, 0.28), 1.0, 1.0, steps=10),
              W.rising_bubble(16, steps=10)]
     probs[3].init_args = dict(probs[3].init_args, velocity="stream", vseed=6, vamp=0.1)
-    print("batch vs oracle 2D:", [p.n for p in probs], flush=True)
-    b, st, stats = batch_run(probs, 10)
+    print("batch (%s) vs oracle 2D:" % form, [p.n for p in probs], flush=True)
+    b, st, stats = batch_run(probs, 10, form=form)
     for i, p in enumerate(probs):
         compare(b.view(st, i), _oracle(p, 10), 2, 1e-9, "problem %d %s" % (i, p.n))
 
 
-def test_batch_matches_oracle_3d():
-    probs = [W.drop3d(16, steps=3), W.drop3d(8, steps=3)]
-    print("batch vs oracle 3D:", [p.n for p in probs], flush=True)
-    b, st, stats = batch_run(probs, 3)
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_matches_oracle_3d(form):
+    probs = [W.drop3d(16, steps=3), W.drop3d(8, steps=3), W.drop3d(32, steps=3)]
+    print("batch (%s) vs oracle 3D:" % form, [p.n for p in probs], flush=True)
+    b, st, stats = batch_run(probs, 3, form=form)
     for i, p in enumerate(probs):
         compare(b.view(st, i), _oracle(p, 3), 3, 1e-9, "problem %d %s" % (i, p.n))
 
 
-def test_batch_precision_form_within_1e5():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_precision_form_within_1e5(form):
     P = _lib()
     probs = W.ensemble_stratified(per_size=3, steps=20, **W.PRECISION_FORM_TOLERANCES)
-    print("batch precision form vs FP64 batch", flush=True)
-    b64, s64, _ = batch_run(probs, 20, P.CHNS_FP64)
-    b32, s32, stats = batch_run(probs, 20, P.CHNS_FP32_REFINE)
+    print("batch (%s) precision form vs FP64 batch" % form, flush=True)
+    b64, s64, _ = batch_run(probs, 20, P.CHNS_FP64, form=form)
+    b32, s32, stats = batch_run(probs, 20, P.CHNS_FP32_REFINE, form=form)
     for i, p in enumerate(probs):
         v = b64.view(s64, i)
         ref = {"phi": to_np(v["phi"]), "u": [to_np(x) for x in v["u"]], "p": to_np(v["p"])}
         compare(b32.view(s32, i), ref, 2, 1e-5, "problem %d (%d^2) fp32+refine" % (i, p.n[0]))
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("form,prec", [("persistent", 0), ("tiled", 0), ("tiled", 1)])
+def test_batch_graph_replays_match_eager(form, prec):
     P = _lib()
-    probs = [W.oscillating_drop(n, (0.25, 0.21), 50.0, 7.0, steps=5) for n in (32, 48, 64, 96, 64, 32)]
+    probs = [W.oscillating_drop(n, (0.25, 0.21), 50.0, 7.0, steps=5) for n in (32, 48, 64, 96, 64, 32, 128)]
+    if prec:
+        probs = [W.oscillating_drop(n, (0.25, 0.21), 50.0, 7.0, steps=5, **W.PRECISION_FORM_TOLERANCES)
+                 for n in (32, 48, 64, 96, 64, 32, 128)]
     inits = [W.initial_state(p) for p in probs]
-    print("graph replay vs eager", flush=True)
-    b = P.create_batch(probs)
+    print("graph replay vs eager", form, prec, flush=True)
+    b = P.create_batch(probs, prec)
+    if form == "tiled":
+        b.set_tiled(1024)
+        b.set_budget(60, 60, 120)
     st = b.new_state(inits)
     b.step(st, 5, use_graph=False)
     eager = {"phi": st["phi"].clone(), "u": [x.clone() for x in st["u"]], "p": st["p"].clone()}
@@ -155,13 +171,16 @@ def test_batch_autotune_restores_state_and_shapes_agree():
     res = b.autotune(st, 1)
     torch.cuda.synchronize()
     print("autotune:", res, flush=True)
-    assert res["block"] in (128, 256, 512) and res["grid"] >= 1 and len(res["candidates"]) >= 3
+    assert res["mode"] in ("persistent", "tiled") and len(res["candidates"]) >= 5
     for k in ("phi", "p"):
         assert torch.equal(st[k], before[k])
     outs = []
-    for block, grid in ((128, 5), (512, 24), (256, 13)):
+    for shape in ((128, 5), (512, 24), (256, 13), ("tiled", 512), ("tiled", 2048)):
         s = b.new_state(inits)
-        b.set_launch(block, grid)
+        if shape[0] == "tiled":
+            b.set_tiled(shape[1])
+        else:
+            b.set_launch(*shape)
         b.step(s, 3)
         outs.append(s)
     for o in outs[1:]:
@@ -169,9 +188,10 @@ def test_batch_autotune_restores_state_and_shapes_agree():
         assert relerr(to_np(o["u"][0]), to_np(outs[0]["u"][0])) <= 1e-9
 
 
-def test_batch_mass_conservation():
+@pytest.mark.parametrize("form", FORMS)
+def test_batch_mass_conservation(form):
     probs = W.ensemble(count=10, seed=5, sizes=(32, 64, 96), steps=20)
-    b, st, stats = batch_run(probs, 20)
+    b, st, stats = batch_run(probs, 20, form=form)
     for i, p in enumerate(probs):
         phi0 = W.initial_state(p)["phi"]
         phi = to_np(b.view(st, i)["phi"])
