@@ -14,7 +14,8 @@ with --no-extras):
                   FP32 multigrid under FP64 refinement, throughput ratio and
                   the state difference after the timed steps
   batched         ensemble of 512 oscillating drops (64^2 .. 256^2), FP32 +
-                  refinement, autotuned launch shape, hipGraph-captured steps
+                  refinement, autotuned form and launch shape; eager steps and
+                  hipGraph-captured steps
   adjoint         oscillating drop 128^2, FP64: backward (checkpoint every 20
                   steps, segment recompute, adjoint steps) vs forward time
 
@@ -113,24 +114,30 @@ def bench_precision_form(P, W, steps):
 
 
 def bench_batched(P, W, steps):
-    """Batched ensemble: 512 problems, FP32 + refinement, graph-captured."""
+    """Batched ensemble: 512 problems, FP32 + refinement; autotuned form and
+    launch shape; timed eagerly (solves run to convergence with host checks)
+    and as a captured hipGraph (fixed per-solve iteration budgets)."""
     probs = W.ensemble(count=512, seed=4, steps=200, **W.PRECISION_FORM_TOLERANCES)
     b = P.create_batch(probs, P.CHNS_FP32_REFINE, device="cuda:0")
     st = b.new_state([W.initial_state(p) for p in probs])
     tune = b.autotune(st, 1)
-    b.step(st, steps, use_graph=True, stats=False)     # capture + first replay (warm-up)
-    _sync()
-    t0 = time.perf_counter()
-    stats = b.step(st, steps, use_graph=True, stats=True)
-    dt = time.perf_counter() - t0
-    tot = sum(s["total_iters"] for s in stats)
-    return {"workload": "ensemble_512_oscillating_drops_fp32_refine", "problems": len(probs),
-            "cells": b.total_cells, "steps": steps, "value": round(b.total_cells * steps / dt, 1),
-            "ms_per_step": round(dt / steps * 1e3, 3), "graph": True,
-            "launch": {"block": tune["block"], "grid": tune["grid"]},
-            "autotune_ms_per_step": {"%dx%d" % (c[0], c[1]): round(c[2], 2) for c in tune["candidates"]},
-            "pcg_iterations_per_problem_step": round(tot / (len(probs) * steps), 2),
-            "unconverged": sum(1 for s in stats if s["flags"])}
+    out = {"workload": "ensemble_512_oscillating_drops_fp32_refine", "problems": len(probs),
+           "cells": b.total_cells, "steps": steps,
+           "form": tune["mode"], "tile_cells": tune["tile_cells"], "graph_budgets": list(tune["budgets"]),
+           "autotune_ms_per_step": {"%s_%d_%d" % (c[0], c[1], c[2]): round(c[3], 2) for c in tune["candidates"]}}
+    for label, graph in (("eager", False), ("graph", True)):
+        b.step(st, steps, use_graph=graph, stats=False)     # warm-up (and capture)
+        _sync()
+        t0 = time.perf_counter()
+        stats = b.step(st, steps, use_graph=graph, stats=True)
+        dt = time.perf_counter() - t0
+        tot = sum(s["total_iters"] for s in stats)
+        out[label] = {"value": round(b.total_cells * steps / dt, 1), "ms_per_step": round(dt / steps * 1e3, 3),
+                      "pcg_iterations_per_problem_step": round(tot / (len(probs) * steps), 2),
+                      "unconverged": sum(1 for s in stats if s["flags"])}
+    out["value"] = out["graph"]["value"]
+    out["ms_per_step"] = out["graph"]["ms_per_step"]
+    return out
 
 
 def bench_adjoint(P, W):

@@ -77,7 +77,9 @@ struct chns_batch {
     chns::Scal *d_scal;
     int *d_active;                    // number of problems whose current solve is not done
     int budget[3];                    // graph mode: PCG iterations launched per solve (CH, momentum, pressure)
+    int rbudget[3];                   // graph mode, FP32 hierarchy: iterations of the one refinement round
     int last_iters[3];                // eager mode: most iterations any problem needed, last step
+    int last_refine[3];               // eager mode: most iterations in refinement rounds, last step
 };
 
 

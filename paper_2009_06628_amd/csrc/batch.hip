@@ -626,7 +626,10 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     b->budget[0] = 30;
     b->budget[1] = 30;
     b->budget[2] = 60;
-    b->last_iters[0] = b->last_iters[1] = b->last_iters[2] = 0;
+    for (int k = 0; k < 3; ++k) {
+        b->rbudget[k] = 8;
+        b->last_iters[k] = b->last_refine[k] = 0;
+    }
     b->nlev.resize(count);
     b->lsb.resize(count);
     b->nlev_max = 0;
@@ -790,7 +793,7 @@ int chns_batch_autotune(chns_batch *b, const chns_state *packed, int steps_per_t
     BHIPCHK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
     int rc = copy_state(b, st, 1, b->stream);
     double best = 1e300;
-    int most[3] = {0, 0, 0};
+    int most[3] = {0, 0, 0}, most_r[3] = {0, 0, 0};
     for (const Cand &c : cands) {
         if (rc || res.ncand >= CHNS_MAX_TUNING) break;
         if (c.mode == CHNS_BATCH_TILED) {
@@ -815,7 +818,10 @@ int chns_batch_autotune(chns_batch *b, const chns_state *packed, int steps_per_t
             break;
         }
         if (c.mode == CHNS_BATCH_TILED)
-            for (int k = 0; k < 3; ++k) most[k] = std::max(most[k], b->last_iters[k]);
+            for (int k = 0; k < 3; ++k) {
+                most[k] = std::max(most[k], b->last_iters[k]);
+                most_r[k] = std::max(most_r[k], b->last_refine[k]);
+            }
         const double per = ms / steps_per_trial;
         res.cand_mode[res.ncand] = c.mode;
         res.cand_block[res.ncand] = c.a;
@@ -843,9 +849,12 @@ int chns_batch_autotune(chns_batch *b, const chns_state *packed, int steps_per_t
         return rc;
     }
     // graph budgets of the tiled form: the most iterations any problem
-    // needed in the trials, with a margin
+    // needed in the trials (eager steps), plus a margin of 2
     for (int k = 0; k < 3; ++k)
-        if (most[k] > 0) b->budget[k] = most[k] + most[k] / 4 + 2;
+        if (most[k] > 0) {
+            b->budget[k] = most[k] + 2;
+            b->rbudget[k] = most_r[k] > 0 ? most_r[k] + 1 : 0;
+        }
     res.budget_ch = b->budget[0];
     res.budget_mom = b->budget[1];
     res.budget_p = b->budget[2];

@@ -678,13 +678,19 @@ struct Tiled {
         return CHNS_OK;
     }
     // One solve for every problem.  The iteration count of a problem runs on
-    // across refinement rounds (fin_init does not reset it).
+    // across refinement rounds (fin_init does not reset it).  Eager: rounds
+    // continue while the true residual of any problem misses the tolerance,
+    // iterations while any problem is active (host check per chunk).
+    // Graph: round 0 launches budget iterations and, with an FP32 hierarchy,
+    // one refinement round launches rbudget more (after its true-residual
+    // check); problems that converge earlier skip the remaining launches.
     int solve(int sv, chns_batch_stats *stats) {
-        const int kind_budget = sv == TS_CH ? 0 : (sv == TS_P ? 2 : 1);
-        const int rounds = sizeof(TP) < sizeof(double) ? kMaxRefine : 1;
+        const int kb = sv == TS_CH ? 0 : (sv == TS_P ? 2 : 1);
+        const bool fp32 = sizeof(TP) < sizeof(double);
+        const int rounds = graph ? (fp32 ? 2 : 1) : (fp32 ? kMaxRefine : 1);
         const int gb = (np() + 255) / 256;
         hipLaunchKernelGGL((k_t_solve_begin<TP>), dim3(gb), dim3(256), 0, s, probs(), np());
-        int most = 0;
+        int most0 = 0, most1 = 0;
         for (int round = 0; round < rounds; ++round) {
             if (sv == TS_CH)
                 hipLaunchKernelGGL((k_t_ch_lap_x<TP, DIM>), dim3(nt(0)), dim3(kTileBlock), 0, s, probs(), tl(0), nt(0),
@@ -693,6 +699,8 @@ struct Tiled {
                                sv, b->tpart0, b->tpart1);
             hipLaunchKernelGGL((k_t_fin_init<TP>), dim3(np()), dim3(kTileBlock), 0, s, probs(), sv,
                                (const double *)b->tpart0, (const double *)b->tpart1);
+            const int cap = graph ? (round == 0 ? b->budget[kb] : b->rbudget[kb]) : 1 << 30;
+            if (graph && cap <= 0) continue;
             int n = 1;
             if (!graph) {
                 if (int rc = active(n)) return rc;
@@ -701,23 +709,25 @@ struct Tiled {
             precond(sv);
             rz(sv, 1);
             int launched = 0;
-            const int cap = graph ? (round == 0 ? b->budget[kind_budget] : std::max(2, b->budget[kind_budget] / 4))
-                                  : 1 << 30;
-            int chunk = std::max(1, b->last_iters[kind_budget] > 0 ? b->last_iters[kind_budget] : 4);
+            int chunk = round == 0 ? std::max(1, b->last_iters[kb] > 0 ? b->last_iters[kb] : 4) : 2;
             for (;;) {
-                const int todo = graph ? cap : std::min(chunk, 100000);
+                const int todo = graph ? cap : chunk;
                 for (int it = 0; it < todo; ++it) iteration(sv, launched + it);
                 launched += todo;
                 if (graph) break;
                 if (int rc = active(n)) return rc;
-                if (n == 0) break;
+                if (n == 0 || launched > 100000) break;
                 chunk = 2;
-                if (launched > 100000) break;
             }
-            most = std::max(most, launched);
-            if (graph && round == 0 && sizeof(TP) == sizeof(double)) break;
+            if (round == 0)
+                most0 = launched;
+            else
+                most1 += launched;
         }
-        if (!graph) b->last_iters[kind_budget] = std::max(1, most);
+        if (!graph) {
+            b->last_iters[kb] = std::max(1, most0);
+            b->last_refine[kb] = most1;
+        }
         hipLaunchKernelGGL((k_t_record<TP>), dim3(gb), dim3(256), 0, s, probs(), np(), sv, stats);
         return CHNS_OK;
     }
