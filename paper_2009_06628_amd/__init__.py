@@ -134,6 +134,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _LIB
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built: run `python -m paper_2009_06628_amd.build`")
+    # torch first: its HIP runtime must be the one libchns.so binds to (a
+    # library loaded before torch would bring up a second runtime instance
+    # that sees no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)
