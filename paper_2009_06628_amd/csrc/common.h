@@ -245,16 +245,17 @@ const char *kclass_name(int cls);
 // In timing mode the start / stop events are recorded by the dispatch itself
 // (hipExtLaunchKernelGGL), so their difference is the kernel's execution time
 // without the gaps between launches.
-#define TLAUNCH(cls, bytes, kern, grid, block, st, ...)                                   \
+#define TLAUNCHS(cls, bytes, kern, grid, block, shm, st, ...)                             \
     do {                                                                                  \
         if (chns::g_prof) {                                                               \
             hipEvent_t e0_, e1_;                                                          \
             chns::prof_slot((cls), (double)(bytes), &e0_, &e1_);                          \
-            hipExtLaunchKernelGGL(kern, grid, block, 0, st, e0_, e1_, 0, __VA_ARGS__);    \
+            hipExtLaunchKernelGGL(kern, grid, block, shm, st, e0_, e1_, 0, __VA_ARGS__);  \
         } else {                                                                          \
-            hipLaunchKernelGGL(kern, grid, block, 0, st, __VA_ARGS__);                    \
+            hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);                  \
         }                                                                                 \
     } while (0)
+#define TLAUNCH(cls, bytes, kern, grid, block, st, ...) TLAUNCHS(cls, bytes, kern, grid, block, 0, st, __VA_ARGS__)
 
 // ---------------------------------------------------------------------------
 // device buffers of the discrete adjoint (carved from the adjoint workspace)

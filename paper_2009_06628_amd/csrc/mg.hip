@@ -121,6 +121,25 @@ __global__ void __launch_bounds__(kSBThreads) k_vcycle_block(Slot<T> S, int l0, 
     vcycle_block_dev<T, TB, DIM>(S, l0, b0, x0);
 }
 
+// Levels [l0, nlev) out of LDS: n16 16-byte words (plus tail8 trailing 8
+// bytes) of their contiguous storage are copied in, x of level l0 is written
+// back.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kSBThreads) k_vcycle_lds(Slot<T> S, int l0, int n16, int tail8,
+                                                           const int *__restrict__ done) {
+    if (*done) return;
+    extern __shared__ uint4 lds_words[];
+    char *lds = (char *)lds_words;
+    const char *base = (const char *)S.lev[l0].s;
+    copy_to_lds(lds_words, (const uint4 *)base, n16);
+    if (tail8 && threadIdx.x == 0) *(double *)(lds + 16 * (size_t)n16) = *(const double *)(base + 16 * (size_t)n16);
+    __syncthreads();
+    vcycle_lds_dev<T, DIM>(S, l0, lds, base);
+    const T *xl = lds_image(lds, base, S.lev[l0].x);
+    T *xg = S.lev[l0].x;
+    LDS_LOOP(S.lev[l0].g.N) xg[c] = xl[c];
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kSBThreads) k_setup_block(Slot<T> S, int l0) {
     __shared__ SetupLds sh;
@@ -537,13 +556,31 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
         for (int l = 1; l < lsb; ++l) vcycle_down<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
     }
     {
-        double bytes = 8.0 * S.ncoarse * S.ncoarse;
-        for (int l = lsb; l < S.nlev; ++l) bytes += W * 12.0 * S.lev[l].g.N;
-        if (lsb == 0)
-            LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, TB, DIM>), kSBThreads, st, S, 0, b0, x0, done);
-        else
-            LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, T, DIM>), kSBThreads, st, S, lsb,
-                    (const T *)S.lev[lsb].b, S.lev[lsb].x, done);
+        // storage of the small levels: one contiguous range from lev[lsb].s
+        // to the end of the coarsest inverse
+        const size_t range = lsb > 0 ? (size_t)((const char *)(S.Ainv + (size_t)S.ncoarse * S.ncoarse) -
+                                                (const char *)S.lev[lsb].s)
+                                     : 0;
+        if (lsb > 0 && range <= (size_t)kLdsVcycleBytes) {
+            // the range is read once and x of level lsb written back
+            static bool attr = false;
+            if (!attr) {
+                (void)hipFuncSetAttribute((const void *)k_vcycle_lds<T, DIM>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, kLdsVcycleBytes);
+                attr = true;
+            }
+            const double bytes = (double)range + W * S.lev[lsb].g.N;
+            TLAUNCHS(K_COARSE_SOLVE, bytes, (k_vcycle_lds<T, DIM>), dim3(1), dim3(kSBThreads), range, st, S, lsb,
+                     (int)(range / 16), (int)((range % 16) != 0), done);
+        } else {
+            double bytes = 8.0 * S.ncoarse * S.ncoarse;
+            for (int l = lsb; l < S.nlev; ++l) bytes += W * 12.0 * S.lev[l].g.N;
+            if (lsb == 0)
+                LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, TB, DIM>), kSBThreads, st, S, 0, b0, x0, done);
+            else
+                LAUNCH1(K_COARSE_SOLVE, bytes, (k_vcycle_block<T, T, DIM>), kSBThreads, st, S, lsb,
+                        (const T *)S.lev[lsb].b, S.lev[lsb].x, done);
+        }
     }
     if (lsb > 0) {
         for (int l = lsb - 1; l >= 1; --l) vcycle_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);

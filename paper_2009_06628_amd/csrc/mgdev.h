@@ -336,6 +336,166 @@ __device__ inline void vcycle_block_dev(const Slot<T> &S, int l0, const TB *__re
     block_up<T, TB, DIM>(S, l0, b0, x0);
 }
 
+// ---------------------------------------------------------------------------
+// LDS-resident V-cycle of the small levels
+// ---------------------------------------------------------------------------
+// The storage of levels [l0, nlev) of a slot is one contiguous range of the
+// workspace (per level s, cs, invd, r, x, b, then the coarsest inverse).  A
+// one-workgroup launch may land on an XCD whose L2 holds none of it, so the
+// global-memory form pays several dependent memory round trips in every
+// sweep.  Here the workgroup copies the whole range into LDS in one round of
+// independent 16-byte loads, runs every sweep out of LDS with the same
+// per-cell code, and writes back x of level l0.
+constexpr int kLdsCopyUnroll = 10;                  // 16-byte loads in flight per thread
+constexpr int kLdsVcycleBytes = 160 * 1024;         // LDS of one workgroup on gfx950
+
+// The LDS kernel always runs kSBThreads threads; a compile-time stride keeps
+// the loops from reading the workgroup size from the dispatch arguments.
+#define LDS_LOOP(N) for (int c = (int)threadIdx.x; c < (int)(N); c += kSBThreads)
+
+// Copy n16 >= 1 16-byte words: every load of a round is issued before its
+// stores.  Indices past the end are clamped to the last word, which is then
+// stored again with its own value, so no load or store is conditional.
+__device__ inline void copy_to_lds(uint4 *dst, const uint4 *src, int n16) {
+    for (int base = 0; base < n16; base += kLdsCopyUnroll * kSBThreads) {
+        uint4 v[kLdsCopyUnroll];
+#pragma unroll
+        for (int k = 0; k < kLdsCopyUnroll; ++k) {
+            const int i = base + k * kSBThreads + (int)threadIdx.x;
+            v[k] = src[i < n16 ? i : n16 - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kLdsCopyUnroll; ++k) {
+            const int i = base + k * kSBThreads + (int)threadIdx.x;
+            dst[i < n16 ? i : n16 - 1] = v[k];
+        }
+    }
+}
+
+// The LDS image of a workspace pointer p of the copied range starting at base.
+template <typename T>
+__device__ inline T *lds_image(char *lds, const char *base, const T *p) {
+    return (T *)(lds + (unsigned)((const char *)p - base));
+}
+
+template <typename T, int DIM>
+__device__ inline Level<T> lds_level(const Level<T> &G, char *lds, const char *base) {
+    Level<T> L;
+    L.g = G.g;
+    L.s = lds_image(lds, base, G.s);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) L.cs[b] = b < DIM ? lds_image(lds, base, G.cs[b]) : L.s;
+    L.invd = lds_image(lds, base, G.invd);
+    L.r = lds_image(lds, base, G.r);
+    L.x = lds_image(lds, base, G.x);
+    L.b = lds_image(lds, base, G.b);
+    return L;
+}
+
+// k-th cell of colour col ((i + j + k) & 1) of a level whose x extent is
+// even (every level above the coarsest); its coordinates go to ia.
+template <int DIM>
+__device__ inline int color_cell(const Geo &g, int k, int col, int ia[3]) {
+    const int hx = (int)g.n[0] >> 1;
+    const int row = k / hx;   // y + ny z
+    const int m = k - row * hx;
+    int y = row, z = 0;
+    if (DIM == 3) {
+        z = row / (int)g.n[1];
+        y = row - z * (int)g.n[1];
+    }
+    ia[0] = 2 * m + ((y + z + col) & 1);
+    ia[1] = y;
+    ia[2] = z;
+    return ia[0] + (int)g.n[0] * row;
+}
+
+#define LDS_COLOR_LOOP(N) for (int k = (int)threadIdx.x; k < (int)(N) / 2; k += kSBThreads)
+
+// Gauss-Seidel update of cell c from its neighbours' current x
+template <typename T, int DIM>
+__device__ inline void gs_at(const Level<T> &L, int c, const int ia[3]) {
+    using R = T;
+    auto xv = [&](int e) { return (R)L.x[e]; };
+    L.x[c] = (T)(((R)L.b[c] + offsum_at<T, DIM>(L, c, ia, xv)) * (R)L.invd[c]);
+}
+
+// V-cycle over levels [l0, nlev), l0 >= 1, on the LDS image of their
+// storage.  The arithmetic is that of vcycle_block_dev, but with LDS
+// barriers being cheap the fused passes are split by colour so that no
+// value is recomputed and no wave runs both colours' branches:
+//   pre-smoothing  red x = b / d | black GS   (the black update reads the
+//                  stored red values, which equal the b / d products the
+//                  fused pass recomputes)
+//   post-smoothing red x += P e | black GS | red GS
+// Ends with a workgroup barrier.
+template <typename T, int DIM>
+__device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
+    using R = T;
+    const int L = S.nlev;
+    for (int l = l0; l < L - 1; ++l) {
+        const Level<T> lv = lds_level<T, DIM>(S.lev[l], lds, base);
+        const Level<T> lc = lds_level<T, DIM>(S.lev[l + 1], lds, base);
+        LDS_COLOR_LOOP(lv.g.N) {
+            int ia[3];
+            const int c = color_cell<DIM>(lv.g, k, 0, ia);
+            lv.x[c] = (T)((R)lv.b[c] * (R)lv.invd[c]);
+        }
+        __syncthreads();
+        LDS_COLOR_LOOP(lv.g.N) {
+            int ia[3];
+            const int c = color_cell<DIM>(lv.g, k, 1, ia);
+            gs_at<T, DIM>(lv, c, ia);
+        }
+        __syncthreads();
+        LDS_LOOP(lv.g.N) residual_cell<T, T, DIM>(lv, lv.b, lv.x, c);
+        __syncthreads();
+        LDS_LOOP(lc.g.N) restrict_cell<T, DIM>(lv.g, lc.g, lv.r, lc.b, c);
+        __syncthreads();
+    }
+    {
+        // x = Ainv b on the coarsest level (FP64 inverse); thread i walks row
+        // i from column i on, so that the lanes of a wave read different LDS
+        // banks
+        const Level<T> lc = lds_level<T, DIM>(S.lev[L - 1], lds, base);
+        const double *Ainv = lds_image(lds, base, S.Ainv);
+        const int n = (int)lc.g.N;
+        LDS_LOOP(n) {
+            double v = 0.0;
+            const double *row = Ainv + c * n;
+            int j = c;
+            for (int t = 0; t < n; ++t) {
+                v += row[j] * (double)lc.b[j];
+                j = j + 1 == n ? 0 : j + 1;
+            }
+            lc.x[c] = (T)v;
+        }
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= l0; --l) {
+        const Level<T> lv = lds_level<T, DIM>(S.lev[l], lds, base);
+        const Level<T> lc = lds_level<T, DIM>(S.lev[l + 1], lds, base);
+        LDS_COLOR_LOOP(lv.g.N) {
+            int ia[3];
+            const int c = color_cell<DIM>(lv.g, k, 0, ia);
+            lv.x[c] = (T)((R)lv.x[c] + prolong_at<T, DIM>(lv.g, lc.g, lc.x, ia));
+        }
+        __syncthreads();
+        LDS_COLOR_LOOP(lv.g.N) {
+            int ia[3];
+            const int c = color_cell<DIM>(lv.g, k, 1, ia);
+            gs_at<T, DIM>(lv, c, ia);
+        }
+        __syncthreads();
+        LDS_COLOR_LOOP(lv.g.N) {
+            int ia[3];
+            const int c = color_cell<DIM>(lv.g, k, 0, ia);
+            gs_at<T, DIM>(lv, c, ia);
+        }
+        __syncthreads();
+    }
+}
+
 // In-place Gauss-Jordan inversion of the n x n SPD matrix held in A (no
 // pivoting), block-wide; f is a scratch row of n doubles.
 __device__ inline void gauss_jordan_inplace(double *A, int n, double *f, double *piv) {
