@@ -26,7 +26,8 @@ thread_local Prof *g_prof = nullptr;
 static const char *kNames[K_NCLASS] = {"ch_rhs",   "mu",          "phi_update",   "mom_setup", "p_setup",
                                        "project",  "smooth",      "residual",     "restrict",  "prolong",
                                        "coarse_solve", "mg_setup", "pcg_apply",   "pcg_update", "pcg_dot",
-                                       "pcg_init", "mean",        "diag",        "adjoint"};
+                                       "pcg_init", "mean",        "diag",        "adjoint",   "mg_down",
+                                       "mg_up"};
 
 const char *kclass_name(int c) { return (c >= 0 && c < K_NCLASS) ? kNames[c] : "?"; }
 

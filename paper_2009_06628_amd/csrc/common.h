@@ -219,7 +219,7 @@ struct Red {
 enum KClass {
     K_CH_RHS = 0, K_MU, K_PHI_UPDATE, K_MOM_SETUP, K_P_SETUP, K_PROJECT,
     K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE, K_MG_SETUP,
-    K_PCG_APPLY, K_PCG_UPDATE, K_PCG_DOT, K_PCG_INIT, K_MEAN, K_DIAG, K_ADJOINT,
+    K_PCG_APPLY, K_PCG_UPDATE, K_PCG_DOT, K_PCG_INIT, K_MEAN, K_DIAG, K_ADJOINT, K_MG_DOWN, K_MG_UP,
     K_NCLASS
 };
 
