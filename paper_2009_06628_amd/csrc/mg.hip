@@ -104,6 +104,135 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gf, Geo gc, const T 
     }
 }
 
+// Two consecutive values along x (the pair starts at an even index).
+template <typename T>
+struct Pair2 {
+    T v[2];
+};
+
+// 3D prolongation x += P e, one thread per coarse cell: the 3 x 3 x 3 coarse
+// neighbourhood (parent, lower and upper side neighbour per axis, from
+// pro_axis) is loaded once and the eight children are updated with the taps,
+// weights and summation order of prolong_at.  Needs an even fine x extent.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_add3(Geo gf, Geo gc, const T *__restrict__ xc,
+                                                         T *__restrict__ x, const int *__restrict__ done) {
+    if (*done) return;
+    using R = T;
+    GRID_LOOP(gc.N) {
+        int I[3];
+        coords_of<3>(gc, c, I);
+        int q[3][3];   // [axis][0: parent, 1: lower child's neighbour, 2: upper child's neighbour]
+        R w0[3][2], w1[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            q[a][0] = I[a];
+#pragma unroll
+            for (int sd = 0; sd < 2; ++sd) {
+                int c0, c1;
+                pro_axis<R>(2 * I[a] + sd, (int)gc.n[a], gc.per[a], c0, c1, w0[a][sd], w1[a][sd]);
+                q[a][1 + sd] = c1;
+            }
+        }
+        const int nx = (int)gc.n[0], nxy = nx * (int)gc.n[1];
+        R X[3][3][3];
+#pragma unroll
+        for (int z = 0; z < 3; ++z)
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+#pragma unroll
+                for (int xx = 0; xx < 3; ++xx) X[z][y][xx] = (R)xc[q[2][z] * nxy + q[1][y] * nx + q[0][xx]];
+        const int fnx = (int)gf.n[0], fnxy = fnx * (int)gf.n[1];
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const int f = 2 * I[0] + fnx * (2 * I[1] + dy) + fnxy * (2 * I[2] + dz);
+                Pair2<T> pr = *(const Pair2<T> *)(x + f);
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) {
+                    R v = 0.0;
+#pragma unroll
+                    for (int dz2 = 0; dz2 < 2; ++dz2) {
+                        const R wz = dz2 ? w1[2][dz] : w0[2][dz];
+                        const int zi = dz2 ? 1 + dz : 0;
+#pragma unroll
+                        for (int dy2 = 0; dy2 < 2; ++dy2) {
+                            const R wyz = wz * (dy2 ? w1[1][dy] : w0[1][dy]);
+                            const int yi = dy2 ? 1 + dy : 0;
+                            v += wyz * (w0[0][dx] * X[zi][yi][0] + w1[0][dx] * X[zi][yi][1 + dx]);
+                        }
+                    }
+                    pr.v[dx] = (T)((T)pr.v[dx] + v);
+                }
+                *(Pair2<T> *)(x + f) = pr;
+            }
+    }
+}
+
+// 3D restriction, one thread per two x-adjacent coarse cells (I even): each
+// fine row is read as four aligned pairs covering the taps 2I-1 .. 2I+4 of
+// both cells; the weights and summation order are those of restrict_cell.
+// Needs an even coarse x extent.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict3_pair(Geo gf, Geo gc, const T *__restrict__ rf,
+                                                           T *__restrict__ bc, const int *__restrict__ done) {
+    if (*done) return;
+    using R = T;
+    GRID_LOOP(gc.N / 2) {
+        int I[3];
+        coords_of<3>(gc, 2 * c, I);
+        int fx[2][4], fy[4], fz[4];
+        R wx[2][4], wy[4], wz[4];
+        res_axis<R>(I[0], (int)gc.n[0], (int)gf.n[0], gc.per[0], fx[0], wx[0]);
+        res_axis<R>(I[0] + 1, (int)gc.n[0], (int)gf.n[0], gc.per[0], fx[1], wx[1]);
+        res_axis<R>(I[1], (int)gc.n[1], (int)gf.n[1], gc.per[1], fy, wy);
+        res_axis<R>(I[2], (int)gc.n[2], (int)gf.n[2], gc.per[2], fz, wz);
+        // pair starts 2I-2, 2I, 2I+2, 2I+4 (wrapped on a periodic axis; an
+        // out-of-range pair outside a wall only feeds taps of weight 0 and
+        // is read from the nearest pair in range)
+        const int nfx = (int)gf.n[0];
+        int p0[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int st = 2 * I[0] - 2 + 2 * k;
+            if (gc.per[0])
+                st = st < 0 ? st + nfx : (st >= nfx ? st - nfx : st);
+            else
+                st = st < 0 ? 0 : (st >= nfx ? nfx - 2 : st);
+            p0[k] = st;
+        }
+        const int nxy = nfx * (int)gf.n[1];
+        R v0 = 0.0, v1 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int kz = fz[a] * nxy;
+            const R wza = wz[a];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int row = kz + fy[qq] * nfx;
+                R t[8];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const Pair2<T> pr = *(const Pair2<T> *)(rf + row + p0[k]);
+                    t[2 * k] = (R)pr.v[0];
+                    t[2 * k + 1] = (R)pr.v[1];
+                }
+                // t[j] holds fine 2I-2+j: cell I taps j = 1..4, cell I+1 taps j = 3..6
+                R s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s0 += wx[0][e] * t[1 + e];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s1 += wx[1][e] * t[3 + e];
+                v0 += (wy[qq] * wza) * s0;
+                v1 += (wy[qq] * wza) * s1;
+            }
+        }
+        bc[2 * c] = (T)v0;
+        bc[2 * c + 1] = (T)v1;
+    }
+}
+
 template <typename T, typename TB, int DIM>
 __global__ void __launch_bounds__(kBlock) k_gs_color(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,
                                                      int color, const int *__restrict__ done) {
@@ -714,8 +843,12 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
     const double WB = sizeof(TB) - W;   // extra bytes of a wider right-hand side
     LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
     LAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual<T, TB, DIM>), N, st, lv, b, (const T *)x, done);
-    LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict<T, DIM>), Nc, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
-           S.lev[l + 1].b, done);
+    if (DIM == 3 && (S.lev[l + 1].g.n[0] & 1) == 0)
+        LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict3_pair<T>), Nc / 2, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
+               S.lev[l + 1].b, done);
+    else
+        LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict<T, DIM>), Nc, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
+               S.lev[l + 1].b, done);
 }
 
 template <typename T, typename TB, int DIM>
@@ -733,7 +866,8 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
     }
     const double WB = sizeof(TB) - W;
     if (DIM == 3) {
-        LAUNCH(K_PROLONG, W * (2 * N + Nc), (k_prolong_add<T, DIM>), N, st, lv.g, S.lev[l + 1].g,
+        // one thread per coarse cell (fine x extent is even on every level above the coarsest)
+        LAUNCH(K_PROLONG, W * (2 * N + Nc), (k_prolong_add3<T>), Nc, st, lv.g, S.lev[l + 1].g,
                (const T *)S.lev[l + 1].x, x, done);
         LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 1, done);
         LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 0, done);

@@ -92,7 +92,8 @@ def test_pressure_operator_matches_oracle(n, per):
     assert relerr(to_np(y), ref) <= 1e-14
 
 
-@pytest.mark.parametrize("n,per", [((64, 128), (True, False)), ((96, 96), (True, True)), ((32, 16, 24), (True, True, False))])
+@pytest.mark.parametrize("n,per", [((64, 128), (True, False)), ((96, 96), (True, True)), ((80, 48), (False, False)),
+                                   ((96, 40), (False, True)), ((32, 16, 24), (True, True, False))])
 def test_solve_pressure_matches_oracle(n, per):
     P = _lib()
     rng = np.random.default_rng(11)
