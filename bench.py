@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=20)
+    ap.add_argument("--extras", default="precision_form,batched,adjoint",
+                    help="comma-separated secondary measurements to run (subset of the default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -254,14 +256,21 @@ def main():
         cpu = cpu_baseline(prob, args.cpu_steps)
 
     secondary = None
-    if not args.no_extras:
+    extras = [e for e in args.extras.split(",") if e] if not args.no_extras else []
+    unknown = set(extras) - {"precision_form", "batched", "adjoint"}
+    if unknown:
+        print("unknown --extras entries: %s" % ", ".join(sorted(unknown)), file=sys.stderr)
+        sys.exit(2)
+    if extras:
         del g, st
-        torch.cuda.empty_cache()
-        secondary = {"precision_form": bench_precision_form(P, W, args.extra_steps)}
-        torch.cuda.empty_cache()
-        secondary["batched"] = bench_batched(P, W, args.extra_steps)
-        torch.cuda.empty_cache()
-        secondary["adjoint"] = bench_adjoint(P, W)
+        secondary = {}
+        runs = {"precision_form": lambda: bench_precision_form(P, W, args.extra_steps),
+                "batched": lambda: bench_batched(P, W, args.extra_steps),
+                "adjoint": lambda: bench_adjoint(P, W)}
+        for name in ("precision_form", "batched", "adjoint"):
+            if name in extras:
+                torch.cuda.empty_cache()
+                secondary[name] = runs[name]()
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1,
