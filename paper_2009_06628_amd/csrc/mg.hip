@@ -16,11 +16,15 @@
 //   * coarsest       explicit FP64 inverse (Gauss-Jordan in one workgroup)
 //                    with a rank-one shift tau 1 1^T for the singular
 //                    pressure operator.
-// Launch structure: levels with more than kSBCells cells use one grid-wide
-// kernel per pass (5 per level: fused zero-guess pre-smoothing, residual,
-// restriction, fused prolongation + black sweep, red sweep); all smaller
-// levels run inside ONE single-workgroup kernel, which removes the launch
-// latency that otherwise dominates the coarse levels.
+// Launch structure (a launch costs a few microseconds whatever its size):
+//   * 2D levels above kSBCells cells: two tile kernels per level, one for
+//     the way down (pre-smoothing, residual, restriction) and one for the
+//     way up (prolongation, black sweep, red sweep), on LDS tiles with halos;
+//   * 3D levels above kSBCells cells: one grid-wide kernel per pass (fused
+//     zero-guess pre-smoothing, residual, restriction, prolongation, black
+//     sweep, red sweep);
+//   * all smaller levels: ONE single-workgroup kernel that copies their
+//     storage into LDS and runs every sweep there.
 // Reductions are deterministic and fence-free: per-block partials from a
 // fixed grid-stride partition, summed in a fixed order either by a
 // one-workgroup finalize kernel or redundantly by every block of the kernel
