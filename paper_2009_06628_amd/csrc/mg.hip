@@ -275,28 +275,51 @@ template <typename T, typename TB>
 __global__ void __launch_bounds__(kTileThreads) k_down_tile2(Level<T> L, Geo gc, const TB *__restrict__ b,
                                                              T *__restrict__ xs, T *__restrict__ bc, int ntx,
                                                              int ntiles, const int *__restrict__ done) {
-    if (*done) return;
     using R = T;
     constexpr int H = 3, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
+    constexpr int KL = (NL + kTileThreads - 1) / kTileThreads;   // staged cells per thread
     __shared__ T sB[NL], sI[NL], sS[NL], sC0[NL], sC1[NL], sX[NL], sR[NL];
     const int tile = xcd_block();
     if (tile >= ntiles) return;
+    const int dn = *done;   // tested once the staging loads are in flight
     const int ty = tile / ntx, tx = tile - ty * ntx;
     const int nx = (int)L.g.n[0], ny = (int)L.g.n[1];
     const int px = L.g.per[0], py = L.g.per[1];
     const int gx0 = tx * kTFX - H, gy0 = ty * kTFY - H;
-    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
+    // Stage: every load of the thread is issued before the first LDS store
+    // (indices past the region are clamped to its last cell, which is then
+    // stored again with the same values).
+    T lb[KL], li[KL], ls[KL], l0[KL], l1[KL];
+    bool lv[KL], m0[KL], m1[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
         const int ly = i / WX, lx = i - ly * WX;
         bool vx, vy;
         const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
         const bool v = vx && vy;
         const int g = v ? gx + nx * gy : 0;
-        const T bv = (T)b[g], iv = L.invd[g], sv = L.s[g], c0 = L.cs[0][g], c1 = L.cs[1][g];
-        sB[i] = v ? bv : (T)0;
-        sI[i] = v ? iv : (T)0;
-        sS[i] = v ? sv : (T)0;
-        sC0[i] = (v && (px || gx > 0)) ? c0 : (T)0;   // a wall face couples nothing
-        sC1[i] = (v && (py || gy > 0)) ? c1 : (T)0;
+        lb[k] = (T)b[g];
+        li[k] = L.invd[g];
+        ls[k] = L.s[g];
+        l0[k] = L.cs[0][g];
+        l1[k] = L.cs[1][g];
+        lv[k] = v;
+        m0[k] = v && (px || gx > 0);   // a wall face couples nothing
+        m1[k] = v && (py || gy > 0);
+    }
+    if (dn) return;
+    // masks applied as factors 0 / 1 (the values come from valid addresses and
+    // are finite), so that no load turns into a branch of its own
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const T fv = lv[k] ? (T)1 : (T)0;
+        sB[i] = lb[k] * fv;
+        sI[i] = li[k] * fv;
+        sS[i] = ls[k] * fv;
+        sC0[i] = l0[k] * (m0[k] ? (T)1 : (T)0);
+        sC1[i] = l1[k] * (m1[k] ? (T)1 : (T)0);
     }
     __syncthreads();
     // x on the tile and 2 halo cells
@@ -367,33 +390,52 @@ __global__ void __launch_bounds__(kTileThreads) k_up_tile2(Level<T> L, Geo gc, c
                                                            const TB *__restrict__ b, const T *__restrict__ xs,
                                                            T *__restrict__ x, int ntx, int ntiles,
                                                            const int *__restrict__ done) {
-    if (*done) return;
     using R = T;
     constexpr int H = 2, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
+    constexpr int KL = (NL + kTileThreads - 1) / kTileThreads;
     __shared__ T sB[NL], sI[NL], sC0[NL], sC1[NL], sX[NL];
     const int tile = xcd_block();
     if (tile >= ntiles) return;
+    const int dn = *done;
     const int ty = tile / ntx, tx = tile - ty * ntx;
     const int nx = (int)L.g.n[0], ny = (int)L.g.n[1];
     const int px = L.g.per[0], py = L.g.per[1];
     const int gx0 = tx * kTFX - H, gy0 = ty * kTFY - H;
-    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
+    // Stage as on the way down; the prolongation is evaluated for every
+    // staged cell (at coordinate 0 for cells that do not exist) and kept for
+    // the red cells only.
+    T lb[KL], li[KL], l0[KL], l1[KL], lx_[KL];
+    bool lv[KL], m0[KL], m1[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
         const int ly = i / WX, lx = i - ly * WX;
         bool vx, vy;
         const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
         const bool v = vx && vy;
         const int g = v ? gx + nx * gy : 0;
-        const T bv = (T)b[g], iv = L.invd[g], c0 = L.cs[0][g], c1 = L.cs[1][g], xv = xs[g];
-        sB[i] = v ? bv : (T)0;
-        sI[i] = v ? iv : (T)0;
-        sC0[i] = (v && (px || gx > 0)) ? c0 : (T)0;
-        sC1[i] = (v && (py || gy > 0)) ? c1 : (T)0;
-        T xr = (T)0;
-        if (v && ((gx0 + lx + gy0 + ly) & 1) == 0) {
-            const int ia[3] = {gx, gy, 0};
-            xr = (T)((R)xv + prolong_at<T, 2>(L.g, gc, xc, ia));
-        }
-        sX[i] = xr;
+        lb[k] = (T)b[g];
+        li[k] = L.invd[g];
+        l0[k] = L.cs[0][g];
+        l1[k] = L.cs[1][g];
+        const int ia[3] = {v ? gx : 0, v ? gy : 0, 0};
+        const R pe = prolong_at<T, 2>(L.g, gc, xc, ia);
+        const T red = (v && ((gx0 + lx + gy0 + ly) & 1) == 0) ? (T)1 : (T)0;
+        lx_[k] = (T)((R)xs[g] + pe) * red;
+        lv[k] = v;
+        m0[k] = v && (px || gx > 0);
+        m1[k] = v && (py || gy > 0);
+    }
+    if (dn) return;
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const T fv = lv[k] ? (T)1 : (T)0;
+        sB[i] = lb[k] * fv;
+        sI[i] = li[k] * fv;
+        sC0[i] = l0[k] * (m0[k] ? (T)1 : (T)0);
+        sC1[i] = l1[k] * (m1[k] ? (T)1 : (T)0);
+        sX[i] = lx_[k];
     }
     __syncthreads();
     auto gs = [&](int i) {
@@ -437,11 +479,12 @@ __global__ void __launch_bounds__(kSBThreads) k_vcycle_block(Slot<T> S, int l0, 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kSBThreads) k_vcycle_lds(Slot<T> S, int l0, int n16, int tail8,
                                                            const int *__restrict__ done) {
-    if (*done) return;
+    const int dn = *done;   // tested after the copy (which only reads memory and writes LDS)
     extern __shared__ uint4 lds_words[];
     char *lds = (char *)lds_words;
     const char *base = (const char *)S.lev[l0].s;
     copy_to_lds(lds_words, (const uint4 *)base, n16);
+    if (dn) return;
     if (tail8 && threadIdx.x == 0) *(double *)(lds + 16 * (size_t)n16) = *(const double *)(base + 16 * (size_t)n16);
     __syncthreads();
     vcycle_lds_dev<T, DIM>(S, l0, lds, base);
