@@ -1,6 +1,7 @@
 // Tables of the batched ensemble, shared by the persistent (workgroup per
 // problem) and the tiled (one launch per sweep over all problems) forms.
 #pragma once
+#include <array>
 #include <vector>
 
 #include "common.h"
@@ -70,9 +71,15 @@ struct chns_batch {
     int nlev_max;
     std::vector<int> nlev, lsb;       // per problem
     std::vector<long long> ncells[chns::kMaxLev];   // per level, per problem
+    std::vector<std::array<long long, 3>> lev_n[chns::kMaxLev];   // per level, per problem: extents
     chns::BTile *d_tiles[chns::kMaxLev];
     int ntiles[chns::kMaxLev];
     size_t tile_cap[chns::kMaxLev];
+    // 2D: per level, the kTFX x kTFY tiles {prob, tx, ty} of every problem
+    // whose level is above its single-workgroup levels (fused V-cycle passes)
+    chns::BTile *d_t2[chns::kMaxLev];
+    int nt2[chns::kMaxLev];
+    size_t t2_cap[chns::kMaxLev];
     double *tpart0, *tpart1, *tpart2; // per-tile partial sums (level-0 tile capacity)
     chns::Scal *d_scal;
     int *d_active;                    // number of problems whose current solve is not done

@@ -26,6 +26,7 @@
 #include "plan.h"
 #include "solvers.h"
 #include "stepdev.h"
+#include "tile2d.h"
 
 namespace chns {
 
@@ -38,6 +39,13 @@ struct PcgRes {
 
 constexpr int kBatchMaxThreads = 512;
 constexpr int kBatchSBCells = 2048;   // tiled form: levels at or below this run in one workgroup
+
+// first level of a problem that the single-workgroup part handles
+static int batch_lsb(const Plan &P) {
+    int lsb = 0;
+    while (lsb < P.nlev - 1 && P.lev[lsb].N > kBatchSBCells) ++lsb;
+    return lsb;
+}
 
 // r.z (with the singular projection), returned to every thread
 template <typename TP>
@@ -396,6 +404,20 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
         cap[l] = n + 8;
         tiles[l] = B.take<BTile>(cap[l]);
     }
+    // 2D tiles of the fused V-cycle passes (levels above each problem's
+    // single-workgroup levels)
+    BTile *t2[kMaxLev];
+    size_t cap2[kMaxLev];
+    for (int l = 0; l < kMaxLev; ++l) {
+        size_t n = 8;
+        for (int i = 0; i < count; ++i) {
+            const Plan &P = plans[i];
+            if (P.dim != 2 || l >= batch_lsb(P)) continue;
+            n += (size_t)((P.lev[l].n[0] + kTFX - 1) / kTFX) * (size_t)((P.lev[l].n[1] + kTFY - 1) / kTFY);
+        }
+        cap2[l] = n + 8;
+        t2[l] = B.take<BTile>(cap2[l]);
+    }
     double *tp0 = B.take<double>(cap[0]), *tp1 = B.take<double>(cap[0]), *tp2 = B.take<double>(cap[0]);
     if (b) {
         b->d_probs = probs;
@@ -408,6 +430,8 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
         for (int l = 0; l < kMaxLev; ++l) {
             b->d_tiles[l] = tiles[l];
             b->tile_cap[l] = cap[l];
+            b->d_t2[l] = t2[l];
+            b->t2_cap[l] = cap2[l];
         }
         b->tpart0 = tp0;
         b->tpart1 = tp1;
@@ -454,9 +478,7 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
         }
         Q.sc = scal ? scal + i : nullptr;
         {
-            int lsb = 0;   // first level with at most kSBCells cells (single-workgroup part)
-            while (lsb < P.nlev - 1 && P.lev[lsb].N > kBatchSBCells) ++lsb;
-            Q.lsb = lsb;
+            Q.lsb = batch_lsb(P);   // first level of the single-workgroup part
         }
         if (host) {   // step constants and CH operator are filled in by the caller
             const chns_props &p = props[i];
@@ -634,16 +656,21 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     b->lsb.resize(count);
     b->nlev_max = 0;
     b->lg = 0;
-    for (int l = 0; l < kMaxLev; ++l) b->ncells[l].assign(count, 0);
+    for (int l = 0; l < kMaxLev; ++l) {
+        b->ncells[l].assign(count, 0);
+        b->lev_n[l].assign(count, std::array<long long, 3>{0, 0, 0});
+    }
     for (int i = 0; i < count; ++i) {
         const Plan &P = plans[i];
         b->nlev[i] = P.nlev;
-        int lsb = 0;
-        while (lsb < P.nlev - 1 && P.lev[lsb].N > kBatchSBCells) ++lsb;
+        const int lsb = batch_lsb(P);
         b->lsb[i] = lsb;
         b->nlev_max = std::max(b->nlev_max, P.nlev);
         b->lg = std::max(b->lg, lsb);
-        for (int l = 0; l < P.nlev; ++l) b->ncells[l][i] = P.lev[l].N;
+        for (int l = 0; l < P.nlev; ++l) {
+            b->ncells[l][i] = P.lev[l].N;
+            for (int a = 0; a < 3; ++a) b->lev_n[l][i][a] = P.lev[l].n[a];
+        }
     }
     Bump B{(char *)workspace, 0};
     std::vector<char> host_table;

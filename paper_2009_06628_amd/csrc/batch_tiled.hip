@@ -19,6 +19,7 @@
 #include "mgdev.h"
 #include "plan.h"
 #include "stepdev.h"
+#include "tile2d.h"
 
 namespace chns {
 
@@ -198,6 +199,35 @@ __global__ void __launch_bounds__(kTileBlock) k_t_sweep(const BatchProb<TP> *__r
             break;
         default: TILE_LOOP(t) gs_color_cell<TP, TB, DIM>(L, b, x, op == 5 ? 1 : 0, c); break;
     }
+}
+
+// 2D: the fused way down / way up of level l over the kTFX x kTFY tiles of
+// every problem whose level l lies above its single-workgroup levels (the
+// tile list holds only those); same bodies as the single-grid kernels.  The
+// level's residual array carries the smoothed x from the way down to the
+// way up.
+template <typename TP, typename TB>
+__global__ void __launch_bounds__(kTileThreads) k_t_down2(const BatchProb<TP> *__restrict__ probs,
+                                                          const BTile *__restrict__ tiles, int ntiles, int s, int l,
+                                                          int bsel) {
+    BTile t;
+    if (!tile_of(tiles, ntiles, t)) return;
+    const BatchProb<TP> &P = probs[t.prob];
+    const Slot<TP> &S = tslot(P, s);
+    down_tile2<TP, TB>(S.lev[l], S.lev[l + 1].g, level_b<TP, TB>(P, S, l, bsel), S.lev[l].r, S.lev[l + 1].b, t.c0,
+                       t.c1, P.sc->done);
+}
+
+template <typename TP, typename TB>
+__global__ void __launch_bounds__(kTileThreads) k_t_up2(const BatchProb<TP> *__restrict__ probs,
+                                                        const BTile *__restrict__ tiles, int ntiles, int s, int l,
+                                                        int bsel, int xsel) {
+    BTile t;
+    if (!tile_of(tiles, ntiles, t)) return;
+    const BatchProb<TP> &P = probs[t.prob];
+    const Slot<TP> &S = tslot(P, s);
+    up_tile2<TP, TB>(S.lev[l], S.lev[l + 1].g, (const TP *)S.lev[l + 1].x, level_b<TP, TB>(P, S, l, bsel),
+                     (const TP *)S.lev[l].r, level_x(P, S, l, xsel), t.c0, t.c1, P.sc->done);
 }
 
 // restriction of level l's residual into level l + 1 (tiles of level l + 1)
@@ -614,6 +644,28 @@ struct Tiled {
     }
     template <typename TB>
     void vcycle(int sv, int bsel, int xsel) {
+        if (DIM == 2) {
+            // fused passes: one launch per level on the way down and one on the way up
+            for (int l = 0; l < b->lg; ++l) {
+                if (l == 0)
+                    hipLaunchKernelGGL((k_t_down2<TP, TB>), dim3(b->nt2[0]), dim3(kTileThreads), 0, s, probs(),
+                                       b->d_t2[0], b->nt2[0], sv, 0, bsel);
+                else
+                    hipLaunchKernelGGL((k_t_down2<TP, TP>), dim3(b->nt2[l]), dim3(kTileThreads), 0, s, probs(),
+                                       b->d_t2[l], b->nt2[l], sv, l, 0);
+            }
+            hipLaunchKernelGGL((k_t_vcycle_small<TP, TB, DIM>), dim3(np()), dim3(kSBThreads), 0, s, probs(), sv,
+                               bsel, xsel);
+            for (int l = b->lg - 1; l >= 0; --l) {
+                if (l == 0)
+                    hipLaunchKernelGGL((k_t_up2<TP, TB>), dim3(b->nt2[0]), dim3(kTileThreads), 0, s, probs(),
+                                       b->d_t2[0], b->nt2[0], sv, 0, bsel, xsel);
+                else
+                    hipLaunchKernelGGL((k_t_up2<TP, TP>), dim3(b->nt2[l]), dim3(kTileThreads), 0, s, probs(),
+                                       b->d_t2[l], b->nt2[l], sv, l, 0, 0);
+            }
+            return;
+        }
         for (int l = 0; l < b->lg; ++l) {
             if (l == 0) {
                 sweep<TB>(sv, 0, bsel, xsel, 0);
@@ -799,6 +851,25 @@ int tiled_build(chns_batch *b, int tile_cells) {
             }
         }
         hipError_t e = hipMemcpy(b->d_tiles[l], v.data(), sizeof(BTile) * v.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("tile table: ") + hipGetErrorString(e));
+    }
+    // 2D tiles of the fused passes (independent of tile_cells)
+    for (int l = 0; l < kMaxLev; ++l) {
+        std::vector<BTile> v;
+        if (b->dim == 2 && l < b->lg) {
+            for (int p = 0; p < b->count; ++p) {
+                if (l >= b->lsb[p]) continue;
+                const int ntx = (int)((b->lev_n[l][p][0] + kTFX - 1) / kTFX);
+                const int nty = (int)((b->lev_n[l][p][1] + kTFY - 1) / kTFY);
+                for (int ty = 0; ty < nty; ++ty)
+                    for (int tx = 0; tx < ntx; ++tx) v.push_back(BTile{p, tx, ty, 0});
+            }
+        }
+        if (v.empty()) v.push_back(BTile{-1, 0, 0, 0});
+        while (v.size() > 8 && (v.size() & 7)) v.push_back(BTile{-1, 0, 0, 0});
+        if (v.size() > b->t2_cap[l]) return set_error(CHNS_EINVAL, "2D tile list exceeds its capacity");
+        b->nt2[l] = (int)v.size();
+        hipError_t e = hipMemcpy(b->d_t2[l], v.data(), sizeof(BTile) * v.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("tile table: ") + hipGetErrorString(e));
     }
     b->tile_cells = tile_cells;

@@ -1,0 +1,215 @@
+// Device bodies of the 2D multigrid tile passes (gfx950).
+#pragma once
+#include "mgdev.h"
+
+namespace chns {
+
+// ---------------------------------------------------------------------------
+// 2D tile passes of the grid levels: one for the way down, one for the way
+// up (shared by the single-grid kernels and the tiled batched form)
+// ---------------------------------------------------------------------------
+// A workgroup owns kTFX x kTFY fine cells (kTFX/2 x kTFY/2 coarse cells) and
+// stages the level on the tile plus a halo in LDS.  Cells outside a walled
+// axis are zero with zero coupling, which is what the branch-free per-cell
+// stencils add for a missing neighbour; periodic axes wrap.  Halo values are
+// recomputed by every tile that needs them, with the arithmetic of the
+// per-cell passes in the same order, so the results are those of the
+// separate passes.  Levels here have even extents (only the coarsest may
+// not), so colours do not change across a periodic seam.
+constexpr int kTFX = 32, kTFY = 16;   // fine cells per tile
+constexpr int kTileThreads = 256;
+
+// Local index -> global coordinate along one axis: wrapped on a periodic
+// axis; v tells whether the cell exists.
+__device__ inline int tile_coord(int g, int n, int per, bool &v) {
+    v = per || (g >= 0 && g < n);
+    return per ? ((g % n) + n) % n : g;
+}
+
+// Way down: zero-guess pre-smoothing (red x = b / d, black GS from those),
+// residual r = b - A x, restriction of r to the coarse right-hand side bc.
+// Writes the smoothed x of the tile to xs (the level's residual array, which
+// no longer holds a residual: the way up reads x from there while it writes
+// the level's x) and bc on the tile's coarse cells.
+template <typename T, typename TB>
+__device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__restrict__ b, T *__restrict__ xs,
+                                  T *__restrict__ bc, int tx, int ty, int skip) {
+    using R = T;
+    constexpr int H = 3, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
+    constexpr int KL = (NL + kTileThreads - 1) / kTileThreads;   // staged cells per thread
+    __shared__ T sB[NL], sI[NL], sS[NL], sC0[NL], sC1[NL], sX[NL], sR[NL];
+    const int nx = (int)L.g.n[0], ny = (int)L.g.n[1];
+    const int px = L.g.per[0], py = L.g.per[1];
+    const int gx0 = tx * kTFX - H, gy0 = ty * kTFY - H;
+    // Stage: every load of the thread is issued before the first LDS store
+    // (indices past the region are clamped to its last cell, which is then
+    // stored again with the same values).
+    T lb[KL], li[KL], ls[KL], l0[KL], l1[KL];
+    bool lv[KL], m0[KL], m1[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const int ly = i / WX, lx = i - ly * WX;
+        bool vx, vy;
+        const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
+        const bool v = vx && vy;
+        const int g = v ? gx + nx * gy : 0;
+        lb[k] = (T)b[g];
+        li[k] = L.invd[g];
+        ls[k] = L.s[g];
+        l0[k] = L.cs[0][g];
+        l1[k] = L.cs[1][g];
+        lv[k] = v;
+        m0[k] = v && (px || gx > 0);   // a wall face couples nothing
+        m1[k] = v && (py || gy > 0);
+    }
+    if (skip) return;   // tested once the staging loads are in flight
+    // masks applied as factors 0 / 1 (the values come from valid addresses and
+    // are finite), so that no load turns into a branch of its own
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const T fv = lv[k] ? (T)1 : (T)0;
+        sB[i] = lb[k] * fv;
+        sI[i] = li[k] * fv;
+        sS[i] = ls[k] * fv;
+        sC0[i] = l0[k] * (m0[k] ? (T)1 : (T)0);
+        sC1[i] = l1[k] * (m1[k] ? (T)1 : (T)0);
+    }
+    __syncthreads();
+    // x on the tile and 2 halo cells
+    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
+        const int ly = i / WX, lx = i - ly * WX;
+        if (lx < 1 || lx >= WX - 1 || ly < 1 || ly >= WY - 1) continue;
+        if (((gx0 + lx + gy0 + ly) & 1) == 0) {
+            sX[i] = (T)((R)sB[i] * (R)sI[i]);
+        } else {
+            auto red = [&](int j) { return (R)sB[j] * (R)sI[j]; };
+            R acc = 0.0;
+            acc += (R)sC0[i] * red(i - 1);
+            acc += (R)sC0[i + 1] * red(i + 1);
+            acc += (R)sC1[i] * red(i - WX);
+            acc += (R)sC1[i + WX] * red(i + WX);
+            sX[i] = (T)(((R)sB[i] + acc) * (R)sI[i]);
+        }
+    }
+    __syncthreads();
+    // residual on the tile and 1 halo cell
+    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
+        const int ly = i / WX, lx = i - ly * WX;
+        if (lx < 2 || lx >= WX - 2 || ly < 2 || ly >= WY - 2) continue;
+        const R xc = (R)sX[i];
+        R acc = (R)sS[i] * xc;
+        acc += (R)sC0[i] * (xc - (R)sX[i - 1]);
+        acc += (R)sC0[i + 1] * (xc - (R)sX[i + 1]);
+        acc += (R)sC1[i] * (xc - (R)sX[i - WX]);
+        acc += (R)sC1[i + WX] * (xc - (R)sX[i + WX]);
+        sR[i] = (T)((R)sB[i] - acc);
+    }
+    __syncthreads();
+    // restriction (taps 2I-1 .. 2I+2 per axis; an absent tap has weight 0)
+    constexpr int CX = kTFX / 2, CY = kTFY / 2;
+    const int ncx = (int)gc.n[0], ncy = (int)gc.n[1];
+    for (int j = (int)threadIdx.x; j < CX * CY; j += kTileThreads) {
+        const int cy = j / CX, cx = j - cy * CX;
+        const int I = tx * CX + cx, J = ty * CY + cy;
+        if (I >= ncx || J >= ncy) continue;
+        int fx[4], fy[4];
+        R wx[4], wy[4];
+        res_axis<R>(I, ncx, nx, gc.per[0], fx, wx);
+        res_axis<R>(J, ncy, ny, gc.per[1], fy, wy);
+        R v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = (2 * cy + H - 1 + q) * WX + 2 * cx + H - 1;
+            R s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s += wx[e] * (R)sR[row + e];
+            v += (wy[q] * (R)1.0) * s;
+        }
+        bc[I + ncx * J] = (T)v;
+    }
+    // x of the tile's own cells
+    for (int j = (int)threadIdx.x; j < kTFX * kTFY; j += kTileThreads) {
+        const int ly = j / kTFX, lx = j - ly * kTFX;
+        const int gx = tx * kTFX + lx, gy = ty * kTFY + ly;
+        if (gx < nx && gy < ny) xs[gx + nx * gy] = sX[(ly + H) * WX + lx + H];
+    }
+}
+
+// Way up: red x += P e, black GS, red GS (the post-smoothing), with e the
+// coarse correction xc and the pre-smoothed x read from xs.  Writes x on the
+// tile (never read here, so tiles do not race on their halos).
+template <typename T, typename TB>
+__device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__restrict__ xc, const TB *__restrict__ b,
+                                const T *__restrict__ xs, T *__restrict__ x, int tx, int ty, int skip) {
+    using R = T;
+    constexpr int H = 2, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
+    constexpr int KL = (NL + kTileThreads - 1) / kTileThreads;
+    __shared__ T sB[NL], sI[NL], sC0[NL], sC1[NL], sX[NL];
+    const int nx = (int)L.g.n[0], ny = (int)L.g.n[1];
+    const int px = L.g.per[0], py = L.g.per[1];
+    const int gx0 = tx * kTFX - H, gy0 = ty * kTFY - H;
+    // Stage as on the way down; the prolongation is evaluated for every
+    // staged cell (at coordinate 0 for cells that do not exist) and kept for
+    // the red cells only.
+    T lb[KL], li[KL], l0[KL], l1[KL], lx_[KL];
+    bool lv[KL], m0[KL], m1[KL];
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const int ly = i / WX, lx = i - ly * WX;
+        bool vx, vy;
+        const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
+        const bool v = vx && vy;
+        const int g = v ? gx + nx * gy : 0;
+        lb[k] = (T)b[g];
+        li[k] = L.invd[g];
+        l0[k] = L.cs[0][g];
+        l1[k] = L.cs[1][g];
+        const int ia[3] = {v ? gx : 0, v ? gy : 0, 0};
+        const R pe = prolong_at<T, 2>(L.g, gc, xc, ia);
+        const T red = (v && ((gx0 + lx + gy0 + ly) & 1) == 0) ? (T)1 : (T)0;
+        lx_[k] = (T)((R)xs[g] + pe) * red;
+        lv[k] = v;
+        m0[k] = v && (px || gx > 0);
+        m1[k] = v && (py || gy > 0);
+    }
+    if (skip) return;
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const T fv = lv[k] ? (T)1 : (T)0;
+        sB[i] = lb[k] * fv;
+        sI[i] = li[k] * fv;
+        sC0[i] = l0[k] * (m0[k] ? (T)1 : (T)0);
+        sC1[i] = l1[k] * (m1[k] ? (T)1 : (T)0);
+        sX[i] = lx_[k];
+    }
+    __syncthreads();
+    auto gs = [&](int i) {
+        R acc = 0.0;
+        acc += (R)sC0[i] * (R)sX[i - 1];
+        acc += (R)sC0[i + 1] * (R)sX[i + 1];
+        acc += (R)sC1[i] * (R)sX[i - WX];
+        acc += (R)sC1[i + WX] * (R)sX[i + WX];
+        return (T)(((R)sB[i] + acc) * (R)sI[i]);
+    };
+    // black on the tile and 1 halo cell (reads red cells only)
+    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
+        const int ly = i / WX, lx = i - ly * WX;
+        if (lx < 1 || lx >= WX - 1 || ly < 1 || ly >= WY - 1) continue;
+        if (((gx0 + lx + gy0 + ly) & 1) == 1) sX[i] = gs(i);
+    }
+    __syncthreads();
+    // red on the tile (reads black cells only); both colours written out
+    for (int j = (int)threadIdx.x; j < kTFX * kTFY; j += kTileThreads) {
+        const int ly = j / kTFX, lx = j - ly * kTFX;
+        const int gx = tx * kTFX + lx, gy = ty * kTFY + ly;
+        if (gx >= nx || gy >= ny) continue;
+        const int i = (ly + H) * WX + lx + H;
+        x[gx + nx * gy] = ((gx + gy) & 1) == 0 ? gs(i) : sX[i];
+    }
+}
+
+}  // namespace chns
