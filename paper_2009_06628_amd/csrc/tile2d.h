@@ -16,7 +16,13 @@ namespace chns {
 // per-cell passes in the same order, so the results are those of the
 // separate passes.  Levels here have even extents (only the coarsest may
 // not), so colours do not change across a periodic seam.
-constexpr int kTFX = 32, kTFY = 16;   // fine cells per tile
+#ifndef CHNS_TILE2_X
+#define CHNS_TILE2_X 32
+#endif
+#ifndef CHNS_TILE2_Y
+#define CHNS_TILE2_Y 16
+#endif
+constexpr int kTFX = CHNS_TILE2_X, kTFY = CHNS_TILE2_Y;   // fine cells per tile (even)
 constexpr int kTileThreads = 256;
 
 // Local index -> global coordinate along one axis: wrapped on a periodic

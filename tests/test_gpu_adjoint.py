@@ -224,15 +224,16 @@ def test_checkpointed_gradient_is_bitwise_equal():
             assert torch.equal(a.cpu(), b.cpu())
 
 
-def test_oscillating_drop_128_finite_differences():
-    """sigma, M and four seeded unit-RMS phi_0 directions (seed 55) against
-    central differences of the GPU rollout, 128 x 128, 40 steps.  The
-    directions are Gaussian noise times (1 - phi_0^2), normalised to unit RMS:
-    in the bulk phi_0 = +-(1 - 4e-16), where a perturbation of 1e-6 would
-    step across the kink of the pull-back at |phi| = 1 and the central
+@pytest.mark.parametrize("steps,ndirs", [(40, 4), (400, 2)])
+def test_oscillating_drop_128_finite_differences(steps, ndirs):
+    """sigma, M and seeded unit-RMS phi_0 directions (seed 55) against
+    central differences (step 1e-6) of the GPU rollout, 128 x 128, over 40
+    steps and over the configuration's full 400 steps (checkpoint every 20).
+    The directions are Gaussian noise times (1 - phi_0^2), normalised to unit
+    RMS: in the bulk phi_0 = +-(1 - 4e-16), where a perturbation of 1e-6
+    would step across the kink of the pull-back at |phi| = 1 and the central
     difference would no longer measure the derivative."""
     P = _lib()
-    steps = 40
     prob = W.adjoint_drop(128, steps=steps)
     props = tight(prob.props)
     init = W.initial_state(prob)
@@ -269,7 +270,7 @@ def test_oscillating_drop_128_finite_differences():
                                                s0 * EPS)),
            "M": (float(mob.grad), cdiff(L(phi_init, s0, m0 * (1 + EPS)), L(phi_init, s0, m0 * (1 - EPS)), m0 * EPS))}
     rng = np.random.default_rng(55)
-    for k in range(4):
+    for k in range(ndirs):
         d = rng.normal(size=prob.shape) * (1.0 - init["phi"] ** 2)
         d /= np.sqrt(np.mean(d * d))
         dd = dev(d)

@@ -97,8 +97,11 @@ def test_batch_matches_oracle_2d(form):
     probs = [W.oscillating_drop(16, (0.3, 0.22), 10.0, 5.0, steps=10),
              W.oscillating_drop(24, (0.25, 0.2), 300.0, 30.0, steps=10),
              W.oscillating_drop(32, (0.22, 0.28), 1.0, 1.0, steps=10),
-             W.rising_bubble(16, steps=10)]
+             W.rising_bubble(16, steps=10),
+             W.rising_bubble(48, steps=10),          # walls on a level above the single-workgroup part
+             W.oscillating_drop(80, (0.26, 0.21), 20.0, 4.0, steps=10)]   # partial tiles (80 = 2.5 x 32)
     probs[3].init_args = dict(probs[3].init_args, velocity="stream", vseed=6, vamp=0.1)
+    probs[4].init_args = dict(probs[4].init_args, velocity="stream", vseed=7, vamp=0.1)
     print("batch (%s) vs oracle 2D:" % form, [p.n for p in probs], flush=True)
     b, st, stats = batch_run(probs, 10, form=form)
     for i, p in enumerate(probs):
