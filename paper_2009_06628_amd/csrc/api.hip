@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 
 #include "common.h"
 #include "solvers.h"
@@ -205,6 +206,33 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     g->diag = B.take<double>(8 * (size_t)kMaxBlocks + 16);
     g->red.counter = B.take<unsigned int>(64);
     g->red.scal = B.take<Scal>(1);
+    // momentum components 1 .. dim-1 (own hierarchy, vectors, scratch)
+    for (int a = 1; a < P.dim; ++a) {
+        MomCtx &M = g->mc[a - 1];
+        M.rhs = B.take<double>(N);
+        M.vr = B.take<double>(N);
+        M.vz = B.take<double>(N);
+        M.vp0 = B.take<double>(N);
+        M.vp1 = B.take<double>(N);
+        M.vq = B.take<double>(N);
+        M.vt = B.take<double>(N);
+        carve_slot(B, P, M.mom, 0);
+        double *maug = nc > kLdsInverse ? B.take<double>((size_t)nc * nc) : nullptr;
+        M.mom.aug = maug;
+        if (prec == CHNS_FP32_REFINE) {
+            carve_slot(B, P, M.mom32, 0);
+            M.mom32.aug = maug;
+            M.f_z = B.take<float>(N);
+            M.f_t = B.take<float>(N);
+        } else {
+            M.f_z = M.f_t = nullptr;
+        }
+        M.red.part0 = B.take<double>(kMaxBlocks);
+        M.red.part1 = B.take<double>(kMaxBlocks);
+        M.red.part2 = B.take<double>(kMaxBlocks);
+        M.red.counter = B.take<unsigned int>(64);
+        M.red.scal = B.take<Scal>(1);
+    }
 }
 
 StepConst step_const(const chns_grid *g) { return step_const_of(g->props, g->h); }
@@ -213,30 +241,74 @@ PcgVecs<double> vecs(chns_grid *g) { return PcgVecs<double>{g->vr, g->vz, g->vp0
 
 int next_predict(int last) { return last < 1 ? 1 : last; }
 
-// One linear solve in the handle's precision form.  which: 0 CH (constant
-// hierarchy, set up by chns_set_properties), 1 momentum, 2 pressure (their
-// level-0 coefficients were just written by the set-up kernels).  pidx
-// indexes the iteration predictions.
-hipError_t run_solve(chns_grid *g, int which, OpKind kind, ChOp ch, const double *b, double *x, double rtol,
-                     int pidx, SolveOut *o) {
-    Slot<double> &S64 = which == 0 ? g->ch : (which == 1 ? g->mom : g->pres);
-    hipStream_t s = g->stream;
-    PcgVecs<double> v = vecs(g);
+// What one linear solve works on: hierarchies, vectors, reduction scratch
+// and the stream its launches go to.
+struct SolveCtx {
+    Slot<double> *S64;
+    Slot<float> *S32;
+    PcgVecs<double> v;
+    float *f_z, *f_t;
+    Red red;
+    hipStream_t s;
+};
+
+// One linear solve in the handle's precision form.  setup: rebuild the
+// hierarchy from the level-0 coefficients just written by the set-up
+// kernels (momentum, pressure); the CH hierarchy is constant (set up by
+// chns_set_properties).  pidx indexes the iteration predictions.
+hipError_t run_solve_ctx(chns_grid *g, const SolveCtx &c, int setup, OpKind kind, ChOp ch, const double *b,
+                         double *x, double rtol, int pidx, SolveOut *o) {
+    Slot<double> &S64 = *c.S64;
+    PcgVecs<double> v = c.v;
+    Red red = c.red;
     if (g->prec == CHNS_FP64) {
-        if (which != 0) mg_setup(S64, g->dim, s);
+        if (setup) mg_setup(S64, g->dim, c.s);
         hipError_t e = pcg_solve(S64, g->dim, kind, ch, b, x, rtol, g->props.max_iter, next_predict(g->last_iters[pidx]),
-                                 g->red, v, s, o);
+                                 red, v, c.s, o);
         g->last_iters[pidx] = o->iters;
         return e;
     }
-    Slot<float> &S32 = which == 0 ? g->ch32 : (which == 1 ? g->mom32 : g->pres32);
-    if (which != 0) {
-        convert_level0(S64, S32, g->dim, s);
-        mg_setup(S32, g->dim, s);
+    Slot<float> &S32 = *c.S32;
+    if (setup) {
+        convert_level0(S64, S32, g->dim, c.s);
+        mg_setup(S32, g->dim, c.s);
     }
-    const PcgVecs2<double, float> v2{v.r, v.p0, v.p1, v.q, v.t, g->f_z, g->f_t};
-    return refine_solve(S64, S32, g->dim, kind, ch, b, x, rtol, g->props.max_iter, &g->last_inner[pidx], g->red, v2, s,
-                        o);
+    const PcgVecs2<double, float> v2{v.r, v.p0, v.p1, v.q, v.t, c.f_z, c.f_t};
+    return refine_solve(S64, S32, g->dim, kind, ch, b, x, rtol, g->props.max_iter, &g->last_inner[pidx], red, v2,
+                        c.s, o);
+}
+
+// The handle's own buffers; which: 0 CH, 1 momentum, 2 pressure.
+SolveCtx main_ctx(chns_grid *g, int which) {
+    SolveCtx c;
+    c.S64 = which == 0 ? &g->ch : (which == 1 ? &g->mom : &g->pres);
+    c.S32 = which == 0 ? &g->ch32 : (which == 1 ? &g->mom32 : &g->pres32);
+    c.v = vecs(g);
+    c.f_z = g->f_z;
+    c.f_t = g->f_t;
+    c.red = g->red;
+    c.s = g->stream;
+    return c;
+}
+
+// Buffers of momentum component a (0: the handle's own).
+SolveCtx mom_ctx(chns_grid *g, int a) {
+    if (a == 0) return main_ctx(g, 1);
+    MomCtx &M = g->mc[a - 1];
+    SolveCtx c;
+    c.S64 = &M.mom;
+    c.S32 = &M.mom32;
+    c.v = PcgVecs<double>{M.vr, M.vz, M.vp0, M.vp1, M.vq, M.vt};
+    c.f_z = M.f_z;
+    c.f_t = M.f_t;
+    c.red = M.red;
+    c.s = M.stream;
+    return c;
+}
+
+hipError_t run_solve(chns_grid *g, int which, OpKind kind, ChOp ch, const double *b, double *x, double rtol,
+                     int pidx, SolveOut *o) {
+    return run_solve_ctx(g, main_ctx(g, which), which != 0, kind, ch, b, x, rtol, pidx, o);
 }
 
 int check_solve(const SolveOut &o, const char *what) {
@@ -267,16 +339,55 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     // S3, S4
     launch_mu(dim, geo, k, phi, g->phihat, mu, s);
     launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);
-    // S5..S7
-    for (int a = 0; a < dim; ++a) {
-        Level<double> &L0 = g->mom.lev[0];
+    // S5..S7: the components are independent.  With the per-kernel timing
+    // off, component a > 0 runs on its own stream (forked from and joined
+    // back to the handle's stream by events) and its own host thread, so
+    // the launch latencies of the components overlap; the arithmetic of
+    // each solve is unchanged.
+    const bool concurrent = dim > 1 && g->mc_ready && !g_prof;
+    SolveOut om[3];
+    hipError_t em[3] = {hipSuccess, hipSuccess, hipSuccess};
+    auto momentum = [&](int a) {
+        const SolveCtx c = mom_ctx(g, a);
+        if (a > 0 && concurrent) {
+            em[a] = hipStreamWaitEvent(c.s, g->ev_fork, 0);
+            if (em[a] != hipSuccess) return;
+        }
+        Level<double> &L0 = c.S64->lev[0];
+        double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
         double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-        launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, g->rhs, g->ustar[a], s);
-        HIPCHK(run_solve(g, 1, OP_SLOT, ch, (const double *)g->rhs, g->ustar[a], p.rtol_mom, 1 + a, &o));
-        if (int rc = check_solve(o, "momentum")) return rc;
-        last.iters_mom[a] = o.iters;
-        last.res_mom[a] = o.rel_res;
-        last.unconverged |= o.unconverged ? (2 << a) : 0;
+        launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, rhs, g->ustar[a], c.s);
+        em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
+        if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
+    };
+    if (concurrent) {
+        HIPCHK(hipEventRecord(g->ev_fork, s));
+        std::thread workers[2];
+        for (int a = 1; a < dim; ++a) workers[a - 1] = std::thread(momentum, a);
+        momentum(0);
+        for (int a = 1; a < dim; ++a) workers[a - 1].join();
+        for (int a = 1; a < dim; ++a)
+            if (em[a] == hipSuccess) em[a] = hipStreamWaitEvent(s, g->mc[a - 1].done_ev, 0);
+    } else {
+        for (int a = 0; a < dim; ++a) {
+            if (a > 0) {   // sequential: component a uses its buffers on the handle's stream
+                MomCtx &M = g->mc[a - 1];
+                const hipStream_t keep = M.stream;
+                M.stream = s;
+                momentum(a);
+                M.stream = keep;
+            } else {
+                momentum(a);
+            }
+            if (em[a] != hipSuccess) break;
+        }
+    }
+    for (int a = 0; a < dim; ++a) {
+        if (em[a] != hipSuccess) return fail(CHNS_EDEVICE, std::string("momentum solve: ") + hipGetErrorString(em[a]));
+        if (int rc = check_solve(om[a], "momentum")) return rc;
+        last.iters_mom[a] = om[a].iters;
+        last.res_mom[a] = om[a].rel_res;
+        last.unconverged |= om[a].unconverged ? (2 << a) : 0;
     }
     // S8
     Level<double> &L0 = g->pres.lev[0];
@@ -323,6 +434,26 @@ int chns_workspace_size(const chns_grid_desc *desc, size_t *bytes) {
     return CHNS_OK;
 }
 
+// Streams and events of the momentum components (waits for their work).
+static void release_streams(chns_grid *g) {
+    for (int a = 0; a < 2; ++a) {
+        if (g->mc[a].stream) {
+            (void)hipStreamSynchronize(g->mc[a].stream);
+            (void)hipStreamDestroy(g->mc[a].stream);
+            g->mc[a].stream = nullptr;
+        }
+        if (g->mc[a].done_ev) {
+            (void)hipEventDestroy(g->mc[a].done_ev);
+            g->mc[a].done_ev = nullptr;
+        }
+    }
+    if (g->ev_fork) {
+        (void)hipEventDestroy(g->ev_fork);
+        g->ev_fork = nullptr;
+    }
+    g->mc_ready = 0;
+}
+
 int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, void *hip_stream, chns_grid **out) {
     if (!out) return fail(CHNS_EINVAL, "out is NULL");
     *out = nullptr;
@@ -348,10 +479,35 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     layout(B, P, g, desc->precision);
     for (int k = 0; k < 12; ++k) g->last_iters[k] = g->last_inner[k] = 4;
     g->adj_ready = 0;
+    // streams (default priority) and events of the momentum components
+    g->mc_ready = 0;
+    g->ev_fork = nullptr;
+    for (int a = 0; a < 2; ++a) {
+        g->mc[a].stream = nullptr;
+        g->mc[a].done_ev = nullptr;
+    }
+    if (P.dim > 1) {
+        hipError_t e = hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming);
+        for (int a = 1; a < P.dim && e == hipSuccess; ++a) {
+            e = hipStreamCreateWithFlags(&g->mc[a - 1].stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&g->mc[a - 1].done_ev, hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            release_streams(g);
+            delete g;
+            return fail(CHNS_EDEVICE, std::string("stream set-up: ") + hipGetErrorString(e));
+        }
+        g->mc_ready = 1;
+    }
     memset(&g->last, 0, sizeof g->last);
     hipError_t e = hipMemsetAsync(g->red.counter, 0, 64 * sizeof(unsigned int), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->red.scal, 0, sizeof(Scal), g->stream);
+    for (int a = 1; a < P.dim && e == hipSuccess; ++a) {
+        e = hipMemsetAsync(g->mc[a - 1].red.counter, 0, 64 * sizeof(unsigned int), g->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(g->mc[a - 1].red.scal, 0, sizeof(Scal), g->stream);
+    }
     if (e != hipSuccess) {
+        release_streams(g);
         delete g;
         return fail(CHNS_EDEVICE, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
     }
@@ -640,7 +796,10 @@ int chns_get_timing(chns_grid *g, chns_kernel_timing *out, int max, int *count) 
 }
 
 int chns_destroy_grid(chns_grid *g) {
-    if (g) prof_release(g->prof);
+    if (g) {
+        prof_release(g->prof);
+        release_streams(g);
+    }
     delete g;
     return CHNS_OK;
 }

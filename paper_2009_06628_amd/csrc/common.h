@@ -276,6 +276,22 @@ struct AdjBufs {
 // ---------------------------------------------------------------------------
 // the handle
 // ---------------------------------------------------------------------------
+namespace chns {
+// Buffers of one momentum component solved on a stream of its own (the
+// components of S7 are independent): its own hierarchy, PCG vectors,
+// reduction scratch and right-hand side.
+struct MomCtx {
+    Slot<double> mom;
+    Slot<float> mom32;
+    double *rhs;
+    double *vr, *vz, *vp0, *vp1, *vq, *vt;
+    float *f_z, *f_t;
+    Red red;
+    hipStream_t stream;
+    hipEvent_t done_ev;   // recorded on stream after the solve
+};
+}  // namespace chns
+
 struct chns_grid {
     chns_grid_desc desc;
     chns_props props;
@@ -296,6 +312,9 @@ struct chns_grid {
     chns::Red red;
     double *diag;                            // diagnostics scratch
     int last_iters[12];                      // iteration-count predictions
+    chns::MomCtx mc[2];                      // momentum components 1, 2 (component 0 uses the buffers above)
+    hipEvent_t ev_fork;                      // main stream -> component streams
+    int mc_ready;                            // streams and events of mc created
     int adj_ready;                           // adjoint workspace attached
     chns::AdjBufs adj;
     chns_step_stats last;

@@ -44,12 +44,11 @@ namespace chns {
 constexpr int kSBCellsDefault = 2048;
 
 static int sb_cells() {
-    static int v = -1;
-    if (v < 0) {
+    static const int v = [] {   // thread-safe one-time initialisation
         const char *e = getenv("CHNS_SB_CELLS");
-        v = e ? atoll(e) : kSBCellsDefault;
-        if (v < 1) v = 1;
-    }
+        const long long x = e ? atoll(e) : kSBCellsDefault;
+        return (int)(x < 1 ? 1 : x);
+    }();
     return v;
 }
 
@@ -750,12 +749,12 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
                                      : 0;
         if (lsb > 0 && range <= (size_t)kLdsVcycleBytes) {
             // the range is read once and x of level lsb written back
-            static bool attr = false;
-            if (!attr) {
+            static const bool attr = [] {   // once per instantiation, thread-safe
                 (void)hipFuncSetAttribute((const void *)k_vcycle_lds<T, DIM>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsVcycleBytes);
-                attr = true;
-            }
+                return true;
+            }();
+            (void)attr;
             const double bytes = (double)range + W * S.lev[lsb].g.N;
             TLAUNCHS(K_COARSE_SOLVE, bytes, (k_vcycle_lds<T, DIM>), dim3(1), dim3(kSBThreads), range, st, S, lsb,
                      (int)(range / 16), (int)((range % 16) != 0), done);
