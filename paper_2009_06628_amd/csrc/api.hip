@@ -3,6 +3,7 @@
 // every buffer is carved out of the caller's workspace.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -316,6 +317,16 @@ int check_solve(const SolveOut &o, const char *what) {
     return CHNS_OK;
 }
 
+// CHNS_SERIAL_MOMENTUM=1 runs the momentum components one after another on
+// the handle's stream (per-kernel profiles without overlapping kernels).
+static bool serial_momentum() {
+    static const bool v = [] {
+        const char *e = getenv("CHNS_SERIAL_MOMENTUM");
+        return e && e[0] == '1';
+    }();
+    return v;
+}
+
 // S1..S8 of one step from (phi, u) with the pressure initial guess in pr:
 // phihat, mu, phi_new, ustar and p; solver statistics into last.
 int forward_core(chns_grid *g, const double *phi, const double *const uc[3], double *mu, double *pr,
@@ -344,7 +355,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     // back to the handle's stream by events) and its own host thread, so
     // the launch latencies of the components overlap; the arithmetic of
     // each solve is unchanged.
-    const bool concurrent = dim > 1 && g->mc_ready && !g_prof;
+    const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum();
     SolveOut om[3];
     hipError_t em[3] = {hipSuccess, hipSuccess, hipSuccess};
     auto momentum = [&](int a) {

@@ -65,6 +65,20 @@ __global__ void __launch_bounds__(kBlock) k_presmooth(Level<T> L, const TB *__re
     GRID_LOOP(L.g.N) presmooth_cell<T, TB, DIM>(L, b, x, c);
 }
 
+// The same pass with one thread per x-adjacent pair of cells (even x
+// extent): each lane updates one red and one black cell, so a wave whose
+// lanes share a row runs each colour's branch once instead of both with
+// half of its lanes masked off.
+template <typename T, typename TB, int DIM>
+__global__ void __launch_bounds__(kBlock) k_presmooth_pair(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,
+                                                           const int *__restrict__ done) {
+    if (*done) return;
+    GRID_LOOP(L.g.N / 2) {
+        presmooth_cell<T, TB, DIM>(L, b, x, 2 * c);
+        presmooth_cell<T, TB, DIM>(L, b, x, 2 * c + 1);
+    }
+}
+
 template <typename T, typename TB, int DIM>
 __global__ void __launch_bounds__(kBlock) k_residual(Level<T> L, const TB *__restrict__ b, const T *__restrict__ x,
                                                      const int *__restrict__ done) {
@@ -343,11 +357,14 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
         const double pc = pv(c);
         double qc = (double)L.s[c] * pc;
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) {
+        for (int b = 0; b < DIM; ++b) {   // branch-free: a missing neighbour is c itself with weight 0
             const int lo = nb_lo(L.g, c, ia[b], b);
             const int hi = nb_hi(L.g, c, ia[b], b);
-            if (lo >= 0) qc += (double)L.cs[b][c] * (pc - pv(lo));
-            if (hi >= 0) qc += (double)L.cs[b][hi] * (pc - pv(hi));
+            const int l = lo >= 0 ? lo : c, h = hi >= 0 ? hi : c;
+            const double vl = pv(l), vh = pv(h);
+            const double wl = (double)L.cs[b][c], wh = (double)L.cs[b][h];
+            qc += (lo >= 0 ? wl : 0.0) * (pc - vl);
+            qc += (hi >= 0 ? wh : 0.0) * (pc - vh);
         }
         pnew[c] = (T)pc;
         q[c] = (T)qc;
@@ -693,7 +710,10 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
         return;
     }
     const double WB = sizeof(TB) - W;   // extra bytes of a wider right-hand side
-    LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
+    if ((lv.g.n[0] & 1) == 0)
+        LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth_pair<T, TB, DIM>), N / 2, st, lv, b, x, done);
+    else
+        LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
     LAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual<T, TB, DIM>), N, st, lv, b, (const T *)x, done);
     if (DIM == 3 && (S.lev[l + 1].g.n[0] & 1) == 0)
         LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict3_pair<T>), Nc / 2, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
