@@ -198,12 +198,16 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
         g->ch32.aug = g->mom32.aug = g->pres32.aug = aug;
         g->f_z = B.take<float>(N);
         g->f_t = B.take<float>(N);
+        g->f_r = B.take<float>(N);
     } else {
-        g->f_z = g->f_t = nullptr;
+        g->f_z = g->f_t = g->f_r = nullptr;
     }
     g->red.part0 = B.take<double>(kMaxBlocks);
     g->red.part1 = B.take<double>(kMaxBlocks);
     g->red.part2 = B.take<double>(kMaxBlocks);
+    g->red.rz0 = B.take<double>(kRedBlocks);
+    g->red.rz1 = B.take<double>(kRedBlocks);
+    g->red.rz2 = B.take<double>(kRedBlocks);
     g->diag = B.take<double>(8 * (size_t)kMaxBlocks + 16);
     g->red.counter = B.take<unsigned int>(64);
     g->red.scal = B.take<Scal>(1);
@@ -225,12 +229,16 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
             M.mom32.aug = maug;
             M.f_z = B.take<float>(N);
             M.f_t = B.take<float>(N);
+            M.f_r = B.take<float>(N);
         } else {
-            M.f_z = M.f_t = nullptr;
+            M.f_z = M.f_t = M.f_r = nullptr;
         }
         M.red.part0 = B.take<double>(kMaxBlocks);
         M.red.part1 = B.take<double>(kMaxBlocks);
         M.red.part2 = B.take<double>(kMaxBlocks);
+        M.red.rz0 = B.take<double>(kRedBlocks);
+        M.red.rz1 = B.take<double>(kRedBlocks);
+        M.red.rz2 = B.take<double>(kRedBlocks);
         M.red.counter = B.take<unsigned int>(64);
         M.red.scal = B.take<Scal>(1);
     }
@@ -248,7 +256,7 @@ struct SolveCtx {
     Slot<double> *S64;
     Slot<float> *S32;
     PcgVecs<double> v;
-    float *f_z, *f_t;
+    float *f_z, *f_t, *f_r;
     Red red;
     hipStream_t s;
 };
@@ -274,7 +282,7 @@ hipError_t run_solve_ctx(chns_grid *g, const SolveCtx &c, int setup, OpKind kind
         convert_level0(S64, S32, g->dim, c.s);
         mg_setup(S32, g->dim, c.s);
     }
-    const PcgVecs2<double, float> v2{v.r, v.p0, v.p1, v.q, v.t, c.f_z, c.f_t};
+    const PcgVecs2<double, float> v2{v.r, v.p0, v.p1, v.q, v.t, c.f_z, c.f_t, c.f_r};
     return refine_solve(S64, S32, g->dim, kind, ch, b, x, rtol, g->props.max_iter, &g->last_inner[pidx], red, v2,
                         c.s, o);
 }
@@ -287,6 +295,7 @@ SolveCtx main_ctx(chns_grid *g, int which) {
     c.v = vecs(g);
     c.f_z = g->f_z;
     c.f_t = g->f_t;
+    c.f_r = g->f_r;
     c.red = g->red;
     c.s = g->stream;
     return c;
@@ -302,6 +311,7 @@ SolveCtx mom_ctx(chns_grid *g, int a) {
     c.v = PcgVecs<double>{M.vr, M.vz, M.vp0, M.vp1, M.vq, M.vt};
     c.f_z = M.f_z;
     c.f_t = M.f_t;
+    c.f_r = M.f_r;
     c.red = M.red;
     c.s = M.stream;
     return c;

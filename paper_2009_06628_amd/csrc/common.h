@@ -174,6 +174,7 @@ __device__ inline double sum_partials(const double *part, int nparts, double *ld
 // ---------------------------------------------------------------------------
 struct Scal {
     double rz, pq, rr, bb, alpha, beta, rtol2, sum0, sum1, zmean;
+    double rzs[2];   // single-grid PCG: r.z of iteration k in rzs[k & 1]
     int done, iter, max_iter, nonfinite;
     int unconverged, pad0, pad1, pad2;
 };
@@ -208,6 +209,7 @@ struct Slot {
 // Reduction scratch shared by all solves of a handle.
 struct Red {
     double *part0, *part1, *part2;   // kMaxBlocks partials each
+    double *rz0, *rz1, *rz2;         // kRedBlocks partials each: r.z, sum z, sum r
     unsigned int *counter;     // last-block counters (several)
     Scal *scal;                // device scalars
 };
@@ -285,7 +287,7 @@ struct MomCtx {
     Slot<float> mom32;
     double *rhs;
     double *vr, *vz, *vp0, *vp1, *vq, *vt;
-    float *f_z, *f_t;
+    float *f_z, *f_t, *f_r;
     Red red;
     hipStream_t stream;
     hipEvent_t done_ev;   // recorded on stream after the solve
@@ -308,6 +310,7 @@ struct chns_grid {
     int prec;
     chns::Slot<float> ch32, mom32, pres32;
     float *f_z, *f_t;   // FP32 preconditioned vector and V-cycle scratch
+    float *f_r;         // FP32 copy of the CG residual (the V-cycle's right-hand side)
     int last_inner[12];
     chns::Red red;
     double *diag;                            // diagnostics scratch

@@ -32,6 +32,7 @@
 // kernel returns at once when the device "done" flag is set, so the host
 // launches iterations in chunks and checks the flag once per chunk.
 #include <cstdlib>
+#include <type_traits>
 
 #include "mgdev.h"
 #include "solvers.h"
@@ -339,16 +340,59 @@ __device__ inline double sum_parts_all(const double *__restrict__ part, int npar
     return block_sum_all(v, lds);
 }
 
+// Start of CG iteration k, evaluated by every block of the kernel that
+// consumes it (the sums are the same in every block): rz = r.(z - zmean)
+// from the partials of k_pcg_rz, zmean = mean(z) for a singular operator
+// (else 0), beta = rz / rz_previous (0 for k = 0).  For a singular
+// (pure Neumann / periodic) operator the preconditioned vector is projected
+// onto the range: the V-cycle amplifies the constant mode, and without the
+// projection rounding noise in that mode destroys the conjugacy of the
+// search directions.  Block 0 stores rz in sc->rzs[k & 1] while the blocks
+// read the previous value from the other entry, and publishes rz, zmean,
+// beta; a non-finite rz ends the solve.  Returns false when the solve ends.
+struct IterStart {
+    double rz, zm, beta;
+};
+__device__ inline bool iter_start(Scal *sc, const double *__restrict__ p0, const double *__restrict__ p1,
+                                  const double *__restrict__ p2, int nparts, long long N, int k, int singular,
+                                  double *lds, IterStart &o) {
+    const double trz = sum_parts_all(p0, nparts, lds);
+    const double tz = singular ? sum_parts_all(p1, nparts, lds) : 0.0;
+    const double tr = singular ? sum_parts_all(p2, nparts, lds) : 0.0;
+    o.zm = singular ? tz / (double)N : 0.0;
+    o.rz = trz - o.zm * tr;
+    const double prev = k > 0 ? sc->rzs[(k + 1) & 1] : 0.0;
+    o.beta = (k == 0 || prev == 0.0) ? 0.0 : o.rz / prev;
+    const bool ok = isfinite(o.rz);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ok) {
+            sc->rzs[k & 1] = o.rz;
+            sc->rz = o.rz;
+            sc->zmean = o.zm;
+            sc->beta = o.beta;
+        } else {
+            sc->nonfinite = 1;
+            sc->done = 1;
+        }
+    }
+    return ok;
+}
+
 // p_new = (z - zmean) + beta p_old (beta = 0: p_new = z - zmean);
 // q = A p_new (slot operator); partial p.q
 template <typename T, typename TZ, int DIM>
 __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ *__restrict__ z,
                                                            const T *__restrict__ pold, T *__restrict__ pnew,
-                                                           T *__restrict__ q, const Scal *__restrict__ sc,
-                                                           double *__restrict__ part) {
+                                                           T *__restrict__ q, Scal *sc, double *__restrict__ part,
+                                                           const double *__restrict__ rz0,
+                                                           const double *__restrict__ rz1,
+                                                           const double *__restrict__ rz2, int nrz, int k,
+                                                           int singular) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
-    const double beta = sc->beta, zm = sc->zmean;
+    IterStart it;
+    if (!iter_start(sc, rz0, rz1, rz2, nrz, L.g.N, k, singular, lds, it)) return;
+    const double beta = it.beta, zm = it.zm;
     auto pv = [&](int e) { return ((double)z[e] - zm) + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
     double acc = 0.0;
     GRID_LOOP(L.g.N) {
@@ -378,9 +422,13 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
 template <typename T, typename TZ, int DIM>
 __global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const TZ *__restrict__ z,
                                                        const T *__restrict__ pold, T *__restrict__ pnew,
-                                                       T *__restrict__ t, const Scal *__restrict__ sc) {
+                                                       T *__restrict__ t, Scal *sc, const double *__restrict__ rz0,
+                                                       int nrz, int k) {
     if (sc->done) return;
-    const double beta = sc->beta;
+    __shared__ double lds[kBlock / kWave];
+    IterStart it;
+    if (!iter_start(sc, rz0, rz0, rz0, nrz, g.N, k, 0, lds, it)) return;
+    const double beta = it.beta;
     auto pv = [&](int e) { return (double)z[e] + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
     GRID_LOOP(g.N) {
         int ia[3];
@@ -413,12 +461,13 @@ __global__ void __launch_bounds__(kBlock) k_pcg_ch_apply(Geo g, double ih2, doub
 }
 
 // alpha = rz / sum(part_pq) (every block, same order); x += alpha p;
-// r -= alpha q; partial r.r
-template <typename T>
+// r -= alpha q; partial r.r.  TP != T: also rp = r rounded to TP (the
+// right-hand side of the preconditioner in its own precision).
+template <typename T, typename TP = T>
 __global__ void __launch_bounds__(kBlock) k_pcg_update(int N, const T *__restrict__ p, const T *__restrict__ q,
                                                        T *__restrict__ x, T *__restrict__ r, Scal *sc,
                                                        const double *__restrict__ part_pq, int nparts,
-                                                       double *__restrict__ part_rr) {
+                                                       double *__restrict__ part_rr, TP *__restrict__ rp = nullptr) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
     const double pq = sum_parts_all(part_pq, nparts, lds);
@@ -432,10 +481,17 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(int N, const T *__restric
         x[c] = (T)((double)x[c] + alpha * (double)p[c]);
         const double rc = (double)r[c] - alpha * (double)q[c];
         r[c] = (T)rc;
+        if constexpr (!std::is_same<T, TP>::value) rp[c] = (TP)(T)rc;
         acc += rc * rc;
     }
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// rp = r rounded to the preconditioner's precision
+template <typename T, typename TP>
+__global__ void __launch_bounds__(kBlock) k_round_vec(int N, const T *__restrict__ r, TP *__restrict__ rp) {
+    GRID_LOOP(N) rp[c] = (TP)r[c];
 }
 
 // one workgroup: rr = sum(part_rr); iteration count; convergence flag
@@ -479,33 +535,6 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rz(int N, const T *__restrict__ 
         p0[blockIdx.x] = s0;
         p1[blockIdx.x] = s1;
         p2[blockIdx.x] = s2;
-    }
-}
-
-// One workgroup: rz_new = r.(z - zmean), beta = rz_new / rz (0 on the first
-// call).  For a singular (pure Neumann / periodic) operator the
-// preconditioned vector is projected onto the range: zmean = mean(z),
-// otherwise 0.  The V-cycle amplifies the constant mode, and without the
-// projection rounding noise in that mode destroys the conjugacy of the
-// search directions.
-__global__ void __launch_bounds__(kBlock) k_pcg_fin_rz(Scal *sc, const double *__restrict__ p0,
-                                                       const double *__restrict__ p1, const double *__restrict__ p2,
-                                                       int nparts, int N, int first, int singular) {
-    if (sc->done) return;
-    __shared__ double lds[kBlock / kWave];
-    const double trz = sum_parts_all(p0, nparts, lds);
-    const double tz = singular ? sum_parts_all(p1, nparts, lds) : 0.0;
-    const double tr = singular ? sum_parts_all(p2, nparts, lds) : 0.0;
-    if (threadIdx.x == 0) {
-        const double zm = singular ? tz / (double)N : 0.0;
-        const double rz = trz - zm * tr;
-        sc->zmean = zm;
-        sc->beta = (first || sc->rz == 0.0) ? 0.0 : rz / sc->rz;
-        sc->rz = rz;
-        if (!isfinite(rz)) {
-            sc->nonfinite = 1;
-            sc->done = 1;
-        }
     }
 }
 
@@ -858,11 +887,15 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
             return hipGetLastError();
         }
     }
-    precond_d<T, TP, DIM>(SP, kind, v.r, v.z, v.w, done, st);
+    // With a lower-precision hierarchy the V-cycle reads the residual
+    // already rounded to its precision (the value its sweeps would round it
+    // to), so the level-0 passes read 4 instead of 8 bytes per cell of it.
+    constexpr bool split = !std::is_same<T, TP>::value;
+    const TP *rpre = split ? (const TP *)v.rp : (const TP *)(const void *)v.r;
+    if (split) LAUNCH(K_PCG_INIT, (W + WP) * N, (k_round_vec<T, TP>), N, st, N, (const T *)v.r, v.rp);
+    precond_d<TP, TP, DIM>(SP, kind, rpre, v.z, v.w, done, st);
     LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z, (const Scal *)sc,
-           red.part0, red.part1, red.part2, singular);
-    LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
-            (const double *)red.part1, (const double *)red.part2, nb, N, 1, singular);
+           red.rz0, red.rz1, red.rz2, singular);
     int launched = 0;
     int chunk = predict < 1 ? 1 : predict;
     for (;;) {
@@ -871,23 +904,24 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
             const int k = launched + it;
             T *pnew = (k & 1) ? v.p1 : v.p0;
             T *pold = (k & 1) ? v.p0 : v.p1;
+            // the consumer of the r.z partials starts the iteration (beta)
             if (kind == OP_SLOT) {
                 LAUNCHR(K_PCG_APPLY, W * (4 + DIM) * N + WP * N, (k_pcg_apply_slot<T, TP, DIM>), N, st, L0,
-                       (const TP *)v.z, (const T *)pold, pnew, v.q, (const Scal *)sc, red.part0);
+                        (const TP *)v.z, (const T *)pold, pnew, v.q, sc, red.part0, (const double *)red.rz0,
+                        (const double *)red.rz1, (const double *)red.rz2, nb, k, singular);
             } else {
-                LAUNCH(K_PCG_APPLY, W * 3 * N + WP * N, (k_pcg_ch_lap<T, TP, DIM>), N, st, g, ch.ih2, (const TP *)v.z,
-                       (const T *)pold, pnew, v.t, (const Scal *)sc);
+                LAUNCHR(K_PCG_APPLY, W * 3 * N + WP * N, (k_pcg_ch_lap<T, TP, DIM>), N, st, g, ch.ih2,
+                        (const TP *)v.z, (const T *)pold, pnew, v.t, sc, (const double *)red.rz0, nb, k);
                 LAUNCHR(K_PCG_APPLY, W * 3 * N, (k_pcg_ch_apply<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, (const T *)pnew,
                        (const T *)v.t, v.q, (const Scal *)sc, red.part0);
             }
-            LAUNCHR(K_PCG_UPDATE, W * 6 * N, (k_pcg_update<T>), N, st, N, (const T *)pnew, (const T *)v.q, x, v.r, sc,
-                   (const double *)red.part0, nb, red.part1);
+            LAUNCHR(K_PCG_UPDATE, W * 6 * N + (split ? WP * N : 0.0), (k_pcg_update<T, TP>), N, st, N,
+                    (const T *)pnew, (const T *)v.q, x, v.r, sc, (const double *)red.part0, nb, red.part1,
+                    split ? v.rp : (TP *)nullptr);
             LAUNCH1(K_PCG_UPDATE, 8.0 * nb, (k_pcg_fin_rr), kBlock, st, sc, (const double *)red.part1, nb);
-            precond_d<T, TP, DIM>(SP, kind, v.r, v.z, v.w, done, st);
+            precond_d<TP, TP, DIM>(SP, kind, rpre, v.z, v.w, done, st);
             LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
-                   (const Scal *)sc, red.part0, red.part1, red.part2, singular);
-            LAUNCH1(K_PCG_DOT, 24.0 * nb, (k_pcg_fin_rz), kBlock, st, sc, (const double *)red.part0,
-                    (const double *)red.part1, (const double *)red.part2, nb, N, 0, singular);
+                    (const Scal *)sc, red.rz0, red.rz1, red.rz2, singular);
         }
         launched += chunk;
         hipError_t e = hipMemcpyAsync(&hs, sc, sizeof(Scal), hipMemcpyDeviceToHost, st);
@@ -908,7 +942,7 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
 template <typename T>
 hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x, double rtol, int max_iter,
                      int predict, Red &red, PcgVecs<T> &v, hipStream_t st, SolveOut *out, int zero_guess) {
-    const PcgVecs2<T, T> v2{v.r, v.p0, v.p1, v.q, v.t, v.z, v.t};
+    const PcgVecs2<T, T> v2{v.r, v.p0, v.p1, v.q, v.t, v.z, v.t, nullptr};
     if (dim == 2) return pcg_d<T, T, 2>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess);
     return pcg_d<T, T, 3>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess);
 }

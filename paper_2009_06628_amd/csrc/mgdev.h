@@ -421,13 +421,12 @@ __device__ inline void gs_at(const Level<T> &L, int c, const int ia[3]) {
 }
 
 // V-cycle over levels [l0, nlev), l0 >= 1, on the LDS image of their
-// storage.  The arithmetic is that of vcycle_block_dev, but with LDS
-// barriers being cheap the fused passes are split by colour so that no
-// value is recomputed and no wave runs both colours' branches:
-//   pre-smoothing  red x = b / d | black GS   (the black update reads the
-//                  stored red values, which equal the b / d products the
-//                  fused pass recomputes)
-//   post-smoothing red x += P e | black GS | red GS
+// storage.  The arithmetic is that of vcycle_block_dev, with each pass
+// enumerating the cells of one colour (no wave runs both colours' branches):
+//   pre-smoothing  the k-th red (x = b / d) and the k-th black cell (GS from
+//                  its red neighbours' b / d) in one pass
+//   post-smoothing red x += P e | black GS | red GS  (no prolonged value is
+//                  recomputed, unlike the fused pass of the grid kernels)
 // Ends with a workgroup barrier.
 template <typename T, int DIM>
 __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
@@ -436,16 +435,16 @@ __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const
     for (int l = l0; l < L - 1; ++l) {
         const Level<T> lv = lds_level<T, DIM>(S.lev[l], lds, base);
         const Level<T> lc = lds_level<T, DIM>(S.lev[l + 1], lds, base);
+        // zero-guess smoothing: the k-th red and the k-th black cell in one
+        // pass; the black update evaluates its red neighbours' b / d itself
         LDS_COLOR_LOOP(lv.g.N) {
             int ia[3];
             const int c = color_cell<DIM>(lv.g, k, 0, ia);
             lv.x[c] = (T)((R)lv.b[c] * (R)lv.invd[c]);
-        }
-        __syncthreads();
-        LDS_COLOR_LOOP(lv.g.N) {
-            int ia[3];
-            const int c = color_cell<DIM>(lv.g, k, 1, ia);
-            gs_at<T, DIM>(lv, c, ia);
+            int ib[3];
+            const int cb = color_cell<DIM>(lv.g, k, 1, ib);
+            auto red = [&](int e) { return (R)lv.b[e] * (R)lv.invd[e]; };
+            lv.x[cb] = (T)(((R)lv.b[cb] + offsum_at<T, DIM>(lv, cb, ib, red)) * (R)lv.invd[cb]);
         }
         __syncthreads();
         LDS_LOOP(lv.g.N) residual_cell<T, T, DIM>(lv, lv.b, lv.x, c);

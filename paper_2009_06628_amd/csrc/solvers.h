@@ -17,6 +17,7 @@ template <typename T, typename TP>
 struct PcgVecs2 {
     T *r, *p0, *p1, *q, *t;
     TP *z, *w;
+    TP *rp;   // the residual rounded to the preconditioner's precision (TP != T only)
 };
 
 struct SolveOut {
