@@ -676,15 +676,46 @@ int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_i
     unconv |= o.unconverged ? 16 : 0;
     remove_mean(geo, A.zeta, g->red, s);
     adj_proj_faces(dim, geo, k, g->phi_new, A.p_t, A.zeta, ubar, A, uout, s);
-    // reverse of S7..S5, one velocity component at a time
-    for (int a = 0; a < dim; ++a) {
-        Level<double> &L0 = g->mom.lev[0];
-        double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-        launch_mom_setup(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, L0.s, cs, g->rhs, g->ustar[a], s, 1);
-        HIPCHK(run_solve(g, 1, OP_SLOT, ch, (const double *)A.usb[a], A.nu[a], p.rtol_mom, 7 + a, &o));
-        if (int rc = check_solve(o, "adjoint momentum")) return rc;
-        unconv |= o.unconverged ? (2 << a) : 0;
-        adj_mom(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, usc, A, uout, s);
+    // reverse of S7..S5: K_a nu_a = ubar*_a for every component (the forward
+    // operators; independent, so they run like the forward momentum solves,
+    // on the components' streams when allowed), then the gathers of each
+    // component in order (they accumulate into shared adjoint fields)
+    {
+        const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum();
+        SolveOut om[3];
+        hipError_t em[3] = {hipSuccess, hipSuccess, hipSuccess};
+        auto nu_solve = [&](int a, hipStream_t sa) {
+            SolveCtx c = mom_ctx(g, a);
+            c.s = sa;
+            if (a > 0 && concurrent) {
+                em[a] = hipStreamWaitEvent(sa, g->ev_fork, 0);
+                if (em[a] != hipSuccess) return;
+            }
+            Level<double> &L0 = c.S64->lev[0];
+            double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
+            double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, L0.s, cs, rhs, g->ustar[a], sa, 1);
+            em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)A.usb[a], A.nu[a], p.rtol_mom, 7 + a, &om[a]);
+            if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, sa);
+        };
+        if (concurrent) {
+            HIPCHK(hipEventRecord(g->ev_fork, s));
+            std::thread workers[2];
+            for (int a = 1; a < dim; ++a) workers[a - 1] = std::thread(nu_solve, a, g->mc[a - 1].stream);
+            nu_solve(0, s);
+            for (int a = 1; a < dim; ++a) workers[a - 1].join();
+            for (int a = 1; a < dim; ++a)
+                if (em[a] == hipSuccess) em[a] = hipStreamWaitEvent(s, g->mc[a - 1].done_ev, 0);
+        } else {
+            for (int a = 0; a < dim && (a == 0 || em[a - 1] == hipSuccess); ++a) nu_solve(a, s);
+        }
+        for (int a = 0; a < dim; ++a) {
+            if (em[a] != hipSuccess)
+                return fail(CHNS_EDEVICE, std::string("adjoint momentum solve: ") + hipGetErrorString(em[a]));
+            if (int rc = check_solve(om[a], "adjoint momentum")) return rc;
+            unconv |= om[a].unconverged ? (2 << a) : 0;
+        }
+        for (int a = 0; a < dim; ++a) adj_mom(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, usc, A, uout, s);
     }
     // reverse of the density / viscosity maps, S4 and S3
     adj_rho_flux_mu(dim, geo, k, phi, g->phi_new, A.mu_t, uc, phibar_in, A, uout, phibar_out, s);
