@@ -208,6 +208,31 @@ typedef struct {
 int chns_adjoint_step(struct chns_grid *g, const chns_state *fwd, const chns_adj *lam_in, chns_adj *lam_out,
                       double grad_params[2]);
 
+/* The forward fields of one step that its reverse step reads (device arrays
+ * of the grid's layout, caller-owned): phihat (S2), phi_new = phi^{n+1}
+ * (S4), mu = mu^{n+1} (S3), p = p^{n+1} (S8) in cell arrays, ustar[a] = u*
+ * (S7) in the face arrays of component a (ustar[2] NULL in 2D).          */
+typedef struct {
+    void *phihat, *phi_new, *mu, *p;
+    void *ustar[3];
+} chns_record;
+
+/* chns_step with nsteps = 1 that also copies the step's forward fields into
+ * rec (for chns_adjoint_step_recorded; checkpointed reverse passes that
+ * re-run a segment record its steps instead of recomputing them again in
+ * every reverse step).  Same return codes as chns_step.                    */
+int chns_step_record(struct chns_grid *g, chns_state *st, const chns_record *rec);
+
+/* chns_adjoint_step with the forward fields of the step taken from rec,
+ * written by chns_step_record from the state fwd under the same properties,
+ * instead of recomputing S1..S8 (fwd->p is not read).  The step's forward
+ * fields are a function of fwd alone (every solve starts from a guess built
+ * from fwd), so the result equals chns_adjoint_step's bit for bit.
+ * Argument rules, accumulation into grad_params and return codes as for
+ * chns_adjoint_step.                                                      */
+int chns_adjoint_step_recorded(struct chns_grid *g, const chns_state *fwd, const chns_record *rec,
+                               const chns_adj *lam_in, chns_adj *lam_out, double grad_params[2]);
+
 /* ---- batched ensemble -------------------------------------------------
  * Many independent problems of uneven size (same dim and precision) advanced
  * together: one persistent kernel per time step in which each workgroup

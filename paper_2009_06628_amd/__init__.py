@@ -61,6 +61,11 @@ class chns_adj(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_void_p), ("u", ctypes.c_void_p * 3)]
 
 
+class chns_record(ctypes.Structure):
+    _fields_ = [("phihat", ctypes.c_void_p), ("phi_new", ctypes.c_void_p), ("mu", ctypes.c_void_p),
+                ("p", ctypes.c_void_p), ("ustar", ctypes.c_void_p * 3)]
+
+
 class chns_batch_stats(ctypes.Structure):
     _fields_ = [("iters_ch", ctypes.c_int), ("iters_mom", ctypes.c_int * 3), ("iters_p", ctypes.c_int),
                 ("flags", ctypes.c_int), ("steps", ctypes.c_int), ("pad", ctypes.c_int),
@@ -102,6 +107,10 @@ EXPORTS = {
     "chns_attach_adjoint_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "chns_adjoint_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.POINTER(chns_adj),
                                          ctypes.POINTER(chns_adj), ctypes.POINTER(ctypes.c_double)]),
+    "chns_step_record": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.POINTER(chns_record)]),
+    "chns_adjoint_step_recorded": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state),
+                                                  ctypes.POINTER(chns_record), ctypes.POINTER(chns_adj),
+                                                  ctypes.POINTER(chns_adj), ctypes.POINTER(ctypes.c_double)]),
     "chns_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(chns_grid_desc),
                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "chns_create_batch": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(chns_grid_desc), ctypes.POINTER(chns_props),
@@ -324,6 +333,44 @@ class Grid:
         li, lo = self._cadj(lam_in), self._cadj(lam_out)
         rc = self._lib.chns_adjoint_step(self._h, ctypes.byref(cs), ctypes.byref(li), ctypes.byref(lo), grad)
         return _check(rc, "chns_adjoint_step", allow_noconv)
+
+    def new_record(self) -> Dict:
+        """Device buffers for the forward fields of one step (chns_record)."""
+        torch = _torch()
+        z = lambda: torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        return {"phihat": z(), "phi_new": z(), "mu": z(), "p": z(), "ustar": [z() for _ in range(self.dim)]}
+
+    def _crec(self, rec: Dict) -> chns_record:
+        cr = chns_record()
+        cr.phihat, cr.phi_new = _ptr(rec["phihat"]), _ptr(rec["phi_new"])
+        cr.mu, cr.p = _ptr(rec["mu"]), _ptr(rec["p"])
+        for a in range(3):
+            cr.ustar[a] = _ptr(rec["ustar"][a]) if a < self.dim else None
+        return cr
+
+    def step_record(self, st: Dict, rec: Dict, allow_noconv: bool = False) -> int:
+        """One step (chns_step_record) that also stores its forward fields in
+        rec (from new_record)."""
+        cs = self._cstate(st)
+        rc = self._lib.chns_step_record(self._h, ctypes.byref(cs), ctypes.byref(self._crec(rec)))
+        return _check(rc, "chns_step_record", allow_noconv)
+
+    def adjoint_step_recorded(self, fwd: Dict, rec: Dict, lam_in: Dict, lam_out: Dict, grad=None,
+                              allow_noconv: bool = False) -> int:
+        """One reverse step from the recorded forward fields of the step that
+        started at fwd (chns_adjoint_step_recorded)."""
+        if getattr(self, "adj_workspace", None) is None:
+            self.attach_adjoint()
+        cs = chns_state()
+        cs.phi = _ptr(fwd["phi"])
+        for a in range(3):
+            cs.u[a] = _ptr(fwd["u"][a]) if a < self.dim else None
+        cs.p = None
+        cs.mu = None
+        li, lo = self._cadj(lam_in), self._cadj(lam_out)
+        rc = self._lib.chns_adjoint_step_recorded(self._h, ctypes.byref(cs), ctypes.byref(self._crec(rec)),
+                                                  ctypes.byref(li), ctypes.byref(lo), grad)
+        return _check(rc, "chns_adjoint_step_recorded", allow_noconv)
 
     # -- per-kernel timing ------------------------------------------------------
     def set_timing(self, enable: bool) -> None:

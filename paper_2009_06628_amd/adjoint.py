@@ -5,9 +5,11 @@ checkpointing.
 The forward pass advances ``nsteps`` steps and keeps the state (phi, u, p)
 only every ``checkpoint_every`` steps.  The backward pass walks the segments
 in reverse: it re-runs the forward steps of a segment from its checkpoint,
-keeping the segment's states, then applies the adjoint step to them in
-reverse order.  Forward and recomputation run the same kernels on the same
-inputs, so the gradient does not depend on ``checkpoint_every`` (bit for bit).
+keeping the segment's states and recording each step's forward fields
+(``Grid.step_record``), then applies the reverse step to them in reverse
+order (``Grid.adjoint_step_recorded``), so no step is computed a third time.
+Forward and recomputation run the same kernels on the same inputs, so the
+gradient does not depend on ``checkpoint_every`` (bit for bit).
 
 Differentiable inputs: the initial phi field, the initial velocity, and the
 surface tension sigma and mobility M, which enter the properties as
@@ -86,17 +88,17 @@ class CHNSRollout:
                              for g in gu]}
                 grad = (ctypes.c_double * 2)(0.0, 0.0)
                 nseg = len(ctx.checkpoints)
+                recs = [grid.new_record() for _ in range(min(ctx.every, ctx.nsteps))]
                 for seg in reversed(range(nseg)):
                     start = seg * ctx.every
                     end = min(start + ctx.every, ctx.nsteps)
-                    states = [ctx.checkpoints[seg]]
-                    if end - start > 1:
-                        st = _restore(grid, ctx.checkpoints[seg])
-                        for _ in range(start + 1, end):
-                            grid.step(st, 1, stats=False)
-                            states.append(_snapshot(st))
-                    for fwd in reversed(states):
-                        grid.adjoint_step(fwd, lam, lam, grad)
+                    st = _restore(grid, ctx.checkpoints[seg])
+                    states = []
+                    for i in range(end - start):
+                        states.append({"phi": st["phi"].clone(), "u": [x.clone() for x in st["u"]]})
+                        grid.step_record(st, recs[i])
+                    for i in reversed(range(end - start)):
+                        grid.adjoint_step_recorded(states[i], recs[i], lam, lam, grad)
                 dtype, device = ctx.params_meta
                 gparams = torch.tensor([grad[0], grad[1]], dtype=dtype, device=device)
                 return (None, None, None, None, gparams, lam["phi"], *lam["u"])

@@ -632,15 +632,17 @@ int chns_attach_adjoint_workspace(chns_grid *g, void *workspace, size_t bytes) {
     return CHNS_OK;
 }
 
-int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_in, chns_adj *lam_out,
-                      double grad_params[2]) {
-    if (!g || !fwd || !lam_in || !lam_out) return fail(CHNS_EINVAL, "NULL argument");
-    if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
-    if (!g->adj_ready) return fail(CHNS_EINVAL, "chns_attach_adjoint_workspace must be called first");
-    if (!fwd->phi || !fwd->p || !lam_in->phi || !lam_out->phi) return fail(CHNS_EINVAL, "state pointer is NULL");
-    for (int a = 0; a < g->dim; ++a)
-        if (!fwd->u[a] || !lam_in->u[a] || !lam_out->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
-    ProfScope prof_scope(g);
+// Forward fields of one step that the reverse step reads.
+struct FwdFields {
+    const double *phihat, *phi_new, *mu, *p;   // S2, S4, S3 (mu^{n+1}), S8 (p^{n+1})
+    const double *ustar[3];                     // S7
+};
+
+// The reverse of S9 .. S1 (A1 .. A15) of the step from the state fwd, given
+// that step's forward fields F.  The pressure slot must hold the operator of
+// that step.  unconv: unconverged bits of the forward recomputation.
+static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F, const chns_adj *lam_in,
+                        chns_adj *lam_out, double grad_params[2], int unconv) {
     const int dim = g->dim;
     const Geo &geo = g->geo;
     const StepConst k = step_const(g);
@@ -650,32 +652,22 @@ int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_i
     const double *phi = (const double *)fwd->phi;
     const double *uc[3] = {(const double *)fwd->u[0], (const double *)fwd->u[1],
                            dim == 3 ? (const double *)fwd->u[2] : nullptr};
-    const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
     const double *ubar[3] = {(const double *)lam_in->u[0], (const double *)lam_in->u[1],
                              dim == 3 ? (const double *)lam_in->u[2] : nullptr};
     double *uout[3] = {(double *)lam_out->u[0], (double *)lam_out->u[1], dim == 3 ? (double *)lam_out->u[2] : nullptr};
     const double *phibar_in = (const double *)lam_in->phi;
     double *phibar_out = (double *)lam_out->phi;
     const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
-
-    // Forward recomputation of S1..S8 from the stored state (the pressure
-    // solve starts from the stored p, as the original step did).
-    HIPCHK(hipMemcpyAsync(A.p_t, fwd->p, sizeof(double) * geo.N, hipMemcpyDeviceToDevice, s));
-    chns_step_stats last;
-    memset(&last, 0, sizeof last);
-    if (int rc = forward_core(g, phi, uc, A.mu_t, A.p_t, last)) return rc;
-    int unconv = last.unconverged;
-
     SolveOut o;
     // reverse of S9 and S8: adjoint pressure solve (the pressure slot still
     // holds the operator of the recomputed step)
-    adj_p_rhs(dim, geo, k, g->phi_new, ubar, A.pbar, A.zeta, s);
+    adj_p_rhs(dim, geo, k, F.phi_new, ubar, A.pbar, A.zeta, s);
     remove_mean(geo, A.pbar, g->red, s);
     HIPCHK(run_solve(g, 2, OP_SLOT, ch, (const double *)A.pbar, A.zeta, p.rtol_p, 10, &o));
     if (int rc = check_solve(o, "adjoint pressure")) return rc;
     unconv |= o.unconverged ? 16 : 0;
     remove_mean(geo, A.zeta, g->red, s);
-    adj_proj_faces(dim, geo, k, g->phi_new, A.p_t, A.zeta, ubar, A, uout, s);
+    adj_proj_faces(dim, geo, k, F.phi_new, F.p, A.zeta, ubar, A, uout, s);
     // reverse of S7..S5: K_a nu_a = ubar*_a for every component (the forward
     // operators; independent, so they run like the forward momentum solves,
     // on the components' streams when allowed), then the gathers of each
@@ -694,7 +686,7 @@ int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_i
             Level<double> &L0 = c.S64->lev[0];
             double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
             double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, L0.s, cs, rhs, g->ustar[a], sa, 1);
+            launch_mom_setup(dim, geo, k, a, phi, F.phi_new, F.mu, uc, L0.s, cs, rhs, g->ustar[a], sa, 1);
             em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)A.usb[a], A.nu[a], p.rtol_mom, 7 + a, &om[a]);
             if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, sa);
         };
@@ -715,12 +707,12 @@ int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_i
             if (int rc = check_solve(om[a], "adjoint momentum")) return rc;
             unconv |= om[a].unconverged ? (2 << a) : 0;
         }
-        for (int a = 0; a < dim; ++a) adj_mom(dim, geo, k, a, phi, g->phi_new, A.mu_t, uc, usc, A, uout, s);
+        for (int a = 0; a < dim; ++a) adj_mom(dim, geo, k, a, phi, F.phi_new, F.mu, uc, F.ustar, A, uout, s);
     }
     // reverse of the density / viscosity maps, S4 and S3
-    adj_rho_flux_mu(dim, geo, k, phi, g->phi_new, A.mu_t, uc, phibar_in, A, uout, phibar_out, s);
+    adj_rho_flux_mu(dim, geo, k, phi, F.phi_new, F.mu, uc, phibar_in, A, uout, phibar_out, s);
     // reverse of S2 (adjoint CH solve) and S1
-    adj_ch_rhs(dim, geo, k, g->phihat, A, s);
+    adj_ch_rhs(dim, geo, k, F.phihat, A, s);
     HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)A.chr, A.omega, p.rtol_ch, 6, &o));
     if (int rc = check_solve(o, "adjoint Cahn-Hilliard")) return rc;
     unconv |= o.unconverged ? 1 : 0;
@@ -742,6 +734,75 @@ int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_i
         return CHNS_ENOCONV;
     }
     return CHNS_OK;
+}
+
+int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_in, chns_adj *lam_out,
+                      double grad_params[2]) {
+    if (!g || !fwd || !lam_in || !lam_out) return fail(CHNS_EINVAL, "NULL argument");
+    if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
+    if (!g->adj_ready) return fail(CHNS_EINVAL, "chns_attach_adjoint_workspace must be called first");
+    if (!fwd->phi || !fwd->p || !lam_in->phi || !lam_out->phi) return fail(CHNS_EINVAL, "state pointer is NULL");
+    for (int a = 0; a < g->dim; ++a)
+        if (!fwd->u[a] || !lam_in->u[a] || !lam_out->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
+    ProfScope prof_scope(g);
+    AdjBufs &A = g->adj;
+    const double *phi = (const double *)fwd->phi;
+    const double *uc[3] = {(const double *)fwd->u[0], (const double *)fwd->u[1],
+                           g->dim == 3 ? (const double *)fwd->u[2] : nullptr};
+    // Forward recomputation of S1..S8 from the stored state (the pressure
+    // solve starts from the stored p, as the original step did).
+    HIPCHK(hipMemcpyAsync(A.p_t, fwd->p, sizeof(double) * g->geo.N, hipMemcpyDeviceToDevice, g->stream));
+    chns_step_stats last;
+    memset(&last, 0, sizeof last);
+    if (int rc = forward_core(g, phi, uc, A.mu_t, A.p_t, last)) return rc;
+    const FwdFields F{g->phihat, g->phi_new, A.mu_t, A.p_t, {g->ustar[0], g->ustar[1], g->ustar[2]}};
+    return adjoint_core(g, fwd, F, lam_in, lam_out, grad_params, last.unconverged);
+}
+
+static int check_record(const chns_grid *g, const chns_record *rec) {
+    if (!rec) return fail(CHNS_EINVAL, "record is NULL");
+    if (!rec->phihat || !rec->phi_new || !rec->mu || !rec->p) return fail(CHNS_EINVAL, "record pointer is NULL");
+    for (int a = 0; a < g->dim; ++a)
+        if (!rec->ustar[a]) return fail(CHNS_EINVAL, "record velocity pointer is NULL");
+    return CHNS_OK;
+}
+
+int chns_step_record(chns_grid *g, chns_state *st, const chns_record *rec) {
+    if (!g) return fail(CHNS_EINVAL, "NULL argument");
+    if (int rc = check_record(g, rec)) return rc;
+    const int rc = chns_step(g, st, 1, nullptr);
+    if (rc != CHNS_OK && rc != CHNS_ENOCONV) return rc;
+    hipStream_t s = g->stream;
+    const size_t bytes = sizeof(double) * g->geo.N;
+    HIPCHK(hipMemcpyAsync(rec->phihat, g->phihat, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rec->phi_new, g->phi_new, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rec->mu, st->mu, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(rec->p, st->p, bytes, hipMemcpyDeviceToDevice, s));
+    for (int a = 0; a < g->dim; ++a)
+        HIPCHK(hipMemcpyAsync(rec->ustar[a], g->ustar[a], bytes, hipMemcpyDeviceToDevice, s));
+    return rc;
+}
+
+int chns_adjoint_step_recorded(chns_grid *g, const chns_state *fwd, const chns_record *rec, const chns_adj *lam_in,
+                               chns_adj *lam_out, double grad_params[2]) {
+    if (!g || !fwd || !lam_in || !lam_out) return fail(CHNS_EINVAL, "NULL argument");
+    if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
+    if (!g->adj_ready) return fail(CHNS_EINVAL, "chns_attach_adjoint_workspace must be called first");
+    if (!fwd->phi || !lam_in->phi || !lam_out->phi) return fail(CHNS_EINVAL, "state pointer is NULL");
+    for (int a = 0; a < g->dim; ++a)
+        if (!fwd->u[a] || !lam_in->u[a] || !lam_out->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
+    if (int rc = check_record(g, rec)) return rc;
+    ProfScope prof_scope(g);
+    // the pressure operator of the recorded step (S8 set-up from its
+    // phi^{n+1} and u*; the right-hand side it also writes is not used)
+    Level<double> &L0 = g->pres.lev[0];
+    double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+    const double *usr[3] = {(const double *)rec->ustar[0], (const double *)rec->ustar[1],
+                            g->dim == 3 ? (const double *)rec->ustar[2] : nullptr};
+    launch_p_setup(g->dim, g->geo, step_const(g), (const double *)rec->phi_new, usr, L0.s, cs, g->rhs, g->stream);
+    const FwdFields F{(const double *)rec->phihat, (const double *)rec->phi_new, (const double *)rec->mu,
+                      (const double *)rec->p, {usr[0], usr[1], usr[2]}};
+    return adjoint_core(g, fwd, F, lam_in, lam_out, grad_params, 0);
 }
 
 int chns_solve_pressure(chns_grid *g, const void *rho, const void *rhs, void *p, double rtol, int max_iter,

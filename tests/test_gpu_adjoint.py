@@ -15,6 +15,7 @@ Checks, in order of locality:
 Bar: relative agreement 1e-6.  Forward solves run at relative residuals of
 1e-13 .. 1e-15 so that solver noise divided by the step stays far below it.
 """
+import ctypes
 import os
 
 import numpy as np
@@ -280,6 +281,44 @@ def test_oscillating_drop_128_finite_differences(steps, ndirs):
           "cells crossing |phi|=1 between FD runs:", kinks, flush=True)
     for k, (a, f) in res.items():
         assert rel(a, f) <= TOL, (k, a, f)
+
+
+@pytest.mark.parametrize("name", ["bubble_walls", "drop3d"])
+def test_recorded_reverse_step_matches_recomputing(name):
+    """chns_adjoint_step_recorded (forward fields recorded by
+    chns_step_record) equals chns_adjoint_step (which recomputes S1..S8)
+    bit for bit, over three reverse steps with a warm-started adjoint."""
+    P = _lib()
+    prob = W.rising_bubble(32, steps=3) if name == "bubble_walls" else W.drop3d(16, steps=3)
+    if name == "bubble_walls":
+        prob.init_args = dict(prob.init_args, velocity="stream", vseed=3, vamp=0.05)
+    init = W.initial_state(prob)
+    g = P.grid_for_problem(prob)
+    st = g.new_state(init)
+    states, recs = [], []
+    for _ in range(3):
+        states.append({"phi": st["phi"].clone(), "u": [x.clone() for x in st["u"]], "p": st["p"].clone()})
+        rec = g.new_record()
+        g.step_record(st, rec)
+        recs.append(rec)
+    rng = np.random.default_rng(8)
+    lam0 = {"phi": dev(rng.normal(size=prob.shape)), "u": [dev(rng.normal(size=prob.shape)) for _ in st["u"]]}
+    outs = []
+    for recorded in (False, True):
+        lam = {"phi": lam0["phi"].clone(), "u": [x.clone() for x in lam0["u"]]}
+        grad = (ctypes.c_double * 2)(0.0, 0.0)
+        for i in reversed(range(3)):
+            if recorded:
+                g.adjoint_step_recorded(states[i], recs[i], lam, lam, grad)
+            else:
+                g.adjoint_step(states[i], lam, lam, grad)
+        torch.cuda.synchronize()
+        outs.append((lam, (grad[0], grad[1])))
+    (la, ga), (lb, gb) = outs
+    assert torch.equal(la["phi"], lb["phi"])
+    for d in range(len(la["u"])):
+        assert torch.equal(la["u"][d], lb["u"][d]), d
+    assert ga == gb, (ga, gb)
 
 
 def test_adjoint_step_argument_errors():
