@@ -83,15 +83,18 @@ def test_precision_form_drops3d_vs_oracle():
     assert max(e.values()) <= 1e-5
 
 
-def test_precision_form_drops3d_128_vs_fp64():
+@pytest.mark.parametrize("steps", [10, 500])
+def test_precision_form_drops3d_128_vs_fp64(steps):
     """Full 128^3 drop configuration, precision form at its own (looser)
     tolerances vs the FP64 GPU path at the parity tolerances after 10 steps
-    (the oracle is too slow at this size): within 1e-5, mass to 1e-12."""
+    and after the configuration's 500 steps (the oracle is too slow at this
+    size; the FP64 path is pinned to it on the smaller grids): within 1e-5,
+    mass to 1e-12."""
     import paper_2009_06628_amd as P
-    prob = W.drops3d(128, steps=10)
-    _, s64, st64 = run(prob, 10, P.CHNS_FP64)
-    prob32 = W.drops3d(128, steps=10, **W.PRECISION_FORM_TOLERANCES)
-    _, s32, st32 = run(prob32, 10, P.CHNS_FP32_REFINE)
+    prob = W.drops3d(128, steps=steps)
+    _, s64, st64 = run(prob, steps, P.CHNS_FP64)
+    prob32 = W.drops3d(128, steps=steps, **W.PRECISION_FORM_TOLERANCES)
+    _, s32, st32 = run(prob32, steps, P.CHNS_FP32_REFINE)
     so = {"phi": to_np(s64["phi"]), "u": [to_np(x) for x in s64["u"]], "p": to_np(s64["p"])}
     e = errs(s32, so, 3)
     assert max(e.values()) <= 1e-5
