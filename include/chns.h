@@ -300,7 +300,15 @@ int chns_batch_offsets(struct chns_batch *b, long long *offsets);
  * hipGraph on the first call and replays it while nsteps, the pointers and
  * the launch shape stay the same.  stats (host, count entries) or NULL; if
  * given the call synchronises and returns CHNS_ENOCONV / CHNS_ENONFINITE
- * when any problem's solve reported it.                                    */
+ * when any problem's solve reported it.  In the tiled form a captured step
+ * launches a fixed number of iterations per solve (the budgets): such a call
+ * keeps a copy of the state and always synchronises; when a solve ran out of
+ * its budget, that solve's budgets grow (iterations by max(2, a quarter),
+ * the FP32 refinement round by max(2, a half), at most to the largest
+ * max_iter), the state is restored and the steps are captured and replayed
+ * again, so the result is that of converged solves.  Grown budgets stay for
+ * later calls.  A graph holds at most 20 steps; longer calls replay a graph
+ * of the largest divisor of nsteps up to 20.                              */
 int chns_batch_step(struct chns_batch *b, const chns_state *packed, int nsteps, int use_graph,
                     chns_batch_stats *stats);
 

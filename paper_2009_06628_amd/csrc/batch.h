@@ -87,6 +87,7 @@ struct chns_batch {
     int rbudget[3];                   // graph mode, FP32 hierarchy: iterations of the one refinement round
     int last_iters[3];                // eager mode: most iterations any problem needed, last step
     int last_refine[3];               // eager mode: most iterations in refinement rounds, last step
+    int max_iter_max;                 // largest max_iter of the problems (graph budgets never exceed it)
 };
 
 

@@ -519,8 +519,12 @@ void launch_step(chns_batch *b, const BatchState &st, hipStream_t s) {
                        b->d_stats);
 }
 
+// graph != 0: the launches are being captured; the per-call statistics are
+// then reset by the caller before the replays (a call may replay a graph
+// several times and the flags of every replay must survive).
 int launch_steps(chns_batch *b, const BatchState &st, int nsteps, hipStream_t s, int graph) {
-    hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_stats, b->count);
+    if (!graph)
+        hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_stats, b->count);
     if (b->mode == CHNS_BATCH_TILED) return tiled_steps(b, st, nsteps, graph, s, b->d_stats);
     for (int n = 0; n < nsteps; ++n) {
         if (b->prec == CHNS_FP64) {
@@ -556,10 +560,32 @@ bool same_state(const BatchState &x, const BatchState &y) {
 }
 
 // Run nsteps on the batch's own stream (ordered after the caller's stream).
-int run_steps(chns_batch *b, const BatchState &st, int nsteps, int use_graph) {
+int copy_state(chns_batch *b, const BatchState &st, int to_backup, hipStream_t s);
+
+// Captured graphs hold at most this many steps; longer calls replay a graph
+// of the largest divisor of nsteps up to it.  (A host-side crash was seen
+// while capturing 50 tiled steps of the 512-problem ensemble, ~55k kernel
+// nodes; graphs of up to 20 steps have always run.  Its cause is not known,
+// so longer captures are not made.)
+constexpr int kGraphMaxSteps = 20;
+
+int graph_chunk(int nsteps) {
+    int c = nsteps < kGraphMaxSteps ? nsteps : kGraphMaxSteps;
+    while (c > 1 && nsteps % c) --c;
+    return c;
+}
+
+// keep: 1 copies the state to the backup before the steps, 2 restores it
+// from the backup first (a replay with other budgets), 0 neither.
+int run_steps(chns_batch *b, const BatchState &st, int nsteps, int use_graph, int keep = 0) {
     BHIPCHK(hipEventRecord(b->ev_in, b->user_stream));
     BHIPCHK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    if (keep)
+        if (int rc = copy_state(b, st, keep == 1, b->stream)) return rc;
+    const int chunk = use_graph && nsteps > 0 ? graph_chunk(nsteps) : 0;
     if (use_graph && nsteps > 0) {
+        const int nsteps_all = nsteps;
+        nsteps = chunk;   // the captured graph holds one chunk
         if (!(b->exec && b->g_steps == nsteps && b->g_block == b->block && b->g_grid == b->grid &&
               b->g_mode == b->mode && b->g_tile == b->tile_cells && same_state(b->g_state, st))) {
             drop_graph(b);
@@ -585,7 +611,9 @@ int run_steps(chns_batch *b, const BatchState &st, int nsteps, int use_graph) {
             b->g_tile = b->tile_cells;
             b->g_state = st;
         }
-        BHIPCHK(hipGraphLaunch(b->exec, b->stream));
+        hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, b->stream, b->d_stats,
+                           b->count);
+        for (int done = 0; done < nsteps_all; done += chunk) BHIPCHK(hipGraphLaunch(b->exec, b->stream));
     } else {
         if (int rc = launch_steps(b, st, nsteps, b->stream, 0)) return rc;
     }
@@ -648,6 +676,8 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     b->budget[0] = 30;
     b->budget[1] = 30;
     b->budget[2] = 60;
+    b->max_iter_max = 1;
+    for (int i = 0; i < count; ++i) b->max_iter_max = std::max(b->max_iter_max, props[i].max_iter);
     for (int k = 0; k < 3; ++k) {
         b->rbudget[k] = 8;
         b->last_iters[k] = b->last_refine[k] = 0;
@@ -748,12 +778,50 @@ int chns_batch_step(chns_batch *b, const chns_state *packed, int nsteps, int use
     if (nsteps < 0) return set_error(CHNS_EINVAL, "nsteps must be >= 0");
     BatchState st;
     if (int rc = state_of(b, packed, st)) return rc;
-    if (int rc = run_steps(b, st, nsteps, use_graph)) return rc;
-    if (!stats) return CHNS_OK;
-    BHIPCHK(hipMemcpyAsync(stats, b->d_stats, sizeof(chns_batch_stats) * b->count, hipMemcpyDeviceToHost, b->stream));
-    BHIPCHK(hipStreamSynchronize(b->stream));
     int flags = 0;
-    for (int i = 0; i < b->count; ++i) flags |= stats[i].flags;
+    if (use_graph && nsteps > 0 && b->mode == CHNS_BATCH_TILED) {
+        // Captured tiled steps launch a fixed number of iterations per solve
+        // (the budgets).  The state is kept; when a replay reports a solve
+        // that ran out of its budget, that budget grows, the state is
+        // restored and the steps are captured and replayed again.  Grown
+        // budgets stay for later calls.
+        std::vector<chns_batch_stats> hs(stats ? 0 : b->count);
+        chns_batch_stats *out = stats ? stats : hs.data();
+        for (int attempt = 0;; ++attempt) {
+            if (int rc = run_steps(b, st, nsteps, 1, attempt == 0 ? 1 : 2)) return rc;
+            BHIPCHK(hipMemcpyAsync(out, b->d_stats, sizeof(chns_batch_stats) * b->count, hipMemcpyDeviceToHost,
+                                   b->stream));
+            BHIPCHK(hipStreamSynchronize(b->stream));
+            flags = 0;
+            for (int i = 0; i < b->count; ++i) flags |= out[i].flags;
+            if (!(flags & 31) || (flags & 32)) break;
+            // the flag does not tell which round of the solve ran short (the
+            // iterations or, with the FP32 hierarchy, the refinement round
+            // after the true-residual check), so both budgets grow
+            bool grown = false;
+            auto grow = [&](int kind) {
+                const int nb = std::min(b->max_iter_max, b->budget[kind] + std::max(2, b->budget[kind] / 4));
+                const int nr = std::min(b->max_iter_max, b->rbudget[kind] + std::max(2, b->rbudget[kind] / 2));
+                if (nb > b->budget[kind] || nr > b->rbudget[kind]) {
+                    b->budget[kind] = nb;
+                    b->rbudget[kind] = nr;
+                    grown = true;
+                }
+            };
+            if (flags & 1) grow(0);
+            if (flags & 14) grow(1);
+            if (flags & 16) grow(2);
+            if (!grown) break;   // at max_iter: genuinely unconverged
+            drop_graph(b);
+        }
+    } else {
+        if (int rc = run_steps(b, st, nsteps, use_graph)) return rc;
+        if (!stats) return CHNS_OK;
+        BHIPCHK(hipMemcpyAsync(stats, b->d_stats, sizeof(chns_batch_stats) * b->count, hipMemcpyDeviceToHost,
+                               b->stream));
+        BHIPCHK(hipStreamSynchronize(b->stream));
+        for (int i = 0; i < b->count; ++i) flags |= stats[i].flags;
+    }
     if (flags & 32) return set_error(CHNS_ENONFINITE, "non-finite residual in a batched solve");
     if (flags) {
         char buf[160];
