@@ -171,8 +171,8 @@ __device__ inline TP *level_x(const BatchProb<TP> &P, const Slot<TP> &S, int l, 
     return l ? S.lev[l].x : (xsel ? P.w : P.z);
 }
 
-// op: 0 presmooth, 1 residual, 2 prolong + black (2D), 3 red from tmp (2D),
-// 4 prolong-add (3D), 5 black GS (3D), 6 red GS (3D)
+// op: 0 presmooth, 1 residual, 4 prolong-add, 5 black GS, 6 red GS (3D; the
+// 2D V-cycle runs the fused tile passes)
 template <typename TP, typename TB, int DIM>
 __global__ void __launch_bounds__(kTileBlock) k_t_sweep(const BatchProb<TP> *__restrict__ probs,
                                                         const BTile *__restrict__ tiles, int ntiles, int s, int l,
@@ -188,8 +188,6 @@ __global__ void __launch_bounds__(kTileBlock) k_t_sweep(const BatchProb<TP> *__r
     switch (op) {
         case 0: TILE_LOOP(t) presmooth_cell<TP, TB, DIM>(L, b, x, c); break;
         case 1: TILE_LOOP(t) residual_cell<TP, TB, DIM>(L, b, x, c); break;
-        case 2: TILE_LOOP(t) prolong_black_cell<TP, TB, DIM>(L, S.lev[l + 1].g, S.lev[l + 1].x, b, x, L.r, c); break;
-        case 3: TILE_LOOP(t) red_from_tmp_cell<TP, TB, DIM>(L, b, L.r, x, c); break;
         case 4:
             TILE_LOOP(t) {
                 int ia[3];
@@ -680,10 +678,8 @@ struct Tiled {
         hipLaunchKernelGGL((k_t_vcycle_small<TP, TB, DIM>), dim3(np()), dim3(kSBThreads), 0, s, probs(), sv, bsel,
                            xsel);
         for (int l = b->lg - 1; l >= 0; --l) {
-            const int ops2[2] = {2, 3}, ops3[3] = {4, 5, 6};
-            const int *ops = DIM == 2 ? ops2 : ops3;
-            const int nops = DIM == 2 ? 2 : 3;
-            for (int o = 0; o < nops; ++o) {
+            const int ops[3] = {4, 5, 6};
+            for (int o = 0; o < 3; ++o) {
                 if (l == 0)
                     sweep<TB>(sv, 0, bsel, xsel, ops[o]);
                 else

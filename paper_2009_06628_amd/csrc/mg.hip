@@ -94,35 +94,6 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Geo gf, Geo gc, const T *__
     GRID_LOOP(gc.N) restrict_cell<T, DIM>(gf, gc, rf, bc, c);
 }
 
-template <typename T, typename TB, int DIM>
-__global__ void __launch_bounds__(kBlock) k_prolong_black(Level<T> L, Geo gc, const T *__restrict__ xc,
-                                                          const TB *__restrict__ b, const T *__restrict__ x,
-                                                          T *__restrict__ tmp, const int *__restrict__ done) {
-    if (*done) return;
-    GRID_LOOP(L.g.N) prolong_black_cell<T, TB, DIM>(L, gc, xc, b, x, tmp, c);
-}
-
-template <typename T, typename TB, int DIM>
-__global__ void __launch_bounds__(kBlock) k_red_from_tmp(Level<T> L, const TB *__restrict__ b,
-                                                         const T *__restrict__ tmp, T *__restrict__ x,
-                                                         const int *__restrict__ done) {
-    if (*done) return;
-    GRID_LOOP(L.g.N) red_from_tmp_cell<T, TB, DIM>(L, b, tmp, x, c);
-}
-
-// 3D fine levels: separate prolongation and colour sweeps (the fused pass
-// would interpolate each red neighbour of a black cell again: 48 coarse loads)
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_prolong_add(Geo gf, Geo gc, const T *__restrict__ xc, T *__restrict__ x,
-                                                        const int *__restrict__ done) {
-    if (*done) return;
-    GRID_LOOP(gf.N) {
-        int ia[3];
-        coords_of<DIM>(gf, c, ia);
-        x[c] = (T)((T)x[c] + prolong_at<T, DIM>(gf, gc, xc, ia));
-    }
-}
-
 // Two consecutive values along x (the pair starts at an even index).
 template <typename T>
 struct Pair2 {
@@ -355,10 +326,37 @@ struct IterStart {
 };
 __device__ inline bool iter_start(Scal *sc, const double *__restrict__ p0, const double *__restrict__ p1,
                                   const double *__restrict__ p2, int nparts, long long N, int k, int singular,
-                                  double *lds, IterStart &o) {
-    const double trz = sum_parts_all(p0, nparts, lds);
-    const double tz = singular ? sum_parts_all(p1, nparts, lds) : 0.0;
-    const double tr = singular ? sum_parts_all(p2, nparts, lds) : 0.0;
+                                  IterStart &o) {
+    // the three sums in one pass: the same per-thread and per-wave order as
+    // three separate block sums, one round of barriers
+    __shared__ double wsum[3][kBlock / kWave];
+    double trz = 0.0, tz = 0.0, tr = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        trz += p0[i];
+        if (singular) {
+            tz += p1[i];
+            tr += p2[i];
+        }
+    }
+    trz = wave_sum(trz);
+    tz = wave_sum(tz);
+    tr = wave_sum(tr);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) {
+        wsum[0][w] = trz;
+        wsum[1][w] = tz;
+        wsum[2][w] = tr;
+    }
+    __syncthreads();
+    trz = tz = tr = 0.0;
+    for (int q = 0; q < (int)(blockDim.x / kWave); ++q) {
+        trz += wsum[0][q];
+        tz += wsum[1][q];
+        tr += wsum[2][q];
+    }
+    __syncthreads();
+    if (!singular) tz = tr = 0.0;
     o.zm = singular ? tz / (double)N : 0.0;
     o.rz = trz - o.zm * tr;
     const double prev = k > 0 ? sc->rzs[(k + 1) & 1] : 0.0;
@@ -391,7 +389,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
     IterStart it;
-    if (!iter_start(sc, rz0, rz1, rz2, nrz, L.g.N, k, singular, lds, it)) return;
+    if (!iter_start(sc, rz0, rz1, rz2, nrz, L.g.N, k, singular, it)) return;
     const double beta = it.beta, zm = it.zm;
     auto pv = [&](int e) { return ((double)z[e] - zm) + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
     double acc = 0.0;
@@ -425,9 +423,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const 
                                                        T *__restrict__ t, Scal *sc, const double *__restrict__ rz0,
                                                        int nrz, int k) {
     if (sc->done) return;
-    __shared__ double lds[kBlock / kWave];
     IterStart it;
-    if (!iter_start(sc, rz0, rz0, rz0, nrz, g.N, k, 0, lds, it)) return;
+    if (!iter_start(sc, rz0, rz0, rz0, nrz, g.N, k, 0, it)) return;
     const double beta = it.beta;
     auto pv = [&](int e) { return (double)z[e] + (beta != 0.0 ? beta * (double)pold[e] : 0.0); };
     GRID_LOOP(g.N) {
@@ -772,12 +769,7 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
                (const T *)S.lev[l + 1].x, x, done);
         LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 1, done);
         LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 0, done);
-        return;
     }
-    LAUNCH(K_PROLONG, W * ((4 + DIM) * N + Nc) + WB * N, (k_prolong_black<T, TB, DIM>), N, st, lv, S.lev[l + 1].g,
-           (const T *)S.lev[l + 1].x, b, (const T *)x, lv.r, done);
-    LAUNCH(K_SMOOTH, W * (4 + DIM) * N + WB * N, (k_red_from_tmp<T, TB, DIM>), N, st, lv, b, (const T *)lv.r, x,
-           done);
 }
 
 // One V-cycle of slot S: x0 ~ A^{-1} b0 (b0 may be stored in another
