@@ -205,27 +205,28 @@ __global__ void __launch_bounds__(kTileBlock) k_t_sweep(const BatchProb<TP> *__r
 // level's residual array carries the smoothed x from the way down to the
 // way up.
 template <typename TP, typename TB>
-__global__ void __launch_bounds__(kTileThreads) k_t_down2(const BatchProb<TP> *__restrict__ probs,
+__global__ void __launch_bounds__(kTileThreadsBatch) k_t_down2(const BatchProb<TP> *__restrict__ probs,
                                                           const BTile *__restrict__ tiles, int ntiles, int s, int l,
                                                           int bsel) {
     BTile t;
     if (!tile_of(tiles, ntiles, t)) return;
     const BatchProb<TP> &P = probs[t.prob];
     const Slot<TP> &S = tslot(P, s);
-    down_tile2<TP, TB>(S.lev[l], S.lev[l + 1].g, level_b<TP, TB>(P, S, l, bsel), S.lev[l].r, S.lev[l + 1].b, t.c0,
-                       t.c1, P.sc->done);
+    down_tile2<TP, TB, kTileThreadsBatch>(S.lev[l], S.lev[l + 1].g, level_b<TP, TB>(P, S, l, bsel), S.lev[l].r,
+                                          S.lev[l + 1].b, t.c0, t.c1, P.sc->done);
 }
 
 template <typename TP, typename TB>
-__global__ void __launch_bounds__(kTileThreads) k_t_up2(const BatchProb<TP> *__restrict__ probs,
+__global__ void __launch_bounds__(kTileThreadsBatch) k_t_up2(const BatchProb<TP> *__restrict__ probs,
                                                         const BTile *__restrict__ tiles, int ntiles, int s, int l,
                                                         int bsel, int xsel) {
     BTile t;
     if (!tile_of(tiles, ntiles, t)) return;
     const BatchProb<TP> &P = probs[t.prob];
     const Slot<TP> &S = tslot(P, s);
-    up_tile2<TP, TB>(S.lev[l], S.lev[l + 1].g, (const TP *)S.lev[l + 1].x, level_b<TP, TB>(P, S, l, bsel),
-                     (const TP *)S.lev[l].r, level_x(P, S, l, xsel), t.c0, t.c1, P.sc->done);
+    up_tile2<TP, TB, kTileThreadsBatch>(S.lev[l], S.lev[l + 1].g, (const TP *)S.lev[l + 1].x,
+                                        level_b<TP, TB>(P, S, l, bsel), (const TP *)S.lev[l].r,
+                                        level_x(P, S, l, xsel), t.c0, t.c1, P.sc->done);
 }
 
 // restriction of level l's residual into level l + 1 (tiles of level l + 1)
@@ -646,20 +647,20 @@ struct Tiled {
             // fused passes: one launch per level on the way down and one on the way up
             for (int l = 0; l < b->lg; ++l) {
                 if (l == 0)
-                    hipLaunchKernelGGL((k_t_down2<TP, TB>), dim3(b->nt2[0]), dim3(kTileThreads), 0, s, probs(),
+                    hipLaunchKernelGGL((k_t_down2<TP, TB>), dim3(b->nt2[0]), dim3(kTileThreadsBatch), 0, s, probs(),
                                        b->d_t2[0], b->nt2[0], sv, 0, bsel);
                 else
-                    hipLaunchKernelGGL((k_t_down2<TP, TP>), dim3(b->nt2[l]), dim3(kTileThreads), 0, s, probs(),
+                    hipLaunchKernelGGL((k_t_down2<TP, TP>), dim3(b->nt2[l]), dim3(kTileThreadsBatch), 0, s, probs(),
                                        b->d_t2[l], b->nt2[l], sv, l, 0);
             }
             hipLaunchKernelGGL((k_t_vcycle_small<TP, TB, DIM>), dim3(np()), dim3(kSBThreads), 0, s, probs(), sv,
                                bsel, xsel);
             for (int l = b->lg - 1; l >= 0; --l) {
                 if (l == 0)
-                    hipLaunchKernelGGL((k_t_up2<TP, TB>), dim3(b->nt2[0]), dim3(kTileThreads), 0, s, probs(),
+                    hipLaunchKernelGGL((k_t_up2<TP, TB>), dim3(b->nt2[0]), dim3(kTileThreadsBatch), 0, s, probs(),
                                        b->d_t2[0], b->nt2[0], sv, 0, bsel, xsel);
                 else
-                    hipLaunchKernelGGL((k_t_up2<TP, TP>), dim3(b->nt2[l]), dim3(kTileThreads), 0, s, probs(),
+                    hipLaunchKernelGGL((k_t_up2<TP, TP>), dim3(b->nt2[l]), dim3(kTileThreadsBatch), 0, s, probs(),
                                        b->d_t2[l], b->nt2[l], sv, l, 0, 0);
             }
             return;

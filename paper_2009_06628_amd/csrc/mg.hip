@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kTileThreads) k_down_tile2(Level<T> L, Geo gc,
     const int tile = xcd_block();
     if (tile >= ntiles) return;
     const int ty = tile / ntx, tx = tile - ty * ntx;
-    down_tile2<T, TB>(L, gc, b, xs, bc, tx, ty, *done);
+    down_tile2<T, TB, kTileThreads>(L, gc, b, xs, bc, tx, ty, *done);
 }
 
 template <typename T, typename TB>
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kTileThreads) k_up_tile2(Level<T> L, Geo gc, c
     const int tile = xcd_block();
     if (tile >= ntiles) return;
     const int ty = tile / ntx, tx = tile - ty * ntx;
-    up_tile2<T, TB>(L, gc, xc, b, xs, x, tx, ty, *done);
+    up_tile2<T, TB, kTileThreads>(L, gc, xc, b, xs, x, tx, ty, *done);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,21 +264,22 @@ __global__ void __launch_bounds__(kSBThreads) k_vcycle_block(Slot<T> S, int l0, 
     vcycle_block_dev<T, TB, DIM>(S, l0, b0, x0);
 }
 
-// Levels [l0, nlev) out of LDS: n16 16-byte words (plus tail8 trailing 8
-// bytes) of their contiguous storage are copied in, x of level l0 is written
-// back.
+// Levels [l0, nlev) out of LDS: the segments cp of their contiguous storage
+// are copied in, x of level l0 is written back.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kSBThreads) k_vcycle_lds(Slot<T> S, int l0, int n16, int tail8,
+__global__ void __launch_bounds__(kSBThreads) k_vcycle_lds(Slot<T> S, int l0, LdsCopy cp,
                                                            const int *__restrict__ done) {
     const int dn = *done;   // tested after the copy (which only reads memory and writes LDS)
     extern __shared__ uint4 lds_words[];
     char *lds = (char *)lds_words;
     const char *base = (const char *)S.lev[l0].s;
-    copy_to_lds(lds_words, (const uint4 *)base, n16);
+    copy_to_lds(lds_words, (const uint4 *)base, cp);
     if (dn) return;
-    if (tail8 && threadIdx.x == 0) *(double *)(lds + 16 * (size_t)n16) = *(const double *)(base + 16 * (size_t)n16);
     __syncthreads();
-    vcycle_lds_dev<T, DIM>(S, l0, lds, base);
+    if constexpr (DIM == 2)
+        vcycle_lds2_dev<T>(S, l0, lds, base);
+    else
+        vcycle_lds_dev<T, DIM>(S, l0, lds, base);
     const T *xl = lds_image(lds, base, S.lev[l0].x);
     T *xg = S.lev[l0].x;
     LDS_LOOP(S.lev[l0].g.N) xg[c] = xl[c];
@@ -772,6 +773,61 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
     }
 }
 
+// Copy plan of the LDS V-cycle of levels [lsb, nlev): the byte intervals
+// read before they are written (s, cs, invd of each level, b of level lsb,
+// the coarsest inverse), merged across the smallest gaps down to
+// kLdsCopySegs segments, in whole 16-byte words of the range (arrays start
+// on 256-byte boundaries; a rounded-up end stays inside the workspace).
+template <typename T>
+static LdsCopy lds_copy_plan(const Slot<T> &S, int lsb) {
+    const char *base = (const char *)S.lev[lsb].s;
+    long long a[2 * kMaxLev + 2], e[2 * kMaxLev + 2];
+    int n = 0;
+    auto add = [&](const void *p, size_t bytes) {
+        a[n] = (const char *)p - base;
+        e[n] = a[n] + (long long)bytes;
+        ++n;
+    };
+    for (int l = lsb; l < S.nlev; ++l) {
+        const Level<T> &L = S.lev[l];
+        add(L.s, (size_t)((const char *)(L.invd + L.g.N) - (const char *)L.s));   // s, cs[], invd
+        if (l == lsb) add(L.b, sizeof(T) * (size_t)L.g.N);
+    }
+    add(S.Ainv, sizeof(double) * (size_t)S.ncoarse * S.ncoarse);
+    // sort by start (a handful of entries)
+    for (int i = 1; i < n; ++i)
+        for (int j = i; j > 0 && a[j] < a[j - 1]; --j) {
+            std::swap(a[j], a[j - 1]);
+            std::swap(e[j], e[j - 1]);
+        }
+    while (n > kLdsCopySegs) {
+        int best = 0;
+        for (int i = 1; i + 1 < n; ++i)
+            if (a[i + 1] - e[i] < a[best + 1] - e[best]) best = i;
+        e[best] = std::max(e[best], e[best + 1]);
+        for (int i = best + 1; i + 1 < n; ++i) {
+            a[i] = a[i + 1];
+            e[i] = e[i + 1];
+        }
+        --n;
+    }
+    LdsCopy cp;
+    int done = 0;
+    for (int i = 0; i < kLdsCopySegs; ++i) {
+        if (i < n) {
+            const int w0 = (int)(a[i] / 16), w1 = (int)((e[i] + 15) / 16);
+            cp.shift[i] = w0 - done;
+            done += w1 - w0;
+            cp.cend[i] = done;
+        } else {
+            cp.shift[i] = cp.shift[n - 1];
+            cp.cend[i] = done;
+        }
+    }
+    cp.total = done;
+    return cp;
+}
+
 // One V-cycle of slot S: x0 ~ A^{-1} b0 (b0 may be stored in another
 // precision than the hierarchy).
 template <typename T, typename TB, int DIM>
@@ -788,7 +844,8 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
         const size_t range = lsb > 0 ? (size_t)((const char *)(S.Ainv + (size_t)S.ncoarse * S.ncoarse) -
                                                 (const char *)S.lev[lsb].s)
                                      : 0;
-        if (lsb > 0 && range <= (size_t)kLdsVcycleBytes) {
+        const size_t range16 = (range + 15) & ~(size_t)15;   // LDS image, whole 16-byte words
+        if (lsb > 0 && range16 <= (size_t)kLdsVcycleBytes) {
             // the range is read once and x of level lsb written back
             static const bool attr = [] {   // once per instantiation, thread-safe
                 (void)hipFuncSetAttribute((const void *)k_vcycle_lds<T, DIM>,
@@ -796,9 +853,10 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
                 return true;
             }();
             (void)attr;
-            const double bytes = (double)range + W * S.lev[lsb].g.N;
-            TLAUNCHS(K_COARSE_SOLVE, bytes, (k_vcycle_lds<T, DIM>), dim3(1), dim3(kSBThreads), range, st, S, lsb,
-                     (int)(range / 16), (int)((range % 16) != 0), done);
+            const LdsCopy cp = lds_copy_plan(S, lsb);
+            const double bytes = 16.0 * cp.total + W * S.lev[lsb].g.N;
+            TLAUNCHS(K_COARSE_SOLVE, bytes, (k_vcycle_lds<T, DIM>), dim3(1), dim3(kSBThreads), range16, st, S, lsb,
+                     cp, done);
         } else {
             double bytes = 8.0 * S.ncoarse * S.ncoarse;
             for (int l = lsb; l < S.nlev; ++l) bytes += W * 12.0 * S.lev[l].g.N;

@@ -275,8 +275,11 @@ __device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, int c)
             }
     constexpr double nchild = (DIM == 3) ? 8.0 : 4.0;
     C.s[c] = (T)(s / nchild);
+    // a face on a wall holds 0: every other pass masks it, and the LDS
+    // V-cycle relies on it to index walled axes as periodic ones
 #pragma unroll
-    for (int b = 0; b < DIM; ++b) C.cs[b][c] = (T)(cs[b] / (nchild * 0.5) * 0.25);
+    for (int b = 0; b < DIM; ++b)
+        C.cs[b][c] = (C.g.per[b] || I[b] > 0) ? (T)(cs[b] / (nchild * 0.5) * 0.25) : (T)0;
 }
 
 
@@ -353,22 +356,38 @@ constexpr int kLdsVcycleBytes = 160 * 1024;         // LDS of one workgroup on g
 // the loops from reading the workgroup size from the dispatch arguments.
 #define LDS_LOOP(N) for (int c = (int)threadIdx.x; c < (int)(N); c += kSBThreads)
 
-// Copy n16 >= 1 16-byte words: every load of a round is issued before its
-// stores.  Indices past the end are clamped to the last word, which is then
-// stored again with its own value, so no load or store is conditional.
-__device__ inline void copy_to_lds(uint4 *dst, const uint4 *src, int n16) {
-    for (int base = 0; base < n16; base += kLdsCopyUnroll * kSBThreads) {
+// The parts of the range that a V-cycle reads before writing them (s, cs,
+// invd of every level, b of the first, the coarsest inverse), as at most
+// kLdsCopySegs segments of 16-byte words, each copied to the same offset in
+// LDS: segment i covers words [cend[i-1] + shift[i], cend[i] + shift[i])
+// of the range (cend[-1] = 0); unused segments have cend = total.
+constexpr int kLdsCopySegs = 4;
+struct LdsCopy {
+    int total;                    // words to copy (>= 1)
+    int cend[kLdsCopySegs];       // running end of the copied words
+    int shift[kLdsCopySegs];      // range word = copied word + shift
+};
+
+// Copy the segments: every load of a round is issued before its stores.
+// Indices past the end are clamped to the last word, which is then stored
+// again with its own value, so no load or store is conditional.
+__device__ inline void copy_to_lds(uint4 *dst, const uint4 *src, const LdsCopy &cp) {
+    const int n = cp.total;
+    for (int base = 0; base < n; base += kLdsCopyUnroll * kSBThreads) {
         uint4 v[kLdsCopyUnroll];
+        int w[kLdsCopyUnroll];
 #pragma unroll
         for (int k = 0; k < kLdsCopyUnroll; ++k) {
-            const int i = base + k * kSBThreads + (int)threadIdx.x;
-            v[k] = src[i < n16 ? i : n16 - 1];
+            int i = base + k * kSBThreads + (int)threadIdx.x;
+            i = i < n ? i : n - 1;
+            int sh = cp.shift[0];
+#pragma unroll
+            for (int j = 1; j < kLdsCopySegs; ++j) sh = i >= cp.cend[j - 1] ? cp.shift[j] : sh;
+            w[k] = i + sh;
+            v[k] = src[w[k]];
         }
 #pragma unroll
-        for (int k = 0; k < kLdsCopyUnroll; ++k) {
-            const int i = base + k * kSBThreads + (int)threadIdx.x;
-            dst[i < n16 ? i : n16 - 1] = v[k];
-        }
+        for (int k = 0; k < kLdsCopyUnroll; ++k) dst[w[k]] = v[k];
     }
 }
 
@@ -420,6 +439,25 @@ __device__ inline void gs_at(const Level<T> &L, int c, const int ia[3]) {
     L.x[c] = (T)(((R)L.b[c] + offsum_at<T, DIM>(L, c, ia, xv)) * (R)L.invd[c]);
 }
 
+// x = Ainv b on the coarsest level (FP64 inverse, all operands in LDS): G
+// lanes per row (G a power of two, at most a wave, G n <= kSBThreads where
+// n allows), lane q summing columns q, q + G, ... in order, then a butterfly
+// sum over the G lanes.  The lanes of a group (aligned within a wave) run
+// the same rows, so every shuffle pairs two active lanes of one group.
+template <typename T>
+__device__ inline void coarse_solve_lds(int n, const double *Ainv, const T *b, T *x) {
+    int G = 1;
+    while (G < kWave && 2 * G * n <= kSBThreads) G *= 2;
+    const int q = (int)threadIdx.x & (G - 1);
+    for (int i = (int)threadIdx.x / G; i < n; i += kSBThreads / G) {
+        const double *row = Ainv + i * n;
+        double v = 0.0;
+        for (int j = q; j < n; j += G) v += row[j] * (double)b[j];
+        for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if (q == 0) x[i] = (T)v;
+    }
+}
+
 // V-cycle over levels [l0, nlev), l0 >= 1, on the LDS image of their
 // storage.  The arithmetic is that of vcycle_block_dev, with each pass
 // enumerating the cells of one colour (no wave runs both colours' branches):
@@ -453,22 +491,8 @@ __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const
         __syncthreads();
     }
     {
-        // x = Ainv b on the coarsest level (FP64 inverse); thread i walks row
-        // i from column i on, so that the lanes of a wave read different LDS
-        // banks
         const Level<T> lc = lds_level<T, DIM>(S.lev[L - 1], lds, base);
-        const double *Ainv = lds_image(lds, base, S.Ainv);
-        const int n = (int)lc.g.N;
-        LDS_LOOP(n) {
-            double v = 0.0;
-            const double *row = Ainv + c * n;
-            int j = c;
-            for (int t = 0; t < n; ++t) {
-                v += row[j] * (double)lc.b[j];
-                j = j + 1 == n ? 0 : j + 1;
-            }
-            lc.x[c] = (T)v;
-        }
+        coarse_solve_lds<T>((int)lc.g.N, lds_image(lds, base, S.Ainv), lc.b, lc.x);
         __syncthreads();
     }
     for (int l = L - 2; l >= l0; --l) {
@@ -490,6 +514,119 @@ __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const
             int ia[3];
             const int c = color_cell<DIM>(lv.g, k, 0, ia);
             gs_at<T, DIM>(lv, c, ia);
+        }
+        __syncthreads();
+    }
+}
+
+// 2D form of vcycle_lds_dev with the same arithmetic per cell and pass.
+// Faces on walls hold 0 on these levels (coarsen_cell), so every axis is
+// indexed as periodic: the wrapped neighbour of a cell on a wall enters with
+// weight 0, where the masked stencils add 0 for the missing neighbour.  Each
+// thread takes the k-th red and the k-th black cell of a level (x extent
+// even): row y = k / (nx / 2), red at x = 2 (k mod nx / 2) + (y & 1), black
+// at x ^ 1.
+struct Wrap2 {
+    int c, xl, xh, yl, yh;
+};
+__device__ inline Wrap2 wrap2(int x, int y, int nx, int ny, int nwrap) {
+    Wrap2 w;
+    w.c = x + nx * y;
+    w.xl = x > 0 ? w.c - 1 : w.c + nx - 1;
+    w.xh = x < nx - 1 ? w.c + 1 : w.c + 1 - nx;
+    w.yl = y > 0 ? w.c - nx : w.c + nwrap;
+    w.yh = y < ny - 1 ? w.c + nx : w.c - nwrap;
+    return w;
+}
+
+#define LDS_PAIR_LOOP(N) for (int k = (int)threadIdx.x; k < (int)(N) / 2; k += kSBThreads)
+
+template <typename T>
+__device__ inline void vcycle_lds2_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
+    using R = T;
+    const int L = S.nlev;
+    // red / black cells of pair k and their neighbours
+    auto pair_of = [](const Geo &g, int k, Wrap2 &r, Wrap2 &bl, int ia[3]) {
+        const int nx = (int)g.n[0], ny = (int)g.n[1], hx = nx >> 1;
+        const int y = k / hx, xr = 2 * (k - y * hx) + (y & 1);
+        const int nwrap = nx * (ny - 1);
+        r = wrap2(xr, y, nx, ny, nwrap);
+        bl = wrap2(xr ^ 1, y, nx, ny, nwrap);
+        ia[0] = xr;
+        ia[1] = y;
+        ia[2] = 0;
+    };
+    // sum of cs * v over the four neighbours, in the order of offsum_at
+    auto offsum = [](const Level<T> &lv, const Wrap2 &w, auto v) {
+        R acc = 0.0;
+        acc += (R)lv.cs[0][w.c] * v(w.xl);
+        acc += (R)lv.cs[0][w.xh] * v(w.xh);
+        acc += (R)lv.cs[1][w.c] * v(w.yl);
+        acc += (R)lv.cs[1][w.yh] * v(w.yh);
+        return acc;
+    };
+    // (A x)_c in the order of apply_at
+    auto apply = [](const Level<T> &lv, const Wrap2 &w) {
+        const R xc = (R)lv.x[w.c];
+        R acc = (R)lv.s[w.c] * xc;
+        acc += (R)lv.cs[0][w.c] * (xc - (R)lv.x[w.xl]);
+        acc += (R)lv.cs[0][w.xh] * (xc - (R)lv.x[w.xh]);
+        acc += (R)lv.cs[1][w.c] * (xc - (R)lv.x[w.yl]);
+        acc += (R)lv.cs[1][w.yh] * (xc - (R)lv.x[w.yh]);
+        return acc;
+    };
+    for (int l = l0; l < L - 1; ++l) {
+        const Level<T> lv = lds_level<T, 2>(S.lev[l], lds, base);
+        const Level<T> lc = lds_level<T, 2>(S.lev[l + 1], lds, base);
+        // zero-guess smoothing: red x = b / d, black GS from those values
+        LDS_PAIR_LOOP(lv.g.N) {
+            Wrap2 r, bl;
+            int ia[3];
+            pair_of(lv.g, k, r, bl, ia);
+            lv.x[r.c] = (T)((R)lv.b[r.c] * (R)lv.invd[r.c]);
+            auto red = [&](int e) { return (R)lv.b[e] * (R)lv.invd[e]; };
+            lv.x[bl.c] = (T)(((R)lv.b[bl.c] + offsum(lv, bl, red)) * (R)lv.invd[bl.c]);
+        }
+        __syncthreads();
+        LDS_PAIR_LOOP(lv.g.N) {
+            Wrap2 r, bl;
+            int ia[3];
+            pair_of(lv.g, k, r, bl, ia);
+            lv.r[r.c] = (T)((R)lv.b[r.c] - apply(lv, r));
+            lv.r[bl.c] = (T)((R)lv.b[bl.c] - apply(lv, bl));
+        }
+        __syncthreads();
+        LDS_LOOP(lc.g.N) restrict_cell<T, 2>(lv.g, lc.g, lv.r, lc.b, c);
+        __syncthreads();
+    }
+    {
+        const Level<T> lc = lds_level<T, 2>(S.lev[L - 1], lds, base);
+        coarse_solve_lds<T>((int)lc.g.N, lds_image(lds, base, S.Ainv), lc.b, lc.x);
+        __syncthreads();
+    }
+    for (int l = L - 2; l >= l0; --l) {
+        const Level<T> lv = lds_level<T, 2>(S.lev[l], lds, base);
+        const Level<T> lc = lds_level<T, 2>(S.lev[l + 1], lds, base);
+        auto xv = [&](int e) { return (R)lv.x[e]; };
+        LDS_PAIR_LOOP(lv.g.N) {
+            Wrap2 r, bl;
+            int ia[3];
+            pair_of(lv.g, k, r, bl, ia);
+            lv.x[r.c] = (T)((R)lv.x[r.c] + prolong_at<T, 2>(lv.g, lc.g, lc.x, ia));
+        }
+        __syncthreads();
+        LDS_PAIR_LOOP(lv.g.N) {
+            Wrap2 r, bl;
+            int ia[3];
+            pair_of(lv.g, k, r, bl, ia);
+            lv.x[bl.c] = (T)(((R)lv.b[bl.c] + offsum(lv, bl, xv)) * (R)lv.invd[bl.c]);
+        }
+        __syncthreads();
+        LDS_PAIR_LOOP(lv.g.N) {
+            Wrap2 r, bl;
+            int ia[3];
+            pair_of(lv.g, k, r, bl, ia);
+            lv.x[r.c] = (T)(((R)lv.b[r.c] + offsum(lv, r, xv)) * (R)lv.invd[r.c]);
         }
         __syncthreads();
     }

@@ -22,8 +22,27 @@ namespace chns {
 #ifndef CHNS_TILE2_Y
 #define CHNS_TILE2_Y 16
 #endif
+#ifndef CHNS_TILE2_THREADS
+#define CHNS_TILE2_THREADS 512
+#endif
+#ifndef CHNS_TILE2_BATCH_THREADS
+#define CHNS_TILE2_BATCH_THREADS 256
+#endif
 constexpr int kTFX = CHNS_TILE2_X, kTFY = CHNS_TILE2_Y;   // fine cells per tile (even)
-constexpr int kTileThreads = 256;
+// Threads per tile: a single grid has few tiles per CU, so more threads per
+// tile shorten each phase; the batched form has many tiles per CU and
+// prefers more workgroups of fewer threads (measured).
+constexpr int kTileThreads = CHNS_TILE2_THREADS;              // single-grid kernels
+constexpr int kTileThreadsBatch = CHNS_TILE2_BATCH_THREADS;   // batched form
+static_assert(kTFX % 2 == 0 && kTFY % 2 == 0, "tile extents must be even");
+
+// Local x of the m-th cell of colour col in local row ly of a region that
+// starts at local x 1 and has an even width, for a tile whose local (0, 0)
+// has global parity par: the colour of a cell is the parity of its global
+// x + y.
+__device__ inline int tile_color_x(int m, int ly, int par, int col) {
+    return 1 + 2 * m + ((ly + par + col + 1) & 1);
+}
 
 // Local index -> global coordinate along one axis: wrapped on a periodic
 // axis; v tells whether the cell exists.
@@ -37,12 +56,12 @@ __device__ inline int tile_coord(int g, int n, int per, bool &v) {
 // Writes the smoothed x of the tile to xs (the level's residual array, which
 // no longer holds a residual: the way up reads x from there while it writes
 // the level's x) and bc on the tile's coarse cells.
-template <typename T, typename TB>
+template <typename T, typename TB, int NT>
 __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__restrict__ b, T *__restrict__ xs,
                                   T *__restrict__ bc, int tx, int ty, int skip) {
     using R = T;
     constexpr int H = 3, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
-    constexpr int KL = (NL + kTileThreads - 1) / kTileThreads;   // staged cells per thread
+    constexpr int KL = (NL + NT - 1) / NT;   // staged cells per thread
     __shared__ T sB[NL], sI[NL], sS[NL], sC0[NL], sC1[NL], sX[NL], sR[NL];
     const int nx = (int)L.g.n[0], ny = (int)L.g.n[1];
     const int px = L.g.per[0], py = L.g.per[1];
@@ -54,7 +73,7 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
     bool lv[KL], m0[KL], m1[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const int i0 = (int)threadIdx.x + k * NT, i = i0 < NL ? i0 : NL - 1;
         const int ly = i / WX, lx = i - ly * WX;
         bool vx, vy;
         const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
@@ -74,7 +93,7 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
     // are finite), so that no load turns into a branch of its own
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const int i0 = (int)threadIdx.x + k * NT, i = i0 < NL ? i0 : NL - 1;
         const T fv = lv[k] ? (T)1 : (T)0;
         sB[i] = lb[k] * fv;
         sI[i] = li[k] * fv;
@@ -83,27 +102,29 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
         sC1[i] = l1[k] * (m1[k] ? (T)1 : (T)0);
     }
     __syncthreads();
-    // x on the tile and 2 halo cells
-    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
-        const int ly = i / WX, lx = i - ly * WX;
-        if (lx < 1 || lx >= WX - 1 || ly < 1 || ly >= WY - 1) continue;
-        if (((gx0 + lx + gy0 + ly) & 1) == 0) {
-            sX[i] = (T)((R)sB[i] * (R)sI[i]);
-        } else {
-            auto red = [&](int j) { return (R)sB[j] * (R)sI[j]; };
-            R acc = 0.0;
-            acc += (R)sC0[i] * red(i - 1);
-            acc += (R)sC0[i + 1] * red(i + 1);
-            acc += (R)sC1[i] * red(i - WX);
-            acc += (R)sC1[i + WX] * red(i + WX);
-            sX[i] = (T)(((R)sB[i] + acc) * (R)sI[i]);
-        }
+    // x on the tile and 2 halo cells (local [1, WX-1) x [1, WY-1), rows of
+    // even width): the k-th red and the k-th black cell in one thread, so no
+    // wave runs both colours' branches
+    const int par = (gx0 + gy0) & 1;
+    constexpr int XP = (WX - 2) / 2;   // cells of one colour per row
+    for (int k = (int)threadIdx.x; k < XP * (WY - 2); k += NT) {
+        const int row = k / XP, m = k - row * XP, ly = 1 + row;
+        const int ir = ly * WX + tile_color_x(m, ly, par, 0);
+        const int i = ly * WX + tile_color_x(m, ly, par, 1);
+        sX[ir] = (T)((R)sB[ir] * (R)sI[ir]);
+        auto red = [&](int j) { return (R)sB[j] * (R)sI[j]; };
+        R acc = 0.0;
+        acc += (R)sC0[i] * red(i - 1);
+        acc += (R)sC0[i + 1] * red(i + 1);
+        acc += (R)sC1[i] * red(i - WX);
+        acc += (R)sC1[i + WX] * red(i + WX);
+        sX[i] = (T)(((R)sB[i] + acc) * (R)sI[i]);
     }
     __syncthreads();
-    // residual on the tile and 1 halo cell
-    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
-        const int ly = i / WX, lx = i - ly * WX;
-        if (lx < 2 || lx >= WX - 2 || ly < 2 || ly >= WY - 2) continue;
+    // residual on the tile and 1 halo cell (local [2, WX-2) x [2, WY-2))
+    constexpr int RW = WX - 4;
+    for (int j = (int)threadIdx.x; j < RW * (WY - 4); j += NT) {
+        const int ry = j / RW, i = (ry + 2) * WX + (j - ry * RW) + 2;
         const R xc = (R)sX[i];
         R acc = (R)sS[i] * xc;
         acc += (R)sC0[i] * (xc - (R)sX[i - 1]);
@@ -116,7 +137,7 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
     // restriction (taps 2I-1 .. 2I+2 per axis; an absent tap has weight 0)
     constexpr int CX = kTFX / 2, CY = kTFY / 2;
     const int ncx = (int)gc.n[0], ncy = (int)gc.n[1];
-    for (int j = (int)threadIdx.x; j < CX * CY; j += kTileThreads) {
+    for (int j = (int)threadIdx.x; j < CX * CY; j += NT) {
         const int cy = j / CX, cx = j - cy * CX;
         const int I = tx * CX + cx, J = ty * CY + cy;
         if (I >= ncx || J >= ncy) continue;
@@ -136,7 +157,7 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
         bc[I + ncx * J] = (T)v;
     }
     // x of the tile's own cells
-    for (int j = (int)threadIdx.x; j < kTFX * kTFY; j += kTileThreads) {
+    for (int j = (int)threadIdx.x; j < kTFX * kTFY; j += NT) {
         const int ly = j / kTFX, lx = j - ly * kTFX;
         const int gx = tx * kTFX + lx, gy = ty * kTFY + ly;
         if (gx < nx && gy < ny) xs[gx + nx * gy] = sX[(ly + H) * WX + lx + H];
@@ -146,12 +167,12 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
 // Way up: red x += P e, black GS, red GS (the post-smoothing), with e the
 // coarse correction xc and the pre-smoothed x read from xs.  Writes x on the
 // tile (never read here, so tiles do not race on their halos).
-template <typename T, typename TB>
+template <typename T, typename TB, int NT>
 __device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__restrict__ xc, const TB *__restrict__ b,
                                 const T *__restrict__ xs, T *__restrict__ x, int tx, int ty, int skip) {
     using R = T;
     constexpr int H = 2, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
-    constexpr int KL = (NL + kTileThreads - 1) / kTileThreads;
+    constexpr int KL = (NL + NT - 1) / NT;
     __shared__ T sB[NL], sI[NL], sC0[NL], sC1[NL], sX[NL];
     const int nx = (int)L.g.n[0], ny = (int)L.g.n[1];
     const int px = L.g.per[0], py = L.g.per[1];
@@ -163,7 +184,7 @@ __device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__res
     bool lv[KL], m0[KL], m1[KL];
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const int i0 = (int)threadIdx.x + k * NT, i = i0 < NL ? i0 : NL - 1;
         const int ly = i / WX, lx = i - ly * WX;
         bool vx, vy;
         const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
@@ -184,7 +205,7 @@ __device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__res
     if (skip) return;
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
-        const int i0 = (int)threadIdx.x + k * kTileThreads, i = i0 < NL ? i0 : NL - 1;
+        const int i0 = (int)threadIdx.x + k * NT, i = i0 < NL ? i0 : NL - 1;
         const T fv = lv[k] ? (T)1 : (T)0;
         sB[i] = lb[k] * fv;
         sI[i] = li[k] * fv;
@@ -201,15 +222,18 @@ __device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__res
         acc += (R)sC1[i + WX] * (R)sX[i + WX];
         return (T)(((R)sB[i] + acc) * (R)sI[i]);
     };
-    // black on the tile and 1 halo cell (reads red cells only)
-    for (int i = (int)threadIdx.x; i < NL; i += kTileThreads) {
-        const int ly = i / WX, lx = i - ly * WX;
-        if (lx < 1 || lx >= WX - 1 || ly < 1 || ly >= WY - 1) continue;
-        if (((gx0 + lx + gy0 + ly) & 1) == 1) sX[i] = gs(i);
+    // black on the tile and 1 halo cell (local [1, WX-1) x [1, WY-1); reads
+    // red cells only)
+    const int par = (gx0 + gy0) & 1;
+    constexpr int XP = (WX - 2) / 2;
+    for (int k = (int)threadIdx.x; k < XP * (WY - 2); k += NT) {
+        const int row = k / XP, m = k - row * XP, ly = 1 + row;
+        const int i = ly * WX + tile_color_x(m, ly, par, 1);
+        sX[i] = gs(i);
     }
     __syncthreads();
     // red on the tile (reads black cells only); both colours written out
-    for (int j = (int)threadIdx.x; j < kTFX * kTFY; j += kTileThreads) {
+    for (int j = (int)threadIdx.x; j < kTFX * kTFY; j += NT) {
         const int ly = j / kTFX, lx = j - ly * kTFX;
         const int gx = tx * kTFX + lx, gy = ty * kTFY + ly;
         if (gx >= nx || gy >= ny) continue;
