@@ -212,8 +212,8 @@ __global__ void __launch_bounds__(kTileThreadsBatch) k_t_down2(const BatchProb<T
     if (!tile_of(tiles, ntiles, t)) return;
     const BatchProb<TP> &P = probs[t.prob];
     const Slot<TP> &S = tslot(P, s);
-    down_tile2<TP, TB, kTileThreadsBatch>(S.lev[l], S.lev[l + 1].g, level_b<TP, TB>(P, S, l, bsel), S.lev[l].r,
-                                          S.lev[l + 1].b, t.c0, t.c1, P.sc->done);
+    down_tile2<TP, kTileThreadsBatch>(S.lev[l], S.lev[l + 1].g, RhsStored<TB>{level_b<TP, TB>(P, S, l, bsel)},
+                                      S.lev[l].r, S.lev[l + 1].b, t.c0, t.c1, P.sc->done);
 }
 
 template <typename TP, typename TB>
@@ -224,9 +224,9 @@ __global__ void __launch_bounds__(kTileThreadsBatch) k_t_up2(const BatchProb<TP>
     if (!tile_of(tiles, ntiles, t)) return;
     const BatchProb<TP> &P = probs[t.prob];
     const Slot<TP> &S = tslot(P, s);
-    up_tile2<TP, TB, kTileThreadsBatch>(S.lev[l], S.lev[l + 1].g, (const TP *)S.lev[l + 1].x,
-                                        level_b<TP, TB>(P, S, l, bsel), (const TP *)S.lev[l].r,
-                                        level_x(P, S, l, xsel), t.c0, t.c1, P.sc->done);
+    up_tile2<TP, kTileThreadsBatch>(S.lev[l], S.lev[l + 1].g, (const TP *)S.lev[l + 1].x,
+                                    RhsStored<TB>{level_b<TP, TB>(P, S, l, bsel)}, (const TP *)S.lev[l].r,
+                                    level_x(P, S, l, xsel), t.c0, t.c1, P.sc->done);
 }
 
 // restriction of level l's residual into level l + 1 (tiles of level l + 1)

@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kTileThreads) k_down_tile2(Level<T> L, Geo gc,
     const int tile = xcd_block();
     if (tile >= ntiles) return;
     const int ty = tile / ntx, tx = tile - ty * ntx;
-    down_tile2<T, TB, kTileThreads>(L, gc, b, xs, bc, tx, ty, *done);
+    down_tile2<T, kTileThreads>(L, gc, RhsStored<TB>{b}, xs, bc, tx, ty, *done);
 }
 
 template <typename T, typename TB>
@@ -251,7 +251,82 @@ __global__ void __launch_bounds__(kTileThreads) k_up_tile2(Level<T> L, Geo gc, c
     const int tile = xcd_block();
     if (tile >= ntiles) return;
     const int ty = tile / ntx, tx = tile - ty * ntx;
-    up_tile2<T, TB, kTileThreads>(L, gc, xc, b, xs, x, tx, ty, *done);
+    up_tile2<T, kTileThreads>(L, gc, xc, RhsStored<TB>{b}, xs, x, tx, ty, *done);
+}
+
+// Level 0 of the preconditioner of CG iteration k, fused with the update
+// that precedes it: alpha = rz / p.q (every block sums the apply's partials
+// in the same order), x += alpha p on the tile's cells, the partial of r.r
+// per tile for r - alpha q, and the way down from r - alpha q.  r itself is
+// not stored here (neighbouring tiles still read the old r in their halos):
+// the next operator apply stores it.
+template <typename T, typename TR>
+__global__ void __launch_bounds__(kTileThreads) k_down_tile2_cg(Level<T> L, Geo gc, const TR *__restrict__ r,
+                                                                const TR *__restrict__ q, const TR *__restrict__ p,
+                                                                TR *__restrict__ x, T *__restrict__ xs,
+                                                                T *__restrict__ bc, int ntx, int ntiles, Scal *sc,
+                                                                const double *__restrict__ part_pq, int npq,
+                                                                double *__restrict__ part_rr) {
+    const int tile = xcd_block();
+    if (tile >= ntiles) return;
+    if (sc->done) return;
+    __shared__ double bcast;
+    double pq = 0.0, u0 = 0.0, u1 = 0.0;
+    for (int i = (int)threadIdx.x; i < npq; i += kTileThreads) pq += part_pq[i];
+    tile_sum3<kTileThreads>(pq, u0, u1);
+    if (threadIdx.x == 0) bcast = pq;
+    __syncthreads();
+    pq = bcast;
+    const double alpha = pq != 0.0 ? sc->rz / pq : 0.0;
+    if (tile == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = alpha;
+    }
+    const int ty = tile / ntx, tx = tile - ty * ntx;
+    down_tile2<T, kTileThreads>(L, gc, RhsPending<TR, T>{r, q, alpha}, xs, bc, tx, ty, 0);
+    const int nx = (int)L.g.n[0], ny = (int)L.g.n[1];
+    double rr = 0.0;
+    u0 = u1 = 0.0;
+    for (int j = (int)threadIdx.x; j < kTFX * kTFY; j += kTileThreads) {
+        const int ly = j / kTFX, lx = j - ly * kTFX;
+        const int gx = tx * kTFX + lx, gy = ty * kTFY + ly;
+        if (gx < nx && gy < ny) {
+            const int g = gx + nx * gy;
+            x[g] = (TR)((double)x[g] + alpha * (double)p[g]);
+            const double rc = cg_residual((double)r[g], (double)q[g], alpha);
+            rr += rc * rc;
+        }
+    }
+    tile_sum3<kTileThreads>(rr, u0, u1);
+    if (threadIdx.x == 0) part_rr[tile] = rr;
+}
+
+// Level 0 of the way up inside CG: right-hand side as stored (b) or pending
+// (r - alpha q, bpend); dmode 0: no partials, 1: partials of r.z, sum z,
+// sum r per tile with r as stored, 2: with r pending.
+template <typename T, typename TR>
+__global__ void __launch_bounds__(kTileThreads) k_up_tile2_cg(Level<T> L, Geo gc, const T *__restrict__ xc,
+                                                              const T *__restrict__ b, const TR *__restrict__ r,
+                                                              const TR *__restrict__ q, const T *__restrict__ xs,
+                                                              T *__restrict__ x, int ntx, int ntiles,
+                                                              const Scal *__restrict__ sc, int bpend, int dmode,
+                                                              double *__restrict__ p0, double *__restrict__ p1,
+                                                              double *__restrict__ p2,
+                                                              const int *__restrict__ done) {
+    const int tile = xcd_block();
+    if (tile >= ntiles) return;
+    const int ty = tile / ntx, tx = tile - ty * ntx;
+    const double alpha = (bpend || dmode == 2) ? sc->alpha : 0.0;
+    const int skip = *done;
+    if (dmode == 0) {
+        up_tile2<T, kTileThreads>(L, gc, xc, RhsPending<TR, T>{r, q, alpha}, xs, x, tx, ty, skip);
+        return;
+    }
+    const RzDots<TR> d{r, q, alpha, dmode == 2, p0, p1, p2, tile};
+    if (bpend)
+        up_tile2<T, kTileThreads>(L, gc, xc, RhsPending<TR, T>{r, q, alpha}, xs, x, tx, ty, skip, d);
+    else
+        up_tile2<T, kTileThreads>(L, gc, xc, RhsStored<T>{b}, xs, x, tx, ty, skip, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,9 +461,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
                                                            const double *__restrict__ rz0,
                                                            const double *__restrict__ rz1,
                                                            const double *__restrict__ rz2, int nrz, int k,
-                                                           int singular) {
+                                                           int singular, T *__restrict__ rpend) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
+    const double alpha_prev = rpend ? sc->alpha : 0.0;   // read before iter_start
     IterStart it;
     if (!iter_start(sc, rz0, rz1, rz2, nrz, L.g.N, k, singular, it)) return;
     const double beta = it.beta, zm = it.zm;
@@ -397,6 +473,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
     GRID_LOOP(L.g.N) {
         int ia[3];
         coords_of<DIM>(L.g, c, ia);
+        // residual of the previous iteration, stored before q is overwritten
+        if (rpend) rpend[c] = (T)cg_residual((double)rpend[c], (double)q[c], alpha_prev);
         const double pc = pv(c);
         double qc = (double)L.s[c] * pc;
 #pragma unroll
@@ -422,8 +500,10 @@ template <typename T, typename TZ, int DIM>
 __global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const TZ *__restrict__ z,
                                                        const T *__restrict__ pold, T *__restrict__ pnew,
                                                        T *__restrict__ t, Scal *sc, const double *__restrict__ rz0,
-                                                       int nrz, int k) {
+                                                       int nrz, int k, T *__restrict__ rpend,
+                                                       const T *__restrict__ q) {
     if (sc->done) return;
+    const double alpha_prev = rpend ? sc->alpha : 0.0;
     IterStart it;
     if (!iter_start(sc, rz0, rz0, rz0, nrz, g.N, k, 0, it)) return;
     const double beta = it.beta;
@@ -431,6 +511,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const 
     GRID_LOOP(g.N) {
         int ia[3];
         coords_of<DIM>(g, c, ia);
+        // residual of the previous iteration (q is rewritten by the second half)
+        if (rpend) rpend[c] = (T)cg_residual((double)rpend[c], (double)q[c], alpha_prev);
         pnew[c] = (T)pv(c);
         t[c] = (T)lap_at<DIM>(g, c, ia, ih2, pv);
     }
@@ -477,7 +559,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_update(int N, const T *__restric
     double acc = 0.0;
     GRID_LOOP(N) {
         x[c] = (T)((double)x[c] + alpha * (double)p[c]);
-        const double rc = (double)r[c] - alpha * (double)q[c];
+        const double rc = cg_residual((double)r[c], (double)q[c], alpha);
         r[c] = (T)rc;
         if constexpr (!std::is_same<T, TP>::value) rp[c] = (TP)(T)rc;
         acc += rc * rc;
@@ -717,20 +799,49 @@ void mg_setup(Slot<T> &S, int dim, hipStream_t st) {
 }
 
 // 2D tile grid of a level: tiles along x, rounded up to whole XCD groups
+// Level-0 role of a 2D V-cycle inside CG (tile kernels only): down_upd:
+// the way down also performs the CG update of the iteration
+// (k_down_tile2_cg, then k_pcg_fin_rr); bpend: the right-hand side is the
+// pending residual r - alpha q; dmode: partials of r.z, sum z, sum r on the
+// way up (0 none, 1 r as stored, 2 r pending).
+template <typename TR>
+struct L0Cg {
+    int down_upd, bpend, dmode;
+    const TR *r, *q, *p;
+    TR *x;
+    Scal *sc;
+    const double *part_pq;
+    int npq;
+    double *part_rr;
+    double *rz0, *rz1, *rz2;
+};
+
 static void tile_grid2(const Geo &g, int &ntx, int &ntiles, int &grid) {
     ntx = ((int)g.n[0] + kTFX - 1) / kTFX;
     ntiles = ntx * (((int)g.n[1] + kTFY - 1) / kTFY);
     grid = ntiles > 8 ? (ntiles + 7) & ~7 : ntiles;
 }
 
-template <typename T, typename TB, int DIM>
-static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st) {
+template <typename T, typename TB, int DIM, typename TR = T>
+static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st,
+                        const L0Cg<TR> *cg = nullptr) {
     constexpr double W = sizeof(T);
     Level<T> &lv = S.lev[l];
     const int N = (int)lv.g.N, Nc = (int)S.lev[l + 1].g.N;
     if (DIM == 2) {
         int ntx, ntiles, grid;
         tile_grid2(lv.g, ntx, ntiles, grid);
+        if (cg && cg->down_upd) {
+            constexpr double WR = sizeof(TR);
+            // r, q, p, x in, x out; invd, s, cs in; x, bc out
+            const double bytes = 5.0 * WR * N + W * (3 + DIM) * N + W * Nc;
+            TLAUNCH(K_MG_DOWN, bytes, (k_down_tile2_cg<T, TR>), dim3(grid), dim3(kTileThreads), st, lv,
+                    S.lev[l + 1].g, cg->r, cg->q, cg->p, cg->x, lv.r, S.lev[l + 1].b, ntx, ntiles, cg->sc,
+                    cg->part_pq, cg->npq, cg->part_rr);
+            LAUNCH1(K_PCG_UPDATE, 8.0 * ntiles, (k_pcg_fin_rr), kBlock, st, cg->sc, (const double *)cg->part_rr,
+                    ntiles);
+            return;
+        }
         const double bytes = (sizeof(TB) + W * (3 + DIM)) * N + W * Nc;   // b, invd, s, cs in; x, bc out
         TLAUNCH(K_MG_DOWN, bytes, (k_down_tile2<T, TB>), dim3(grid), dim3(kTileThreads), st, lv, S.lev[l + 1].g, b,
                 lv.r, S.lev[l + 1].b, ntx, ntiles, done);
@@ -750,14 +861,28 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
                S.lev[l + 1].b, done);
 }
 
-template <typename T, typename TB, int DIM>
-static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st) {
+template <typename T, typename TB, int DIM, typename TR = T>
+static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st,
+                      const L0Cg<TR> *cg = nullptr) {
     constexpr double W = sizeof(T);
     Level<T> &lv = S.lev[l];
     const int N = (int)lv.g.N, Nc = (int)S.lev[l + 1].g.N;
     if (DIM == 2) {
         int ntx, ntiles, grid;
         tile_grid2(lv.g, ntx, ntiles, grid);
+        if constexpr (std::is_same<TB, T>::value) {
+            if (cg && (cg->bpend || cg->dmode)) {
+                constexpr double WR = sizeof(TR);
+                // right-hand side (r, q when pending), invd, cs, x, xc in; x out; r (and q) for the dots
+                const double rhs = cg->bpend ? 2.0 * WR : (double)sizeof(TB);
+                const double dots = cg->dmode == 0 ? 0.0 : (cg->bpend ? 0.0 : (cg->dmode == 2 ? 2.0 : 1.0) * WR);
+                const double bytes = (rhs + dots + W * (3 + DIM)) * N + W * Nc;
+                TLAUNCH(K_MG_UP, bytes, (k_up_tile2_cg<T, TR>), dim3(grid), dim3(kTileThreads), st, lv,
+                        S.lev[l + 1].g, (const T *)S.lev[l + 1].x, (const T *)b, cg->r, cg->q, (const T *)lv.r, x,
+                        ntx, ntiles, (const Scal *)cg->sc, cg->bpend, cg->dmode, cg->rz0, cg->rz1, cg->rz2, done);
+                return;
+            }
+        }
         const double bytes = (sizeof(TB) + W * (3 + DIM)) * N + W * Nc;   // b, invd, cs, x, xc in; x out
         TLAUNCH(K_MG_UP, bytes, (k_up_tile2<T, TB>), dim3(grid), dim3(kTileThreads), st, lv, S.lev[l + 1].g,
                 (const T *)S.lev[l + 1].x, b, (const T *)lv.r, x, ntx, ntiles, done);
@@ -830,12 +955,13 @@ static LdsCopy lds_copy_plan(const Slot<T> &S, int lsb) {
 
 // One V-cycle of slot S: x0 ~ A^{-1} b0 (b0 may be stored in another
 // precision than the hierarchy).
-template <typename T, typename TB, int DIM>
-static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream_t st) {
+template <typename T, typename TB, int DIM, typename TR = T>
+static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream_t st,
+                     const L0Cg<TR> *cg = nullptr) {
     constexpr double W = sizeof(T);
     const int lsb = S.lsb;
     if (lsb > 0) {
-        vcycle_down<T, TB, DIM>(S, 0, b0, x0, done, st);
+        vcycle_down<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg);
         for (int l = 1; l < lsb; ++l) vcycle_down<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
     }
     {
@@ -869,7 +995,7 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
     }
     if (lsb > 0) {
         for (int l = lsb - 1; l >= 1; --l) vcycle_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
-        vcycle_up<T, TB, DIM>(S, 0, b0, x0, done, st);
+        vcycle_up<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg);
     }
 }
 
@@ -890,6 +1016,24 @@ static void precond_d(Slot<TP> &SP, OpKind kind, const T *r, TP *z, TP *w, const
         vcycle_d<TP, TP, DIM>(SP, w, z, done, st);
     } else {
         vcycle_d<TP, T, DIM>(SP, r, z, done, st);
+    }
+}
+
+// The same inside CG with the level-0 roles of cg (2D tile levels); for the
+// CH operator the first V-cycle takes the update and the pending
+// right-hand side, the second the dot products.
+template <typename TP, int DIM, typename TR>
+static void precond_cg_d(Slot<TP> &SP, OpKind kind, const TP *r, TP *z, TP *w, const int *done, hipStream_t st,
+                         const L0Cg<TR> &cg) {
+    if (kind == OP_CH) {
+        L0Cg<TR> c1 = cg, c2 = cg;
+        c1.dmode = 0;
+        c2.down_upd = 0;
+        c2.bpend = 0;
+        vcycle_d<TP, TP, DIM, TR>(SP, r, w, done, st, &c1);
+        vcycle_d<TP, TP, DIM, TR>(SP, w, z, done, st, &c2);
+    } else {
+        vcycle_d<TP, TP, DIM, TR>(SP, r, z, done, st, &cg);
     }
 }
 
@@ -943,9 +1087,25 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
     constexpr bool split = !std::is_same<T, TP>::value;
     const TP *rpre = split ? (const TP *)v.rp : (const TP *)(const void *)v.r;
     if (split) LAUNCH(K_PCG_INIT, (W + WP) * N, (k_round_vec<T, TP>), N, st, N, (const T *)v.r, v.rp);
-    precond_d<TP, TP, DIM>(SP, kind, rpre, v.z, v.w, done, st);
-    LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z, (const Scal *)sc,
-           red.rz0, red.rz1, red.rz2, singular);
+    // 2D with tiled level 0: the update and the r.z partials ride on the
+    // level-0 tile passes (one partial per tile), and the residual store
+    // moves to the next operator apply
+    int ntiles0 = 0;
+    if (DIM == 2 && SP.lsb > 0) {
+        int ntx, grid;
+        tile_grid2(SP.lev[0].g, ntx, ntiles0, grid);
+    }
+    const bool fuse = DIM == 2 && SP.lsb > 0 && ntiles0 <= kRedBlocks;
+    const int nrz = fuse ? ntiles0 : nb;
+    L0Cg<T> cg{0, 0, 1, (const T *)v.r, (const T *)v.q, nullptr, x, sc, (const double *)red.part0, nb,
+               red.part1, red.rz0, red.rz1, red.rz2};
+    if (fuse) {
+        precond_cg_d<TP, DIM, T>(SP, kind, rpre, v.z, v.w, done, st, cg);
+    } else {
+        precond_d<TP, TP, DIM>(SP, kind, rpre, v.z, v.w, done, st);
+        LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
+                (const Scal *)sc, red.rz0, red.rz1, red.rz2, singular);
+    }
     int launched = 0;
     int chunk = predict < 1 ? 1 : predict;
     for (;;) {
@@ -954,16 +1114,29 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
             const int k = launched + it;
             T *pnew = (k & 1) ? v.p1 : v.p0;
             T *pold = (k & 1) ? v.p0 : v.p1;
-            // the consumer of the r.z partials starts the iteration (beta)
+            // the consumer of the r.z partials starts the iteration (beta);
+            // fused: it also stores the previous iteration's residual
+            T *rpend = fuse && k > 0 ? v.r : nullptr;
+            const double WRP = rpend ? 2.0 * W : 0.0;   // r read and written
             if (kind == OP_SLOT) {
-                LAUNCHR(K_PCG_APPLY, W * (4 + DIM) * N + WP * N, (k_pcg_apply_slot<T, TP, DIM>), N, st, L0,
-                        (const TP *)v.z, (const T *)pold, pnew, v.q, sc, red.part0, (const double *)red.rz0,
-                        (const double *)red.rz1, (const double *)red.rz2, nb, k, singular);
+                LAUNCHR(K_PCG_APPLY, W * (4 + DIM) * N + WP * N + WRP * N, (k_pcg_apply_slot<T, TP, DIM>), N, st,
+                        L0, (const TP *)v.z, (const T *)pold, pnew, v.q, sc, red.part0, (const double *)red.rz0,
+                        (const double *)red.rz1, (const double *)red.rz2, nrz, k, singular, rpend);
             } else {
-                LAUNCHR(K_PCG_APPLY, W * 3 * N + WP * N, (k_pcg_ch_lap<T, TP, DIM>), N, st, g, ch.ih2,
-                        (const TP *)v.z, (const T *)pold, pnew, v.t, sc, (const double *)red.rz0, nb, k);
+                LAUNCHR(K_PCG_APPLY, W * 3 * N + WP * N + WRP * N, (k_pcg_ch_lap<T, TP, DIM>), N, st, g, ch.ih2,
+                        (const TP *)v.z, (const T *)pold, pnew, v.t, sc, (const double *)red.rz0, nrz, k, rpend,
+                        (const T *)v.q);
                 LAUNCHR(K_PCG_APPLY, W * 3 * N, (k_pcg_ch_apply<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, (const T *)pnew,
                        (const T *)v.t, v.q, (const Scal *)sc, red.part0);
+            }
+            if (fuse) {
+                L0Cg<T> c = cg;
+                c.down_upd = 1;
+                c.bpend = 1;
+                c.dmode = 2;
+                c.p = pnew;
+                precond_cg_d<TP, DIM, T>(SP, kind, rpre, v.z, v.w, done, st, c);
+                continue;
             }
             LAUNCHR(K_PCG_UPDATE, W * 6 * N + (split ? WP * N : 0.0), (k_pcg_update<T, TP>), N, st, N,
                     (const T *)pnew, (const T *)v.q, x, v.r, sc, (const double *)red.part0, nb, red.part1,

@@ -51,13 +51,97 @@ __device__ inline int tile_coord(int g, int n, int per, bool &v) {
     return per ? ((g % n) + n) % n : g;
 }
 
+// Right-hand side of a tile pass, staged in the hierarchy's precision T.
+// As stored:
+template <typename TB>
+struct RhsStored {
+    const TB *b;
+    template <typename T>
+    __device__ T at(int g) const {
+        return (T)b[g];
+    }
+};
+// The residual r - alpha q of a CG iteration whose store is still pending
+// (the next operator apply stores it): the value the update stores in the
+// CG precision TR, as read by the hierarchy through its right-hand side
+// type TB.
+__device__ inline double cg_residual(double r, double q, double alpha) { return fma(-alpha, q, r); }
+template <typename TR, typename TB>
+struct RhsPending {
+    const TR *r, *q;
+    double alpha;
+    template <typename T>
+    __device__ T at(int g) const {
+        return (T)(TB)(TR)cg_residual((double)r[g], (double)q[g], alpha);
+    }
+};
+
+// Sums of three per-thread values over a workgroup of NT threads, valid in
+// thread 0 (fixed order: waves by shuffles, then the waves in order).
+template <int NT>
+__device__ inline void tile_sum3(double &a, double &b, double &c) {
+    __shared__ double ws[3][NT / kWave];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int lane = (int)threadIdx.x & (kWave - 1), w = (int)threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) {
+        ws[0][w] = a;
+        ws[1][w] = b;
+        ws[2][w] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / kWave; ++k) {
+            a += ws[0][k];
+            b += ws[1][k];
+            c += ws[2][k];
+        }
+}
+
+// Epilogue of the way up: nothing, or the partials of r.z, sum z and sum r
+// over the tile's cells for the CG iteration that consumes z (r as stored,
+// or pending as in RhsPending).
+struct NoDots {
+    __device__ void add(int, double) {}
+    template <int NT>
+    __device__ void finish() {}
+};
+template <typename TR>
+struct RzDots {
+    const TR *r, *q;
+    double alpha;
+    int pending;
+    double *p0, *p1, *p2;
+    int slot;
+    double arz = 0.0, az = 0.0, ar = 0.0;
+    __device__ void add(int g, double z) {
+        const double rc =
+            pending ? (double)(TR)cg_residual((double)r[g], (double)q[g], alpha) : (double)r[g];
+        arz += rc * z;
+        az += z;
+        ar += rc;
+    }
+    template <int NT>
+    __device__ void finish() {
+        tile_sum3<NT>(arz, az, ar);
+        if (threadIdx.x == 0) {
+            p0[slot] = arz;
+            p1[slot] = az;
+            p2[slot] = ar;
+        }
+    }
+};
+
 // Way down: zero-guess pre-smoothing (red x = b / d, black GS from those),
 // residual r = b - A x, restriction of r to the coarse right-hand side bc.
 // Writes the smoothed x of the tile to xs (the level's residual array, which
 // no longer holds a residual: the way up reads x from there while it writes
 // the level's x) and bc on the tile's coarse cells.
-template <typename T, typename TB, int NT>
-__device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__restrict__ b, T *__restrict__ xs,
+template <typename T, int NT, typename BS>
+__device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const BS &b, T *__restrict__ xs,
                                   T *__restrict__ bc, int tx, int ty, int skip) {
     using R = T;
     constexpr int H = 3, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
@@ -79,7 +163,7 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
         const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
         const bool v = vx && vy;
         const int g = v ? gx + nx * gy : 0;
-        lb[k] = (T)b[g];
+        lb[k] = b.template at<T>(g);
         li[k] = L.invd[g];
         ls[k] = L.s[g];
         l0[k] = L.cs[0][g];
@@ -167,9 +251,10 @@ __device__ inline void down_tile2(const Level<T> &L, const Geo &gc, const TB *__
 // Way up: red x += P e, black GS, red GS (the post-smoothing), with e the
 // coarse correction xc and the pre-smoothed x read from xs.  Writes x on the
 // tile (never read here, so tiles do not race on their halos).
-template <typename T, typename TB, int NT>
-__device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__restrict__ xc, const TB *__restrict__ b,
-                                const T *__restrict__ xs, T *__restrict__ x, int tx, int ty, int skip) {
+template <typename T, int NT, typename BS, typename DOTS = NoDots>
+__device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__restrict__ xc, const BS &b,
+                                const T *__restrict__ xs, T *__restrict__ x, int tx, int ty, int skip,
+                                DOTS dots = DOTS()) {
     using R = T;
     constexpr int H = 2, WX = kTFX + 2 * H, WY = kTFY + 2 * H, NL = WX * WY;
     constexpr int KL = (NL + NT - 1) / NT;
@@ -190,7 +275,7 @@ __device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__res
         const int gx = tile_coord(gx0 + lx, nx, px, vx), gy = tile_coord(gy0 + ly, ny, py, vy);
         const bool v = vx && vy;
         const int g = v ? gx + nx * gy : 0;
-        lb[k] = (T)b[g];
+        lb[k] = b.template at<T>(g);
         li[k] = L.invd[g];
         l0[k] = L.cs[0][g];
         l1[k] = L.cs[1][g];
@@ -238,8 +323,11 @@ __device__ inline void up_tile2(const Level<T> &L, const Geo &gc, const T *__res
         const int gx = tx * kTFX + lx, gy = ty * kTFY + ly;
         if (gx >= nx || gy >= ny) continue;
         const int i = (ly + H) * WX + lx + H;
-        x[gx + nx * gy] = ((gx + gy) & 1) == 0 ? gs(i) : sX[i];
+        const T v = ((gx + gy) & 1) == 0 ? gs(i) : sX[i];
+        x[gx + nx * gy] = v;
+        dots.add(gx + nx * gy, (double)v);
     }
+    dots.template finish<NT>();
 }
 
 }  // namespace chns
