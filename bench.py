@@ -65,18 +65,22 @@ def parse():
 
 
 def recorded_traffic(kernel_class):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    record (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a
-    plain copy of known size); None if the record is for another kernel or the
-    kernel's sources changed since the counters were taken."""
+    """HBM bytes per launch of a kernel class (dispatch-weighted over its
+    kernels) from the committed counter record (two rocprofv3 --pmc passes,
+    FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); None if
+    the record holds no such class or the kernels' sources changed since the
+    counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
-        if rec.get("kernel_class") != kernel_class:
-            return None
         h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])).hexdigest()
-        return rec["traffic_bytes_per_launch"] if h == rec["sources_sha256"] else None
+        if h != rec["sources_sha256"]:
+            return None
+        for r in rec["records"]:
+            if r["kernel_class"] == kernel_class:
+                return r["traffic_bytes_per_launch"]
+        return None
     except (OSError, ValueError, KeyError):
         return None
 
