@@ -9,6 +9,7 @@
 #include <string>
 #include <thread>
 
+#include "spectral.h"
 #include "common.h"
 #include "solvers.h"
 #include "step.h"
@@ -29,7 +30,7 @@ static const char *kNames[K_NCLASS] = {"ch_rhs",   "mu",          "phi_update", 
                                        "project",  "smooth",      "residual",     "restrict",  "prolong",
                                        "coarse_solve", "mg_setup", "pcg_apply",   "pcg_update", "pcg_dot",
                                        "pcg_init", "mean",        "diag",        "adjoint",   "mg_down",
-                                       "mg_up"};
+                                       "mg_up",      "ch_spectral"};
 
 const char *kclass_name(int c) { return (c >= 0 && c < K_NCLASS) ? kNames[c] : "?"; }
 
@@ -242,6 +243,7 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
         M.red.counter = B.take<unsigned int>(64);
         M.red.scal = B.take<Scal>(1);
     }
+    spectral_carve(B, P.lev[0], P.dim, g->spec);
 }
 
 StepConst step_const(const chns_grid *g) { return step_const_of(g->props, g->h); }
@@ -267,6 +269,18 @@ struct SolveCtx {
 // chns_set_properties).  pidx indexes the iteration predictions.
 hipError_t run_solve_ctx(chns_grid *g, const SolveCtx &c, int setup, OpKind kind, ChOp ch, const double *b,
                          double *x, double rtol, int pidx, SolveOut *o) {
+    if (kind == OP_CH && g->spec.on) {
+        // direct solve (the same in both precision forms); v.q, v.t are
+        // free while the CH system is solved
+        std::string err;
+        hipError_t e = spectral_solve(g->spec, ch.a, ch.b, b, x, c.v.q, c.v.t, c.s, err);
+        if (e != hipSuccess && !err.empty()) set_error(CHNS_EDEVICE, err);
+        o->iters = 1;
+        o->rel_res = 0.0;
+        o->unconverged = 0;
+        o->nonfinite = 0;
+        return e;
+    }
     Slot<double> &S64 = *c.S64;
     PcgVecs<double> v = c.v;
     Red red = c.red;
@@ -519,6 +533,19 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
             return fail(CHNS_EDEVICE, std::string("stream set-up: ") + hipGetErrorString(e));
         }
         g->mc_ready = 1;
+    }
+    // direct CH solve unless CHNS_CH_SOLVER=pcg asks for MG-PCG
+    {
+        const char *cs = getenv("CHNS_CH_SOLVER");
+        if (g->spec.carved && !(cs && strcmp(cs, "pcg") == 0)) {
+            std::string err;
+            if (spectral_init(g->spec, desc->h, err)) {
+                spectral_release(g->spec);
+                release_streams(g);
+                delete g;
+                return fail(CHNS_EDEVICE, err);
+            }
+        }
     }
     memset(&g->last, 0, sizeof g->last);
     hipError_t e = hipMemsetAsync(g->red.counter, 0, 64 * sizeof(unsigned int), g->stream);
@@ -912,6 +939,7 @@ int chns_destroy_grid(chns_grid *g) {
     if (g) {
         prof_release(g->prof);
         release_streams(g);
+        spectral_release(g->spec);
     }
     delete g;
     return CHNS_OK;

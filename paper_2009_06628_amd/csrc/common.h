@@ -222,7 +222,7 @@ enum KClass {
     K_CH_RHS = 0, K_MU, K_PHI_UPDATE, K_MOM_SETUP, K_P_SETUP, K_PROJECT,
     K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE, K_MG_SETUP,
     K_PCG_APPLY, K_PCG_UPDATE, K_PCG_DOT, K_PCG_INIT, K_MEAN, K_DIAG, K_ADJOINT, K_MG_DOWN, K_MG_UP,
-    K_NCLASS
+    K_CH_SPECTRAL, K_NCLASS
 };
 
 struct Prof {
@@ -292,6 +292,17 @@ struct MomCtx {
     hipStream_t stream;
     hipEvent_t done_ev;   // recorded on stream after the solve
 };
+
+// Bases of the direct Cahn-Hilliard solve (spectral.h, spectral.hip).
+constexpr int kSpectralMaxN = 2048;   // larger axes keep the MG-PCG solve
+struct Spectral {
+    int carved;        // bases carved from the workspace (every axis <= kSpectralMaxN)
+    int on;            // set up and in use (else the CH system is solved by MG-PCG)
+    int dim, n[3], per[3];
+    double *Q[3];      // per axis: n x n basis, column-major, column k = mode k
+    double *lam[3];    // per axis: eigenvalue of each mode (1/h^2 included)
+    void *blas;        // rocBLAS handle
+};
 }  // namespace chns
 
 struct chns_grid {
@@ -316,6 +327,7 @@ struct chns_grid {
     double *diag;                            // diagnostics scratch
     int last_iters[12];                      // iteration-count predictions
     chns::MomCtx mc[2];                      // momentum components 1, 2 (component 0 uses the buffers above)
+    chns::Spectral spec;                     // direct CH solve (single grids)
     hipEvent_t ev_fork;                      // main stream -> component streams
     int mc_ready;                            // streams and events of mc created
     int adj_ready;                           // adjoint workspace attached

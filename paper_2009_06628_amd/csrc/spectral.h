@@ -1,0 +1,34 @@
+// Direct solve of the Cahn-Hilliard system of the split step (S2):
+// (I - a L + b L^2) x = r with constant a, b >= 0 and the cell-centred
+// Laplacian L of the grid (walled axes Neumann, periodic axes wrapped).
+#pragma once
+#include <string>
+
+#include "common.h"
+#include "plan.h"
+
+namespace chns {
+
+// L is a sum of 1D second differences, one per axis, each diagonalised by
+// a real orthonormal basis: DCT-II vectors on a walled axis, the real
+// Fourier basis (1, cos, sin, ..., alternating signs) on a periodic one.  So
+// the system matrix is Q diag(1 - a lam + b lam^2) Q^T with Q the tensor
+// product of the axis bases and lam the sum of the axis eigenvalues, and
+// the solve is three steps: transform every axis, divide by the
+// eigenvalue, transform back.  Each transform along an axis is a product
+// with an n x n matrix (FP64 GEMMs on the matrix cores).
+// (struct Spectral and kSpectralMaxN live in common.h, inside the handle.)
+
+// Carve the bases (sizing pass when B.base is null).
+void spectral_carve(Bump &B, const Geo &g, int dim, Spectral &S);
+// Build the bases on the host, upload them, create the BLAS handle.  Returns
+// 0, or a nonzero code with a message in err.
+int spectral_init(Spectral &S, double h, std::string &err);
+void spectral_release(Spectral &S);
+// x = (I - a L + b L^2)^{-1} r on stream st; t0, t1: scratch of N doubles.
+// Returns hipSuccess, or an error (a failed BLAS call reports
+// hipErrorLaunchFailure and its status in err).
+hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, double *x, double *t0, double *t1,
+                          hipStream_t st, std::string &err);
+
+}  // namespace chns
