@@ -29,8 +29,17 @@
  *       N_a the skew-symmetric advection of the appendix remark,
  *   S8  -D(rho_f^{-1} G p) = -(We/dt) D u*,  mean(p) = 0,
  *   S9  u^{n+1} = u* - (dt/We) rho_f^{-1} G p.
- * Every linear system is solved matrix-free by multigrid-preconditioned
- * conjugate gradients on the device.
+ * The variable-coefficient systems (S7, S8) are solved matrix-free by
+ * multigrid-preconditioned conjugate gradients on the device.  The S2
+ * system has constant coefficients: on a single grid whose axes all have at
+ * most 2048 cells it is solved directly (the 1D second difference of each
+ * axis is diagonalised by an orthonormal DCT-II basis on a walled axis and
+ * the real Fourier basis on a periodic one; the solve is one transform per
+ * axis, a division by 1 - a lam + b lam^2, and the inverse transforms, as
+ * FP64 matrix products through rocBLAS on the grid's stream).  Setting
+ * CHNS_CH_SOLVER=pcg in the environment before chns_create_grid selects
+ * multigrid-preconditioned CG for S2 instead; larger grids and the batched
+ * entry points always use it.
  *
  * Data layout (device memory, float64, row-major, x fastest):
  *   cell arrays   idx = i + nx*(j + ny*k), nx*ny*nz entries (nz = 1 in 2D);
@@ -41,9 +50,12 @@
  *                 not stored.
  *
  * Ownership: every device array (state, workspace) belongs to the caller.
- * The library keeps raw pointers and small host metadata, never allocates
- * device memory, and runs all work on the stream given at creation.  Handles
- * are not thread-safe; distinct handles are independent.
+ * The library keeps raw pointers and small host metadata and allocates no
+ * device memory for fields, hierarchies or scratch; the only device memory
+ * it does not get from the caller is what the rocBLAS handle of a
+ * single-grid handle holds (see chns_create_grid).  All work runs on the
+ * stream given at creation.  Handles are not thread-safe; distinct handles
+ * are independent.
  *
  * Errors: functions return CHNS_OK (0), the warning CHNS_ENOCONV (> 0: the
  * call completed but a linear solve stopped at max_iter), or a negative code.
@@ -131,13 +143,18 @@ typedef struct {
 
 /* Bytes of device workspace that chns_create_grid needs for this grid
  * (field buffers, multigrid hierarchy, coarse-grid inverse, reduction
- * scratch).  Returns CHNS_EINVAL for an unsupported description.         */
+ * scratch, and the S2 bases: n_a^2 + n_a doubles per axis when every axis
+ * has at most 2048 cells).  Returns CHNS_EINVAL for an unsupported
+ * description.                                                           */
 int chns_workspace_size(const chns_grid_desc *desc, size_t *bytes);
 
 /* Create a handle.  workspace: device memory of at least
  * chns_workspace_size bytes, 256-byte aligned, owned by the caller and kept
  * alive until chns_destroy_grid.  hip_stream: a hipStream_t (NULL = default
- * stream).  No device memory is allocated here or later.  The handle also
+ * stream).  The library allocates no device memory of its own for the
+ * grid; the direct S2 solve's rocBLAS handle (created here, synchronously
+ * uploading the bases into the workspace) holds the library's own small
+ * device allocations until chns_destroy_grid.  The handle also
  * creates dim - 1 non-blocking streams of default priority for the velocity
  * components 1 .. dim-1 (their momentum solves of S7 overlap with the first
  * component's; event waits order them with hip_stream, so every call still
