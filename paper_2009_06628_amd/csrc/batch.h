@@ -6,6 +6,7 @@
 
 #include "common.h"
 #include "solvers.h"
+#include "spectral.h"
 #include "step.h"
 
 namespace chns {
@@ -88,6 +89,12 @@ struct chns_batch {
     int last_iters[3];                // eager mode: most iterations any problem needed, last step
     int last_refine[3];               // eager mode: most iterations in refinement rounds, last step
     int max_iter_max;                 // largest max_iter of the problems (graph budgets never exceed it)
+    // direct CH solve of the tiled form (2D, every axis <= kSpectralMaxN):
+    // one group per problem shape, its members, the rocBLAS handle
+    std::vector<chns::SpecGroup> spec;
+    std::vector<std::vector<int>> spec_members;
+    void *blas;
+    int spec_on;
 };
 
 

@@ -14,9 +14,13 @@
 //   * per-cell arithmetic is shared with the single-grid kernels, so a batched
 //     problem matches its own single-grid run up to the order of the sums.
 // Workgroup size and workgroup count are chosen by chns_batch_autotune.
+#include <rocblas/rocblas.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -262,10 +266,11 @@ __device__ inline void record(PcgRes o, int bit, int *iters, double *res, int &f
     if (o.nonfinite) flags |= 1 << 5;
 }
 
-// S1..S9 of one problem by the calling workgroup.
+// S1..S9 of one problem by the calling workgroup.  part 0: all of them;
+// part 1: S1 only; part 2: S3..S9, S2 having been solved directly in between.
 template <typename TP, int DIM>
 __device__ void batch_problem_step(const BatchProb<TP> &P, const BatchState &st, chns_batch_stats *S,
-                                   SetupLds &sh, double *red) {
+                                   SetupLds &sh, double *red, int part) {
     const Geo &g = P.g;
     const int N = (int)g.N;
     const StepConst &k = P.k;
@@ -276,11 +281,22 @@ __device__ void batch_problem_step(const BatchProb<TP> &P, const BatchState &st,
     const W3 opcs{{P.op.cs[0], P.op.cs[1], P.op.cs[2]}};
     int flags = 0;
     long long total = 0;
-    // S1, S2
-    BLOCK_LOOP(N) ch_rhs_cell<DIM>(g, k, phi, uc, P.rch, P.phihat, c);
-    __syncthreads();
-    PcgRes o = pcg_block<TP, DIM>(P, OP_CH, P.chs, 0, P.rch, P.phihat, P.rtol_ch, P.max_iter, red);
-    record(o, 0, &S->iters_ch, &S->res_ch, flags, total);
+    PcgRes o;
+    if (part != 2) {
+        // S1, S2
+        BLOCK_LOOP(N) ch_rhs_cell<DIM>(g, k, phi, uc, P.rch, P.phihat, c);
+        __syncthreads();
+        if (part == 1) return;
+        o = pcg_block<TP, DIM>(P, OP_CH, P.chs, 0, P.rch, P.phihat, P.rtol_ch, P.max_iter, red);
+        record(o, 0, &S->iters_ch, &S->res_ch, flags, total);
+    } else {
+        // S2 solved directly: one application, no residual left
+        if (threadIdx.x == 0) {
+            S->iters_ch = 1;
+            S->res_ch = 0.0;
+        }
+        total += 1;
+    }
     // S3, S4
     BLOCK_LOOP(N) mu_cell<DIM>(g, k, phi, P.phihat, mu, c);
     __syncthreads();
@@ -318,7 +334,7 @@ template <typename TP, int DIM>
 __global__ void __launch_bounds__(kBatchMaxThreads) k_batch_step(const BatchProb<TP> *__restrict__ probs,
                                                                  const int *__restrict__ order, int nprob,
                                                                  unsigned int *queue, BatchState st,
-                                                                 chns_batch_stats *stats) {
+                                                                 chns_batch_stats *stats, int part) {
     __shared__ SetupLds sh;
     __shared__ double red[kBatchMaxThreads / kWave];
     __shared__ int s_t;
@@ -331,7 +347,7 @@ __global__ void __launch_bounds__(kBatchMaxThreads) k_batch_step(const BatchProb
         const int t = __builtin_amdgcn_readfirstlane(s_t);
         if (t >= nprob) break;
         const int i = __builtin_amdgcn_readfirstlane(order[t]);
-        batch_problem_step<TP, DIM>(probs[i], st, stats + i, sh, red);
+        batch_problem_step<TP, DIM>(probs[i], st, stats + i, sh, red, part);
     }
 }
 
@@ -490,7 +506,107 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
         }
     }
     if (b) b->total_cells = tot;
+    // direct CH solve (2D): bases and tables of every problem shape
+    bool spec_ok = dim == 2;
+    for (int i = 0; i < count && spec_ok; ++i)
+        for (int a = 0; a < 2; ++a)
+            if (plans[i].lev[0].n[a] > kSpectralMaxN) spec_ok = false;
+    std::vector<SpecGroup> groups;
+    std::vector<std::vector<int>> members;
+    if (spec_ok) {
+        for (int i = 0; i < count; ++i) {
+            const Geo &g = plans[i].lev[0];
+            size_t k = 0;
+            while (k < groups.size() && !(groups[k].nx == g.n[0] && groups[k].ny == g.n[1] &&
+                                          groups[k].perx == g.per[0] && groups[k].pery == g.per[1]))
+                ++k;
+            if (k == groups.size()) {
+                SpecGroup G;
+                memset(&G, 0, sizeof G);
+                G.nx = g.n[0];
+                G.ny = g.n[1];
+                G.perx = g.per[0];
+                G.pery = g.per[1];
+                groups.push_back(G);
+                members.emplace_back();
+            }
+            groups[k].m += 1;
+            members[k].push_back(i);
+        }
+        for (SpecGroup &G : groups) {
+            const size_t m = (size_t)G.m;
+            G.Q[0] = B.take<double>((size_t)G.nx * G.nx);
+            G.Q[1] = B.take<double>((size_t)G.ny * G.ny);
+            G.lam[0] = B.take<double>((size_t)G.nx);
+            G.lam[1] = B.take<double>((size_t)G.ny);
+            G.abh = B.take<double>(3 * m);
+            G.r = (const double **)B.take<double *>(m);
+            G.x = B.take<double *>(m);
+            G.t0 = B.take<double *>(m);
+            G.t1 = B.take<double *>(m);
+            G.Qx = (const double **)B.take<double *>(m);
+            G.Qy = (const double **)B.take<double *>(m);
+        }
+    }
+    if (b) {
+        b->spec = groups;
+        b->spec_members = members;
+    }
     return B.off;
+}
+
+// Tables and bases of the direct CH solve; handle; one warm-up solve (so
+// that a captured step never meets rocBLAS's first-use set-up).  Off with
+// CHNS_CH_SOLVER=pcg, for 3D batches and for axes over kSpectralMaxN.
+template <typename TP>
+int spectral_batch_setup(chns_batch *b, const std::vector<BatchProb<TP>> &h) {
+    b->spec_on = 0;
+    b->blas = nullptr;
+    const char *cs = getenv("CHNS_CH_SOLVER");
+    if (b->spec.empty() || (cs && strcmp(cs, "pcg") == 0)) return CHNS_OK;
+    for (size_t k = 0; k < b->spec.size(); ++k) {
+        const SpecGroup &G = b->spec[k];
+        const std::vector<int> &mem = b->spec_members[k];
+        std::vector<double> Q, lam, abh;
+        std::vector<const double *> r, qx, qy;
+        std::vector<double *> x, t0, t1;
+        for (int i : mem) {
+            abh.push_back(h[i].ch.a);
+            abh.push_back(h[i].ch.b);
+            abh.push_back(h[i].ch.ih2);
+            r.push_back(h[i].rch);
+            x.push_back(h[i].phihat);
+            t0.push_back(h[i].q);
+            t1.push_back(h[i].t);
+            qx.push_back(G.Q[0]);
+            qy.push_back(G.Q[1]);
+        }
+        hipError_t e = hipSuccess;
+        for (int a = 0; a < 2 && e == hipSuccess; ++a) {
+            spectral_axis(a ? G.ny : G.nx, a ? G.pery : G.perx, 1.0, Q, lam);
+            e = hipMemcpy(G.Q[a], Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(G.lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice);
+        }
+        const size_t pm = sizeof(void *) * mem.size();
+        if (e == hipSuccess) e = hipMemcpy(G.abh, abh.data(), abh.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy((void *)G.r, r.data(), pm, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy((void *)G.x, x.data(), pm, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy((void *)G.t0, t0.data(), pm, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy((void *)G.t1, t1.data(), pm, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy((void *)G.Qx, qx.data(), pm, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy((void *)G.Qy, qy.data(), pm, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("CH bases: ") + hipGetErrorString(e));
+    }
+    rocblas_handle hb = nullptr;
+    if (rocblas_create_handle(&hb) != rocblas_status_success) return set_error(CHNS_EDEVICE, "rocblas_create_handle");
+    b->blas = hb;
+    std::string err;
+    hipError_t e = spectral_batch_solve(b->blas, b->spec, b->stream, err);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess)
+        return set_error(CHNS_EDEVICE, "CH warm-up solve: " + (err.empty() ? std::string(hipGetErrorString(e)) : err));
+    b->spec_on = 1;
+    return CHNS_OK;
 }
 
 int check_descs(int count, const chns_grid_desc *descs, std::vector<Plan> &plans) {
@@ -511,12 +627,24 @@ size_t batch_bytes(int count, const std::vector<Plan> &plans) {
     return layout_batch<TP>(B, count, plans.data(), nullptr, nullptr, nullptr) + 256;
 }
 
+// One persistent step; with the direct CH solve, S1 | S2 (batched GEMMs) |
+// S3..S9.  Returns 0 or an error code.
 template <typename TP, int DIM>
-void launch_step(chns_batch *b, const BatchState &st, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset_queue, dim3(1), dim3(64), 0, s, b->d_queue);
-    hipLaunchKernelGGL((k_batch_step<TP, DIM>), dim3(b->grid), dim3(b->block), 0, s,
-                       (const BatchProb<TP> *)b->d_probs, (const int *)b->d_order, b->count, b->d_queue, st,
-                       b->d_stats);
+int launch_step(chns_batch *b, const BatchState &st, hipStream_t s) {
+    const int parts[2] = {b->spec_on ? 1 : 0, 2};
+    for (int k = 0; k < (b->spec_on ? 2 : 1); ++k) {
+        if (k == 1) {
+            std::string err;
+            const hipError_t e = spectral_batch_solve(b->blas, b->spec, s, err);
+            if (e != hipSuccess)
+                return set_error(CHNS_EDEVICE, "CH direct solve: " + (err.empty() ? hipGetErrorString(e) : err));
+        }
+        hipLaunchKernelGGL(k_batch_reset_queue, dim3(1), dim3(64), 0, s, b->d_queue);
+        hipLaunchKernelGGL((k_batch_step<TP, DIM>), dim3(b->grid), dim3(b->block), 0, s,
+                           (const BatchProb<TP> *)b->d_probs, (const int *)b->d_order, b->count, b->d_queue, st,
+                           b->d_stats, parts[k]);
+    }
+    return CHNS_OK;
 }
 
 // graph != 0: the launches are being captured; the per-call statistics are
@@ -527,11 +655,12 @@ int launch_steps(chns_batch *b, const BatchState &st, int nsteps, hipStream_t s,
         hipLaunchKernelGGL(k_batch_reset_stats, dim3((b->count + 255) / 256), dim3(256), 0, s, b->d_stats, b->count);
     if (b->mode == CHNS_BATCH_TILED) return tiled_steps(b, st, nsteps, graph, s, b->d_stats);
     for (int n = 0; n < nsteps; ++n) {
-        if (b->prec == CHNS_FP64) {
-            if (b->dim == 2) launch_step<double, 2>(b, st, s); else launch_step<double, 3>(b, st, s);
-        } else {
-            if (b->dim == 2) launch_step<float, 2>(b, st, s); else launch_step<float, 3>(b, st, s);
-        }
+        int rc;
+        if (b->prec == CHNS_FP64)
+            rc = b->dim == 2 ? launch_step<double, 2>(b, st, s) : launch_step<double, 3>(b, st, s);
+        else
+            rc = b->dim == 2 ? launch_step<float, 2>(b, st, s) : launch_step<float, 3>(b, st, s);
+        if (rc) return rc;
     }
     return CHNS_OK;
 }
@@ -705,6 +834,7 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     Bump B{(char *)workspace, 0};
     std::vector<char> host_table;
     size_t entry = 0;
+    std::function<int(chns_batch *)> spec_host;
     auto fill = [&](auto tag) {
         using TP = decltype(tag);
         std::vector<BatchProb<TP>> h;
@@ -718,6 +848,7 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
         entry = sizeof(BatchProb<TP>);
         host_table.resize(entry * count);
         memcpy(host_table.data(), h.data(), entry * count);
+        spec_host = [h](chns_batch *bb) { return spectral_batch_setup<TP>(bb, h); };
     };
     if (b->prec == CHNS_FP64) fill(double()); else fill(float());
     b->offsets.resize(count + 1);
@@ -729,6 +860,7 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     std::stable_sort(b->order.begin(), b->order.end(),
                      [&](int x, int y) { return plans[x].lev[0].N > plans[y].lev[0].N; });
     auto cleanup = [&](int rc) {
+        if (b->blas) (void)rocblas_destroy_handle((rocblas_handle)b->blas);
         if (b->stream) (void)hipStreamDestroy(b->stream);
         if (b->ev_in) (void)hipEventDestroy(b->ev_in);
         if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -763,6 +895,7 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return cleanup(set_error(CHNS_EDEVICE, std::string("batch init: ") + hipGetErrorString(e)));
+    if (int rc = spec_host(b)) return cleanup(rc);
     *out = b;
     return CHNS_OK;
 }
@@ -976,6 +1109,7 @@ int chns_destroy_batch(chns_batch *b) {
     drop_graph(b);
     if (b->stream) {
         (void)hipStreamSynchronize(b->stream);
+        if (b->blas) (void)rocblas_destroy_handle((rocblas_handle)b->blas);
         (void)hipStreamDestroy(b->stream);
     }
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);

@@ -598,6 +598,15 @@ __global__ void k_t_record(const BatchProb<TP> *__restrict__ probs, int nprob, i
     }
 }
 
+// statistics of the direct CH solve: one application, no residual left
+__global__ void k_t_record_direct(int nprob, chns_batch_stats *__restrict__ stats) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nprob; i += gridDim.x * blockDim.x) {
+        stats[i].iters_ch = 1;
+        stats[i].res_ch = 0.0;
+        stats[i].total_iters += 1;
+    }
+}
+
 }  // namespace chns
 
 // ---------------------------------------------------------------------------
@@ -782,7 +791,15 @@ struct Tiled {
     }
     int step(chns_batch_stats *stats) {
         phase(0);   // S1
-        if (int rc = solve(TS_CH, stats)) return rc;
+        if (b->spec_on) {   // S2 by the direct solve
+            std::string err;
+            const hipError_t e = spectral_batch_solve(b->blas, b->spec, s, err);
+            if (e != hipSuccess)
+                return set_error(CHNS_EDEVICE, "CH direct solve: " + (err.empty() ? hipGetErrorString(e) : err));
+            hipLaunchKernelGGL(k_t_record_direct, dim3((np() + 255) / 256), dim3(256), 0, s, np(), stats);
+        } else if (int rc = solve(TS_CH, stats)) {
+            return rc;
+        }
         phase(1);   // S3
         phase(2);   // S4
         for (int a = 0; a < DIM; ++a) {

@@ -3,6 +3,7 @@
 // Laplacian L of the grid (walled axes Neumann, periodic axes wrapped).
 #pragma once
 #include <string>
+#include <vector>
 
 #include "common.h"
 #include "plan.h"
@@ -18,6 +19,24 @@ namespace chns {
 // eigenvalue, transform back.  Each transform along an axis is a product
 // with an n x n matrix (FP64 GEMMs on the matrix cores).
 // (struct Spectral and kSpectralMaxN live in common.h, inside the handle.)
+
+// Basis and eigenvalues of the 1D second difference on n cells of spacing h
+// (host; walled axis: DCT-II, periodic: real Fourier), column-major.
+void spectral_axis(int n, int per, double h, std::vector<double> &Q, std::vector<double> &lam);
+
+// Batched form (2D): the problems of one shape {nx, ny, periodic axes}
+// share the bases; per problem a, b, 1/h^2 and the pointers of its arrays.
+struct SpecGroup {
+    int nx, ny, perx, pery, m;
+    double *Q[2], *lam[2];       // bases, eigenvalues for unit spacing
+    double *abh;                 // per problem: a, b, 1/h^2
+    const double **r;            // per problem: right-hand side
+    double **x;                  // per problem: solution
+    double **t0, **t1;           // per problem: scratch
+    const double **Qx, **Qy;     // the bases repeated m times (batched GEMM operands)
+};
+// x_p = (I - a_p L + b_p L^2)^{-1} r_p for every problem of every group, on st.
+hipError_t spectral_batch_solve(void *blas, const std::vector<SpecGroup> &groups, hipStream_t st, std::string &err);
 
 // Carve the bases (sizing pass when B.base is null).
 void spectral_carve(Bump &B, const Geo &g, int dim, Spectral &S);

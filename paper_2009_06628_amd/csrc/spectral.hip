@@ -2,6 +2,7 @@
 #include <rocblas/rocblas.h>
 
 #include <cmath>
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -35,7 +36,7 @@ void spectral_carve(Bump &B, const Geo &g, int dim, Spectral &S) {
 // 0 < k < n / 2 (eigenvalue -(4 / h^2) sin^2(pi k / n) for both), then
 // (-1)^j / sqrt(n) when n is even.  Angles are reduced exactly in integers
 // before the trigonometric call.
-static void axis_basis(int n, int per, double h, std::vector<double> &Q, std::vector<double> &lam) {
+void spectral_axis(int n, int per, double h, std::vector<double> &Q, std::vector<double> &lam) {
     const double pi = std::acos(-1.0), ih2 = 1.0 / (h * h);
     Q.assign((size_t)n * n, 0.0);
     lam.assign((size_t)n, 0.0);
@@ -76,7 +77,7 @@ int spectral_init(Spectral &S, double h, std::string &err) {
     if (!S.carved) return 0;
     std::vector<double> Q, lam;
     for (int a = 0; a < S.dim; ++a) {
-        axis_basis(S.n[a], S.per[a], h, Q, lam);
+        spectral_axis(S.n[a], S.per[a], h, Q, lam);
         hipError_t e = hipMemcpy(S.Q[a], Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(S.lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
@@ -169,6 +170,48 @@ hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, doub
     std::swap(cur, oth);
     BLASCHK(rocblas_dgemm(hb, N, N, nx, ny * nz, nx, &one, S.Q[0], nx, cur, nx, &zero, x, nx));
     if (e1) (void)hipEventRecord(e1, st);
+    return hipGetLastError();
+}
+
+// t_p /= 1 - a_p lam + b_p lam^2, lam = (lam_x(i) + lam_y(j)) / h_p^2;
+// blockIdx.y = problem of the group
+__global__ void __launch_bounds__(kBlock) k_spectral_scale_batch(int nx, int ny, const double *__restrict__ lx,
+                                                                 const double *__restrict__ ly,
+                                                                 const double *__restrict__ abh,
+                                                                 double *const *__restrict__ t) {
+    const int p = (int)blockIdx.y;
+    const double a = abh[3 * p], b = abh[3 * p + 1], ih2 = abh[3 * p + 2];
+    double *tp = t[p];
+    const int n = nx * ny, stride = (int)(gridDim.x * blockDim.x);
+    for (int c = (int)(blockIdx.x * blockDim.x + threadIdx.x); c < n; c += stride) {
+        const int j = c / nx, i = c - j * nx;
+        const double lam = ih2 * (lx[i] + ly[j]);
+        tp[c] = tp[c] / (1.0 - a * lam + b * lam * lam);
+    }
+}
+
+hipError_t spectral_batch_solve(void *blas, const std::vector<SpecGroup> &groups, hipStream_t st, std::string &err) {
+    rocblas_handle hb = (rocblas_handle)blas;
+    const double one = 1.0, zero = 0.0;
+    const rocblas_operation N = rocblas_operation_none, T = rocblas_operation_transpose;
+    BLASCHK(rocblas_set_stream(hb, st));
+    for (const SpecGroup &G : groups) {
+        const int nx = G.nx, ny = G.ny, m = G.m;
+        // column-major nx x ny per problem (x fastest): t0 = Qx^T r, t1 = t0 Qy
+        BLASCHK(rocblas_dgemm_batched(hb, T, N, nx, ny, nx, &one, G.Qx, nx, G.r, nx, &zero, G.t0, nx, m));
+        BLASCHK(rocblas_dgemm_batched(hb, N, N, nx, ny, ny, &one, (const double *const *)G.t0, nx, G.Qy, ny, &zero,
+                                      G.t1, nx, m));
+        const int bx = std::min((nx * ny + kBlock - 1) / kBlock, 64);
+        hipLaunchKernelGGL(k_spectral_scale_batch, dim3(bx, m), dim3(kBlock), 0, st, nx, ny, (const double *)G.lam[0],
+                           (const double *)G.lam[1], (const double *)G.abh, (double *const *)G.t1);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        // back: t0 = t1 Qy^T, x = Qx t0
+        BLASCHK(rocblas_dgemm_batched(hb, N, T, nx, ny, ny, &one, (const double *const *)G.t1, nx, G.Qy, ny, &zero,
+                                      G.t0, nx, m));
+        BLASCHK(rocblas_dgemm_batched(hb, N, N, nx, ny, nx, &one, G.Qx, nx, (const double *const *)G.t0, nx, &zero,
+                                      G.x, nx, m));
+    }
     return hipGetLastError();
 }
 
