@@ -288,6 +288,22 @@ __device__ inline void coarsen_cell(const Level<T> &F, const Level<T> &C, int c)
 // ---------------------------------------------------------------------------
 #define BLOCK_LOOP(N) for (int c = (int)threadIdx.x; c < (int)(N); c += (int)blockDim.x)
 
+// Red-black sweeps on each side of the cycle on the levels of at most
+// kSmallSweepCells cells, the part run by one workgroup (one sweep on the
+// larger levels).  With one sweep there, the coarse levels of a high-
+// contrast system (density ratio 1000) leave most of the error: a CPU
+// emulation of the bubble's pressure system at 256 x 512 needs 30 CG
+// iterations with one sweep, 18 with two and 15 with three on these
+// levels, which cost LDS passes but no launches (measured on the device:
+// 30 / 19 / 17 iterations, 2.67 / 2.25 / 2.17 ms per bubble step).  The
+// pre-sweeps run red then black, the post-sweeps black then red, so the
+// cycle stays symmetric.
+#ifndef CHNS_SMALL_SWEEPS
+#define CHNS_SMALL_SWEEPS 3
+#endif
+constexpr int kSmallSweeps = CHNS_SMALL_SWEEPS;
+constexpr int kSmallSweepCells = 2048;
+
 // x = Ainv b on the coarsest level (FP64 matrix, block-wide)
 template <typename T, typename TB>
 __device__ inline void coarse_solve_block(int n, const double *__restrict__ Ainv, const TB *__restrict__ b,
@@ -305,6 +321,13 @@ __device__ inline void block_down(const Slot<T> &S, int l, const TB *__restrict_
     const Level<T> &lv = S.lev[l];
     BLOCK_LOOP(lv.g.N) presmooth_cell<T, TB, DIM>(lv, b, x, c);
     __syncthreads();
+    if (lv.g.N <= kSmallSweepCells)
+        for (int sw = 1; sw < kSmallSweeps; ++sw) {
+            BLOCK_LOOP(lv.g.N) gs_color_cell<T, TB, DIM>(lv, b, x, 0, c);
+            __syncthreads();
+            BLOCK_LOOP(lv.g.N) gs_color_cell<T, TB, DIM>(lv, b, x, 1, c);
+            __syncthreads();
+        }
     BLOCK_LOOP(lv.g.N) residual_cell<T, TB, DIM>(lv, b, x, c);
     __syncthreads();
     BLOCK_LOOP(S.lev[l + 1].g.N) restrict_cell<T, DIM>(lv.g, S.lev[l + 1].g, lv.r, S.lev[l + 1].b, c);
@@ -318,6 +341,13 @@ __device__ inline void block_up(const Slot<T> &S, int l, const TB *__restrict__ 
     __syncthreads();
     BLOCK_LOOP(lv.g.N) red_from_tmp_cell<T, TB, DIM>(lv, b, lv.r, x, c);
     __syncthreads();
+    if (lv.g.N <= kSmallSweepCells)
+        for (int sw = 1; sw < kSmallSweeps; ++sw) {
+            BLOCK_LOOP(lv.g.N) gs_color_cell<T, TB, DIM>(lv, b, x, 1, c);
+            __syncthreads();
+            BLOCK_LOOP(lv.g.N) gs_color_cell<T, TB, DIM>(lv, b, x, 0, c);
+            __syncthreads();
+        }
 }
 
 // V-cycle over levels [l0, nlev) in one workgroup.  b0 / x0 are the
@@ -463,8 +493,10 @@ __device__ inline void coarse_solve_lds(int n, const double *Ainv, const T *b, T
 // enumerating the cells of one colour (no wave runs both colours' branches):
 //   pre-smoothing  the k-th red (x = b / d) and the k-th black cell (GS from
 //                  its red neighbours' b / d) in one pass
-//   post-smoothing red x += P e | black GS | red GS  (no prolonged value is
-//                  recomputed, unlike the fused pass of the grid kernels)
+//                  (then kSmallSweeps - 1 more red | black sweeps)
+//   post-smoothing red x += P e, then kSmallSweeps x (black GS | red GS)
+//                  (no prolonged value is recomputed, unlike the fused pass
+//                  of the grid kernels)
 // Ends with a workgroup barrier.
 template <typename T, int DIM>
 __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
@@ -485,6 +517,15 @@ __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const
             lv.x[cb] = (T)(((R)lv.b[cb] + offsum_at<T, DIM>(lv, cb, ib, red)) * (R)lv.invd[cb]);
         }
         __syncthreads();
+        for (int sw = 1; sw < kSmallSweeps; ++sw)
+            for (int col = 0; col < 2; ++col) {
+                LDS_COLOR_LOOP(lv.g.N) {
+                    int ia[3];
+                    const int c = color_cell<DIM>(lv.g, k, col, ia);
+                    gs_at<T, DIM>(lv, c, ia);
+                }
+                __syncthreads();
+            }
         LDS_LOOP(lv.g.N) residual_cell<T, T, DIM>(lv, lv.b, lv.x, c);
         __syncthreads();
         LDS_LOOP(lc.g.N) restrict_cell<T, DIM>(lv.g, lc.g, lv.r, lc.b, c);
@@ -504,18 +545,15 @@ __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const
             lv.x[c] = (T)((R)lv.x[c] + prolong_at<T, DIM>(lv.g, lc.g, lc.x, ia));
         }
         __syncthreads();
-        LDS_COLOR_LOOP(lv.g.N) {
-            int ia[3];
-            const int c = color_cell<DIM>(lv.g, k, 1, ia);
-            gs_at<T, DIM>(lv, c, ia);
-        }
-        __syncthreads();
-        LDS_COLOR_LOOP(lv.g.N) {
-            int ia[3];
-            const int c = color_cell<DIM>(lv.g, k, 0, ia);
-            gs_at<T, DIM>(lv, c, ia);
-        }
-        __syncthreads();
+        for (int sw = 0; sw < kSmallSweeps; ++sw)
+            for (int col = 1; col >= 0; --col) {
+                LDS_COLOR_LOOP(lv.g.N) {
+                    int ia[3];
+                    const int c = color_cell<DIM>(lv.g, k, col, ia);
+                    gs_at<T, DIM>(lv, c, ia);
+                }
+                __syncthreads();
+            }
     }
 }
 
@@ -588,6 +626,18 @@ __device__ inline void vcycle_lds2_dev(const Slot<T> &S, int l0, char *lds, cons
             lv.x[bl.c] = (T)(((R)lv.b[bl.c] + offsum(lv, bl, red)) * (R)lv.invd[bl.c]);
         }
         __syncthreads();
+        auto xd = [&](int e) { return (R)lv.x[e]; };
+        for (int sw = 1; sw < kSmallSweeps; ++sw)
+            for (int col = 0; col < 2; ++col) {
+                LDS_PAIR_LOOP(lv.g.N) {
+                    Wrap2 r, bl;
+                    int ia[3];
+                    pair_of(lv.g, k, r, bl, ia);
+                    const Wrap2 &w = col ? bl : r;
+                    lv.x[w.c] = (T)(((R)lv.b[w.c] + offsum(lv, w, xd)) * (R)lv.invd[w.c]);
+                }
+                __syncthreads();
+            }
         LDS_PAIR_LOOP(lv.g.N) {
             Wrap2 r, bl;
             int ia[3];
@@ -615,20 +665,17 @@ __device__ inline void vcycle_lds2_dev(const Slot<T> &S, int l0, char *lds, cons
             lv.x[r.c] = (T)((R)lv.x[r.c] + prolong_at<T, 2>(lv.g, lc.g, lc.x, ia));
         }
         __syncthreads();
-        LDS_PAIR_LOOP(lv.g.N) {
-            Wrap2 r, bl;
-            int ia[3];
-            pair_of(lv.g, k, r, bl, ia);
-            lv.x[bl.c] = (T)(((R)lv.b[bl.c] + offsum(lv, bl, xv)) * (R)lv.invd[bl.c]);
-        }
-        __syncthreads();
-        LDS_PAIR_LOOP(lv.g.N) {
-            Wrap2 r, bl;
-            int ia[3];
-            pair_of(lv.g, k, r, bl, ia);
-            lv.x[r.c] = (T)(((R)lv.b[r.c] + offsum(lv, r, xv)) * (R)lv.invd[r.c]);
-        }
-        __syncthreads();
+        for (int sw = 0; sw < kSmallSweeps; ++sw)
+            for (int col = 1; col >= 0; --col) {
+                LDS_PAIR_LOOP(lv.g.N) {
+                    Wrap2 r, bl;
+                    int ia[3];
+                    pair_of(lv.g, k, r, bl, ia);
+                    const Wrap2 &w = col ? bl : r;
+                    lv.x[w.c] = (T)(((R)lv.b[w.c] + offsum(lv, w, xv)) * (R)lv.invd[w.c]);
+                }
+                __syncthreads();
+            }
     }
 }
 
