@@ -262,6 +262,10 @@ def main():
                 "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
                 "launches_per_step": round(dom["launches"] / args.profile_steps, 1),
                 "share_of_kernel_time": round(dom["ms"] / sum(k["ms"] for k in kernels), 4)}
+        if dom["name"] == "coarse_solve":
+            roof["note"] = ("one-workgroup V-cycle of the levels of <= 2048 cells out of LDS: ~45 dependent "
+                            "LDS passes on one CU, latency-bound; its HBM bytes are the copy-in and the "
+                            "write-back of x")
 
     cpu = None
     if not args.no_cpu_baseline and args.cpu_steps > 0:
