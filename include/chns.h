@@ -298,14 +298,23 @@ typedef struct {
     double cand_ms[CHNS_MAX_TUNING];
 } chns_batch_tuning;
 
-/* Workspace bytes for count problems (descs[i] as for a single grid).     */
+/* Workspace bytes for count problems (descs[i] as for a single grid),
+ * including, for 2D batches, the S2 bases of every distinct problem shape
+ * and per-problem pointer tables of the direct solve.                    */
 int chns_batch_workspace_size(int count, const chns_grid_desc *descs, size_t *bytes);
 
 /* Create a batch: descs[count], props[count] (copied), caller-owned device
  * workspace (256-byte aligned).  hip_stream: the caller's stream; the batch
  * runs on an internal non-blocking stream ordered after it and before any
  * later work on it.  Builds the constant CH hierarchies (synchronises).
- * No device memory is allocated here or later.                            */
+ * 2D batches solve S2 directly, as single grids do: the problems of one
+ * shape share their bases, and each solve is four rocBLAS batched GEMMs per
+ * shape plus a scaling launch.  Both forms (persistent, tiled) use it.  The
+ * rocBLAS handle is created here and runs one warm-up solve, so a captured
+ * step never meets rocBLAS's first-use set-up; it holds the only device
+ * memory the library does not get from the caller, until
+ * chns_destroy_batch.  CHNS_CH_SOLVER=pcg in the environment, 3D batches
+ * and axes over 2048 cells keep multigrid-preconditioned CG for S2.       */
 int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *props, void *workspace,
                       size_t bytes, void *hip_stream, struct chns_batch **out);
 
