@@ -89,11 +89,10 @@ struct chns_batch {
     int last_iters[3];                // eager mode: most iterations any problem needed, last step
     int last_refine[3];               // eager mode: most iterations in refinement rounds, last step
     int max_iter_max;                 // largest max_iter of the problems (graph budgets never exceed it)
-    // direct CH solve of the tiled form (2D, every axis <= kSpectralMaxN):
-    // one group per problem shape, its members, the rocBLAS handle
+    // direct CH solve (2D, every axis <= kSpectralMaxN): one group per
+    // problem shape, and its members
     std::vector<chns::SpecGroup> spec;
     std::vector<std::vector<int>> spec_members;
-    void *blas;
     int spec_on;
 };
 

@@ -14,8 +14,6 @@
 //   * per-cell arithmetic is shared with the single-grid kernels, so a batched
 //     problem matches its own single-grid run up to the order of the sums.
 // Workgroup size and workgroup count are chosen by chns_batch_autotune.
-#include <rocblas/rocblas.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -544,8 +542,6 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
             G.x = B.take<double *>(m);
             G.t0 = B.take<double *>(m);
             G.t1 = B.take<double *>(m);
-            G.Qx = (const double **)B.take<double *>(m);
-            G.Qy = (const double **)B.take<double *>(m);
         }
     }
     if (b) {
@@ -555,20 +551,18 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
     return B.off;
 }
 
-// Tables and bases of the direct CH solve; handle; one warm-up solve (so
-// that a captured step never meets rocBLAS's first-use set-up).  Off with
-// CHNS_CH_SOLVER=pcg, for 3D batches and for axes over kSpectralMaxN.
+// Tables and bases of the direct CH solve.  Off with CHNS_CH_SOLVER=pcg,
+// for 3D batches and for axes over kSpectralMaxN.
 template <typename TP>
 int spectral_batch_setup(chns_batch *b, const std::vector<BatchProb<TP>> &h) {
     b->spec_on = 0;
-    b->blas = nullptr;
     const char *cs = getenv("CHNS_CH_SOLVER");
     if (b->spec.empty() || (cs && strcmp(cs, "pcg") == 0)) return CHNS_OK;
     for (size_t k = 0; k < b->spec.size(); ++k) {
         const SpecGroup &G = b->spec[k];
         const std::vector<int> &mem = b->spec_members[k];
         std::vector<double> Q, lam, abh;
-        std::vector<const double *> r, qx, qy;
+        std::vector<const double *> r;
         std::vector<double *> x, t0, t1;
         for (int i : mem) {
             abh.push_back(h[i].ch.a);
@@ -578,8 +572,6 @@ int spectral_batch_setup(chns_batch *b, const std::vector<BatchProb<TP>> &h) {
             x.push_back(h[i].phihat);
             t0.push_back(h[i].q);
             t1.push_back(h[i].t);
-            qx.push_back(G.Q[0]);
-            qy.push_back(G.Q[1]);
         }
         hipError_t e = hipSuccess;
         for (int a = 0; a < 2 && e == hipSuccess; ++a) {
@@ -593,18 +585,8 @@ int spectral_batch_setup(chns_batch *b, const std::vector<BatchProb<TP>> &h) {
         if (e == hipSuccess) e = hipMemcpy((void *)G.x, x.data(), pm, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy((void *)G.t0, t0.data(), pm, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy((void *)G.t1, t1.data(), pm, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy((void *)G.Qx, qx.data(), pm, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy((void *)G.Qy, qy.data(), pm, hipMemcpyHostToDevice);
         if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("CH bases: ") + hipGetErrorString(e));
     }
-    rocblas_handle hb = nullptr;
-    if (rocblas_create_handle(&hb) != rocblas_status_success) return set_error(CHNS_EDEVICE, "rocblas_create_handle");
-    b->blas = hb;
-    std::string err;
-    hipError_t e = spectral_batch_solve(b->blas, b->spec, b->stream, err);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess)
-        return set_error(CHNS_EDEVICE, "CH warm-up solve: " + (err.empty() ? std::string(hipGetErrorString(e)) : err));
     b->spec_on = 1;
     return CHNS_OK;
 }
@@ -634,10 +616,8 @@ int launch_step(chns_batch *b, const BatchState &st, hipStream_t s) {
     const int parts[2] = {b->spec_on ? 1 : 0, 2};
     for (int k = 0; k < (b->spec_on ? 2 : 1); ++k) {
         if (k == 1) {
-            std::string err;
-            const hipError_t e = spectral_batch_solve(b->blas, b->spec, s, err);
-            if (e != hipSuccess)
-                return set_error(CHNS_EDEVICE, "CH direct solve: " + (err.empty() ? hipGetErrorString(e) : err));
+            const hipError_t e = spectral_batch_solve(b->spec, s);
+            if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("CH direct solve: ") + hipGetErrorString(e));
         }
         hipLaunchKernelGGL(k_batch_reset_queue, dim3(1), dim3(64), 0, s, b->d_queue);
         hipLaunchKernelGGL((k_batch_step<TP, DIM>), dim3(b->grid), dim3(b->block), 0, s,
@@ -860,7 +840,6 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     std::stable_sort(b->order.begin(), b->order.end(),
                      [&](int x, int y) { return plans[x].lev[0].N > plans[y].lev[0].N; });
     auto cleanup = [&](int rc) {
-        if (b->blas) (void)rocblas_destroy_handle((rocblas_handle)b->blas);
         if (b->stream) (void)hipStreamDestroy(b->stream);
         if (b->ev_in) (void)hipEventDestroy(b->ev_in);
         if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -1109,7 +1088,6 @@ int chns_destroy_batch(chns_batch *b) {
     drop_graph(b);
     if (b->stream) {
         (void)hipStreamSynchronize(b->stream);
-        if (b->blas) (void)rocblas_destroy_handle((rocblas_handle)b->blas);
         (void)hipStreamDestroy(b->stream);
     }
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);

@@ -792,10 +792,8 @@ struct Tiled {
     int step(chns_batch_stats *stats) {
         phase(0);   // S1
         if (b->spec_on) {   // S2 by the direct solve
-            std::string err;
-            const hipError_t e = spectral_batch_solve(b->blas, b->spec, s, err);
-            if (e != hipSuccess)
-                return set_error(CHNS_EDEVICE, "CH direct solve: " + (err.empty() ? hipGetErrorString(e) : err));
+            const hipError_t e = spectral_batch_solve(b->spec, s);
+            if (e != hipSuccess) return set_error(CHNS_EDEVICE, std::string("CH direct solve: ") + hipGetErrorString(e));
             hipLaunchKernelGGL(k_t_record_direct, dim3((np() + 255) / 256), dim3(256), 0, s, np(), stats);
         } else if (int rc = solve(TS_CH, stats)) {
             return rc;

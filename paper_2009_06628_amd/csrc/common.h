@@ -301,7 +301,6 @@ struct Spectral {
     int dim, n[3], per[3];
     double *Q[3];      // per axis: n x n basis, column-major, column k = mode k
     double *lam[3];    // per axis: eigenvalue of each mode (1/h^2 included)
-    void *blas;        // rocBLAS handle
 };
 }  // namespace chns
 

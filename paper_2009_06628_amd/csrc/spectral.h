@@ -17,7 +17,7 @@ namespace chns {
 // product of the axis bases and lam the sum of the axis eigenvalues, and
 // the solve is three steps: transform every axis, divide by the
 // eigenvalue, transform back.  Each transform along an axis is a product
-// with an n x n matrix (FP64 GEMMs on the matrix cores).
+// with an n x n matrix (a hand-written FP64 tiled kernel, vector FMAs).
 // (struct Spectral and kSpectralMaxN live in common.h, inside the handle.)
 
 // Basis and eigenvalues of the 1D second difference on n cells of spacing h
@@ -33,20 +33,18 @@ struct SpecGroup {
     const double **r;            // per problem: right-hand side
     double **x;                  // per problem: solution
     double **t0, **t1;           // per problem: scratch
-    const double **Qx, **Qy;     // the bases repeated m times (batched GEMM operands)
 };
 // x_p = (I - a_p L + b_p L^2)^{-1} r_p for every problem of every group, on st.
-hipError_t spectral_batch_solve(void *blas, const std::vector<SpecGroup> &groups, hipStream_t st, std::string &err);
+hipError_t spectral_batch_solve(const std::vector<SpecGroup> &groups, hipStream_t st);
 
 // Carve the bases (sizing pass when B.base is null).
 void spectral_carve(Bump &B, const Geo &g, int dim, Spectral &S);
-// Build the bases on the host, upload them, create the BLAS handle.  Returns
-// 0, or a nonzero code with a message in err.
+// Build the bases on the host and upload them.  Returns 0, or a nonzero code
+// with a message in err.
 int spectral_init(Spectral &S, double h, std::string &err);
 void spectral_release(Spectral &S);
 // x = (I - a L + b L^2)^{-1} r on stream st; t0, t1: scratch of N doubles.
-// Returns hipSuccess, or an error (a failed BLAS call reports
-// hipErrorLaunchFailure and its status in err).
+// Returns hipSuccess or the launch error.
 hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, double *x, double *t0, double *t1,
                           hipStream_t st, std::string &err);
 

@@ -1,6 +1,4 @@
 // Direct (spectral) solve of the Cahn-Hilliard system; see spectral.h.
-#include <rocblas/rocblas.h>
-
 #include <cmath>
 #include <algorithm>
 #include <utility>
@@ -14,7 +12,6 @@ void spectral_carve(Bump &B, const Geo &g, int dim, Spectral &S) {
     S.carved = 1;
     S.on = 0;
     S.dim = dim;
-    S.blas = nullptr;
     for (int a = 0; a < 3; ++a) {
         S.n[a] = a < dim ? (int)g.n[a] : 1;
         S.per[a] = a < dim ? g.per[a] : 1;
@@ -85,21 +82,137 @@ int spectral_init(Spectral &S, double h, std::string &err) {
             return 1;
         }
     }
-    rocblas_handle hb = nullptr;
-    const rocblas_status st = rocblas_create_handle(&hb);
-    if (st != rocblas_status_success) {
-        err = std::string("rocblas_create_handle: ") + rocblas_status_to_string(st);
-        return 1;
-    }
-    S.blas = hb;
     S.on = 1;
     return 0;
 }
 
-void spectral_release(Spectral &S) {
-    if (S.blas) (void)rocblas_destroy_handle((rocblas_handle)S.blas);
-    S.blas = nullptr;
-    S.on = 0;
+void spectral_release(Spectral &S) { S.on = 0; }
+
+// ---------------------------------------------------------------------------
+// axis transforms: C(m, n) = sum_k A(m, k) B(k, n) per batch entry, FP64
+// FMAs on 64 x 64 output tiles of a 256-thread workgroup (4 x 4 outputs per
+// thread, k in chunks of 16 staged in LDS).  Operands are addressed by
+// element strides, so one kernel covers every axis and both directions.
+// ---------------------------------------------------------------------------
+struct AxOp {
+    const double *p;            // base of batch entry 0
+    const double *const *tab;   // per-entry bases, or null (then p + b * bs)
+    long long bs;               // batch stride in elements
+    int s0, s1;                 // element strides of the first / second index
+    __device__ const double *at(int b) const { return tab ? tab[b] : p + (long long)b * bs; }
+};
+struct AxOut {
+    double *p;
+    double *const *tab;
+    long long bs;
+    int s0, s1;
+    __device__ double *at(int b) const { return tab ? tab[b] : p + (long long)b * bs; }
+};
+
+constexpr int kGK = 16, kGThreads = 256;
+
+// TS x TS output tile (TS = 64 or 32): a 16 x 16 thread grid, each thread
+// (TS / 16)^2 outputs
+template <int TS>
+__global__ void __launch_bounds__(kGThreads) k_axis_gemm(int M, int N, int K, AxOp A, AxOp B, AxOut C) {
+    constexpr int R = TS / 16;
+    __shared__ double As[kGK][TS + 1], Bs[kGK][TS + 1];
+    const int bz = (int)blockIdx.z;
+    const double *a = A.at(bz), *bp = B.at(bz);
+    double *c = C.at(bz);
+    const int m0 = (int)blockIdx.y * TS, n0 = (int)blockIdx.x * TS;
+    const int tid = (int)threadIdx.x, tm = tid / 16, tn = tid % 16;
+    double acc[R][R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < K; k0 += kGK) {
+        // stage the A and B chunks; the index that is contiguous in memory
+        // runs fastest across the threads
+        for (int e = tid; e < TS * kGK; e += kGThreads) {
+            int mm, kk;
+            if (A.s1 == 1) {
+                kk = e % kGK;
+                mm = e / kGK;
+            } else {
+                mm = e % TS;
+                kk = e / TS;
+            }
+            const int gm = m0 + mm, gk = k0 + kk;
+            As[kk][mm] = (gm < M && gk < K) ? a[(long long)gm * A.s0 + (long long)gk * A.s1] : 0.0;
+        }
+        for (int e = tid; e < TS * kGK; e += kGThreads) {
+            int nn, kk;
+            if (B.s1 == 1) {
+                nn = e % TS;
+                kk = e / TS;
+            } else {
+                kk = e % kGK;
+                nn = e / kGK;
+            }
+            const int gn = n0 + nn, gk = k0 + kk;
+            Bs[kk][nn] = (gn < N && gk < K) ? bp[(long long)gk * B.s0 + (long long)gn * B.s1] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; ++kk) {
+            double av[R], bv[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) av[i] = As[kk][tm + 16 * i];
+#pragma unroll
+            for (int j = 0; j < R; ++j) bv[j] = Bs[kk][tn + 16 * j];
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int j = 0; j < R; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int gm = m0 + tm + 16 * i, gn = n0 + tn + 16 * j;
+            if (gm < M && gn < N) c[(long long)gm * C.s0 + (long long)gn * C.s1] = acc[i][j];
+        }
+}
+
+// 64 x 64 tiles when they give every CU a workgroup, else 32 x 32
+static void axis_gemm(int M, int N, int K, const AxOp &A, const AxOp &B, const AxOut &C, int batch, hipStream_t st) {
+    const long long big = (long long)((M + 63) / 64) * ((N + 63) / 64) * batch;
+    if (big >= 256)
+        hipLaunchKernelGGL(k_axis_gemm<64>, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(kGThreads), 0, st, M, N,
+                           K, A, B, C);
+    else
+        hipLaunchKernelGGL(k_axis_gemm<32>, dim3((N + 31) / 32, (M + 31) / 32, batch), dim3(kGThreads), 0, st, M, N,
+                           K, A, B, C);
+}
+
+// Transform along one axis (length na, stride nb; x: nb = 1) of a field
+// stored with x fastest: forward applies Q^T along the axis, inverse Q.
+// Entry (mode k, index j) of Q is Q[j + na k].  Fields: ntab problems given
+// by pointer tables, or (tables null) one field of `above` consecutive
+// blocks of na * nb cells (x axis: `above` = rows of length na).
+static void axis_transform(const double *Q, int na, int nb, int above, bool fwd, const double *in,
+                           const double *const *in_tab, double *out, double *const *out_tab, int ntab,
+                           hipStream_t st) {
+    if (nb == 1) {
+        // out(row, n) = sum_k in(row, k) B(k, n), B = Q (forward) or Q^T
+        const int batch = in_tab ? ntab : 1;
+        const AxOp a{in, in_tab, 0, na, 1};
+        const AxOp b{Q, nullptr, 0, fwd ? 1 : na, fwd ? na : 1};
+        const AxOut c{out, out_tab, 0, na, 1};
+        axis_gemm(above, na, na, a, b, c, batch, st);
+    } else {
+        // per block: out(m, rest) = sum_k A(m, k) in(k, rest), A = Q^T or Q
+        const int batch = in_tab ? ntab : above;
+        const long long bs = in_tab ? 0 : (long long)na * nb;
+        const AxOp a{Q, nullptr, 0, fwd ? na : 1, fwd ? 1 : na};
+        const AxOp b{in, in_tab, bs, nb, 1};
+        const AxOut c{out, out_tab, bs, nb, 1};
+        axis_gemm(na, nb, na, a, b, c, batch, st);
+    }
 }
 
 // t /= 1 - a lam + b lam^2, lam = lam_x(i) + lam_y(j) + lam_z(k)
@@ -116,38 +229,22 @@ __global__ void __launch_bounds__(kBlock) k_spectral_scale(Geo g, const double *
     }
 }
 
-#define BLASCHK(call)                                                    \
-    do {                                                                 \
-        const rocblas_status st_ = (call);                               \
-        if (st_ != rocblas_status_success) {                             \
-            err = std::string("rocBLAS: ") + rocblas_status_to_string(st_); \
-            return hipErrorLaunchFailure;                                \
-        }                                                                \
-    } while (0)
-
 hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, double *x, double *t0, double *t1,
                           hipStream_t st, std::string &err) {
-    rocblas_handle hb = (rocblas_handle)S.blas;
+    (void)err;
     const int nx = S.n[0], ny = S.n[1], nz = S.dim == 3 ? S.n[2] : 1;
-    const rocblas_stride sxy = (rocblas_stride)nx * ny;
-    const double one = 1.0, zero = 0.0;
-    const rocblas_operation N = rocblas_operation_none, T = rocblas_operation_transpose;
-    // the field is column-major nx x (ny nz) (x fastest); each axis
-    // transform multiplies by that axis' basis
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_prof) {
         const double N3 = (double)nx * ny * nz;
         prof_slot(K_CH_SPECTRAL, 8.0 * N3 * 2.0 * (2 * S.dim + 1), &e0, &e1);
         (void)hipEventRecord(e0, st);
     }
-    BLASCHK(rocblas_set_stream(hb, st));
-    // forward: x, then y (slab by slab), then z
-    BLASCHK(rocblas_dgemm(hb, T, N, nx, ny * nz, nx, &one, S.Q[0], nx, r, nx, &zero, t0, nx));
-    BLASCHK(rocblas_dgemm_strided_batched(hb, N, N, nx, ny, ny, &one, t0, nx, sxy, S.Q[1], ny, 0, &zero, t1, nx,
-                                          sxy, nz));
+    // forward: x (rows), y (z slabs), z
+    axis_transform(S.Q[0], nx, 1, ny * nz, true, r, nullptr, t0, nullptr, 0, st);
+    axis_transform(S.Q[1], ny, nx, nz, true, t0, nullptr, t1, nullptr, 0, st);
     double *cur = t1, *oth = t0;
     if (S.dim == 3) {
-        BLASCHK(rocblas_dgemm(hb, N, N, nx * ny, nz, nz, &one, cur, nx * ny, S.Q[2], nz, &zero, oth, nx * ny));
+        axis_transform(S.Q[2], nz, nx * ny, 1, true, cur, nullptr, oth, nullptr, 0, st);
         std::swap(cur, oth);
     }
     Geo g;
@@ -158,17 +255,14 @@ hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, doub
     g.N = (long long)nx * ny * nz;
     hipLaunchKernelGGL(k_spectral_scale, dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, (const double *)S.lam[0],
                        (const double *)S.lam[1], (const double *)(S.dim == 3 ? S.lam[2] : nullptr), a, b, cur);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     // inverse: z, y, x
     if (S.dim == 3) {
-        BLASCHK(rocblas_dgemm(hb, N, T, nx * ny, nz, nz, &one, cur, nx * ny, S.Q[2], nz, &zero, oth, nx * ny));
+        axis_transform(S.Q[2], nz, nx * ny, 1, false, cur, nullptr, oth, nullptr, 0, st);
         std::swap(cur, oth);
     }
-    BLASCHK(rocblas_dgemm_strided_batched(hb, N, T, nx, ny, ny, &one, cur, nx, sxy, S.Q[1], ny, 0, &zero, oth, nx,
-                                          sxy, nz));
+    axis_transform(S.Q[1], ny, nx, nz, false, cur, nullptr, oth, nullptr, 0, st);
     std::swap(cur, oth);
-    BLASCHK(rocblas_dgemm(hb, N, N, nx, ny * nz, nx, &one, S.Q[0], nx, cur, nx, &zero, x, nx));
+    axis_transform(S.Q[0], nx, 1, ny * nz, false, cur, nullptr, x, nullptr, 0, st);
     if (e1) (void)hipEventRecord(e1, st);
     return hipGetLastError();
 }
@@ -190,27 +284,16 @@ __global__ void __launch_bounds__(kBlock) k_spectral_scale_batch(int nx, int ny,
     }
 }
 
-hipError_t spectral_batch_solve(void *blas, const std::vector<SpecGroup> &groups, hipStream_t st, std::string &err) {
-    rocblas_handle hb = (rocblas_handle)blas;
-    const double one = 1.0, zero = 0.0;
-    const rocblas_operation N = rocblas_operation_none, T = rocblas_operation_transpose;
-    BLASCHK(rocblas_set_stream(hb, st));
+hipError_t spectral_batch_solve(const std::vector<SpecGroup> &groups, hipStream_t st) {
     for (const SpecGroup &G : groups) {
         const int nx = G.nx, ny = G.ny, m = G.m;
-        // column-major nx x ny per problem (x fastest): t0 = Qx^T r, t1 = t0 Qy
-        BLASCHK(rocblas_dgemm_batched(hb, T, N, nx, ny, nx, &one, G.Qx, nx, G.r, nx, &zero, G.t0, nx, m));
-        BLASCHK(rocblas_dgemm_batched(hb, N, N, nx, ny, ny, &one, (const double *const *)G.t0, nx, G.Qy, ny, &zero,
-                                      G.t1, nx, m));
+        axis_transform(G.Q[0], nx, 1, ny, true, nullptr, G.r, nullptr, G.t0, m, st);
+        axis_transform(G.Q[1], ny, nx, 1, true, nullptr, (const double *const *)G.t0, nullptr, G.t1, m, st);
         const int bx = std::min((nx * ny + kBlock - 1) / kBlock, 64);
         hipLaunchKernelGGL(k_spectral_scale_batch, dim3(bx, m), dim3(kBlock), 0, st, nx, ny, (const double *)G.lam[0],
                            (const double *)G.lam[1], (const double *)G.abh, (double *const *)G.t1);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        // back: t0 = t1 Qy^T, x = Qx t0
-        BLASCHK(rocblas_dgemm_batched(hb, N, T, nx, ny, ny, &one, (const double *const *)G.t1, nx, G.Qy, ny, &zero,
-                                      G.t0, nx, m));
-        BLASCHK(rocblas_dgemm_batched(hb, N, N, nx, ny, nx, &one, G.Qx, nx, (const double *const *)G.t0, nx, &zero,
-                                      G.x, nx, m));
+        axis_transform(G.Q[1], ny, nx, 1, false, nullptr, (const double *const *)G.t1, nullptr, G.t0, m, st);
+        axis_transform(G.Q[0], nx, 1, ny, false, nullptr, (const double *const *)G.t0, nullptr, G.x, m, st);
     }
     return hipGetLastError();
 }
