@@ -36,7 +36,7 @@
  * axis is diagonalised by an orthonormal DCT-II basis on a walled axis and
  * the real Fourier basis on a periodic one; the solve is one transform per
  * axis, a division by 1 - a lam + b lam^2, and the inverse transforms, as
- * FP64 matrix products through rocBLAS on the grid's stream).  Setting
+ * FP64 matrix products by a tiled kernel on the grid's stream).  Setting
  * CHNS_CH_SOLVER=pcg in the environment before chns_create_grid selects
  * multigrid-preconditioned CG for S2 instead; larger grids and the batched
  * entry points always use it.
@@ -50,12 +50,9 @@
  *                 not stored.
  *
  * Ownership: every device array (state, workspace) belongs to the caller.
- * The library keeps raw pointers and small host metadata and allocates no
- * device memory for fields, hierarchies or scratch; the only device memory
- * it does not get from the caller is what the rocBLAS handle of a
- * single-grid handle holds (see chns_create_grid).  All work runs on the
- * stream given at creation.  Handles are not thread-safe; distinct handles
- * are independent.
+ * The library keeps raw pointers and small host metadata, never allocates
+ * device memory, and runs all work on the stream given at creation.  Handles
+ * are not thread-safe; distinct handles are independent.
  *
  * Errors: functions return CHNS_OK (0), the warning CHNS_ENOCONV (> 0: the
  * call completed but a linear solve stopped at max_iter), or a negative code.
@@ -151,15 +148,14 @@ int chns_workspace_size(const chns_grid_desc *desc, size_t *bytes);
 /* Create a handle.  workspace: device memory of at least
  * chns_workspace_size bytes, 256-byte aligned, owned by the caller and kept
  * alive until chns_destroy_grid.  hip_stream: a hipStream_t (NULL = default
- * stream).  The library allocates no device memory of its own for the
- * grid; the direct S2 solve's rocBLAS handle (created here, synchronously
- * uploading the bases into the workspace) holds the library's own small
- * device allocations until chns_destroy_grid.  The handle also
- * creates dim - 1 non-blocking streams of default priority for the velocity
- * components 1 .. dim-1 (their momentum solves of S7 overlap with the first
- * component's; event waits order them with hip_stream, so every call still
- * completes on hip_stream); chns_destroy_grid releases them.  A handle must
- * not be used by two host threads at once.                               */
+ * stream).  No device memory is allocated here or later; the S2 bases are
+ * built on the host and copied into the workspace here (synchronously).
+ * The handle also creates dim - 1 non-blocking streams of default priority
+ * for the velocity components 1 .. dim-1 (their momentum solves of S7
+ * overlap with the first component's; event waits order them with
+ * hip_stream, so every call still completes on hip_stream);
+ * chns_destroy_grid releases them.  A handle must not be used by two host
+ * threads at once.                                                       */
 int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes,
                      void *hip_stream, struct chns_grid **out);
 
@@ -308,13 +304,11 @@ int chns_batch_workspace_size(int count, const chns_grid_desc *descs, size_t *by
  * runs on an internal non-blocking stream ordered after it and before any
  * later work on it.  Builds the constant CH hierarchies (synchronises).
  * 2D batches solve S2 directly, as single grids do: the problems of one
- * shape share their bases, and each solve is four rocBLAS batched GEMMs per
- * shape plus a scaling launch.  Both forms (persistent, tiled) use it.  The
- * rocBLAS handle is created here and runs one warm-up solve, so a captured
- * step never meets rocBLAS's first-use set-up; it holds the only device
- * memory the library does not get from the caller, until
- * chns_destroy_batch.  CHNS_CH_SOLVER=pcg in the environment, 3D batches
- * and axes over 2048 cells keep multigrid-preconditioned CG for S2.       */
+ * shape share their bases, and each solve is four batched transform
+ * launches per shape plus a scaling launch.  Both forms (persistent,
+ * tiled) use it.  CHNS_CH_SOLVER=pcg in the environment, 3D batches and
+ * axes over 2048 cells keep multigrid-preconditioned CG for S2.  No device
+ * memory is allocated here or later.                                      */
 int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *props, void *workspace,
                       size_t bytes, void *hip_stream, struct chns_batch **out);
 
