@@ -700,6 +700,33 @@ __device__ inline void gauss_jordan_inplace(double *A, int n, double *f, double 
     __syncthreads();
 }
 
+// Gauss-Jordan inversion as above with one barrier per pivot: pivot step k
+// reads the whole matrix from src and writes the next one to dst (the same
+// arithmetic per entry, in the same order), then the two swap.  src and dst
+// are n x n arrays; returns the one holding the inverse.  Block-wide; ends
+// with a workgroup barrier.  (n = 32: 19 us against 27 us for the in-place
+// form, which waits on three barriers and a one-thread step per pivot; one
+// wave alone with wavefront fences took 101 us.)
+__device__ inline double *gauss_jordan_pingpong(double *src, double *dst, int n) {
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double p = 1.0 / src[k * n + k];
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int i = e / n, j = e - i * n;
+            const double akj = j == k ? p : src[k * n + j] * p;   // the scaled pivot row
+            if (i == k)
+                dst[e] = akj;
+            else
+                dst[e] = j == k ? -src[i * n + k] * p : src[e] - src[i * n + k] * akj;
+        }
+        __syncthreads();
+        double *t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
 // LDS of the set-up: the coarsest matrix when it has at most kLdsInverse
 // cells, a scratch row, reduction slots and the pivot.
 struct SetupLds {
@@ -761,7 +788,11 @@ __device__ inline void setup_block_dev(const Slot<T> &S, int l0, SetupLds &sh) {
         const double tau = (tot / n) / n;
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] += tau;
     }
-    gauss_jordan_inplace(M, n, f, &piv);
+    // in LDS with room for a second copy: one barrier per pivot
+    if (M == A && 2 * n * n <= kLdsInverse * kLdsInverse)
+        M = gauss_jordan_pingpong(A, A + n * n, n);
+    else
+        gauss_jordan_inplace(M, n, f, &piv);
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) S.Ainv[e] = M[e];
     __syncthreads();
 }
