@@ -109,54 +109,72 @@ struct AxOut {
     __device__ double *at(int b) const { return tab ? tab[b] : p + (long long)b * bs; }
 };
 
-constexpr int kGK = 16, kGThreads = 256;
+constexpr int kGThreads = 256;
 
 // TS x TS output tile (TS = 64 or 32): a 16 x 16 thread grid, each thread
-// (TS / 16)^2 outputs
+// (TS / 16)^2 outputs.  k runs in chunks of KC = 2048 / TS staged in LDS;
+// the loads of the next chunk are in flight while the current one is used.
 template <int TS>
 __global__ void __launch_bounds__(kGThreads) k_axis_gemm(int M, int N, int K, AxOp A, AxOp B, AxOut C) {
-    constexpr int R = TS / 16;
-    __shared__ double As[kGK][TS + 1], Bs[kGK][TS + 1];
+    constexpr int R = TS / 16, KC = 2048 / TS, PT = TS * KC / kGThreads;   // staged values per thread
+    __shared__ double As[KC][TS + 1], Bs[KC][TS + 1];
     const int bz = (int)blockIdx.z;
     const double *a = A.at(bz), *bp = B.at(bz);
     double *c = C.at(bz);
     const int m0 = (int)blockIdx.y * TS, n0 = (int)blockIdx.x * TS;
     const int tid = (int)threadIdx.x, tm = tid / 16, tn = tid % 16;
+    // staging positions: the index that is contiguous in memory runs
+    // fastest across the threads
+    auto a_pos = [&](int e, int &mm, int &kk) {
+        if (A.s1 == 1) {
+            kk = e % KC;
+            mm = e / KC;
+        } else {
+            mm = e % TS;
+            kk = e / TS;
+        }
+    };
+    auto b_pos = [&](int e, int &nn, int &kk) {
+        if (B.s1 == 1) {
+            nn = e % TS;
+            kk = e / TS;
+        } else {
+            kk = e % KC;
+            nn = e / KC;
+        }
+    };
+    double ra[PT], rb[PT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            int mm, kk, nn, kb;
+            a_pos(tid + kGThreads * r, mm, kk);
+            b_pos(tid + kGThreads * r, nn, kb);
+            const int gm = m0 + mm, gk = k0 + kk, gn = n0 + nn, gkb = k0 + kb;
+            ra[r] = (gm < M && gk < K) ? a[(long long)gm * A.s0 + (long long)gk * A.s1] : 0.0;
+            rb[r] = (gn < N && gkb < K) ? bp[(long long)gkb * B.s0 + (long long)gn * B.s1] : 0.0;
+        }
+    };
     double acc[R][R];
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
         for (int j = 0; j < R; ++j) acc[i][j] = 0.0;
-    for (int k0 = 0; k0 < K; k0 += kGK) {
-        // stage the A and B chunks; the index that is contiguous in memory
-        // runs fastest across the threads
-        for (int e = tid; e < TS * kGK; e += kGThreads) {
-            int mm, kk;
-            if (A.s1 == 1) {
-                kk = e % kGK;
-                mm = e / kGK;
-            } else {
-                mm = e % TS;
-                kk = e / TS;
-            }
-            const int gm = m0 + mm, gk = k0 + kk;
-            As[kk][mm] = (gm < M && gk < K) ? a[(long long)gm * A.s0 + (long long)gk * A.s1] : 0.0;
-        }
-        for (int e = tid; e < TS * kGK; e += kGThreads) {
-            int nn, kk;
-            if (B.s1 == 1) {
-                nn = e % TS;
-                kk = e / TS;
-            } else {
-                kk = e % kGK;
-                nn = e / kGK;
-            }
-            const int gn = n0 + nn, gk = k0 + kk;
-            Bs[kk][nn] = (gn < N && gk < K) ? bp[(long long)gk * B.s0 + (long long)gn * B.s1] : 0.0;
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            int mm, kk, nn, kb;
+            a_pos(tid + kGThreads * r, mm, kk);
+            b_pos(tid + kGThreads * r, nn, kb);
+            As[kk][mm] = ra[r];
+            Bs[kb][nn] = rb[r];
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kGK; ++kk) {
+        if (k0 + KC < K) fetch(k0 + KC);   // in flight during the products below
+        const int kn = K - k0 < KC ? K - k0 : KC;
+#pragma unroll 4
+        for (int kk = 0; kk < kn; ++kk) {
             double av[R], bv[R];
 #pragma unroll
             for (int i = 0; i < R; ++i) av[i] = As[kk][tm + 16 * i];
