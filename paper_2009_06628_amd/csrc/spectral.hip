@@ -111,7 +111,7 @@ struct AxOut {
 
 constexpr int kGThreads = 256;
 
-// TS x TS output tile (TS = 64 or 32): a 16 x 16 thread grid, each thread
+// TS x TS output tile (TS = 64, 32 or 16): a 16 x 16 thread grid, each thread
 // (TS / 16)^2 outputs.  k runs in chunks of KC = 2048 / TS staged in LDS;
 // the loads of the next chunk are in flight while the current one is used.
 template <int TS>
@@ -196,14 +196,18 @@ __global__ void __launch_bounds__(kGThreads) k_axis_gemm(int M, int N, int K, Ax
         }
 }
 
-// 64 x 64 tiles when they give every CU a workgroup, else 32 x 32
+// The widest of 64, 32, 16 output tiles that still gives every CU a
+// workgroup (the smaller tiles trade operand reuse for parallelism)
 static void axis_gemm(int M, int N, int K, const AxOp &A, const AxOp &B, const AxOut &C, int batch, hipStream_t st) {
-    const long long big = (long long)((M + 63) / 64) * ((N + 63) / 64) * batch;
-    if (big >= 256)
+    auto tiles = [&](int t) { return (long long)((M + t - 1) / t) * ((N + t - 1) / t) * batch; };
+    if (tiles(64) >= 256)
         hipLaunchKernelGGL(k_axis_gemm<64>, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(kGThreads), 0, st, M, N,
                            K, A, B, C);
-    else
+    else if (tiles(32) >= 256)
         hipLaunchKernelGGL(k_axis_gemm<32>, dim3((N + 31) / 32, (M + 31) / 32, batch), dim3(kGThreads), 0, st, M, N,
+                           K, A, B, C);
+    else
+        hipLaunchKernelGGL(k_axis_gemm<16>, dim3((N + 15) / 16, (M + 15) / 16, batch), dim3(kGThreads), 0, st, M, N,
                            K, A, B, C);
 }
 
