@@ -971,7 +971,9 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
                                                 (const char *)S.lev[lsb].s)
                                      : 0;
         const size_t range16 = (range + 15) & ~(size_t)15;   // LDS image, whole 16-byte words
-        if (lsb > 0 && range16 <= (size_t)kLdsVcycleBytes) {
+        // (the 2D LDS form gives each thread one red-black pair of a level)
+        const bool pairs_fit = DIM == 3 || S.lev[lsb].g.N <= 2 * kSBThreads;
+        if (lsb > 0 && range16 <= (size_t)kLdsVcycleBytes && pairs_fit) {
             // the range is read once and x of level lsb written back
             static const bool attr = [] {   // once per instantiation, thread-safe
                 (void)hipFuncSetAttribute((const void *)k_vcycle_lds<T, DIM>,
