@@ -189,14 +189,19 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     carve_slot(B, P, g->mom, 0);
     carve_slot(B, P, g->pres, 1);
     const int nc = g->ch.ncoarse;
+    // set-up scratch of a coarsest level too large for LDS; the pressure
+    // hierarchy has its own, as it is set up while momentum component 0 is
     double *aug = nc > kLdsInverse ? B.take<double>((size_t)nc * nc) : nullptr;
-    g->ch.aug = g->mom.aug = g->pres.aug = aug;
+    double *paug = nc > kLdsInverse ? B.take<double>((size_t)nc * nc) : nullptr;
+    g->ch.aug = g->mom.aug = aug;
+    g->pres.aug = paug;
     g->prec = prec;
     if (prec == CHNS_FP32_REFINE) {
         carve_slot(B, P, g->ch32, 0);
         carve_slot(B, P, g->mom32, 0);
         carve_slot(B, P, g->pres32, 1);
-        g->ch32.aug = g->mom32.aug = g->pres32.aug = aug;
+        g->ch32.aug = g->mom32.aug = aug;
+        g->pres32.aug = paug;
         g->f_z = B.take<float>(N);
         g->f_t = B.take<float>(N);
         g->f_r = B.take<float>(N);
@@ -263,6 +268,17 @@ struct SolveCtx {
     hipStream_t s;
 };
 
+// Rebuild the hierarchy of a solve from the level-0 coefficients just
+// written by the set-up kernels (momentum, pressure), on c.s.
+static void hierarchy_setup(chns_grid *g, const SolveCtx &c) {
+    if (g->prec == CHNS_FP64) {
+        mg_setup(*c.S64, g->dim, c.s);
+    } else {
+        convert_level0(*c.S64, *c.S32, g->dim, c.s);
+        mg_setup(*c.S32, g->dim, c.s);
+    }
+}
+
 // One linear solve in the handle's precision form.  setup: rebuild the
 // hierarchy from the level-0 coefficients just written by the set-up
 // kernels (momentum, pressure); the CH hierarchy is constant (set up by
@@ -284,18 +300,14 @@ hipError_t run_solve_ctx(chns_grid *g, const SolveCtx &c, int setup, OpKind kind
     Slot<double> &S64 = *c.S64;
     PcgVecs<double> v = c.v;
     Red red = c.red;
+    if (setup) hierarchy_setup(g, c);
     if (g->prec == CHNS_FP64) {
-        if (setup) mg_setup(S64, g->dim, c.s);
         hipError_t e = pcg_solve(S64, g->dim, kind, ch, b, x, rtol, g->props.max_iter, next_predict(g->last_iters[pidx]),
                                  red, v, c.s, o);
         g->last_iters[pidx] = o->iters;
         return e;
     }
     Slot<float> &S32 = *c.S32;
-    if (setup) {
-        convert_level0(S64, S32, g->dim, c.s);
-        mg_setup(S32, g->dim, c.s);
-    }
     const PcgVecs2<double, float> v2{v.r, v.p0, v.p1, v.q, v.t, c.f_z, c.f_t, c.f_r};
     return refine_solve(S64, S32, g->dim, kind, ch, b, x, rtol, g->props.max_iter, &g->last_inner[pidx], red, v2,
                         c.s, o);
@@ -378,8 +390,22 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     // off, component a > 0 runs on its own stream (forked from and joined
     // back to the handle's stream by events) and its own host thread, so
     // the launch latencies of the components overlap; the arithmetic of
-    // each solve is unchanged.
+    // each solve is unchanged.  The pressure coefficients and hierarchy
+    // (S8) need only phi_new: they are set up on a further stream and
+    // thread meanwhile.
     const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum();
+    Level<double> &P0 = g->pres.lev[0];
+    double *pcs[3] = {P0.cs[0], P0.cs[1], P0.cs[2]};
+    hipError_t ep = hipSuccess;
+    auto pressure_setup = [&]() {
+        SolveCtx c = main_ctx(g, 2);
+        c.s = g->pstream;
+        ep = hipStreamWaitEvent(c.s, g->ev_fork, 0);
+        if (ep != hipSuccess) return;
+        launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, c.s, kPCoef);
+        hierarchy_setup(g, c);
+        ep = hipEventRecord(g->ev_pset, c.s);
+    };
     SolveOut om[3];
     hipError_t em[3] = {hipSuccess, hipSuccess, hipSuccess};
     auto momentum = [&](int a) {
@@ -397,12 +423,14 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     };
     if (concurrent) {
         HIPCHK(hipEventRecord(g->ev_fork, s));
-        std::thread workers[2];
+        std::thread workers[3];
         for (int a = 1; a < dim; ++a) workers[a - 1] = std::thread(momentum, a);
+        workers[dim - 1] = std::thread(pressure_setup);
         momentum(0);
-        for (int a = 1; a < dim; ++a) workers[a - 1].join();
+        for (int a = 1; a <= dim; ++a) workers[a - 1].join();
         for (int a = 1; a < dim; ++a)
             if (em[a] == hipSuccess) em[a] = hipStreamWaitEvent(s, g->mc[a - 1].done_ev, 0);
+        if (ep == hipSuccess) ep = hipStreamWaitEvent(s, g->ev_pset, 0);
     } else {
         for (int a = 0; a < dim; ++a) {
             if (a > 0) {   // sequential: component a uses its buffers on the handle's stream
@@ -424,12 +452,11 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         last.res_mom[a] = om[a].rel_res;
         last.unconverged |= om[a].unconverged ? (2 << a) : 0;
     }
-    // S8
-    Level<double> &L0 = g->pres.lev[0];
-    double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-    launch_p_setup(dim, geo, k, g->phi_new, usc, L0.s, cs, g->rhs, s);
+    if (ep != hipSuccess) return fail(CHNS_EDEVICE, std::string("pressure set-up: ") + hipGetErrorString(ep));
+    // S8 (coefficients and hierarchy already set up when concurrent)
+    launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs);
     remove_mean(geo, g->rhs, g->red, s);
-    HIPCHK(run_solve(g, 2, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
+    HIPCHK(run_solve_ctx(g, main_ctx(g, 2), !concurrent, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
     if (int rc = check_solve(o, "pressure")) return rc;
     last.iters_p = o.iters;
     last.res_p = o.rel_res;
@@ -482,6 +509,15 @@ static void release_streams(chns_grid *g) {
             g->mc[a].done_ev = nullptr;
         }
     }
+    if (g->pstream) {
+        (void)hipStreamSynchronize(g->pstream);
+        (void)hipStreamDestroy(g->pstream);
+        g->pstream = nullptr;
+    }
+    if (g->ev_pset) {
+        (void)hipEventDestroy(g->ev_pset);
+        g->ev_pset = nullptr;
+    }
     if (g->ev_fork) {
         (void)hipEventDestroy(g->ev_fork);
         g->ev_fork = nullptr;
@@ -514,9 +550,12 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     layout(B, P, g, desc->precision);
     for (int k = 0; k < 12; ++k) g->last_iters[k] = g->last_inner[k] = 4;
     g->adj_ready = 0;
-    // streams (default priority) and events of the momentum components
+    // streams (default priority) and events of the momentum components and
+    // of the pressure set-up
     g->mc_ready = 0;
     g->ev_fork = nullptr;
+    g->pstream = nullptr;
+    g->ev_pset = nullptr;
     for (int a = 0; a < 2; ++a) {
         g->mc[a].stream = nullptr;
         g->mc[a].done_ev = nullptr;
@@ -527,6 +566,8 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
             e = hipStreamCreateWithFlags(&g->mc[a - 1].stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&g->mc[a - 1].done_ev, hipEventDisableTiming);
         }
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->pstream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_pset, hipEventDisableTiming);
         if (e != hipSuccess) {
             release_streams(g);
             delete g;

@@ -309,7 +309,7 @@ __device__ void batch_problem_step(const BatchProb<TP> &P, const BatchState &st,
         record(o, 1 + a, &S->iters_mom[a], &S->res_mom[a], flags, total);
     }
     // S8
-    BLOCK_LOOP(N) p_setup_cell<DIM>(g, k, P.phi_new, usc, P.op.s, opcs, P.rhs, c);
+    BLOCK_LOOP(N) p_setup_cell<DIM>(g, k, P.phi_new, usc, P.op.s, opcs, P.rhs, kPCoef | kPRhs, c);
     __syncthreads();
     remove_mean_block(N, P.rhs, red);
     prepare_slot<TP, DIM>(P, P.pres, sh);

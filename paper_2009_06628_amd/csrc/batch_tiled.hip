@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kTileBlock) k_t_phase(const BatchProb<TP> *__r
         case 3:
             TILE_LOOP(t) mom_setup_cell<DIM>(g, k, a, phi, P.phi_new, mu, uc, P.op.s, opcs, P.rhs, P.ustar[a], 0, c);
             break;
-        case 4: TILE_LOOP(t) p_setup_cell<DIM>(g, k, P.phi_new, usc, P.op.s, opcs, P.rhs, c); break;
+        case 4: TILE_LOOP(t) p_setup_cell<DIM>(g, k, P.phi_new, usc, P.op.s, opcs, P.rhs, kPCoef | kPRhs, c); break;
         default: TILE_LOOP(t) project_cell<DIM>(g, k, P.phi_new, usc, pr, phi, uw, c); break;
     }
 }

@@ -328,7 +328,9 @@ struct chns_grid {
     chns::MomCtx mc[2];                      // momentum components 1, 2 (component 0 uses the buffers above)
     chns::Spectral spec;                     // direct CH solve (single grids)
     hipEvent_t ev_fork;                      // main stream -> component streams
-    int mc_ready;                            // streams and events of mc created
+    hipStream_t pstream;                     // pressure set-up during the momentum solves
+    hipEvent_t ev_pset;                      // recorded on pstream after that set-up
+    int mc_ready;                            // streams and events of mc and the pressure set-up created
     int adj_ready;                           // adjoint workspace attached
     chns::AdjBufs adj;
     chns_step_stats last;

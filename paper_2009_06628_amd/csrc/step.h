@@ -26,10 +26,13 @@ void launch_phi_update(int dim, const Geo &g, const StepConst &k, const double *
 void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const double *phi, const double *phi_new,
                       const double *mu, const double *const u[3], double *s, double *const cs[3], double *rhs,
                       double *ustar, hipStream_t st, int coef_only = 0);
-// S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new) and
-// rhs = -(We/dt) D ustar.
+// S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new)
+// (part & kPCoef) and rhs = -(We/dt) D ustar (part & kPRhs).  The
+// coefficients need only phi_new, so the step sets them and the pressure
+// hierarchy up while the momentum solves run.
+constexpr int kPCoef = 1, kPRhs = 2;
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
-                    double *s, double *const cs[3], double *rhs, hipStream_t st);
+                    double *s, double *const cs[3], double *rhs, hipStream_t st, int part = kPCoef | kPRhs);
 // Pressure coefficients from a given cell density (stand-alone solve).
 void launch_p_coef_from_rho(int dim, const Geo &g, double ih2, const double *rho, double *s, double *const cs[3],
                             hipStream_t st);

@@ -58,8 +58,8 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_p_setup(Geo g, StepConst k, const double *__restrict__ phin, U3 us,
-                                                    double *__restrict__ s, W3 cs, double *__restrict__ rhs) {
-    CELL_LOOP(g.N) p_setup_cell<DIM>(g, k, phin, us, s, cs, rhs, c);
+                                                    double *__restrict__ s, W3 cs, double *__restrict__ rhs, int part) {
+    CELL_LOOP(g.N) p_setup_cell<DIM>(g, k, phin, us, s, cs, rhs, part, c);
 }
 
 template <int DIM>
@@ -186,8 +186,9 @@ void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const do
              ustar, coef_only);
 }
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
-                    double *s, double *const cs[3], double *rhs, hipStream_t st) {
-    DISPATCH(K_P_SETUP, 3 + 2 * dim, dim, k_p_setup, g.N, st, g, k, phi_new, mk_u3(ustar), s, mk_w3(cs), rhs);
+                    double *s, double *const cs[3], double *rhs, hipStream_t st, int part) {
+    const int words = (part & kPCoef ? 2 + dim : 0) + (part & kPRhs ? 1 + dim : 0);
+    DISPATCH(K_P_SETUP, words, dim, k_p_setup, g.N, st, g, k, phi_new, mk_u3(ustar), s, mk_w3(cs), rhs, part);
 }
 void launch_p_coef_from_rho(int dim, const Geo &g, double ih2, const double *rho, double *s, double *const cs[3],
                             hipStream_t st) {

@@ -213,11 +213,11 @@ __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, c
     }
 }
 
-// S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new),
-// rhs = -(We/dt) D ustar
+// S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new)
+// (part & kPCoef), rhs = -(We/dt) D ustar (part & kPRhs).
 template <int DIM>
 __device__ inline void p_setup_cell(const Geo &g, const StepConst &k, const double *__restrict__ phin, const U3 &us,
-                                    double *__restrict__ s, const W3 &cs, double *__restrict__ rhs, int c) {
+                                    double *__restrict__ s, const W3 &cs, double *__restrict__ rhs, int part, int c) {
     int i, j, kk;
     if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
     const int ia[3] = {i, j, kk};
@@ -227,18 +227,20 @@ __device__ inline void p_setup_cell(const Geo &g, const StepConst &k, const doub
     for (int b = 0; b < DIM; ++b) {
         const int lo = nb_lo(g, c, ia[b], b);
         const int hi = nb_hi(g, c, ia[b], b);
-        if (lo >= 0) {
-            const double rl = k.alpha * pullback(phin[lo]) + k.beta;
-            cs.a[b][c] = 1.0 / (0.5 * (rc + rl)) * k.ih2;
-        } else {
-            cs.a[b][c] = 0.0;
+        if (part & kPCoef) {
+            if (lo >= 0) {
+                const double rl = k.alpha * pullback(phin[lo]) + k.beta;
+                cs.a[b][c] = 1.0 / (0.5 * (rc + rl)) * k.ih2;
+            } else {
+                cs.a[b][c] = 0.0;
+            }
         }
         const double flo = lo >= 0 ? us.a[b][c] : 0.0;
         const double fhi = hi >= 0 ? us.a[b][hi] : 0.0;
         div += fhi - flo;
     }
-    s[c] = 0.0;
-    rhs[c] = -(k.We / k.dt) * (div * k.ih);
+    if (part & kPCoef) s[c] = 0.0;
+    if (part & kPRhs) rhs[c] = -(k.We / k.dt) * (div * k.ih);
 }
 
 // S9: u = ustar - (dt/We) G p / rho_f; phi = phi_new
