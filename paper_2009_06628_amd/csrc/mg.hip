@@ -351,10 +351,7 @@ __global__ void __launch_bounds__(kSBThreads) k_vcycle_lds(Slot<T> S, int l0, Ld
     copy_to_lds(lds_words, (const uint4 *)base, cp);
     if (dn) return;
     __syncthreads();
-    if constexpr (DIM == 2)
-        vcycle_lds2_dev<T>(S, l0, lds, base);
-    else
-        vcycle_lds_dev<T, DIM>(S, l0, lds, base);
+    vcycle_lds_dev<T, DIM>(S, l0, lds, base);
     const T *xl = lds_image(lds, base, S.lev[l0].x);
     T *xg = S.lev[l0].x;
     LDS_LOOP(S.lev[l0].g.N) xg[c] = xl[c];
@@ -971,8 +968,8 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
                                                 (const char *)S.lev[lsb].s)
                                      : 0;
         const size_t range16 = (range + 15) & ~(size_t)15;   // LDS image, whole 16-byte words
-        // (the 2D LDS form gives each thread one red-black pair of a level)
-        const bool pairs_fit = DIM == 3 || S.lev[lsb].g.N <= 2 * kSBThreads;
+        // (the LDS form gives each thread one red-black pair of a level)
+        const bool pairs_fit = S.lev[lsb].g.N <= 2 * kSBThreads;
         if (lsb > 0 && range16 <= (size_t)kLdsVcycleBytes && pairs_fit) {
             // the range is read once and x of level lsb written back
             static const bool attr = [] {   // once per instantiation, thread-safe

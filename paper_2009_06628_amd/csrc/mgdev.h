@@ -441,34 +441,6 @@ __device__ inline Level<T> lds_level(const Level<T> &G, char *lds, const char *b
     return L;
 }
 
-// k-th cell of colour col ((i + j + k) & 1) of a level whose x extent is
-// even (every level above the coarsest); its coordinates go to ia.
-template <int DIM>
-__device__ inline int color_cell(const Geo &g, int k, int col, int ia[3]) {
-    const int hx = (int)g.n[0] >> 1;
-    const int row = k / hx;   // y + ny z
-    const int m = k - row * hx;
-    int y = row, z = 0;
-    if (DIM == 3) {
-        z = row / (int)g.n[1];
-        y = row - z * (int)g.n[1];
-    }
-    ia[0] = 2 * m + ((y + z + col) & 1);
-    ia[1] = y;
-    ia[2] = z;
-    return ia[0] + (int)g.n[0] * row;
-}
-
-#define LDS_COLOR_LOOP(N) for (int k = (int)threadIdx.x; k < (int)(N) / 2; k += kSBThreads)
-
-// Gauss-Seidel update of cell c from its neighbours' current x
-template <typename T, int DIM>
-__device__ inline void gs_at(const Level<T> &L, int c, const int ia[3]) {
-    using R = T;
-    auto xv = [&](int e) { return (R)L.x[e]; };
-    L.x[c] = (T)(((R)L.b[c] + offsum_at<T, DIM>(L, c, ia, xv)) * (R)L.invd[c]);
-}
-
 // x = Ainv b on the coarsest level (FP64 inverse, all operands in LDS): G
 // lanes per row (G a power of two, at most a wave, G n <= kSBThreads where
 // n allows), lane q summing columns q, q + G, ... in order, then a butterfly
@@ -489,44 +461,127 @@ __device__ inline void coarse_solve_lds(int n, const double *Ainv, const T *b, T
 }
 
 // V-cycle over levels [l0, nlev), l0 >= 1, on the LDS image of their
-// storage.  The arithmetic is that of vcycle_block_dev, with each pass
-// enumerating the cells of one colour (no wave runs both colours' branches):
-//   pre-smoothing  the k-th red (x = b / d) and the k-th black cell (GS from
-//                  its red neighbours' b / d) in one pass
-//                  (then kSmallSweeps - 1 more red | black sweeps)
+// storage, with the arithmetic of vcycle_block_dev per cell:
+//   pre-smoothing  red x = b / d and black GS from its red neighbours' b / d
+//                  in one pass, then kSmallSweeps - 1 more red | black sweeps
 //   post-smoothing red x += P e, then kSmallSweeps x (black GS | red GS)
-//                  (no prolonged value is recomputed, unlike the fused pass
-//                  of the grid kernels)
-// Ends with a workgroup barrier.
+//                  (black x is overwritten by its GS update, so only red
+//                  cells take the prolonged correction)
+// Thread k takes the k-th red and the k-th black cell of a level (x extent
+// even), a pair in one row: row = y + ny z = k / (nx / 2), red at
+// x = 2 (k mod nx / 2) + ((y + z) & 1), black at x ^ 1.  The host runs this
+// kernel only when every level has at most 2 kSBThreads cells, so each
+// thread owns at most one pair per level and keeps it in registers for all
+// passes of a side of the cycle: its neighbour indices, b, 1 / diag and the
+// coefficients of its faces.  A pass then issues only the reads of the
+// neighbours' x and one write per cell, where recomputing the indices (an
+// integer division) and re-reading the coefficients took most of the issue
+// slots of a pass (bubble 256 x 512: 2.09 -> 1.90 ms per step, with
+// bit-identical results).
+// Faces on walls hold 0 on these levels (coarsen_cell), so every axis is
+// indexed as periodic: the wrapped neighbour of a cell on a wall enters with
+// weight 0, where the masked stencils add 0 for the missing neighbour.
+template <typename T, int DIM>
+struct LdsPair {
+    int c[2];              // red, black
+    int nb[2][2 * DIM];    // wrapped neighbours: x low, x high, y low, y high (, z low, z high)
+    int ia[3];             // coordinates of the red cell
+    T b[2], invd[2];
+    T cw[2][2 * DIM];      // coefficients of the faces towards nb, in the same order
+};
+
+template <typename T, int DIM>
+__device__ inline void load_lds_pair(const Level<T> &lv, int k, LdsPair<T, DIM> &P) {
+    const int nx = (int)lv.g.n[0], ny = (int)lv.g.n[1], nz = DIM == 3 ? (int)lv.g.n[2] : 1;
+    const int nxy = nx * ny;
+    const int row = k / (nx >> 1);   // y + ny z
+    const int z = DIM == 3 ? row / ny : 0;
+    const int y = row - z * ny;
+    const int xr = 2 * (k - row * (nx >> 1)) + ((y + z) & 1);
+    P.ia[0] = xr;
+    P.ia[1] = y;
+    P.ia[2] = z;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int x = q ? xr ^ 1 : xr;
+        const int c = x + nx * row;
+        int *nb = P.nb[q];
+        P.c[q] = c;
+        nb[0] = x > 0 ? c - 1 : c + nx - 1;
+        nb[1] = x < nx - 1 ? c + 1 : c + 1 - nx;
+        nb[2] = y > 0 ? c - nx : c + nx * (ny - 1);
+        nb[3] = y < ny - 1 ? c + nx : c - nx * (ny - 1);
+        if (DIM == 3) {
+            nb[2 * DIM - 2] = z > 0 ? c - nxy : c + nxy * (nz - 1);
+            nb[2 * DIM - 1] = z < nz - 1 ? c + nxy : c - nxy * (nz - 1);
+        }
+        P.b[q] = lv.b[c];
+        P.invd[q] = lv.invd[c];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            P.cw[q][2 * a] = lv.cs[a][c];
+            P.cw[q][2 * a + 1] = lv.cs[a][nb[2 * a + 1]];
+        }
+    }
+}
+
+// sum over the faces of cell Q of the pair of cs * v(neighbour)
+template <int Q, typename T, int DIM, typename V>
+__device__ inline T pair_offsum(const LdsPair<T, DIM> &P, V v) {
+    T acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 2 * DIM; ++i) acc += P.cw[Q][i] * v(P.nb[Q][i]);
+    return acc;
+}
+
+// Gauss-Seidel update of cell Q of the pair from its neighbours' current x
+template <int Q, typename T, int DIM>
+__device__ inline void pair_gs(const LdsPair<T, DIM> &P, T *x) {
+    x[P.c[Q]] = (P.b[Q] + pair_offsum<Q>(P, [&](int e) { return x[e]; })) * P.invd[Q];
+}
+
+// residual b - A x at cell Q of the pair
+template <int Q, typename T, int DIM>
+__device__ inline T pair_residual(const LdsPair<T, DIM> &P, const T *s, const T *x) {
+    const T xc = x[P.c[Q]];
+    T acc = s[P.c[Q]] * xc;
+#pragma unroll
+    for (int i = 0; i < 2 * DIM; ++i) acc += P.cw[Q][i] * (xc - x[P.nb[Q][i]]);
+    return P.b[Q] - acc;
+}
+
 template <typename T, int DIM>
 __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
-    using R = T;
     const int L = S.nlev;
+    const int tid = (int)threadIdx.x;
+    LdsPair<T, DIM> own;   // pair tid of the current level, if the level has one
+    auto load_own = [&](const Level<T> &lv) {
+        if (tid < (int)lv.g.N / 2) load_lds_pair(lv, tid, own);
+    };
+    auto each_pair = [&](const Level<T> &lv, auto body) {
+        if (tid < (int)lv.g.N / 2) body(own);
+    };
+    using P_t = LdsPair<T, DIM>;
     for (int l = l0; l < L - 1; ++l) {
         const Level<T> lv = lds_level<T, DIM>(S.lev[l], lds, base);
         const Level<T> lc = lds_level<T, DIM>(S.lev[l + 1], lds, base);
-        // zero-guess smoothing: the k-th red and the k-th black cell in one
-        // pass; the black update evaluates its red neighbours' b / d itself
-        LDS_COLOR_LOOP(lv.g.N) {
-            int ia[3];
-            const int c = color_cell<DIM>(lv.g, k, 0, ia);
-            lv.x[c] = (T)((R)lv.b[c] * (R)lv.invd[c]);
-            int ib[3];
-            const int cb = color_cell<DIM>(lv.g, k, 1, ib);
-            auto red = [&](int e) { return (R)lv.b[e] * (R)lv.invd[e]; };
-            lv.x[cb] = (T)(((R)lv.b[cb] + offsum_at<T, DIM>(lv, cb, ib, red)) * (R)lv.invd[cb]);
-        }
+        load_own(lv);
+        // zero-guess smoothing: red x = b / d, black GS from those values
+        each_pair(lv, [&](const P_t &P) {
+            lv.x[P.c[0]] = P.b[0] * P.invd[0];
+            lv.x[P.c[1]] = (P.b[1] + pair_offsum<1>(P, [&](int e) { return lv.b[e] * lv.invd[e]; })) * P.invd[1];
+        });
         __syncthreads();
-        for (int sw = 1; sw < kSmallSweeps; ++sw)
-            for (int col = 0; col < 2; ++col) {
-                LDS_COLOR_LOOP(lv.g.N) {
-                    int ia[3];
-                    const int c = color_cell<DIM>(lv.g, k, col, ia);
-                    gs_at<T, DIM>(lv, c, ia);
-                }
-                __syncthreads();
-            }
-        LDS_LOOP(lv.g.N) residual_cell<T, T, DIM>(lv, lv.b, lv.x, c);
+        for (int sw = 1; sw < kSmallSweeps; ++sw) {
+            each_pair(lv, [&](const P_t &P) { pair_gs<0>(P, lv.x); });
+            __syncthreads();
+            each_pair(lv, [&](const P_t &P) { pair_gs<1>(P, lv.x); });
+            __syncthreads();
+        }
+        each_pair(lv, [&](const P_t &P) {
+            lv.r[P.c[0]] = pair_residual<0>(P, lv.s, lv.x);
+            lv.r[P.c[1]] = pair_residual<1>(P, lv.s, lv.x);
+        });
         __syncthreads();
         LDS_LOOP(lc.g.N) restrict_cell<T, DIM>(lv.g, lc.g, lv.r, lc.b, c);
         __syncthreads();
@@ -539,167 +594,15 @@ __device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const
     for (int l = L - 2; l >= l0; --l) {
         const Level<T> lv = lds_level<T, DIM>(S.lev[l], lds, base);
         const Level<T> lc = lds_level<T, DIM>(S.lev[l + 1], lds, base);
-        LDS_COLOR_LOOP(lv.g.N) {
-            int ia[3];
-            const int c = color_cell<DIM>(lv.g, k, 0, ia);
-            lv.x[c] = (T)((R)lv.x[c] + prolong_at<T, DIM>(lv.g, lc.g, lc.x, ia));
-        }
-        __syncthreads();
-        for (int sw = 0; sw < kSmallSweeps; ++sw)
-            for (int col = 1; col >= 0; --col) {
-                LDS_COLOR_LOOP(lv.g.N) {
-                    int ia[3];
-                    const int c = color_cell<DIM>(lv.g, k, col, ia);
-                    gs_at<T, DIM>(lv, c, ia);
-                }
-                __syncthreads();
-            }
-    }
-}
-
-// 2D form of vcycle_lds_dev with the same arithmetic per cell and pass.
-// Faces on walls hold 0 on these levels (coarsen_cell), so every axis is
-// indexed as periodic: the wrapped neighbour of a cell on a wall enters with
-// weight 0, where the masked stencils add 0 for the missing neighbour.  Each
-// thread takes the k-th red and the k-th black cell of a level (x extent
-// even): row y = k / (nx / 2), red at x = 2 (k mod nx / 2) + (y & 1), black
-// at x ^ 1.
-struct Wrap2 {
-    int c, xl, xh, yl, yh;
-};
-__device__ inline Wrap2 wrap2(int x, int y, int nx, int ny, int nwrap) {
-    Wrap2 w;
-    w.c = x + nx * y;
-    w.xl = x > 0 ? w.c - 1 : w.c + nx - 1;
-    w.xh = x < nx - 1 ? w.c + 1 : w.c + 1 - nx;
-    w.yl = y > 0 ? w.c - nx : w.c + nwrap;
-    w.yh = y < ny - 1 ? w.c + nx : w.c - nwrap;
-    return w;
-}
-
-// The k-th red / black pair of a 2D level, with what the passes of the level
-// read about its own two cells: their wrapped neighbours, b, 1 / diag and the
-// coefficients of their four faces (x low, x high, y low, y high, the order
-// of the sums below).  The 2D LDS V-cycle runs only on levels of at most
-// 2 kSBThreads cells (the host checks), so thread k owns pair k for all
-// passes of a side of the cycle and holds it in registers: a pass issues
-// only the reads of its neighbours' x and one write per cell, where
-// recomputing the indices (an integer division) and re-reading the
-// coefficients took most of the issue slots of a pass (bubble 256 x 512:
-// 2.09 -> 1.90 ms per step, bit-identical results).
-template <typename T>
-struct LdsPair {
-    Wrap2 w[2];      // red, black
-    int xr, y;       // coordinates of the red cell
-    T b[2], invd[2];
-    T cw[2][4];
-};
-
-template <typename T>
-__device__ inline void load_lds_pair(const Level<T> &lv, int k, LdsPair<T> &P) {
-    const int nx = (int)lv.g.n[0], ny = (int)lv.g.n[1], hx = nx >> 1;
-    const int y = k / hx, xr = 2 * (k - y * hx) + (y & 1);
-    const int nwrap = nx * (ny - 1);
-    P.w[0] = wrap2(xr, y, nx, ny, nwrap);
-    P.w[1] = wrap2(xr ^ 1, y, nx, ny, nwrap);
-    P.xr = xr;
-    P.y = y;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const Wrap2 &w = P.w[q];
-        P.b[q] = lv.b[w.c];
-        P.invd[q] = lv.invd[w.c];
-        P.cw[q][0] = lv.cs[0][w.c];
-        P.cw[q][1] = lv.cs[0][w.xh];
-        P.cw[q][2] = lv.cs[1][w.c];
-        P.cw[q][3] = lv.cs[1][w.yh];
-    }
-}
-
-// sum over the four faces of cell Q of the pair of cs * v(neighbour)
-template <int Q, typename T, typename V>
-__device__ inline T pair_offsum(const LdsPair<T> &P, V v) {
-    const Wrap2 &w = P.w[Q];
-    T acc = 0.0;
-    acc += P.cw[Q][0] * v(w.xl);
-    acc += P.cw[Q][1] * v(w.xh);
-    acc += P.cw[Q][2] * v(w.yl);
-    acc += P.cw[Q][3] * v(w.yh);
-    return acc;
-}
-
-// Gauss-Seidel update of cell Q of the pair from its neighbours' current x
-template <int Q, typename T>
-__device__ inline void pair_gs(const LdsPair<T> &P, T *x) {
-    x[P.w[Q].c] = (P.b[Q] + pair_offsum<Q>(P, [&](int e) { return x[e]; })) * P.invd[Q];
-}
-
-// residual b - A x at cell Q of the pair
-template <int Q, typename T>
-__device__ inline T pair_residual(const LdsPair<T> &P, const T *s, const T *x) {
-    const Wrap2 &w = P.w[Q];
-    const T xc = x[w.c];
-    T acc = s[w.c] * xc;
-    acc += P.cw[Q][0] * (xc - x[w.xl]);
-    acc += P.cw[Q][1] * (xc - x[w.xh]);
-    acc += P.cw[Q][2] * (xc - x[w.yl]);
-    acc += P.cw[Q][3] * (xc - x[w.yh]);
-    return P.b[Q] - acc;
-}
-
-template <typename T>
-__device__ inline void vcycle_lds2_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
-    const int L = S.nlev;
-    const int tid = (int)threadIdx.x;
-    LdsPair<T> own;   // pair tid of the current level, if the level has one
-    auto load_own = [&](const Level<T> &lv) {
-        if (tid < (int)lv.g.N / 2) load_lds_pair(lv, tid, own);
-    };
-    auto each_pair = [&](const Level<T> &lv, auto body) {
-        if (tid < (int)lv.g.N / 2) body(own);
-    };
-    for (int l = l0; l < L - 1; ++l) {
-        const Level<T> lv = lds_level<T, 2>(S.lev[l], lds, base);
-        const Level<T> lc = lds_level<T, 2>(S.lev[l + 1], lds, base);
         load_own(lv);
-        // zero-guess smoothing: red x = b / d, black GS from those values
-        each_pair(lv, [&](const LdsPair<T> &P) {
-            lv.x[P.w[0].c] = P.b[0] * P.invd[0];
-            lv.x[P.w[1].c] = (P.b[1] + pair_offsum<1>(P, [&](int e) { return lv.b[e] * lv.invd[e]; })) * P.invd[1];
-        });
-        __syncthreads();
-        for (int sw = 1; sw < kSmallSweeps; ++sw) {
-            each_pair(lv, [&](const LdsPair<T> &P) { pair_gs<0>(P, lv.x); });
-            __syncthreads();
-            each_pair(lv, [&](const LdsPair<T> &P) { pair_gs<1>(P, lv.x); });
-            __syncthreads();
-        }
-        each_pair(lv, [&](const LdsPair<T> &P) {
-            lv.r[P.w[0].c] = pair_residual<0>(P, lv.s, lv.x);
-            lv.r[P.w[1].c] = pair_residual<1>(P, lv.s, lv.x);
-        });
-        __syncthreads();
-        LDS_LOOP(lc.g.N) restrict_cell<T, 2>(lv.g, lc.g, lv.r, lc.b, c);
-        __syncthreads();
-    }
-    {
-        const Level<T> lc = lds_level<T, 2>(S.lev[L - 1], lds, base);
-        coarse_solve_lds<T>((int)lc.g.N, lds_image(lds, base, S.Ainv), lc.b, lc.x);
-        __syncthreads();
-    }
-    for (int l = L - 2; l >= l0; --l) {
-        const Level<T> lv = lds_level<T, 2>(S.lev[l], lds, base);
-        const Level<T> lc = lds_level<T, 2>(S.lev[l + 1], lds, base);
-        load_own(lv);
-        each_pair(lv, [&](const LdsPair<T> &P) {
-            const int ia[3] = {P.xr, P.y, 0};
-            lv.x[P.w[0].c] = lv.x[P.w[0].c] + prolong_at<T, 2>(lv.g, lc.g, lc.x, ia);
+        each_pair(lv, [&](const P_t &P) {
+            lv.x[P.c[0]] = lv.x[P.c[0]] + prolong_at<T, DIM>(lv.g, lc.g, lc.x, P.ia);
         });
         __syncthreads();
         for (int sw = 0; sw < kSmallSweeps; ++sw) {
-            each_pair(lv, [&](const LdsPair<T> &P) { pair_gs<1>(P, lv.x); });
+            each_pair(lv, [&](const P_t &P) { pair_gs<1>(P, lv.x); });
             __syncthreads();
-            each_pair(lv, [&](const LdsPair<T> &P) { pair_gs<0>(P, lv.x); });
+            each_pair(lv, [&](const P_t &P) { pair_gs<0>(P, lv.x); });
             __syncthreads();
         }
     }
