@@ -30,6 +30,8 @@ struct BatchProb {
     // tiled mode
     Scal *sc;                              // solver scalars of the problem
     int lsb;                               // first level handled by one workgroup
+    int vlds;                              // LDS bytes of that V-cycle out of LDS (0: from global memory)
+    LdsCopy vcp;                           // its copy plan (the same for every slot of the problem)
     int t0, t1;                            // the problem's tiles in the level-0 tile list
 };
 
@@ -89,6 +91,8 @@ struct chns_batch {
     int last_iters[3];                // eager mode: most iterations any problem needed, last step
     int last_refine[3];               // eager mode: most iterations in refinement rounds, last step
     int max_iter_max;                 // largest max_iter of the problems (graph budgets never exceed it)
+    int vlds_max;                     // largest LDS of the problems' single-workgroup V-cycles
+    int vlds_some_global;             // some problem runs those levels from global memory
     // direct CH solve (2D, every axis <= kSpectralMaxN): one group per
     // problem shape, and its members
     std::vector<chns::SpecGroup> spec;

@@ -493,6 +493,19 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
         Q.sc = scal ? scal + i : nullptr;
         {
             Q.lsb = batch_lsb(P);   // first level of the single-workgroup part
+            // the V-cycle of those levels out of LDS where it fits; one
+            // plan serves every slot (same carving from a 256-byte boundary)
+            Q.vlds = (int)lds_vcycle_bytes(Q.mom, Q.lsb);
+            memset(&Q.vcp, 0, sizeof Q.vcp);
+            if (Q.vlds) {
+                Q.vcp = lds_copy_plan(Q.mom, Q.lsb);
+                const LdsCopy c2 = lds_copy_plan(Q.chs, Q.lsb);
+                if ((int)lds_vcycle_bytes(Q.chs, Q.lsb) != Q.vlds || memcmp(&c2, &Q.vcp, sizeof c2) != 0) Q.vlds = 0;
+            }
+            if (b) {
+                b->vlds_max = std::max(b->vlds_max, Q.vlds);
+                if (Q.vlds == 0) b->vlds_some_global = 1;
+            }
         }
         if (host) {   // step constants and CH operator are filled in by the caller
             const chns_props &p = props[i];
@@ -795,6 +808,8 @@ int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *
     b->lsb.resize(count);
     b->nlev_max = 0;
     b->lg = 0;
+    b->vlds_max = 0;
+    b->vlds_some_global = 0;
     for (int l = 0; l < kMaxLev; ++l) {
         b->ncells[l].assign(count, 0);
         b->lev_n[l].assign(count, std::array<long long, 3>{0, 0, 0});

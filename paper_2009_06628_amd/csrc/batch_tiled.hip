@@ -241,18 +241,52 @@ __global__ void __launch_bounds__(kTileBlock) k_t_restrict(const BatchProb<TP> *
     TILE_LOOP(t) restrict_cell<TP, DIM>(S.lev[l].g, S.lev[l + 1].g, S.lev[l].r, S.lev[l + 1].b, c);
 }
 
-// levels lsb .. coarsest of every active problem, one workgroup per problem
+// levels lsb .. coarsest of every active problem whose plan allows it, one
+// workgroup per problem, out of LDS: the single-grid kernel's copy, V-cycle
+// and write-back of x.  The launch provides the largest LDS any problem
+// takes.
+template <typename TP, int DIM>
+__global__ void __launch_bounds__(kSBThreads) k_t_vcycle_small_lds(const BatchProb<TP> *__restrict__ probs, int s) {
+    extern __shared__ uint4 lds_words[];
+    const BatchProb<TP> &P = probs[blockIdx.x];
+    if (P.vlds == 0 || P.sc->done) return;
+    const Slot<TP> &S = tslot(P, s);
+    const int l0 = P.lsb;
+    char *lds = (char *)lds_words;
+    const char *base = (const char *)S.lev[l0].s;
+    const LdsCopy cp = P.vcp;   // a private copy: the LDS stores cannot alias it
+    copy_to_lds(lds_words, (const uint4 *)base, cp);
+    __syncthreads();
+    vcycle_lds_dev<TP, DIM>(S, l0, lds, base);
+    const TP *xl = lds_image(lds, base, S.lev[l0].x);
+    TP *xg = S.lev[l0].x;
+    LDS_LOOP(S.lev[l0].g.N) xg[c] = xl[c];
+}
+
+// the same levels of the other active problems, from global memory
 template <typename TP, typename TB, int DIM>
 __global__ void __launch_bounds__(kSBThreads) k_t_vcycle_small(const BatchProb<TP> *__restrict__ probs, int s,
                                                                int bsel, int xsel) {
     const BatchProb<TP> &P = probs[blockIdx.x];
-    if (P.sc->done) return;
+    if (P.vlds > 0 || P.sc->done) return;
     const Slot<TP> &S = tslot(P, s);
     const int l0 = P.lsb;
     if (l0 == 0)
         vcycle_block_dev<TP, TB, DIM>(S, 0, level_b<TP, TB>(P, S, 0, bsel), level_x(P, S, 0, xsel));
     else
         vcycle_block_dev<TP, TP, DIM>(S, l0, (const TP *)S.lev[l0].b, S.lev[l0].x);
+}
+
+// Allow k_t_vcycle_small_lds the LDS of one workgroup (once per instantiation;
+// called when the tile lists are built, outside any graph capture).
+template <typename TP, int DIM>
+static void vcycle_small_attrs() {
+    static const bool once = [] {   // thread-safe one-time initialisation
+        (void)hipFuncSetAttribute((const void *)k_t_vcycle_small_lds<TP, DIM>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, kLdsVcycleBytes);
+        return true;
+    }();
+    (void)once;
 }
 
 // ---------------------------------------------------------------------------
@@ -650,6 +684,17 @@ struct Tiled {
                                    nt(l), l, op);
         hipLaunchKernelGGL((k_t_setup_small<TP, DIM>), dim3(np()), dim3(kSBThreads), 0, s, probs(), singular);
     }
+    // the single-workgroup levels of every problem: out of LDS where the
+    // problem's plan allows, else from global memory
+    template <typename TB>
+    void vcycle_small(int sv, int bsel, int xsel) {
+        if (b->vlds_max > 0)
+            hipLaunchKernelGGL((k_t_vcycle_small_lds<TP, DIM>), dim3(np()), dim3(kSBThreads), (size_t)b->vlds_max, s,
+                               probs(), sv);
+        if (b->vlds_some_global)
+            hipLaunchKernelGGL((k_t_vcycle_small<TP, TB, DIM>), dim3(np()), dim3(kSBThreads), 0, s, probs(), sv,
+                               bsel, xsel);
+    }
     template <typename TB>
     void vcycle(int sv, int bsel, int xsel) {
         if (DIM == 2) {
@@ -662,8 +707,7 @@ struct Tiled {
                     hipLaunchKernelGGL((k_t_down2<TP, TP>), dim3(b->nt2[l]), dim3(kTileThreadsBatch), 0, s, probs(),
                                        b->d_t2[l], b->nt2[l], sv, l, 0);
             }
-            hipLaunchKernelGGL((k_t_vcycle_small<TP, TB, DIM>), dim3(np()), dim3(kSBThreads), 0, s, probs(), sv,
-                               bsel, xsel);
+            vcycle_small<TB>(sv, bsel, xsel);
             for (int l = b->lg - 1; l >= 0; --l) {
                 if (l == 0)
                     hipLaunchKernelGGL((k_t_up2<TP, TB>), dim3(b->nt2[0]), dim3(kTileThreadsBatch), 0, s, probs(),
@@ -685,8 +729,7 @@ struct Tiled {
             hipLaunchKernelGGL((k_t_restrict<TP, DIM>), dim3(nt(l + 1)), dim3(kTileBlock), 0, s, probs(), tl(l + 1),
                                nt(l + 1), sv, l);
         }
-        hipLaunchKernelGGL((k_t_vcycle_small<TP, TB, DIM>), dim3(np()), dim3(kSBThreads), 0, s, probs(), sv, bsel,
-                           xsel);
+        vcycle_small<TB>(sv, bsel, xsel);
         for (int l = b->lg - 1; l >= 0; --l) {
             const int ops[3] = {4, 5, 6};
             for (int o = 0; o < 3; ++o) {
@@ -829,6 +872,11 @@ namespace chns {
 
 int tiled_build(chns_batch *b, int tile_cells) {
     if (tile_cells < kTileBlock || tile_cells % kTileBlock) return set_error(CHNS_EINVAL, "bad tile size");
+    if (b->prec == CHNS_FP64) {
+        if (b->dim == 2) vcycle_small_attrs<double, 2>(); else vcycle_small_attrs<double, 3>();
+    } else {
+        if (b->dim == 2) vcycle_small_attrs<float, 2>(); else vcycle_small_attrs<float, 3>();
+    }
     for (int l = 0; l < kMaxLev; ++l) {
         std::vector<BTile> v;
         if (l < b->nlev_max) {

@@ -19,6 +19,20 @@ constexpr int kMaxBlocks = 4096;    // grid-stride cap (fixes reduction order)
 constexpr int kWave = 64;
 constexpr int kLdsInverse = 64;     // coarsest sizes inverted in LDS
 constexpr int kSBThreads = 1024;    // single-workgroup coarse-level kernels
+constexpr int kLdsVcycleBytes = 160 * 1024;   // LDS of one workgroup on gfx950
+
+// The parts of a V-cycle's storage range that it reads before writing them
+// (s, cs, invd of every level, b of the first, the coarsest inverse), as at
+// most kLdsCopySegs segments of 16-byte words, each copied to the same
+// offset in LDS: segment i covers words [cend[i-1] + shift[i],
+// cend[i] + shift[i]) of the range (cend[-1] = 0); unused segments have
+// cend = total.
+constexpr int kLdsCopySegs = 4;
+struct LdsCopy {
+    int total;                    // words to copy (>= 1)
+    int cend[kLdsCopySegs];       // running end of the copied words
+    int shift[kLdsCopySegs];      // range word = copied word + shift
+};
 
 // ---------------------------------------------------------------------------
 // geometry

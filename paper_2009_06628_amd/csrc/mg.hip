@@ -895,61 +895,6 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
     }
 }
 
-// Copy plan of the LDS V-cycle of levels [lsb, nlev): the byte intervals
-// read before they are written (s, cs, invd of each level, b of level lsb,
-// the coarsest inverse), merged across the smallest gaps down to
-// kLdsCopySegs segments, in whole 16-byte words of the range (arrays start
-// on 256-byte boundaries; a rounded-up end stays inside the workspace).
-template <typename T>
-static LdsCopy lds_copy_plan(const Slot<T> &S, int lsb) {
-    const char *base = (const char *)S.lev[lsb].s;
-    long long a[2 * kMaxLev + 2], e[2 * kMaxLev + 2];
-    int n = 0;
-    auto add = [&](const void *p, size_t bytes) {
-        a[n] = (const char *)p - base;
-        e[n] = a[n] + (long long)bytes;
-        ++n;
-    };
-    for (int l = lsb; l < S.nlev; ++l) {
-        const Level<T> &L = S.lev[l];
-        add(L.s, (size_t)((const char *)(L.invd + L.g.N) - (const char *)L.s));   // s, cs[], invd
-        if (l == lsb) add(L.b, sizeof(T) * (size_t)L.g.N);
-    }
-    add(S.Ainv, sizeof(double) * (size_t)S.ncoarse * S.ncoarse);
-    // sort by start (a handful of entries)
-    for (int i = 1; i < n; ++i)
-        for (int j = i; j > 0 && a[j] < a[j - 1]; --j) {
-            std::swap(a[j], a[j - 1]);
-            std::swap(e[j], e[j - 1]);
-        }
-    while (n > kLdsCopySegs) {
-        int best = 0;
-        for (int i = 1; i + 1 < n; ++i)
-            if (a[i + 1] - e[i] < a[best + 1] - e[best]) best = i;
-        e[best] = std::max(e[best], e[best + 1]);
-        for (int i = best + 1; i + 1 < n; ++i) {
-            a[i] = a[i + 1];
-            e[i] = e[i + 1];
-        }
-        --n;
-    }
-    LdsCopy cp;
-    int done = 0;
-    for (int i = 0; i < kLdsCopySegs; ++i) {
-        if (i < n) {
-            const int w0 = (int)(a[i] / 16), w1 = (int)((e[i] + 15) / 16);
-            cp.shift[i] = w0 - done;
-            done += w1 - w0;
-            cp.cend[i] = done;
-        } else {
-            cp.shift[i] = cp.shift[n - 1];
-            cp.cend[i] = done;
-        }
-    }
-    cp.total = done;
-    return cp;
-}
-
 // One V-cycle of slot S: x0 ~ A^{-1} b0 (b0 may be stored in another
 // precision than the hierarchy).
 template <typename T, typename TB, int DIM, typename TR = T>
@@ -964,13 +909,8 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
     {
         // storage of the small levels: one contiguous range from lev[lsb].s
         // to the end of the coarsest inverse
-        const size_t range = lsb > 0 ? (size_t)((const char *)(S.Ainv + (size_t)S.ncoarse * S.ncoarse) -
-                                                (const char *)S.lev[lsb].s)
-                                     : 0;
-        const size_t range16 = (range + 15) & ~(size_t)15;   // LDS image, whole 16-byte words
-        // (the LDS form gives each thread one red-black pair of a level)
-        const bool pairs_fit = S.lev[lsb].g.N <= 2 * kSBThreads;
-        if (lsb > 0 && range16 <= (size_t)kLdsVcycleBytes && pairs_fit) {
+        const size_t range16 = lds_vcycle_bytes(S, lsb);
+        if (range16) {
             // the range is read once and x of level lsb written back
             static const bool attr = [] {   // once per instantiation, thread-safe
                 (void)hipFuncSetAttribute((const void *)k_vcycle_lds<T, DIM>,

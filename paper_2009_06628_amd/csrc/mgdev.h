@@ -4,6 +4,8 @@
 // per launch), the single-workgroup coarse-level kernels and the batched
 // workgroup-per-problem step.
 #pragma once
+#include <algorithm>
+
 #include "common.h"
 
 namespace chns {
@@ -380,31 +382,25 @@ __device__ inline void vcycle_block_dev(const Slot<T> &S, int l0, const TB *__re
 // independent 16-byte loads, runs every sweep out of LDS with the same
 // per-cell code, and writes back x of level l0.
 constexpr int kLdsCopyUnroll = 10;                  // 16-byte loads in flight per thread
-constexpr int kLdsVcycleBytes = 160 * 1024;         // LDS of one workgroup on gfx950
 
 // The LDS kernel always runs kSBThreads threads; a compile-time stride keeps
 // the loops from reading the workgroup size from the dispatch arguments.
 #define LDS_LOOP(N) for (int c = (int)threadIdx.x; c < (int)(N); c += kSBThreads)
 
-// The parts of the range that a V-cycle reads before writing them (s, cs,
-// invd of every level, b of the first, the coarsest inverse), as at most
-// kLdsCopySegs segments of 16-byte words, each copied to the same offset in
-// LDS: segment i covers words [cend[i-1] + shift[i], cend[i] + shift[i])
-// of the range (cend[-1] = 0); unused segments have cend = total.
-constexpr int kLdsCopySegs = 4;
-struct LdsCopy {
-    int total;                    // words to copy (>= 1)
-    int cend[kLdsCopySegs];       // running end of the copied words
-    int shift[kLdsCopySegs];      // range word = copied word + shift
-};
 
 // Copy the segments: every load of a round is issued before its stores.
 // Indices past the end are clamped to the last word, which is then stored
 // again with its own value, so no load or store is conditional.
-__device__ inline void copy_to_lds(uint4 *dst, const uint4 *src, const LdsCopy &cp) {
+__device__ inline void copy_to_lds(uint4 *dst_words, const uint4 *src_words, const LdsCopy &cp) {
+    // src is device memory: global loads (a pointer read from a table would
+    // otherwise be generic, and the loaded words went through scratch)
+    using Word = unsigned int __attribute__((ext_vector_type(4)));
+    using GWord = const __attribute__((address_space(1))) Word;
+    GWord *src = (GWord *)src_words;
+    Word *dst = (Word *)dst_words;
     const int n = cp.total;
     for (int base = 0; base < n; base += kLdsCopyUnroll * kSBThreads) {
-        uint4 v[kLdsCopyUnroll];
+        Word v[kLdsCopyUnroll];
         int w[kLdsCopyUnroll];
 #pragma unroll
         for (int k = 0; k < kLdsCopyUnroll; ++k) {
@@ -419,6 +415,75 @@ __device__ inline void copy_to_lds(uint4 *dst, const uint4 *src, const LdsCopy &
 #pragma unroll
         for (int k = 0; k < kLdsCopyUnroll; ++k) dst[w[k]] = v[k];
     }
+}
+
+// Copy plan of the LDS V-cycle of levels [lsb, nlev): the byte intervals
+// read before they are written (s, cs, invd of each level, b of level lsb,
+// the coarsest inverse), merged across the smallest gaps down to
+// kLdsCopySegs segments, in whole 16-byte words of the range (arrays start
+// on 256-byte boundaries; a rounded-up end stays inside the workspace).
+template <typename T>
+inline LdsCopy lds_copy_plan(const Slot<T> &S, int lsb) {
+    const char *base = (const char *)S.lev[lsb].s;
+    long long a[2 * kMaxLev + 2], e[2 * kMaxLev + 2];
+    int n = 0;
+    auto add = [&](const void *p, size_t bytes) {
+        a[n] = (const char *)p - base;
+        e[n] = a[n] + (long long)bytes;
+        ++n;
+    };
+    for (int l = lsb; l < S.nlev; ++l) {
+        const Level<T> &L = S.lev[l];
+        add(L.s, (size_t)((const char *)(L.invd + L.g.N) - (const char *)L.s));   // s, cs[], invd
+        if (l == lsb) add(L.b, sizeof(T) * (size_t)L.g.N);
+    }
+    add(S.Ainv, sizeof(double) * (size_t)S.ncoarse * S.ncoarse);
+    // sort by start (a handful of entries)
+    for (int i = 1; i < n; ++i)
+        for (int j = i; j > 0 && a[j] < a[j - 1]; --j) {
+            std::swap(a[j], a[j - 1]);
+            std::swap(e[j], e[j - 1]);
+        }
+    while (n > kLdsCopySegs) {
+        int best = 0;
+        for (int i = 1; i + 1 < n; ++i)
+            if (a[i + 1] - e[i] < a[best + 1] - e[best]) best = i;
+        e[best] = std::max(e[best], e[best + 1]);
+        for (int i = best + 1; i + 1 < n; ++i) {
+            a[i] = a[i + 1];
+            e[i] = e[i + 1];
+        }
+        --n;
+    }
+    LdsCopy cp;
+    int done = 0;
+    for (int i = 0; i < kLdsCopySegs; ++i) {
+        if (i < n) {
+            const int w0 = (int)(a[i] / 16), w1 = (int)((e[i] + 15) / 16);
+            cp.shift[i] = w0 - done;
+            done += w1 - w0;
+            cp.cend[i] = done;
+        } else {
+            cp.shift[i] = cp.shift[n - 1];
+            cp.cend[i] = done;
+        }
+    }
+    cp.total = done;
+    return cp;
+}
+
+// LDS bytes of the V-cycle of levels [lsb, nlev) of S in one workgroup (its
+// storage from lev[lsb].s to the end of the coarsest inverse, in whole
+// 16-byte words), or 0 where that kernel does not apply: lsb == 0, more
+// than kLdsVcycleBytes, or a level with more than one red-black pair per
+// thread.
+template <typename T>
+inline size_t lds_vcycle_bytes(const Slot<T> &S, int lsb) {
+    if (lsb <= 0 || S.lev[lsb].g.N > 2 * kSBThreads) return 0;
+    const size_t range =
+        (size_t)((const char *)(S.Ainv + (size_t)S.ncoarse * S.ncoarse) - (const char *)S.lev[lsb].s);
+    const size_t range16 = (range + 15) & ~(size_t)15;
+    return range16 <= (size_t)kLdsVcycleBytes ? range16 : 0;
 }
 
 // The LDS image of a workspace pointer p of the copied range starting at base.
@@ -551,7 +616,7 @@ __device__ inline T pair_residual(const LdsPair<T, DIM> &P, const T *s, const T 
 }
 
 template <typename T, int DIM>
-__device__ inline void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
+__device__ __forceinline__ void vcycle_lds_dev(const Slot<T> &S, int l0, char *lds, const char *base) {
     const int L = S.nlev;
     const int tid = (int)threadIdx.x;
     LdsPair<T, DIM> own;   // pair tid of the current level, if the level has one
