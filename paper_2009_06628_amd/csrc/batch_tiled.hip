@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(kTileBlock) k_t_setup_level(const BatchProb<TP
 // singular: the pressure hierarchy (same arrays as the momentum one).
 template <typename TP, int DIM>
 __global__ void __launch_bounds__(kSBThreads) k_t_setup_small(const BatchProb<TP> *__restrict__ probs, int singular) {
-    __shared__ SetupLds sh;
+    __shared__ SetupLdsPP sh;
     const BatchProb<TP> &P = probs[blockIdx.x];
     setup_block_dev<TP, DIM>(singular ? P.pres : P.mom, P.lsb, sh);
 }

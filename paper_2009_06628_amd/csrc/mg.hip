@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(kSBThreads) k_vcycle_lds(Slot<T> S, int l0, Ld
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kSBThreads) k_setup_block(Slot<T> S, int l0) {
-    __shared__ SetupLds sh;
+    __shared__ SetupLdsPP sh;
     setup_block_dev<T, DIM>(S, l0, sh);
 }
 

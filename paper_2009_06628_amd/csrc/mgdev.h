@@ -721,21 +721,27 @@ __device__ inline double *gauss_jordan_pingpong(double *src, double *dst, int n)
     return src;
 }
 
-// LDS of the set-up: the coarsest matrix when it has at most kLdsInverse
-// cells, a scratch row, reduction slots and the pivot.
-struct SetupLds {
-    double A[kLdsInverse * kLdsInverse];
+// LDS of the set-up: room for CAP doubles of the coarsest matrix (which is
+// in LDS when it has at most kLdsInverse cells; with room for a second copy
+// the inverse takes one barrier per pivot), a scratch row, reduction slots
+// and the pivot.  SetupLds is the size kernels with other LDS use;
+// SetupLdsPP (64 KB more) is for the set-up kernels alone.
+template <int CAP>
+struct SetupLdsT {
+    double A[CAP];
     double f[kMaxCoarse];
     double red[kSBThreads / kWave];
     double piv;
 };
+using SetupLds = SetupLdsT<kLdsInverse * kLdsInverse>;
+using SetupLdsPP = SetupLdsT<2 * kLdsInverse * kLdsInverse>;
 
 // Set-up of the small levels in one workgroup: coarsen from level
 // max(l0,1) - 1 downwards, inverse diagonals, then the coarsest inverse
 // (in LDS when it has at most kLdsInverse cells, else in S.aug).  Ends with
 // a workgroup barrier.
-template <typename T, int DIM>
-__device__ inline void setup_block_dev(const Slot<T> &S, int l0, SetupLds &sh) {
+template <typename T, int DIM, int CAP>
+__device__ inline void setup_block_dev(const Slot<T> &S, int l0, SetupLdsT<CAP> &sh) {
     double *A = sh.A, *f = sh.f, *red = sh.red;
     double &piv = sh.piv;
     const int L = S.nlev;
@@ -783,7 +789,7 @@ __device__ inline void setup_block_dev(const Slot<T> &S, int l0, SetupLds &sh) {
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) M[e] += tau;
     }
     // in LDS with room for a second copy: one barrier per pivot
-    if (M == A && 2 * n * n <= kLdsInverse * kLdsInverse)
+    if (M == A && 2 * n * n <= CAP)
         M = gauss_jordan_pingpong(A, A + n * n, n);
     else
         gauss_jordan_inplace(M, n, f, &piv);
