@@ -111,7 +111,7 @@ struct AxOut {
 
 constexpr int kGThreads = 256;
 
-// TS x TS output tile (TS = 64, 32 or 16): a 16 x 16 thread grid, each thread
+// TS x TS output tile (TS = 64 or 32): a 16 x 16 thread grid, each thread
 // (TS / 16)^2 outputs.  k runs in chunks of KC = 2048 / TS staged in LDS;
 // the loads of the next chunk are in flight while the current one is used.
 template <int TS>
@@ -196,8 +196,101 @@ __global__ void __launch_bounds__(kGThreads) k_axis_gemm(int M, int N, int K, Ax
         }
 }
 
+// 16 x 16 output tile with k split over 16 thread groups: thread t of group
+// g computes the 4 x 4 block of rows t / 4 + 4 i and columns t % 4 + 4 j over
+// the k of each chunk with k mod 16 = g (half an LDS read per FMA, where one
+// output per thread takes two), then the 16 partial blocks are summed in
+// group order.  Staging and chunks (KC = 128) as in k_axis_gemm.
+__global__ void __launch_bounds__(kGThreads) k_axis_gemm16s(int M, int N, int K, AxOp A, AxOp B, AxOut C) {
+    constexpr int TS = 16, KC = 2048 / TS, PT = TS * KC / kGThreads, G = kGThreads / 16;
+    static_assert(2 * KC * (TS + 1) >= G * TS * TS, "partial sums reuse the staging LDS");
+    __shared__ double sm[2 * KC * (TS + 1)];
+    double(*As)[TS + 1] = (double(*)[TS + 1])sm;
+    double(*Bs)[TS + 1] = (double(*)[TS + 1])(sm + KC * (TS + 1));
+    const int bz = (int)blockIdx.z;
+    const double *a = A.at(bz), *bp = B.at(bz);
+    double *c = C.at(bz);
+    const int m0 = (int)blockIdx.y * TS, n0 = (int)blockIdx.x * TS;
+    const int tid = (int)threadIdx.x, g = tid / 16, rm = (tid % 16) / 4, rn = tid % 4;
+    auto a_pos = [&](int e, int &mm, int &kk) {
+        if (A.s1 == 1) {
+            kk = e % KC;
+            mm = e / KC;
+        } else {
+            mm = e % TS;
+            kk = e / TS;
+        }
+    };
+    auto b_pos = [&](int e, int &nn, int &kk) {
+        if (B.s1 == 1) {
+            nn = e % TS;
+            kk = e / TS;
+        } else {
+            kk = e % KC;
+            nn = e / KC;
+        }
+    };
+    double ra[PT], rb[PT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            int mm, kk, nn, kb;
+            a_pos(tid + kGThreads * r, mm, kk);
+            b_pos(tid + kGThreads * r, nn, kb);
+            const int gm = m0 + mm, gk = k0 + kk, gn = n0 + nn, gkb = k0 + kb;
+            ra[r] = (gm < M && gk < K) ? a[(long long)gm * A.s0 + (long long)gk * A.s1] : 0.0;
+            rb[r] = (gn < N && gkb < K) ? bp[(long long)gkb * B.s0 + (long long)gn * B.s1] : 0.0;
+        }
+    };
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            int mm, kk, nn, kb;
+            a_pos(tid + kGThreads * r, mm, kk);
+            b_pos(tid + kGThreads * r, nn, kb);
+            As[kk][mm] = ra[r];
+            Bs[kb][nn] = rb[r];
+        }
+        __syncthreads();
+        if (k0 + KC < K) fetch(k0 + KC);   // in flight during the products below
+        const int kn = K - k0 < KC ? K - k0 : KC;
+#pragma unroll 2
+        for (int kk = g; kk < kn; kk += G) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[kk][rm + 4 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][rn + 4 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    // partial blocks of the groups (the staging LDS is free after the last
+    // barrier), then one output per thread summed over the groups in order
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sm[g * TS * TS + (rm + 4 * i) * TS + rn + 4 * j] = acc[i][j];
+    __syncthreads();
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) v += sm[q * TS * TS + tid];
+    const int gm = m0 + tid / TS, gn = n0 + tid % TS;
+    if (gm < M && gn < N) c[(long long)gm * C.s0 + (long long)gn * C.s1] = v;
+}
+
 // The widest of 64, 32, 16 output tiles that still gives every CU a
-// workgroup (the smaller tiles trade operand reuse for parallelism)
+// workgroup (the smaller tiles trade operand reuse for parallelism; the
+// 16-wide ones split k to keep some)
 static void axis_gemm(int M, int N, int K, const AxOp &A, const AxOp &B, const AxOut &C, int batch, hipStream_t st) {
     auto tiles = [&](int t) { return (long long)((M + t - 1) / t) * ((N + t - 1) / t) * batch; };
     if (tiles(64) >= 256)
@@ -207,8 +300,8 @@ static void axis_gemm(int M, int N, int K, const AxOp &A, const AxOp &B, const A
         hipLaunchKernelGGL(k_axis_gemm<32>, dim3((N + 31) / 32, (M + 31) / 32, batch), dim3(kGThreads), 0, st, M, N,
                            K, A, B, C);
     else
-        hipLaunchKernelGGL(k_axis_gemm<16>, dim3((N + 15) / 16, (M + 15) / 16, batch), dim3(kGThreads), 0, st, M, N,
-                           K, A, B, C);
+        hipLaunchKernelGGL(k_axis_gemm16s, dim3((N + 15) / 16, (M + 15) / 16, batch), dim3(kGThreads), 0, st, M, N, K,
+                           A, B, C);
 }
 
 // Transform along one axis (length na, stride nb; x: nb = 1) of a field
