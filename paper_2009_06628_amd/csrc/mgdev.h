@@ -701,17 +701,32 @@ __device__ inline void gauss_jordan_inplace(double *A, int n, double *f, double 
 // with a workgroup barrier.  (n = 32: 19 us against 27 us for the in-place
 // form, which waits on three barriers and a one-thread step per pivot; one
 // wave alone with wavefront fences took 101 us.)
-__device__ inline double *gauss_jordan_pingpong(double *src, double *dst, int n) {
+__device__ inline double *gauss_jordan_pingpong(double *src, double *dst, int n, double *rp) {
+    // Each thread steps its entries' (i, j) by the stride instead of dividing
+    // e by n per pivot, and the thread that writes the next pivot entry also
+    // stores its reciprocal (rp, two slots by pivot parity), so the other
+    // threads read 1 / a_kk instead of each dividing (the same division of
+    // the same value: results unchanged; n = 32: 19 -> 8 us).
+    const int nn = n * n, bd = (int)blockDim.x, tid = (int)threadIdx.x;
+    const int di = bd / n, dj = bd - di * n;
+    const int i0 = tid / n, j0 = tid - i0 * n;
+    if (tid == 0) rp[0] = 1.0 / src[0];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        const double p = 1.0 / src[k * n + k];
-        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-            const int i = e / n, j = e - i * n;
+        const double p = rp[k & 1];
+        const int kn = k + 1;
+        int i = i0, j = j0;
+        for (int e = tid; e < nn; e += bd) {
             const double akj = j == k ? p : src[k * n + j] * p;   // the scaled pivot row
-            if (i == k)
-                dst[e] = akj;
-            else
-                dst[e] = j == k ? -src[i * n + k] * p : src[e] - src[i * n + k] * akj;
+            const double v = i == k ? akj : (j == k ? -src[i * n + k] * p : src[e] - src[i * n + k] * akj);
+            dst[e] = v;
+            if (i == kn && j == kn) rp[kn & 1] = 1.0 / v;
+            i += di;
+            j += dj;
+            if (j >= n) {
+                j -= n;
+                ++i;
+            }
         }
         __syncthreads();
         double *t = src;
@@ -790,7 +805,7 @@ __device__ inline void setup_block_dev(const Slot<T> &S, int l0, SetupLdsT<CAP> 
     }
     // in LDS with room for a second copy: one barrier per pivot
     if (M == A && 2 * n * n <= CAP)
-        M = gauss_jordan_pingpong(A, A + n * n, n);
+        M = gauss_jordan_pingpong(A, A + n * n, n, f);
     else
         gauss_jordan_inplace(M, n, f, &piv);
     for (int e = threadIdx.x; e < n * n; e += blockDim.x) S.Ainv[e] = M[e];
