@@ -492,6 +492,103 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// The same apply on a 3D grid (no pending residual), marching along z:
+// block b owns the kMX x kMY x zc cells of column tile b mod ncol and z chunk
+// b / ncol, one cell per thread and plane.  p = (z - zmean) + beta p_old of
+// the column and a one-cell halo is formed once per plane into a ring of
+// three LDS planes, where the grid-stride form above evaluates it at all
+// seven stencil points of every cell (128^3: 4 TB/s).  q, p_new and the
+// per-cell arithmetic are those of k_pcg_apply_slot (a missing neighbour
+// enters as the cell itself with weight 0); one p.q partial per block.
+constexpr int kMX = 32, kMY = kBlock / kMX, kMW = kMX + 2, kMH = kMY + 2;
+#ifndef CHNS_MARCH_PLANES
+#define CHNS_MARCH_PLANES 8
+#endif
+constexpr int kMarchPlanes = CHNS_MARCH_PLANES;   // z planes per block (more on grids too large for the partials)
+template <typename T, typename TZ>
+__global__ void __launch_bounds__(kBlock) k_pcg_apply3_march(Level<T> L, const TZ *__restrict__ z,
+                                                             const T *__restrict__ pold, T *__restrict__ pnew,
+                                                             T *__restrict__ q, Scal *sc, double *__restrict__ part,
+                                                             const double *__restrict__ rz0,
+                                                             const double *__restrict__ rz1,
+                                                             const double *__restrict__ rz2, int nrz, int k,
+                                                             int singular, int ncolx, int ncol, int zc) {
+    if (sc->done) return;
+    __shared__ double pl[3][kMH * kMW];
+    __shared__ double lds[kBlock / kWave];
+    IterStart it;
+    if (!iter_start(sc, rz0, rz1, rz2, nrz, L.g.N, k, singular, it)) return;
+    const double beta = it.beta, zm = it.zm;
+    const Geo &g = L.g;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int col = (int)blockIdx.x % ncol, z0 = ((int)blockIdx.x / ncol) * zc;
+    const int x0 = (col % ncolx) * kMX, y0 = (col / ncolx) * kMY;
+    const int z1 = z0 + zc < nz ? z0 + zc : nz;
+    // coordinate of a halo position on one axis (wrapped on a periodic axis);
+    // false outside a walled one
+    auto wrapc = [](int v, int n, int per, int &w) {
+        if (v >= 0 && v < n) {
+            w = v;
+            return true;
+        }
+        w = v < 0 ? v + n : v - n;
+        return per != 0 && w >= 0 && w < n;
+    };
+    // p of plane zz and its halo into P (0 outside the domain; never used
+    // with a nonzero weight there)
+    auto form = [&](int zz, double *P) {
+        int gz;
+        const bool vz = wrapc(zz, nz, g.per[2], gz);
+        for (int i = (int)threadIdx.x; i < kMH * kMW; i += kBlock) {
+            const int ly = i / kMW, lx = i - ly * kMW;
+            int gx, gy;
+            const bool vx = wrapc(x0 - 1 + lx, nx, g.per[0], gx);
+            const bool vy = wrapc(y0 - 1 + ly, ny, g.per[1], gy);
+            const bool v = vx && vy && vz;
+            double pv = 0.0;
+            if (v) {
+                const int e = gx + nx * (gy + ny * gz);
+                pv = ((double)z[e] - zm) + (beta != 0.0 ? beta * (double)pold[e] : 0.0);
+            }
+            P[i] = pv;
+        }
+    };
+    const int tx = (int)threadIdx.x % kMX, ty = (int)threadIdx.x / kMX;
+    const int gx = x0 + tx, gy = y0 + ty, li = (ty + 1) * kMW + tx + 1;
+    const bool own = gx < nx && gy < ny;
+    form(z0 - 1, pl[(z0 + 2) % 3]);
+    form(z0, pl[z0 % 3]);
+    double acc = 0.0;
+    for (int zz = z0; zz < z1; ++zz) {
+        form(zz + 1, pl[(zz + 1) % 3]);
+        __syncthreads();
+        const double *Pm = pl[(zz + 2) % 3], *P0 = pl[zz % 3], *Pp = pl[(zz + 1) % 3];
+        if (own) {
+            const int c = gx + nx * (gy + ny * zz);
+            const int ia[3] = {gx, gy, zz};
+            const double pc = P0[li];
+            const double nbv[3][2] = {{P0[li - 1], P0[li + 1]}, {P0[li - kMW], P0[li + kMW]}, {Pm[li], Pp[li]}};
+            double qc = (double)L.s[c] * pc;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const int lo = nb_lo(g, c, ia[b], b);
+                const int hi = nb_hi(g, c, ia[b], b);
+                const int h = hi >= 0 ? hi : c;
+                const double vl = lo >= 0 ? nbv[b][0] : pc, vh = hi >= 0 ? nbv[b][1] : pc;
+                const double wl = (double)L.cs[b][c], wh = (double)L.cs[b][h];
+                qc += (lo >= 0 ? wl : 0.0) * (pc - vl);
+                qc += (hi >= 0 ? wh : 0.0) * (pc - vh);
+            }
+            pnew[c] = (T)pc;
+            q[c] = (T)qc;
+            acc += pc * qc;
+        }
+        __syncthreads();   // the next plane overwrites this iteration's lower plane
+    }
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // CH operator, first half: p_new = z + beta p_old, t = L p_new.
 template <typename T, typename TZ, int DIM>
 __global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const TZ *__restrict__ z,
@@ -1045,6 +1142,22 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
         LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
                 (const Scal *)sc, red.rz0, red.rz1, red.rz2, singular);
     }
+    // 3D slot operator: the z-marching apply (8 planes per block, more when
+    // the grid would exceed the partial-sum slots)
+    struct {
+        int nb = 0, ncolx = 0, ncol = 0, zc = 0;
+    } march;
+    if (DIM == 3 && kind == OP_SLOT) {
+        const Geo &g0 = L0.g;
+        march.ncolx = (g0.n[0] + kMX - 1) / kMX;
+        march.ncol = march.ncolx * ((g0.n[1] + kMY - 1) / kMY);
+        if (march.ncol <= kMaxBlocks) {   // else the grid-stride apply
+            march.zc = kMarchPlanes;
+            while (march.zc < g0.n[2] && (long long)march.ncol * ((g0.n[2] + march.zc - 1) / march.zc) > kMaxBlocks)
+                march.zc *= 2;
+            march.nb = march.ncol * ((g0.n[2] + march.zc - 1) / march.zc);
+        }
+    }
     int launched = 0;
     int chunk = predict < 1 ? 1 : predict;
     for (;;) {
@@ -1057,7 +1170,12 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
             // fused: it also stores the previous iteration's residual
             T *rpend = fuse && k > 0 ? v.r : nullptr;
             const double WRP = rpend ? 2.0 * W : 0.0;   // r read and written
-            if (kind == OP_SLOT) {
+            if (kind == OP_SLOT && march.nb) {
+                TLAUNCH(K_PCG_APPLY, W * (4 + DIM) * N + WP * N, (k_pcg_apply3_march<T, TP>), dim3(march.nb),
+                        dim3(kBlock), st, L0, (const TP *)v.z, (const T *)pold, pnew, v.q, sc, red.part0,
+                        (const double *)red.rz0, (const double *)red.rz1, (const double *)red.rz2, nrz, k, singular,
+                        march.ncolx, march.ncol, march.zc);
+            } else if (kind == OP_SLOT) {
                 LAUNCHR(K_PCG_APPLY, W * (4 + DIM) * N + WP * N + WRP * N, (k_pcg_apply_slot<T, TP, DIM>), N, st,
                         L0, (const TP *)v.z, (const T *)pold, pnew, v.q, sc, red.part0, (const double *)red.rz0,
                         (const double *)red.rz1, (const double *)red.rz2, nrz, k, singular, rpend);
@@ -1078,8 +1196,8 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
                 continue;
             }
             LAUNCHR(K_PCG_UPDATE, W * 6 * N + (split ? WP * N : 0.0), (k_pcg_update<T, TP>), N, st, N,
-                    (const T *)pnew, (const T *)v.q, x, v.r, sc, (const double *)red.part0, nb, red.part1,
-                    split ? v.rp : (TP *)nullptr);
+                    (const T *)pnew, (const T *)v.q, x, v.r, sc, (const double *)red.part0,
+                    kind == OP_SLOT && march.nb ? march.nb : nb, red.part1, split ? v.rp : (TP *)nullptr);
             LAUNCH1(K_PCG_UPDATE, 8.0 * nb, (k_pcg_fin_rr), kBlock, st, sc, (const double *)red.part1, nb);
             precond_d<TP, TP, DIM>(SP, kind, rpre, v.z, v.w, done, st);
             LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
