@@ -52,10 +52,12 @@ __device__ inline bool tile_of(const BTile *__restrict__ tiles, int ntiles, BTil
 // ---------------------------------------------------------------------------
 // step phases (FP64), over the level-0 tiles
 // ---------------------------------------------------------------------------
-template <typename TP, int DIM>
+// (one kernel per phase, so that the light phases are not held to the
+// register count of the momentum set-up: 97 VGPRs for all of them in one)
+template <typename TP, int DIM, int PHASE>
 __global__ void __launch_bounds__(kTileBlock) k_t_phase(const BatchProb<TP> *__restrict__ probs,
                                                         const BTile *__restrict__ tiles, int ntiles, BatchState st,
-                                                        int phase, int a) {
+                                                        int a) {
     BTile t;
     if (!tile_of(tiles, ntiles, t)) return;
     const BatchProb<TP> &P = probs[t.prob];
@@ -66,15 +68,18 @@ __global__ void __launch_bounds__(kTileBlock) k_t_phase(const BatchProb<TP> *__r
     const W3 uw{{st.u[0] + P.off, st.u[1] + P.off, DIM == 3 ? st.u[2] + P.off : nullptr}};
     const U3 usc{{P.ustar[0], P.ustar[1], P.ustar[2]}};
     const W3 opcs{{P.op.cs[0], P.op.cs[1], P.op.cs[2]}};
-    switch (phase) {
-        case 0: TILE_LOOP(t) ch_rhs_cell<DIM>(g, k, phi, uc, P.rch, P.phihat, c); break;
-        case 1: TILE_LOOP(t) mu_cell<DIM>(g, k, phi, P.phihat, mu, c); break;
-        case 2: TILE_LOOP(t) phi_update_cell<DIM>(g, k, phi, uc, mu, P.phi_new, c); break;
-        case 3:
-            TILE_LOOP(t) mom_setup_cell<DIM>(g, k, a, phi, P.phi_new, mu, uc, P.op.s, opcs, P.rhs, P.ustar[a], 0, c);
-            break;
-        case 4: TILE_LOOP(t) p_setup_cell<DIM>(g, k, P.phi_new, usc, P.op.s, opcs, P.rhs, kPCoef | kPRhs, c); break;
-        default: TILE_LOOP(t) project_cell<DIM>(g, k, P.phi_new, usc, pr, phi, uw, c); break;
+    if constexpr (PHASE == 0) {
+        TILE_LOOP(t) ch_rhs_cell<DIM>(g, k, phi, uc, P.rch, P.phihat, c);
+    } else if constexpr (PHASE == 1) {
+        TILE_LOOP(t) mu_cell<DIM>(g, k, phi, P.phihat, mu, c);
+    } else if constexpr (PHASE == 2) {
+        TILE_LOOP(t) phi_update_cell<DIM>(g, k, phi, uc, mu, P.phi_new, c);
+    } else if constexpr (PHASE == 3) {
+        TILE_LOOP(t) mom_setup_cell<DIM>(g, k, a, phi, P.phi_new, mu, uc, P.op.s, opcs, P.rhs, P.ustar[a], 0, c);
+    } else if constexpr (PHASE == 4) {
+        TILE_LOOP(t) p_setup_cell<DIM>(g, k, P.phi_new, usc, P.op.s, opcs, P.rhs, kPCoef | kPRhs, c);
+    } else {
+        TILE_LOOP(t) project_cell<DIM>(g, k, P.phi_new, usc, pr, phi, uw, c);
     }
 }
 
@@ -668,8 +673,15 @@ struct Tiled {
     int np() const { return b->count; }
 
     void phase(int ph, int a = 0) {
-        hipLaunchKernelGGL((k_t_phase<TP, DIM>), dim3(nt(0)), dim3(kTileBlock), 0, s, probs(), tl(0), nt(0), st, ph,
-                           a);
+        const dim3 gr(nt(0)), bl(kTileBlock);
+        switch (ph) {
+            case 0: hipLaunchKernelGGL((k_t_phase<TP, DIM, 0>), gr, bl, 0, s, probs(), tl(0), nt(0), st, a); break;
+            case 1: hipLaunchKernelGGL((k_t_phase<TP, DIM, 1>), gr, bl, 0, s, probs(), tl(0), nt(0), st, a); break;
+            case 2: hipLaunchKernelGGL((k_t_phase<TP, DIM, 2>), gr, bl, 0, s, probs(), tl(0), nt(0), st, a); break;
+            case 3: hipLaunchKernelGGL((k_t_phase<TP, DIM, 3>), gr, bl, 0, s, probs(), tl(0), nt(0), st, a); break;
+            case 4: hipLaunchKernelGGL((k_t_phase<TP, DIM, 4>), gr, bl, 0, s, probs(), tl(0), nt(0), st, a); break;
+            default: hipLaunchKernelGGL((k_t_phase<TP, DIM, 5>), gr, bl, 0, s, probs(), tl(0), nt(0), st, a); break;
+        }
     }
     void remove_mean(int which) {
         hipLaunchKernelGGL((k_t_sum<TP>), dim3(nt(0)), dim3(kTileBlock), 0, s, probs(), tl(0), nt(0), st, which,
