@@ -471,11 +471,18 @@ __global__ void __launch_bounds__(kTileBlock) k_t_fin_rz(const BatchProb<TP> *__
 
 // p_new = (z - zmean) + beta p_old; q = A p_new; partial p.q.  CH: first
 // half (p_new, t = L p_new) with half = 0, second half (q) with half = 1.
+// Slot operator in 2D: p of the tile's cells and one row on each side is
+// formed once into an LDS window, where it was evaluated at all five stencil
+// points of every cell (the same expression, so the same values; a
+// neighbour outside the window, across a periodic y boundary, is evaluated
+// directly).
+constexpr int kApplyWin = 2048;   // window cells: tile + 2 rows (else no window)
 template <typename TP, int DIM>
 __global__ void __launch_bounds__(kTileBlock) k_t_apply(const BatchProb<TP> *__restrict__ probs,
                                                         const BTile *__restrict__ tiles, int ntiles, int s, int k,
                                                         int half, double *__restrict__ part) {
     __shared__ double lds[kTileBlock / kWave];
+    __shared__ double pw[DIM == 2 ? kApplyWin : 1];
     BTile t;
     const bool ok = tile_of(tiles, ntiles, t);
     double acc = 0.0;
@@ -512,17 +519,28 @@ __global__ void __launch_bounds__(kTileBlock) k_t_apply(const BatchProb<TP> *__r
                 }
             } else {
                 const Level<double> &L = P.op;
+                // window [w0, w1) of cells; the tile (hence win) is uniform
+                // over the workgroup, so the barrier is reached by all
+                const int w0 = t.c0 - (int)g.n[0], w1 = t.c1 + (int)g.n[0];
+                const bool win = DIM == 2 && w1 - w0 <= kApplyWin;
+                if (win) {
+                    const int N = (int)g.N;
+                    for (int e = w0 + (int)threadIdx.x; e < w1; e += (int)blockDim.x)
+                        if (e >= 0 && e < N) pw[e - w0] = pv(e);
+                    __syncthreads();
+                }
+                auto pg = [&](int e) { return win && e >= w0 && e < w1 ? pw[e - w0] : pv(e); };
                 TILE_LOOP(t) {
                     int ia[3];
                     coords_of<DIM>(g, c, ia);
-                    const double pc = pv(c);
+                    const double pc = pg(c);
                     double qc = L.s[c] * pc;
 #pragma unroll
                     for (int bx = 0; bx < DIM; ++bx) {
                         const int lo = nb_lo(g, c, ia[bx], bx);
                         const int hi = nb_hi(g, c, ia[bx], bx);
                         const int lc = lo >= 0 ? lo : c, hc = hi >= 0 ? hi : c;
-                        const double vl = pv(lc), vh = pv(hc);
+                        const double vl = pg(lc), vh = pg(hc);
                         const double wl = L.cs[bx][c], wh = L.cs[bx][hc];
                         qc += (lo >= 0 ? wl : 0.0) * (pc - vl);
                         qc += (hi >= 0 ? wh : 0.0) * (pc - vh);
