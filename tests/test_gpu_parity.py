@@ -93,7 +93,8 @@ def test_pressure_operator_matches_oracle(n, per):
 
 
 @pytest.mark.parametrize("n,per", [((64, 128), (True, False)), ((96, 96), (True, True)), ((80, 48), (False, False)),
-                                   ((96, 40), (False, True)), ((32, 16, 24), (True, True, False))])
+                                   ((96, 40), (False, True)), ((32, 16, 24), (True, True, False)),
+                                   ((40, 20, 12), (False, False, True))])
 def test_solve_pressure_matches_oracle(n, per):
     P = _lib()
     rng = np.random.default_rng(11)
