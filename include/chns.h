@@ -152,9 +152,11 @@ int chns_workspace_size(const chns_grid_desc *desc, size_t *bytes);
  * built on the host and copied into the workspace here (synchronously).
  * The handle also creates dim - 1 non-blocking streams of default priority
  * for the velocity components 1 .. dim-1 (their momentum solves of S7
- * overlap with the first component's; event waits order them with
- * hip_stream, so every call still completes on hip_stream);
- * chns_destroy_grid releases them.  A handle must not be used by two host
+ * overlap with the first component's) and one more for the set-up of the
+ * S8 coefficients and pressure hierarchy, which needs only phi^{n+1} and
+ * runs during those solves; event waits order all of them with hip_stream,
+ * so every call still completes on hip_stream.  chns_destroy_grid releases
+ * them.  A handle must not be used by two host
  * threads at once.                                                       */
 int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes,
                      void *hip_stream, struct chns_grid **out);
@@ -166,10 +168,11 @@ int chns_set_properties(struct chns_grid *g, const chns_props *props);
 /* Advance the state nsteps time steps (S1..S9 each) in place on the grid's
  * stream.  If stats is not NULL the call synchronises the stream and fills
  * it (solver statistics of the last step, diagnostics of the final state).
- * The momentum solves of the components run on their own streams, driven by
- * host threads of the call (serially on the grid's stream while per-kernel
- * timing is on, or with CHNS_SERIAL_MOMENTUM=1 in the environment); the
- * results do not depend on which.
+ * The momentum solves of the components and the pressure set-up run on
+ * their own streams, driven by host threads of the call (serially on the
+ * grid's stream while per-kernel timing is on, or with
+ * CHNS_SERIAL_MOMENTUM=1 in the environment); the results do not depend on
+ * which.
  * Returns CHNS_ENOCONV if any solve of any step hit max_iter.            */
 int chns_step(struct chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats);
 
