@@ -107,3 +107,17 @@ def test_batch_workspace_size_and_validation():
     props = (P.chns_props * 3)()
     assert lib.chns_create_batch(3, descs, props, ctypes.c_void_p(4096), ctypes.c_size_t(1 << 30), None,
                                  ctypes.byref(h)) == P.CHNS_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 (or a multi-rank launch) exits
+    with a message before touching torch or the device."""
+    import subprocess
+    import sys
+    for extra_env, args in (({}, ["--gpus", "2"]), ({"WORLD_SIZE": "2"}, [])):
+        env = dict(os.environ, **extra_env)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args, capture_output=True, text=True,
+                           env=env, timeout=120)
+        assert r.returncode == 2
+        assert "one GPU only" in r.stderr
+        assert r.stdout == ""
