@@ -25,6 +25,7 @@ struct BatchProb {
     double *phi_new, *phihat, *rch, *ustar[3], *rhs;
     double *r, *p0, *p1, *q, *t;           // CG vectors (FP64)
     TP *z, *w;                             // preconditioned vector, V-cycle scratch
+    TP *rp;                                // r rounded to TP (tiled form, FP32 hierarchy; else null)
     Level<double> op;                      // FP64 level-0 operator of the momentum / pressure solves
     Slot<TP> chs, mom, pres;               // CH hierarchy; momentum and pressure share arrays
     // tiled mode

@@ -472,6 +472,7 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
         Q.t = B.take<double>(N);
         Q.z = B.take<TP>(N);
         Q.w = B.take<TP>(N);
+        Q.rp = sizeof(TP) != sizeof(double) ? B.take<TP>(N) : nullptr;
         carve_slot(B, P, Q.chs, 0);
         carve_slot(B, P, Q.mom, 0);
         Q.pres = Q.mom;

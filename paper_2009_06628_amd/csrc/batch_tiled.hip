@@ -163,12 +163,14 @@ __global__ void __launch_bounds__(kSBThreads) k_t_setup_small(const BatchProb<TP
 
 // ---------------------------------------------------------------------------
 // V-cycle sweeps on the levels above lsb.  Level 0 reads its right-hand side
-// from the CG residual r (bsel 0, FP64) or the scratch w (bsel 1, TP) and
+// from the CG residual r (bsel 0, FP64), the scratch w (bsel 1, TP) or the
+// residual rounded to TP (bsel 2, the value the sweeps would round r to) and
 // writes z (xsel 0) or w (xsel 1); coarser levels use their own b, x.
 // ---------------------------------------------------------------------------
 template <typename TP, typename TB>
 __device__ inline const TB *level_b(const BatchProb<TP> &P, const Slot<TP> &S, int l, int bsel) {
     if (l) return (const TB *)(const void *)S.lev[l].b;
+    if (bsel == 2) return (const TB *)(const void *)P.rp;
     return bsel ? (const TB *)(const void *)P.w : (const TB *)(const void *)P.r;
 }
 template <typename TP>
@@ -313,6 +315,7 @@ __global__ void __launch_bounds__(kTileBlock) k_t_cg_init(const BatchProb<TP> *_
         const double *b = tb_of(P, s);
         const double *x = tx_of(P, s, st);
         double *r = P.r;
+        TP *rp = P.rp;
         if (s == TS_CH) {
             const ChOp ch = P.ch;
             const double *tt = P.t;
@@ -323,6 +326,7 @@ __global__ void __launch_bounds__(kTileBlock) k_t_cg_init(const BatchProb<TP> *_
                 const double Mx = x[c] - ch.a * tt[c] + ch.b * lap_at<DIM>(g, c, ia, ch.ih2, tv);
                 const double bc = b[c], rc = bc - Mx;
                 r[c] = rc;
+                if (rp) rp[c] = (TP)rc;
                 bb += bc * bc;
                 rr += rc * rc;
             }
@@ -332,6 +336,7 @@ __global__ void __launch_bounds__(kTileBlock) k_t_cg_init(const BatchProb<TP> *_
                 coords_of<DIM>(g, c, ia);
                 const double bc = b[c], rc = bc - apply_at<double, DIM>(P.op, x, c, ia);
                 r[c] = rc;
+                if (rp) rp[c] = (TP)rc;
                 bb += bc * bc;
                 rr += rc * rc;
             }
@@ -581,11 +586,13 @@ __global__ void __launch_bounds__(kTileBlock) k_t_update(const BatchProb<TP> *__
         const double *pn = (k & 1) ? P.p1 : P.p0;
         double *x = tx_of(P, s, st);
         double *r = P.r;
+        TP *rp = P.rp;
         const double *q = P.q;
         TILE_LOOP(t) {
             x[c] += alpha * pn[c];
             const double rc = r[c] - alpha * q[c];
             r[c] = rc;
+            if (rp) rp[c] = (TP)rc;
             acc += rc * rc;
         }
     }
@@ -775,12 +782,21 @@ struct Tiled {
         hipLaunchKernelGGL((k_t_sweep<TP, TB, DIM>), dim3(nt(l)), dim3(kTileBlock), 0, s, probs(), tl(l), nt(l), sv, l,
                            bsel, xsel, op);
     }
+    // (with a lower-precision hierarchy the level-0 passes read r rounded to
+    // it, written by the CG update: 4 instead of 8 bytes per cell of it)
     void precond(int sv) {
+        constexpr bool low = sizeof(TP) != sizeof(double);
         if (sv == TS_CH) {
-            vcycle<double>(sv, 0, 1);   // r -> w
-            vcycle<TP>(sv, 1, 0);       // w -> z
+            if (low)
+                vcycle<TP>(sv, 2, 1);       // r -> w
+            else
+                vcycle<double>(sv, 0, 1);
+            vcycle<TP>(sv, 1, 0);           // w -> z
         } else {
-            vcycle<double>(sv, 0, 0);   // r -> z
+            if (low)
+                vcycle<TP>(sv, 2, 0);       // r -> z
+            else
+                vcycle<double>(sv, 0, 0);
         }
     }
     void rz(int sv, int first) {
