@@ -727,6 +727,37 @@ static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F,
     double *phibar_out = (double *)lam_out->phi;
     const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
     SolveOut o;
+    // The reverse of S7..S5 below solves with the step's momentum operators,
+    // which depend only on the forward fields.  With the components on
+    // streams of their own, a host thread sets their coefficients and
+    // hierarchies up there (component 0 on the pressure set-up stream) while
+    // the adjoint pressure solve runs; the solves then skip the set-up.
+    const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum();
+    hipError_t eset = hipSuccess;
+    std::thread setup_thread;
+    struct Joiner {
+        std::thread &t;
+        ~Joiner() {
+            if (t.joinable()) t.join();
+        }
+    } joiner{setup_thread};
+    if (concurrent) {
+        HIPCHK(hipEventRecord(g->ev_fork, s));
+        setup_thread = std::thread([&]() {
+            for (int a = 0; a < dim && eset == hipSuccess; ++a) {
+                SolveCtx c = mom_ctx(g, a);
+                c.s = a == 0 ? g->pstream : g->mc[a - 1].stream;
+                eset = hipStreamWaitEvent(c.s, g->ev_fork, 0);
+                if (eset != hipSuccess) break;
+                Level<double> &L0 = c.S64->lev[0];
+                double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
+                double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+                launch_mom_setup(dim, geo, k, a, phi, F.phi_new, F.mu, uc, L0.s, cs, rhs, g->ustar[a], c.s, 1);
+                hierarchy_setup(g, c);
+            }
+            if (eset == hipSuccess) eset = hipEventRecord(g->ev_pset, g->pstream);   // component 0's
+        });
+    }
     // reverse of S9 and S8: adjoint pressure solve (the pressure slot still
     // holds the operator of the recomputed step)
     adj_p_rhs(dim, geo, k, F.phi_new, ubar, A.pbar, A.zeta, s);
@@ -741,7 +772,11 @@ static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F,
     // on the components' streams when allowed), then the gathers of each
     // component in order (they accumulate into shared adjoint fields)
     {
-        const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum();
+        if (concurrent) {
+            setup_thread.join();
+            if (eset != hipSuccess)
+                return fail(CHNS_EDEVICE, std::string("adjoint momentum set-up: ") + hipGetErrorString(eset));
+        }
         SolveOut om[3];
         hipError_t em[3] = {hipSuccess, hipSuccess, hipSuccess};
         auto nu_solve = [&](int a, hipStream_t sa) {
@@ -751,14 +786,18 @@ static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F,
                 em[a] = hipStreamWaitEvent(sa, g->ev_fork, 0);
                 if (em[a] != hipSuccess) return;
             }
-            Level<double> &L0 = c.S64->lev[0];
-            double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
-            double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-            launch_mom_setup(dim, geo, k, a, phi, F.phi_new, F.mu, uc, L0.s, cs, rhs, g->ustar[a], sa, 1);
-            em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)A.usb[a], A.nu[a], p.rtol_mom, 7 + a, &om[a]);
+            if (!concurrent) {   // else set up during the adjoint pressure solve
+                Level<double> &L0 = c.S64->lev[0];
+                double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
+                double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+                launch_mom_setup(dim, geo, k, a, phi, F.phi_new, F.mu, uc, L0.s, cs, rhs, g->ustar[a], sa, 1);
+            }
+            em[a] = run_solve_ctx(g, c, concurrent ? 0 : 1, OP_SLOT, ch, (const double *)A.usb[a], A.nu[a],
+                                  p.rtol_mom, 7 + a, &om[a]);
             if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, sa);
         };
         if (concurrent) {
+            HIPCHK(hipStreamWaitEvent(s, g->ev_pset, 0));   // component 0's operator
             HIPCHK(hipEventRecord(g->ev_fork, s));
             std::thread workers[2];
             for (int a = 1; a < dim; ++a) workers[a - 1] = std::thread(nu_solve, a, g->mc[a - 1].stream);
