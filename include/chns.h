@@ -375,6 +375,32 @@ typedef struct {
 int chns_set_timing(struct chns_grid *g, int enable);
 int chns_get_timing(struct chns_grid *g, chns_kernel_timing *out, int max, int *count);
 
+/* ---- pressure solve without allocation ---------------------------------
+ * For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * stand-alone S8 solve of chns_solve_pressure (same operator, kernels,
+ * arguments and results), on a grid given by its description instead of a
+ * handle, with no workspace argument.  Its multigrid hierarchy, CG vectors
+ * and reduction scratch live in a device array of the library of
+ * CHNS_NOALLOC_SCRATCH_BYTES bytes, which every GPU the library runs on
+ * holds until the process ends; the call allocates nothing (no hipMalloc,
+ * no library allocation).  Grids whose solver storage exceeds that size are
+ * rejected with CHNS_EINVAL (FP64 needs about 115 bytes per cell plus the
+ * coarsest inverse, the precision form about 156: the 256 x 512 grid fits).
+ * rho, rhs: cell arrays (device, float64; rhs projected to mean zero
+ * internally, not modified); p: initial guess on entry, solution with mean
+ * zero on exit.  desc->precision selects FP64 or the FP32 multigrid under
+ * FP64 refinement; desc->nphases is ignored.  Runs on hip_stream (NULL: the
+ * default stream) and synchronises it before returning.  Every call on a
+ * GPU shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (from several threads or streams) race and must be
+ * serialised by the caller.  Returns as chns_solve_pressure.              */
+#define CHNS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int chns_solve_pressure_noalloc(const chns_grid_desc *desc, const void *rho, const void *rhs, void *p,
+                                double rtol, int max_iter, void *hip_stream, chns_solve_stats *stats);
+/* Size in bytes of that array (CHNS_NOALLOC_SCRATCH_BYTES).              */
+size_t chns_solve_pressure_noalloc_capacity(void);
+
 /* Release the handle (host metadata only; device memory is the caller's). */
 int chns_destroy_grid(struct chns_grid *g);
 

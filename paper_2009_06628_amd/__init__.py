@@ -128,6 +128,10 @@ EXPORTS = {
     "chns_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "chns_get_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_kernel_timing), ctypes.c_int,
                                        ctypes.POINTER(ctypes.c_int)]),
+    "chns_solve_pressure_noalloc": (ctypes.c_int, [ctypes.POINTER(chns_grid_desc), ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                                                   ctypes.POINTER(chns_solve_stats)]),
+    "chns_solve_pressure_noalloc_capacity": (ctypes.c_size_t, []),
     "chns_destroy_grid": (ctypes.c_int, [ctypes.c_void_p]),
     "chns_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "chns_last_error": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -508,6 +512,23 @@ class Batch:
                 "ms_per_step": r.ms_per_step, "budgets": (r.budget_ch, r.budget_mom, r.budget_p),
                 "candidates": [(name[r.cand_mode[i]], r.cand_block[i], r.cand_grid[i], r.cand_ms[i])
                                for i in range(r.ncand)]}
+
+
+def solve_pressure_noalloc(n: Sequence[int], h: float, bc: Sequence[str], rho, rhs, p, rtol: float = 1e-12,
+                           max_iter: int = 200, precision: int = CHNS_FP64, stream=None) -> Dict:
+    """Stand-alone pressure solve that allocates nothing
+    (chns_solve_pressure_noalloc): the solver storage is the library's
+    fixed device array, so calls on one GPU must not overlap."""
+    torch = _torch()
+    lib = load_library()
+    d = make_desc(n, h, bc, precision)
+    s = stream if stream is not None else torch.cuda.current_stream(rho.device)
+    out = chns_solve_stats()
+    rc = lib.chns_solve_pressure_noalloc(ctypes.byref(d), ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(_ptr(rhs)),
+                                         ctypes.c_void_p(_ptr(p)), float(rtol), int(max_iter),
+                                         ctypes.c_void_p(s.cuda_stream), ctypes.byref(out))
+    _check(rc, "chns_solve_pressure_noalloc", allow_noconv=True)
+    return {"iters": out.iters, "rel_res": out.rel_res, "rc": rc}
 
 
 def create_batch(problems, precision=CHNS_FP64, device="cuda", stream=None) -> Batch:
