@@ -446,3 +446,167 @@ def test_galilean_translation():
         assert np.abs(st["phi"]).max() < 1.0
     assert np.abs(st["u"][0] - U).max() < 1e-12
     assert np.abs(st["u"][1]).max() < 1e-12
+
+
+@pytest.mark.slow
+def test_manufactured_solution_temporal_order():
+    """Paper's manufactured fields at a fixed 64^2 grid: the split step is
+    first order in time, so with the time error dominant the L2 errors of phi
+    and u against the exact fields halve with dt (slope ~1).  An O(1)
+    inconsistency in time (forcing or a term at the wrong scale) would make
+    the error level off instead."""
+    from oracle import mms
+    prm0 = Params(1.0, 1.0, 10.0, 1.0, 1.0, 3.0, 1.0, 0.0)
+    Tend, n = 0.2, 64
+    g = MACGrid((n, n), 1.0 / n, (False, False))
+    errs = []
+    for nsteps in (5, 10, 20, 40):
+        prm = Params(**{**prm0.__dict__, "dt": Tend / nsteps})
+        st = mms.exact_state(g, prm, 0.0)
+        for k in range(nsteps):
+            st = step(g, st, prm, forcing=mms.forcing(g, prm, (k + 1) * prm.dt))
+        ex = mms.exact_state(g, prm, Tend)
+        eu = math.sqrt(np.mean((st["u"][0] - ex["u"][0]) ** 2 + (st["u"][1] - ex["u"][1]) ** 2))
+        ephi = math.sqrt(np.mean((st["phi"] - ex["phi"]) ** 2))
+        errs.append((ephi, eu))
+    sphi = [math.log2(errs[k][0] / errs[k + 1][0]) for k in range(3)]
+    su = [math.log2(errs[k][1] / errs[k + 1][1]) for k in range(3)]
+    assert all(0.95 <= s <= 1.15 for s in sphi), sphi
+    assert all(0.85 <= s <= 1.1 for s in su), su
+    assert su[-1] >= su[0]          # approaching 1 from below as dt -> 0
+
+
+# --------------------------------------------------------------------------
+# 3D: the conjugate-gradient branches of the momentum and pressure solves
+# --------------------------------------------------------------------------
+
+def test_3d_taylor_green_viscous_decay():
+    """Constant density, non-cubic periodic box (16 x 8 x 12 cells): the
+    discretely divergence-free mode
+      u_x =  A sin(kx x) cos(ky y) cos(kz z),  u_y = -B cos(kx x) sin(ky y) cos(kz z),  u_z = 0,
+    B = A sin(kx h/2) / sin(ky h/2), is an eigenvector of the MAC vector
+    Laplacian with lam = sum_a (2 cos(k_a h) - 2) / h^2, so each step
+    multiplies it by 1 / (1 - dt lam / Re) (all three axes enter lam)."""
+    n = (16, 8, 12)
+    h = 1.0 / 16
+    g = MACGrid(n, h, (True, True, True))
+    L = [m * h for m in n]
+    k = [2 * np.pi / x for x in L]
+    prm = Params(1.0, 1.0, 7.0, 1.0, 0.05, 100.0, 0.0, 2e-3)
+    i, j, kk = g.index(0), g.index(1), g.index(2)
+    A = 1e-10
+    B = A * np.sin(k[0] * h / 2) / np.sin(k[1] * h / 2)
+    ux = A * np.sin(k[0] * i * h) * np.cos(k[1] * (j + 0.5) * h) * np.cos(k[2] * (kk + 0.5) * h)
+    uy = -B * np.cos(k[0] * (i + 0.5) * h) * np.sin(k[1] * j * h) * np.cos(k[2] * (kk + 0.5) * h)
+    uz = np.zeros(g.shape)
+    assert np.abs(g.div([ux, uy, uz])).max() < 1e-14 * A / h
+    st = {"phi": np.ones(g.shape), "u": [ux, uy, uz], "p": np.zeros(g.shape)}
+    lam = sum((2 * np.cos(k[a] * h) - 2) / h ** 2 for a in range(3))
+    fac = 1.0 / (1.0 - prm.dt * lam / prm.Re)
+    for _ in range(10):
+        st = step(g, st, prm)
+    np.testing.assert_allclose(st["u"][0], ux * fac ** 10, rtol=0, atol=1e-12 * A)
+    np.testing.assert_allclose(st["u"][1], uy * fac ** 10, rtol=0, atol=1e-12 * A)
+    assert np.abs(st["u"][2]).max() <= 1e-12 * A
+
+
+@pytest.mark.parametrize("per", [(True, False, True), (False, True, False)])
+def test_3d_projection_is_divergence_free(per):
+    """Variable density (ratio 10 drop), walls on some axes, a random
+    velocity that is not divergence-free: after one step D u^{n+1} = 0 to
+    round-off relative to |u|/h, the wall normal velocity is 0 and mean(p) = 0
+    -- the pressure solve and the projection are consistent."""
+    n = (12, 10, 8)
+    h = 1.0 / 12
+    g = MACGrid(n, h, per)
+    rng = np.random.default_rng(31)
+    prm = Params(0.1, 0.1, 10.0, 1.0, 1.5 * h, 1000.0, 0.0, 1e-3)
+    X = g.coords()
+    r = np.sqrt((X[0] - 0.5) ** 2 + (X[1] - 0.4) ** 2 + (X[2] - 0.3) ** 2)
+    phi = np.tanh((r - 0.22) / (math.sqrt(2) * prm.Cn))
+    u = [rng.uniform(-1, 1, size=g.shape) for _ in range(3)]
+    for a in range(3):
+        u[a][g.wall_face_mask(a)] = 0.0
+    assert np.abs(g.div(u)).max() > 1.0
+    st = step(g, {"phi": phi, "u": u, "p": np.zeros(g.shape)}, prm)
+    umax = max(np.abs(x).max() for x in st["u"])
+    assert umax > 0.1
+    assert np.abs(g.div(st["u"])).max() * h <= 1e-12 * umax
+    for a in range(3):
+        assert np.all(st["u"][a][g.wall_face_mask(a)] == 0.0)
+    assert abs(st["p"].mean()) < 1e-12 * np.abs(st["p"]).max()
+
+
+def test_3d_constant_state_and_uniform_flow():
+    """phi constant inside (-1, 1) and a uniform velocity in a periodic 3D box:
+    every force vanishes and the flow is a Galilean translation, so phi, u
+    stay exactly as they are (to round-off) and p stays 0."""
+    n = (8, 12, 10)
+    g = MACGrid(n, 1.0 / 12, (True, True, True))
+    prm = Params(0.1, 0.05, 10.0, 1.0, 0.1, 100.0, 0.0, 1e-3)
+    U = (0.3, -0.7, 0.45)
+    st = {"phi": np.full(g.shape, 0.3), "u": [np.full(g.shape, x) for x in U], "p": np.zeros(g.shape)}
+    for _ in range(3):
+        st = step(g, st, prm)
+    assert np.abs(st["phi"] - 0.3).max() < 1e-14
+    for a in range(3):
+        assert np.abs(st["u"][a] - U[a]).max() < 1e-12
+    assert np.abs(st["p"]).max() < 1e-10
+
+
+@pytest.mark.parametrize("per", [(True, True, True), (True, True, False)])
+def test_3d_mass_conservation_with_flow(per):
+    """Proposition mass_conservation in 3D: a drop in a flow (the seeded
+    divergence-free field when periodic; gravity-driven between z walls
+    otherwise) conserves both phase masses to 1e-12 over 10 steps, and the
+    wall normal velocity stays 0."""
+    n = 16
+    if all(per):
+        prob = W.drop3d(n, steps=10)
+        prob.init_args = dict(prob.init_args, vamp=0.2)
+    else:
+        prob = W.drop3d(n, steps=10, inv_Fr=1.0)
+        prob = W.Problem(prob.name, prob.n, prob.h, (W.PERIODIC, W.PERIODIC, W.WALL), prob.props, 10, "drop",
+                         {"centre": (0.5, 0.5, 0.4), "radius": 0.25})
+    g = MACGrid(prob.n, prob.h, per)
+    prm = Params.from_props(prob.props)
+    st = W.initial_state(prob)
+    d0 = diagnostics(g, st, prm)
+    for _ in range(10):
+        st = step(g, st, prm)
+    d1 = diagnostics(g, st, prm)
+    for key in ("mass_plus", "mass_minus"):
+        assert abs(d1[key] - d0[key]) <= 1e-12 * d0[key]
+    assert d1["umax"] > 1e-4
+    assert d1["divmax"] * g.h <= 1e-12 * d1["umax"]
+    for a in range(3):
+        assert np.all(st["u"][a][g.wall_face_mask(a)] == 0.0)
+
+
+def test_3d_solve_branches_reach_the_exact_solution():
+    """The 3D branches solve their systems to the exact solution: the
+    momentum system (Jacobi-CG to 1e-14) and the singular pressure system
+    (CG on the consistent system, then the mean removed) agree with sparse LU
+    of the same matrices (the pressure one bordered by the constant vector)
+    on a small walled grid."""
+    import scipy.sparse as sp
+    n = (6, 4, 5)
+    g = MACGrid(n, 0.2, (True, False, False))
+    rng = np.random.default_rng(5)
+    eta = rng.uniform(0.01, 1.0, size=g.shape)
+    for a in range(3):
+        rhof = rng.uniform(0.001, 1.0, size=g.shape)
+        A, unk = O.momentum_matrix(g, a, rhof / 1e-3, eta, 10.0)
+        b = rng.standard_normal(unk.sum())
+        x_cg = O._solve_spd(A, b, 3)
+        x_lu = spla.spsolve(A, b)
+        assert np.abs(x_cg - x_lu).max() <= 1e-11 * np.abs(x_lu).max()
+    rhof = [rng.uniform(0.001, 1.0, size=g.shape) for _ in range(3)]
+    rhs = rng.standard_normal(g.shape)
+    p = O.pressure_solve(g, rhof, rhs)
+    Pm = O.pressure_matrix(g, rhof)
+    N = rhs.size
+    one = sp.csr_matrix(np.ones((N, 1)))
+    K = sp.bmat([[Pm, one], [one.T, None]], format="csc")
+    x = spla.spsolve(K, np.concatenate([rhs.ravel() - rhs.mean(), [0.0]]))[:N]
+    assert np.abs(p.ravel() - x).max() <= 1e-10 * np.abs(x).max()
