@@ -54,6 +54,14 @@ class Props:
     rtol_mom: float = 1e-13
     rtol_p: float = 1e-12
     max_iter: int = 300
+    # three-phase problems (nphases = 3): density and viscosity of phases
+    # 1, 2, 3 and the pairwise surface tensions (sigma_12, sigma_13,
+    # sigma_23); rho_minus / eta_minus are then unused and We only scales the
+    # pressure
+    nphases: int = 2
+    rho3: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    eta3: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    sigma3: Tuple[float, float, float] = (1.0, 1.0, 1.0)
 
     def copy(self, **kw) -> "Props":
         return dataclasses.replace(self, **kw)
@@ -279,10 +287,63 @@ def velocity_potential3d(p: Problem, seed: int, amp: float, kmax2: int = 4) -> L
     return [ux * (amp / m), uy * (amp / m), uz * (amp / m)]
 
 
-def initial_state(p: Problem) -> Dict[str, object]:
-    """Return {'phi': cells, 'u': [faces per axis], 'p': cells} in float64."""
+def _drop_distance(p: Problem, centres, radii) -> np.ndarray:
+    """Signed distance to the nearest of the given spheres / discs (negative
+    inside), minimum-image on periodic axes."""
+    X = cell_centres(p.n, p.h)
+    dmin = np.full(p.shape, np.inf)
+    for c, r in zip(centres, radii):
+        r2 = np.zeros(p.shape)
+        for a in range(p.dim):
+            d = _min_image(X[a] - c[a], p.n[a] * p.h, p.periodic[a])
+            r2 += d * d
+        dmin = np.minimum(dmin, np.sqrt(r2) - r)
+    return dmin
+
+
+def ternary_fields(p: Problem) -> List[np.ndarray]:
+    """phi_1, phi_2 of a three-phase initial condition (phi_i = 2 c_i - 1;
+    phase 3 fills the rest)."""
     a = p.init_args
-    if p.init == "drop":
+    Cn = p.props.Cn
+    if p.init == "ternary_drops":
+        cs_, rs_ = drop_set(p, a["seed"], 2 * a["count"], a["rmin"], a["rmax"], a["gap"])
+        # drops alternate between the two phases in placement order
+        d1 = _drop_distance(p, cs_[0::2], rs_[0::2])
+        d2 = _drop_distance(p, cs_[1::2], rs_[1::2])
+        return [-interface(d1, Cn), -interface(d2, Cn)]
+    if p.init == "ternary_layers":
+        # phase 1 below y1, phase 2 between y1 and y2, phase 3 above y2
+        X = cell_centres(p.n, p.h)
+        y = X[1]
+        y1, y2 = a["y1"], a["y2"]
+        c1 = 0.5 * (1.0 - interface(y - y1, Cn))
+        c12 = 0.5 * (1.0 - interface(y - y2, Cn))
+        return [2.0 * c1 - 1.0, 2.0 * (c12 - c1) - 1.0]
+    if p.init == "ternary_pair":
+        # two-phase drop of phase a["inside"] in phase a["outside"]; the third is absent
+        d = _drop_distance(p, [a["centre"]], [a["radius"]])
+        phi_in = -interface(d, Cn)
+        out = [None, None, None]
+        out[a["inside"]] = phi_in
+        out[a["outside"]] = -phi_in
+        k = 3 - a["inside"] - a["outside"]
+        out[k] = np.full(p.shape, -1.0)
+        return out[:2]
+    if p.init == "ternary_mix":
+        rng = np.random.default_rng(a.get("seed", 0))
+        c = 1.0 / 3.0 + a.get("amp", 0.05) * rng.uniform(-1.0, 1.0, size=(2,) + p.shape)
+        return [2.0 * c[0] - 1.0, 2.0 * c[1] - 1.0]
+    raise ValueError(f"unknown three-phase initial condition {p.init!r}")
+
+
+def initial_state(p: Problem) -> Dict[str, object]:
+    """Return {'phi': cells, 'u': [faces per axis], 'p': cells} in float64;
+    for three-phase problems 'phi' is the list [phi_1, phi_2]."""
+    a = p.init_args
+    if p.props.nphases == 3:
+        phi = [np.ascontiguousarray(x, dtype=np.float64) for x in ternary_fields(p)]
+    elif p.init == "drop":
         phi = phi_drop(p, a["centre"], a["radius"])
     elif p.init == "ellipse":
         phi = phi_ellipse(p, a["centre"], a["semi_axes"])
@@ -303,7 +364,9 @@ def initial_state(p: Problem) -> Dict[str, object]:
         u = velocity_potential3d(p, a.get("vseed", 1), a.get("vamp", 1e-2))
     else:
         u = [np.zeros(p.shape) for _ in range(p.dim)]
-    return {"phi": np.ascontiguousarray(phi, dtype=np.float64),
+    if p.props.nphases != 3:
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+    return {"phi": phi,
             "u": [np.ascontiguousarray(x, dtype=np.float64) for x in u],
             "p": np.zeros(p.shape)}
 
@@ -393,6 +456,50 @@ def drops3d(n: int = 128, steps: int = 500, seed: int = 3, count: int = 16, **kw
     return Problem("drops3d_%d" % n, (n, n, n), h, (PERIODIC,) * 3, pr, steps, "drops",
                    {"seed": seed, "count": count, "rmin": 0.05, "rmax": 0.12, "gap": 6 * 1.5 / 128,
                     "velocity": "potential3d", "vseed": seed + 100, "vamp": 1e-2})
+
+
+def sample_surface_tensions(seed: int, lo: float = 0.5, hi: float = 1.5) -> Tuple[float, float, float]:
+    """Pairwise surface tensions (sigma_12, sigma_13, sigma_23) ~ U[lo, hi]
+    each, redrawn until every spreading coefficient
+    Sigma_i = sigma_ij + sigma_ik - sigma_jk is positive."""
+    rng = np.random.default_rng(seed)
+    while True:
+        s12, s13, s23 = (float(x) for x in rng.uniform(lo, hi, size=3))
+        if min(s12 + s13 - s23, s12 + s23 - s13, s13 + s23 - s12) > 0.0:
+            return (s12, s13, s23)
+
+
+def ternary_drops3d(n: int = 128, steps: int = 500, seed: int = 3, count: int = 8, **kw) -> Problem:
+    """Three-phase drops: unit periodic box, `count` drops of phase 1 and
+    `count` of phase 2 (alternating in the seeded placement order, radii
+    U[0.05, 0.12], surfaces at least 6 x 1.5/128 apart) in a carrier phase 3;
+    pairwise surface tensions U[0.5, 1.5] (seeded, all spreading coefficients
+    positive); densities (100, 10, 1), viscosities (1/Re) eta_i = 1e-2
+    (Re = 1, eta_i = 1e-2); Cn = 1.5 h; 1/Pe = 3 Cn^2; dt = 1e-4; We = 1
+    (pressure scale); divergence-free velocity perturbation of amplitude 1e-2
+    (Fourier modes 1 <= |k|^2 <= 4, seeded)."""
+    h = 1.0 / n
+    Cn = 1.5 * h
+    pr = Props(Re=1.0, We=1.0, Cn=Cn, Pe=1.0 / (3.0 * Cn * Cn), dt=1e-4, nphases=3,
+               rho3=(100.0, 10.0, 1.0), eta3=(1e-2, 1e-2, 1e-2), sigma3=sample_surface_tensions(seed))
+    pr = pr.copy(**kw)
+    return Problem("ternary_drops3d_%d" % n, (n, n, n), h, (PERIODIC,) * 3, pr, steps, "ternary_drops",
+                   {"seed": seed, "count": count, "rmin": 0.05, "rmax": 0.12, "gap": 6 * 1.5 / 128,
+                    "velocity": "potential3d", "vseed": seed + 100, "vamp": 1e-2})
+
+
+def ternary_problem(n: Tuple[int, ...], init: str, init_args: Dict, bc=None, steps: int = 10,
+                    **kw) -> Problem:
+    """A small three-phase test problem on a box of cell size 1/n[0]
+    (defaults: Re = 10, We = 1, Cn = 1.5 h, Pe = 1000, dt = 1e-4, densities
+    (1, 0.1, 0.5), viscosities (1, 0.1, 0.3), sigma (1, 0.8, 1.2))."""
+    n = tuple(n)
+    h = 1.0 / n[0]
+    bc = tuple(bc) if bc is not None else (PERIODIC,) * len(n)
+    pr = Props(Re=10.0, We=1.0, Cn=1.5 * h, Pe=1000.0, dt=1e-4, nphases=3, rho3=(1.0, 0.1, 0.5),
+               eta3=(1.0, 0.1, 0.3), sigma3=(1.0, 0.8, 1.2))
+    pr = pr.copy(**kw)
+    return Problem("ternary_%s_%s" % (init, "x".join(map(str, n))), n, h, bc, pr, steps, init, dict(init_args))
 
 
 def oscillating_drop(n: int, semi_axes, rho_ratio: float, eta_ratio: float, sigma: float = 1.0,
