@@ -41,6 +41,23 @@
  * multigrid-preconditioned CG for S2 instead; larger grids and the batched
  * entry points always use it.
  *
+ * Three-phase model (nphases = 3; the paper is two-phase, this extends its
+ * binary free-energy density by the Boyer-Lapuerta construction): phases
+ * i = 1, 2, 3 with volume fractions c_i = (1 + phi_i)/2, sum_i c_i = 1; the
+ * state holds phi_1, phi_2 and phase 3 is implied.  Free energy
+ * (1/Cn) sum_i (Sigma_i/2) int psi(phi_i) + Cn^2/2 |grad phi_i|^2 with the
+ * spreading coefficients Sigma_i = sigma_ij + sigma_ik - sigma_jk; the
+ * constrained potentials mu~_i = psi'(phi_i) - Cn^2 lap phi_i - w_i Lambda,
+ * Lambda = sum_j psi'(phi_j), w_i = Sigma_T/(3 Sigma_i),
+ * 3/Sigma_T = sum_j 1/Sigma_j, sum to zero; every phase follows the paper's
+ * CH equation d phi_i/dt + div(u phi_i) = kM lap mu~_i; rho and eta are
+ * sum_i rho_i c_i*, sum_i eta_i c_i* with c_i* = clamp(c_i, 0, 1); the
+ * consistent flux is J = -(kM/2) sum_i rho_i grad mu~_i and the capillary
+ * force -(1/(2 Cn)) sum_i Sigma_i phi_i grad mu~_i.  The step T1..T9 is
+ * S1..S9 per phase with Lambda taken at t^n (two S2 solves).  For a pair
+ * i|j with the third phase absent it is the two-phase step with
+ * 1/We = sigma_ij.
+ *
  * Data layout (device memory, float64, row-major, x fastest):
  *   cell arrays   idx = i + nx*(j + ny*k), nx*ny*nz entries (nz = 1 in 2D);
  *   face arrays   one per axis a, same shape as the cell arrays; entry c is
@@ -86,7 +103,9 @@ enum { CHNS_FP64 = 0, CHNS_FP32_REFINE = 1 };
  * no-flux walls on both ends (paper: boundary conditions of the
  * mass-conservation proposition).  precision selects the arithmetic of the
  * linear solves (CHNS_FP64, or FP32 multigrid sweeps under an FP64 outer
- * refinement).  nphases must be 2.
+ * refinement).  nphases = 2 (the paper's two-phase model) or 3 (three-phase
+ * model, see below; single grids only -- the batched and adjoint entry
+ * points reject it).
  * Supported sizes: every n[a] >= 2 and even, and repeated halving of all axes
  * while they stay even must reach a grid of at most 512 cells.            */
 typedef struct {
@@ -111,16 +130,29 @@ typedef struct {
     double rtol_ch, rtol_mom, rtol_p;
     int max_iter;
     int reserved;
+    /* three-phase grids (nphases = 3) only: densities and viscosities of
+     * phases 1, 2, 3 (relative to the reference fluid), pairwise surface
+     * tensions (sigma_12, sigma_13, sigma_23) with every spreading
+     * coefficient sigma_ij + sigma_ik - sigma_jk > 0.  rho_minus and
+     * eta_minus are then unused, and We only scales the pressure (the
+     * capillary forces come from sigma_ij).                               */
+    double rho3[3], eta3[3], sigma3[3];
 } chns_props;
 
 /* Caller-owned device pointers of the state.  phi, p, mu: cell arrays;
  * u[a]: face arrays (u[2] unused in 2D).  chns_step reads phi, u, p and
- * overwrites them with the new state; mu receives mu^{n+1}.             */
+ * overwrites them with the new state; mu receives mu^{n+1}.
+ * Three-phase grids: phi and phi2 hold phi_1 = 2 c_1 - 1 and
+ * phi_2 = 2 c_2 - 1 (phase 3 is implied: c_3 = 1 - c_1 - c_2), and mu, mu2
+ * receive the constrained chemical potentials mu~_1, mu~_2.  phi2 and mu2
+ * are ignored on two-phase grids.                                        */
 typedef struct {
     void *phi;
     void *u[3];
     void *p;
     void *mu;
+    void *phi2;
+    void *mu2;
 } chns_state;
 
 /* Host-side statistics of the last step of a chns_step call.            */
@@ -131,6 +163,9 @@ typedef struct {
     double mass_plus, mass_minus;       /* sum (1 +- phi)/2 h^d            */
     double energy;                      /* discrete total energy           */
     double umax, divmax;                /* max |u|, max |D u|              */
+    double mass_phase[3];               /* sum c_i h^d of phases 1, 2, 3
+                                           (two-phase grids: mass_plus,
+                                           mass_minus, 0)                   */
 } chns_step_stats;
 
 typedef struct {

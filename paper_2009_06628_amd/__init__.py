@@ -36,12 +36,13 @@ class chns_props(ctypes.Structure):
                 ("Pe", ctypes.c_double), ("inv_Fr", ctypes.c_double),
                 ("dt", ctypes.c_double), ("S", ctypes.c_double),
                 ("rtol_ch", ctypes.c_double), ("rtol_mom", ctypes.c_double), ("rtol_p", ctypes.c_double),
-                ("max_iter", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("rho3", ctypes.c_double * 3), ("eta3", ctypes.c_double * 3), ("sigma3", ctypes.c_double * 3)]
 
 
 class chns_state(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_void_p), ("u", ctypes.c_void_p * 3), ("p", ctypes.c_void_p),
-                ("mu", ctypes.c_void_p)]
+                ("mu", ctypes.c_void_p), ("phi2", ctypes.c_void_p), ("mu2", ctypes.c_void_p)]
 
 
 class chns_step_stats(ctypes.Structure):
@@ -49,7 +50,8 @@ class chns_step_stats(ctypes.Structure):
                 ("unconverged", ctypes.c_int),
                 ("res_ch", ctypes.c_double), ("res_mom", ctypes.c_double * 3), ("res_p", ctypes.c_double),
                 ("mass_plus", ctypes.c_double), ("mass_minus", ctypes.c_double),
-                ("energy", ctypes.c_double), ("umax", ctypes.c_double), ("divmax", ctypes.c_double)]
+                ("energy", ctypes.c_double), ("umax", ctypes.c_double), ("divmax", ctypes.c_double),
+                ("mass_phase", ctypes.c_double * 3)]
 
 
 class chns_kernel_timing(ctypes.Structure):
@@ -191,7 +193,8 @@ def _ptr(t, dtype=None) -> int:
     return t.data_ptr()
 
 
-def make_desc(n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64) -> chns_grid_desc:
+def make_desc(n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64,
+              nphases: int = 2) -> chns_grid_desc:
     d = chns_grid_desc()
     d.dim = len(n)
     for a in range(3):
@@ -199,13 +202,14 @@ def make_desc(n: Sequence[int], h: float, bc: Sequence[str], precision: int = CH
         d.bc[a] = (CHNS_BC_WALL if bc[a] == "wall" else CHNS_BC_PERIODIC) if a < len(n) else 0
     d.h = float(h)
     d.precision = precision
-    d.nphases = 2
+    d.nphases = int(nphases)
     return d
 
 
-def workspace_size(n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64) -> int:
+def workspace_size(n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64,
+                   nphases: int = 2) -> int:
     lib = load_library()
-    d = make_desc(n, h, bc, precision)
+    d = make_desc(n, h, bc, precision, nphases)
     out = ctypes.c_size_t(0)
     _check(lib.chns_workspace_size(ctypes.byref(d), ctypes.byref(out)), "chns_workspace_size")
     return out.value
@@ -215,7 +219,7 @@ class Grid:
     """Handle of one uniform grid (create_grid); owns its workspace tensor."""
 
     def __init__(self, n: Sequence[int], h: float, bc: Sequence[str], precision: int = CHNS_FP64,
-                 device: str = "cuda", stream=None):
+                 device: str = "cuda", stream=None, nphases: int = 2):
         torch = _torch()
         lib = load_library()
         self.n = tuple(int(x) for x in n)
@@ -224,8 +228,9 @@ class Grid:
         self.h = float(h)
         self.bc = tuple(bc)
         self.device = torch.device(device)
-        self._desc = make_desc(self.n, h, bc, precision)
-        nbytes = workspace_size(self.n, h, bc, precision)
+        self.nphases = int(nphases)
+        self._desc = make_desc(self.n, h, bc, precision, self.nphases)
+        nbytes = workspace_size(self.n, h, bc, precision, self.nphases)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
@@ -245,21 +250,24 @@ class Grid:
 
     # -- set_properties ------------------------------------------------------
     def set_properties(self, props) -> None:
-        p = chns_props()
-        for name, _ in chns_props._fields_:
-            if name == "reserved":
-                continue
-            setattr(p, name, getattr(props, name))
-        _check(self._lib.chns_set_properties(self._h, ctypes.byref(p)), "chns_set_properties")
+        _check(self._lib.chns_set_properties(self._h, ctypes.byref(_props_struct(props))), "chns_set_properties")
 
     # -- state ---------------------------------------------------------------
     def new_state(self, init: Optional[Dict] = None) -> Dict:
         """Allocate a device state (float64) and fill it from numpy arrays."""
         torch = _torch()
         z = lambda: torch.zeros(self.shape, dtype=torch.float64, device=self.device)
-        st = {"phi": z(), "u": [z() for _ in range(self.dim)], "p": z(), "mu": z()}
+        if self.nphases == 3:
+            # phases 1 and 2 (phase 3 is implied); mu~_1, mu~_2
+            st = {"phi": [z(), z()], "u": [z() for _ in range(self.dim)], "p": z(), "mu": [z(), z()]}
+        else:
+            st = {"phi": z(), "u": [z() for _ in range(self.dim)], "p": z(), "mu": z()}
         if init is not None:
-            st["phi"].copy_(torch.as_tensor(init["phi"]))
+            if self.nphases == 3:
+                for i in range(2):
+                    st["phi"][i].copy_(torch.as_tensor(init["phi"][i]))
+            else:
+                st["phi"].copy_(torch.as_tensor(init["phi"]))
             for a in range(self.dim):
                 st["u"][a].copy_(torch.as_tensor(init["u"][a]))
             if "p" in init:
@@ -268,11 +276,15 @@ class Grid:
 
     def _cstate(self, st: Dict) -> chns_state:
         cs = chns_state()
-        cs.phi = _ptr(st["phi"])
+        if self.nphases == 3:
+            cs.phi, cs.phi2 = _ptr(st["phi"][0]), _ptr(st["phi"][1])
+            cs.mu, cs.mu2 = _ptr(st["mu"][0]), _ptr(st["mu"][1])
+        else:
+            cs.phi = _ptr(st["phi"])
+            cs.mu = _ptr(st["mu"])
         for a in range(3):
             cs.u[a] = _ptr(st["u"][a]) if a < self.dim else None
         cs.p = _ptr(st["p"])
-        cs.mu = _ptr(st["mu"])
         return cs
 
     # -- step ----------------------------------------------------------------
@@ -288,6 +300,7 @@ class Grid:
             "unconverged": out.unconverged, "res_ch": out.res_ch, "res_mom": list(out.res_mom)[: self.dim],
             "res_p": out.res_p, "mass_plus": out.mass_plus, "mass_minus": out.mass_minus,
             "energy": out.energy, "umax": out.umax, "divmax": out.divmax, "rc": rc,
+            "mass_phase": list(out.mass_phase)[: self.nphases],
         }
 
     # -- solve_pressure --------------------------------------------------------
@@ -394,10 +407,13 @@ class Grid:
 
 def _props_struct(props) -> chns_props:
     p = chns_props()
-    for name, _ in chns_props._fields_:
+    for name, ctype in chns_props._fields_:
         if name == "reserved":
             continue
-        setattr(p, name, getattr(props, name))
+        if name in ("rho3", "eta3", "sigma3"):
+            setattr(p, name, ctype(*[float(x) for x in getattr(props, name, (1.0, 1.0, 1.0))]))
+        else:
+            setattr(p, name, getattr(props, name))
     return p
 
 
@@ -535,12 +551,12 @@ def create_batch(problems, precision=CHNS_FP64, device="cuda", stream=None) -> B
     return Batch(problems, precision, device, stream)
 
 
-def create_grid(n, h, bc, precision=CHNS_FP64, device="cuda", stream=None) -> Grid:
-    return Grid(n, h, bc, precision, device, stream)
+def create_grid(n, h, bc, precision=CHNS_FP64, device="cuda", stream=None, nphases: int = 2) -> Grid:
+    return Grid(n, h, bc, precision, device, stream, nphases)
 
 
 def grid_for_problem(problem, precision=CHNS_FP64, device="cuda") -> Grid:
-    """Grid + properties for a workloads.Problem."""
-    g = Grid(problem.n, problem.h, problem.bc, precision, device)
+    """Grid + properties for a workloads.Problem (two- or three-phase)."""
+    g = Grid(problem.n, problem.h, problem.bc, precision, device, nphases=getattr(problem.props, "nphases", 2))
     g.set_properties(problem.props)
     return g

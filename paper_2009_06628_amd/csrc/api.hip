@@ -20,6 +20,9 @@ using namespace chns;
 
 static thread_local std::string g_err;
 
+// partial-sum rows of the diagnostics kernels (8 two-phase, 9 three-phase)
+constexpr int kDiagSlots = 10;
+
 // ---------------------------------------------------------------------------
 // per-kernel timing
 // ---------------------------------------------------------------------------
@@ -115,7 +118,7 @@ int check_props(const chns_props *p) {
 int make_plan(const chns_grid_desc *d, Plan &P) {
     if (!d) return fail(CHNS_EINVAL, "grid description is NULL");
     if (d->dim != 2 && d->dim != 3) return fail(CHNS_EINVAL, "dim must be 2 or 3");
-    if (d->nphases != 2) return fail(CHNS_EINVAL, "only nphases = 2 is supported");
+    if (d->nphases != 2 && d->nphases != 3) return fail(CHNS_EINVAL, "nphases must be 2 or 3");
     if (d->precision != CHNS_FP64 && d->precision != CHNS_FP32_REFINE) return fail(CHNS_EINVAL, "bad precision");
     if (!(d->h > 0.0) || !std::isfinite(d->h)) return fail(CHNS_EINVAL, "h must be positive and finite");
     Geo g;
@@ -134,6 +137,7 @@ int make_plan(const chns_grid_desc *d, Plan &P) {
     }
     if (g.N >= (1LL << 31) - 1) return fail(CHNS_EINVAL, "grid too large (kernels index cells with 32-bit integers)");
     P.dim = d->dim;
+    P.nph = d->nphases;
     P.nlev = 1;
     P.lev[0] = g;
     for (;;) {
@@ -179,6 +183,14 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     g->rch = B.take<double>(N);
     for (int a = 0; a < 3; ++a) g->ustar[a] = a < P.dim ? B.take<double>(N) : nullptr;
     g->rhs = B.take<double>(N);
+    g->nph = P.nph;
+    if (P.nph == 3) {
+        g->phi_new2 = B.take<double>(N);
+        g->phihat2 = B.take<double>(N);
+        g->rch2 = B.take<double>(N);
+    } else {
+        g->phi_new2 = g->phihat2 = g->rch2 = nullptr;
+    }
     g->vr = B.take<double>(N);
     g->vz = B.take<double>(N);
     g->vp0 = B.take<double>(N);
@@ -214,7 +226,7 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     g->red.rz0 = B.take<double>(kRedBlocks);
     g->red.rz1 = B.take<double>(kRedBlocks);
     g->red.rz2 = B.take<double>(kRedBlocks);
-    g->diag = B.take<double>(8 * (size_t)kMaxBlocks + 16);
+    g->diag = B.take<double>(kDiagSlots * (size_t)kMaxBlocks + 16);
     g->red.counter = B.take<unsigned int>(64);
     g->red.scal = B.take<Scal>(1);
     // momentum components 1 .. dim-1 (own hierarchy, vectors, scratch)
@@ -366,7 +378,7 @@ static bool serial_momentum() {
 // S1..S8 of one step from (phi, u) with the pressure initial guess in pr:
 // phihat, mu, phi_new, ustar and p; solver statistics into last.
 int forward_core(chns_grid *g, const double *phi, const double *const uc[3], double *mu, double *pr,
-                 chns_step_stats &last) {
+                 chns_step_stats &last, const double *phi2 = nullptr, double *mu2 = nullptr) {
     const int dim = g->dim;
     const Geo &geo = g->geo;
     const StepConst k = step_const(g);
@@ -376,16 +388,30 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
     SolveOut o;
     memset(&last, 0, sizeof last);
+    // three-phase model: phases 1 and 2 stored (T1..T4 per phase)
+    const bool tern = g->nph == 3;
+    const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2}};
     // S1, S2
-    launch_ch_rhs(dim, geo, k, phi, uc, g->rch, g->phihat, s);
-    HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)g->rch, g->phihat, p.rtol_ch, 0, &o));
-    if (int rc = check_solve(o, "Cahn-Hilliard")) return rc;
-    last.iters_ch = o.iters;
-    last.res_ch = o.rel_res;
-    last.unconverged |= o.unconverged ? 1 : 0;
+    if (tern)
+        launch_ch_rhs3(dim, geo, k, g->tern, ph, uc, g->rch, g->rch2, g->phihat, g->phihat2, s);
+    else
+        launch_ch_rhs(dim, geo, k, phi, uc, g->rch, g->phihat, s);
+    for (int q = 0; q < (tern ? 2 : 1); ++q) {
+        HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)(q ? g->rch2 : g->rch), q ? g->phihat2 : g->phihat,
+                         p.rtol_ch, q ? 11 : 0, &o));
+        if (int rc = check_solve(o, "Cahn-Hilliard")) return rc;
+        last.iters_ch = o.iters > last.iters_ch ? o.iters : last.iters_ch;
+        last.res_ch = o.rel_res > last.res_ch ? o.rel_res : last.res_ch;
+        last.unconverged |= o.unconverged ? 1 : 0;
+    }
     // S3, S4
-    launch_mu(dim, geo, k, phi, g->phihat, mu, s);
-    launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);
+    if (tern) {
+        launch_mu3(dim, geo, k, g->tern, ph, g->phihat, g->phihat2, s);
+        launch_phi_update3(dim, geo, k, ph, uc, s);
+    } else {
+        launch_mu(dim, geo, k, phi, g->phihat, mu, s);
+        launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);
+    }
     // S5..S7: the components are independent.  With the per-kernel timing
     // off, component a > 0 runs on its own stream (forked from and joined
     // back to the handle's stream by events) and its own host thread, so
@@ -402,7 +428,10 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         c.s = g->pstream;
         ep = hipStreamWaitEvent(c.s, g->ev_fork, 0);
         if (ep != hipSuccess) return;
-        launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, c.s, kPCoef);
+        if (tern)
+            launch_p_setup3(dim, geo, k, g->tern, ph, usc, P0.s, pcs, g->rhs, c.s, kPCoef);
+        else
+            launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, c.s, kPCoef);
         hierarchy_setup(g, c);
         ep = hipEventRecord(g->ev_pset, c.s);
     };
@@ -417,7 +446,10 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         Level<double> &L0 = c.S64->lev[0];
         double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
         double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
-        launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, rhs, g->ustar[a], c.s);
+        if (tern)
+            launch_mom_setup3(dim, geo, k, g->tern, ph, a, uc, L0.s, cs, rhs, g->ustar[a], c.s);
+        else
+            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, rhs, g->ustar[a], c.s);
         em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
         if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
     };
@@ -454,7 +486,10 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     }
     if (ep != hipSuccess) return fail(CHNS_EDEVICE, std::string("pressure set-up: ") + hipGetErrorString(ep));
     // S8 (coefficients and hierarchy already set up when concurrent)
-    launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs);
+    if (tern)
+        launch_p_setup3(dim, geo, k, g->tern, ph, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs);
+    else
+        launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs);
     remove_mean(geo, g->rhs, g->red, s);
     HIPCHK(run_solve_ctx(g, main_ctx(g, 2), !concurrent, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
     if (int rc = check_solve(o, "pressure")) return rc;
@@ -607,6 +642,16 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
 int chns_set_properties(chns_grid *g, const chns_props *p) {
     if (!g || !p) return fail(CHNS_EINVAL, "NULL argument");
     if (int rc = check_props(p)) return rc;
+    if (g->nph == 3) {
+        for (int i = 0; i < 3; ++i)
+            if (!(p->rho3[i] > 0.0) || !(p->eta3[i] > 0.0) || !std::isfinite(p->rho3[i]) || !std::isfinite(p->eta3[i]) ||
+                !(p->sigma3[i] > 0.0) || !std::isfinite(p->sigma3[i]))
+                return fail(CHNS_EINVAL, "three-phase densities, viscosities and surface tensions must be positive");
+        const TernConst t = tern_const_of(*p);
+        if (!(t.Sg[0] > 0.0) || !(t.Sg[1] > 0.0) || !(t.Sg[2] > 0.0))
+            return fail(CHNS_EINVAL, "every spreading coefficient sigma_ij + sigma_ik - sigma_jk must be positive");
+        g->tern = t;
+    }
     g->props = *p;
     g->props_set = 1;
     const StepConst k = step_const(g);
@@ -629,6 +674,7 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     if (!st->phi || !st->p || !st->mu) return fail(CHNS_EINVAL, "state pointer is NULL");
     for (int a = 0; a < g->dim; ++a)
         if (!st->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
+    if (g->nph == 3 && (!st->phi2 || !st->mu2)) return fail(CHNS_EINVAL, "three-phase state needs phi2 and mu2");
     ProfScope prof_scope(g);
     const int dim = g->dim;
     const Geo &geo = g->geo;
@@ -636,6 +682,7 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     const chns_props &p = g->props;
     hipStream_t s = g->stream;
     double *phi = (double *)st->phi, *mu = (double *)st->mu, *pr = (double *)st->p;
+    double *phi2 = g->nph == 3 ? (double *)st->phi2 : nullptr, *mu2 = g->nph == 3 ? (double *)st->mu2 : nullptr;
     double *u[3] = {(double *)st->u[0], (double *)st->u[1], dim == 3 ? (double *)st->u[2] : nullptr};
     const double *uc[3] = {u[0], u[1], u[2]};
     const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
@@ -643,26 +690,49 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     chns_step_stats last;
     memset(&last, 0, sizeof last);
     for (int n = 0; n < nsteps; ++n) {
-        if (int rc = forward_core(g, phi, uc, mu, pr, last)) return rc;
+        if (int rc = forward_core(g, phi, uc, mu, pr, last, phi2, mu2)) return rc;
         // S9
-        launch_project(dim, geo, k, g->phi_new, usc, pr, phi, u, s);
+        if (g->nph == 3) {
+            const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2}};
+            launch_project3(dim, geo, k, g->tern, ph, usc, pr, phi, phi2, u, s);
+        } else {
+            launch_project(dim, geo, k, g->phi_new, usc, pr, phi, u, s);
+        }
         HIPCHK(hipGetLastError());
         unconv_any |= last.unconverged;
     }
     if (stats) {
-        launch_diagnostics(dim, geo, k, phi, uc, g->diag, g->red.counter, g->diag + 8 * kMaxBlocks, s);
-        double h8[8];
-        HIPCHK(hipMemcpyAsync(h8, g->diag + 8 * kMaxBlocks, sizeof h8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        double *dout = g->diag + kDiagSlots * kMaxBlocks;
         const double hd = std::pow(g->h, dim);
-        last.mass_plus = h8[0] * hd;
-        last.mass_minus = h8[1] * hd;
-        const double kin = h8[2] * hd;
-        const double fre = (h8[3] * hd + 0.5 * p.Cn * p.Cn * h8[4] * hd) / (p.Cn * p.We);
-        const double grav = p.inv_Fr * h8[5] * hd;
-        last.energy = kin + fre + grav;
-        last.umax = h8[6];
-        last.divmax = h8[7];
+        if (g->nph == 3) {
+            launch_diagnostics3(dim, geo, k, g->tern, phi, phi2, uc, g->diag, g->red.counter, dout, s);
+            double h9[9];
+            HIPCHK(hipMemcpyAsync(h9, dout, sizeof h9, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int q = 0; q < 3; ++q) last.mass_phase[q] = h9[q] * hd;
+            last.mass_plus = last.mass_phase[0];
+            last.mass_minus = last.mass_phase[1];
+            const double fre = (h9[4] * hd + 0.5 * p.Cn * p.Cn * h9[5] * hd) / p.Cn;
+            last.energy = h9[3] * hd + fre + p.inv_Fr * h9[6] * hd;
+            last.umax = h9[7];
+            last.divmax = h9[8];
+        } else {
+            launch_diagnostics(dim, geo, k, phi, uc, g->diag, g->red.counter, dout, s);
+            double h8[8];
+            HIPCHK(hipMemcpyAsync(h8, dout, sizeof h8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            last.mass_plus = h8[0] * hd;
+            last.mass_minus = h8[1] * hd;
+            last.mass_phase[0] = last.mass_plus;
+            last.mass_phase[1] = last.mass_minus;
+            last.mass_phase[2] = 0.0;
+            const double kin = h8[2] * hd;
+            const double fre = (h8[3] * hd + 0.5 * p.Cn * p.Cn * h8[4] * hd) / (p.Cn * p.We);
+            const double grav = p.inv_Fr * h8[5] * hd;
+            last.energy = kin + fre + grav;
+            last.umax = h8[6];
+            last.divmax = h8[7];
+        }
         *stats = last;
     }
     g->last = last;
@@ -680,6 +750,7 @@ int chns_adjoint_workspace_size(const chns_grid_desc *desc, size_t *bytes) {
     Plan P;
     int rc = make_plan(desc, P);
     if (rc) return rc;
+    if (P.nph != 2) return fail(CHNS_EINVAL, "the discrete adjoint covers the two-phase step");
     AdjBufs A;
     Bump B{nullptr, 0};
     layout_adjoint(B, P.lev[0], P.dim, A);
@@ -689,6 +760,7 @@ int chns_adjoint_workspace_size(const chns_grid_desc *desc, size_t *bytes) {
 
 int chns_attach_adjoint_workspace(chns_grid *g, void *workspace, size_t bytes) {
     if (!g) return fail(CHNS_EINVAL, "NULL handle");
+    if (g->nph != 2) return fail(CHNS_EINVAL, "the discrete adjoint covers the two-phase step");
     if (!workspace) return fail(CHNS_EINVAL, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(CHNS_EINVAL, "workspace must be 256-byte aligned");
     size_t need = 0;
@@ -876,6 +948,7 @@ static int check_record(const chns_grid *g, const chns_record *rec) {
 
 int chns_step_record(chns_grid *g, chns_state *st, const chns_record *rec) {
     if (!g) return fail(CHNS_EINVAL, "NULL argument");
+    if (g->nph != 2) return fail(CHNS_EINVAL, "step records cover the two-phase step");
     if (int rc = check_record(g, rec)) return rc;
     const int rc = chns_step(g, st, 1, nullptr);
     if (rc != CHNS_OK && rc != CHNS_ENOCONV) return rc;

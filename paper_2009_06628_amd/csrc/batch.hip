@@ -611,6 +611,7 @@ int check_descs(int count, const chns_grid_desc *descs, std::vector<Plan> &plans
     plans.resize(count);
     for (int i = 0; i < count; ++i) {
         if (int rc = make_plan(&descs[i], plans[i])) return rc;
+        if (descs[i].nphases != 2) return set_error(CHNS_EINVAL, "batched problems are two-phase (nphases = 2)");
         if (descs[i].dim != descs[0].dim || descs[i].precision != descs[0].precision)
             return set_error(CHNS_EINVAL, "every problem of a batch must have the same dim and precision");
     }

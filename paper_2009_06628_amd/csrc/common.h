@@ -307,6 +307,13 @@ struct MomCtx {
     hipEvent_t done_ev;   // recorded on stream after the solve
 };
 
+// Three-phase constants: densities, viscosities, spreading coefficients
+// Sigma_i = sigma_ij + sigma_ik - sigma_jk and the weights
+// w_i = Sigma_T / (3 Sigma_i) of the constrained chemical potentials.
+struct TernConst {
+    double rho[3], eta[3], Sg[3], w[3];
+};
+
 // Bases of the direct Cahn-Hilliard solve (spectral.h, spectral.hip).
 constexpr int kSpectralMaxN = 2048;   // larger axes keep the MG-PCG solve
 struct Spectral {
@@ -328,6 +335,9 @@ struct chns_grid {
     double h;
     // state-independent workspace buffers (double, N cells each)
     double *phi_new, *phihat, *rch, *ustar[3], *rhs;
+    int nph;                                 // phases: 2, or 3 (three-phase model)
+    chns::TernConst tern;                    // three-phase constants (nph == 3)
+    double *phi_new2, *phihat2, *rch2;       // the second stored phase (nph == 3)
     double *vr, *vz, *vp0, *vp1, *vq, *vt;   // PCG vectors
     chns::Slot<double> ch, mom, pres;
     // precision form (FP32 inner solves under FP64 refinement)

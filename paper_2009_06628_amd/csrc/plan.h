@@ -18,6 +18,7 @@ StepConst step_const_of(const chns_props &p, double h);
 
 struct Plan {
     int dim;
+    int nph;       // phases (2 or 3)
     int nlev;
     Geo lev[kMaxLev];
 };

@@ -12,6 +12,46 @@ struct StepConst {
     double inv_Re, inv_We, We, inv_Fr;
 };
 
+constexpr int kPCoef = 1, kPRhs = 2;
+
+// Three-phase constants (TernConst, common.h) from the properties.
+TernConst tern_const_of(const chns_props &p);
+
+// The stored phase fields of a three-phase step (phases 1 and 2; phase 3 is
+// -1 - phi_1 - phi_2): phi^n, phi^{n+1} and mu~^{n+1}.
+struct Phases3 {
+    const double *phi[2];
+    double *phin[2];
+    double *mu[2];
+};
+
+// T1: r_i and phihat_i = phi_i for i = 1, 2.
+void launch_ch_rhs3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
+                    const double *const u[3], double *r1, double *r2, double *hat1, double *hat2, hipStream_t st);
+// T3: mu~_i from phihat_i.
+void launch_mu3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, const double *hat1,
+                const double *hat2, hipStream_t st);
+// T4: phi_i^{n+1}.
+void launch_phi_update3(int dim, const Geo &g, const StepConst &k, const Phases3 &ph, const double *const u[3],
+                        hipStream_t st);
+// T5-T7 set-up of momentum component a.
+void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
+                       const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,
+                       hipStream_t st);
+// T8 set-up (parts as launch_p_setup).
+void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
+                     const double *const ustar[3], double *s, double *const cs[3], double *rhs, hipStream_t st,
+                     int part);
+// T9: projection, phi_i = phi_i^{n+1}.
+void launch_project3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
+                     const double *const ustar[3], const double *p, double *phi1, double *phi2, double *const u[3],
+                     hipStream_t st);
+// Diagnostics into out[0..8] = sum c_1, c_2, c_3, kinetic, sum (Sigma_i/2) psi,
+// sum (Sigma_i/2) |G phi_i|^2, gravity, umax, divmax.
+void launch_diagnostics3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const double *phi1,
+                         const double *phi2, const double *const u[3], double *part, unsigned int *counter,
+                         double *out, hipStream_t st);
+
 // S1: r = phi - dt D(u A phi) + dt kM L(psi'(phi) - S phi); phihat = phi.
 void launch_ch_rhs(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
                    double *r, double *phihat, hipStream_t st);
@@ -30,7 +70,6 @@ void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const do
 // (part & kPCoef) and rhs = -(We/dt) D ustar (part & kPRhs).  The
 // coefficients need only phi_new, so the step sets them and the pressure
 // hierarchy up while the momentum solves run.
-constexpr int kPCoef = 1, kPRhs = 2;
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
                     double *s, double *const cs[3], double *rhs, hipStream_t st, int part = kPCoef | kPRhs);
 // Pressure coefficients from a given cell density (stand-alone solve).

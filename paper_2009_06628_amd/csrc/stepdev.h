@@ -42,6 +42,42 @@ __device__ inline double mflux(const Geo &g, const StepConst &k, const double *_
     return (0.5 * (rl + rlo)) * ub[f] - (k.alpha / (k.Cn * k.Pe)) * ((mu[f] - mu[lo]) * k.ih);
 }
 
+// Mixture policy of the two-phase model: the density / viscosity maps with
+// the pull-back, the mass flux m = A(alpha phi^n + beta) u + J / Pe and the
+// potential-form capillary force (1/(We Cn)) A(phi^n) G mu^{n+1} on a face.
+// The set-up bodies below take a policy, so that the three-phase model
+// (ternary.hip) runs the same momentum / pressure / projection arithmetic.
+struct Mix2 {
+    double alpha, beta, gamma, xi, jcoef, stcoef, ih;   // jcoef = alpha/(Cn Pe), stcoef = 1/(We Cn)
+    const double *phi, *phin, *mu;                     // phi^n, phi^{n+1}, mu^{n+1}
+    __device__ double rho_new(int e) const { return alpha * pullback(phin[e]) + beta; }
+    __device__ double rho_old(int e) const { return alpha * pullback(phi[e]) + beta; }
+    __device__ double eta_new(int e) const { return gamma * pullback(phin[e]) + xi; }
+    // m_b on the face f between lo = f - e_b and f (not a wall face)
+    __device__ double mflux_face(double ub, int f, int lo) const {
+        const double rl = alpha * phi[f] + beta, rlo = alpha * phi[lo] + beta;
+        return (0.5 * (rl + rlo)) * ub - jcoef * ((mu[f] - mu[lo]) * ih);
+    }
+    // capillary term subtracted from the momentum right-hand side on the face
+    // between cam = c - e_a and c
+    __device__ double capillary(int c, int cam) const {
+        return stcoef * (0.5 * (phi[c] + phi[cam])) * ((mu[c] - mu[cam]) * ih);
+    }
+};
+
+__host__ __device__ inline Mix2 mk_mix2(const StepConst &k, const double *phi, const double *phin, const double *mu) {
+    return Mix2{k.alpha, k.beta, k.gamma, k.xi, k.alpha / (k.Cn * k.Pe), k.inv_We / k.Cn, k.ih, phi, phin, mu};
+}
+
+// Mass flux of a mixture policy on the face f of axis b (index ib of f
+// along b), zero on wall faces.
+template <int DIM, typename Mix>
+__device__ inline double mflux_mix(const Geo &g, const Mix &mx, const double *__restrict__ ub, int b, int f, int ib) {
+    if (f < 0) return 0.0;                       // unstored upper wall face
+    if (!g.per[b] && ib == 0) return 0.0;        // stored wall face
+    return mx.mflux_face(ub[f], f, nb_lo(g, f, ib, b));
+}
+
 __device__ inline int wrap_next(int ib, int n) { return ib + 1 < n ? ib + 1 : 0; }
 __device__ inline int wrap_prev(int ib, int n) { return ib > 0 ? ib - 1 : n - 1; }
 
@@ -128,9 +164,8 @@ __device__ inline void phi_update_cell(const Geo &g, const StepConst &k, const d
 
 // S5-S7 set-up for component a: level-0 coefficients of the momentum operator,
 // right-hand side, initial guess ustar_a = u_a
-template <int DIM>
-__device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, const double *__restrict__ phi,
-                                      const double *__restrict__ phin, const double *__restrict__ mu, const U3 &u,
+template <int DIM, typename Mix>
+__device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, const Mix &mx, const U3 &u,
                                       double *__restrict__ s, const W3 &cs, double *__restrict__ rhs,
                                       double *__restrict__ ustar, int coef_only, int c) {
     const double rvis = k.inv_Re * k.ih2;
@@ -150,9 +185,9 @@ __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, c
         return;
     }
     const int cam = nb_lo(g, c, ia[a], a);   // cell c - e_a
-    auto eta_of = [&](int e) { return k.gamma * pullback(phin[e]) + k.xi; };
-    const double rf_new = 0.5 * ((k.alpha * pullback(phin[c]) + k.beta) + (k.alpha * pullback(phin[cam]) + k.beta));
-    const double rf_old = 0.5 * ((k.alpha * pullback(phi[c]) + k.beta) + (k.alpha * pullback(phi[cam]) + k.beta));
+    auto eta_of = [&](int e) { return mx.eta_new(e); };
+    const double rf_new = 0.5 * (mx.rho_new(c) + mx.rho_new(cam));
+    const double rf_old = 0.5 * (mx.rho_old(c) + mx.rho_old(cam));
     const double e_c = eta_of(c), e_am = eta_of(cam);
     double sd = rf_new / k.dt;
     double nadv = 0.0;
@@ -170,9 +205,9 @@ __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, c
             if (!g.per[a] && ia[a] == g.n[a] - 1) sd += e_c * rvis;   // upper wall face
             cs.a[b][c] = w;
             // skew advection, b == a
-            const double m_c = mflux<DIM>(g, k, phi, mu, u.a[a], a, c, ia[a]);
-            const double m_hi = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[a], a, hi, wrap_next(ia[a], g.n[a])) : 0.0;
-            const double m_lo = mflux<DIM>(g, k, phi, mu, u.a[a], a, lo, wrap_prev(ia[a], g.n[a]));
+            const double m_c = mflux_mix<DIM>(g, mx, u.a[a], a, c, ia[a]);
+            const double m_hi = hi >= 0 ? mflux_mix<DIM>(g, mx, u.a[a], a, hi, wrap_next(ia[a], g.n[a])) : 0.0;
+            const double m_lo = mflux_mix<DIM>(g, mx, u.a[a], a, lo, wrap_prev(ia[a], g.n[a]));
             const double mp = 0.5 * (m_c + m_hi), mm = 0.5 * (m_lo + m_c);
             const double up = hi >= 0 ? ua[hi] : 0.0;
             const double um = (!g.per[a] && ia[a] == 1) ? 0.0 : ua[lo];   // wall face
@@ -190,12 +225,12 @@ __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, c
             if (!g.per[b] && ia[b] == g.n[b] - 1) sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
             // skew advection, b != a
             const int ibn = wrap_next(ia[b], g.n[b]);
-            const double mph = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[b], b, hi, ibn) : 0.0;
+            const double mph = hi >= 0 ? mflux_mix<DIM>(g, mx, u.a[b], b, hi, ibn) : 0.0;
             const int hiam = hi >= 0 ? nb_lo(g, hi, ia[a], a) : -1;   // c + e_b - e_a
-            const double mpha = hi >= 0 ? mflux<DIM>(g, k, phi, mu, u.a[b], b, hiam, ibn) : 0.0;
+            const double mpha = hi >= 0 ? mflux_mix<DIM>(g, mx, u.a[b], b, hiam, ibn) : 0.0;
             const double mp = 0.5 * (mph + mpha);
-            const double mm = 0.5 * (mflux<DIM>(g, k, phi, mu, u.a[b], b, c, ia[b]) +
-                                     mflux<DIM>(g, k, phi, mu, u.a[b], b, cam, ia[b]));
+            const double mm = 0.5 * (mflux_mix<DIM>(g, mx, u.a[b], b, c, ia[b]) +
+                                     mflux_mix<DIM>(g, mx, u.a[b], b, cam, ia[b]));
             const double uc = ua[c];
             const double up = hi >= 0 ? ua[hi] : -uc;
             const double um = lo >= 0 ? ua[lo] : -uc;
@@ -203,7 +238,7 @@ __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, c
         }
     }
     nadv *= 0.5 * k.ih;
-    const double st = (k.inv_We / k.Cn) * (0.5 * (phi[c] + phi[cam])) * ((mu[c] - mu[cam]) * k.ih);
+    const double st = mx.capillary(c, cam);
     double f = (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
     if (a == 1 && k.inv_Fr != 0.0) f -= rf_new * k.inv_Fr;     // g_hat = (0, -1, 0)
     s[c] = sd;
@@ -213,15 +248,23 @@ __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, c
     }
 }
 
+template <int DIM>
+__device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, const double *__restrict__ phi,
+                                      const double *__restrict__ phin, const double *__restrict__ mu, const U3 &u,
+                                      double *__restrict__ s, const W3 &cs, double *__restrict__ rhs,
+                                      double *__restrict__ ustar, int coef_only, int c) {
+    mom_setup_body<DIM>(g, k, a, mk_mix2(k, phi, phin, mu), u, s, cs, rhs, ustar, coef_only, c);
+}
+
 // S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new)
 // (part & kPCoef), rhs = -(We/dt) D ustar (part & kPRhs).
-template <int DIM>
-__device__ inline void p_setup_cell(const Geo &g, const StepConst &k, const double *__restrict__ phin, const U3 &us,
+template <int DIM, typename Mix>
+__device__ inline void p_setup_body(const Geo &g, const StepConst &k, const Mix &mx, const U3 &us,
                                     double *__restrict__ s, const W3 &cs, double *__restrict__ rhs, int part, int c) {
     int i, j, kk;
     if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
     const int ia[3] = {i, j, kk};
-    const double rc = k.alpha * pullback(phin[c]) + k.beta;
+    const double rc = (part & kPCoef) ? mx.rho_new(c) : 0.0;
     double div = 0.0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
@@ -229,7 +272,7 @@ __device__ inline void p_setup_cell(const Geo &g, const StepConst &k, const doub
         const int hi = nb_hi(g, c, ia[b], b);
         if (part & kPCoef) {
             if (lo >= 0) {
-                const double rl = k.alpha * pullback(phin[lo]) + k.beta;
+                const double rl = mx.rho_new(lo);
                 cs.a[b][c] = 1.0 / (0.5 * (rc + rl)) * k.ih2;
             } else {
                 cs.a[b][c] = 0.0;
@@ -243,26 +286,37 @@ __device__ inline void p_setup_cell(const Geo &g, const StepConst &k, const doub
     if (part & kPRhs) rhs[c] = -(k.We / k.dt) * (div * k.ih);
 }
 
-// S9: u = ustar - (dt/We) G p / rho_f; phi = phi_new
 template <int DIM>
-__device__ inline void project_cell(const Geo &g, const StepConst &k, const double *__restrict__ phin, const U3 &us,
-                                    const double *__restrict__ p, double *__restrict__ phi, const W3 &u, int c) {
+__device__ inline void p_setup_cell(const Geo &g, const StepConst &k, const double *__restrict__ phin, const U3 &us,
+                                    double *__restrict__ s, const W3 &cs, double *__restrict__ rhs, int part, int c) {
+    p_setup_body<DIM>(g, k, mk_mix2(k, phin, phin, phin), us, s, cs, rhs, part, c);
+}
+
+// S9: u = ustar - (dt/We) G p / rho_f; phi = phi_new
+template <int DIM, typename Mix>
+__device__ inline void project_body(const Geo &g, const StepConst &k, const Mix &mx, const U3 &us,
+                                    const double *__restrict__ p, const W3 &u, int c) {
     int i, j, kk;
     if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
     const int ia[3] = {i, j, kk};
-    const double pn = phin[c];
-    const double rc = k.alpha * pullback(pn) + k.beta;
+    const double rc = mx.rho_new(c);
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const int lo = nb_lo(g, c, ia[a], a);
         double v = 0.0;
         if (lo >= 0) {
-            const double rf = 0.5 * (rc + (k.alpha * pullback(phin[lo]) + k.beta));
+            const double rf = 0.5 * (rc + mx.rho_new(lo));
             v = us.a[a][c] - (k.dt * k.inv_We) * ((p[c] - p[lo]) * k.ih) / rf;
         }
         u.a[a][c] = v;
     }
-    phi[c] = pn;
+}
+
+template <int DIM>
+__device__ inline void project_cell(const Geo &g, const StepConst &k, const double *__restrict__ phin, const U3 &us,
+                                    const double *__restrict__ p, double *__restrict__ phi, const W3 &u, int c) {
+    project_body<DIM>(g, k, mk_mix2(k, phin, phin, phin), us, p, u, c);
+    phi[c] = phin[c];
 }
 
 }  // namespace chns

@@ -1,0 +1,143 @@
+"""Three-phase step (nphases = 3) on the GPU against the three-phase oracle
+(oracle/ternary.py), element by element, and its invariants at the full
+128^3 configuration.
+
+Bar: relative max-norm <= 1e-9 after 100 steps in FP64 (the stated target);
+1e-5 for the precision form (FP32 multigrid under FP64 refinement).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import MACGrid
+from oracle import ternary as T
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _lib():
+    import paper_2009_06628_amd as P
+    return P
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def run_gpu(prob, steps, precision=0):
+    P = _lib()
+    g = P.grid_for_problem(prob, precision)
+    st = g.new_state(W.initial_state(prob))
+    stats = g.step(st, steps)
+    torch.cuda.synchronize()
+    return g, st, stats
+
+
+def run_oracle(prob, steps):
+    g = MACGrid(prob.n, prob.h, prob.periodic)
+    prm = T.Params3.from_props(prob.props)
+    st = W.initial_state(prob)
+    for _ in range(steps):
+        st = T.step3(g, st, prm)
+    return g, st, prm
+
+
+def compare(sg, so, dim):
+    errs = {"phi1": relerr(to_np(sg["phi"][0]), so["phi"][0]), "phi2": relerr(to_np(sg["phi"][1]), so["phi"][1]),
+            "mu1": relerr(to_np(sg["mu"][0]), so["mu"][0]), "mu2": relerr(to_np(sg["mu"][1]), so["mu"][1])}
+    for a in range(dim):
+        errs["u%d" % a] = relerr(to_np(sg["u"][a]), so["u"][a])
+    pg = to_np(sg["p"])
+    errs["p"] = relerr(pg - pg.mean(), so["p"] - so["p"].mean())
+    return errs
+
+
+CASES = {
+    "drops2d_periodic": lambda: W.ternary_problem(
+        (64, 64), "ternary_drops", {"seed": 21, "count": 3, "rmin": 0.08, "rmax": 0.14, "gap": 0.08,
+                                    "velocity": "stream", "vseed": 7, "vamp": 0.1}, steps=100),
+    "drops2d_walls_gravity": lambda: W.ternary_problem(
+        (48, 64), "ternary_drops", {"seed": 22, "count": 2, "rmin": 0.1, "rmax": 0.15, "gap": 0.08,
+                                    "velocity": "stream", "vseed": 8, "vamp": 0.1},
+        bc=(W.PERIODIC, W.WALL), inv_Fr=1.0, rho3=(3.0, 0.2, 1.0), steps=100),
+    "drops3d_32": lambda: W.ternary_drops3d(32, steps=100),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ternary_fp64_matches_oracle_100_steps(case):
+    prob = CASES[case]()
+    print(f"ternary parity case {case} n={prob.n} steps={prob.steps}", flush=True)
+    g, sg, stats = run_gpu(prob, prob.steps)
+    og, so, prm = run_oracle(prob, prob.steps)
+    errs = compare(sg, so, prob.dim)
+    print(case, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= 1e-9, errs
+    d = T.diagnostics3(og, so, prm)
+    for i in range(3):
+        assert abs(stats["mass_phase"][i] - d["mass%d" % (i + 1)]) <= 1e-12 * d["mass%d" % (i + 1)]
+    assert abs(stats["energy"] - d["energy"]) <= 1e-10 * abs(d["energy"])
+
+
+def test_ternary_precision_form_matches_oracle():
+    prob = W.ternary_drops3d(32, steps=20, **W.PRECISION_FORM_TOLERANCES)
+    P = _lib()
+    g, sg, _ = run_gpu(prob, prob.steps, precision=P.CHNS_FP32_REFINE)
+    _, so, _ = run_oracle(W.ternary_drops3d(32, steps=20), prob.steps)
+    errs = compare(sg, so, 3)
+    print({k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+
+
+def test_third_phase_absent_gpu_matches_binary_gpu():
+    """c_3 = 0: the three-phase kernels reproduce the two-phase kernels'
+    step (phase 1 as phi, 1/We = sigma_12) and keep phase 3 absent."""
+    P = _lib()
+    prob3 = W.ternary_problem((64, 64), "ternary_pair",
+                              {"inside": 1, "outside": 0, "centre": (0.5, 0.45), "radius": 0.22,
+                               "velocity": "stream", "vseed": 4, "vamp": 0.2},
+                              bc=(W.PERIODIC, W.WALL), rho3=(1.0, 0.1, 7.0), eta3=(1.0, 0.2, 3.0),
+                              sigma3=(1.0 / 1.3, 0.9, 1.1), We=1.3, inv_Fr=1.0, steps=20)
+    g3, s3, _ = run_gpu(prob3, prob3.steps)
+    prob2 = W.Problem("binary", prob3.n, prob3.h, prob3.bc,
+                      W.Props(rho_minus=0.1, eta_minus=0.2, Re=prob3.props.Re, We=1.3, Cn=prob3.props.Cn,
+                              Pe=prob3.props.Pe, inv_Fr=1.0, dt=prob3.props.dt), 20, "drop", {})
+    g2 = P.grid_for_problem(prob2)
+    init = W.initial_state(prob3)
+    s2 = g2.new_state({"phi": init["phi"][0], "u": init["u"], "p": init["p"]})
+    g2.step(s2, 20)
+    torch.cuda.synchronize()
+    assert relerr(to_np(s3["phi"][0]), to_np(s2["phi"])) <= 1e-12
+    p3 = -1.0 - to_np(s3["phi"][0]) - to_np(s3["phi"][1])
+    assert np.abs(p3 + 1.0).max() <= 1e-14
+    for a in range(2):
+        assert relerr(to_np(s3["u"][a]), to_np(s2["u"][a])) <= 1e-10
+    assert relerr(to_np(s3["p"]), to_np(s2["p"])) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_ternary_full_size_invariants(precision):
+    """The 128^3 three-phase drop configuration in the launch shape the
+    benchmark times: 5 steps conserve every phase mass to 1e-12 and leave a
+    divergence-free velocity (the oracle's 1e-12 divergence bar scaled by
+    the pressure tolerance)."""
+    P = _lib()
+    tol = W.PRECISION_FORM_TOLERANCES if precision else {}
+    prob = W.ternary_drops3d(128, steps=5, **tol)
+    print(f"ternary full size precision={precision}", flush=True)
+    g = P.grid_for_problem(prob, precision)
+    st = g.new_state(W.initial_state(prob))
+    s0 = g.step(st, 0)
+    s1 = g.step(st, 5)
+    for i in range(3):
+        assert abs(s1["mass_phase"][i] - s0["mass_phase"][i]) <= 1e-12 * s0["mass_phase"][i]
+    assert s1["umax"] > 1e-3
+    assert s1["divmax"] * prob.h <= (1e-5 if precision else 1e-8) * s1["umax"]
+    assert s1["unconverged"] == 0
