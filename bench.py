@@ -1,32 +1,41 @@
 #!/usr/bin/env python3
 """Benchmark of the split CHNS time step on one MI355X.
 
-Workload: the 2D rising bubble, 256 x 512 cells on the non-dimensional box
-[0,2] x [0,4], periodic sides, no-slip top / bottom, density ratio 1000,
-viscosity ratio 100, Eo = We = 10, Ar = Re = 35, Fr = 1, Cn = 1.5 h, FP64.
-A step is one full pass S1..S9 (CH solve, momentum predictor, pressure
-projection).  Inputs are synthetic (seeded tanh bubble, fluid at rest) and
-already resident in device memory when the timed region starts.
+Headline workload: the three-phase drops, 128^3 periodic cells (8 drops of
+each of two phases in a carrier phase, seeded radii 0.05-0.12, pairwise
+surface tensions U[0.5, 1.5], densities 100 / 10 / 1, divergence-free
+velocity perturbation of amplitude 1e-2), in two arithmetic forms on the same
+input:
+  fp64         FP64 throughout, at the solver tolerances the oracle parity
+               tests use (CH 1e-15, momentum 1e-13, pressure 1e-12)
+  fp32_refine  the precision form: FP32 multigrid preconditioner under FP64
+               CG and FP64 iterative refinement, at its own tolerances
+               (1e-10 / 1e-10 / 1e-9)
+A step is one full pass T1..T9 (two CH solves, three momentum components,
+pressure projection).  Inputs are synthetic and already resident in device
+memory when the timed region starts.  `value` is the precision form's
+throughput; the FP64 form's and the ratio are in `config`.
 
 Secondary measurements (key "secondary", each on its own workload, skipped
 with --no-extras):
-  precision_form  3D periodic drops (128^3, 16 drops, ratios 100): FP64 vs
-                  FP32 multigrid under FP64 refinement, throughput ratio and
-                  the state difference after the timed steps
-  batched         ensemble of 512 oscillating drops (64^2 .. 256^2), FP32 +
-                  refinement, autotuned form and launch shape; eager steps and
-                  hipGraph-captured steps
-  adjoint         oscillating drop 128^2, FP64: backward (checkpoint every 20
-                  steps, segment recompute, adjoint steps) vs forward time
+  bubble        2D rising bubble 256 x 512, FP64, its dominant kernel class
+  hbm_sweeps    one pressure solve on a 512^3 (FP64) and an 8192^2 (FP64)
+                grid: per kernel class achieved GB/s where every level-0
+                sweep touches far more than the 256 MB Infinity Cache
+  batched       ensemble of 512 oscillating drops (64^2 .. 256^2), FP32 +
+                refinement, autotuned form; eager and hipGraph-captured steps
+  adjoint       oscillating drop 128^2, FP64: checkpointed backward vs
+                forward time
 
 Prints one JSON line:
   value         grid cell-updates/s = cells * steps / wall-time of the timed
-                region (host-side clock after a device synchronisation on
-                both sides; hipEvents on the library stream agree)
+                region (host clock after a device synchronisation on both
+                sides; hipEvents on the library stream agree)
   roofline      the kernel class with the largest share of device time in a
-                separate instrumented pass (hipEvent pair around every launch
-                on the library stream): algorithmic bytes / kernel time vs
-                the 8 TB/s HBM peak
+                separate instrumented pass of the headline form (hipEvent pair
+                recorded by the dispatch of every launch on the library
+                stream): algorithmic bytes / kernel time vs the 8 TB/s HBM peak;
+                traffic = the committed FETCH_SIZE + WRITE_SIZE counter record
   cpu_baseline  the CPU oracle (numpy / scipy, FP64, one thread) on a bounded
                 sample of the same workload
 """
@@ -35,6 +44,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -44,32 +54,43 @@ if ROOT not in sys.path:
 
 METRIC = "grid cell-updates/s per time step (FP64 vs FP32+refine), %HBM roofline, adjoint/fwd"
 HBM_PEAK_GBS = 8000.0
+EXTRAS = ("bubble", "hbm_sweeps", "batched", "adjoint")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-headline", action="store_true", help="skip the headline legs (profiling runs of extras)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=20)
-    ap.add_argument("--extras", default="precision_form,batched,adjoint",
+    ap.add_argument("--extras", default=",".join(EXTRAS),
                     help="comma-separated secondary measurements to run (subset of the default)")
+    ap.add_argument("--serial-components", action="store_true",
+                    help="run the momentum components one after another on the grid's stream (kernel profiles)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for the HBM byte counters)")
+    ap.add_argument("--hbm-shapes", default="512^3,8192^2", help="grids of the hbm_sweeps measurement")
+    ap.add_argument("--traffic-from", nargs="+", metavar="WORKLOAD=FETCH_CSV,WRITE_CSV",
+                    help="no GPU run: build profiles/traffic.json from rocprofv3 --pmc counter CSVs of bench.py "
+                         "runs (one FETCH_SIZE and one WRITE_SIZE pass per workload, each with --calibrate-copy)")
+    ap.add_argument("--durations-from", nargs="+", metavar="WORKLOAD=KERNEL_TRACE_CSV",
+                    help="no GPU run: print per kernel class dispatch counts and mean durations from rocprofv3 "
+                         "--kernel-trace CSVs, with the class filters of --traffic-from")
     return ap.parse_args()
 
 
-def recorded_traffic(kernel_class):
-    """HBM bytes per launch of a kernel class (dispatch-weighted over its
-    kernels) from the committed counter record (two rocprofv3 --pmc passes,
-    FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); None if
-    the record holds no such class or the kernels' sources changed since the
-    counters were taken."""
+def recorded_traffic(workload, kernel_class):
+    """HBM bytes per launch of a kernel class on a workload (dispatch-weighted
+    over its kernels) from the committed counter record (two rocprofv3 --pmc
+    passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size);
+    None if the record holds no such class or the sources of the library
+    changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -78,11 +99,145 @@ def recorded_traffic(kernel_class):
         if h != rec["sources_sha256"]:
             return None
         for r in rec["records"]:
-            if r["kernel_class"] == kernel_class:
+            if r["workload"] == workload and r["kernel_class"] == kernel_class:
                 return r["traffic_bytes_per_launch"]
         return None
     except (OSError, ValueError, KeyError):
         return None
+
+
+# Kernel classes of the library's per-kernel timing, by kernel name (the
+# template arguments after the name are matched by the workload filters).
+KERNEL_CLASSES = {
+    "smooth": ("k_presmooth_pair", "k_presmooth", "k_gs_color"),
+    "residual": ("k_residual",),
+    "restrict": ("k_restrict3_pair", "k_restrict"),
+    "prolong": ("k_prolong_add3",),
+    "coarse_solve": ("k_vcycle_lds", "k_vcycle_block"),
+    "mg_down": ("k_down_tile2", "k_down_tile2_cg"),
+    "mg_up": ("k_up_tile2", "k_up_tile2_cg"),
+    "pcg_apply": ("k_pcg_apply3_march", "k_pcg_apply_slot", "k_pcg_ch_lap", "k_pcg_ch_apply"),
+    "pcg_update": ("k_pcg_update", "k_pcg_fin_rr"),
+    "pcg_dot": ("k_pcg_rz",),
+}
+
+# Which dispatches of a profiled bench.py run belong to a workload: the
+# headline legs run in one process and differ in the multigrid precision
+# (template arguments); the other workloads are profiled in runs of their own.
+WORKLOAD_FILTERS = {
+    "ternary_drops3d_128^3_fp32_refine": lambda args: "float" in args,
+    "ternary_drops3d_128^3_fp64": lambda args: bool(args) and "float" not in args,
+    "rising_bubble_256x512_fp64": lambda args: True,
+    "pressure_512^3_fp64": lambda args: True,
+    "pressure_8192^2_fp64": lambda args: True,
+}
+TRAFFIC_SOURCES = ["paper_2009_06628_amd/csrc/mg.hip", "paper_2009_06628_amd/csrc/mgdev.h",
+                   "paper_2009_06628_amd/csrc/common.h", "paper_2009_06628_amd/csrc/tile2d.h"]
+
+
+def _class_of(kernel_name):
+    """(class, template arguments) of a rocprofv3 kernel name, or None.  The
+    template arguments are the text of the first <...> after the name (empty
+    for a kernel that is not a template)."""
+    name = kernel_name.strip()
+    head = name.split("(")[0]
+    base, _, rest = head.partition("<")
+    base = base.strip().split()[-1].split("::")[-1] if base.strip() else ""
+    depth, targs = 1, ""
+    for ch in rest:
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+            if depth == 0:
+                break
+        targs += ch
+    for cls, names in KERNEL_CLASSES.items():
+        if base in names:
+            return cls, targs
+    return None
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _counter_rows(path, counter):
+    """(kernel name, value in bytes) per dispatch of a --pmc CSV in dispatch
+    order (the counter is reported in KiB)."""
+    rows = []
+    for r in _read_csv(path):
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+    rows.sort()
+    return [(k, v) for (_, k, v) in rows]
+
+
+def build_traffic(specs):
+    """profiles/traffic.json from FETCH_SIZE / WRITE_SIZE CSVs.  Each pass ran
+    bench.py with --calibrate-copy: the copy of 256 MiB (read and write) that
+    starts the run fixes the scale of each counter."""
+    import hashlib
+    records = []
+    scales = {}
+    for spec in specs:
+        workload, files = spec.split("=", 1)
+        fetch_csv, write_csv = files.split(",")
+        filt = WORKLOAD_FILTERS[workload]
+        per = {}
+        for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+            rows = _counter_rows(path, counter)
+            # the calibration copy is the run's first buffer copy (--calibrate-copy
+            # issues it before anything else touches the device)
+            copy = [v for (k, v) in rows if "copyBuffer" in k]
+            ref = 256.0 * 1024 * 1024
+            scale = ref / copy[0] if copy and copy[0] > 0 else 1.0
+            scales.setdefault(workload, {})[counter] = round(scale, 5)
+            for k, v in rows:
+                c = _class_of(k)
+                if c is None or not filt(c[1]):
+                    continue
+                d = per.setdefault(c[0], {"kernels": set(), "FETCH_SIZE": [], "WRITE_SIZE": []})
+                d["kernels"].add(k.split("(")[0].strip())
+                d[counter].append(v * scale)
+        for cls, d in sorted(per.items()):
+            n = min(len(d["FETCH_SIZE"]), len(d["WRITE_SIZE"]))
+            if n == 0:
+                continue
+            fetch = sum(d["FETCH_SIZE"]) / len(d["FETCH_SIZE"])
+            write = sum(d["WRITE_SIZE"]) / len(d["WRITE_SIZE"])
+            records.append({"workload": workload, "kernel_class": cls, "kernels": sorted(d["kernels"]),
+                            "dispatches": n, "fetch_bytes_per_dispatch": round(fetch, 1),
+                            "write_bytes_per_dispatch": round(write, 1),
+                            "traffic_bytes_per_launch": round(fetch + write, 1)})
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in TRAFFIC_SOURCES)).hexdigest()
+    rec = {"counter_scales": scales, "records": records, "sources": TRAFFIC_SOURCES, "sources_sha256": h}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({"written": "profiles/traffic.json", "records": len(records), "scales": scales}))
+
+
+def print_durations(specs):
+    """Per kernel class: dispatches and mean duration (us) from --kernel-trace
+    CSVs, with the workload filters."""
+    for spec in specs:
+        workload, path = spec.split("=", 1)
+        filt = WORKLOAD_FILTERS[workload]
+        per = {}
+        for r in _read_csv(path):
+            c = _class_of(r["Kernel_Name"])
+            if c is None or not filt(c[1]):
+                continue
+            dur = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3
+            d = per.setdefault(c[0], [0, 0.0])
+            d[0] += 1
+            d[1] += dur
+        print(json.dumps({"workload": workload,
+                          "classes": {k: {"dispatches": v[0], "mean_us": round(v[1] / v[0], 3),
+                                          "total_ms": round(v[1] / 1e3, 3)} for k, v in sorted(per.items())}}))
 
 
 def _sync():
@@ -90,32 +245,111 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def bench_precision_form(P, W, steps):
-    """3D drops: FP64 vs FP32+refinement on the same input."""
+def roofline_of(kernels, steps, workload):
+    """Roofline object of the kernel class with the most device time."""
+    dom = max(kernels, key=lambda r: r["ms"])
+    achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": recorded_traffic(workload, dom["name"]),
+            "kernel": dom["name"], "avg_us": round(dom["ms"] * 1e3 / dom["launches"], 3),
+            "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
+            "launches_per_step": round(dom["launches"] / steps, 1),
+            "share_of_kernel_time": round(dom["ms"] / sum(k["ms"] for k in kernels), 4)}
+
+
+def kernel_table(kernels):
+    return [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),
+             "GBs": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)} for k in sorted(kernels, key=lambda r: -r["ms"])]
+
+
+def timed_run(P, prob, precision, warmup, steps, serial):
+    """Warm-up, then `steps` timed steps; returns the grid, the state and the
+    timings (wall clock and hipEvents on the library stream)."""
     import torch
-    prob = W.drops3d(128, steps=steps, **W.PRECISION_FORM_TOLERANCES)
-    init = W.initial_state(prob)
-    out = {"workload": "drops3d_128^3", "cells": prob.cells, "steps": steps}
-    states = {}
-    for name, prec in (("fp64", P.CHNS_FP64), ("fp32_refine", P.CHNS_FP32_REFINE)):
-        g = P.grid_for_problem(prob, prec, device="cuda:0")
-        st = g.new_state(init)
-        g.step(st, 2, stats=False)
+    import workloads as W
+    g = P.grid_for_problem(prob, precision, device="cuda:0")
+    if serial:
+        g.set_option(P.CHNS_OPT_SERIAL_COMPONENTS, 1)
+    st = g.new_state(W.initial_state(prob))
+    if warmup:
+        g.step(st, warmup, stats=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(g.stream)
+    g.step(st, steps, stats=False)
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return g, st, {"wall": wall, "event_s": e0.elapsed_time(e1) / 1e3}
+
+
+def instrumented(g, st, steps, workload):
+    g.set_timing(True)
+    g.step(st, steps, stats=False)
+    _sync()
+    kernels = g.get_timing()
+    g.set_timing(False)
+    return kernels, roofline_of(kernels, steps, workload)
+
+
+def bench_bubble(P, W, steps, warmup, profile_steps, serial):
+    """2D rising bubble, FP64 (latency-bound: ~30 MB working set)."""
+    prob = W.rising_bubble(256, steps=2000)
+    g, st, t = timed_run(P, prob, P.CHNS_FP64, warmup, steps, serial)
+    stats = g.step(st, 1)
+    out = {"workload": "rising_bubble_256x512_fp64", "cells": prob.cells, "steps": steps,
+           "value": round(prob.cells * steps / t["wall"], 1), "ms_per_step": round(t["wall"] / steps * 1e3, 4),
+           "event_seconds": round(t["event_s"], 4),
+           "iters_last_step": {"ch": stats["iters_ch"], "mom": stats["iters_mom"], "p": stats["iters_p"]}}
+    if profile_steps:
+        kernels, roof = instrumented(g, st, profile_steps, out["workload"])
+        out["roofline"] = roof
+        out["kernels"] = kernel_table(kernels)[:8]
+    return out
+
+
+def bench_hbm_sweeps(P, W, hbm_shapes):
+    """One pressure solve (rtol 1e-10) on grids whose level-0 arrays are far
+    larger than the Infinity Cache: 512^3 FP64 (1.07 GB per array) and
+    8192^2 FP64 (0.54 GB per array); density ratio 10 drop.  Per kernel class:
+    launches, ms, achieved GB/s (algorithmic bytes / kernel time)."""
+    import numpy as np
+    import torch
+    out = {}
+    shapes = {"512^3": (512, 512, 512), "8192^2": (8192, 8192)}
+    for key in [x for x in hbm_shapes.split(",") if x]:
+        n = shapes[key]
+        name = "pressure_%s_fp64" % key
+        h = 1.0 / n[0]
+        g = P.create_grid(n, h, ("periodic",) * len(n), device="cuda:0")
+        dev = torch.device("cuda:0")
+        axes = [(torch.arange(m, dtype=torch.float64, device=dev) + 0.5) * h for m in reversed(n)]
+        X = torch.meshgrid(*axes, indexing="ij")
+        r = torch.sqrt(sum((x - 0.5) ** 2 for x in X))
+        del X
+        phi = torch.tanh((r - 0.25) / (2 ** 0.5 * 1.5 * h))
+        del r
+        rho = 0.55 + 0.45 * phi
+        gen = torch.Generator(device=dev).manual_seed(7)
+        rhs = torch.randn(rho.shape, dtype=torch.float64, device=dev, generator=gen)
+        del phi
+        p = torch.zeros_like(rho)
+        g.solve_pressure(rho, rhs, p, rtol=1e-10, max_iter=200)    # warm-up (first-use costs)
+        p.zero_()
         _sync()
-        t0 = time.perf_counter()
-        g.step(st, steps, stats=False)
+        g.set_timing(True)
+        res = g.solve_pressure(rho, rhs, p, rtol=1e-10, max_iter=200)
         _sync()
-        dt = time.perf_counter() - t0
-        out[name] = {"value": round(prob.cells * steps / dt, 1), "ms_per_step": round(dt / steps * 1e3, 3)}
-        states[name] = st
-        del g
-    out["speedup"] = round(out["fp32_refine"]["value"] / out["fp64"]["value"], 3)
-    a, b = states["fp32_refine"], states["fp64"]
-    err = float((a["phi"] - b["phi"]).abs().max() / b["phi"].abs().max())
-    for d in range(3):
-        err = max(err, float((a["u"][d] - b["u"][d]).abs().max() / b["u"][d].abs().max().clamp_min(1e-300)))
-    out["max_rel_diff_vs_fp64"] = err
-    out["tolerances"] = W.PRECISION_FORM_TOLERANCES
+        kernels = g.get_timing()
+        g.set_timing(False)
+        cells = int(np.prod(n))
+        out[name] = {"cells": cells, "iters": res["iters"], "rel_res": res["rel_res"],
+                     "bytes_per_array": 8 * cells,
+                     "kernels": [dict(k, traffic=recorded_traffic(name, k["name"])) for k in kernel_table(kernels)]}
+        del g, rho, rhs, p
+        torch.cuda.empty_cache()
     return out
 
 
@@ -184,29 +418,48 @@ def bench_adjoint(P, W):
             "dL_dsigma": float(sigma.grad), "dL_dM": float(mob.grad)}
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(prob, steps):
-    """Oracle on the host: `steps` steps of the same workload, one thread."""
+    """The three-phase oracle on the host: `steps` steps of the same 128^3
+    workload from its initial state, one thread (no warm-up step: one step
+    takes about a minute)."""
     from threadpoolctl import threadpool_limits
 
     import workloads as W
-    from oracle import MACGrid, Params, step as ostep
+    from oracle import MACGrid
+    from oracle import ternary as T
 
     g = MACGrid(prob.n, prob.h, prob.periodic)
-    prm = Params.from_props(prob.props)
+    prm = T.Params3.from_props(prob.props)
     st = W.initial_state(prob)
     with threadpool_limits(limits=1):
-        st = ostep(g, st, prm)          # warm-up step (not timed)
         t0 = time.perf_counter()
         for _ in range(steps):
-            st = ostep(g, st, prm)
+            st = T.step3(g, st, prm)
         dt = time.perf_counter() - t0
-    return {"value": prob.cells * steps / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d steps of the %dx%d rising bubble after one warm-up step (%.1f s)"
-                      % (steps, prob.n[0], prob.n[1], dt)}
+    return {"value": round(prob.cells * steps / dt, 1), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d step(s) of the %dx%dx%d three-phase drops from the initial state, FP64, one thread "
+                      "(%.1f s; host CPU: %s, %d logical CPUs)"
+                      % (steps, prob.n[0], prob.n[1], prob.n[2], dt, _cpu_model(), os.cpu_count() or 0)}
 
 
 def main():
     args = parse()
+    if args.traffic_from or args.durations_from:
+        if args.traffic_from:
+            build_traffic(args.traffic_from)
+        if args.durations_from:
+            print_durations(args.durations_from)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -218,6 +471,12 @@ def main():
     import paper_2009_06628_amd as P
     import workloads as W
 
+    extras = [e for e in args.extras.split(",") if e] if not args.no_extras else []
+    unknown = set(extras) - set(EXTRAS)
+    if unknown:
+        print("unknown --extras entries: %s" % ", ".join(sorted(unknown)), file=sys.stderr)
+        sys.exit(2)
+
     if args.calibrate_copy:
         # reference kernel for the HBM byte counters: reads and writes 256 MiB
         a = torch.empty(32 << 20, dtype=torch.float64, device="cuda:0").fill_(1.0)
@@ -226,86 +485,69 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    prob = W.rising_bubble(256, steps=2000)
-    g = P.grid_for_problem(prob, device="cuda:0")
-    st = g.new_state(W.initial_state(prob))
-    stream = g.stream
+    workload = "ternary_drops3d_128^3"
+    out = {"metric": METRIC, "value": None, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic", "config": None, "roofline": None,
+           "cpu_baseline": None}
+    prob = None
+    if not args.no_headline:
+        prob = W.ternary_drops3d(128, steps=500)
+        legs = {}
+        states = {}
+        for name, prec, pr in (("fp64", P.CHNS_FP64, prob),
+                               ("fp32_refine", P.CHNS_FP32_REFINE,
+                                W.ternary_drops3d(128, steps=500, **W.PRECISION_FORM_TOLERANCES))):
+            g, st, t = timed_run(P, pr, prec, args.warmup, args.steps, args.serial_components)
+            stats = g.step(st, 1)     # outside the timed region: solver statistics and diagnostics
+            legs[name] = {"value": round(prob.cells * args.steps / t["wall"], 1),
+                          "ms_per_step": round(t["wall"] / args.steps * 1e3, 4),
+                          "event_seconds": round(t["event_s"], 4),
+                          "tolerances": {"ch": pr.props.rtol_ch, "mom": pr.props.rtol_mom, "p": pr.props.rtol_p},
+                          "iters_last_step": {"ch": stats["iters_ch"], "mom": stats["iters_mom"],
+                                              "p": stats["iters_p"]},
+                          "mass_phase": stats["mass_phase"], "energy": stats["energy"]}
+            if not args.no_profile and args.profile_steps > 0:
+                kernels, roof = instrumented(g, st, args.profile_steps, workload + "_" + name)
+                legs[name]["roofline"] = roof
+                legs[name]["kernels"] = kernel_table(kernels)
+            states[name] = st
+            del g
+            torch.cuda.empty_cache()
+        a, b = states["fp32_refine"], states["fp64"]
+        diff = 0.0
+        for i in range(2):
+            diff = max(diff, float((a["phi"][i] - b["phi"][i]).abs().max() / b["phi"][i].abs().max()))
+        for d in range(3):
+            diff = max(diff, float((a["u"][d] - b["u"][d]).abs().max() / b["u"][d].abs().max().clamp_min(1e-300)))
+        del states, a, b
+        torch.cuda.empty_cache()
+        f64, f32 = legs["fp64"], legs["fp32_refine"]
+        out.update(value=f32["value"], ms_per_step=f32["ms_per_step"], roofline=f32.pop("roofline", None))
+        out["config"] = {"workload": workload, "grid": list(prob.n), "cells": prob.cells, "bc": list(prob.bc),
+                         "nphases": 3, "densities": list(prob.props.rho3), "viscosities": list(prob.props.eta3),
+                         "surface_tensions": [round(x, 6) for x in prob.props.sigma3], "Re": prob.props.Re,
+                         "dt": prob.props.dt, "form": "fp32_refine",
+                         "fp32_refine": f32, "fp64": f64,
+                         "speedup_fp32_refine_vs_fp64": round(f32["value"] / f64["value"], 3),
+                         "max_rel_state_diff_fp32_refine_vs_fp64": diff,
+                         "serial_components": bool(args.serial_components)}
+        if not args.no_cpu_baseline and args.cpu_steps > 0:
+            out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps)
 
-    if args.warmup:
-        g.step(st, args.warmup, stats=False)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    g.step(st, args.steps, stats=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_s = e0.elapsed_time(e1) / 1e3
-    value = prob.cells * args.steps / wall
-    stats = g.step(st, 1)     # one more step, outside the timed region: solver stats + diagnostics
-
-    roof = None
-    kernels = None
-    if not args.no_profile and args.profile_steps > 0:
-        g.set_timing(True)
-        g.step(st, args.profile_steps, stats=False)
-        torch.cuda.synchronize()
-        kernels = g.get_timing()
-        g.set_timing(False)
-        dom = max(kernels, key=lambda r: r["ms"])
-        achieved = dom["bytes"] / (dom["ms"] / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": recorded_traffic(dom["name"]),
-                "kernel": dom["name"], "avg_us": round(dom["ms"] * 1e3 / dom["launches"], 3),
-                "bytes_per_launch": round(dom["bytes"] / dom["launches"], 1),
-                "launches_per_step": round(dom["launches"] / args.profile_steps, 1),
-                "share_of_kernel_time": round(dom["ms"] / sum(k["ms"] for k in kernels), 4)}
-        if dom["name"] == "coarse_solve":
-            roof["note"] = ("one-workgroup V-cycle of the levels of <= 2048 cells out of LDS: ~45 dependent "
-                            "LDS passes on one CU, latency-bound; its HBM bytes are the copy-in and the "
-                            "write-back of x")
-
-    cpu = None
-    if not args.no_cpu_baseline and args.cpu_steps > 0:
-        cpu = cpu_baseline(prob, args.cpu_steps)
-
-    secondary = None
-    extras = [e for e in args.extras.split(",") if e] if not args.no_extras else []
-    unknown = set(extras) - {"precision_form", "batched", "adjoint"}
-    if unknown:
-        print("unknown --extras entries: %s" % ", ".join(sorted(unknown)), file=sys.stderr)
-        sys.exit(2)
     if extras:
-        del g, st
         secondary = {}
-        runs = {"precision_form": lambda: bench_precision_form(P, W, args.extra_steps),
+        runs = {"bubble": lambda: bench_bubble(P, W, 2000 if args.steps >= 100 else args.steps, args.warmup,
+                                               args.profile_steps if not args.no_profile else 0,
+                                               args.serial_components),
+                "hbm_sweeps": lambda: bench_hbm_sweeps(P, W, args.hbm_shapes),
                 "batched": lambda: bench_batched(P, W, args.extra_steps),
                 "adjoint": lambda: bench_adjoint(P, W)}
-        for name in ("precision_form", "batched", "adjoint"):
+        for name in EXTRAS:
             if name in extras:
                 torch.cuda.empty_cache()
                 secondary[name] = runs[name]()
-
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "rising_bubble_256x512_fp64", "grid": list(prob.n), "cells": prob.cells,
-                   "bc": list(prob.bc), "density_ratio": 1000, "viscosity_ratio": 100, "We": prob.props.We,
-                   "Re": prob.props.Re, "dt": prob.props.dt, "event_seconds": round(ev_s, 4),
-                   "iters_last_step": {"ch": stats["iters_ch"], "mom": stats["iters_mom"], "p": stats["iters_p"]},
-                   "mass_minus": stats["mass_minus"], "energy": stats["energy"]},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "secondary": secondary,
-    }
-    if kernels is not None:
-        out["kernels"] = [{"name": k["name"], "launches": k["launches"], "ms": round(k["ms"], 3),
-                           "GBs": round(k["bytes"] / max(k["ms"], 1e-9) / 1e6, 1)} for k in
-                          sorted(kernels, key=lambda r: -r["ms"])]
+        out["secondary"] = secondary
     print(json.dumps(out), flush=True)
 
 

@@ -36,10 +36,10 @@
  * axis is diagonalised by an orthonormal DCT-II basis on a walled axis and
  * the real Fourier basis on a periodic one; the solve is one transform per
  * axis, a division by 1 - a lam + b lam^2, and the inverse transforms, as
- * FP64 matrix products by a tiled kernel on the grid's stream).  Setting
- * CHNS_CH_SOLVER=pcg in the environment before chns_create_grid selects
- * multigrid-preconditioned CG for S2 instead; larger grids and the batched
- * entry points always use it.
+ * FP64 matrix products by a tiled kernel on the grid's stream).
+ * chns_set_option(g, CHNS_OPT_CH_SOLVER, CHNS_CH_PCG) selects
+ * multigrid-preconditioned CG for S2 instead; larger grids and 3D batches
+ * always use it.
  *
  * Three-phase model (nphases = 3; the paper is two-phase, this extends its
  * binary free-energy density by the Boyer-Lapuerta construction): phases
@@ -205,9 +205,8 @@ int chns_set_properties(struct chns_grid *g, const chns_props *props);
  * it (solver statistics of the last step, diagnostics of the final state).
  * The momentum solves of the components and the pressure set-up run on
  * their own streams, driven by host threads of the call (serially on the
- * grid's stream while per-kernel timing is on, or with
- * CHNS_SERIAL_MOMENTUM=1 in the environment); the results do not depend on
- * which.
+ * grid's stream while per-kernel timing is on, or with the option
+ * CHNS_OPT_SERIAL_COMPONENTS set); the results do not depend on which.
  * Returns CHNS_ENOCONV if any solve of any step hit max_iter.            */
 int chns_step(struct chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats);
 
@@ -344,8 +343,8 @@ int chns_batch_workspace_size(int count, const chns_grid_desc *descs, size_t *by
  * 2D batches solve S2 directly, as single grids do: the problems of one
  * shape share their bases, and each solve is four batched transform
  * launches per shape plus a scaling launch.  Both forms (persistent,
- * tiled) use it.  CHNS_CH_SOLVER=pcg in the environment, 3D batches and
- * axes over 2048 cells keep multigrid-preconditioned CG for S2.  No device
+ * tiled) use it.  3D batches and axes over 2048 cells keep
+ * multigrid-preconditioned CG for S2.  No device
  * memory is allocated here or later.                                      */
 int chns_create_batch(int count, const chns_grid_desc *descs, const chns_props *props, void *workspace,
                       size_t bytes, void *hip_stream, struct chns_batch **out);
@@ -435,6 +434,21 @@ int chns_solve_pressure_noalloc(const chns_grid_desc *desc, const void *rho, con
                                 double rtol, int max_iter, void *hip_stream, chns_solve_stats *stats);
 /* Size in bytes of that array (CHNS_NOALLOC_SCRATCH_BYTES).              */
 size_t chns_solve_pressure_noalloc_capacity(void);
+
+/* Per-handle options (host state; take effect from the next call):
+ *   CHNS_OPT_CH_SOLVER          CHNS_CH_DIRECT (default where every axis has
+ *                               at most 2048 cells: the direct S2 solve) or
+ *                               CHNS_CH_PCG (multigrid-preconditioned CG);
+ *                               CHNS_EINVAL for DIRECT on larger grids;
+ *   CHNS_OPT_SERIAL_COMPONENTS  1: the momentum components of S7 and the S8
+ *                               set-up run one after another on the grid's
+ *                               stream (kernel profiles without overlap);
+ *                               0 (default): on their own streams.
+ * Results do not depend on CHNS_OPT_SERIAL_COMPONENTS; the two S2 solvers
+ * agree to the CH tolerance.                                              */
+enum { CHNS_OPT_CH_SOLVER = 1, CHNS_OPT_SERIAL_COMPONENTS = 2 };
+enum { CHNS_CH_DIRECT = 0, CHNS_CH_PCG = 1 };
+int chns_set_option(struct chns_grid *g, int option, int value);
 
 /* Release the handle (host metadata only; device memory is the caller's). */
 int chns_destroy_grid(struct chns_grid *g);

@@ -23,6 +23,8 @@ LIB_PATH = os.path.join(HERE, "libchns.so")
 CHNS_OK, CHNS_ENOCONV, CHNS_EINVAL, CHNS_ENOMEM, CHNS_EDEVICE, CHNS_ENONFINITE = 0, 1, -1, -2, -3, -4
 CHNS_BC_PERIODIC, CHNS_BC_WALL = 0, 1
 CHNS_FP64, CHNS_FP32_REFINE = 0, 1
+CHNS_OPT_CH_SOLVER, CHNS_OPT_SERIAL_COMPONENTS = 1, 2
+CHNS_CH_DIRECT, CHNS_CH_PCG = 0, 1
 
 
 class chns_grid_desc(ctypes.Structure):
@@ -134,6 +136,7 @@ EXPORTS = {
                                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
                                                    ctypes.POINTER(chns_solve_stats)]),
     "chns_solve_pressure_noalloc_capacity": (ctypes.c_size_t, []),
+    "chns_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "chns_destroy_grid": (ctypes.c_int, [ctypes.c_void_p]),
     "chns_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "chns_last_error": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -388,6 +391,12 @@ class Grid:
         rc = self._lib.chns_adjoint_step_recorded(self._h, ctypes.byref(cs), ctypes.byref(self._crec(rec)),
                                                   ctypes.byref(li), ctypes.byref(lo), grad)
         return _check(rc, "chns_adjoint_step_recorded", allow_noconv)
+
+    # -- options ---------------------------------------------------------------
+    def set_option(self, option: int, value: int) -> None:
+        """chns_set_option: CHNS_OPT_CH_SOLVER (CHNS_CH_DIRECT / CHNS_CH_PCG),
+        CHNS_OPT_SERIAL_COMPONENTS (0 / 1)."""
+        _check(self._lib.chns_set_option(self._h, int(option), int(value)), "chns_set_option")
 
     # -- per-kernel timing ------------------------------------------------------
     def set_timing(self, enable: bool) -> None:

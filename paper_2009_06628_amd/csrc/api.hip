@@ -365,15 +365,10 @@ int check_solve(const SolveOut &o, const char *what) {
     return CHNS_OK;
 }
 
-// CHNS_SERIAL_MOMENTUM=1 runs the momentum components one after another on
-// the handle's stream (per-kernel profiles without overlapping kernels).
-static bool serial_momentum() {
-    static const bool v = [] {
-        const char *e = getenv("CHNS_SERIAL_MOMENTUM");
-        return e && e[0] == '1';
-    }();
-    return v;
-}
+// CHNS_OPT_SERIAL_COMPONENTS = 1 runs the momentum components one after
+// another on the handle's stream (per-kernel profiles without overlapping
+// kernels).
+static bool serial_momentum(const chns_grid *g) { return g->serial_components != 0; }
 
 // S1..S8 of one step from (phi, u) with the pressure initial guess in pr:
 // phihat, mu, phi_new, ustar and p; solver statistics into last.
@@ -419,7 +414,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     // each solve is unchanged.  The pressure coefficients and hierarchy
     // (S8) need only phi_new: they are set up on a further stream and
     // thread meanwhile.
-    const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum();
+    const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum(g);
     Level<double> &P0 = g->pres.lev[0];
     double *pcs[3] = {P0.cs[0], P0.cs[1], P0.cs[2]};
     hipError_t ep = hipSuccess;
@@ -610,17 +605,15 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
         }
         g->mc_ready = 1;
     }
-    // direct CH solve unless CHNS_CH_SOLVER=pcg asks for MG-PCG
-    {
-        const char *cs = getenv("CHNS_CH_SOLVER");
-        if (g->spec.carved && !(cs && strcmp(cs, "pcg") == 0)) {
-            std::string err;
-            if (spectral_init(g->spec, desc->h, err)) {
-                spectral_release(g->spec);
-                release_streams(g);
-                delete g;
-                return fail(CHNS_EDEVICE, err);
-            }
+    // direct CH solve where the bases fit (chns_set_option can select MG-PCG)
+    g->serial_components = 0;
+    if (g->spec.carved) {
+        std::string err;
+        if (spectral_init(g->spec, desc->h, err)) {
+            spectral_release(g->spec);
+            release_streams(g);
+            delete g;
+            return fail(CHNS_EDEVICE, err);
         }
     }
     memset(&g->last, 0, sizeof g->last);
@@ -804,7 +797,7 @@ static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F,
     // streams of their own, a host thread sets their coefficients and
     // hierarchies up there (component 0 on the pressure set-up stream) while
     // the adjoint pressure solve runs; the solves then skip the set-up.
-    const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum();
+    const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum(g);
     hipError_t eset = hipSuccess;
     std::thread setup_thread;
     struct Joiner {
@@ -1022,6 +1015,31 @@ int chns_apply_pressure_operator(chns_grid *g, const void *rho, const void *x, v
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(g->stream));
     return CHNS_OK;
+}
+
+int chns_set_option(chns_grid *g, int option, int value) {
+    if (!g) return fail(CHNS_EINVAL, "NULL handle");
+    switch (option) {
+        case CHNS_OPT_CH_SOLVER:
+            if (value == CHNS_CH_PCG) {
+                if (g->spec.on) spectral_release(g->spec);
+                return CHNS_OK;
+            }
+            if (value != CHNS_CH_DIRECT) return fail(CHNS_EINVAL, "CH solver must be CHNS_CH_DIRECT or CHNS_CH_PCG");
+            if (!g->spec.carved) return fail(CHNS_EINVAL, "the direct CH solve needs every axis <= 2048 cells");
+            if (!g->spec.on) {
+                std::string err;
+                HIPCHK(hipStreamSynchronize(g->stream));
+                if (spectral_init(g->spec, g->h, err)) return fail(CHNS_EDEVICE, err);
+            }
+            return CHNS_OK;
+        case CHNS_OPT_SERIAL_COMPONENTS:
+            if (value != 0 && value != 1) return fail(CHNS_EINVAL, "serial-components value must be 0 or 1");
+            g->serial_components = value;
+            return CHNS_OK;
+        default:
+            return fail(CHNS_EINVAL, "unknown option");
+    }
 }
 
 static void prof_release(Prof &P) {

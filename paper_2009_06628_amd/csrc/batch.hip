@@ -565,13 +565,12 @@ size_t layout_batch(Bump &B, int count, const Plan *plans, const chns_props *pro
     return B.off;
 }
 
-// Tables and bases of the direct CH solve.  Off with CHNS_CH_SOLVER=pcg,
-// for 3D batches and for axes over kSpectralMaxN.
+// Tables and bases of the direct CH solve.  Off for 3D batches and for
+// axes over kSpectralMaxN.
 template <typename TP>
 int spectral_batch_setup(chns_batch *b, const std::vector<BatchProb<TP>> &h) {
     b->spec_on = 0;
-    const char *cs = getenv("CHNS_CH_SOLVER");
-    if (b->spec.empty() || (cs && strcmp(cs, "pcg") == 0)) return CHNS_OK;
+    if (b->spec.empty()) return CHNS_OK;
     for (size_t k = 0; k < b->spec.size(); ++k) {
         const SpecGroup &G = b->spec[k];
         const std::vector<int> &mem = b->spec_members[k];

@@ -355,6 +355,7 @@ struct chns_grid {
     hipStream_t pstream;                     // pressure set-up during the momentum solves
     hipEvent_t ev_pset;                      // recorded on pstream after that set-up
     int mc_ready;                            // streams and events of mc and the pressure set-up created
+    int serial_components;                   // CHNS_OPT_SERIAL_COMPONENTS
     int adj_ready;                           // adjoint workspace attached
     chns::AdjBufs adj;
     chns_step_stats last;

@@ -40,18 +40,10 @@
 
 namespace chns {
 
-// Levels at or below this many cells run in the single-workgroup kernel
-// (default; the CHNS_SB_CELLS environment variable overrides it at set-up).
-constexpr int kSBCellsDefault = 2048;
+// Levels at or below this many cells run in the single-workgroup kernel.
+constexpr int kSBCells = 2048;
 
-static int sb_cells() {
-    static const int v = [] {   // thread-safe one-time initialisation
-        const char *e = getenv("CHNS_SB_CELLS");
-        const long long x = e ? atoll(e) : kSBCellsDefault;
-        return (int)(x < 1 ? 1 : x);
-    }();
-    return v;
-}
+static int sb_cells() { return kSBCells; }
 
 // ---------------------------------------------------------------------------
 // grid-wide V-cycle kernels (one pass each)

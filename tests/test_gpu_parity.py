@@ -205,9 +205,10 @@ def test_deterministic_bitwise():
 
 
 @pytest.mark.parametrize("case", ["bubble2d", "drops3d"])
-def test_ch_direct_solve_matches_mg_pcg(case, monkeypatch):
+def test_ch_direct_solve_matches_mg_pcg(case):
     """The Cahn-Hilliard system is solved directly (axis eigenbases, FP64
-    GEMMs) by default and by MG-PCG with CHNS_CH_SOLVER=pcg; the states must
+    transforms) by default and by MG-PCG with the CHNS_OPT_CH_SOLVER option;
+    the states must
     agree to the PCG tolerance (1e-10 per solve) after several steps, and
     the direct solve must report one application."""
     P = _lib()
@@ -216,12 +217,9 @@ def test_ch_direct_solve_matches_mg_pcg(case, monkeypatch):
     init = W.initial_state(prob)
     out = []
     for solver in ("direct", "pcg"):
-        if solver == "pcg":
-            monkeypatch.setenv("CHNS_CH_SOLVER", "pcg")
-        else:
-            monkeypatch.delenv("CHNS_CH_SOLVER", raising=False)
         print("CH solver", case, solver, flush=True)
         g = P.grid_for_problem(prob)
+        g.set_option(P.CHNS_OPT_CH_SOLVER, P.CHNS_CH_PCG if solver == "pcg" else P.CHNS_CH_DIRECT)
         st = g.new_state(init)
         stats = g.step(st, steps)
         out.append((st, stats))
@@ -237,26 +235,29 @@ def test_ch_direct_solve_matches_mg_pcg(case, monkeypatch):
 @pytest.mark.parametrize("case", ["bubble2d", "drops3d"])
 def test_concurrent_momentum_matches_serial_bitwise(case):
     """The momentum components run on their own streams and host threads; with
-    the per-kernel timing on they run one after another on the handle's
-    stream.  Both orders must give the same state bit for bit."""
+    the per-kernel timing on, or with CHNS_OPT_SERIAL_COMPONENTS, they run one
+    after another on the handle's stream.  All orders must give the same
+    state bit for bit."""
     P = _lib()
     prob = W.rising_bubble(64, steps=6) if case == "bubble2d" else W.drops3d(32, steps=3)
     steps = 6 if case == "bubble2d" else 3
     init = W.initial_state(prob)
     out = []
-    for timing in (True, False):
+    for mode in ("timing", "serial", "concurrent"):
         g = P.grid_for_problem(prob)
         st = g.new_state(init)
-        g.set_timing(timing)
+        g.set_timing(mode == "timing")
+        g.set_option(P.CHNS_OPT_SERIAL_COMPONENTS, 1 if mode == "serial" else 0)
         g.step(st, steps)
         torch.cuda.synchronize()
         g.set_timing(False)
         out.append(st)
-    a, b = out
-    for k in ("phi", "p", "mu"):
-        assert torch.equal(a[k], b[k]), k
-    for d in range(len(a["u"])):
-        assert torch.equal(a["u"][d], b["u"][d]), d
+    a = out[-1]
+    for b in out[:-1]:
+        for k in ("phi", "p", "mu"):
+            assert torch.equal(a[k], b[k]), k
+        for d in range(len(a["u"])):
+            assert torch.equal(a["u"][d], b["u"][d]), d
 
 
 def test_error_paths():
