@@ -188,8 +188,10 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
         g->phi_new2 = B.take<double>(N);
         g->phihat2 = B.take<double>(N);
         g->rch2 = B.take<double>(N);
+        for (int q = 0; q < 5; ++q) g->mix3[q] = B.take<double>(N);
     } else {
         g->phi_new2 = g->phihat2 = g->rch2 = nullptr;
+        for (int q = 0; q < 5; ++q) g->mix3[q] = nullptr;
     }
     g->vr = B.take<double>(N);
     g->vz = B.take<double>(N);
@@ -385,7 +387,8 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     memset(&last, 0, sizeof last);
     // three-phase model: phases 1 and 2 stored (T1..T4 per phase)
     const bool tern = g->nph == 3;
-    const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2}};
+    const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2},
+                     {g->mix3[0], g->mix3[1], g->mix3[2], g->mix3[3], g->mix3[4]}};
     // S1, S2
     if (tern)
         launch_ch_rhs3(dim, geo, k, g->tern, ph, uc, g->rch, g->rch2, g->phihat, g->phihat2, s);
@@ -403,6 +406,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     if (tern) {
         launch_mu3(dim, geo, k, g->tern, ph, g->phihat, g->phihat2, s);
         launch_phi_update3(dim, geo, k, ph, uc, s);
+        launch_mix3_fields(geo, k, g->tern, ph, s);
     } else {
         launch_mu(dim, geo, k, phi, g->phihat, mu, s);
         launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);
@@ -686,7 +690,8 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
         if (int rc = forward_core(g, phi, uc, mu, pr, last, phi2, mu2)) return rc;
         // S9
         if (g->nph == 3) {
-            const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2}};
+            const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2},
+                             {g->mix3[0], g->mix3[1], g->mix3[2], g->mix3[3], g->mix3[4]}};
             launch_project3(dim, geo, k, g->tern, ph, usc, pr, phi, phi2, u, s);
         } else {
             launch_project(dim, geo, k, g->phi_new, usc, pr, phi, u, s);

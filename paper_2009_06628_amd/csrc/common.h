@@ -338,6 +338,7 @@ struct chns_grid {
     int nph;                                 // phases: 2, or 3 (three-phase model)
     chns::TernConst tern;                    // three-phase constants (nph == 3)
     double *phi_new2, *phihat2, *rch2;       // the second stored phase (nph == 3)
+    double *mix3[5];                         // per-step mixture fields (nph == 3)
     double *vr, *vz, *vp0, *vp1, *vq, *vt;   // PCG vectors
     chns::Slot<double> ch, mom, pres;
     // precision form (FP32 inner solves under FP64 refinement)

@@ -23,6 +23,7 @@ struct Phases3 {
     const double *phi[2];
     double *phin[2];
     double *mu[2];
+    double *mix[5];   // per-step mixture fields: rho^{n+1}, rho^n, eta^{n+1}, rho_lin^n, chi
 };
 
 // T1: r_i and phihat_i = phi_i for i = 1, 2.
@@ -34,6 +35,8 @@ void launch_mu3(int dim, const Geo &g, const StepConst &k, const TernConst &t, c
 // T4: phi_i^{n+1}.
 void launch_phi_update3(int dim, const Geo &g, const StepConst &k, const Phases3 &ph, const double *const u[3],
                         hipStream_t st);
+// Mixture fields of the step (after T4; read by the set-up and projection).
+void launch_mix3_fields(const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, hipStream_t st);
 // T5-T7 set-up of momentum component a.
 void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
                        const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,

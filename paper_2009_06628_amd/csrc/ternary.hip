@@ -57,6 +57,31 @@ struct Mix3 {
     }
 };
 
+// The same mixture read from cell fields computed once per step by
+// k_mix3_fields (rho^{n+1}, rho^n with the pull-back, eta^{n+1}, rho_lin^n and
+// chi = (kM/2) sum_{i=1,2} (rho_i - rho_3) mu~_i, so that J = -G chi): the
+// momentum set-up evaluates the mass flux on up to 11 faces per cell and
+// component, and the three-phase maps are the costly part of it.
+struct MixPre {
+    const double *rn, *ro, *en, *rl, *chi;
+    double ih;
+    double cap[3];
+    const double *phi1, *phi2, *mu1, *mu2;
+    __device__ double rho_new(int e) const { return rn[e]; }
+    __device__ double rho_old(int e) const { return ro[e]; }
+    __device__ double eta_new(int e) const { return en[e]; }
+    __device__ double mflux_face(double ub, int f, int lo) const {
+        return (0.5 * (rl[f] + rl[lo])) * ub - (chi[f] - chi[lo]) * ih;
+    }
+    __device__ double capillary(int c, int cam) const {
+        const double a1 = 0.5 * (phi1[c] + phi1[cam]), a2 = 0.5 * (phi2[c] + phi2[cam]);
+        const double a3 = 0.5 * ((-1.0 - phi1[c] - phi2[c]) + (-1.0 - phi1[cam] - phi2[cam]));
+        const double g1 = (mu1[c] - mu1[cam]) * ih, g2 = (mu2[c] - mu2[cam]) * ih;
+        const double g3 = ((-mu1[c] - mu2[c]) - (-mu1[cam] - mu2[cam])) * ih;
+        return cap[0] * a1 * g1 + cap[1] * a2 * g2 + cap[2] * a3 * g3;
+    }
+};
+
 static Mix3 mk_mix3(const StepConst &k, const TernConst &t, const double *phi1, const double *phi2,
                     const double *phin1, const double *phin2, const double *mu1, const double *mu2) {
     Mix3 m;
@@ -74,6 +99,19 @@ static Mix3 mk_mix3(const StepConst &k, const TernConst &t, const double *phi1, 
     m.mu1 = mu1;
     m.mu2 = mu2;
     return m;
+}
+
+// Cell fields of MixPre (one pass per step, after T4).
+__global__ void __launch_bounds__(kBlock) k_mix3_fields(long long N, Mix3 mx, double *__restrict__ rn,
+                                                        double *__restrict__ ro, double *__restrict__ en,
+                                                        double *__restrict__ rl, double *__restrict__ chi) {
+    CELL_LOOP(N) {
+        rn[c] = mx.rho_new(c);
+        ro[c] = mx.rho_old(c);
+        en[c] = mx.eta_new(c);
+        rl[c] = mx.rho_lin(c);
+        chi[c] = mx.jc[0] * mx.mu1[c] + mx.jc[1] * mx.mu2[c];
+    }
 }
 
 __device__ inline double lambda3(double p1, double p2) {
@@ -196,7 +234,7 @@ __global__ void __launch_bounds__(kBlock) k_phi_update3(Geo g, StepConst k, cons
 
 // T5-T7 set-up for component a (the binary body with the three-phase mixture)
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_mom_setup3(Geo g, StepConst k, int a, Mix3 mx, U3 u,
+__global__ void __launch_bounds__(kBlock) k_mom_setup3(Geo g, StepConst k, int a, MixPre mx, U3 u,
                                                        double *__restrict__ s, W3 cs, double *__restrict__ rhs,
                                                        double *__restrict__ ustar, int coef_only) {
     CELL_LOOP(g.N) mom_setup_body<DIM>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c);
@@ -204,19 +242,20 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup3(Geo g, StepConst k, int a
 
 // T8 set-up
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_p_setup3(Geo g, StepConst k, Mix3 mx, U3 us, double *__restrict__ s,
+__global__ void __launch_bounds__(kBlock) k_p_setup3(Geo g, StepConst k, MixPre mx, U3 us, double *__restrict__ s,
                                                      W3 cs, double *__restrict__ rhs, int part) {
     CELL_LOOP(g.N) p_setup_body<DIM>(g, k, mx, us, s, cs, rhs, part, c);
 }
 
 // T9: projection; phi_i = phi_i^{n+1}
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_project3(Geo g, StepConst k, Mix3 mx, U3 us, const double *__restrict__ p,
-                                                     W3 u, double *__restrict__ phi1, double *__restrict__ phi2) {
+__global__ void __launch_bounds__(kBlock) k_project3(Geo g, StepConst k, MixPre mx, U3 us, const double *__restrict__ p,
+                                                     W3 u, const double *__restrict__ pn1, const double *__restrict__ pn2,
+                                                     double *__restrict__ phi1, double *__restrict__ phi2) {
     CELL_LOOP(g.N) {
         project_body<DIM>(g, k, mx, us, p, u, c);
-        phi1[c] = mx.phin1[c];
-        phi2[c] = mx.phin2[c];
+        phi1[c] = pn1[c];
+        phi2[c] = pn2[c];
     }
 }
 
@@ -329,26 +368,47 @@ static Mix3 mix_of(const StepConst &k, const TernConst &t, const Phases3 &ph) {
     return mk_mix3(k, t, ph.phi[0], ph.phi[1], ph.phin[0], ph.phin[1], ph.mu[0], ph.mu[1]);
 }
 
+static MixPre pre_of(const StepConst &k, const TernConst &t, const Phases3 &ph) {
+    MixPre m;
+    m.rn = ph.mix[0];
+    m.ro = ph.mix[1];
+    m.en = ph.mix[2];
+    m.rl = ph.mix[3];
+    m.chi = ph.mix[4];
+    m.ih = k.ih;
+    for (int i = 0; i < 3; ++i) m.cap[i] = (0.5 / k.Cn) * t.Sg[i];
+    m.phi1 = ph.phi[0];
+    m.phi2 = ph.phi[1];
+    m.mu1 = ph.mu[0];
+    m.mu2 = ph.mu[1];
+    return m;
+}
+
+void launch_mix3_fields(const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, hipStream_t st) {
+    TLAUNCH(K_MOM_SETUP, 8.0 * 11 * g.N, k_mix3_fields, dim3(grid_for(g.N)), dim3(kBlock), st, g.N, mix_of(k, t, ph),
+            ph.mix[0], ph.mix[1], ph.mix[2], ph.mix[3], ph.mix[4]);
+}
+
 void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
                        const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,
                        hipStream_t st) {
-    DISPATCH(K_MOM_SETUP, 9 + 2 * dim, dim, k_mom_setup3, g.N, st, g, k, a, mix_of(k, t, ph), mk_u3(u), s, mk_w3(cs),
+    DISPATCH(K_MOM_SETUP, 11 + 2 * dim, dim, k_mom_setup3, g.N, st, g, k, a, pre_of(k, t, ph), mk_u3(u), s, mk_w3(cs),
              rhs, ustar, 0);
 }
 
 void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], double *s, double *const cs[3], double *rhs, hipStream_t st,
                      int part) {
-    const int words = (part & kPCoef ? 3 + dim : 0) + (part & kPRhs ? 1 + dim : 0);
-    DISPATCH(K_P_SETUP, words, dim, k_p_setup3, g.N, st, g, k, mix_of(k, t, ph), mk_u3(ustar), s, mk_w3(cs), rhs,
+    const int words = (part & kPCoef ? 2 + dim : 0) + (part & kPRhs ? 1 + dim : 0);
+    DISPATCH(K_P_SETUP, words, dim, k_p_setup3, g.N, st, g, k, pre_of(k, t, ph), mk_u3(ustar), s, mk_w3(cs), rhs,
              part);
 }
 
 void launch_project3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], const double *p, double *phi1, double *phi2, double *const u[3],
                      hipStream_t st) {
-    DISPATCH(K_PROJECT, 5 + 2 * dim, dim, k_project3, g.N, st, g, k, mix_of(k, t, ph), mk_u3(ustar), p, mk_w3(u),
-             phi1, phi2);
+    DISPATCH(K_PROJECT, 6 + 2 * dim, dim, k_project3, g.N, st, g, k, pre_of(k, t, ph), mk_u3(ustar), p, mk_w3(u),
+             ph.phin[0], ph.phin[1], phi1, phi2);
 }
 
 void launch_diagnostics3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const double *phi1,

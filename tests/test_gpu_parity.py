@@ -285,3 +285,43 @@ def test_ragged_and_small_grids():
         _, sg, _ = run_gpu(prob, 3)
         _, so, _ = run_oracle(prob, 3)
         compare_states(sg, so, 2, 1e-10, tol_u=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# full-size code paths
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["walls768", "drop3d_112"])
+def test_one_step_past_the_kernel_grid_caps(case):
+    """Sizes where the launch shapes change: more than 262,144 cells (kernels
+    writing per-block partials loop over several cells per thread), more
+    than 1,048,576 cells in 3D (every grid-stride sweep does), and more than
+    1024 level-0 tiles in 2D (the CG update leaves the level-0 tile passes).
+    One step against the oracle."""
+    if case == "walls768":
+        n = 768
+        prob = W.Problem("walls768", (n, n), 1.0 / n, (W.WALL, W.WALL), W.static_drop(n).props, 1, "drop",
+                         {"centre": (0.5, 0.45), "radius": 0.25, "velocity": "stream", "vseed": 3, "vamp": 0.05})
+        assert (n // 32) * (n // 16) > 1024 and n * n > 262144
+    else:
+        prob = W.drop3d(112, steps=1)
+        assert prob.cells > 1048576
+    print("full-size one step", case, prob.n, flush=True)
+    _, sg, stats = run_gpu(prob, 1)
+    _, so, _ = run_oracle(prob, 1)
+    print("stats", stats, flush=True)
+    compare_states(sg, so, prob.dim, 1e-10)
+
+
+def test_rising_bubble_full_size_100_steps_parity():
+    """The full 256 x 512 rising-bubble configuration (density ratio 1000,
+    viscosity ratio 100, walls, gravity) from its initial state: 100 steps
+    against the oracle at the 1e-9 bar, phase masses to 1e-12."""
+    prob = W.rising_bubble(256, steps=100)
+    print("bubble 256x512, 100 steps", flush=True)
+    g, sg, stats = run_gpu(prob, 100)
+    og, so, prm = run_oracle(prob, 100)
+    compare_states(sg, so, 2, 1e-9)
+    d0 = diagnostics(og, W.initial_state(prob), prm)
+    for key in ("mass_plus", "mass_minus"):
+        assert abs(stats[key] - d0[key]) <= 1e-12 * d0[key]
