@@ -210,6 +210,37 @@ int chns_set_properties(struct chns_grid *g, const chns_props *props);
  * Returns CHNS_ENOCONV if any solve of any step hit max_iter.            */
 int chns_step(struct chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats);
 
+/* Energy-law monitor of one step (the time-step condition of the paper's
+ * energy-stability theorem), with the step's own fields u^{n+1}, mu^{n+1},
+ * eta^{n+1} in place of the theorem's Crank-Nicolson averages:
+ *   visc   (1/Re) ||sqrt(eta) grad u||^2: sum_a u_a^T K_a u_a h^d with K_a
+ *          the viscous part of the step's momentum operator of component a
+ *   chem   (1/(Pe Cn^2 We)) ||G mu||^2
+ *   cubic  (1/(24 We Cn)) sum 6 max(|phi^n|, |phi^{n+1}|) |phi^{n+1} - phi^n|^3 h^d,
+ *          a bound of the magnitude of the theorem's cubic term (the third
+ *          derivative of psi is 6 phi, taken between phi^n and phi^{n+1})
+ *   inert  (1/8) sum_a sum_faces |A_a(rho^{n+1} - rho^n)| (u_a^{n+1} - u_a^n)^2 h^d,
+ *          a bound of the magnitude of the density-change term
+ *   holds  dt (visc + chem) >= cubic + inert (the theorem's condition with
+ *          the bounds: the energy cannot rise)
+ *   dt_max dt sqrt(dt (visc + chem) / (cubic + inert)): the bounds grow like
+ *          dt^3 and the dissipation like dt (HUGE_VAL when both bounds are 0)
+ *   energy_before, energy_after: the discrete total energy at t^n, t^{n+1}. */
+typedef struct {
+    double visc, chem, cubic, inert;
+    double dt_max;
+    double energy_before, energy_after;
+    int holds;
+    int reserved;
+} chns_energy_monitor;
+
+/* One step (chns_step with nsteps = 1) that also evaluates the energy-law
+ * monitor on the device (one reduction kernel between S8 and S9, plus the
+ * energy of the state before and after).  Two-phase grids only
+ * (CHNS_EINVAL otherwise).  Synchronises the stream.  Return codes as
+ * chns_step.                                                              */
+int chns_step_monitor(struct chns_grid *g, chns_state *st, chns_energy_monitor *out);
+
 /* Stand-alone pressure solve of S8:  -D(rho_f^{-1} G p) = rhs, mean(p) = 0,
  * with rho a cell array of densities (rho_f = face averages, used as is)
  * and rhs a cell array (projected to mean zero internally; not modified).

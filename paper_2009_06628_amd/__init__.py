@@ -56,6 +56,12 @@ class chns_step_stats(ctypes.Structure):
                 ("mass_phase", ctypes.c_double * 3)]
 
 
+class chns_energy_monitor(ctypes.Structure):
+    _fields_ = [("visc", ctypes.c_double), ("chem", ctypes.c_double), ("cubic", ctypes.c_double),
+                ("inert", ctypes.c_double), ("dt_max", ctypes.c_double), ("energy_before", ctypes.c_double),
+                ("energy_after", ctypes.c_double), ("holds", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
 class chns_kernel_timing(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -103,6 +109,8 @@ EXPORTS = {
     "chns_set_properties": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_props)]),
     "chns_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state), ctypes.c_int,
                                  ctypes.POINTER(chns_step_stats)]),
+    "chns_step_monitor": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(chns_state),
+                                         ctypes.POINTER(chns_energy_monitor)]),
     "chns_solve_pressure": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_double, ctypes.c_int, ctypes.POINTER(chns_solve_stats)]),
     "chns_apply_pressure_operator": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -305,6 +313,17 @@ class Grid:
             "energy": out.energy, "umax": out.umax, "divmax": out.divmax, "rc": rc,
             "mass_phase": list(out.mass_phase)[: self.nphases],
         }
+
+    # -- step_monitor ------------------------------------------------------------
+    def step_monitor(self, st: Dict, allow_noconv: bool = False) -> Dict:
+        """One step with the energy-law monitor (chns_step_monitor)."""
+        cs = self._cstate(st)
+        out = chns_energy_monitor()
+        rc = self._lib.chns_step_monitor(self._h, ctypes.byref(cs), ctypes.byref(out))
+        _check(rc, "chns_step_monitor", allow_noconv)
+        return {"visc": out.visc, "chem": out.chem, "cubic": out.cubic, "inert": out.inert, "dt_max": out.dt_max,
+                "holds": bool(out.holds), "energy_before": out.energy_before, "energy_after": out.energy_after,
+                "rc": rc}
 
     # -- solve_pressure --------------------------------------------------------
     def solve_pressure(self, rho, rhs, p, rtol: float = 1e-12, max_iter: int = 200) -> Dict:

@@ -743,6 +743,74 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     return CHNS_OK;
 }
 
+// Total energy of a two-phase state (diagnostics kernel), synchronous.
+static int state_energy(chns_grid *g, const double *phi, const double *const uc[3], double *energy) {
+    const StepConst k = step_const(g);
+    const chns_props &p = g->props;
+    double *dout = g->diag + kDiagSlots * kMaxBlocks;
+    launch_diagnostics(g->dim, g->geo, k, phi, uc, g->diag, g->red.counter, dout, g->stream);
+    double h8[8];
+    HIPCHK(hipMemcpyAsync(h8, dout, sizeof h8, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    const double hd = std::pow(g->h, g->dim);
+    *energy = h8[2] * hd + (h8[3] * hd + 0.5 * p.Cn * p.Cn * h8[4] * hd) / (p.Cn * p.We) + p.inv_Fr * h8[5] * hd;
+    return CHNS_OK;
+}
+
+int chns_step_monitor(chns_grid *g, chns_state *st, chns_energy_monitor *out) {
+    if (!g || !st || !out) return fail(CHNS_EINVAL, "NULL argument");
+    if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
+    if (g->nph != 2) return fail(CHNS_EINVAL, "the energy monitor covers the two-phase step");
+    if (!st->phi || !st->p || !st->mu) return fail(CHNS_EINVAL, "state pointer is NULL");
+    for (int a = 0; a < g->dim; ++a)
+        if (!st->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
+    ProfScope prof_scope(g);
+    const int dim = g->dim;
+    const Geo &geo = g->geo;
+    const StepConst k = step_const(g);
+    const chns_props &p = g->props;
+    hipStream_t s = g->stream;
+    double *phi = (double *)st->phi, *mu = (double *)st->mu, *pr = (double *)st->p;
+    double *u[3] = {(double *)st->u[0], (double *)st->u[1], dim == 3 ? (double *)st->u[2] : nullptr};
+    const double *uc[3] = {u[0], u[1], u[2]};
+    const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
+    memset(out, 0, sizeof *out);
+    if (int rc = state_energy(g, phi, uc, &out->energy_before)) return rc;
+    chns_step_stats last;
+    if (int rc = forward_core(g, phi, uc, mu, pr, last)) return rc;
+    const double *ms[3] = {nullptr, nullptr, nullptr};
+    const double *mcs[3][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    for (int a = 0; a < dim; ++a) {
+        const Level<double> &L0 = a == 0 ? g->mom.lev[0] : g->mc[a - 1].mom.lev[0];
+        ms[a] = L0.s;
+        for (int b = 0; b < dim; ++b) mcs[a][b] = L0.cs[b];
+    }
+    double *dout = g->diag + kDiagSlots * kMaxBlocks;
+    launch_energy_monitor(dim, geo, k, phi, g->phi_new, mu, uc, usc, pr, ms, mcs, g->diag, g->red.counter, dout, s);
+    double h4[4];
+    HIPCHK(hipMemcpyAsync(h4, dout, sizeof h4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    launch_project(dim, geo, k, g->phi_new, usc, pr, phi, u, s);
+    HIPCHK(hipGetLastError());
+    if (int rc = state_energy(g, phi, uc, &out->energy_after)) return rc;
+    const double hd = std::pow(g->h, dim);
+    out->visc = h4[0] * hd;
+    out->chem = h4[1] * hd / (p.Pe * p.Cn * p.Cn * p.We);
+    out->cubic = h4[2] * hd / (24.0 * p.We * p.Cn);
+    out->inert = h4[3] * hd / 8.0;
+    const double diss = p.dt * (out->visc + out->chem), ind = out->cubic + out->inert;
+    out->holds = diss >= ind ? 1 : 0;
+    out->dt_max = ind == 0.0 ? HUGE_VAL : p.dt * std::sqrt(diss / ind);
+    g->last = last;
+    if (last.unconverged) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "unconverged solves (bit 0 CH, 1..3 momentum, 4 pressure): mask %d", last.unconverged);
+        g_err = buf;
+        return CHNS_ENOCONV;
+    }
+    return CHNS_OK;
+}
+
 int chns_adjoint_workspace_size(const chns_grid_desc *desc, size_t *bytes) {
     if (!bytes) return fail(CHNS_EINVAL, "bytes is NULL");
     Plan P;

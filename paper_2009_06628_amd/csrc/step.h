@@ -55,6 +55,14 @@ void launch_diagnostics3(int dim, const Geo &g, const StepConst &k, const TernCo
                          const double *phi2, const double *const u[3], double *part, unsigned int *counter,
                          double *out, hipStream_t st);
 
+// Energy-law monitor of one two-phase step (after S8, before S9): unscaled
+// sums visc, chem, cubic, inert into out[0..3]; s[a], cs[a][b] the level-0
+// momentum coefficients of component a.
+void launch_energy_monitor(int dim, const Geo &g, const StepConst &k, const double *phi, const double *phi_new,
+                           const double *mu, const double *const u[3], const double *const ustar[3], const double *p,
+                           const double *const s[3], const double *const cs[3][3], double *part,
+                           unsigned int *counter, double *out, hipStream_t st);
+
 // S1: r = phi - dt D(u A phi) + dt kM L(psi'(phi) - S phi); phihat = phi.
 void launch_ch_rhs(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
                    double *r, double *phihat, hipStream_t st);
