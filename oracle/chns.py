@@ -317,15 +317,39 @@ def pressure_solve(g: MACGrid, rhof: List[np.ndarray], rhs: np.ndarray) -> np.nd
 # the step
 # ---------------------------------------------------------------------------
 
+def wall_velocity_rhs(g: MACGrid, a: int, eta_new: np.ndarray, prm, wall_u: Optional[Dict]) -> np.ndarray:
+    """Right-hand-side term of the momentum rows of component a next to a wall
+    that moves tangentially (inhomogeneous Dirichlet data, as the lid of the
+    paper's lid-driven cavity): with the no-slip ghost value 2 U - u in place
+    of -u, the wall edge adds 2 k U, k = (eta_c + eta_{c-e_a}) / (2 Re h^2)
+    the coefficient of that edge in the momentum matrix.  wall_u maps
+    (b, side, a) -> face array of component a whose layer next to the wall
+    (index 0 along b for side 0, n_b - 1 for side 1) holds U."""
+    out = np.zeros(g.shape)
+    if not wall_u:
+        return out
+    e2 = _at(g, eta_new, {a: -1}, fill=0.0)
+    kw = 0.5 * (eta_new + e2) / (prm.Re * g.h * g.h)
+    for (b, side, comp), U in wall_u.items():
+        if comp != a or b == a or g.periodic[b]:
+            continue
+        mask = _top(g, b) if side else _bot(g, b)
+        out = out + np.where(mask, 2.0 * kw * U, 0.0)
+    return out
+
+
 def step(g: MACGrid, st: Dict, prm: Params, forcing: Optional[Dict] = None, ch_solver: str = "spectral",
-         ch_only: bool = False) -> Dict:
+         ch_only: bool = False, wall_u: Optional[Dict] = None) -> Dict:
     """One step n -> n+1 of Algorithm S.  st = {'phi', 'u': [..], 'p'}.
 
     Returns a new state dict with 'phi', 'u', 'p', 'mu' and the intermediates
     'phihat', 'ustar', 'rho', 'eta', 'm'.  `forcing` (manufactured-solution
     tests only) may hold 'phi' (cells), 'mu' (cells) and 'u' (faces), all
     evaluated at t^{n+1}.  ch_only=True stops after S4 (velocity and pressure
-    are carried over unchanged): the Cahn-Hilliard sub-step alone."""
+    are carried over unchanged): the Cahn-Hilliard sub-step alone.  wall_u:
+    tangential velocities of moving walls (see wall_velocity_rhs); the
+    normal velocity and the mass flux through every wall stay 0, so only
+    the viscous wall term of S7 changes."""
     d = g.dim
     phi = st["phi"]
     u = st["u"]
@@ -389,6 +413,8 @@ def step(g: MACGrid, st: Dict, prm: Params, forcing: Optional[Dict] = None, ch_s
             rhs = rhs - rhof_new[a] * prm.inv_Fr
         if "u" in f:
             rhs = rhs + f["u"][a]
+        if wall_u:
+            rhs = rhs + wall_velocity_rhs(g, a, eta_new, prm, wall_u)
         ustar.append(momentum_solve(g, a, rhof_new[a], eta_new, prm, rhs))
 
     # S8  pressure:  -D(rho_f^{-1} G p) = -(We/dt) D u*

@@ -610,3 +610,68 @@ def test_3d_solve_branches_reach_the_exact_solution():
     K = sp.bmat([[Pm, one], [one.T, None]], format="csc")
     x = spla.spsolve(K, np.concatenate([rhs.ravel() - rhs.mean(), [0.0]]))[:N]
     assert np.abs(p.ravel() - x).max() <= 1e-10 * np.abs(x).max()
+
+
+# --------------------------------------------------------------------------
+# walls with inhomogeneous Dirichlet data (moving lid)
+# --------------------------------------------------------------------------
+
+def test_couette_profile_is_the_steady_state():
+    """Plane Couette flow: periodic x, no-slip bottom, top wall moving at U.
+    With the ghost value 2U - u at the moving wall, the linear profile
+    u_x = U (j + 1/2) / n is the exact discrete steady state (the viscous
+    rows sum to zero, also next to both walls), so it stays to round-off;
+    a wall term with the wrong factor or sign would drive it away."""
+    n, U = 16, 0.7
+    prob = W.Problem("couette", (8, n), 1.0 / n, (W.PERIODIC, W.WALL),
+                     W.Props(rho_minus=1.0, eta_minus=1.0, Re=5.0, We=1.0, Cn=0.1, Pe=100.0, dt=1e-2),
+                     1, "const", {"value": 1.0, "lid": "couette", "speed": U})
+    g = MACGrid(prob.n, prob.h, prob.periodic)
+    prm = Params.from_props(prob.props)
+    j = g.index(1)
+    lin = U * (j + 0.5) / n
+    st = {"phi": np.ones(g.shape), "u": [lin.astype(float), np.zeros(g.shape)], "p": np.zeros(g.shape)}
+    wu = W.wall_velocity(prob)
+    for _ in range(20):
+        st = step(g, st, prm, wall_u=wu)
+    assert np.abs(st["u"][0] - lin).max() < 1e-13
+    assert np.abs(st["u"][1]).max() < 1e-14
+    # from rest the flow approaches it: after the faster modes have died out
+    # the deviation is the slowest mode, amplitude 2U/pi, damped by the
+    # implicit step's factor 1 / (1 + dt pi^2 / Re) per step
+    st = {"phi": np.ones(g.shape), "u": [np.zeros(g.shape), np.zeros(g.shape)], "p": np.zeros(g.shape)}
+    N = 200
+    for _ in range(N):
+        st = step(g, st, prm, wall_u=wu)
+    pred = 2 * U / np.pi * (1.0 / (1.0 + prm.dt * np.pi ** 2 / prm.Re)) ** N
+    dev = np.abs(st["u"][0] - lin).max()
+    assert 0.85 * pred < dev < 1.15 * pred
+
+
+def test_lid_driven_cavity_symmetry_and_conservation():
+    """The paper's lid profile 16 x (1 - x) z (1 - z) is even about z = 1/2:
+    the cavity flow keeps that mirror symmetry (u_x, u_y, phi even, u_z odd),
+    both phase masses (the lid moves tangentially, no flux through any wall)
+    and a divergence-free velocity with zero normal velocity on every wall."""
+    prob = W.lid_driven_cavity3d(12, steps=6)
+    g = MACGrid(prob.n, prob.h, prob.periodic)
+    prm = Params.from_props(prob.props)
+    st = W.initial_state(prob)
+    wu = W.wall_velocity(prob)
+    d0 = diagnostics(g, st, prm)
+    for _ in range(6):
+        st = step(g, st, prm, wall_u=wu)
+    d1 = diagnostics(g, st, prm)
+    for key in ("mass_plus", "mass_minus"):
+        assert abs(d1[key] - d0[key]) <= 1e-12 * d0[key]
+    assert d1["umax"] > 1e-3 and d1["divmax"] * g.h <= 1e-12 * d1["umax"]
+    for a in range(3):
+        assert np.all(st["u"][a][g.wall_face_mask(a)] == 0.0)
+    zf = lambda q: q[::-1]                    # cells / x, y faces mirrored in z (numpy axis 0)
+    for a in (0, 1):
+        assert np.abs(zf(st["u"][a]) - st["u"][a]).max() <= 1e-12 * d1["umax"]
+    uz = st["u"][2]
+    mirrored = np.zeros_like(uz)
+    mirrored[1:] = -uz[1:][::-1]              # face k <-> face n - k (face 0 is the wall)
+    assert np.abs(mirrored - uz).max() <= 1e-12 * d1["umax"]
+    assert np.abs(zf(st["phi"]) - st["phi"]).max() <= 1e-12

@@ -352,6 +352,10 @@ def initial_state(p: Problem) -> Dict[str, object]:
     elif p.init == "drops":
         cs_, rs_ = drop_set(p, a["seed"], a["count"], a["rmin"], a["rmax"], a["gap"])
         phi = phi_drops(p, cs_, rs_)
+    elif p.init == "rt_surface":
+        X = cell_centres(p.n, p.h)
+        gz = a["amp"] * (np.cos(2 * np.pi * X[0]) + np.cos(2 * np.pi * X[2]))
+        phi = interface(X[1] - a["h0"] - gz, p.props.Cn)
     elif p.init == "spinodal":
         phi = phi_spinodal(p, a.get("seed", 0), a.get("amp", 0.05))
     elif p.init == "const":
@@ -456,6 +460,55 @@ def drops3d(n: int = 128, steps: int = 500, seed: int = 3, count: int = 16, **kw
     return Problem("drops3d_%d" % n, (n, n, n), h, (PERIODIC,) * 3, pr, steps, "drops",
                    {"seed": seed, "count": count, "rmin": 0.05, "rmax": 0.12, "gap": 6 * 1.5 / 128,
                     "velocity": "potential3d", "vseed": seed + 100, "vamp": 1e-2})
+
+
+def lid_driven_cavity3d(n: int = 128, steps: int = 200, **kw) -> Problem:
+    """Two-phase lid-driven cavity (the paper's 3D lid-driven cavity): unit
+    cube with walls on every side, the two fluids in the lower and upper
+    halves with a flat interface at y = 1/2 (equilibrium profile), density
+    and viscosity ratio 1, Re = 100, We = 100, Cn = 1.5 h, 1/Pe = 3 Cn^2,
+    fluid at rest; the top wall (y = 1) moves along x with
+    u_x = 16 x (1 - x) z (1 - z) (zero at its edges), the other walls are
+    no-slip.  dt = 1e-3 (advective CFL 0.128 at 128^3 with the lid speed 1)."""
+    h = 1.0 / n
+    Cn = 1.5 * h
+    pr = Props(rho_minus=1.0, eta_minus=1.0, Re=100.0, We=100.0, Cn=Cn, Pe=1.0 / (3.0 * Cn * Cn), dt=1e-3)
+    pr = pr.copy(**kw)
+    return Problem("lid_driven_cavity3d_%d" % n, (n, n, n), h, (WALL,) * 3, pr, steps, "slab",
+                   {"height": 0.5, "lid": "paper"})
+
+
+def rayleigh_taylor3d(n: int = 64, steps: int = 200, **kw) -> Problem:
+    """Reduced 3D Rayleigh-Taylor instability (one wavelength of the paper's
+    3D initial condition): box [0,1] x [0,4] x [0,1] of n x 4n x n cells, walls
+    on every side, the heavy fluid (phi = +1, the reference) above the
+    interface y = h0 + g(x, z), h0 = 2, g = 0.05 (cos 2 pi x + cos 2 pi z);
+    Atwood number 0.15 (rho_- = 0.85 / 1.15), viscosity ratio 1, Re = 1000,
+    We = 1000, Fr = 1 with gravity along -y, Cn = 1.5 h, 1/Pe = 3 Cn^2,
+    dt = 2.5e-3, fluid at rest."""
+    h = 1.0 / n
+    Cn = 1.5 * h
+    pr = Props(rho_minus=0.85 / 1.15, eta_minus=1.0, Re=1000.0, We=1000.0, Cn=Cn, Pe=1.0 / (3.0 * Cn * Cn),
+               inv_Fr=1.0, dt=2.5e-3)
+    pr = pr.copy(**kw)
+    return Problem("rayleigh_taylor3d_%d" % n, (n, 4 * n, n), h, (WALL,) * 3, pr, steps, "rt_surface",
+                   {"h0": 2.0, "amp": 0.05})
+
+
+def wall_velocity(p: Problem) -> Dict[Tuple[int, int, int], np.ndarray]:
+    """Tangential velocities of moving walls: {(b, side, a): face array of
+    component a whose layer next to wall (b, side) holds the wall speed}.
+    Empty for problems whose walls are all at rest."""
+    a = p.init_args
+    if a.get("lid") == "paper":
+        # u_x on the top wall y = 1 at the x-face positions (i h, 1, (k + 1/2) h)
+        X = cell_centres(p.n, p.h)
+        xf = X[0] - 0.5 * p.h
+        z = X[2]
+        return {(1, 1, 0): 16.0 * xf * (1.0 - xf) * z * (1.0 - z)}
+    if a.get("lid") == "couette":
+        return {(1, 1, 0): np.full(p.shape, float(a["speed"]))}
+    return {}
 
 
 def sample_surface_tensions(seed: int, lo: float = 0.5, hi: float = 1.5) -> Tuple[float, float, float]:
