@@ -466,6 +466,21 @@ int chns_solve_pressure_noalloc(const chns_grid_desc *desc, const void *rho, con
 /* Size in bytes of that array (CHNS_NOALLOC_SCRATCH_BYTES).              */
 size_t chns_solve_pressure_noalloc_capacity(void);
 
+/* Walls with inhomogeneous Dirichlet data (the moving lid of the paper's
+ * lid-driven cavity): the wall of walled axis `axis` on side `side` (0: the
+ * lower wall, 1: the upper one) moves tangentially with velocity component
+ * `component` (!= axis) given by `values`, a face array of that component
+ * (device, float64, caller-owned, read by every later step until replaced)
+ * whose layer next to the wall (index 0 along `axis` for side 0, n - 1 for
+ * side 1) holds the wall speed at the faces' positions on the wall; other
+ * entries are not read.  NULL makes that wall component rest again.  The
+ * no-slip ghost value next to the wall becomes 2 U - u, so the wall edge of
+ * those momentum rows adds 2 k U to their right-hand side (k the edge's
+ * viscous coefficient); the normal velocity and the mass and phase fluxes
+ * through every wall stay zero.  chns_step_monitor rejects grids with
+ * moving walls.                                                            */
+int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int component, const void *values);
+
 /* Per-handle options (host state; take effect from the next call):
  *   CHNS_OPT_CH_SOLVER          CHNS_CH_DIRECT (default where every axis has
  *                               at most 2048 cells: the direct S2 solve) or

@@ -145,6 +145,8 @@ EXPORTS = {
                                                    ctypes.POINTER(chns_solve_stats)]),
     "chns_solve_pressure_noalloc_capacity": (ctypes.c_size_t, []),
     "chns_set_option": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "chns_set_wall_velocity": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_void_p]),
     "chns_destroy_grid": (ctypes.c_int, [ctypes.c_void_p]),
     "chns_error_string": (ctypes.c_char_p, [ctypes.c_int]),
     "chns_last_error": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t]),
@@ -411,6 +413,22 @@ class Grid:
                                                   ctypes.byref(li), ctypes.byref(lo), grad)
         return _check(rc, "chns_adjoint_step_recorded", allow_noconv)
 
+    # -- moving walls ------------------------------------------------------------
+    def set_wall_velocity(self, axis: int, side: int, component: int, values) -> None:
+        """chns_set_wall_velocity: values is a face tensor of `component`
+        (kept referenced by the grid) or None to stop that wall."""
+        if not hasattr(self, "_walls"):
+            self._walls = {}
+        key = (axis, side, component)
+        if values is None:
+            self._walls.pop(key, None)
+            ptr = None
+        else:
+            self._walls[key] = values
+            ptr = ctypes.c_void_p(_ptr(values))
+        _check(self._lib.chns_set_wall_velocity(self._h, int(axis), int(side), int(component), ptr),
+               "chns_set_wall_velocity")
+
     # -- options ---------------------------------------------------------------
     def set_option(self, option: int, value: int) -> None:
         """chns_set_option: CHNS_OPT_CH_SOLVER (CHNS_CH_DIRECT / CHNS_CH_PCG),
@@ -584,7 +602,12 @@ def create_grid(n, h, bc, precision=CHNS_FP64, device="cuda", stream=None, nphas
 
 
 def grid_for_problem(problem, precision=CHNS_FP64, device="cuda") -> Grid:
-    """Grid + properties for a workloads.Problem (two- or three-phase)."""
+    """Grid + properties (and moving-wall data) for a workloads.Problem."""
     g = Grid(problem.n, problem.h, problem.bc, precision, device, nphases=getattr(problem.props, "nphases", 2))
+    walls = getattr(problem, "wall_velocity", None)
+    if walls:
+        torch = _torch()
+        for (b, side, a), U in walls.items():
+            g.set_wall_velocity(b, side, a, torch.tensor(U, dtype=torch.float64, device=g.device).contiguous())
     g.set_properties(problem.props)
     return g

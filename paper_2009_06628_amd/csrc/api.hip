@@ -445,10 +445,13 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         Level<double> &L0 = c.S64->lev[0];
         double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
         double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+        WallVel wv;
+        memcpy(wv.v, g->wall_u, sizeof wv.v);
+        const WallVel *pw = g->walls_move ? &wv : nullptr;
         if (tern)
-            launch_mom_setup3(dim, geo, k, g->tern, ph, a, uc, L0.s, cs, rhs, g->ustar[a], c.s);
+            launch_mom_setup3(dim, geo, k, g->tern, ph, a, uc, L0.s, cs, rhs, g->ustar[a], c.s, pw);
         else
-            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, rhs, g->ustar[a], c.s);
+            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, rhs, g->ustar[a], c.s, 0, pw);
         em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
         if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
     };
@@ -611,6 +614,8 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     }
     // direct CH solve where the bases fit (chns_set_option can select MG-PCG)
     g->serial_components = 0;
+    memset(g->wall_u, 0, sizeof g->wall_u);
+    g->walls_move = 0;
     if (g->spec.carved) {
         std::string err;
         if (spectral_init(g->spec, desc->h, err)) {
@@ -761,6 +766,7 @@ int chns_step_monitor(chns_grid *g, chns_state *st, chns_energy_monitor *out) {
     if (!g || !st || !out) return fail(CHNS_EINVAL, "NULL argument");
     if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
     if (g->nph != 2) return fail(CHNS_EINVAL, "the energy monitor covers the two-phase step");
+    if (g->walls_move) return fail(CHNS_EINVAL, "the energy monitor covers walls at rest");
     if (!st->phi || !st->p || !st->mu) return fail(CHNS_EINVAL, "state pointer is NULL");
     for (int a = 0; a < g->dim; ++a)
         if (!st->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
@@ -1087,6 +1093,21 @@ int chns_apply_pressure_operator(chns_grid *g, const void *rho, const void *x, v
     slot_apply(g->pres, g->dim, (const double *)x, (double *)y, g->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(g->stream));
+    return CHNS_OK;
+}
+
+int chns_set_wall_velocity(chns_grid *g, int axis, int side, int component, const void *values) {
+    if (!g) return fail(CHNS_EINVAL, "NULL handle");
+    if (axis < 0 || axis >= g->dim || g->geo.per[axis]) return fail(CHNS_EINVAL, "axis must be a walled axis");
+    if (side != 0 && side != 1) return fail(CHNS_EINVAL, "side must be 0 (lower wall) or 1 (upper wall)");
+    if (component < 0 || component >= g->dim || component == axis)
+        return fail(CHNS_EINVAL, "component must be a velocity component tangential to the wall");
+    g->wall_u[axis][side][component] = (const double *)values;
+    g->walls_move = 0;
+    for (int b = 0; b < 3; ++b)
+        for (int q = 0; q < 2; ++q)
+            for (int a = 0; a < 3; ++a)
+                if (g->wall_u[b][q][a]) g->walls_move = 1;
     return CHNS_OK;
 }
 

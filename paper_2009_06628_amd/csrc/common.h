@@ -357,6 +357,8 @@ struct chns_grid {
     hipEvent_t ev_pset;                      // recorded on pstream after that set-up
     int mc_ready;                            // streams and events of mc and the pressure set-up created
     int serial_components;                   // CHNS_OPT_SERIAL_COMPONENTS
+    const double *wall_u[3][2][3];           // moving-wall data [axis][side][component] (caller-owned)
+    int walls_move;                          // any of them set
     int adj_ready;                           // adjoint workspace attached
     chns::AdjBufs adj;
     chns_step_stats last;

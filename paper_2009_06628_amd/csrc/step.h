@@ -14,6 +14,13 @@ struct StepConst {
 
 constexpr int kPCoef = 1, kPRhs = 2;
 
+// Tangential velocities of moving walls: v[b][side][a] is a face array of
+// component a whose layer next to wall (b, side) holds the wall speed, or
+// null for a wall at rest.
+struct WallVel {
+    const double *v[3][2][3];
+};
+
 // Three-phase constants (TernConst, common.h) from the properties.
 TernConst tern_const_of(const chns_props &p);
 
@@ -40,7 +47,7 @@ void launch_mix3_fields(const Geo &g, const StepConst &k, const TernConst &t, co
 // T5-T7 set-up of momentum component a.
 void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
                        const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,
-                       hipStream_t st);
+                       hipStream_t st, const WallVel *wv = nullptr);
 // T8 set-up (parts as launch_p_setup).
 void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], double *s, double *const cs[3], double *rhs, hipStream_t st,
@@ -74,9 +81,10 @@ void launch_phi_update(int dim, const Geo &g, const StepConst &k, const double *
                        const double *mu, double *phi_new, hipStream_t st);
 // S5-S7 set-up for component a: level-0 coefficients of the momentum slot,
 // right-hand side, and initial guess ustar_a = u_a.
+// wv: tangential velocities of moving walls (null: every wall at rest).
 void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const double *phi, const double *phi_new,
                       const double *mu, const double *const u[3], double *s, double *const cs[3], double *rhs,
-                      double *ustar, hipStream_t st, int coef_only = 0);
+                      double *ustar, hipStream_t st, int coef_only = 0, const WallVel *wv = nullptr);
 // S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new)
 // (part & kPCoef) and rhs = -(We/dt) D ustar (part & kPRhs).  The
 // coefficients need only phi_new, so the step sets them and the pressure

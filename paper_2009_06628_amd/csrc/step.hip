@@ -53,6 +53,17 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup(Geo g, StepConst k, int a,
     CELL_LOOP(g.N) mom_setup_cell<DIM>(g, k, a, phi, phin, mu, u, s, cs, rhs, ustar, coef_only, c);
 }
 
+// The same with moving walls.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_mom_setup_walls(Geo g, StepConst k, int a, const double *__restrict__ phi,
+                                                            const double *__restrict__ phin,
+                                                            const double *__restrict__ mu, U3 u,
+                                                            double *__restrict__ s, W3 cs, double *__restrict__ rhs,
+                                                            double *__restrict__ ustar, int coef_only, WallVel wv) {
+    const Mix2 mx = mk_mix2(k, phi, phin, mu);
+    CELL_LOOP(g.N) mom_setup_body<DIM, Mix2, true>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c, &wv);
+}
+
 // ---------------------------------------------------------------------------
 // S8 set-up
 // ---------------------------------------------------------------------------
@@ -181,7 +192,12 @@ void launch_phi_update(int dim, const Geo &g, const StepConst &k, const double *
 }
 void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const double *phi, const double *phi_new,
                       const double *mu, const double *const u[3], double *s, double *const cs[3], double *rhs,
-                      double *ustar, hipStream_t st, int coef_only) {
+                      double *ustar, hipStream_t st, int coef_only, const WallVel *wv) {
+    if (wv) {
+        DISPATCH(K_MOM_SETUP, 6 + 2 * dim, dim, k_mom_setup_walls, g.N, st, g, k, a, phi, phi_new, mu, mk_u3(u), s,
+                 mk_w3(cs), rhs, ustar, coef_only, *wv);
+        return;
+    }
     DISPATCH(K_MOM_SETUP, 6 + 2 * dim, dim, k_mom_setup, g.N, st, g, k, a, phi, phi_new, mu, mk_u3(u), s, mk_w3(cs), rhs,
              ustar, coef_only);
 }

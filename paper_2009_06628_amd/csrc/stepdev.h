@@ -164,10 +164,14 @@ __device__ inline void phi_update_cell(const Geo &g, const StepConst &k, const d
 
 // S5-S7 set-up for component a: level-0 coefficients of the momentum operator,
 // right-hand side, initial guess ustar_a = u_a
-template <int DIM, typename Mix>
+// WALLS: some walls move (wv their tangential velocities): the no-slip ghost
+// value next to such a wall is 2 U - u instead of -u, which adds 2 k U to
+// the right-hand side of the row (k the wall edge's coefficient).
+template <int DIM, typename Mix, bool WALLS = false>
 __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, const Mix &mx, const U3 &u,
                                       double *__restrict__ s, const W3 &cs, double *__restrict__ rhs,
-                                      double *__restrict__ ustar, int coef_only, int c) {
+                                      double *__restrict__ ustar, int coef_only, int c,
+                                      const WallVel *wv = nullptr) {
     const double rvis = k.inv_Re * k.ih2;
     int i, j, kk;
     if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
@@ -189,6 +193,7 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
     const double rf_new = 0.5 * (mx.rho_new(c) + mx.rho_new(cam));
     const double rf_old = 0.5 * (mx.rho_old(c) + mx.rho_old(cam));
     const double e_c = eta_of(c), e_am = eta_of(cam);
+    double fwall = 0.0;
     double sd = rf_new / k.dt;
     double nadv = 0.0;
 #pragma unroll
@@ -221,8 +226,14 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
             } else {
                 cs.a[b][c] = 0.0;
             }
-            if (!g.per[b] && ia[b] == 0) sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
-            if (!g.per[b] && ia[b] == g.n[b] - 1) sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
+            if (!g.per[b] && ia[b] == 0) {
+                sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
+                if (WALLS && wv->v[b][0][a]) fwall += (2.0 * (0.5 * (e_c + e_am)) * rvis) * wv->v[b][0][a][c];
+            }
+            if (!g.per[b] && ia[b] == g.n[b] - 1) {
+                sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
+                if (WALLS && wv->v[b][1][a]) fwall += (2.0 * (0.5 * (e_c + e_am)) * rvis) * wv->v[b][1][a][c];
+            }
             // skew advection, b != a
             const int ibn = wrap_next(ia[b], g.n[b]);
             const double mph = hi >= 0 ? mflux_mix<DIM>(g, mx, u.a[b], b, hi, ibn) : 0.0;
@@ -241,6 +252,7 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
     const double st = mx.capillary(c, cam);
     double f = (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
     if (a == 1 && k.inv_Fr != 0.0) f -= rf_new * k.inv_Fr;     // g_hat = (0, -1, 0)
+    if (WALLS) f += fwall;
     s[c] = sd;
     if (!coef_only) {
         rhs[c] = f;

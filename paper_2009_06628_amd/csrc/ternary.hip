@@ -240,6 +240,13 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup3(Geo g, StepConst k, int a
     CELL_LOOP(g.N) mom_setup_body<DIM>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c);
 }
 
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_mom_setup3_walls(Geo g, StepConst k, int a, MixPre mx, U3 u,
+                                                             double *__restrict__ s, W3 cs, double *__restrict__ rhs,
+                                                             double *__restrict__ ustar, int coef_only, WallVel wv) {
+    CELL_LOOP(g.N) mom_setup_body<DIM, MixPre, true>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c, &wv);
+}
+
 // T8 set-up
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_p_setup3(Geo g, StepConst k, MixPre mx, U3 us, double *__restrict__ s,
@@ -391,7 +398,12 @@ void launch_mix3_fields(const Geo &g, const StepConst &k, const TernConst &t, co
 
 void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
                        const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,
-                       hipStream_t st) {
+                       hipStream_t st, const WallVel *wv) {
+    if (wv) {
+        DISPATCH(K_MOM_SETUP, 11 + 2 * dim, dim, k_mom_setup3_walls, g.N, st, g, k, a, pre_of(k, t, ph), mk_u3(u), s,
+                 mk_w3(cs), rhs, ustar, 0, *wv);
+        return;
+    }
     DISPATCH(K_MOM_SETUP, 11 + 2 * dim, dim, k_mom_setup3, g.N, st, g, k, a, pre_of(k, t, ph), mk_u3(u), s, mk_w3(cs),
              rhs, ustar, 0);
 }

@@ -94,6 +94,11 @@ class Problem:
     def periodic(self) -> Tuple[bool, ...]:
         return tuple(b == PERIODIC for b in self.bc)
 
+    @property
+    def wall_velocity(self) -> Dict:
+        """Tangential velocities of moving walls (see wall_velocity())."""
+        return wall_velocity(self)
+
 
 # ---------------------------------------------------------------------------
 # coordinates
