@@ -490,10 +490,37 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  *                               set-up run one after another on the grid's
  *                               stream (kernel profiles without overlap);
  *                               0 (default): on their own streams.
+ *   CHNS_OPT_TIME_SCHEME        CHNS_SCHEME_SPLIT (default: the first-order
+ *                               split step S1..S9) or CHNS_SCHEME_CN (the
+ *                               second-order Crank-Nicolson variant, two-phase
+ *                               grids only; see below);
+ *   CHNS_OPT_PICARD_ITERATIONS  Picard iterations per Crank-Nicolson step
+ *                               (default 3).
  * Results do not depend on CHNS_OPT_SERIAL_COMPONENTS; the two S2 solvers
- * agree to the CH tolerance.                                              */
-enum { CHNS_OPT_CH_SOLVER = 1, CHNS_OPT_SERIAL_COMPONENTS = 2 };
+ * agree to the CH tolerance.
+ *
+ * Crank-Nicolson variant (the paper's time scheme: every term at the
+ * midpoint, v~ = (v^k + v^{k+1})/2, phi~, mu~, p~, rho(phi~), eta(phi~),
+ * psi'(phi~), advection (rho~ v~ + J~/Pe) . grad v~).  The library solves
+ * that nonlinear system by a fixed number of Picard iterations, each a
+ * sequence of the split step's linear solves: with the previous iterate
+ * phi~m, v~m, p~m,
+ *   C1-C4  (I - dt/2 kM S L + dt/2 kM Cn^2 L L) phi~ = phi^k - dt/2 D(v~m A phi~m)
+ *            + dt/2 kM L(psi'(phi~m) - S phi~m);  mu~ = psi'(phi~m) + S (phi~ - phi~m)
+ *            - Cn^2 L phi~;  phi^{k+1} = phi^k - dt D(v~m A phi~m - kM G mu~)
+ *   C5-C7  (2 rho~_f/dt) v~* - (1/Re) div(eta~ grad v~*) = (2 rho~_f/dt) v^k
+ *            - (m~ . grad) v~m - (1/We) G p~m - (1/(We Cn)) A(phi~m) G mu~ + rho~_f g_hat/Fr
+ *   C8-C9  -D(rho~_f^{-1} G dp) = -(2 We/dt) D v~*,  v~ = v~* - dt/(2 We) rho~_f^{-1} G dp,
+ *            p~ += dp
+ * and v^{k+1} = 2 v~ - v^k.  At a fixed point the stabiliser term and the
+ * pressure increment vanish and the midpoint system holds.  chns_step then
+ * returns mu~ in mu and the midpoint pressure in p; the momentum components
+ * run one after another on the grid's stream.  The adjoint, step records
+ * and the energy monitor cover the split step only.                        */
+enum { CHNS_OPT_CH_SOLVER = 1, CHNS_OPT_SERIAL_COMPONENTS = 2, CHNS_OPT_TIME_SCHEME = 3,
+       CHNS_OPT_PICARD_ITERATIONS = 4 };
 enum { CHNS_CH_DIRECT = 0, CHNS_CH_PCG = 1 };
+enum { CHNS_SCHEME_SPLIT = 0, CHNS_SCHEME_CN = 1 };
 int chns_set_option(struct chns_grid *g, int option, int value);
 
 /* Release the handle (host metadata only; device memory is the caller's). */

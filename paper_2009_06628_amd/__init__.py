@@ -23,8 +23,9 @@ LIB_PATH = os.path.join(HERE, "libchns.so")
 CHNS_OK, CHNS_ENOCONV, CHNS_EINVAL, CHNS_ENOMEM, CHNS_EDEVICE, CHNS_ENONFINITE = 0, 1, -1, -2, -3, -4
 CHNS_BC_PERIODIC, CHNS_BC_WALL = 0, 1
 CHNS_FP64, CHNS_FP32_REFINE = 0, 1
-CHNS_OPT_CH_SOLVER, CHNS_OPT_SERIAL_COMPONENTS = 1, 2
+CHNS_OPT_CH_SOLVER, CHNS_OPT_SERIAL_COMPONENTS, CHNS_OPT_TIME_SCHEME, CHNS_OPT_PICARD_ITERATIONS = 1, 2, 3, 4
 CHNS_CH_DIRECT, CHNS_CH_PCG = 0, 1
+CHNS_SCHEME_SPLIT, CHNS_SCHEME_CN = 0, 1
 
 
 class chns_grid_desc(ctypes.Structure):

@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libchns.so")
-SOURCES = ["api.hip", "mg.hip", "step.hip", "adjoint.hip", "batch.hip", "batch_tiled.hip", "spectral.hip", "noalloc.hip", "ternary.hip", "energy.hip"]
+SOURCES = ["api.hip", "mg.hip", "step.hip", "adjoint.hip", "batch.hip", "batch_tiled.hip", "spectral.hip", "noalloc.hip", "ternary.hip", "energy.hip", "cn.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

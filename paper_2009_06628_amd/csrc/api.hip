@@ -193,6 +193,15 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
         g->phi_new2 = g->phihat2 = g->rch2 = nullptr;
         for (int q = 0; q < 5; ++q) g->mix3[q] = nullptr;
     }
+    if (P.nph == 2) {   // Crank-Nicolson variant: midpoint iterates and pressure increment
+        g->cn_phim = B.take<double>(N);
+        g->cn_phimid = B.take<double>(N);
+        g->cn_dp = B.take<double>(N);
+        for (int a = 0; a < 3; ++a) g->cn_vt[a] = a < P.dim ? B.take<double>(N) : nullptr;
+    } else {
+        g->cn_phim = g->cn_phimid = g->cn_dp = nullptr;
+        for (int a = 0; a < 3; ++a) g->cn_vt[a] = nullptr;
+    }
     g->vr = B.take<double>(N);
     g->vz = B.take<double>(N);
     g->vp0 = B.take<double>(N);
@@ -502,6 +511,80 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     return CHNS_OK;
 }
 
+// One step of the Crank-Nicolson variant (Algorithm C: Picard iterations of
+// midpoint sub-steps, see cn.hip) from (phi, u, p) in place; mu receives
+// mu~ and p the midpoint pressure.  The momentum components run one after
+// another on the handle's stream.
+int cn_step(chns_grid *g, double *phi, double *const u[3], double *mu, double *pr, chns_step_stats &last) {
+    const int dim = g->dim;
+    const Geo &geo = g->geo;
+    const StepConst k = step_const(g);
+    StepConst kh = k;
+    kh.dt = 0.5 * k.dt;
+    const chns_props &p = g->props;
+    hipStream_t s = g->stream;
+    const ChOp ch{kh.dt * k.kM * p.S, kh.dt * k.kM * p.Cn * p.Cn, k.ih2};
+    const size_t bytes = sizeof(double) * geo.N;
+    double *phim = g->cn_phim, *phimid = g->cn_phimid;
+    double *vt[3] = {g->cn_vt[0], g->cn_vt[1], g->cn_vt[2]};
+    const double *vtc[3] = {vt[0], vt[1], vt[2]};
+    const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
+    Level<double> &P0 = g->pres.lev[0];
+    double *pcs[3] = {P0.cs[0], P0.cs[1], P0.cs[2]};
+    WallVel wv;
+    memcpy(wv.v, g->wall_u, sizeof wv.v);
+    const WallVel *pw = g->walls_move ? &wv : nullptr;
+    memset(&last, 0, sizeof last);
+    HIPCHK(hipMemcpyAsync(phim, phi, bytes, hipMemcpyDeviceToDevice, s));
+    for (int a = 0; a < dim; ++a) HIPCHK(hipMemcpyAsync(vt[a], u[a], bytes, hipMemcpyDeviceToDevice, s));
+    SolveOut o;
+    for (int it = 0; it < g->picard; ++it) {
+        memset(&last, 0, sizeof last);
+        // C1 - C4
+        launch_cn_ch_rhs(dim, geo, kh, phi, phim, vtc, g->rch, g->phihat, s);
+        HIPCHK(run_solve(g, 0, OP_CH, ch, (const double *)g->rch, g->phihat, p.rtol_ch, 0, &o));
+        if (int rc = check_solve(o, "Cahn-Hilliard")) return rc;
+        last.iters_ch = o.iters;
+        last.res_ch = o.rel_res;
+        last.unconverged |= o.unconverged ? 1 : 0;
+        launch_mu(dim, geo, k, phim, g->phihat, mu, s);
+        launch_cn_phi_update(dim, geo, k, phi, phim, vtc, mu, g->phi_new, phimid, s);
+        // C5 - C7
+        for (int a = 0; a < dim; ++a) {
+            SolveCtx c = mom_ctx(g, a);
+            c.s = s;
+            Level<double> &L0 = c.S64->lev[0];
+            double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
+            double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+            launch_cn_mom_setup(dim, geo, kh, a, phim, phimid, mu, vtc, L0.s, cs, rhs, g->ustar[a], u[a], pr, pw, s);
+            SolveOut om;
+            HIPCHK(run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om));
+            if (int rc = check_solve(om, "momentum")) return rc;
+            last.iters_mom[a] = om.iters;
+            last.res_mom[a] = om.rel_res;
+            last.unconverged |= om.unconverged ? (2 << a) : 0;
+        }
+        // C8, C9
+        launch_p_setup(dim, geo, kh, phimid, usc, P0.s, pcs, g->rhs, s, kPCoef | kPRhs);
+        remove_mean(geo, g->rhs, g->red, s);
+        launch_cn_zero(geo, g->cn_dp, s);
+        HIPCHK(run_solve_ctx(g, main_ctx(g, 2), 1, OP_SLOT, ch, (const double *)g->rhs, g->cn_dp, p.rtol_p, 4, &o));
+        if (int rc = check_solve(o, "pressure")) return rc;
+        last.iters_p = o.iters;
+        last.res_p = o.rel_res;
+        last.unconverged |= o.unconverged ? 16 : 0;
+        remove_mean(geo, g->cn_dp, g->red, s);
+        launch_cn_project(dim, geo, kh, phimid, usc, g->cn_dp, vt, pr, s);
+        double *t = phim;
+        phim = phimid;
+        phimid = t;
+    }
+    launch_cn_finish(dim, geo, vtc, u, phi, g->phi_new, s);
+    remove_mean(geo, pr, g->red, s);
+    HIPCHK(hipGetLastError());
+    return CHNS_OK;
+}
+
 // Adjoint workspace: the forward recomputation's p and mu, the cell and
 // face adjoints, and the parameter partials.
 void layout_adjoint(Bump &B, const Geo &geo, int dim, AdjBufs &A) {
@@ -614,6 +697,8 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     }
     // direct CH solve where the bases fit (chns_set_option can select MG-PCG)
     g->serial_components = 0;
+    g->scheme = CHNS_SCHEME_SPLIT;
+    g->picard = 3;
     memset(g->wall_u, 0, sizeof g->wall_u);
     g->walls_move = 0;
     if (g->spec.carved) {
@@ -692,6 +777,11 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     chns_step_stats last;
     memset(&last, 0, sizeof last);
     for (int n = 0; n < nsteps; ++n) {
+        if (g->scheme == CHNS_SCHEME_CN) {
+            if (int rc = cn_step(g, phi, u, mu, pr, last)) return rc;
+            unconv_any |= last.unconverged;
+            continue;
+        }
         if (int rc = forward_core(g, phi, uc, mu, pr, last, phi2, mu2)) return rc;
         // S9
         if (g->nph == 3) {
@@ -767,6 +857,7 @@ int chns_step_monitor(chns_grid *g, chns_state *st, chns_energy_monitor *out) {
     if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
     if (g->nph != 2) return fail(CHNS_EINVAL, "the energy monitor covers the two-phase step");
     if (g->walls_move) return fail(CHNS_EINVAL, "the energy monitor covers walls at rest");
+    if (g->scheme != CHNS_SCHEME_SPLIT) return fail(CHNS_EINVAL, "the energy monitor covers the split step");
     if (!st->phi || !st->p || !st->mu) return fail(CHNS_EINVAL, "state pointer is NULL");
     for (int a = 0; a < g->dim; ++a)
         if (!st->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
@@ -992,6 +1083,7 @@ int chns_adjoint_step(chns_grid *g, const chns_state *fwd, const chns_adj *lam_i
     if (!g || !fwd || !lam_in || !lam_out) return fail(CHNS_EINVAL, "NULL argument");
     if (!g->props_set) return fail(CHNS_EINVAL, "chns_set_properties must be called first");
     if (!g->adj_ready) return fail(CHNS_EINVAL, "chns_attach_adjoint_workspace must be called first");
+    if (g->scheme != CHNS_SCHEME_SPLIT) return fail(CHNS_EINVAL, "the discrete adjoint covers the split step");
     if (!fwd->phi || !fwd->p || !lam_in->phi || !lam_out->phi) return fail(CHNS_EINVAL, "state pointer is NULL");
     for (int a = 0; a < g->dim; ++a)
         if (!fwd->u[a] || !lam_in->u[a] || !lam_out->u[a]) return fail(CHNS_EINVAL, "velocity pointer is NULL");
@@ -1021,6 +1113,7 @@ static int check_record(const chns_grid *g, const chns_record *rec) {
 int chns_step_record(chns_grid *g, chns_state *st, const chns_record *rec) {
     if (!g) return fail(CHNS_EINVAL, "NULL argument");
     if (g->nph != 2) return fail(CHNS_EINVAL, "step records cover the two-phase step");
+    if (g->scheme != CHNS_SCHEME_SPLIT) return fail(CHNS_EINVAL, "step records cover the split step");
     if (int rc = check_record(g, rec)) return rc;
     const int rc = chns_step(g, st, 1, nullptr);
     if (rc != CHNS_OK && rc != CHNS_ENOCONV) return rc;
@@ -1126,6 +1219,17 @@ int chns_set_option(chns_grid *g, int option, int value) {
                 HIPCHK(hipStreamSynchronize(g->stream));
                 if (spectral_init(g->spec, g->h, err)) return fail(CHNS_EDEVICE, err);
             }
+            return CHNS_OK;
+        case CHNS_OPT_TIME_SCHEME:
+            if (value != CHNS_SCHEME_SPLIT && value != CHNS_SCHEME_CN)
+                return fail(CHNS_EINVAL, "time scheme must be CHNS_SCHEME_SPLIT or CHNS_SCHEME_CN");
+            if (value == CHNS_SCHEME_CN && g->nph != 2)
+                return fail(CHNS_EINVAL, "the Crank-Nicolson variant covers the two-phase step");
+            g->scheme = value;
+            return CHNS_OK;
+        case CHNS_OPT_PICARD_ITERATIONS:
+            if (value < 1 || value > 1000) return fail(CHNS_EINVAL, "Picard iterations must be in 1..1000");
+            g->picard = value;
             return CHNS_OK;
         case CHNS_OPT_SERIAL_COMPONENTS:
             if (value != 0 && value != 1) return fail(CHNS_EINVAL, "serial-components value must be 0 or 1");

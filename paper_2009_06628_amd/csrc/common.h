@@ -357,6 +357,8 @@ struct chns_grid {
     hipEvent_t ev_pset;                      // recorded on pstream after that set-up
     int mc_ready;                            // streams and events of mc and the pressure set-up created
     int serial_components;                   // CHNS_OPT_SERIAL_COMPONENTS
+    int scheme, picard;                      // CHNS_OPT_TIME_SCHEME, CHNS_OPT_PICARD_ITERATIONS
+    double *cn_phim, *cn_phimid, *cn_dp, *cn_vt[3];   // Crank-Nicolson iterates (two-phase grids)
     const double *wall_u[3][2][3];           // moving-wall data [axis][side][component] (caller-owned)
     int walls_move;                          // any of them set
     int adj_ready;                           // adjoint workspace attached

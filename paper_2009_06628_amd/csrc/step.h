@@ -70,6 +70,21 @@ void launch_energy_monitor(int dim, const Geo &g, const StepConst &k, const doub
                            const double *const s[3], const double *const cs[3][3], double *part,
                            unsigned int *counter, double *out, hipStream_t st);
 
+// Crank-Nicolson variant (cn.hip): kh is the step constants with dt/2.
+void launch_cn_ch_rhs(int dim, const Geo &g, const StepConst &kh, const double *phik, const double *phim,
+                      const double *const vm[3], double *r, double *phihat, hipStream_t st);
+void launch_cn_phi_update(int dim, const Geo &g, const StepConst &k, const double *phik, const double *phim,
+                          const double *const vm[3], const double *mu, double *phin, double *phimid, hipStream_t st);
+void launch_cn_mom_setup(int dim, const Geo &g, const StepConst &kh, int a, const double *phim,
+                         const double *phimid, const double *mu, const double *const vm[3], double *s,
+                         double *const cs[3], double *rhs, double *ustar, const double *vk, const double *pm,
+                         const WallVel *wv, hipStream_t st);
+void launch_cn_project(int dim, const Geo &g, const StepConst &kh, const double *phimid,
+                       const double *const ustar[3], const double *dp, double *const vt[3], double *p, hipStream_t st);
+void launch_cn_finish(int dim, const Geo &g, const double *const vt[3], double *const u[3], double *phi,
+                      const double *phin, hipStream_t st);
+void launch_cn_zero(const Geo &g, double *x, hipStream_t st);
+
 // S1: r = phi - dt D(u A phi) + dt kM L(psi'(phi) - S phi); phihat = phi.
 void launch_ch_rhs(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
                    double *r, double *phihat, hipStream_t st);

@@ -167,11 +167,18 @@ __device__ inline void phi_update_cell(const Geo &g, const StepConst &k, const d
 // WALLS: some walls move (wv their tangential velocities): the no-slip ghost
 // value next to such a wall is 2 U - u instead of -u, which adds 2 k U to
 // the right-hand side of the row (k the wall edge's coefficient).
-template <int DIM, typename Mix, bool WALLS = false>
+// CN: the midpoint momentum equation of the Crank-Nicolson variant, for the
+// unknown v~ with k.dt = dt/2: the operator (2 rho~_f/dt) - (1/Re) div(eta~ grad),
+// the right-hand side (2 rho~_f/dt) v^k (vk) - (m~ . grad) v~m - capillary
+// - (1/We) G p~m (pm) + gravity, where u holds v~m and mx the midpoint
+// mixture; the advection is the advective form (the advective half of the
+// skew-symmetric operator) instead of the skew-symmetric one.
+template <int DIM, typename Mix, bool WALLS = false, bool CN = false>
 __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, const Mix &mx, const U3 &u,
                                       double *__restrict__ s, const W3 &cs, double *__restrict__ rhs,
                                       double *__restrict__ ustar, int coef_only, int c,
-                                      const WallVel *wv = nullptr) {
+                                      const WallVel *wv = nullptr, const double *__restrict__ vk = nullptr,
+                                      const double *__restrict__ pm = nullptr) {
     const double rvis = k.inv_Re * k.ih2;
     int i, j, kk;
     if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
@@ -216,7 +223,7 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
             const double mp = 0.5 * (m_c + m_hi), mm = 0.5 * (m_lo + m_c);
             const double up = hi >= 0 ? ua[hi] : 0.0;
             const double um = (!g.per[a] && ia[a] == 1) ? 0.0 : ua[lo];   // wall face
-            nadv += mp * up - mm * um;
+            nadv += CN ? mp * (up - ua[c]) + mm * (ua[c] - um) : mp * up - mm * um;
         } else {
             // viscous coupling through the edge between faces c - e_b and c
             if (lo >= 0) {
@@ -245,12 +252,13 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
             const double uc = ua[c];
             const double up = hi >= 0 ? ua[hi] : -uc;
             const double um = lo >= 0 ? ua[lo] : -uc;
-            nadv += mp * up - mm * um;
+            nadv += CN ? mp * (up - uc) + mm * (uc - um) : mp * up - mm * um;
         }
     }
     nadv *= 0.5 * k.ih;
     const double st = mx.capillary(c, cam);
-    double f = (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
+    double f = CN ? rf_new / k.dt * vk[c] - nadv - st - k.inv_We * ((pm[c] - pm[cam]) * k.ih)
+                  : (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
     if (a == 1 && k.inv_Fr != 0.0) f -= rf_new * k.inv_Fr;     // g_hat = (0, -1, 0)
     if (WALLS) f += fwall;
     s[c] = sd;
