@@ -15,6 +15,7 @@
 #include "step.h"
 #include "adjoint.h"
 #include "plan.h"
+#include "pool.h"
 
 using namespace chns;
 
@@ -351,6 +352,37 @@ SolveCtx main_ctx(chns_grid *g, int which) {
 }
 
 // Buffers of momentum component a (0: the handle's own).
+// The handle's host worker threads (created on first use; null if the
+// threads could not be started).
+WorkerPool *grid_pool(chns_grid *g) {
+    if (!g->pool) {
+        try {
+            g->pool = new WorkerPool();
+        } catch (...) {
+            g->pool = nullptr;
+        }
+    }
+    return g->pool;
+}
+
+// Waits for a worker's task when leaving a scope (early returns included).
+struct TaskWait {
+    WorkerPool *pool = nullptr;
+    int w = 0;
+    bool active = false;
+    void start(WorkerPool *p, int worker, std::function<void()> f) {
+        pool = p;
+        w = worker;
+        active = true;
+        p->run(worker, std::move(f));
+    }
+    void wait() {
+        if (active) pool->wait(w);
+        active = false;
+    }
+    ~TaskWait() { wait(); }
+};
+
 SolveCtx mom_ctx(chns_grid *g, int a) {
     if (a == 0) return main_ctx(g, 1);
     MomCtx &M = g->mc[a - 1];
@@ -448,29 +480,43 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     auto momentum = [&](int a) {
         const SolveCtx c = mom_ctx(g, a);
         if (a > 0 && concurrent) {
-            em[a] = hipStreamWaitEvent(c.s, g->ev_fork, 0);
+            em[a] = hipStreamWaitEvent(c.s, g->ev_mset, 0);
             if (em[a] != hipSuccess) return;
         }
-        Level<double> &L0 = c.S64->lev[0];
         double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
-        double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
+        em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
+        if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
+    };
+    // S5..S7 set-up of every component in one pass on the handle's stream
+    // (the pressure set-up stream forks before it: it needs only phi_new)
+    if (concurrent) HIPCHK(hipEventRecord(g->ev_fork, s));
+    {
+        MomOut mo{};
+        for (int a = 0; a < dim; ++a) {
+            Level<double> &L0 = mom_ctx(g, a).S64->lev[0];
+            mo.s[a] = L0.s;
+            for (int b = 0; b < 3; ++b) mo.cs[a][b] = L0.cs[b];
+            mo.rhs[a] = a == 0 ? g->rhs : g->mc[a - 1].rhs;
+            mo.ustar[a] = g->ustar[a];
+        }
         WallVel wv;
         memcpy(wv.v, g->wall_u, sizeof wv.v);
         const WallVel *pw = g->walls_move ? &wv : nullptr;
         if (tern)
-            launch_mom_setup3(dim, geo, k, g->tern, ph, a, uc, L0.s, cs, rhs, g->ustar[a], c.s, pw);
+            launch_mom_setup3_all(dim, geo, k, g->tern, ph, uc, mo, s, pw);
         else
-            launch_mom_setup(dim, geo, k, a, phi, g->phi_new, mu, uc, L0.s, cs, rhs, g->ustar[a], c.s, 0, pw);
-        em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
-        if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
-    };
+            launch_mom_setup_all(dim, geo, k, phi, g->phi_new, mu, uc, mo, s, pw);
+    }
     if (concurrent) {
-        HIPCHK(hipEventRecord(g->ev_fork, s));
-        std::thread workers[3];
-        for (int a = 1; a < dim; ++a) workers[a - 1] = std::thread(momentum, a);
-        workers[dim - 1] = std::thread(pressure_setup);
-        momentum(0);
-        for (int a = 1; a <= dim; ++a) workers[a - 1].join();
+        HIPCHK(hipEventRecord(g->ev_mset, s));
+        WorkerPool *pool = grid_pool(g);
+        if (!pool) return fail(CHNS_EDEVICE, "host worker threads could not be started");
+        {
+            TaskWait tw[3];
+            for (int a = 1; a < dim; ++a) tw[a - 1].start(pool, a - 1, [&momentum, a]() { momentum(a); });
+            tw[2].start(pool, 2, pressure_setup);
+            momentum(0);
+        }
         for (int a = 1; a < dim; ++a)
             if (em[a] == hipSuccess) em[a] = hipStreamWaitEvent(s, g->mc[a - 1].done_ev, 0);
         if (ep == hipSuccess) ep = hipStreamWaitEvent(s, g->ev_pset, 0);
@@ -642,6 +688,10 @@ static void release_streams(chns_grid *g) {
         (void)hipEventDestroy(g->ev_fork);
         g->ev_fork = nullptr;
     }
+    if (g->ev_mset) {
+        (void)hipEventDestroy(g->ev_mset);
+        g->ev_mset = nullptr;
+    }
     g->mc_ready = 0;
 }
 
@@ -674,6 +724,8 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     // of the pressure set-up
     g->mc_ready = 0;
     g->ev_fork = nullptr;
+    g->ev_mset = nullptr;
+    g->pool = nullptr;
     g->pstream = nullptr;
     g->ev_pset = nullptr;
     for (int a = 0; a < 2; ++a) {
@@ -688,6 +740,7 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
         }
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&g->pstream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_pset, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g->ev_mset, hipEventDisableTiming);
         if (e != hipSuccess) {
             release_streams(g);
             delete g;
@@ -969,16 +1022,12 @@ static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F,
     // the adjoint pressure solve runs; the solves then skip the set-up.
     const bool concurrent = dim > 1 && g->mc_ready && !g_prof && !serial_momentum(g);
     hipError_t eset = hipSuccess;
-    std::thread setup_thread;
-    struct Joiner {
-        std::thread &t;
-        ~Joiner() {
-            if (t.joinable()) t.join();
-        }
-    } joiner{setup_thread};
+    WorkerPool *pool = concurrent ? grid_pool(g) : nullptr;
+    if (concurrent && !pool) return fail(CHNS_EDEVICE, "host worker threads could not be started");
+    TaskWait setup_task;
     if (concurrent) {
         HIPCHK(hipEventRecord(g->ev_fork, s));
-        setup_thread = std::thread([&]() {
+        setup_task.start(pool, 2, [&]() {
             for (int a = 0; a < dim && eset == hipSuccess; ++a) {
                 SolveCtx c = mom_ctx(g, a);
                 c.s = a == 0 ? g->pstream : g->mc[a - 1].stream;
@@ -1008,7 +1057,7 @@ static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F,
     // component in order (they accumulate into shared adjoint fields)
     {
         if (concurrent) {
-            setup_thread.join();
+            setup_task.wait();
             if (eset != hipSuccess)
                 return fail(CHNS_EDEVICE, std::string("adjoint momentum set-up: ") + hipGetErrorString(eset));
         }
@@ -1034,10 +1083,12 @@ static int adjoint_core(chns_grid *g, const chns_state *fwd, const FwdFields &F,
         if (concurrent) {
             HIPCHK(hipStreamWaitEvent(s, g->ev_pset, 0));   // component 0's operator
             HIPCHK(hipEventRecord(g->ev_fork, s));
-            std::thread workers[2];
-            for (int a = 1; a < dim; ++a) workers[a - 1] = std::thread(nu_solve, a, g->mc[a - 1].stream);
-            nu_solve(0, s);
-            for (int a = 1; a < dim; ++a) workers[a - 1].join();
+            {
+                TaskWait tw[2];
+                for (int a = 1; a < dim; ++a)
+                    tw[a - 1].start(pool, a - 1, [&nu_solve, a, sa = g->mc[a - 1].stream]() { nu_solve(a, sa); });
+                nu_solve(0, s);
+            }
             for (int a = 1; a < dim; ++a)
                 if (em[a] == hipSuccess) em[a] = hipStreamWaitEvent(s, g->mc[a - 1].done_ev, 0);
         } else {
@@ -1306,6 +1357,8 @@ int chns_get_timing(chns_grid *g, chns_kernel_timing *out, int max, int *count) 
 
 int chns_destroy_grid(chns_grid *g) {
     if (g) {
+        delete g->pool;
+        g->pool = nullptr;
         prof_release(g->prof);
         release_streams(g);
         spectral_release(g->spec);

@@ -11,6 +11,7 @@
 #include "../../include/chns.h"
 
 namespace chns {
+class WorkerPool;
 
 constexpr int kMaxLev = 16;
 constexpr int kMaxCoarse = 512;     // cells of the coarsest (dense) level
@@ -353,6 +354,8 @@ struct chns_grid {
     chns::MomCtx mc[2];                      // momentum components 1, 2 (component 0 uses the buffers above)
     chns::Spectral spec;                     // direct CH solve (single grids)
     hipEvent_t ev_fork;                      // main stream -> component streams
+    hipEvent_t ev_mset;                      // main stream after the momentum set-up -> component streams
+    chns::WorkerPool *pool;                  // host threads of the concurrent solves (created on first use)
     hipStream_t pstream;                     // pressure set-up during the momentum solves
     hipEvent_t ev_pset;                      // recorded on pstream after that set-up
     int mc_ready;                            // streams and events of mc and the pressure set-up created

@@ -196,6 +196,96 @@ __global__ void __launch_bounds__(kGThreads) k_axis_gemm(int M, int N, int K, Ax
         }
 }
 
+// 64 x 64 output tile on the FP64 matrix cores: the four waves of the
+// workgroup form a 2 x 2 grid of 32 x 32 blocks, each four 16 x 16 x 4 MFMA
+// accumulators.  Staging and chunks (KC = 32) as in k_axis_gemm<64>.
+// Operand layout of the FP64 16 x 16 x 4 MFMA: lane l supplies A(l % 16,
+// l / 16) and B(l / 16, l % 16); element v of its accumulator is
+// C(4 v + l / 16, l % 16).  Values staged past M, N or K are zero, so every
+// chunk runs all of its k.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kGThreads) k_axis_mfma64(int M, int N, int K, AxOp A, AxOp B, AxOut C) {
+    constexpr int TS = 64, KC = 2048 / TS, PT = TS * KC / kGThreads;
+    __shared__ double As[KC][TS + 1], Bs[KC][TS + 1];
+    const int bz = (int)blockIdx.z;
+    const double *a = A.at(bz), *bp = B.at(bz);
+    double *c = C.at(bz);
+    const int m0 = (int)blockIdx.y * TS, n0 = (int)blockIdx.x * TS;
+    const int tid = (int)threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = (w >> 1) * 32, wn = (w & 1) * 32, li = lane & 15, lk = lane >> 4;
+    auto a_pos = [&](int e, int &mm, int &kk) {
+        if (A.s1 == 1) {
+            kk = e % KC;
+            mm = e / KC;
+        } else {
+            mm = e % TS;
+            kk = e / TS;
+        }
+    };
+    auto b_pos = [&](int e, int &nn, int &kk) {
+        if (B.s1 == 1) {
+            nn = e % TS;
+            kk = e / TS;
+        } else {
+            kk = e % KC;
+            nn = e / KC;
+        }
+    };
+    double ra[PT], rb[PT];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            int mm, kk, nn, kb;
+            a_pos(tid + kGThreads * r, mm, kk);
+            b_pos(tid + kGThreads * r, nn, kb);
+            const int gm = m0 + mm, gk = k0 + kk, gn = n0 + nn, gkb = k0 + kb;
+            ra[r] = (gm < M && gk < K) ? a[(long long)gm * A.s0 + (long long)gk * A.s1] : 0.0;
+            rb[r] = (gn < N && gkb < K) ? bp[(long long)gkb * B.s0 + (long long)gn * B.s1] : 0.0;
+        }
+    };
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += KC) {
+#pragma unroll
+        for (int r = 0; r < PT; ++r) {
+            int mm, kk, nn, kb;
+            a_pos(tid + kGThreads * r, mm, kk);
+            b_pos(tid + kGThreads * r, nn, kb);
+            As[kk][mm] = ra[r];
+            Bs[kb][nn] = rb[r];
+        }
+        __syncthreads();
+        if (k0 + KC < K) fetch(k0 + KC);   // in flight during the products below
+#pragma unroll
+        for (int k4 = 0; k4 < KC; k4 += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = As[k4 + lk][wm + 16 * i + li];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[k4 + lk][wn + 16 * j + li];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gm = m0 + wm + 16 * i + 4 * v + lk, gn = n0 + wn + 16 * j + li;
+                if (gm < M && gn < N) c[(long long)gm * C.s0 + (long long)gn * C.s1] = acc[i][j][v];
+            }
+}
+
 // 16 x 16 output tile with k split over 16 thread groups: thread t of group
 // g computes the 4 x 4 block of rows t / 4 + 4 i and columns t % 4 + 4 j over
 // the k of each chunk with k mod 16 = g (half an LDS read per FMA, where one
@@ -294,8 +384,8 @@ __global__ void __launch_bounds__(kGThreads) k_axis_gemm16s(int M, int N, int K,
 static void axis_gemm(int M, int N, int K, const AxOp &A, const AxOp &B, const AxOut &C, int batch, hipStream_t st) {
     auto tiles = [&](int t) { return (long long)((M + t - 1) / t) * ((N + t - 1) / t) * batch; };
     if (tiles(64) >= 256)
-        hipLaunchKernelGGL(k_axis_gemm<64>, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(kGThreads), 0, st, M, N,
-                           K, A, B, C);
+        hipLaunchKernelGGL(k_axis_mfma64, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(kGThreads), 0, st, M, N, K,
+                           A, B, C);
     else if (tiles(32) >= 256)
         hipLaunchKernelGGL(k_axis_gemm<32>, dim3((N + 31) / 32, (M + 31) / 32, batch), dim3(kGThreads), 0, st, M, N,
                            K, A, B, C);

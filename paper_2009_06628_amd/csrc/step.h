@@ -21,6 +21,15 @@ struct WallVel {
     const double *v[3][2][3];
 };
 
+// Outputs of the set-up of every momentum component (component a: level-0
+// coefficients s, cs[b] of its hierarchy, right-hand side, initial guess).
+struct MomOut {
+    double *s[3];
+    double *cs[3][3];   // [component][direction]
+    double *rhs[3];
+    double *ustar[3];
+};
+
 // Three-phase constants (TernConst, common.h) from the properties.
 TernConst tern_const_of(const chns_props &p);
 
@@ -48,6 +57,9 @@ void launch_mix3_fields(const Geo &g, const StepConst &k, const TernConst &t, co
 void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
                        const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,
                        hipStream_t st, const WallVel *wv = nullptr);
+// T5-T7 set-up of every component in one pass (as launch_mom_setup_all).
+void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
+                           const double *const u[3], const MomOut &o, hipStream_t st, const WallVel *wv = nullptr);
 // T8 set-up (parts as launch_p_setup).
 void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], double *s, double *const cs[3], double *rhs, hipStream_t st,
@@ -100,6 +112,12 @@ void launch_phi_update(int dim, const Geo &g, const StepConst &k, const double *
 void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const double *phi, const double *phi_new,
                       const double *mu, const double *const u[3], double *s, double *const cs[3], double *rhs,
                       double *ustar, hipStream_t st, int coef_only = 0, const WallVel *wv = nullptr);
+// S5-S7 set-up of all d components in one pass (each thread sets up the
+// faces of every axis at its cell index): the components read the same
+// mixture, flux and velocity fields, so one sweep over them replaces d.
+void launch_mom_setup_all(int dim, const Geo &g, const StepConst &k, const double *phi, const double *phi_new,
+                          const double *mu, const double *const u[3], const MomOut &o, hipStream_t st,
+                          const WallVel *wv = nullptr);
 // S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new)
 // (part & kPCoef) and rhs = -(We/dt) D ustar (part & kPRhs).  The
 // coefficients need only phi_new, so the step sets them and the pressure

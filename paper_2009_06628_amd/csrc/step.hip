@@ -64,6 +64,15 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup_walls(Geo g, StepConst k, 
     CELL_LOOP(g.N) mom_setup_body<DIM, Mix2, true>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c, &wv);
 }
 
+// All components in one pass.
+template <int DIM, bool WALLS>
+__global__ void __launch_bounds__(kBlock) k_mom_setup_all(Geo g, StepConst k, const double *__restrict__ phi,
+                                                          const double *__restrict__ phin,
+                                                          const double *__restrict__ mu, U3 u, MomOut o, WallVel wv) {
+    const Mix2 mx = mk_mix2(k, phi, phin, mu);
+    CELL_LOOP(g.N) mom_setup_all_body<DIM, Mix2, WALLS>(g, k, mx, u, o, c, &wv);
+}
+
 // ---------------------------------------------------------------------------
 // S8 set-up
 // ---------------------------------------------------------------------------
@@ -200,6 +209,30 @@ void launch_mom_setup(int dim, const Geo &g, const StepConst &k, int a, const do
     }
     DISPATCH(K_MOM_SETUP, 6 + 2 * dim, dim, k_mom_setup, g.N, st, g, k, a, phi, phi_new, mu, mk_u3(u), s, mk_w3(cs), rhs,
              ustar, coef_only);
+}
+void launch_mom_setup_all(int dim, const Geo &g, const StepConst &k, const double *phi, const double *phi_new,
+                          const double *mu, const double *const u[3], const MomOut &o, hipStream_t st,
+                          const WallVel *wv) {
+    WallVel w{};
+    if (wv) w = *wv;
+    // phi, phi_new, mu and u[d] read; s, cs[d], rhs, ustar written per component
+    const double bytes = 8.0 * (3 + dim + dim * (3 + dim)) * g.N;
+    const dim3 grid(grid_for(g.N)), block(kBlock);
+    if (dim == 2) {
+        if (wv)
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup_all<2, true>), grid, block, st, g, k, phi, phi_new, mu, mk_u3(u),
+                    o, w);
+        else
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup_all<2, false>), grid, block, st, g, k, phi, phi_new, mu, mk_u3(u),
+                    o, w);
+    } else {
+        if (wv)
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup_all<3, true>), grid, block, st, g, k, phi, phi_new, mu, mk_u3(u),
+                    o, w);
+        else
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup_all<3, false>), grid, block, st, g, k, phi, phi_new, mu, mk_u3(u),
+                    o, w);
+    }
 }
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
                     double *s, double *const cs[3], double *rhs, hipStream_t st, int part) {

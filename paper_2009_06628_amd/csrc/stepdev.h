@@ -268,6 +268,18 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
     }
 }
 
+// Set-up of every component at cell index c (the face of axis a at c for
+// component a), one component after the other with the body above.
+template <int DIM, typename Mix, bool WALLS = false>
+__device__ inline void mom_setup_all_body(const Geo &g, const StepConst &k, const Mix &mx, const U3 &u,
+                                          const MomOut &o, int c, const WallVel *wv = nullptr) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const W3 cs{{o.cs[a][0], o.cs[a][1], o.cs[a][2]}};
+        mom_setup_body<DIM, Mix, WALLS>(g, k, a, mx, u, o.s[a], cs, o.rhs[a], o.ustar[a], 0, c, wv);
+    }
+}
+
 template <int DIM>
 __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, const double *__restrict__ phi,
                                       const double *__restrict__ phin, const double *__restrict__ mu, const U3 &u,

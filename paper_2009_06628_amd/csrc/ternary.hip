@@ -247,6 +247,11 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup3_walls(Geo g, StepConst k,
     CELL_LOOP(g.N) mom_setup_body<DIM, MixPre, true>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c, &wv);
 }
 
+template <int DIM, bool WALLS>
+__global__ void __launch_bounds__(kBlock) k_mom_setup3_all(Geo g, StepConst k, MixPre mx, U3 u, MomOut o, WallVel wv) {
+    CELL_LOOP(g.N) mom_setup_all_body<DIM, MixPre, WALLS>(g, k, mx, u, o, c, &wv);
+}
+
 // T8 set-up
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_p_setup3(Geo g, StepConst k, MixPre mx, U3 us, double *__restrict__ s,
@@ -406,6 +411,27 @@ void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernCons
     }
     DISPATCH(K_MOM_SETUP, 11 + 2 * dim, dim, k_mom_setup3, g.N, st, g, k, a, pre_of(k, t, ph), mk_u3(u), s, mk_w3(cs),
              rhs, ustar, 0);
+}
+
+void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
+                           const double *const u[3], const MomOut &o, hipStream_t st, const WallVel *wv) {
+    WallVel w{};
+    if (wv) w = *wv;
+    const MixPre mx = pre_of(k, t, ph);
+    // the five mixture fields, phi_1, phi_2, mu_1, mu_2 and u[d] read; s, cs[d], rhs, ustar written per component
+    const double bytes = 8.0 * (9 + dim + dim * (3 + dim)) * g.N;
+    const dim3 grid(grid_for(g.N)), block(kBlock);
+    if (dim == 2) {
+        if (wv)
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup3_all<2, true>), grid, block, st, g, k, mx, mk_u3(u), o, w);
+        else
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup3_all<2, false>), grid, block, st, g, k, mx, mk_u3(u), o, w);
+    } else {
+        if (wv)
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup3_all<3, true>), grid, block, st, g, k, mx, mk_u3(u), o, w);
+        else
+            TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup3_all<3, false>), grid, block, st, g, k, mx, mk_u3(u), o, w);
+    }
 }
 
 void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
