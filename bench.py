@@ -8,8 +8,8 @@ velocity perturbation of amplitude 1e-2), in two arithmetic forms on the same
 input:
   fp64         FP64 throughout, at the solver tolerances the oracle parity
                tests use (CH 1e-15, momentum 1e-13, pressure 1e-12)
-  fp32_refine  the precision form: FP32 multigrid preconditioner under FP64
-               CG and FP64 iterative refinement, at its own tolerances
+  fp32_refine  the precision form: FP32 multigrid preconditioner inside FP64
+               CG (FP64 vectors, operator apply and dots), at its own tolerances
                (1e-10 / 1e-10 / 1e-9)
 A step is one full pass T1..T9 (two CH solves, three momentum components,
 pressure projection).  Inputs are synthetic and already resident in device

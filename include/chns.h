@@ -102,8 +102,10 @@ enum { CHNS_FP64 = 0, CHNS_FP32_REFINE = 1 };
  * 2D); h the uniform cell size; bc[a] per axis: periodic, or no-slip /
  * no-flux walls on both ends (paper: boundary conditions of the
  * mass-conservation proposition).  precision selects the arithmetic of the
- * linear solves (CHNS_FP64, or FP32 multigrid sweeps under an FP64 outer
- * refinement).  nphases = 2 (the paper's two-phase model) or 3 (three-phase
+ * linear solves (CHNS_FP64, or FP64 conjugate gradients preconditioned by
+ * FP32 multigrid: vectors, operator apply, updates, dot products and the
+ * coarsest inverse in FP64; coefficients, sweeps and transfers of the
+ * V-cycle in FP32).  nphases = 2 (the paper's two-phase model) or 3 (three-phase
  * model, see below; single grids only -- the batched and adjoint entry
  * points reject it).
  * Supported sizes: every n[a] >= 2 and even, and repeated halving of all axes
@@ -454,8 +456,8 @@ int chns_get_timing(struct chns_grid *g, chns_kernel_timing *out, int max, int *
  * coarsest inverse, the precision form about 156: the 256 x 512 grid fits).
  * rho, rhs: cell arrays (device, float64; rhs projected to mean zero
  * internally, not modified); p: initial guess on entry, solution with mean
- * zero on exit.  desc->precision selects FP64 or the FP32 multigrid under
- * FP64 refinement; desc->nphases is ignored.  Runs on hip_stream (NULL: the
+ * zero on exit.  desc->precision selects FP64 or FP64 CG with the FP32
+ * multigrid preconditioner; desc->nphases is ignored.  Runs on hip_stream (NULL: the
  * default stream) and synchronises it before returning.  Every call on a
  * GPU shares that GPU's array and leaves its contents behind: calls that
  * overlap on one GPU (from several threads or streams) race and must be

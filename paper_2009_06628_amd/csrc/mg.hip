@@ -1070,7 +1070,7 @@ static void precond_cg_d(Slot<TP> &SP, OpKind kind, const TP *r, TP *z, TP *w, c
 template <typename T, typename TP, int DIM>
 static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T *b, T *x, double rtol, int max_iter,
                         int predict, Red &red, const PcgVecs2<T, TP> &v, hipStream_t st, SolveOut *out,
-                        int zero_guess, int check_init = 0) {
+                        int zero_guess) {
     constexpr double W = sizeof(T);
     constexpr double WP = sizeof(TP);
     const Level<T> &L0 = SA.lev[0];
@@ -1093,22 +1093,6 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
     LAUNCH1(K_PCG_INIT, 16.0 * nb, (k_pcg_fin_init), kBlock, st, sc, (const double *)red.part0,
             (const double *)red.part1, nb, rtol, max_iter);
     Scal hs;
-    if (check_init) {
-        // refinement round: return at once if the true residual already meets
-        // the tolerance (no V-cycle or early-exit launches are queued)
-        hipError_t e = hipMemcpyAsync(&hs, sc, sizeof(Scal), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return e;
-        if (hs.done) {
-            if (out) {
-                out->iters = 0;
-                out->rel_res = hs.bb > 0.0 ? sqrt(hs.rr / hs.bb) : 0.0;
-                out->unconverged = 0;
-                out->nonfinite = hs.nonfinite;
-            }
-            return hipGetLastError();
-        }
-    }
     // With a lower-precision hierarchy the V-cycle reads the residual
     // already rounded to its precision (the value its sweeps would round it
     // to), so the level-0 passes read 4 instead of 8 bytes per cell of it.
@@ -1220,11 +1204,13 @@ hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x
 }
 
 // ---------------------------------------------------------------------------
-// precision form: FP32 multigrid-preconditioned CG inside an FP64 iterative
-// refinement.  The outer loop computes the residual r = b - A x in FP64 with
-// the FP64 level-0 coefficients, solves A e = r in FP32 (FP32 vectors,
-// coefficients and sweeps; FP64 dot products and coarse inverse) and adds e
-// in FP64, until ||r||_2 <= rtol max(||b||_2, ||r_0||_2) as in the FP64 form.
+// precision form: FP64 CG preconditioned by the FP32 hierarchy.  x, r, p,
+// q, the level-0 operator of the CG recurrence, its updates and every dot
+// product are FP64; the V-cycle runs on FP32 coefficients, sweeps and
+// transfers (FP64 coarsest inverse) and returns z in FP32.  The initial
+// residual is the true FP64 residual b - A x of the starting iterate and the
+// recurrence residual is that of an FP64 CG, so the solve stops on the FP64
+// form's test, ||r||_2 <= rtol max(||b||_2, ||r_0||_2).
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_conv_coef(Level<double> A, Level<float> B) {
@@ -1248,29 +1234,11 @@ template <int DIM>
 static hipError_t refine_d(Slot<double> &S64, Slot<float> &S32, OpKind kind, ChOp ch, const double *b, double *x,
                            double rtol, int max_iter, int *predict, Red &red, const PcgVecs2<double, float> &v,
                            hipStream_t st, SolveOut *out) {
-    // Rounds of FP64 PCG with the FP32 V-cycle preconditioner, each started
-    // from the current x: its initial residual is the true FP64 residual
-    // b - A x, so the loop ends when that residual meets the tolerance
-    // (a round that converges at its initial residual).
-    int total = 0;
     SolveOut o;
-    o.iters = 0;
-    o.rel_res = 0.0;
-    o.unconverged = 1;
-    o.nonfinite = 0;
-    for (int round = 0; round < kMaxRefine && total < max_iter; ++round) {
-        hipError_t e = pcg_d<double, float, DIM>(S64, S32, kind, ch, b, x, rtol, max_iter - total,
-                                                 round == 0 ? *predict : 2, red, v, st, &o, 0, round > 0);
-        if (e != hipSuccess) return e;
-        total += o.iters;
-        if (o.nonfinite) break;
-        if (o.iters > 0 && round == 0) *predict = o.iters;
-        if (o.iters == 0 && !o.unconverged) break;   // true residual already within tolerance
-    }
-    if (out) {
-        *out = o;
-        out->iters = total;
-    }
+    hipError_t e = pcg_d<double, float, DIM>(S64, S32, kind, ch, b, x, rtol, max_iter, *predict, red, v, st, &o, 0);
+    if (e != hipSuccess) return e;
+    if (o.iters > 0) *predict = o.iters;
+    if (out) *out = o;
     return hipGetLastError();
 }
 

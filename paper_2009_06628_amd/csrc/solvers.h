@@ -51,13 +51,14 @@ hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x
                      int max_iter, int predict, Red &red, PcgVecs<T> &v, hipStream_t st,
                      SolveOut *out, int zero_guess = 0);
 
-// Precision form: FP64 conjugate gradients (residual recurrence, updates and
-// dot products in FP64) preconditioned by FP32 V-cycles (FP32 coefficients,
-// smoother sweeps and transfers; FP64 coarsest inverse), wrapped in FP64
-// iterative refinement: rounds restart from the current x with the true
-// FP64 residual until it meets the tolerance.  S64 supplies the FP64
+// Precision form: FP64 conjugate gradients (residual recurrence, operator
+// apply, updates and dot products in FP64) preconditioned by FP32 V-cycles
+// (FP32 coefficients, smoother sweeps and transfers; FP64 coarsest
+// inverse).  Its initial residual is the true FP64 residual of the starting
+// iterate and it stops on the FP64 form's test.  S64 supplies the FP64
 // level-0 operator, S32 the FP32 hierarchy (level-0 coefficients converted by
 // convert_level0 and coarsened by mg_setup<float> beforehand).
+// FP64 refinement rounds of the batched precision form (at most).
 constexpr int kMaxRefine = 4;
 void convert_level0(const Slot<double> &A, Slot<float> &B, int dim, hipStream_t st);
 hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kind, ChOp ch, const double *b,

@@ -602,8 +602,8 @@ def ensemble_stratified(per_size: int = 3, seed: int = 4, sizes=(64, 96, 128, 19
     return out
 
 
-# Solver tolerances of the precision form (FP32 multigrid under FP64
-# refinement): its budget is 1e-5 relative to the FP64 oracle, so the solves
+# Solver tolerances of the precision form (FP64 CG with the FP32 multigrid
+# preconditioner): its budget is 1e-5 relative to the FP64 oracle, so the solves
 # stop at these looser relative residuals (measured error ~2e-7).
 PRECISION_FORM_TOLERANCES = dict(rtol_ch=1e-10, rtol_mom=1e-10, rtol_p=1e-9)
 
