@@ -206,7 +206,8 @@ int chns_set_properties(struct chns_grid *g, const chns_props *props);
  * stream.  If stats is not NULL the call synchronises the stream and fills
  * it (solver statistics of the last step, diagnostics of the final state).
  * The momentum solves of the components and the pressure set-up run on
- * their own streams, driven by host threads of the call (serially on the
+ * their own streams, driven by host worker threads of the handle (created
+ * on its first such step, joined by chns_destroy_grid; serially on the
  * grid's stream while per-kernel timing is on, or with the option
  * CHNS_OPT_SERIAL_COMPONENTS set); the results do not depend on which.
  * Returns CHNS_ENOCONV if any solve of any step hit max_iter.            */
