@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for the HBM byte counters)")
     ap.add_argument("--hbm-shapes", default="512^3,8192^2", help="grids of the hbm_sweeps measurement")
+    ap.add_argument("--batched-form", default="auto",
+                    help="batched leg: 'auto' (autotuned), 'tiled:TILE_CELLS' or 'persistent:THREADS:BLOCKS' "
+                         "(fixed form, no autotuning: profiling runs)")
     ap.add_argument("--traffic-from", nargs="+", metavar="WORKLOAD=FETCH_CSV,WRITE_CSV",
                     help="no GPU run: build profiles/traffic.json from rocprofv3 --pmc counter CSVs of bench.py "
                          "runs (one FETCH_SIZE and one WRITE_SIZE pass per workload, each with --calibrate-copy)")
@@ -111,7 +114,7 @@ def recorded_traffic(workload, kernel_class):
 KERNEL_CLASSES = {
     "smooth": ("k_presmooth_pair", "k_presmooth", "k_gs_color"),
     "residual": ("k_residual",),
-    "restrict": ("k_restrict3_pair", "k_restrict"),
+    "restrict": ("k_restrict3_lds", "k_restrict3_pair", "k_restrict"),
     "prolong": ("k_prolong_add3",),
     "coarse_solve": ("k_vcycle_lds", "k_vcycle_block"),
     "mg_down": ("k_down_tile2", "k_down_tile2_cg"),
@@ -119,6 +122,16 @@ KERNEL_CLASSES = {
     "pcg_apply": ("k_pcg_apply3_march", "k_pcg_apply_slot", "k_pcg_ch_lap", "k_pcg_ch_apply"),
     "pcg_update": ("k_pcg_update", "k_pcg_fin_rr"),
     "pcg_dot": ("k_pcg_rz",),
+    # the batched tiled form (one launch per sweep over the tiles of all problems)
+    "t_down": ("k_t_down2",),
+    "t_up": ("k_t_up2",),
+    "t_apply": ("k_t_apply",),
+    "t_update": ("k_t_update", "k_t_fin_rr"),
+    "t_dot": ("k_t_rz", "k_t_fin_rz"),
+    "t_small_levels": ("k_t_vcycle_small_lds", "k_t_vcycle_small"),
+    "t_sweep": ("k_t_sweep", "k_t_restrict"),
+    "t_phase": ("k_t_phase",),
+    "ch_spectral": ("k_axis_mfma64", "k_axis_gemm", "k_axis_gemm16s", "k_spectral_scale_batch", "k_spectral_scale"),
 }
 
 # Which dispatches of a profiled bench.py run belong to a workload: the
@@ -130,6 +143,7 @@ WORKLOAD_FILTERS = {
     "rising_bubble_256x512_fp64": lambda args: True,
     "pressure_512^3_fp64": lambda args: True,
     "pressure_8192^2_fp64": lambda args: True,
+    "ensemble_512_fp32_refine": lambda args: True,
 }
 TRAFFIC_SOURCES = ["paper_2009_06628_amd/csrc/mg.hip", "paper_2009_06628_amd/csrc/mgdev.h",
                    "paper_2009_06628_amd/csrc/common.h", "paper_2009_06628_amd/csrc/tile2d.h"]
@@ -353,18 +367,29 @@ def bench_hbm_sweeps(P, W, hbm_shapes):
     return out
 
 
-def bench_batched(P, W, steps):
-    """Batched ensemble: 512 problems, FP32 + refinement; autotuned form and
-    launch shape; timed eagerly (solves run to convergence with host checks)
-    and as a captured hipGraph (fixed per-solve iteration budgets)."""
+def bench_batched(P, W, steps, form="auto", cpu_problems=0):
+    """Batched ensemble: 512 problems, precision form; autotuned form and
+    launch shape (or a fixed one); timed eagerly (solves run to convergence
+    with host checks) and as a captured hipGraph (fixed per-solve iteration
+    budgets).  cpu_problems > 0: the oracle's step on the first members of the
+    ensemble as its CPU baseline."""
     probs = W.ensemble(count=512, seed=4, steps=200, **W.PRECISION_FORM_TOLERANCES)
     b = P.create_batch(probs, P.CHNS_FP32_REFINE, device="cuda:0")
     st = b.new_state([W.initial_state(p) for p in probs])
-    tune = b.autotune(st, 1)
     out = {"workload": "ensemble_512_oscillating_drops_fp32_refine", "problems": len(probs),
-           "cells": b.total_cells, "steps": steps,
-           "form": tune["mode"], "tile_cells": tune["tile_cells"], "graph_budgets": list(tune["budgets"]),
-           "autotune_ms_per_step": {"%s_%d_%d" % (c[0], c[1], c[2]): round(c[3], 2) for c in tune["candidates"]}}
+           "cells": b.total_cells, "steps": steps}
+    if form == "auto":
+        tune = b.autotune(st, 1)
+        out.update({"form": tune["mode"], "tile_cells": tune["tile_cells"], "graph_budgets": list(tune["budgets"]),
+                    "autotune_ms_per_step": {"%s_%d_%d" % (c[0], c[1], c[2]): round(c[3], 2)
+                                             for c in tune["candidates"]}})
+    else:
+        parts = form.split(":")
+        if parts[0] == "tiled":
+            b.set_tiled(int(parts[1]))
+        else:
+            b.set_launch(int(parts[1]), int(parts[2]))
+        out.update({"form": parts[0], "launch": [int(x) for x in parts[1:]]})
     for label, graph in (("eager", False), ("graph", True)):
         b.step(st, steps, use_graph=graph, stats=False)     # warm-up (and capture)
         _sync()
@@ -377,6 +402,8 @@ def bench_batched(P, W, steps):
                       "unconverged": sum(1 for s in stats if s["flags"])}
     out["value"] = out["graph"]["value"]
     out["ms_per_step"] = out["graph"]["ms_per_step"]
+    if cpu_problems > 0:
+        out["cpu_baseline"] = cpu_baseline_batched(probs[:cpu_problems])
     return out
 
 
@@ -450,6 +477,28 @@ def cpu_baseline(prob, steps):
             "sample": "%d step(s) of the %dx%dx%d three-phase drops from the initial state, FP64, one thread "
                       "(%.1f s; host CPU: %s, %d logical CPUs)"
                       % (steps, prob.n[0], prob.n[1], prob.n[2], dt, _cpu_model(), os.cpu_count() or 0)}
+
+
+def cpu_baseline_batched(probs):
+    """The two-phase oracle on the host: one step of each given member of the
+    ensemble from its initial state, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
+    from oracle import MACGrid, Params
+    from oracle import chns as C
+
+    cells = sum(p.cells for p in probs)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for p in probs:
+            C.step(MACGrid(p.n, p.h, p.periodic), W.initial_state(p), Params.from_props(p.props))
+        dt = time.perf_counter() - t0
+    sizes = sorted(set(p.n[0] for p in probs))
+    return {"value": round(cells / dt, 1), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "one step of each of the first %d members of the 512-problem ensemble (n in %s, %d cells), "
+                      "FP64, one thread (%.1f s; host CPU: %s, %d logical CPUs)"
+                      % (len(probs), sizes, cells, dt, _cpu_model(), os.cpu_count() or 0)}
 
 
 def main():
@@ -541,7 +590,8 @@ def main():
                                                args.profile_steps if not args.no_profile else 0,
                                                args.serial_components),
                 "hbm_sweeps": lambda: bench_hbm_sweeps(P, W, args.hbm_shapes),
-                "batched": lambda: bench_batched(P, W, args.extra_steps),
+                "batched": lambda: bench_batched(P, W, args.extra_steps, args.batched_form,
+                                                 0 if args.no_cpu_baseline else 16),
                 "adjoint": lambda: bench_adjoint(P, W)}
         for name in EXTRAS:
             if name in extras:

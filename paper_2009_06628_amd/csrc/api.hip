@@ -446,8 +446,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     // S3, S4
     if (tern) {
         launch_mu3(dim, geo, k, g->tern, ph, g->phihat, g->phihat2, s);
-        launch_phi_update3(dim, geo, k, ph, uc, s);
-        launch_mix3_fields(geo, k, g->tern, ph, s);
+        launch_phi_update3(dim, geo, k, g->tern, ph, uc, s);
     } else {
         launch_mu(dim, geo, k, phi, g->phihat, mu, s);
         launch_phi_update(dim, geo, k, phi, uc, mu, g->phi_new, s);

@@ -79,13 +79,6 @@ __global__ void __launch_bounds__(kBlock) k_residual(Level<T> L, const TB *__res
     GRID_LOOP(L.g.N) residual_cell<T, TB, DIM>(L, b, x, c);
 }
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kBlock) k_restrict(Geo gf, Geo gc, const T *__restrict__ rf, T *__restrict__ bc,
-                                                     const int *__restrict__ done) {
-    if (*done) return;
-    GRID_LOOP(gc.N) restrict_cell<T, DIM>(gf, gc, rf, bc, c);
-}
-
 // Two consecutive values along x (the pair starts at an even index).
 template <typename T>
 struct Pair2 {
@@ -152,67 +145,78 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add3(Geo gf, Geo gc, const T
     }
 }
 
-// 3D restriction, one thread per two x-adjacent coarse cells (I even): each
-// fine row is read as four aligned pairs covering the taps 2I-1 .. 2I+4 of
-// both cells; the weights and summation order are those of restrict_cell.
-// Needs an even coarse x extent.
+// 3D restriction through LDS: a workgroup takes a tile of kRCX x kRCY x kRCZ
+// coarse cells and stages the fine cells 2I-1 .. 2I+2 of all of them once
+// (wrapped on periodic axes; clamped at walls, where restrict_cell gives
+// those taps weight 0 and reads the same clamped cell); each thread then
+// sums the 64 taps of its coarse cell out of LDS with the weights and the
+// summation order of restrict_cell.  The per-thread form read every fine
+// value eight times from the caches, 64 loads per coarse cell.
+constexpr int kRCX = 16, kRCY = 4, kRCZ = 4;   // coarse tile (kRCX * kRCY * kRCZ = kBlock)
+constexpr int kRFX = 2 * kRCX + 2, kRFY = 2 * kRCY + 2, kRFZ = 2 * kRCZ + 2;
+static_assert(kRCX * kRCY * kRCZ == kBlock, "one coarse cell per thread");
+
+// Fine index of staged position g (>= -1): one wrap on a periodic axis (the
+// taps of coarse cells inside the grid reach -1 .. n at most), clamped to the
+// grid otherwise and for positions past a partial tile's last coarse cell.
+__device__ inline int res_fine_index(int g, int n, int per) {
+    if (per) g = g < 0 ? g + n : (g >= n ? g - n : g);
+    return g < 0 ? 0 : (g >= n ? n - 1 : g);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict3_pair(Geo gf, Geo gc, const T *__restrict__ rf,
-                                                           T *__restrict__ bc, const int *__restrict__ done) {
-    if (*done) return;
+__global__ void __launch_bounds__(kBlock) k_restrict3_lds(Geo gf, Geo gc, const T *__restrict__ rf,
+                                                          T *__restrict__ bc, int ntx, int nty, int ntiles,
+                                                          const int *__restrict__ done) {
     using R = T;
-    GRID_LOOP(gc.N / 2) {
-        int I[3];
-        coords_of<3>(gc, 2 * c, I);
-        int fx[2][4], fy[4], fz[4];
-        R wx[2][4], wy[4], wz[4];
-        res_axis<R>(I[0], (int)gc.n[0], (int)gf.n[0], gc.per[0], fx[0], wx[0]);
-        res_axis<R>(I[0] + 1, (int)gc.n[0], (int)gf.n[0], gc.per[0], fx[1], wx[1]);
-        res_axis<R>(I[1], (int)gc.n[1], (int)gf.n[1], gc.per[1], fy, wy);
-        res_axis<R>(I[2], (int)gc.n[2], (int)gf.n[2], gc.per[2], fz, wz);
-        // pair starts 2I-2, 2I, 2I+2, 2I+4 (wrapped on a periodic axis; an
-        // out-of-range pair outside a wall only feeds taps of weight 0 and
-        // is read from the nearest pair in range)
-        const int nfx = (int)gf.n[0];
-        int p0[4];
+    const int tile = xcd_block();
+    if (tile >= ntiles || *done) return;
+    __shared__ T sf[kRFZ][kRFY][kRFX];
+    const int tz = tile / (ntx * nty), trem = tile - tz * ntx * nty, ty = trem / ntx, tx = trem - ty * ntx;
+    const int X0 = tx * kRCX, Y0 = ty * kRCY, Z0 = tz * kRCZ;
+    const int nfx = (int)gf.n[0], nfy = (int)gf.n[1], nfz = (int)gf.n[2];
+    // every staging load of a thread is issued before its first LDS store
+    constexpr int kStage = kRFX * kRFY * kRFZ, kPer = (kStage + kBlock - 1) / kBlock;
+    T v[kPer];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            int st = 2 * I[0] - 2 + 2 * k;
-            if (gc.per[0])
-                st = st < 0 ? st + nfx : (st >= nfx ? st - nfx : st);
-            else
-                st = st < 0 ? 0 : (st >= nfx ? nfx - 2 : st);
-            p0[k] = st;
+    for (int r = 0; r < kPer; ++r) {
+        const int e = (int)threadIdx.x + r * kBlock;
+        if (e < kStage) {
+            const int z = e / (kRFX * kRFY), r2 = e - z * (kRFX * kRFY), y = r2 / kRFX, x = r2 - y * kRFX;
+            const int gx = res_fine_index(2 * X0 - 1 + x, nfx, gc.per[0]);
+            const int gy = res_fine_index(2 * Y0 - 1 + y, nfy, gc.per[1]);
+            const int gz = res_fine_index(2 * Z0 - 1 + z, nfz, gc.per[2]);
+            v[r] = rf[(gz * nfy + gy) * nfx + gx];
         }
-        const int nxy = nfx * (int)gf.n[1];
-        R v0 = 0.0, v1 = 0.0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int kz = fz[a] * nxy;
-            const R wza = wz[a];
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int row = kz + fy[qq] * nfx;
-                R t[8];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const Pair2<T> pr = *(const Pair2<T> *)(rf + row + p0[k]);
-                    t[2 * k] = (R)pr.v[0];
-                    t[2 * k + 1] = (R)pr.v[1];
-                }
-                // t[j] holds fine 2I-2+j: cell I taps j = 1..4, cell I+1 taps j = 3..6
-                R s0 = 0.0, s1 = 0.0;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) s0 += wx[0][e] * t[1 + e];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) s1 += wx[1][e] * t[3 + e];
-                v0 += (wy[qq] * wza) * s0;
-                v1 += (wy[qq] * wza) * s1;
-            }
-        }
-        bc[2 * c] = (T)v0;
-        bc[2 * c + 1] = (T)v1;
     }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int e = (int)threadIdx.x + r * kBlock;
+        if (e < kStage) (&sf[0][0][0])[e] = v[r];
+    }
+    __syncthreads();
+    const int lx = (int)threadIdx.x % kRCX, ly = ((int)threadIdx.x / kRCX) % kRCY, lz = (int)threadIdx.x / (kRCX * kRCY);
+    const int I[3] = {X0 + lx, Y0 + ly, Z0 + lz};
+    if (I[0] >= gc.n[0] || I[1] >= gc.n[1] || I[2] >= gc.n[2]) return;
+    int f[4];
+    R wx[4], wy[4], wz[4];
+    res_axis<R>(I[0], gc.n[0], nfx, gc.per[0], f, wx);
+    res_axis<R>(I[1], gc.n[1], nfy, gc.per[1], f, wy);
+    res_axis<R>(I[2], gc.n[2], nfz, gc.per[2], f, wz);
+    R acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const R wza = wz[a];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T *row = &sf[2 * lz + a][2 * ly + q][2 * lx];
+            R s = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s += wx[e] * (R)row[e];
+            acc += (wy[q] * wza) * s;
+        }
+    }
+    bc[(I[2] * (int)gc.n[1] + I[1]) * (int)gc.n[0] + I[0]] = (T)acc;
 }
 
 template <typename T, typename TB, int DIM>
@@ -939,12 +943,14 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
     else
         LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
     LAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual<T, TB, DIM>), N, st, lv, b, (const T *)x, done);
-    if (DIM == 3 && (S.lev[l + 1].g.n[0] & 1) == 0)
-        LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict3_pair<T>), Nc / 2, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
-               S.lev[l + 1].b, done);
-    else
-        LAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict<T, DIM>), Nc, st, lv.g, S.lev[l + 1].g, (const T *)lv.r,
-               S.lev[l + 1].b, done);
+    {
+        const Geo &gc = S.lev[l + 1].g;
+        const int ntx = (int)((gc.n[0] + kRCX - 1) / kRCX), nty = (int)((gc.n[1] + kRCY - 1) / kRCY);
+        const int ntiles = ntx * nty * (int)((gc.n[2] + kRCZ - 1) / kRCZ);
+        const int grid = ntiles > 8 ? (ntiles + 7) & ~7 : ntiles;
+        TLAUNCH(K_RESTRICT, W * (N + Nc), (k_restrict3_lds<T>), dim3(grid), dim3(kBlock), st, lv.g, gc,
+                (const T *)lv.r, S.lev[l + 1].b, ntx, nty, ntiles, done);
+    }
 }
 
 template <typename T, typename TB, int DIM, typename TR = T>

@@ -204,9 +204,11 @@ __global__ void __launch_bounds__(kGThreads) k_axis_gemm(int M, int N, int K, Ax
 // C(4 v + l / 16, l % 16).  Values staged past M, N or K are zero, so every
 // chunk runs all of its k.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaKC = 32;   // k per staged chunk
 
+template <int KC>
 __global__ void __launch_bounds__(kGThreads) k_axis_mfma64(int M, int N, int K, AxOp A, AxOp B, AxOut C) {
-    constexpr int TS = 64, KC = 2048 / TS, PT = TS * KC / kGThreads;
+    constexpr int TS = 64, PT = TS * KC / kGThreads;
     __shared__ double As[KC][TS + 1], Bs[KC][TS + 1];
     const int bz = (int)blockIdx.z;
     const double *a = A.at(bz), *bp = B.at(bz);
@@ -384,8 +386,8 @@ __global__ void __launch_bounds__(kGThreads) k_axis_gemm16s(int M, int N, int K,
 static void axis_gemm(int M, int N, int K, const AxOp &A, const AxOp &B, const AxOut &C, int batch, hipStream_t st) {
     auto tiles = [&](int t) { return (long long)((M + t - 1) / t) * ((N + t - 1) / t) * batch; };
     if (tiles(64) >= 256)
-        hipLaunchKernelGGL(k_axis_mfma64, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(kGThreads), 0, st, M, N, K,
-                           A, B, C);
+        hipLaunchKernelGGL(k_axis_mfma64<kMfmaKC>, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(kGThreads), 0, st, M,
+                           N, K, A, B, C);
     else if (tiles(32) >= 256)
         hipLaunchKernelGGL(k_axis_gemm<32>, dim3((N + 31) / 32, (M + 31) / 32, batch), dim3(kGThreads), 0, st, M, N,
                            K, A, B, C);

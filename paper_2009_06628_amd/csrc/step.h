@@ -48,15 +48,10 @@ void launch_ch_rhs3(int dim, const Geo &g, const StepConst &k, const TernConst &
 // T3: mu~_i from phihat_i.
 void launch_mu3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, const double *hat1,
                 const double *hat2, hipStream_t st);
-// T4: phi_i^{n+1}.
-void launch_phi_update3(int dim, const Geo &g, const StepConst &k, const Phases3 &ph, const double *const u[3],
-                        hipStream_t st);
-// Mixture fields of the step (after T4; read by the set-up and projection).
-void launch_mix3_fields(const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, hipStream_t st);
-// T5-T7 set-up of momentum component a.
-void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
-                       const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,
-                       hipStream_t st, const WallVel *wv = nullptr);
+// T4: phi_i^{n+1}, and the per-step mixture fields read by the set-up and
+// projection (rho^{n+1}, rho^n, eta^{n+1}, rho_lin^n, chi), from the same pass.
+void launch_phi_update3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
+                        const double *const u[3], hipStream_t st);
 // T5-T7 set-up of every component in one pass (as launch_mom_setup_all).
 void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                            const double *const u[3], const MomOut &o, hipStream_t st, const WallVel *wv = nullptr);

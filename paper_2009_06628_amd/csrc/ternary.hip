@@ -19,6 +19,11 @@
 
 namespace chns {
 
+// Five cell arrays written by one kernel.
+struct W5 {
+    double *a[5];
+};
+
 // Mixture policy of the three-phase model (see stepdev.h for the interface).
 struct Mix3 {
     double rho[3], eta[3];
@@ -58,7 +63,7 @@ struct Mix3 {
 };
 
 // The same mixture read from cell fields computed once per step by
-// k_mix3_fields (rho^{n+1}, rho^n with the pull-back, eta^{n+1}, rho_lin^n and
+// k_phi_update3 (rho^{n+1}, rho^n with the pull-back, eta^{n+1}, rho_lin^n and
 // chi = (kM/2) sum_{i=1,2} (rho_i - rho_3) mu~_i, so that J = -G chi): the
 // momentum set-up evaluates the mass flux on up to 11 faces per cell and
 // component, and the three-phase maps are the costly part of it.
@@ -99,19 +104,6 @@ static Mix3 mk_mix3(const StepConst &k, const TernConst &t, const double *phi1, 
     m.mu1 = mu1;
     m.mu2 = mu2;
     return m;
-}
-
-// Cell fields of MixPre (one pass per step, after T4).
-__global__ void __launch_bounds__(kBlock) k_mix3_fields(long long N, Mix3 mx, double *__restrict__ rn,
-                                                        double *__restrict__ ro, double *__restrict__ en,
-                                                        double *__restrict__ rl, double *__restrict__ chi) {
-    CELL_LOOP(N) {
-        rn[c] = mx.rho_new(c);
-        ro[c] = mx.rho_old(c);
-        en[c] = mx.eta_new(c);
-        rl[c] = mx.rho_lin(c);
-        chi[c] = mx.jc[0] * mx.mu1[c] + mx.jc[1] * mx.mu2[c];
-    }
 }
 
 __device__ inline double lambda3(double p1, double p2) {
@@ -205,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) k_phi_update3(Geo g, StepConst k, cons
                                                         const double *__restrict__ phi2, U3 u,
                                                         const double *__restrict__ mu1,
                                                         const double *__restrict__ mu2, double *__restrict__ pn1,
-                                                        double *__restrict__ pn2) {
+                                                        double *__restrict__ pn2, Mix3 mx, W5 fields) {
     CELL_LOOP(g.N) {
         int i, j, kk;
         cc<DIM>(g, c, i, j, kk);
@@ -227,26 +219,20 @@ __global__ void __launch_bounds__(kBlock) k_phi_update3(Geo g, StepConst k, cons
                 div2 += phi_face_flux(k, ua, p2, phi2[hi], m2, mu2[hi]);
             }
         }
-        pn1[c] = p1 - k.dt * (div1 * k.ih);
-        pn2[c] = p2 - k.dt * (div2 * k.ih);
+        const double q1 = p1 - k.dt * (div1 * k.ih), q2 = p2 - k.dt * (div2 * k.ih);
+        pn1[c] = q1;
+        pn2[c] = q2;
+        // the cell fields of MixPre: rho^{n+1}, rho^n (pull-back), eta^{n+1},
+        // rho_lin^n and chi = (kM/2) sum_{i=1,2} (rho_i - rho_3) mu~_i
+        fields.a[0][c] = Mix3::mixc(mx.rho, q1, q2);
+        fields.a[1][c] = Mix3::mixc(mx.rho, p1, p2);
+        fields.a[2][c] = Mix3::mixc(mx.eta, q1, q2);
+        fields.a[3][c] = mx.rho_lin(c);
+        fields.a[4][c] = mx.jc[0] * m1 + mx.jc[1] * m2;
     }
 }
 
-// T5-T7 set-up for component a (the binary body with the three-phase mixture)
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_mom_setup3(Geo g, StepConst k, int a, MixPre mx, U3 u,
-                                                       double *__restrict__ s, W3 cs, double *__restrict__ rhs,
-                                                       double *__restrict__ ustar, int coef_only) {
-    CELL_LOOP(g.N) mom_setup_body<DIM>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c);
-}
-
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_mom_setup3_walls(Geo g, StepConst k, int a, MixPre mx, U3 u,
-                                                             double *__restrict__ s, W3 cs, double *__restrict__ rhs,
-                                                             double *__restrict__ ustar, int coef_only, WallVel wv) {
-    CELL_LOOP(g.N) mom_setup_body<DIM, MixPre, true>(g, k, a, mx, u, s, cs, rhs, ustar, coef_only, c, &wv);
-}
-
+// T5-T7 set-up of every component (the binary body with the three-phase mixture)
 template <int DIM, bool WALLS>
 __global__ void __launch_bounds__(kBlock) k_mom_setup3_all(Geo g, StepConst k, MixPre mx, U3 u, MomOut o, WallVel wv) {
     CELL_LOOP(g.N) mom_setup_all_body<DIM, MixPre, WALLS>(g, k, mx, u, o, c, &wv);
@@ -370,14 +356,16 @@ void launch_mu3(int dim, const Geo &g, const StepConst &k, const TernConst &t, c
     DISPATCH(K_MU, 6, dim, k_mu3, g.N, st, g, k, t, ph.phi[0], ph.phi[1], hat1, hat2, ph.mu[0], ph.mu[1]);
 }
 
-void launch_phi_update3(int dim, const Geo &g, const StepConst &k, const Phases3 &ph, const double *const u[3],
-                        hipStream_t st) {
-    DISPATCH(K_PHI_UPDATE, 6 + dim, dim, k_phi_update3, g.N, st, g, k, ph.phi[0], ph.phi[1], mk_u3(u), ph.mu[0],
-             ph.mu[1], ph.phin[0], ph.phin[1]);
-}
-
 static Mix3 mix_of(const StepConst &k, const TernConst &t, const Phases3 &ph) {
     return mk_mix3(k, t, ph.phi[0], ph.phi[1], ph.phin[0], ph.phin[1], ph.mu[0], ph.mu[1]);
+}
+
+void launch_phi_update3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
+                        const double *const u[3], hipStream_t st) {
+    const W5 f{{ph.mix[0], ph.mix[1], ph.mix[2], ph.mix[3], ph.mix[4]}};
+    // phi_i, mu_i, u[d] read; phi_i^{n+1} and the five mixture fields written
+    DISPATCH(K_PHI_UPDATE, 4 + dim + 7, dim, k_phi_update3, g.N, st, g, k, ph.phi[0], ph.phi[1], mk_u3(u), ph.mu[0],
+             ph.mu[1], ph.phin[0], ph.phin[1], mix_of(k, t, ph), f);
 }
 
 static MixPre pre_of(const StepConst &k, const TernConst &t, const Phases3 &ph) {
@@ -394,23 +382,6 @@ static MixPre pre_of(const StepConst &k, const TernConst &t, const Phases3 &ph) 
     m.mu1 = ph.mu[0];
     m.mu2 = ph.mu[1];
     return m;
-}
-
-void launch_mix3_fields(const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, hipStream_t st) {
-    TLAUNCH(K_MOM_SETUP, 8.0 * 11 * g.N, k_mix3_fields, dim3(grid_for(g.N)), dim3(kBlock), st, g.N, mix_of(k, t, ph),
-            ph.mix[0], ph.mix[1], ph.mix[2], ph.mix[3], ph.mix[4]);
-}
-
-void launch_mom_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, int a,
-                       const double *const u[3], double *s, double *const cs[3], double *rhs, double *ustar,
-                       hipStream_t st, const WallVel *wv) {
-    if (wv) {
-        DISPATCH(K_MOM_SETUP, 11 + 2 * dim, dim, k_mom_setup3_walls, g.N, st, g, k, a, pre_of(k, t, ph), mk_u3(u), s,
-                 mk_w3(cs), rhs, ustar, 0, *wv);
-        return;
-    }
-    DISPATCH(K_MOM_SETUP, 11 + 2 * dim, dim, k_mom_setup3, g.N, st, g, k, a, pre_of(k, t, ph), mk_u3(u), s, mk_w3(cs),
-             rhs, ustar, 0);
 }
 
 void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
