@@ -778,6 +778,35 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     return CHNS_OK;
 }
 
+// Diagonal dominance at which a 3D momentum V-cycle ends: the first grid
+// level l >= 1 where the smallest diagonal shift rho_min / dt is at least
+// kMomTruncRatio times the largest sum of the level's off-diagonal
+// couplings, 2 d eta_max / (Re h_l^2) (the re-discretised coarse operators
+// scale their couplings by (h / h_l)^2).  One symmetric Gauss-Seidel sweep
+// solves such a level to ~1/ratio^2, and the levels below it would add
+// corrections of that size; ending there saves their launches and set-up.
+constexpr double kMomTruncRatio = 30.0;
+
+static int momentum_trunc_level(const chns_grid *g, const chns_props &p) {
+    if (g->dim != 3) return 0;
+    double rho_min, eta_max;
+    if (g->nph == 3) {
+        rho_min = std::min(p.rho3[0], std::min(p.rho3[1], p.rho3[2]));
+        eta_max = std::max(p.eta3[0], std::max(p.eta3[1], p.eta3[2]));
+    } else {
+        rho_min = std::min(1.0, p.rho_minus);
+        eta_max = std::max(1.0, p.eta_minus);
+    }
+    const Slot<double> &S = g->mom;
+    const double shift = rho_min / p.dt;
+    for (int l = 1; l < S.nlev && S.lev[l].g.N > kSBCells; ++l) {
+        const double hl = g->h * (double)(1 << l);
+        const double off = 2.0 * g->dim * eta_max / (p.Re * hl * hl);
+        if (shift >= kMomTruncRatio * off) return l;
+    }
+    return 0;
+}
+
 int chns_set_properties(chns_grid *g, const chns_props *p) {
     if (!g || !p) return fail(CHNS_EINVAL, "NULL argument");
     if (int rc = check_props(p)) return rc;
@@ -793,6 +822,11 @@ int chns_set_properties(chns_grid *g, const chns_props *p) {
     }
     g->props = *p;
     g->props_set = 1;
+    {
+        const int lt = momentum_trunc_level(g, *p);
+        g->mom.ltrunc = g->mom32.ltrunc = lt;
+        for (int a = 0; a < 2; ++a) g->mc[a].mom.ltrunc = g->mc[a].mom32.ltrunc = lt;
+    }
     const StepConst k = step_const(g);
     const double cb = p->dt * k.kM * p->Cn * p->Cn;
     double *cs[3] = {g->ch.lev[0].cs[0], g->ch.lev[0].cs[1], g->ch.lev[0].cs[2]};

@@ -214,6 +214,8 @@ template <typename T>
 struct Slot {
     int nlev;
     int lsb;        // first level handled by the single-workgroup kernel
+    int ltrunc;     // 3D: the V-cycle ends at this grid level with a symmetric
+                    // Gauss-Seidel solve (0: full cycle down to the coarsest)
     int singular;
     int ncoarse;
     Level<T> lev[kMaxLev];

@@ -4,6 +4,11 @@
 
 namespace chns {
 
+// Multigrid levels at or below this many cells run in the single-workgroup
+// kernel.
+constexpr int kSBCells = 2048;
+
+
 enum OpKind { OP_SLOT = 0, OP_CH = 1 };
 
 template <typename T>

@@ -188,6 +188,20 @@ def test_drop3d_parity():
     compare_states(sg, so, 3, 1e-10)
 
 
+def test_drop3d_truncated_momentum_cycle_parity():
+    """Momentum operator dominated by its diagonal shift (Re = 1000 at 32^3:
+    rho_min / dt = 1e3 against 2 d eta_max / (Re h_1^2) = 1.5 on the 16^3
+    level, ratio ~650 >= 30): the 3D momentum V-cycles end at that level with
+    a symmetric Gauss-Seidel sweep.  20 steps against the oracle."""
+    prob = W.drop3d(32, steps=20, Re=1000.0)
+    h1 = 2.0 * prob.h
+    assert (0.1 / prob.props.dt) >= 30.0 * 6.0 * 1.0 / (prob.props.Re * h1 * h1)
+    _, sg, stats = run_gpu(prob, 20)
+    _, so, _ = run_oracle(prob, 20)
+    print("stats", stats, flush=True)
+    compare_states(sg, so, 3, 1e-10)
+
+
 def test_flat_interface_stays_at_rest_gpu():
     prob = W.flat_interface(32, 32, steps=100, gravity=True)
     _, sg, stats = run_gpu(prob, 100)

@@ -67,6 +67,9 @@ CASES = {
         (48, 64), "ternary_drops", {"seed": 22, "count": 2, "rmin": 0.1, "rmax": 0.15, "gap": 0.08,
                                     "velocity": "stream", "vseed": 8, "vamp": 0.1},
         bc=(W.PERIODIC, W.WALL), inv_Fr=1.0, rho3=(3.0, 0.2, 1.0), steps=100),
+    # densities (100, 10, 1), viscosities 1e-2, Re = 1, dt = 1e-4: the momentum
+    # shift 1e4 is ~650x the off-diagonal sum of the 16^3 level, so the 3D
+    # momentum V-cycles end there (symmetric Gauss-Seidel solve)
     "drops3d_32": lambda: W.ternary_drops3d(32, steps=100),
 }
 
