@@ -82,6 +82,10 @@ def parse():
     ap.add_argument("--traffic-from", nargs="+", metavar="WORKLOAD=FETCH_CSV,WRITE_CSV",
                     help="no GPU run: build profiles/traffic.json from rocprofv3 --pmc counter CSVs of bench.py "
                          "runs (one FETCH_SIZE and one WRITE_SIZE pass per workload, each with --calibrate-copy)")
+    ap.add_argument("--dispatch-table", nargs=3, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: per kernel and launch size, mean duration and counter bytes per dispatch "
+                         "(the largest --top entries by total time)")
+    ap.add_argument("--top", type=int, default=20)
     ap.add_argument("--durations-from", nargs="+", metavar="WORKLOAD=KERNEL_TRACE_CSV",
                     help="no GPU run: print per kernel class dispatch counts and mean durations from rocprofv3 "
                          "--kernel-trace CSVs, with the class filters of --traffic-from")
@@ -252,6 +256,55 @@ def print_durations(specs):
         print(json.dumps({"workload": workload,
                           "classes": {k: {"dispatches": v[0], "mean_us": round(v[1] / v[0], 3),
                                           "total_ms": round(v[1] / 1e3, 3)} for k, v in sorted(per.items())}}))
+
+
+def print_dispatch_table(trace_csv, fetch_csv, write_csv, top):
+    """Per kernel and launch size (grid threads): dispatches and mean duration
+    from a --kernel-trace CSV and mean FETCH_SIZE + WRITE_SIZE bytes per
+    dispatch from two --pmc CSVs of the same command run with --calibrate-copy
+    (scaled by the run's first buffer copy).  The three runs issue the same
+    dispatch sequence, so the k-th dispatch of a kernel in the trace is paired
+    with its k-th dispatch in each counter pass.  Grid-stride kernels cap their
+    grid, so several levels can share a launch size: each group is also
+    reported for its largest launches alone (duration >= half the group's
+    longest).  The `top` groups with the largest total time."""
+    def by_name(rows, value):
+        out = {}
+        for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
+            out.setdefault(r["Kernel_Name"].split("(")[0].replace("void ", "").strip(), []).append(value(r))
+        return out
+
+    trace = by_name(_read_csv(trace_csv), lambda r: (
+        int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]),
+        (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3))
+    counters = []
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = [r for r in _read_csv(path) if r.get("Counter_Name", counter) == counter]
+        first_copy = min((r for r in rows if "copyBuffer" in r["Kernel_Name"]), key=lambda r: int(r["Dispatch_Id"]),
+                         default=None)
+        scale = 1.0
+        if first_copy is not None and float(first_copy["Counter_Value"]) > 0:
+            scale = 256.0 * 1024 * 1024 / (float(first_copy["Counter_Value"]) * 1024.0)
+        counters.append(by_name(rows, lambda r, sc=scale: float(r["Counter_Value"]) * 1024.0 * sc))
+    groups = {}
+    for name, seq in trace.items():
+        f, w = counters[0].get(name, []), counters[1].get(name, [])
+        paired = len(f) == len(seq) and len(w) == len(seq)
+        for k, (grid, dur) in enumerate(seq):
+            groups.setdefault((name, grid), []).append((dur, f[k] + w[k] if paired else None))
+    out = []
+    for (name, grid), rows in sorted(groups.items(), key=lambda kv: -sum(d for d, _ in kv[1]))[:top]:
+        def summary(sel):
+            n = len(sel)
+            mean = sum(d for d, _ in sel) / n
+            byts = [b for _, b in sel if b is not None]
+            traffic = sum(byts) / len(byts) if len(byts) == n else None
+            return {"dispatches": n, "mean_us": round(mean, 3), "counter_bytes": round(traffic) if traffic else None,
+                    "counter_TBs": round(traffic / mean / 1e6, 3) if traffic else None}
+        longest = max(d for d, _ in rows)
+        out.append({"kernel": name, "grid_threads": grid, "all": summary(rows),
+                    "largest": summary([r for r in rows if r[0] >= 0.5 * longest])})
+    print(json.dumps(out, indent=0))
 
 
 def _sync():
@@ -503,6 +556,9 @@ def cpu_baseline_batched(probs):
 
 def main():
     args = parse()
+    if args.dispatch_table:
+        print_dispatch_table(*args.dispatch_table, args.top)
+        return
     if args.traffic_from or args.durations_from:
         if args.traffic_from:
             build_traffic(args.traffic_from)
