@@ -499,6 +499,13 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  *                               grids only; see below);
  *   CHNS_OPT_PICARD_ITERATIONS  Picard iterations per Crank-Nicolson step
  *                               (default 3).
+ *   CHNS_OPT_MARCH_SWEEP_CELLS  3D multigrid levels with at least this many
+ *                               cells run their smoothing and residual
+ *                               sweeps marching along z with the stencil's
+ *                               planes in LDS (default 16777216: levels whose
+ *                               arrays outgrow the 256 MB Infinity Cache);
+ *                               >= 1.  The two sweep forms compute the same
+ *                               per-cell arithmetic.
  * Results do not depend on CHNS_OPT_SERIAL_COMPONENTS; the two S2 solvers
  * agree to the CH tolerance.
  *
@@ -521,7 +528,7 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  * run one after another on the grid's stream.  The adjoint, step records
  * and the energy monitor cover the split step only.                        */
 enum { CHNS_OPT_CH_SOLVER = 1, CHNS_OPT_SERIAL_COMPONENTS = 2, CHNS_OPT_TIME_SCHEME = 3,
-       CHNS_OPT_PICARD_ITERATIONS = 4 };
+       CHNS_OPT_PICARD_ITERATIONS = 4, CHNS_OPT_MARCH_SWEEP_CELLS = 5 };
 enum { CHNS_CH_DIRECT = 0, CHNS_CH_PCG = 1 };
 enum { CHNS_SCHEME_SPLIT = 0, CHNS_SCHEME_CN = 1 };
 int chns_set_option(struct chns_grid *g, int option, int value);

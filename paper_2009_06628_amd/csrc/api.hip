@@ -1319,6 +1319,14 @@ int chns_set_option(chns_grid *g, int option, int value) {
             if (value != 0 && value != 1) return fail(CHNS_EINVAL, "serial-components value must be 0 or 1");
             g->serial_components = value;
             return CHNS_OK;
+        case CHNS_OPT_MARCH_SWEEP_CELLS: {
+            if (value < 1) return fail(CHNS_EINVAL, "march-sweep cells must be >= 1");
+            Slot<double> *s64[] = {&g->ch, &g->mom, &g->pres, &g->mc[0].mom, &g->mc[1].mom};
+            Slot<float> *s32[] = {&g->ch32, &g->mom32, &g->pres32, &g->mc[0].mom32, &g->mc[1].mom32};
+            for (Slot<double> *S : s64) S->march_cells = value;
+            for (Slot<float> *S : s32) S->march_cells = value;
+            return CHNS_OK;
+        }
         default:
             return fail(CHNS_EINVAL, "unknown option");
     }

@@ -216,12 +216,17 @@ struct Slot {
     int lsb;        // first level handled by the single-workgroup kernel
     int ltrunc;     // 3D: the V-cycle ends at this grid level with a symmetric
                     // Gauss-Seidel solve (0: full cycle down to the coarsest)
+    long long march_cells;   // 3D levels with at least this many cells sweep marching along z
     int singular;
     int ncoarse;
     Level<T> lev[kMaxLev];
     double *Ainv;   // coarsest-level inverse, ncoarse x ncoarse (FP64)
     double *aug;    // scratch for the inverse when ncoarse > kLdsInverse
 };
+
+// Default of Slot::march_cells: levels whose arrays outgrow the Infinity
+// Cache (256^3 cells and up).
+constexpr long long kMarchSweepCells = 1LL << 24;
 
 // Reduction scratch shared by all solves of a handle.
 struct Red {

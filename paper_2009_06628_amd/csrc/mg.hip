@@ -582,6 +582,178 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply3_march(Level<T> L, const T
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// ---------------------------------------------------------------------------
+// 3D smoother and residual sweeps marching along z (levels of at least
+// Slot::march_cells cells, by default those whose arrays exceed the Infinity
+// Cache): block b
+// owns the kMX x kMY columns of tile b mod ncol over kSweepPlanes planes of z
+// chunk b / ncol.  The value a stencil reads at the neighbours (x, or b / diag
+// for the zero-guess pre-smoothing) is formed once per plane with a one-cell
+// x / y halo into a ring of three LDS planes, so the z neighbours come from
+// LDS instead of another pass over memory (a grid-stride sweep capped at
+// 4096 workgroups spreads four z planes over the eight XCDs per round, and
+// the z neighbours of a cell then sit in another XCD's L2).  Per-cell
+// arithmetic and order as the grid-stride bodies (a missing neighbour enters
+// as the cell itself with weight 0).
+// ---------------------------------------------------------------------------
+constexpr int kSweepPlanes = 16;
+
+// Ring of three planes (with halo) of a value v(e), 0 outside the domain.
+template <typename T>
+struct SweepRing {
+    T pl[3][kMH * kMW];
+};
+
+struct MarchTile {
+    int x0, y0, z0, z1, gx, gy, li;
+    bool own;
+};
+
+// Tile of logical block lb (XCD-contiguous numbering: the columns of a z
+// chunk, whose halos overlap, run on the same XCD).
+__device__ inline MarchTile march_tile(const Geo &g, int ncolx, int ncol, int lb) {
+    MarchTile t;
+    const int col = lb % ncol;
+    t.z0 = (lb / ncol) * kSweepPlanes;
+    t.z1 = t.z0 + kSweepPlanes < (int)g.n[2] ? t.z0 + kSweepPlanes : (int)g.n[2];
+    t.x0 = (col % ncolx) * kMX;
+    t.y0 = (col / ncolx) * kMY;
+    const int tx = (int)threadIdx.x % kMX, ty = (int)threadIdx.x / kMX;
+    t.gx = t.x0 + tx;
+    t.gy = t.y0 + ty;
+    t.li = (ty + 1) * kMW + tx + 1;
+    t.own = t.gx < g.n[0] && t.gy < g.n[1];
+    return t;
+}
+
+// fill plane slot P with v at plane zz of the tile and its halo
+template <typename T, typename V>
+__device__ inline void march_form(const Geo &g, const MarchTile &t, int zz, T *P, V v) {
+    auto wrapc = [](int q, int n, int per, int &w) {
+        if (q >= 0 && q < n) {
+            w = q;
+            return true;
+        }
+        w = q < 0 ? q + n : q - n;
+        return per != 0 && w >= 0 && w < n;
+    };
+    int gz;
+    const bool vz = wrapc(zz, (int)g.n[2], g.per[2], gz);
+    for (int i = (int)threadIdx.x; i < kMH * kMW; i += kBlock) {
+        const int ly = i / kMW, lx = i - ly * kMW;
+        int gx, gy;
+        const bool vx = wrapc(t.x0 - 1 + lx, (int)g.n[0], g.per[0], gx);
+        const bool vy = wrapc(t.y0 - 1 + ly, (int)g.n[1], g.per[1], gy);
+        P[i] = (vx && vy && vz) ? v(gx + (int)g.n[0] * (gy + (int)g.n[1] * gz)) : (T)0;
+    }
+}
+
+// March over the tile's planes: cell(c, ia, xc, nbv) for every owned cell,
+// with the ring values of the cell and its six neighbours.
+template <typename T, typename V, typename Cell>
+__device__ inline void march_sweep(const Geo &g, int ncolx, int ncol, int ntiles, SweepRing<T> &R, V v, Cell cell) {
+    const int lb = xcd_block();
+    if (lb >= ntiles) return;   // the whole block (grid rounded up to whole XCD groups)
+    const MarchTile t = march_tile(g, ncolx, ncol, lb);
+    march_form(g, t, t.z0 - 1, R.pl[(t.z0 + 2) % 3], v);
+    march_form(g, t, t.z0, R.pl[t.z0 % 3], v);
+    for (int zz = t.z0; zz < t.z1; ++zz) {
+        march_form(g, t, zz + 1, R.pl[(zz + 1) % 3], v);
+        __syncthreads();
+        const T *Pm = R.pl[(zz + 2) % 3], *P0 = R.pl[zz % 3], *Pp = R.pl[(zz + 1) % 3];
+        if (t.own) {
+            const int c = t.gx + (int)g.n[0] * (t.gy + (int)g.n[1] * zz);
+            const int ia[3] = {t.gx, t.gy, zz};
+            const T nbv[3][2] = {{P0[t.li - 1], P0[t.li + 1]}, {P0[t.li - kMW], P0[t.li + kMW]}, {Pm[t.li], Pp[t.li]}};
+            cell(c, ia, P0[t.li], nbv);
+        }
+        __syncthreads();   // the next plane overwrites this iteration's lower plane
+    }
+}
+
+// sum_b cs * v_nb with the neighbour values of the ring
+template <typename T>
+__device__ inline T march_offsum(const Level<T> &L, int c, const int ia[3], T vc, const T nbv[3][2]) {
+    using R = T;
+    R acc = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int lo = nb_lo(L.g, c, ia[b], b);
+        const int hi = nb_hi(L.g, c, ia[b], b);
+        const int h = hi >= 0 ? hi : c;
+        const R vl = lo >= 0 ? (R)nbv[b][0] : (R)vc, vh = hi >= 0 ? (R)nbv[b][1] : (R)vc;
+        const R wl = (R)L.cs[b][c], wh = (R)L.cs[b][h];
+        acc += (lo >= 0 ? wl : (R)0) * vl;
+        acc += (hi >= 0 ? wh : (R)0) * vh;
+    }
+    return acc;
+}
+
+// zero-guess pre-smoothing: red x = b / d, black from those red values
+template <typename T, typename TB>
+__global__ void __launch_bounds__(kBlock) k_presmooth_march(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,
+                                                            const int *__restrict__ done, int ncolx, int ncol,
+                                                            int ntiles) {
+    if (*done) return;
+    using R = T;
+    __shared__ SweepRing<T> ring;
+    auto red = [&](int e) { return (T)((R)b[e] * (R)L.invd[e]); };
+    march_sweep<T>(L.g, ncolx, ncol, ntiles, ring, red, [&](int c, const int ia[3], T vc, const T nbv[3][2]) {
+        if (((ia[0] + ia[1] + ia[2]) & 1) == 0)
+            x[c] = vc;
+        else
+            x[c] = (T)(((R)b[c] + march_offsum<T>(L, c, ia, vc, nbv)) * (R)L.invd[c]);
+    });
+}
+
+// in-place Gauss-Seidel update of one colour
+template <typename T, typename TB>
+__global__ void __launch_bounds__(kBlock) k_gs_color_march(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,
+                                                           int color, const int *__restrict__ done, int ncolx,
+                                                           int ncol, int ntiles) {
+    if (*done) return;
+    using R = T;
+    __shared__ SweepRing<T> ring;
+    march_sweep<T>(L.g, ncolx, ncol, ntiles, ring, [&](int e) { return x[e]; },
+                   [&](int c, const int ia[3], T vc, const T nbv[3][2]) {
+                       if (((ia[0] + ia[1] + ia[2]) & 1) != color) return;
+                       x[c] = (T)(((R)b[c] + march_offsum<T>(L, c, ia, vc, nbv)) * (R)L.invd[c]);
+                   });
+}
+
+// r = b - A x
+template <typename T, typename TB>
+__global__ void __launch_bounds__(kBlock) k_residual_march(Level<T> L, const TB *__restrict__ b,
+                                                           const T *__restrict__ x, const int *__restrict__ done,
+                                                           int ncolx, int ncol, int ntiles) {
+    if (*done) return;
+    using R = T;
+    __shared__ SweepRing<T> ring;
+    march_sweep<T>(L.g, ncolx, ncol, ntiles, ring, [&](int e) { return x[e]; },
+                   [&](int c, const int ia[3], T vc, const T nbv[3][2]) {
+                       R acc = (R)L.s[c] * (R)vc;
+#pragma unroll
+                       for (int a = 0; a < 3; ++a) {
+                           const int lo = nb_lo(L.g, c, ia[a], a);
+                           const int hi = nb_hi(L.g, c, ia[a], a);
+                           const int h = hi >= 0 ? hi : c;
+                           const R xl = lo >= 0 ? (R)nbv[a][0] : (R)vc, xh = hi >= 0 ? (R)nbv[a][1] : (R)vc;
+                           const R wl = (R)L.cs[a][c], wh = (R)L.cs[a][h];
+                           acc += (lo >= 0 ? wl : (R)0) * ((R)vc - xl);
+                           acc += (hi >= 0 ? wh : (R)0) * ((R)vc - xh);
+                       }
+                       L.r[c] = (T)((R)b[c] - acc);
+                   });
+}
+
+// tiles and grid (rounded up to whole XCD groups) of a marching sweep
+static inline int march_sweep_grid(const Geo &g, int &ncolx, int &ncol, int &ntiles) {
+    ncolx = (int)((g.n[0] + kMX - 1) / kMX);
+    ncol = ncolx * (int)((g.n[1] + kMY - 1) / kMY);
+    ntiles = ncol * (int)((g.n[2] + kSweepPlanes - 1) / kSweepPlanes);
+    return ntiles > 8 ? (ntiles + 7) & ~7 : ntiles;
+}
+
 // CH operator, first half: p_new = z + beta p_old, t = L p_new.
 template <typename T, typename TZ, int DIM>
 __global__ void __launch_bounds__(kBlock) k_pcg_ch_lap(Geo g, double ih2, const TZ *__restrict__ z,
@@ -943,11 +1115,20 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
         return;
     }
     const double WB = sizeof(TB) - W;   // extra bytes of a wider right-hand side
-    if ((lv.g.n[0] & 1) == 0)
-        LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth_pair<T, TB, DIM>), N / 2, st, lv, b, x, done);
-    else
-        LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
-    LAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual<T, TB, DIM>), N, st, lv, b, (const T *)x, done);
+    if (DIM == 3 && lv.g.N >= S.march_cells) {
+        int ncolx, ncol, ntiles;
+        const int grid = march_sweep_grid(lv.g, ncolx, ncol, ntiles);
+        TLAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth_march<T, TB>), dim3(grid), dim3(kBlock), st, lv, b,
+                x, done, ncolx, ncol, ntiles);
+        TLAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual_march<T, TB>), dim3(grid), dim3(kBlock), st, lv,
+                b, (const T *)x, done, ncolx, ncol, ntiles);
+    } else {
+        if ((lv.g.n[0] & 1) == 0)
+            LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth_pair<T, TB, DIM>), N / 2, st, lv, b, x, done);
+        else
+            LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WB * N, (k_presmooth<T, TB, DIM>), N, st, lv, b, x, done);
+        LAUNCH(K_RESIDUAL, W * (4 + DIM) * N + WB * N, (k_residual<T, TB, DIM>), N, st, lv, b, (const T *)x, done);
+    }
     {
         const Geo &gc = S.lev[l + 1].g;
         const int ntx = (int)((gc.n[0] + kRCX - 1) / kRCX), nty = (int)((gc.n[1] + kRCY - 1) / kRCY);
@@ -990,8 +1171,16 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
         // one thread per coarse cell (fine x extent is even on every level above the coarsest)
         LAUNCH(K_PROLONG, W * (2 * N + Nc), (k_prolong_add3<T>), Nc, st, lv.g, S.lev[l + 1].g,
                (const T *)S.lev[l + 1].x, x, done);
-        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 1, done);
-        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 0, done);
+        if (lv.g.N >= S.march_cells) {
+            int ncolx, ncol, ntiles;
+            const int grid = march_sweep_grid(lv.g, ncolx, ncol, ntiles);
+            for (int color = 1; color >= 0; --color)
+                TLAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color_march<T, TB>), dim3(grid), dim3(kBlock),
+                        st, lv, b, x, color, done, ncolx, ncol, ntiles);
+        } else {
+            LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 1, done);
+            LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 0, done);
+        }
     }
 }
 

@@ -45,6 +45,7 @@ inline void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
     S.nlev = P.nlev;
     S.lsb = 0;
     S.ltrunc = 0;
+    S.march_cells = kMarchSweepCells;
     S.singular = singular;
     S.ncoarse = (int)P.lev[P.nlev - 1].N;
     for (int l = 0; l < P.nlev; ++l) {
