@@ -502,10 +502,13 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  *   CHNS_OPT_MARCH_SWEEP_CELLS  3D multigrid levels with at least this many
  *                               cells run their smoothing and residual
  *                               sweeps marching along z with the stencil's
- *                               planes in LDS (default 16777216: levels whose
- *                               arrays outgrow the 256 MB Infinity Cache);
- *                               >= 1.  The two sweep forms compute the same
- *                               per-cell arithmetic.
+ *                               planes in LDS, and the CG apply of a pressure
+ *                               solve on such a grid forms its face
+ *                               coefficients from the cell density instead
+ *                               of reading them (default 16777216: levels
+ *                               whose arrays outgrow the 256 MB Infinity
+ *                               Cache); >= 1.  Either form computes the same
+ *                               per-cell arithmetic, bit for bit.
  * Results do not depend on CHNS_OPT_SERIAL_COMPONENTS; the two S2 solvers
  * agree to the CH tolerance.
  *

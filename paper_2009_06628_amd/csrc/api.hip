@@ -184,6 +184,7 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     g->rch = B.take<double>(N);
     for (int a = 0; a < 3; ++a) g->ustar[a] = a < P.dim ? B.take<double>(N) : nullptr;
     g->rhs = B.take<double>(N);
+    g->prho = B.take<double>(N);
     g->nph = P.nph;
     if (P.nph == 3) {
         g->phi_new2 = B.take<double>(N);
@@ -468,9 +469,9 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         ep = hipStreamWaitEvent(c.s, g->ev_fork, 0);
         if (ep != hipSuccess) return;
         if (tern)
-            launch_p_setup3(dim, geo, k, g->tern, ph, usc, P0.s, pcs, g->rhs, c.s, kPCoef);
+            launch_p_setup3(dim, geo, k, g->tern, ph, usc, P0.s, pcs, g->rhs, c.s, kPCoef, g->prho);
         else
-            launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, c.s, kPCoef);
+            launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, c.s, kPCoef, g->prho);
         hierarchy_setup(g, c);
         ep = hipEventRecord(g->ev_pset, c.s);
     };
@@ -543,9 +544,11 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     if (ep != hipSuccess) return fail(CHNS_EDEVICE, std::string("pressure set-up: ") + hipGetErrorString(ep));
     // S8 (coefficients and hierarchy already set up when concurrent)
     if (tern)
-        launch_p_setup3(dim, geo, k, g->tern, ph, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs);
+        launch_p_setup3(dim, geo, k, g->tern, ph, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs,
+                        g->prho);
     else
-        launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs);
+        launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs,
+                       g->prho);
     remove_mean(geo, g->rhs, g->red, s);
     HIPCHK(run_solve_ctx(g, main_ctx(g, 2), !concurrent, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
     if (int rc = check_solve(o, "pressure")) return rc;
@@ -610,7 +613,7 @@ int cn_step(chns_grid *g, double *phi, double *const u[3], double *mu, double *p
             last.unconverged |= om.unconverged ? (2 << a) : 0;
         }
         // C8, C9
-        launch_p_setup(dim, geo, kh, phimid, usc, P0.s, pcs, g->rhs, s, kPCoef | kPRhs);
+        launch_p_setup(dim, geo, kh, phimid, usc, P0.s, pcs, g->rhs, s, kPCoef | kPRhs, g->prho);
         remove_mean(geo, g->rhs, g->red, s);
         launch_cn_zero(geo, g->cn_dp, s);
         HIPCHK(run_solve_ctx(g, main_ctx(g, 2), 1, OP_SLOT, ch, (const double *)g->rhs, g->cn_dp, p.rtol_p, 4, &o));
@@ -717,6 +720,13 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     g->ws_bytes = bytes;
     Bump B{(char *)workspace, 0};
     layout(B, P, g, desc->precision);
+    // the CG apply of the step's pressure solves forms the face coefficients
+    // from the cell density its set-up writes (expression and 1/h^2 of the set-up)
+    g->pres.rho = g->prho;
+    {
+        const double ih = 1.0 / desc->h;   // as step_const_of
+        g->pres.rho_ih2 = ih * ih;
+    }
     for (int k = 0; k < 12; ++k) g->last_iters[k] = g->last_inner[k] = 4;
     g->adj_ready = 0;
     // streams (default priority) and events of the momentum components and
@@ -1228,7 +1238,8 @@ int chns_adjoint_step_recorded(chns_grid *g, const chns_state *fwd, const chns_r
     double *cs[3] = {L0.cs[0], L0.cs[1], L0.cs[2]};
     const double *usr[3] = {(const double *)rec->ustar[0], (const double *)rec->ustar[1],
                             g->dim == 3 ? (const double *)rec->ustar[2] : nullptr};
-    launch_p_setup(g->dim, g->geo, step_const(g), (const double *)rec->phi_new, usr, L0.s, cs, g->rhs, g->stream);
+    launch_p_setup(g->dim, g->geo, step_const(g), (const double *)rec->phi_new, usr, L0.s, cs, g->rhs, g->stream,
+                   kPCoef | kPRhs, g->prho);
     const FwdFields F{(const double *)rec->phihat, (const double *)rec->phi_new, (const double *)rec->mu,
                       (const double *)rec->p, {usr[0], usr[1], usr[2]}};
     return adjoint_core(g, fwd, F, lam_in, lam_out, grad_params, 0);
@@ -1249,7 +1260,15 @@ int chns_solve_pressure(chns_grid *g, const void *rho, const void *rhs, void *p,
     SolveOut o;
     const int saved = g->props.max_iter;
     g->props.max_iter = max_iter;
+    // the CG apply forms its coefficients from the given density, as
+    // launch_p_coef_from_rho above (the same 1/h^2)
+    const double *rho_step = g->pres.rho;
+    const double ih2_step = g->pres.rho_ih2;
+    g->pres.rho = (const double *)rho;
+    g->pres.rho_ih2 = 1.0 / (g->h * g->h);
     hipError_t e = run_solve(g, 2, OP_SLOT, ChOp{0, 0, 0}, (const double *)g->rhs, (double *)p, rtol, 5, &o);
+    g->pres.rho = rho_step;
+    g->pres.rho_ih2 = ih2_step;
     g->props.max_iter = saved;
     HIPCHK(e);
     if (int rc = check_solve(o, "pressure")) return rc;

@@ -217,6 +217,10 @@ struct Slot {
     int ltrunc;     // 3D: the V-cycle ends at this grid level with a symmetric
                     // Gauss-Seidel solve (0: full cycle down to the coarsest)
     long long march_cells;   // 3D levels with at least this many cells sweep marching along z
+    const double *rho;       // pressure slots: cell densities whose face averages give the level-0
+    double rho_ih2;          // coefficients 1/(rho_f h^2) (rho_ih2 = the 1/h^2 they were formed with);
+                             // the 3D CG apply forms them on the fly on grids of at least march_cells
+                             // cells (null: it reads the stored cs)
     int singular;
     int ncoarse;
     Level<T> lev[kMaxLev];
@@ -345,6 +349,7 @@ struct chns_grid {
     double *phi_new, *phihat, *rch, *ustar[3], *rhs;
     int nph;                                 // phases: 2, or 3 (three-phase model)
     chns::TernConst tern;                    // three-phase constants (nph == 3)
+    double *prho;                            // cell density of the step's pressure operator (its set-up writes it)
     double *phi_new2, *phihat2, *rch2;       // the second stored phase (nph == 3)
     double *mix3[5];                         // per-step mixture fields (nph == 3)
     double *vr, *vz, *vp0, *vp1, *vq, *vt;   // PCG vectors

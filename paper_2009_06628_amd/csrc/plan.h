@@ -46,6 +46,8 @@ inline void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
     S.lsb = 0;
     S.ltrunc = 0;
     S.march_cells = kMarchSweepCells;
+    S.rho = nullptr;
+    S.rho_ih2 = 0.0;
     S.singular = singular;
     S.ncoarse = (int)P.lev[P.nlev - 1].N;
     for (int l = 0; l < P.nlev; ++l) {

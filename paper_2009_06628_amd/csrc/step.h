@@ -58,7 +58,7 @@ void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const Tern
 // T8 set-up (parts as launch_p_setup).
 void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], double *s, double *const cs[3], double *rhs, hipStream_t st,
-                     int part);
+                     int part, double *rho_out = nullptr);
 // T9: projection, phi_i = phi_i^{n+1}.
 void launch_project3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], const double *p, double *phi1, double *phi2, double *const u[3],
@@ -118,7 +118,8 @@ void launch_mom_setup_all(int dim, const Geo &g, const StepConst &k, const doubl
 // coefficients need only phi_new, so the step sets them and the pressure
 // hierarchy up while the momentum solves run.
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
-                    double *s, double *const cs[3], double *rhs, hipStream_t st, int part = kPCoef | kPRhs);
+                    double *s, double *const cs[3], double *rhs, hipStream_t st, int part = kPCoef | kPRhs,
+                    double *rho_out = nullptr);
 // Pressure coefficients from a given cell density (stand-alone solve).
 void launch_p_coef_from_rho(int dim, const Geo &g, double ih2, const double *rho, double *s, double *const cs[3],
                             hipStream_t st);

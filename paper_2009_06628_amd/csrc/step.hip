@@ -78,8 +78,10 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup_all(Geo g, StepConst k, co
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_p_setup(Geo g, StepConst k, const double *__restrict__ phin, U3 us,
-                                                    double *__restrict__ s, W3 cs, double *__restrict__ rhs, int part) {
-    CELL_LOOP(g.N) p_setup_cell<DIM>(g, k, phin, us, s, cs, rhs, part, c);
+                                                    double *__restrict__ s, W3 cs, double *__restrict__ rhs, int part,
+                                                    double *__restrict__ rho_out) {
+    const Mix2 mx = mk_mix2(k, phin, phin, phin);
+    CELL_LOOP(g.N) p_setup_body<DIM>(g, k, mx, us, s, cs, rhs, part, c, rho_out);
 }
 
 template <int DIM>
@@ -235,9 +237,9 @@ void launch_mom_setup_all(int dim, const Geo &g, const StepConst &k, const doubl
     }
 }
 void launch_p_setup(int dim, const Geo &g, const StepConst &k, const double *phi_new, const double *const ustar[3],
-                    double *s, double *const cs[3], double *rhs, hipStream_t st, int part) {
-    const int words = (part & kPCoef ? 2 + dim : 0) + (part & kPRhs ? 1 + dim : 0);
-    DISPATCH(K_P_SETUP, words, dim, k_p_setup, g.N, st, g, k, phi_new, mk_u3(ustar), s, mk_w3(cs), rhs, part);
+                    double *s, double *const cs[3], double *rhs, hipStream_t st, int part, double *rho_out) {
+    const int words = (part & kPCoef ? 2 + dim + (rho_out ? 1 : 0) : 0) + (part & kPRhs ? 1 + dim : 0);
+    DISPATCH(K_P_SETUP, words, dim, k_p_setup, g.N, st, g, k, phi_new, mk_u3(ustar), s, mk_w3(cs), rhs, part, rho_out);
 }
 void launch_p_coef_from_rho(int dim, const Geo &g, double ih2, const double *rho, double *s, double *const cs[3],
                             hipStream_t st) {

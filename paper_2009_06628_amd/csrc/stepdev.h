@@ -289,10 +289,12 @@ __device__ inline void mom_setup_cell(const Geo &g, const StepConst &k, int a, c
 }
 
 // S8 set-up: pressure coefficients 1/(rho_f h^2) from clamp(phi_new)
-// (part & kPCoef), rhs = -(We/dt) D ustar (part & kPRhs).
+// (part & kPCoef; rho_out, when given, receives the cell density the
+// coefficients are formed from), rhs = -(We/dt) D ustar (part & kPRhs).
 template <int DIM, typename Mix>
 __device__ inline void p_setup_body(const Geo &g, const StepConst &k, const Mix &mx, const U3 &us,
-                                    double *__restrict__ s, const W3 &cs, double *__restrict__ rhs, int part, int c) {
+                                    double *__restrict__ s, const W3 &cs, double *__restrict__ rhs, int part, int c,
+                                    double *__restrict__ rho_out = nullptr) {
     int i, j, kk;
     if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
     const int ia[3] = {i, j, kk};
@@ -314,7 +316,10 @@ __device__ inline void p_setup_body(const Geo &g, const StepConst &k, const Mix 
         const double fhi = hi >= 0 ? us.a[b][hi] : 0.0;
         div += fhi - flo;
     }
-    if (part & kPCoef) s[c] = 0.0;
+    if (part & kPCoef) {
+        s[c] = 0.0;
+        if (rho_out) rho_out[c] = rc;
+    }
     if (part & kPRhs) rhs[c] = -(k.We / k.dt) * (div * k.ih);
 }
 

@@ -241,8 +241,9 @@ __global__ void __launch_bounds__(kBlock) k_mom_setup3_all(Geo g, StepConst k, M
 // T8 set-up
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_p_setup3(Geo g, StepConst k, MixPre mx, U3 us, double *__restrict__ s,
-                                                     W3 cs, double *__restrict__ rhs, int part) {
-    CELL_LOOP(g.N) p_setup_body<DIM>(g, k, mx, us, s, cs, rhs, part, c);
+                                                     W3 cs, double *__restrict__ rhs, int part,
+                                                     double *__restrict__ rho_out) {
+    CELL_LOOP(g.N) p_setup_body<DIM>(g, k, mx, us, s, cs, rhs, part, c, rho_out);
 }
 
 // T9: projection; phi_i = phi_i^{n+1}
@@ -407,10 +408,10 @@ void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const Tern
 
 void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], double *s, double *const cs[3], double *rhs, hipStream_t st,
-                     int part) {
-    const int words = (part & kPCoef ? 2 + dim : 0) + (part & kPRhs ? 1 + dim : 0);
+                     int part, double *rho_out) {
+    const int words = (part & kPCoef ? 2 + dim + (rho_out ? 1 : 0) : 0) + (part & kPRhs ? 1 + dim : 0);
     DISPATCH(K_P_SETUP, words, dim, k_p_setup3, g.N, st, g, k, pre_of(k, t, ph), mk_u3(ustar), s, mk_w3(cs), rhs,
-             part);
+             part, rho_out);
 }
 
 void launch_project3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,

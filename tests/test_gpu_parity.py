@@ -123,8 +123,10 @@ def test_march_sweeps_match_grid_stride_and_oracle(n, per):
     """3D smoothing and residual sweeps marching along z (used by default on
     levels of 2^24 cells and more), forced onto every level with
     CHNS_OPT_MARCH_SWEEP_CELLS = 1 on grids with ragged x / y tiles and
-    several z chunks: the pressure solve is bit for bit that of the
-    grid-stride sweeps (same per-cell arithmetic) and matches the oracle."""
+    several z chunks (which also makes the CG apply form the pressure
+    coefficients from the density): the pressure solve is bit for bit that of
+    the grid-stride sweeps and stored coefficients (same per-cell arithmetic)
+    and matches the oracle."""
     P = _lib()
     rng = np.random.default_rng(12)
     og = MACGrid(n, 1.0 / n[0], per)
