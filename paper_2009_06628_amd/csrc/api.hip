@@ -191,9 +191,11 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
         g->phihat2 = B.take<double>(N);
         g->rch2 = B.take<double>(N);
         for (int q = 0; q < 5; ++q) g->mix3[q] = B.take<double>(N);
+        for (int b = 0; b < 3; ++b) g->mflux3[b] = b < P.dim ? B.take<double>(N) : nullptr;
     } else {
         g->phi_new2 = g->phihat2 = g->rch2 = nullptr;
         for (int q = 0; q < 5; ++q) g->mix3[q] = nullptr;
+        for (int b = 0; b < 3; ++b) g->mflux3[b] = nullptr;
     }
     if (P.nph == 2) {   // Crank-Nicolson variant: midpoint iterates and pressure increment
         g->cn_phim = B.take<double>(N);
@@ -503,7 +505,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         memcpy(wv.v, g->wall_u, sizeof wv.v);
         const WallVel *pw = g->walls_move ? &wv : nullptr;
         if (tern)
-            launch_mom_setup3_all(dim, geo, k, g->tern, ph, uc, mo, s, pw);
+            launch_mom_setup3_all(dim, geo, k, g->tern, ph, uc, mo, g->mflux3, s, pw);
         else
             launch_mom_setup_all(dim, geo, k, phi, g->phi_new, mu, uc, mo, s, pw);
     }

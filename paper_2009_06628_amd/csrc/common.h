@@ -352,6 +352,7 @@ struct chns_grid {
     double *prho;                            // cell density of the step's pressure operator (its set-up writes it)
     double *phi_new2, *phihat2, *rch2;       // the second stored phase (nph == 3)
     double *mix3[5];                         // per-step mixture fields (nph == 3)
+    double *mflux3[3];                       // per-step face mass fluxes (nph == 3)
     double *vr, *vz, *vp0, *vp1, *vq, *vt;   // PCG vectors
     chns::Slot<double> ch, mom, pres;
     // precision form (FP32 inner solves under FP64 refinement)

@@ -53,8 +53,10 @@ void launch_mu3(int dim, const Geo &g, const StepConst &k, const TernConst &t, c
 void launch_phi_update3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                         const double *const u[3], hipStream_t st);
 // T5-T7 set-up of every component in one pass (as launch_mom_setup_all).
+// m: face mass-flux arrays of the step (written here first).
 void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
-                           const double *const u[3], const MomOut &o, hipStream_t st, const WallVel *wv = nullptr);
+                           const double *const u[3], const MomOut &o, double *const m[3], hipStream_t st,
+                           const WallVel *wv = nullptr);
 // T8 set-up (parts as launch_p_setup).
 void launch_p_setup3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                      const double *const ustar[3], double *s, double *const cs[3], double *rhs, hipStream_t st,

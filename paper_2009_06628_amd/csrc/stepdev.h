@@ -48,6 +48,7 @@ __device__ inline double mflux(const Geo &g, const StepConst &k, const double *_
 // The set-up bodies below take a policy, so that the three-phase model
 // (ternary.hip) runs the same momentum / pressure / projection arithmetic.
 struct Mix2 {
+    static constexpr bool kStoredFlux = false;          // mass flux evaluated per face (mflux_face)
     double alpha, beta, gamma, xi, jcoef, stcoef, ih;   // jcoef = alpha/(Cn Pe), stcoef = 1/(We Cn)
     const double *phi, *phin, *mu;                     // phi^n, phi^{n+1}, mu^{n+1}
     __device__ double rho_new(int e) const { return alpha * pullback(phin[e]) + beta; }
@@ -74,8 +75,12 @@ __host__ __device__ inline Mix2 mk_mix2(const StepConst &k, const double *phi, c
 template <int DIM, typename Mix>
 __device__ inline double mflux_mix(const Geo &g, const Mix &mx, const double *__restrict__ ub, int b, int f, int ib) {
     if (f < 0) return 0.0;                       // unstored upper wall face
-    if (!g.per[b] && ib == 0) return 0.0;        // stored wall face
-    return mx.mflux_face(ub[f], f, nb_lo(g, f, ib, b));
+    if constexpr (Mix::kStoredFlux) {
+        return mx.m[b][f];                       // the step's face fluxes (0 on stored wall faces)
+    } else {
+        if (!g.per[b] && ib == 0) return 0.0;    // stored wall face
+        return mx.mflux_face(ub[f], f, nb_lo(g, f, ib, b));
+    }
 }
 
 __device__ inline int wrap_next(int ib, int n) { return ib + 1 < n ? ib + 1 : 0; }

@@ -26,6 +26,7 @@ struct W5 {
 
 // Mixture policy of the three-phase model (see stepdev.h for the interface).
 struct Mix3 {
+    static constexpr bool kStoredFlux = false;
     double rho[3], eta[3];
     double jc[2];     // (kM/2)(rho_i - rho_3), i = 1, 2
     double cap[3];    // Sigma_i / (2 Cn)
@@ -68,6 +69,7 @@ struct Mix3 {
 // momentum set-up evaluates the mass flux on up to 11 faces per cell and
 // component, and the three-phase maps are the costly part of it.
 struct MixPre {
+    static constexpr bool kStoredFlux = false;
     const double *rn, *ro, *en, *rl, *chi;
     double ih;
     double cap[3];
@@ -85,6 +87,14 @@ struct MixPre {
         const double g3 = ((-mu1[c] - mu2[c]) - (-mu1[cam] - mu2[cam])) * ih;
         return cap[0] * a1 * g1 + cap[1] * a2 * g2 + cap[2] * a3 * g3;
     }
+};
+
+// The same with the step's face mass fluxes read from m[b] (written once per
+// step by k_mflux3 with MixPre's expression): the momentum set-up evaluates
+// the flux on 11 faces per face and component in 3D, five loads each.
+struct MixPreFlux : MixPre {
+    static constexpr bool kStoredFlux = true;
+    const double *m[3];
 };
 
 static Mix3 mk_mix3(const StepConst &k, const TernConst &t, const double *phi1, const double *phi2,
@@ -234,8 +244,22 @@ __global__ void __launch_bounds__(kBlock) k_phi_update3(Geo g, StepConst k, cons
 
 // T5-T7 set-up of every component (the binary body with the three-phase mixture)
 template <int DIM, bool WALLS>
-__global__ void __launch_bounds__(kBlock) k_mom_setup3_all(Geo g, StepConst k, MixPre mx, U3 u, MomOut o, WallVel wv) {
-    CELL_LOOP(g.N) mom_setup_all_body<DIM, MixPre, WALLS>(g, k, mx, u, o, c, &wv);
+__global__ void __launch_bounds__(kBlock) k_mom_setup3_all(Geo g, StepConst k, MixPreFlux mx, U3 u, MomOut o,
+                                                           WallVel wv) {
+    CELL_LOOP(g.N) mom_setup_all_body<DIM, MixPreFlux, WALLS>(g, k, mx, u, o, c, &wv);
+}
+
+// The face mass fluxes m_b = A_b(rho_lin) u_b - G_b chi of the step on every
+// face (0 on the stored wall faces).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_mflux3(Geo g, MixPre mx, U3 u, W3 m) {
+    CELL_LOOP(g.N) {
+        int i, j, kk;
+        cc<DIM>(g, c, i, j, kk);
+        const int ia[3] = {i, j, kk};
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) m.a[b][c] = mflux_mix<DIM>(g, mx, u.a[b], b, c, ia[b]);
+    }
 }
 
 // T8 set-up
@@ -386,13 +410,23 @@ static MixPre pre_of(const StepConst &k, const TernConst &t, const Phases3 &ph) 
 }
 
 void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
-                           const double *const u[3], const MomOut &o, hipStream_t st, const WallVel *wv) {
+                           const double *const u[3], const MomOut &o, double *const m[3], hipStream_t st,
+                           const WallVel *wv) {
     WallVel w{};
     if (wv) w = *wv;
-    const MixPre mx = pre_of(k, t, ph);
-    // the five mixture fields, phi_1, phi_2, mu_1, mu_2 and u[d] read; s, cs[d], rhs, ustar written per component
-    const double bytes = 8.0 * (9 + dim + dim * (3 + dim)) * g.N;
+    const MixPre pre = pre_of(k, t, ph);
     const dim3 grid(grid_for(g.N)), block(kBlock);
+    // face fluxes: rho_lin, chi and u[d] read, m[d] written
+    if (dim == 2)
+        TLAUNCH(K_MOM_SETUP, 8.0 * (2 + 2 * dim) * g.N, (k_mflux3<2>), grid, block, st, g, pre, mk_u3(u), mk_w3(m));
+    else
+        TLAUNCH(K_MOM_SETUP, 8.0 * (2 + 2 * dim) * g.N, (k_mflux3<3>), grid, block, st, g, pre, mk_u3(u), mk_w3(m));
+    MixPreFlux mx;
+    static_cast<MixPre &>(mx) = pre;
+    for (int b = 0; b < 3; ++b) mx.m[b] = m[b];
+    // rho^{n+1}, rho^n, eta^{n+1}, phi_1, phi_2, mu_1, mu_2, m[d] and u[d] read; s, cs[d], rhs, ustar written
+    // per component
+    const double bytes = 8.0 * (7 + 2 * dim + dim * (3 + dim)) * g.N;
     if (dim == 2) {
         if (wv)
             TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup3_all<2, true>), grid, block, st, g, k, mx, mk_u3(u), o, w);
