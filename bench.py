@@ -116,8 +116,8 @@ def recorded_traffic(workload, kernel_class):
 # Kernel classes of the library's per-kernel timing, by kernel name (the
 # template arguments after the name are matched by the workload filters).
 KERNEL_CLASSES = {
-    "smooth": ("k_presmooth_pair", "k_presmooth", "k_gs_color"),
-    "residual": ("k_residual",),
+    "smooth": ("k_presmooth_pair", "k_presmooth", "k_gs_color", "k_presmooth_march", "k_gs_color_march"),
+    "residual": ("k_residual", "k_residual_march"),
     "restrict": ("k_restrict3_lds", "k_restrict3_pair", "k_restrict"),
     "prolong": ("k_prolong_add3",),
     "coarse_solve": ("k_vcycle_lds", "k_vcycle_block"),
