@@ -121,8 +121,8 @@ KERNEL_CLASSES = {
     "restrict": ("k_restrict3_lds", "k_restrict3_pair", "k_restrict"),
     "prolong": ("k_prolong_add3",),
     "coarse_solve": ("k_vcycle_lds", "k_vcycle_block"),
-    "mg_down": ("k_down_tile2", "k_down_tile2_cg"),
-    "mg_up": ("k_up_tile2", "k_up_tile2_cg"),
+    "mg_down": ("k_down_tile2", "k_down_tile2_cg", "k_down3_tile"),
+    "mg_up": ("k_up_tile2", "k_up_tile2_cg", "k_up3_tile"),
     "pcg_apply": ("k_pcg_apply3_march", "k_pcg_apply_slot", "k_pcg_ch_lap", "k_pcg_ch_apply"),
     "pcg_update": ("k_pcg_update", "k_pcg_fin_rr"),
     "pcg_dot": ("k_pcg_rz",),

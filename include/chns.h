@@ -509,6 +509,14 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  *                               whose arrays outgrow the 256 MB Infinity
  *                               Cache); >= 1.  Either form computes the same
  *                               per-cell arithmetic, bit for bit.
+ *   CHNS_OPT_TILE_CYCLE_CELLS   3D multigrid levels with at most this many
+ *                               cells (below the march-sweep size, above the
+ *                               part solved in one workgroup) run each side
+ *                               of the V-cycle as one launch over 8^3-cell
+ *                               tiles that recompute their halos in LDS
+ *                               instead of three grid-wide launches (default
+ *                               262144: 64^3 cells and below; 0: never).
+ *                               Same per-cell arithmetic, bit for bit.
  * Results do not depend on CHNS_OPT_SERIAL_COMPONENTS; the two S2 solvers
  * agree to the CH tolerance.
  *
@@ -531,7 +539,7 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  * run one after another on the grid's stream.  The adjoint, step records
  * and the energy monitor cover the split step only.                        */
 enum { CHNS_OPT_CH_SOLVER = 1, CHNS_OPT_SERIAL_COMPONENTS = 2, CHNS_OPT_TIME_SCHEME = 3,
-       CHNS_OPT_PICARD_ITERATIONS = 4, CHNS_OPT_MARCH_SWEEP_CELLS = 5 };
+       CHNS_OPT_PICARD_ITERATIONS = 4, CHNS_OPT_MARCH_SWEEP_CELLS = 5, CHNS_OPT_TILE_CYCLE_CELLS = 6 };
 enum { CHNS_CH_DIRECT = 0, CHNS_CH_PCG = 1 };
 enum { CHNS_SCHEME_SPLIT = 0, CHNS_SCHEME_CN = 1 };
 int chns_set_option(struct chns_grid *g, int option, int value);

@@ -1348,6 +1348,14 @@ int chns_set_option(chns_grid *g, int option, int value) {
             for (Slot<float> *S : s32) S->march_cells = value;
             return CHNS_OK;
         }
+        case CHNS_OPT_TILE_CYCLE_CELLS: {
+            if (value < 0) return fail(CHNS_EINVAL, "tile-cycle cells must be >= 0");
+            Slot<double> *s64[] = {&g->ch, &g->mom, &g->pres, &g->mc[0].mom, &g->mc[1].mom};
+            Slot<float> *s32[] = {&g->ch32, &g->mom32, &g->pres32, &g->mc[0].mom32, &g->mc[1].mom32};
+            for (Slot<double> *S : s64) S->tile_cells = value;
+            for (Slot<float> *S : s32) S->tile_cells = value;
+            return CHNS_OK;
+        }
         default:
             return fail(CHNS_EINVAL, "unknown option");
     }

@@ -217,6 +217,8 @@ struct Slot {
     int ltrunc;     // 3D: the V-cycle ends at this grid level with a symmetric
                     // Gauss-Seidel solve (0: full cycle down to the coarsest)
     long long march_cells;   // 3D levels with at least this many cells sweep marching along z
+    long long tile_cells;    // 3D levels with at most this many cells (above the single-workgroup
+                             // part, below march_cells) run one tile pass per side of the cycle
     const double *rho;       // pressure slots: cell densities whose face averages give the level-0
     double rho_ih2;          // coefficients 1/(rho_f h^2) (rho_ih2 = the 1/h^2 they were formed with);
                              // the 3D CG apply forms them on the fly on grids of at least march_cells
@@ -231,6 +233,9 @@ struct Slot {
 // Default of Slot::march_cells: levels whose arrays outgrow the Infinity
 // Cache (256^3 cells and up).
 constexpr long long kMarchSweepCells = 1LL << 24;
+// Default of Slot::tile_cells: the levels whose sweeps cost less than their
+// launches (64^3 cells and below).
+constexpr long long kTileCycleCells = 1LL << 18;
 
 // Reduction scratch shared by all solves of a handle.
 struct Red {

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add3(Geo gf, Geo gc, const T
                         for (int dy2 = 0; dy2 < 2; ++dy2) {
                             const R wyz = wz * (dy2 ? w1[1][dy] : w0[1][dy]);
                             const int yi = dy2 ? 1 + dy : 0;
-                            v += wyz * (w0[0][dx] * X[zi][yi][0] + w1[0][dx] * X[zi][yi][1 + dx]);
+                            v = pro_row(v, wyz, w0[0][dx], X[zi][yi][0], w1[0][dx], X[zi][yi][1 + dx]);
                         }
                     }
                     pr.v[dx] = (T)((T)pr.v[dx] + v);
@@ -209,8 +209,8 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_lds(Geo gf, Geo gc, const 
             const T *row = &sf[2 * lz + a][2 * ly + q][2 * lx];
             R s = 0.0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) s += wx[e] * (R)row[e];
-            acc += (wy[q] * wza) * s;
+            for (int e = 0; e < 4; ++e) s = fmar(wx[e], (R)row[e], s);
+            acc = fmar(wy[q] * wza, s, acc);
         }
     }
     bc[(I[2] * (int)gc.n[1] + I[1]) * (int)gc.n[0] + I[0]] = (T)acc;
@@ -714,8 +714,8 @@ __device__ inline T march_offsum(const Level<T> &L, int c, const int ia[3], T vc
         const int h = hi >= 0 ? hi : c;
         const R vl = lo >= 0 ? (R)nbv[b][0] : (R)vc, vh = hi >= 0 ? (R)nbv[b][1] : (R)vc;
         const R wl = (R)L.cs[b][c], wh = (R)L.cs[b][h];
-        acc += (lo >= 0 ? wl : (R)0) * vl;
-        acc += (hi >= 0 ? wh : (R)0) * vh;
+        acc = fmar(lo >= 0 ? wl : (R)0, vl, acc);
+        acc = fmar(hi >= 0 ? wh : (R)0, vh, acc);
     }
     return acc;
 }
@@ -770,8 +770,8 @@ __global__ void __launch_bounds__(kBlock) k_residual_march(Level<T> L, const TB 
                            const int h = hi >= 0 ? hi : c;
                            const R xl = lo >= 0 ? (R)nbv[a][0] : (R)vc, xh = hi >= 0 ? (R)nbv[a][1] : (R)vc;
                            const R wl = (R)L.cs[a][c], wh = (R)L.cs[a][h];
-                           acc += (lo >= 0 ? wl : (R)0) * ((R)vc - xl);
-                           acc += (hi >= 0 ? wh : (R)0) * ((R)vc - xh);
+                           acc = fmar(lo >= 0 ? wl : (R)0, (R)vc - xl, acc);
+                           acc = fmar(hi >= 0 ? wh : (R)0, (R)vc - xh, acc);
                        }
                        L.r[c] = (T)((R)b[c] - acc);
                    });
@@ -782,6 +782,353 @@ static inline int march_sweep_grid(const Geo &g, int &ncolx, int &ncol, int &nti
     ncolx = (int)((g.n[0] + kMX - 1) / kMX);
     ncol = ncolx * (int)((g.n[1] + kMY - 1) / kMY);
     ntiles = ncol * (int)((g.n[2] + kSweepPlanes - 1) / kSweepPlanes);
+    return ntiles > 8 ? (ntiles + 7) & ~7 : ntiles;
+}
+
+// ---------------------------------------------------------------------------
+// 3D V-cycle passes on cubic tiles (levels of at most Slot::tile_cells cells
+// above the single-workgroup part): ONE launch per level on the way down
+// (zero-guess pre-smoothing, residual, restriction) and one on the way up
+// (prolongation, black sweep, red sweep), where the grid-wide form takes
+// three dependent launches each -- on these levels a launch costs more than
+// its sweep.  A workgroup owns a kTF^3 block of fine cells (kTC^3 coarse
+// cells) and recomputes into LDS what its cells' stencils reach in the
+// neighbouring tiles:
+//   down: b / d of the red cells on a halo of 3, x on a halo of 2, the
+//         residual on a halo of 1 (the restriction's outer taps);
+//   up:   red x + P e on a halo of 2, the black GS values on a halo of 1,
+//         then the red GS values of the owned cells.
+// Each value is formed with the arithmetic and order of the grid-wide
+// bodies (presmooth_cell, apply_at, restrict_cell, prolong_at,
+// gs_color_cell), so both forms give the same bits.  The pre-smoothed x of
+// the owned cells goes to the level's r array (the residual stays in LDS)
+// and the way up reads it there, writing the smoothed x: a workgroup writes
+// its cells while its neighbours still read their halo values.  Positions
+// past a wall hold 0 and enter only with weight 0, as a missing neighbour
+// does in the grid-wide bodies (the zero product added to a sum that starts
+// at +0 leaves it unchanged).
+// ---------------------------------------------------------------------------
+constexpr int kTF = 8, kTC = kTF / 2;   // fine / coarse cells per tile edge
+// Threads per tile: at most one cell of each region per thread (two of the
+// widest halo), so that all loads of a tile kernel are issued together.
+constexpr int kT3Threads = 1024;
+
+// Global index and coordinates of position (lx, ly, lz) of a tile whose
+// first fine cell is f0, with a halo of H cells, wrapped on periodic axes;
+// ok = false past a wall (the index is then that of a cell inside).
+template <int H>
+__device__ inline int tile_cell(const Geo &g, const int f0[3], int lx, int ly, int lz, int ia[3], bool &ok) {
+    const int l[3] = {lx, ly, lz};
+    ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int p = f0[a] - H + l[a];
+        if (p < 0 || p >= g.n[a]) {
+            ok = ok && g.per[a] != 0;
+            p %= g.n[a];
+            p = p < 0 ? p + g.n[a] : p;
+        }
+        ia[a] = p;
+    }
+    return ia[0] + g.n[0] * (ia[1] + g.n[1] * ia[2]);
+}
+
+// x-pair k of a region of edge E (E even, halo H): position of the member
+// of colour col (colour = parity of the global coordinates; the tile origin
+// is even and periodic extents are even, so it is the parity of the
+// unwrapped position)
+template <int E, int H>
+__device__ inline void tile_pair(int k, int col, int &lx, int &ly, int &lz) {
+    const int kx = k % (E / 2), r = k / (E / 2);
+    ly = r % E;
+    lz = r / E;
+    lx = 2 * kx + ((H + ly + lz + col) & 1);
+}
+
+template <int E>
+__device__ inline void tile_split(int q, int &lx, int &ly, int &lz) {
+    lx = q % E;
+    const int r = q / E;
+    ly = r % E;
+    lz = r / E;
+}
+
+// The loads of one cell's stencil, issued at the start of a tile kernel
+// (each kernel then waits on one round of loads, not one per pass):
+// neighbour existence (nb_lo / nb_hi), b, the diagonal term (1 / d for a
+// sweep, s for the residual) and the coefficients of the faces towards the
+// neighbours.
+template <typename T>
+struct TileSt {
+    bool lo[3], hi[3];
+    T bv, dv, wl[3], wh[3];
+};
+
+template <typename T, typename TB, bool RES>
+__device__ inline void tile_load(const Level<T> &L, const TB *__restrict__ b, int c, const int ia[3], TileSt<T> &S) {
+    using R = T;
+    S.bv = (R)b[c];
+    S.dv = RES ? (R)L.s[c] : (R)L.invd[c];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int lo = nb_lo(L.g, c, ia[a], a);
+        const int hi = nb_hi(L.g, c, ia[a], a);
+        const int h = hi >= 0 ? hi : c;
+        S.lo[a] = lo >= 0;
+        S.hi[a] = hi >= 0;
+        S.wl[a] = (R)L.cs[a][c];
+        S.wh[a] = (R)L.cs[a][h];
+    }
+}
+
+// GS value (b_c + sum_b cs * v_nb) / d_c from the neighbours' values at
+// stride offsets of position q of an LDS region of edge E (offsum_at's
+// order; a missing neighbour enters as 0 with weight 0)
+template <typename T, int E>
+__device__ inline T tile_gs(const TileSt<T> &S, const T *v, int q) {
+    using R = T;
+    constexpr int st[3] = {1, E, E * E};
+    R acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R vl = S.lo[a] ? (R)v[q - st[a]] : (R)0, vh = S.hi[a] ? (R)v[q + st[a]] : (R)0;
+        acc = fmar(S.lo[a] ? S.wl[a] : (R)0, vl, acc);
+        acc = fmar(S.hi[a] ? S.wh[a] : (R)0, vh, acc);
+    }
+    return (T)((S.bv + acc) * S.dv);
+}
+
+// residual b - A x at position q (apply_at's order)
+template <typename T, int E>
+__device__ inline T tile_res(const TileSt<T> &S, const T *v, int q) {
+    using R = T;
+    constexpr int st[3] = {1, E, E * E};
+    const R xc = (R)v[q];
+    R acc = S.dv * xc;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const R xl = S.lo[a] ? (R)v[q - st[a]] : xc, xh = S.hi[a] ? (R)v[q + st[a]] : xc;
+        acc = fmar(S.lo[a] ? S.wl[a] : (R)0, xc - xl, acc);
+        acc = fmar(S.hi[a] ? S.wh[a] : (R)0, xc - xh, acc);
+    }
+    return (T)(S.bv - acc);
+}
+
+// P e at fine cell fi: the eight coarse taps loaded up front, then
+// prolong_at's weights and summation order
+template <typename T>
+struct TilePro {
+    T X[2][2][2];
+    T w0[3], w1[3];
+};
+
+template <typename T>
+__device__ inline void pro_load(const Geo &gc, const T *__restrict__ xc, const int fi[3], TilePro<T> &P) {
+    using R = T;
+    int c0[3], c1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pro_axis<R>(fi[a], gc.n[a], gc.per[a], c0[a], c1[a], P.w0[a], P.w1[a]);
+    const int nx = gc.n[0], nxy = gc.n[0] * gc.n[1];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        const int kz = (dz ? c1[2] : c0[2]) * nxy;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int ky = kz + (dy ? c1[1] : c0[1]) * nx;
+            P.X[dz][dy][0] = xc[ky + c0[0]];
+            P.X[dz][dy][1] = xc[ky + c1[0]];
+        }
+    }
+}
+
+template <typename T>
+__device__ inline T pro_value(const TilePro<T> &P) {
+    using R = T;
+    R v = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+        const R wz = dz ? P.w1[2] : P.w0[2];
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const R wyz = wz * (dy ? P.w1[1] : P.w0[1]);
+            v = pro_row(v, wyz, P.w0[0], (R)P.X[dz][dy][0], P.w1[0], (R)P.X[dz][dy][1]);
+        }
+    }
+    return v;
+}
+
+template <typename T, typename TB>
+__global__ void __launch_bounds__(kT3Threads) k_down3_tile(Level<T> L, Geo gc, const TB *__restrict__ b,
+                                                           T *__restrict__ bc, int ntx, int nty, int ntiles,
+                                                           const int *__restrict__ done) {
+    using R = T;
+    const int tile = xcd_block();
+    if (tile >= ntiles || *done) return;
+    constexpr int E3 = kTF + 6, E2 = kTF + 4, E1 = kTF + 2;
+    constexpr int N3 = E3 * E3 * E3 / 2, N2 = E2 * E2 * E2 / 2, N1 = E1 * E1 * E1;
+    constexpr int K3 = (N3 + kT3Threads - 1) / kT3Threads;
+    static_assert(N2 <= kT3Threads && N1 <= kT3Threads, "one x pair and one residual cell per thread");
+    __shared__ T sd[E3 * E3 * E3];   // red b / d, halo 3
+    __shared__ T sx[E2 * E2 * E2];   // pre-smoothed x, halo 2
+    __shared__ T sr[E1 * E1 * E1];   // residual, halo 1
+    const Geo &g = L.g;
+    const int tz = tile / (ntx * nty), trem = tile - tz * ntx * nty, ty = trem / ntx, tx = trem - ty * ntx;
+    const int f0[3] = {tx * kTF, ty * kTF, tz * kTF};
+    const int tid = (int)threadIdx.x;
+    // loads: red b and 1 / d (halo 3), the black member of an x-pair (halo 2),
+    // a residual cell (halo 1)
+    R rb[K3], rd[K3];
+    int rq[K3];
+    bool rok[K3];
+#pragma unroll
+    for (int j = 0; j < K3; ++j) {
+        const int k = tid + j * kT3Threads;
+        int lx, ly, lz, ia[3];
+        tile_pair<E3, 3>(k < N3 ? k : N3 - 1, 0, lx, ly, lz);
+        const int c = tile_cell<3>(g, f0, lx, ly, lz, ia, rok[j]);
+        rq[j] = lx + E3 * (ly + E3 * lz);
+        rb[j] = (R)b[c];
+        rd[j] = (R)L.invd[c];
+    }
+    int x2, y2, z2, ia2[3];
+    bool ok2;
+    tile_pair<E2, 2>(tid < N2 ? tid : 0, 1, x2, y2, z2);
+    TileSt<T> S2;
+    tile_load<T, TB, false>(L, b, tile_cell<2>(g, f0, x2, y2, z2, ia2, ok2), ia2, S2);
+    int x1, y1, z1, ia1[3];
+    bool ok1;
+    tile_split<E1>(tid < N1 ? tid : 0, x1, y1, z1);
+    TileSt<T> S1;
+    tile_load<T, TB, true>(L, b, tile_cell<1>(g, f0, x1, y1, z1, ia1, ok1), ia1, S1);
+#pragma unroll
+    for (int j = 0; j < K3; ++j)
+        if (tid + j * kT3Threads < N3) sd[rq[j]] = rok[j] ? (T)(rb[j] * rd[j]) : (T)0;
+    __syncthreads();
+    // x: black GS from the red neighbours' b / d, red b / d
+    if (tid < N2) {
+        const int q = x2 + E2 * (y2 + E2 * z2);
+        const int q3 = (x2 + 1) + E3 * ((y2 + 1) + E3 * (z2 + 1));
+        const T v = tile_gs<T, E3>(S2, sd, q3);
+        sx[q] = ok2 ? v : (T)0;
+        const int d = 1 - 2 * (x2 & 1);   // the red member of the x-pair
+        sx[q + d] = sd[q3 + d];
+    }
+    __syncthreads();
+    // r = b - A x
+    if (tid < N1) {
+        const T v = tile_res<T, E2>(S1, sx, (x1 + 1) + E2 * ((y1 + 1) + E2 * (z1 + 1)));
+        sr[tid] = ok1 ? v : (T)0;
+    }
+    // the owned cells' pre-smoothed x (read back on the way up)
+    if (tid < kTF * kTF * kTF) {
+        int lx, ly, lz;
+        tile_split<kTF>(tid, lx, ly, lz);
+        const int gx = f0[0] + lx, gy = f0[1] + ly, gz = f0[2] + lz;
+        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2])
+            L.r[gx + g.n[0] * (gy + g.n[1] * gz)] = sx[(lx + 2) + E2 * ((ly + 2) + E2 * (lz + 2))];
+    }
+    __syncthreads();
+    // restriction (restrict_cell's weights and order) of the tile's coarse cells
+    if (tid < kTC * kTC * kTC) {
+        int cx, cy, cz;
+        tile_split<kTC>(tid, cx, cy, cz);
+        const int I[3] = {tx * kTC + cx, ty * kTC + cy, tz * kTC + cz};
+        if (I[0] < gc.n[0] && I[1] < gc.n[1] && I[2] < gc.n[2]) {
+            int f[4];
+            R wx[4], wy[4], wz[4];
+            res_axis<R>(I[0], gc.n[0], g.n[0], gc.per[0], f, wx);
+            res_axis<R>(I[1], gc.n[1], g.n[1], gc.per[1], f, wy);
+            res_axis<R>(I[2], gc.n[2], g.n[2], gc.per[2], f, wz);
+            R acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const R wza = wz[a];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const T *row = &sr[2 * cx + E1 * ((2 * cy + q) + E1 * (2 * cz + a))];
+                    R s = 0.0;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) s = fmar(wx[e], (R)row[e], s);
+                    acc = fmar(wy[q] * wza, s, acc);
+                }
+            }
+            bc[(I[2] * gc.n[1] + I[1]) * gc.n[0] + I[0]] = (T)acc;
+        }
+    }
+}
+
+template <typename T, typename TB>
+__global__ void __launch_bounds__(kT3Threads) k_up3_tile(Level<T> L, Geo gc, const T *__restrict__ xc,
+                                                         const TB *__restrict__ b, const T *__restrict__ xpre,
+                                                         T *__restrict__ x, int ntx, int nty, int ntiles,
+                                                         const int *__restrict__ done) {
+    using R = T;
+    const int tile = xcd_block();
+    if (tile >= ntiles || *done) return;
+    constexpr int E2 = kTF + 4, E1 = kTF + 2;
+    constexpr int N2 = E2 * E2 * E2 / 2, N1 = E1 * E1 * E1 / 2, N0 = kTF * kTF * kTF / 2;
+    static_assert(N2 <= kT3Threads, "one red cell of the halo-2 region per thread");
+    __shared__ T se[E2 * E2 * E2];   // red x + P e, halo 2
+    __shared__ T sb[E1 * E1 * E1];   // black GS values, halo 1
+    const Geo &g = L.g;
+    const int tz = tile / (ntx * nty), trem = tile - tz * ntx * nty, ty = trem / ntx, tx = trem - ty * ntx;
+    const int f0[3] = {tx * kTF, ty * kTF, tz * kTF};
+    const int tid = (int)threadIdx.x;
+    // loads: a red cell's x and coarse taps (halo 2), a black cell (halo 1),
+    // an owned x-pair
+    int x2, y2, z2, ia2[3];
+    bool ok2;
+    tile_pair<E2, 2>(tid < N2 ? tid : 0, 0, x2, y2, z2);
+    const int c2 = tile_cell<2>(g, f0, x2, y2, z2, ia2, ok2);
+    const R xp = (R)xpre[c2];
+    TilePro<T> P;
+    pro_load<T>(gc, xc, ia2, P);
+    int x1, y1, z1, ia1[3];
+    bool ok1;
+    tile_pair<E1, 1>(tid < N1 ? tid : 0, 1, x1, y1, z1);
+    TileSt<T> S1;
+    tile_load<T, TB, false>(L, b, tile_cell<1>(g, f0, x1, y1, z1, ia1, ok1), ia1, S1);
+    int x0, y0, z0;
+    tile_pair<kTF, 0>(tid < N0 ? tid : 0, 0, x0, y0, z0);
+    int ia0[3] = {f0[0] + x0, f0[1] + y0, f0[2] + z0};
+    // whole pairs (even extents): the red member inside <=> the pair inside
+    const bool own0 = tid < N0 && ia0[0] < g.n[0] && ia0[1] < g.n[1] && ia0[2] < g.n[2];
+    if (!own0) ia0[0] = ia0[1] = ia0[2] = 0;
+    const int c0 = ia0[0] + g.n[0] * (ia0[1] + g.n[1] * ia0[2]);
+    TileSt<T> S0;
+    tile_load<T, TB, false>(L, b, c0, ia0, S0);
+    if (tid < N2) {
+        const T v = (T)(xp + pro_value<T>(P));
+        se[x2 + E2 * (y2 + E2 * z2)] = ok2 ? v : (T)0;
+    }
+    __syncthreads();
+    if (tid < N1) {
+        const T v = tile_gs<T, E2>(S1, se, (x1 + 1) + E2 * ((y1 + 1) + E2 * (z1 + 1)));
+        sb[x1 + E1 * (y1 + E1 * z1)] = ok1 ? v : (T)0;
+    }
+    __syncthreads();
+    if (own0) {
+        const int q1 = (x0 + 1) + E1 * ((y0 + 1) + E1 * (z0 + 1));
+        const int d = 1 - 2 * (x0 & 1);   // the black member of the x-pair
+        x[c0] = tile_gs<T, E1>(S0, sb, q1);
+        x[c0 + d] = sb[q1 + d];
+    }
+}
+
+// Whether level l of a 3D slot runs the tile passes: above the
+// single-workgroup part, below march_cells and at most tile_cells cells,
+// with even extents (every level that has a coarser one).
+template <typename T>
+static bool tile3_level(const Slot<T> &S, int l) {
+    const Geo &g = S.lev[l].g;
+    return l + 1 < S.nlev && g.N <= S.tile_cells && g.N < S.march_cells && (g.n[0] & 1) == 0 &&
+           (g.n[1] & 1) == 0 && (g.n[2] & 1) == 0;
+}
+
+static inline int tile3_grid(const Geo &gc, int &ntx, int &nty, int &ntiles) {
+    ntx = (gc.n[0] + kTC - 1) / kTC;
+    nty = (gc.n[1] + kTC - 1) / kTC;
+    ntiles = ntx * nty * ((gc.n[2] + kTC - 1) / kTC);
     return ntiles > 8 ? (ntiles + 7) & ~7 : ntiles;
 }
 
@@ -1146,6 +1493,14 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
         return;
     }
     const double WB = sizeof(TB) - W;   // extra bytes of a wider right-hand side
+    if (DIM == 3 && tile3_level(S, l)) {
+        // b, invd, s, cs in; pre-smoothed x (to r) and the coarse b out
+        int ntx, nty, ntiles;
+        const int grid = tile3_grid(S.lev[l + 1].g, ntx, nty, ntiles);
+        TLAUNCH(K_MG_DOWN, (sizeof(TB) + W * (3 + DIM)) * N + W * Nc, (k_down3_tile<T, TB>), dim3(grid),
+                dim3(kT3Threads), st, lv, S.lev[l + 1].g, b, S.lev[l + 1].b, ntx, nty, ntiles, done);
+        return;
+    }
     if (DIM == 3 && lv.g.N >= S.march_cells) {
         int ncolx, ncol, ntiles;
         const int grid = march_sweep_grid(lv.g, ncolx, ncol, ntiles);
@@ -1198,6 +1553,15 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
         return;
     }
     const double WB = sizeof(TB) - W;
+    if (DIM == 3 && tile3_level(S, l)) {
+        // pre-smoothed x (from r), b, invd, cs, coarse x in; x out
+        int ntx, nty, ntiles;
+        const int grid = tile3_grid(S.lev[l + 1].g, ntx, nty, ntiles);
+        TLAUNCH(K_MG_UP, (sizeof(TB) + W * (3 + DIM)) * N + W * Nc, (k_up3_tile<T, TB>), dim3(grid),
+                dim3(kT3Threads), st, lv, S.lev[l + 1].g, (const T *)S.lev[l + 1].x, b, (const T *)lv.r, x, ntx, nty,
+                ntiles, done);
+        return;
+    }
     if (DIM == 3) {
         // one thread per coarse cell (fine x extent is even on every level above the coarsest)
         LAUNCH(K_PROLONG, W * (2 * N + Nc), (k_prolong_add3<T>), Nc, st, lv.g, S.lev[l + 1].g,

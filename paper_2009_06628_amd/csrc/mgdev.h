@@ -26,6 +26,14 @@ __device__ inline void coords_of(const Geo &g, int c, int ia[3]) {
 // stencil is unconditional and can be issued together (adding 0 leaves the
 // sums unchanged).
 
+// a * b + c, rounded once.  The stencil sums of the multigrid spell their
+// fused multiply-adds out: left to contraction, a sum that starts with two
+// products is fused on one or the other depending on the surrounding code,
+// and the grid-wide, marching, tile and LDS forms of a pass must round alike
+// (they are compared bit for bit).
+__device__ inline float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // (A x)_c
 template <typename T, int DIM>
 __device__ inline T apply_at(const Level<T> &L, const T *__restrict__ x, int c, const int ia[3]) {
@@ -40,8 +48,8 @@ __device__ inline T apply_at(const Level<T> &L, const T *__restrict__ x, int c, 
         const int l = lo >= 0 ? lo : c, h = hi >= 0 ? hi : c;
         const R xl = (R)x[l], xh = (R)x[h];
         const R wl = (R)L.cs[b][c], wh = (R)L.cs[b][h];
-        acc += (lo >= 0 ? wl : (R)0) * (xc - xl);
-        acc += (hi >= 0 ? wh : (R)0) * (xc - xh);
+        acc = fmar(lo >= 0 ? wl : (R)0, xc - xl, acc);
+        acc = fmar(hi >= 0 ? wh : (R)0, xc - xh, acc);
     }
     return acc;
 }
@@ -59,8 +67,8 @@ __device__ inline T offsum_at(const Level<T> &L, int c, const int ia[3], F xv) {
         const int l = lo >= 0 ? lo : c, h = hi >= 0 ? hi : c;
         const R vl = xv(l), vh = xv(h);
         const R wl = (R)L.cs[b][c], wh = (R)L.cs[b][h];
-        acc += (lo >= 0 ? wl : (R)0) * vl;
-        acc += (hi >= 0 ? wh : (R)0) * vh;
+        acc = fmar(lo >= 0 ? wl : (R)0, vl, acc);
+        acc = fmar(hi >= 0 ? wh : (R)0, vh, acc);
     }
     return acc;
 }
@@ -102,6 +110,12 @@ __device__ inline void residual_cell(const Level<T> &L, const TB *__restrict__ b
     int ia[3];
     coords_of<DIM>(L.g, c, ia);
     L.r[c] = (T)((R)b[c] - apply_at<T, DIM>(L, x, c, ia));
+}
+
+// One (z, y) row of the prolongation: v + wyz (w0 a + w1 b)
+template <typename R>
+__device__ inline R pro_row(R v, R wyz, R w0, R a, R w1, R b) {
+    return fmar(wyz, fmar(w0, a, w1 * b), v);
 }
 
 // cell-centred linear prolongation along one axis: fine f takes 3/4 of its
@@ -152,7 +166,7 @@ __device__ inline T prolong_at(const Geo &gf, const Geo &gc, const T *__restrict
         for (int dy = 0; dy < 2; ++dy) {
             const int ky = kz + (dy ? c1[1] : c0[1]) * nx;
             const R wyz = wz * (dy ? w1[1] : w0[1]);
-            v += wyz * (w0[0] * (R)xc[ky + c0[0]] + w1[0] * (R)xc[ky + c1[0]]);
+            v = pro_row(v, wyz, w0[0], (R)xc[ky + c0[0]], w1[0], (R)xc[ky + c1[0]]);
         }
     }
     return v;
@@ -198,8 +212,8 @@ __device__ inline void restrict_cell(const Geo &gf, const Geo &gc, const T *__re
             const int row = kz + fy[q] * nx;
             R s = 0.0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) s += wx[e] * (R)rf[row + fx[e]];
-            v += (wy[q] * wza) * s;
+            for (int e = 0; e < 4; ++e) s = fmar(wx[e], (R)rf[row + fx[e]], s);
+            v = fmar(wy[q] * wza, s, v);
         }
     }
     bc[c] = (T)v;
@@ -595,7 +609,7 @@ template <int Q, typename T, int DIM, typename V>
 __device__ inline T pair_offsum(const LdsPair<T, DIM> &P, V v) {
     T acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < 2 * DIM; ++i) acc += P.cw[Q][i] * v(P.nb[Q][i]);
+    for (int i = 0; i < 2 * DIM; ++i) acc = fmar(P.cw[Q][i], v(P.nb[Q][i]), acc);
     return acc;
 }
 
@@ -611,7 +625,7 @@ __device__ inline T pair_residual(const LdsPair<T, DIM> &P, const T *s, const T 
     const T xc = x[P.c[Q]];
     T acc = s[P.c[Q]] * xc;
 #pragma unroll
-    for (int i = 0; i < 2 * DIM; ++i) acc += P.cw[Q][i] * (xc - x[P.nb[Q][i]]);
+    for (int i = 0; i < 2 * DIM; ++i) acc = fmar(P.cw[Q][i], xc - x[P.nb[Q][i]], acc);
     return P.b[Q] - acc;
 }
 

@@ -46,6 +46,7 @@ inline void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
     S.lsb = 0;
     S.ltrunc = 0;
     S.march_cells = kMarchSweepCells;
+    S.tile_cells = kTileCycleCells;
     S.rho = nullptr;
     S.rho_ih2 = 0.0;
     S.singular = singular;

@@ -172,6 +172,64 @@ def test_march_sweeps_whole_step_bitwise():
         assert torch.equal(out[0]["u"][a], out[1]["u"][a]), a
 
 
+@pytest.mark.parametrize("n,per", [((36, 20, 40), (False, True, False)), ((32, 32, 32), (True, True, True)),
+                                   ((48, 24, 32), (True, False, True))])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tile_cycle_matches_grid_stride_and_oracle(n, per, precision):
+    """3D V-cycle passes over 8^3-cell tiles with recomputed halos (one
+    launch per level and side), forced onto every level above the
+    single-workgroup part with a large CHNS_OPT_TILE_CYCLE_CELLS, on grids
+    with ragged tiles and walls: the pressure solve is bit for bit that of
+    the grid-wide passes (tile cells 0) in both precision forms and matches
+    the oracle."""
+    P = _lib()
+    rng = np.random.default_rng(13)
+    og = MACGrid(n, 1.0 / n[0], per)
+    X = og.coords()
+    r2 = sum((X[a] - 0.5 * og.n[a] * og.h) ** 2 for a in range(og.dim))
+    phi = np.tanh((np.sqrt(r2) - 0.25) / (math.sqrt(2) * 3 * og.h))
+    rho = 0.5 * (1 - 1e-2) * phi + 0.5 * (1 + 1e-2)
+    rhs = rng.normal(size=og.shape)
+    rhs -= rhs.mean()
+    ref = O.pressure_solve(og, [og.avg(rho, a) for a in range(og.dim)], rhs)
+    bc = ["periodic" if p else "wall" for p in per]
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    sols = []
+    for cells in (0, 1 << 30):
+        g = P.create_grid(n, 1.0 / n[0], bc, precision=precision)
+        g.set_option(P.CHNS_OPT_TILE_CYCLE_CELLS, cells)
+        p = dev(np.zeros(og.shape))
+        out = g.solve_pressure(dev(rho), dev(rhs), p, rtol=1e-12, max_iter=300)
+        print("pressure solve", n, "precision", precision, "tile cells", cells, out, flush=True)
+        assert out["rc"] == 0
+        sols.append(p)
+    assert torch.equal(sols[0], sols[1])
+    assert relerr(to_np(sols[1]), ref) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tile_cycle_whole_step_bitwise(precision):
+    """Five steps of the 3D drop (CH by MG-PCG, truncated momentum cycles)
+    with the tile passes on every eligible level equal the run with the
+    grid-wide passes only, bit for bit."""
+    P = _lib()
+    prob = W.drop3d(32, steps=5)
+    if precision:
+        prob = W.drop3d(32, steps=5, **W.PRECISION_FORM_TOLERANCES)
+    out = []
+    for cells in (0, 1 << 30):
+        g = P.grid_for_problem(prob, precision)
+        g.set_option(P.CHNS_OPT_TILE_CYCLE_CELLS, cells)
+        g.set_option(P.CHNS_OPT_CH_SOLVER, P.CHNS_CH_PCG)
+        st = g.new_state(W.initial_state(prob))
+        g.step(st, 5)
+        out.append(st)
+    for k in ("phi", "p", "mu"):
+        assert torch.equal(out[0][k], out[1][k]), k
+    for a in range(3):
+        assert torch.equal(out[0]["u"][a], out[1]["u"][a]), a
+
+
 # ---------------------------------------------------------------------------
 # whole steps
 # ---------------------------------------------------------------------------
