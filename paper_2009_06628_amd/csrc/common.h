@@ -215,7 +215,7 @@ struct Slot {
     int nlev;
     int lsb;        // first level handled by the single-workgroup kernel
     int ltrunc;     // 3D: the V-cycle ends at this grid level with a symmetric
-                    // Gauss-Seidel solve (0: full cycle down to the coarsest)
+                    // Gauss-Seidel solve (-1: full cycle down to the coarsest)
     long long march_cells;   // 3D levels with at least this many cells sweep marching along z
     long long tile_cells;    // 3D levels with at most this many cells (above the single-workgroup
                              // part, below march_cells) run one tile pass per side of the cycle

@@ -1410,10 +1410,10 @@ static int single_block_level(const Slot<T> &S) {
     return l;
 }
 
-// Level at which the V-cycle of S ends (0: it runs down to the coarsest).
+// Level at which the V-cycle of S ends (-1: it runs down to the coarsest).
 template <typename T>
 static int trunc_level(const Slot<T> &S, int dim) {
-    return dim == 3 && S.ltrunc > 0 && S.ltrunc < S.lsb ? S.ltrunc : 0;
+    return dim == 3 && S.ltrunc >= 0 && S.ltrunc < S.lsb ? S.ltrunc : -1;
 }
 
 template <typename T, int DIM>
@@ -1423,12 +1423,12 @@ static void mg_setup_d(Slot<T> &S, hipStream_t st) {
     const int lsb = S.lsb;
     const int lt = trunc_level(S, DIM);
     if (lsb > 0) LAUNCH(K_MG_SETUP, W * (2 + DIM) * S.lev[0].g.N, (k_invd<T, DIM>), S.lev[0].g.N, st, S.lev[0]);
-    for (int l = 1; l < (lt ? lt + 1 : lsb); ++l) {
+    for (int l = 1; l < (lt >= 0 ? lt + 1 : lsb); ++l) {
         LAUNCH(K_MG_SETUP, W * (1 + DIM) * (S.lev[l - 1].g.N + S.lev[l].g.N), (k_coarsen<T, DIM>), S.lev[l].g.N, st,
                S.lev[l - 1], S.lev[l]);
         LAUNCH(K_MG_SETUP, W * (2 + DIM) * S.lev[l].g.N, (k_invd<T, DIM>), S.lev[l].g.N, st, S.lev[l]);
     }
-    if (lt) return;   // the cycle ends at level lt: no small levels, no coarsest inverse
+    if (lt >= 0) return;   // the cycle ends at level lt: no small levels, no coarsest inverse
     double bytes = 0.0;
     for (int l = lsb; l < S.nlev; ++l) bytes += W * (2 + 2 * DIM) * S.lev[l].g.N;
     bytes += 8.0 * S.ncoarse * S.ncoarse;
@@ -1586,20 +1586,29 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
                      const L0Cg<TR> *cg = nullptr) {
     constexpr double W = sizeof(T);
     const int lsb = S.lsb;
-    if (const int lt = trunc_level(S, DIM)) {
+    if (const int lt = trunc_level(S, DIM); lt >= 0) {
         // truncated cycle (3D): down to level lt, which is solved by one
         // symmetric red-black Gauss-Seidel sweep from zero (red, black as the
         // zero-guess pre-smoothing, then red again: the backward sweep's black
-        // half would repeat the forward one), then back up
+        // half would repeat the forward one), then back up; at lt = 0 the
+        // preconditioner is that sweep alone
+        auto sgs = [&](Level<T> &L, const auto *b, T *x) {
+            using TL = std::remove_cv_t<std::remove_pointer_t<decltype(b)>>;
+            const double WL = sizeof(TL) - W;
+            const int N = (int)L.g.N;
+            if ((L.g.n[0] & 1) == 0)
+                LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WL * N, (k_presmooth_pair<T, TL, DIM>), N / 2, st, L, b, x, done);
+            else
+                LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WL * N, (k_presmooth<T, TL, DIM>), N, st, L, b, x, done);
+            LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WL * N, (k_gs_color<T, TL, DIM>), N, st, L, b, x, 0, done);
+        };
+        if (lt == 0) {
+            sgs(S.lev[0], b0, x0);
+            return;
+        }
         vcycle_down<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg);
         for (int l = 1; l < lt; ++l) vcycle_down<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
-        Level<T> &L = S.lev[lt];
-        const int N = (int)L.g.N;
-        if ((L.g.n[0] & 1) == 0)
-            LAUNCH(K_SMOOTH, W * (3 + DIM) * N, (k_presmooth_pair<T, T, DIM>), N / 2, st, L, (const T *)L.b, L.x, done);
-        else
-            LAUNCH(K_SMOOTH, W * (3 + DIM) * N, (k_presmooth<T, T, DIM>), N, st, L, (const T *)L.b, L.x, done);
-        LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N, (k_gs_color<T, T, DIM>), N, st, L, (const T *)L.b, L.x, 0, done);
+        sgs(S.lev[lt], (const T *)S.lev[lt].b, S.lev[lt].x);
         for (int l = lt - 1; l >= 1; --l) vcycle_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
         vcycle_up<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg);
         return;

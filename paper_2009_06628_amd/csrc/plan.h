@@ -44,7 +44,7 @@ template <typename T>
 inline void carve_slot(Bump &B, const Plan &P, Slot<T> &S, int singular) {
     S.nlev = P.nlev;
     S.lsb = 0;
-    S.ltrunc = 0;
+    S.ltrunc = -1;
     S.march_cells = kMarchSweepCells;
     S.tile_cells = kTileCycleCells;
     S.rho = nullptr;

@@ -68,8 +68,8 @@ CASES = {
                                     "velocity": "stream", "vseed": 8, "vamp": 0.1},
         bc=(W.PERIODIC, W.WALL), inv_Fr=1.0, rho3=(3.0, 0.2, 1.0), steps=100),
     # densities (100, 10, 1), viscosities 1e-2, Re = 1, dt = 1e-4: the momentum
-    # shift 1e4 is ~650x the off-diagonal sum of the 16^3 level, so the 3D
-    # momentum V-cycles end there (symmetric Gauss-Seidel solve)
+    # shift 1e4 is ~160x the off-diagonal sum on the grid, so the 3D momentum
+    # preconditioner is one symmetric Gauss-Seidel sweep on the grid
     "drops3d_32": lambda: W.ternary_drops3d(32, steps=100),
 }
 
