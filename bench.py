@@ -116,7 +116,7 @@ def recorded_traffic(workload, kernel_class):
 # Kernel classes of the library's per-kernel timing, by kernel name (the
 # template arguments after the name are matched by the workload filters).
 KERNEL_CLASSES = {
-    "smooth": ("k_presmooth_pair", "k_presmooth", "k_gs_color", "k_presmooth_march", "k_gs_color_march"),
+    "smooth": ("k_presmooth_pair", "k_presmooth", "k_gs_color", "k_presmooth_march", "k_gs_color_march", "k_gs_red_rz"),
     "residual": ("k_residual", "k_residual_march"),
     "restrict": ("k_restrict3_lds", "k_restrict3_pair", "k_restrict"),
     "prolong": ("k_prolong_add3",),

@@ -1177,6 +1177,22 @@ __global__ void __launch_bounds__(kBlock) k_pcg_ch_apply(Geo g, double ih2, doub
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// End of CG iteration: r.r, the iteration count and the stop flags (thread 0)
+__device__ inline void pcg_fin_rr_dev(Scal *sc, double rr) {
+    if (threadIdx.x != 0) return;
+    sc->rr = rr;
+    sc->iter += 1;
+    if (!isfinite(rr)) {
+        sc->nonfinite = 1;
+        sc->done = 1;
+    } else if (rr <= sc->rtol2 * sc->bb) {
+        sc->done = 1;
+    } else if (sc->iter >= sc->max_iter) {
+        sc->unconverged = 1;
+        sc->done = 1;
+    }
+}
+
 // alpha = rz / sum(part_pq) (every block, same order); x += alpha p;
 // r -= alpha q; partial r.r.  TP != T: also rp = r rounded to TP (the
 // right-hand side of the preconditioner in its own precision).
@@ -1215,20 +1231,7 @@ __global__ void __launch_bounds__(kBlock) k_round_vec(int N, const T *__restrict
 __global__ void __launch_bounds__(kBlock) k_pcg_fin_rr(Scal *sc, const double *__restrict__ part_rr, int nparts) {
     if (sc->done) return;
     __shared__ double lds[kBlock / kWave];
-    const double rr = sum_parts_all(part_rr, nparts, lds);
-    if (threadIdx.x == 0) {
-        sc->rr = rr;
-        sc->iter += 1;
-        if (!isfinite(rr)) {
-            sc->nonfinite = 1;
-            sc->done = 1;
-        } else if (rr <= sc->rtol2 * sc->bb) {
-            sc->done = 1;
-        } else if (sc->iter >= sc->max_iter) {
-            sc->unconverged = 1;
-            sc->done = 1;
-        }
-    }
+    pcg_fin_rr_dev(sc, sum_parts_all(part_rr, nparts, lds));
 }
 
 // partials of r.z, sum z, sum r
@@ -1241,6 +1244,36 @@ __global__ void __launch_bounds__(kBlock) k_pcg_rz(int N, const T *__restrict__ 
     double arz = 0.0, az = 0.0, ar = 0.0;
     GRID_LOOP(N) {
         const double rc = (double)r[c], zc = (double)z[c];
+        arz += rc * zc;
+        az += zc;
+        ar += rc;
+    }
+    const double s0 = block_sum(arz, lds);
+    const double s1 = singular ? block_sum(az, lds) : 0.0;
+    const double s2 = singular ? block_sum(ar, lds) : 0.0;
+    if (threadIdx.x == 0) {
+        p0[blockIdx.x] = s0;
+        p1[blockIdx.x] = s1;
+        p2[blockIdx.x] = s2;
+    }
+}
+
+// The last pass of a 3D preconditioner (the red sweep of level 0) with the
+// partials of k_pcg_rz: the same cells per thread and block (grid-stride
+// over grid_red(N) blocks) and the same sums, so the partials are those of
+// the separate pass bit for bit; the z of a black cell is read back, the
+// z of a red cell is its new value.
+template <typename T, typename TB, int DIM, typename TR>
+__global__ void __launch_bounds__(kBlock) k_gs_red_rz(Level<T> L, const TB *__restrict__ b, T *__restrict__ x,
+                                                      const TR *__restrict__ r, const Scal *__restrict__ sc,
+                                                      double *__restrict__ p0, double *__restrict__ p1,
+                                                      double *__restrict__ p2, int singular) {
+    if (sc->done) return;
+    __shared__ double lds[kBlock / kWave];
+    double arz = 0.0, az = 0.0, ar = 0.0;
+    GRID_LOOP(L.g.N) {
+        gs_color_cell<T, TB, DIM>(L, b, x, 0, c);
+        const double rc = (double)r[c], zc = (double)x[c];
         arz += rc * zc;
         az += zc;
         ar += rc;
@@ -1467,6 +1500,32 @@ static void tile_grid2(const Geo &g, int &ntx, int &ntiles, int &grid) {
     grid = ntiles > 8 ? (ntiles + 7) & ~7 : ntiles;
 }
 
+// The r.z partials of CG (k_pcg_rz) taken by the last pass of a 3D
+// preconditioner, the red sweep of level 0 (k_gs_red_rz); *taken is set
+// when that pass ran in the grid-wide form, which is the one that can.
+template <typename TR>
+struct RzFuse {
+    const TR *r;
+    const Scal *sc;
+    double *p0, *p1, *p2;
+    int singular;
+    bool *taken;
+};
+
+// red sweep of level 0, with the r.z partials when rz is given
+template <typename T, typename TB, int DIM, typename TR>
+static void gs_red_last(Level<T> &L, const TB *b, T *x, const int *done, hipStream_t st, const RzFuse<TR> *rz) {
+    const double N = (double)L.g.N;
+    const double bytes = sizeof(T) * (3.5 + DIM) * N + (sizeof(TB) - sizeof(T)) * N;
+    if (rz) {
+        LAUNCHR(K_SMOOTH, bytes + sizeof(TR) * N, (k_gs_red_rz<T, TB, DIM, TR>), L.g.N, st, L, b, x, rz->r, rz->sc,
+                rz->p0, rz->p1, rz->p2, rz->singular);
+        *rz->taken = true;
+    } else {
+        LAUNCH(K_SMOOTH, bytes, (k_gs_color<T, TB, DIM>), L.g.N, st, L, b, x, 0, done);
+    }
+}
+
 template <typename T, typename TB, int DIM, typename TR = T>
 static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st,
                         const L0Cg<TR> *cg = nullptr) {
@@ -1527,7 +1586,7 @@ static void vcycle_down(Slot<T> &S, int l, const TB *b, T *x, const int *done, h
 
 template <typename T, typename TB, int DIM, typename TR = T>
 static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hipStream_t st,
-                      const L0Cg<TR> *cg = nullptr) {
+                      const L0Cg<TR> *cg = nullptr, const RzFuse<TR> *rz = nullptr) {
     constexpr double W = sizeof(T);
     Level<T> &lv = S.lev[l];
     const int N = (int)lv.g.N, Nc = (int)S.lev[l + 1].g.N;
@@ -1574,7 +1633,7 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
                         st, lv, b, x, color, done, ncolx, ncol, ntiles);
         } else {
             LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 1, done);
-            LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WB * N, (k_gs_color<T, TB, DIM>), N, st, lv, b, x, 0, done);
+            gs_red_last<T, TB, DIM, TR>(lv, b, x, done, st, rz);
         }
     }
 }
@@ -1583,7 +1642,7 @@ static void vcycle_up(Slot<T> &S, int l, const TB *b, T *x, const int *done, hip
 // precision than the hierarchy).
 template <typename T, typename TB, int DIM, typename TR = T>
 static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream_t st,
-                     const L0Cg<TR> *cg = nullptr) {
+                     const L0Cg<TR> *cg = nullptr, const RzFuse<TR> *rz = nullptr) {
     constexpr double W = sizeof(T);
     const int lsb = S.lsb;
     if (const int lt = trunc_level(S, DIM); lt >= 0) {
@@ -1592,7 +1651,7 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
         // zero-guess pre-smoothing, then red again: the backward sweep's black
         // half would repeat the forward one), then back up; at lt = 0 the
         // preconditioner is that sweep alone
-        auto sgs = [&](Level<T> &L, const auto *b, T *x) {
+        auto sgs = [&](Level<T> &L, const auto *b, T *x, const RzFuse<TR> *rzl) {
             using TL = std::remove_cv_t<std::remove_pointer_t<decltype(b)>>;
             const double WL = sizeof(TL) - W;
             const int N = (int)L.g.N;
@@ -1600,17 +1659,17 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
                 LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WL * N, (k_presmooth_pair<T, TL, DIM>), N / 2, st, L, b, x, done);
             else
                 LAUNCH(K_SMOOTH, W * (3 + DIM) * N + WL * N, (k_presmooth<T, TL, DIM>), N, st, L, b, x, done);
-            LAUNCH(K_SMOOTH, W * (3.5 + DIM) * N + WL * N, (k_gs_color<T, TL, DIM>), N, st, L, b, x, 0, done);
+            gs_red_last<T, TL, DIM, TR>(L, b, x, done, st, rzl);
         };
         if (lt == 0) {
-            sgs(S.lev[0], b0, x0);
+            sgs(S.lev[0], b0, x0, rz);
             return;
         }
         vcycle_down<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg);
         for (int l = 1; l < lt; ++l) vcycle_down<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
-        sgs(S.lev[lt], (const T *)S.lev[lt].b, S.lev[lt].x);
+        sgs(S.lev[lt], (const T *)S.lev[lt].b, S.lev[lt].x, nullptr);
         for (int l = lt - 1; l >= 1; --l) vcycle_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
-        vcycle_up<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg);
+        vcycle_up<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg, rz);
         return;
     }
     if (lsb > 0) {
@@ -1645,7 +1704,7 @@ static void vcycle_d(Slot<T> &S, const TB *b0, T *x0, const int *done, hipStream
     }
     if (lsb > 0) {
         for (int l = lsb - 1; l >= 1; --l) vcycle_up<T, T, DIM>(S, l, S.lev[l].b, S.lev[l].x, done, st);
-        vcycle_up<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg);
+        vcycle_up<T, TB, DIM, TR>(S, 0, b0, x0, done, st, cg, rz);
     }
 }
 
@@ -1658,14 +1717,16 @@ void mg_vcycle(Slot<T> &S, int dim, const T *b0, T *x0, const int *done, hipStre
 }
 
 // Preconditioner z = B r with the hierarchy SP (precision TP); r in T.
-template <typename T, typename TP, int DIM>
-static void precond_d(Slot<TP> &SP, OpKind kind, const T *r, TP *z, TP *w, const int *done, hipStream_t st) {
+// rz: the r.z partials of CG (vector precision TR) may ride on the last pass.
+template <typename T, typename TP, int DIM, typename TR = T>
+static void precond_d(Slot<TP> &SP, OpKind kind, const T *r, TP *z, TP *w, const int *done, hipStream_t st,
+                      const RzFuse<TR> *rz = nullptr) {
     if (kind == OP_CH) {
         // M ~ (I - c L)^2 with c = sqrt(b): two V-cycles of the slot operator
         vcycle_d<TP, T, DIM>(SP, r, w, done, st);
         vcycle_d<TP, TP, DIM>(SP, w, z, done, st);
     } else {
-        vcycle_d<TP, T, DIM>(SP, r, z, done, st);
+        vcycle_d<TP, T, DIM, TR>(SP, r, z, done, st, nullptr, rz);
     }
 }
 
@@ -1721,6 +1782,16 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
     constexpr bool split = !std::is_same<T, TP>::value;
     const TP *rpre = split ? (const TP *)v.rp : (const TP *)(const void *)v.r;
     if (split) LAUNCH(K_PCG_INIT, (W + WP) * N, (k_round_vec<T, TP>), N, st, N, (const T *)v.r, v.rp);
+    // preconditioner, then the r.z partials (in 3D with the slot operator
+    // they ride on the preconditioner's last pass where that can take them)
+    auto precond_rz = [&]() {
+        bool taken = false;
+        const RzFuse<T> rzf{(const T *)v.r, (const Scal *)sc, red.rz0, red.rz1, red.rz2, singular, &taken};
+        precond_d<TP, TP, DIM, T>(SP, kind, rpre, v.z, v.w, done, st, DIM == 3 && kind == OP_SLOT ? &rzf : nullptr);
+        if (!taken)
+            LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
+                    (const Scal *)sc, red.rz0, red.rz1, red.rz2, singular);
+    };
     // 2D with tiled level 0: the update and the r.z partials ride on the
     // level-0 tile passes (one partial per tile), and the residual store
     // moves to the next operator apply
@@ -1736,9 +1807,7 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
     if (fuse) {
         precond_cg_d<TP, DIM, T>(SP, kind, rpre, v.z, v.w, done, st, cg);
     } else {
-        precond_d<TP, TP, DIM>(SP, kind, rpre, v.z, v.w, done, st);
-        LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
-                (const Scal *)sc, red.rz0, red.rz1, red.rz2, singular);
+        precond_rz();
     }
     // 3D slot operator: the z-marching apply (8 planes per block, more when
     // the grid would exceed the partial-sum slots)
@@ -1799,13 +1868,13 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
                 precond_cg_d<TP, DIM, T>(SP, kind, rpre, v.z, v.w, done, st, c);
                 continue;
             }
+            // (a last-block finalize inside the update would need a
+            // device-scope fence per block, which costs more than this launch)
             LAUNCHR(K_PCG_UPDATE, W * 6 * N + (split ? WP * N : 0.0), (k_pcg_update<T, TP>), N, st, N,
                     (const T *)pnew, (const T *)v.q, x, v.r, sc, (const double *)red.part0,
                     kind == OP_SLOT && march.nb ? march.nb : nb, red.part1, split ? v.rp : (TP *)nullptr);
             LAUNCH1(K_PCG_UPDATE, 8.0 * nb, (k_pcg_fin_rr), kBlock, st, sc, (const double *)red.part1, nb);
-            precond_d<TP, TP, DIM>(SP, kind, rpre, v.z, v.w, done, st);
-            LAUNCHR(K_PCG_DOT, (W + WP) * N, (k_pcg_rz<T, TP>), N, st, N, (const T *)v.r, (const TP *)v.z,
-                    (const Scal *)sc, red.rz0, red.rz1, red.rz2, singular);
+            precond_rz();
         }
         launched += chunk;
         hipError_t e = hipMemcpyAsync(&hs, sc, sizeof(Scal), hipMemcpyDeviceToHost, st);
