@@ -135,7 +135,8 @@ KERNEL_CLASSES = {
     "t_small_levels": ("k_t_vcycle_small_lds", "k_t_vcycle_small"),
     "t_sweep": ("k_t_sweep", "k_t_restrict"),
     "t_phase": ("k_t_phase",),
-    "ch_spectral": ("k_axis_mfma64", "k_axis_gemm", "k_axis_gemm16s", "k_spectral_scale_batch", "k_spectral_scale"),
+    "ch_spectral": ("k_axis_mfma64", "k_axis_gemm", "k_axis_gemm16s", "k_spectral_scale_batch", "k_spectral_scale",
+                    "k_axis_fft"),
 }
 
 # Which dispatches of a profiled bench.py run belong to a workload: the

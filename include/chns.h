@@ -35,8 +35,9 @@
  * most 2048 cells it is solved directly (the 1D second difference of each
  * axis is diagonalised by an orthonormal DCT-II basis on a walled axis and
  * the real Fourier basis on a periodic one; the solve is one transform per
- * axis, a division by 1 - a lam + b lam^2, and the inverse transforms, as
- * FP64 matrix products by a tiled kernel on the grid's stream).
+ * axis, a division by 1 - a lam + b lam^2, and the inverse transforms, in
+ * FP64 on the grid's stream: a radix-2 FFT along periodic axes of 16 .. 512
+ * cells (a power of two), a product with the dense basis along the others).
  * chns_set_option(g, CHNS_OPT_CH_SOLVER, CHNS_CH_PCG) selects
  * multigrid-preconditioned CG for S2 instead; larger grids and 3D batches
  * always use it.
@@ -486,9 +487,11 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
 
 /* Per-handle options (host state; take effect from the next call):
  *   CHNS_OPT_CH_SOLVER          CHNS_CH_DIRECT (default where every axis has
- *                               at most 2048 cells: the direct S2 solve) or
- *                               CHNS_CH_PCG (multigrid-preconditioned CG);
- *                               CHNS_EINVAL for DIRECT on larger grids;
+ *                               at most 2048 cells: the direct S2 solve),
+ *                               CHNS_CH_DIRECT_DENSE (the direct solve with
+ *                               the dense basis product on every axis, no
+ *                               FFT) or CHNS_CH_PCG (multigrid-preconditioned
+ *                               CG); CHNS_EINVAL for DIRECT on larger grids;
  *   CHNS_OPT_SERIAL_COMPONENTS  1: the momentum components of S7 and the S8
  *                               set-up run one after another on the grid's
  *                               stream (kernel profiles without overlap);
@@ -540,7 +543,7 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  * and the energy monitor cover the split step only.                        */
 enum { CHNS_OPT_CH_SOLVER = 1, CHNS_OPT_SERIAL_COMPONENTS = 2, CHNS_OPT_TIME_SCHEME = 3,
        CHNS_OPT_PICARD_ITERATIONS = 4, CHNS_OPT_MARCH_SWEEP_CELLS = 5, CHNS_OPT_TILE_CYCLE_CELLS = 6 };
-enum { CHNS_CH_DIRECT = 0, CHNS_CH_PCG = 1 };
+enum { CHNS_CH_DIRECT = 0, CHNS_CH_PCG = 1, CHNS_CH_DIRECT_DENSE = 2 };
 enum { CHNS_SCHEME_SPLIT = 0, CHNS_SCHEME_CN = 1 };
 int chns_set_option(struct chns_grid *g, int option, int value);
 

@@ -26,7 +26,7 @@ CHNS_FP64, CHNS_FP32_REFINE = 0, 1
 CHNS_OPT_CH_SOLVER, CHNS_OPT_SERIAL_COMPONENTS, CHNS_OPT_TIME_SCHEME, CHNS_OPT_PICARD_ITERATIONS = 1, 2, 3, 4
 CHNS_OPT_MARCH_SWEEP_CELLS = 5
 CHNS_OPT_TILE_CYCLE_CELLS = 6
-CHNS_CH_DIRECT, CHNS_CH_PCG = 0, 1
+CHNS_CH_DIRECT, CHNS_CH_PCG, CHNS_CH_DIRECT_DENSE = 0, 1, 2
 CHNS_SCHEME_SPLIT, CHNS_SCHEME_CN = 0, 1
 
 
@@ -434,7 +434,8 @@ class Grid:
 
     # -- options ---------------------------------------------------------------
     def set_option(self, option: int, value: int) -> None:
-        """chns_set_option: CHNS_OPT_CH_SOLVER (CHNS_CH_DIRECT / CHNS_CH_PCG),
+        """chns_set_option: CHNS_OPT_CH_SOLVER (CHNS_CH_DIRECT / CHNS_CH_PCG /
+        CHNS_CH_DIRECT_DENSE),
         CHNS_OPT_SERIAL_COMPONENTS (0 / 1), CHNS_OPT_TIME_SCHEME
         (CHNS_SCHEME_SPLIT / CHNS_SCHEME_CN), CHNS_OPT_PICARD_ITERATIONS (>= 1),
         CHNS_OPT_MARCH_SWEEP_CELLS (>= 1), CHNS_OPT_TILE_CYCLE_CELLS (>= 0)."""

@@ -1323,13 +1323,15 @@ int chns_set_option(chns_grid *g, int option, int value) {
                 if (g->spec.on) spectral_release(g->spec);
                 return CHNS_OK;
             }
-            if (value != CHNS_CH_DIRECT) return fail(CHNS_EINVAL, "CH solver must be CHNS_CH_DIRECT or CHNS_CH_PCG");
+            if (value != CHNS_CH_DIRECT && value != CHNS_CH_DIRECT_DENSE)
+                return fail(CHNS_EINVAL, "CH solver must be CHNS_CH_DIRECT, CHNS_CH_DIRECT_DENSE or CHNS_CH_PCG");
             if (!g->spec.carved) return fail(CHNS_EINVAL, "the direct CH solve needs every axis <= 2048 cells");
             if (!g->spec.on) {
                 std::string err;
                 HIPCHK(hipStreamSynchronize(g->stream));
                 if (spectral_init(g->spec, g->h, err)) return fail(CHNS_EDEVICE, err);
             }
+            g->spec.dense = value == CHNS_CH_DIRECT_DENSE;
             return CHNS_OK;
         case CHNS_OPT_TIME_SCHEME:
             if (value != CHNS_SCHEME_SPLIT && value != CHNS_SCHEME_CN)

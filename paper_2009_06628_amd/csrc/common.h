@@ -333,12 +333,19 @@ struct TernConst {
 
 // Bases of the direct Cahn-Hilliard solve (spectral.h, spectral.hip).
 constexpr int kSpectralMaxN = 2048;   // larger axes keep the MG-PCG solve
+// Periodic axes of 2^kFftMinLog .. 2^kFftMaxLog cells are transformed by a
+// radix-2 FFT instead of the product with the dense basis.
+constexpr int kFftMinLog = 4, kFftMaxLog = 9;
+
 struct Spectral {
     int carved;        // bases carved from the workspace (every axis <= kSpectralMaxN)
     int on;            // set up and in use (else the CH system is solved by MG-PCG)
+    int dense;         // 1: dense transforms on every axis (no FFT)
     int dim, n[3], per[3];
+    int fft[3];        // per axis: log2 n when the FFT can transform it, else 0
     double *Q[3];      // per axis: n x n basis, column-major, column k = mode k
     double *lam[3];    // per axis: eigenvalue of each mode (1/h^2 included)
+    double *tw[3];     // FFT axes: cos, sin of 2 pi k / n, k < n (interleaved)
 };
 }  // namespace chns
 

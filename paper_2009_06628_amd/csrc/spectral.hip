@@ -8,20 +8,31 @@
 
 namespace chns {
 
+// log2 n for a periodic axis the FFT can transform, else 0
+static int fft_log(int n, int per) {
+    if (!per || (n & (n - 1)) != 0) return 0;
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l >= kFftMinLog && l <= kFftMaxLog ? l : 0;
+}
+
 void spectral_carve(Bump &B, const Geo &g, int dim, Spectral &S) {
     S.carved = 1;
     S.on = 0;
+    S.dense = 0;
     S.dim = dim;
     for (int a = 0; a < 3; ++a) {
         S.n[a] = a < dim ? (int)g.n[a] : 1;
         S.per[a] = a < dim ? g.per[a] : 1;
-        S.Q[a] = S.lam[a] = nullptr;
+        S.fft[a] = a < dim ? fft_log(S.n[a], S.per[a]) : 0;
+        S.Q[a] = S.lam[a] = S.tw[a] = nullptr;
         if (a < dim && g.n[a] > kSpectralMaxN) S.carved = 0;
     }
     if (!S.carved) return;
     for (int a = 0; a < dim; ++a) {
         S.Q[a] = B.take<double>((size_t)S.n[a] * S.n[a]);
         S.lam[a] = B.take<double>((size_t)S.n[a]);
+        if (S.fft[a]) S.tw[a] = B.take<double>((size_t)2 * S.n[a]);
     }
 }
 
@@ -77,6 +88,21 @@ int spectral_init(Spectral &S, double h, std::string &err) {
         spectral_axis(S.n[a], S.per[a], h, Q, lam);
         hipError_t e = hipMemcpy(S.Q[a], Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(S.lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess && S.fft[a]) {
+            // twiddles cos, sin of 2 pi k / n (angles reduced exactly: the
+            // quadrant symmetry makes e.g. cos(pi / 2) exactly 0)
+            const int n = S.n[a];
+            std::vector<double> tw(2 * (size_t)n);
+            const double pi = std::acos(-1.0);
+            for (int k = 0; k < n; ++k) {
+                const int q = (4 * k) / n, r = 4 * k - q * n;   // angle = (q + r / n) pi / 2
+                const double t = 0.5 * pi * (double)r / n, c = std::cos(t), sn = std::sin(t);
+                const double cs[4] = {c, -sn, -c, sn}, ss[4] = {sn, c, -sn, -c};
+                tw[2 * k] = cs[q];
+                tw[2 * k + 1] = ss[q];
+            }
+            e = hipMemcpy(S.tw[a], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
+        }
         if (e != hipSuccess) {
             err = std::string("spectral basis upload: ") + hipGetErrorString(e);
             return 1;
@@ -436,40 +462,327 @@ __global__ void __launch_bounds__(kBlock) k_spectral_scale(Geo g, const double *
     }
 }
 
+// ---------------------------------------------------------------------------
+// FFT transforms of periodic power-of-two axes.  With the DFT
+// X_k = sum_j x_j e^{-2 pi i k j / n} of a pencil along such an axis
+// (m = n / 2), the coefficients in the real Fourier basis are
+//   mode 0 = X_0 / sqrt(n),  mode 2k-1 = sqrt(2/n) Re X_k,
+//   mode 2k = -sqrt(2/n) Im X_k (0 < k < m),  mode n-1 = X_m / sqrt(n),
+// and back x_j = Re sum_{k <= m} c_k e^{+2 pi i k j / n} with
+// c_0 = mode 0 / sqrt(n), c_k = sqrt(2/n) (mode 2k-1 - i mode 2k),
+// c_m = mode n-1 / sqrt(n): O(log n) operations per value where the basis
+// product takes O(n).  A 256-thread workgroup takes P = 2048 / n pencils into
+// LDS and runs the log2 n radix-2 stages: decimation in time on
+// bit-reversed input for the forward transform, decimation in frequency
+// with bit-reversed output for the inverse.
+// MODE 0: forward; 1: inverse; 2: forward, division by 1 - a lam + b lam^2,
+// inverse (the last axis of the solve, whose pencils carry every mode of the
+// other axes).  Pencil q of an axis: element j at
+// (q / nin) ostride + q % nin + j nb.
+// ---------------------------------------------------------------------------
+struct FftAxis {
+    int nb, nin, npen;
+    long long ostride;
+    const double *tw;   // cos, sin of 2 pi k / n
+};
+struct FftScale {         // MODE 2
+    double a, b;
+    const double *lx, *ly;   // eigenvalues of the other axes (ly null in 2D)
+    const double *lz;        // eigenvalues of this axis' modes
+    int nx;                  // 3D pencil q: (x, y) = (q % nx, q / nx); 2D: x = q
+};
+
+// Radix-2 stages in groups of up to three held in registers: the stages of
+// half-sizes H, 2H, 4H (H = 2^r0) only pair elements within the sets
+// {base + H m : m < 8}, base = hi 8H + lo (lo < H), so a thread loads a set,
+// runs the group's butterflies on it (the twiddle of the pair (m, m + 2^r)
+// at half-size H 2^r is W^(H (m mod 2^r) + lo)) and stores it back: one LDS
+// round trip per three stages (and one twiddle read per stage: the others
+// follow by eighth-turn rotations).  Element j of pencil p sits at
+// p * W + j + j / 8 (one padding word per eight, so that the sets of
+// consecutive threads fall in different LDS banks).
+template <int LOGN>
+struct FftLds {
+    static constexpr int n = 1 << LOGN, P = 2048 / n, W = n + n / 8 + 1;
+    __device__ static int at(int p, int j) { return p * W + j + (j >> 3); }
+};
+
+// DIT (forward, bit-reversed input) or DIF (inverse, bit-reversed output)
+// group of S stages starting at half-size 2^r0; sgn: sign of the exponent.
+template <int LOGN, int S, bool DIT>
+__device__ inline void fft_group(double *re, double *im, const double *tw, double sgn, int r0) {
+    using L = FftLds<LOGN>;
+    constexpr int n = L::n, Z = 1 << S, NS = L::P * n / Z;
+    static_assert(NS % kBlock == 0, "whole sets per thread");
+    const int H = 1 << r0;
+#pragma unroll
+    for (int sg = (int)threadIdx.x; sg < NS; sg += kBlock) {
+        const int p = sg / (n / Z), si = sg % (n / Z), lo = si & (H - 1), hi = si >> r0;
+        const int j0 = hi * Z * H + lo;
+        double xr[Z], xi[Z];
+#pragma unroll
+        for (int m = 0; m < Z; ++m) {
+            xr[m] = re[L::at(p, j0 + H * m)];
+            xi[m] = im[L::at(p, j0 + H * m)];
+        }
+#pragma unroll
+        for (int rr = 0; rr < S; ++rr) {
+            const int r = DIT ? rr : S - 1 - rr, hh = 1 << r, tstep = n / (2 * (H << r));
+            // W^(H m' + lo) = W^lo e^(sgn 2 pi i e / 8) with e = m' 8 / 2^(r+1) < 4
+            const double br = tw[2 * lo * tstep], bi = sgn * tw[2 * lo * tstep + 1];
+#pragma unroll
+            for (int m = 0; m < Z; ++m) {
+                if (m & hh) continue;
+                const int e = (m & (hh - 1)) * (8 >> (r + 1)), mm = m + hh;
+                constexpr double c = 0.70710678118654752440;   // sqrt(1/2)
+                double wr = br, wi = bi;
+                if (e == 1) {
+                    wr = c * (br - sgn * bi);
+                    wi = c * (bi + sgn * br);
+                } else if (e == 2) {
+                    wr = -sgn * bi;
+                    wi = sgn * br;
+                } else if (e == 3) {
+                    wr = -c * (br + sgn * bi);
+                    wi = c * (sgn * br - bi);
+                }
+                if (DIT) {
+                    const double tr = wr * xr[mm] - wi * xi[mm], ti = wr * xi[mm] + wi * xr[mm];
+                    xr[mm] = xr[m] - tr;
+                    xi[mm] = xi[m] - ti;
+                    xr[m] += tr;
+                    xi[m] += ti;
+                } else {
+                    const double dr = xr[m] - xr[mm], di = xi[m] - xi[mm];
+                    xr[m] += xr[mm];
+                    xi[m] += xi[mm];
+                    xr[mm] = wr * dr - wi * di;
+                    xi[mm] = wr * di + wi * dr;
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < Z; ++m) {
+            re[L::at(p, j0 + H * m)] = xr[m];
+            im[L::at(p, j0 + H * m)] = xi[m];
+        }
+    }
+    __syncthreads();
+}
+
+// all log2 n stages: DIT groups from the smallest half-size up, DIF groups
+// from the largest down (three stages per group, the remainder last / first)
+template <int LOGN, bool DIT>
+__device__ inline void fft_run(double *re, double *im, const double *tw, double sgn) {
+    constexpr int G = LOGN / 3, REM = LOGN % 3;
+    if (DIT) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) fft_group<LOGN, 3, true>(re, im, tw, sgn, 3 * g);
+        if (REM) fft_group<LOGN, (REM ? REM : 1), true>(re, im, tw, sgn, 3 * G);
+    } else {
+        if (REM) fft_group<LOGN, (REM ? REM : 1), false>(re, im, tw, sgn, 3 * G);
+#pragma unroll
+        for (int g = G - 1; g >= 0; --g) fft_group<LOGN, 3, false>(re, im, tw, sgn, 3 * g);
+    }
+}
+
+template <int LOGN, int MODE>
+__global__ void __launch_bounds__(kBlock) k_axis_fft(FftAxis ax, const double *__restrict__ in,
+                                                     double *__restrict__ out, FftScale sc) {
+    using L = FftLds<LOGN>;
+    constexpr int n = L::n, m = n / 2, P = L::P;
+    __shared__ double re[P * L::W], im[P * L::W], tws[2 * n];
+    __shared__ long long base[P];
+    const int tid = (int)threadIdx.x, q0 = (int)blockIdx.x * P;
+    const double s0 = 1.0 / sqrt((double)n), s1 = sqrt(2.0 / (double)n);
+    for (int i = tid; i < 2 * n; i += kBlock) tws[i] = ax.tw[i];
+    if (tid < P) {
+        const int q = q0 + tid;
+        base[tid] = (long long)(q / ax.nin) * ax.ostride + q % ax.nin;
+    }
+    __syncthreads();
+    auto at = [&](int p, int j) { return base[p] + (long long)j * ax.nb; };
+    // element e of the workgroup's pencils: the index contiguous in memory
+    // runs fastest across the threads
+    auto split = [&](int e, int &p, int &j) {
+        if (ax.nb == 1) {
+            p = e / n;
+            j = e % n;
+        } else {
+            j = e / P;
+            p = e % P;
+        }
+    };
+    auto brev = [](int j) { return (int)(__brev((unsigned)j) >> (32 - LOGN)); };
+    for (int e = tid; e < P * n; e += kBlock) {
+        int p, j;
+        split(e, p, j);
+        const bool ok = q0 + p < ax.npen;
+        double vr = 0.0, vi = 0.0;
+        if (MODE != 1) {
+            if (ok) vr = in[at(p, j)];
+            re[L::at(p, brev(j))] = vr;
+            im[L::at(p, brev(j))] = 0.0;
+        } else {
+            if (ok && j <= m) {   // j is the frequency k
+                if (j == 0) {
+                    vr = s0 * in[at(p, 0)];
+                } else if (j == m) {
+                    vr = s0 * in[at(p, n - 1)];
+                } else {
+                    vr = s1 * in[at(p, 2 * j - 1)];
+                    vi = -s1 * in[at(p, 2 * j)];
+                }
+            }
+            re[L::at(p, j)] = vr;
+            im[L::at(p, j)] = vi;
+        }
+    }
+    __syncthreads();
+    if (MODE != 1) fft_run<LOGN, true>(re, im, tws, -1.0);
+    if (MODE == 0) {
+        for (int e = tid; e < P * n; e += kBlock) {
+            int p, c;
+            split(e, p, c);
+            if (q0 + p >= ax.npen) continue;
+            const int k = c == n - 1 ? m : (c + 1) / 2;
+            const double v = c == 0 || c == n - 1 ? s0 * re[L::at(p, k)]
+                                                  : ((c & 1) ? s1 * re[L::at(p, k)] : -s1 * im[L::at(p, k)]);
+            out[at(p, c)] = v;
+        }
+        return;
+    }
+    if (MODE == 2) {
+        // c_k = f_k X_k / (1 - a lam + b lam^2), f = 1 / n at k = 0, m, else 2 / n
+        const double inv_n = 1.0 / (double)n;
+        for (int e = tid; e < P * n; e += kBlock) {
+            const int p = e / n, k = e % n, q = q0 + p;
+            double f = 0.0;
+            if (k <= m && q < ax.npen) {
+                const double lxy = sc.ly ? sc.lx[q % sc.nx] + sc.ly[q / sc.nx] : sc.lx[q];
+                const double lam = lxy + sc.lz[k == 0 ? 0 : (k == m ? n - 1 : 2 * k - 1)];
+                f = (k == 0 || k == m ? inv_n : 2.0 * inv_n) / (1.0 - sc.a * lam + sc.b * lam * lam);
+            }
+            re[L::at(p, k)] *= f;
+            im[L::at(p, k)] *= f;
+        }
+        __syncthreads();
+    }
+    fft_run<LOGN, false>(re, im, tws, 1.0);
+    for (int e = tid; e < P * n; e += kBlock) {
+        int p, j;
+        split(e, p, j);
+        if (q0 + p < ax.npen) out[at(p, j)] = re[L::at(p, brev(j))];
+    }
+}
+
+// Pencils of axis a of the grid n[0..2] (x fastest).
+static FftAxis fft_axis_of(const Spectral &S, int a) {
+    const int nx = S.n[0], ny = S.n[1], nz = S.dim == 3 ? S.n[2] : 1;
+    FftAxis ax;
+    ax.tw = S.tw[a];
+    if (a == 0) {
+        ax.nb = 1;
+        ax.nin = 1;
+        ax.ostride = nx;
+        ax.npen = ny * nz;
+    } else if (a == 1) {
+        ax.nb = nx;
+        ax.nin = nx;
+        ax.ostride = (long long)nx * ny;
+        ax.npen = nx * nz;
+    } else {
+        ax.nb = nx * ny;
+        ax.nin = nx * ny;
+        ax.ostride = 0;
+        ax.npen = nx * ny;
+    }
+    return ax;
+}
+
+template <int LOGN>
+static void fft_launch(const FftAxis &ax, int mode, const double *in, double *out, const FftScale &sc,
+                       hipStream_t st) {
+    constexpr int P = 2048 >> LOGN;
+    const dim3 grid((ax.npen + P - 1) / P);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_axis_fft<LOGN, 0>), grid, dim3(kBlock), 0, st, ax, in, out, sc);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_axis_fft<LOGN, 1>), grid, dim3(kBlock), 0, st, ax, in, out, sc);
+    else
+        hipLaunchKernelGGL((k_axis_fft<LOGN, 2>), grid, dim3(kBlock), 0, st, ax, in, out, sc);
+}
+
+static void fft_transform(const Spectral &S, int a, int mode, const double *in, double *out, const FftScale &sc,
+                          hipStream_t st) {
+    const FftAxis ax = fft_axis_of(S, a);
+    switch (S.fft[a]) {
+        case 4: fft_launch<4>(ax, mode, in, out, sc, st); break;
+        case 5: fft_launch<5>(ax, mode, in, out, sc, st); break;
+        case 6: fft_launch<6>(ax, mode, in, out, sc, st); break;
+        case 7: fft_launch<7>(ax, mode, in, out, sc, st); break;
+        case 8: fft_launch<8>(ax, mode, in, out, sc, st); break;
+        default: fft_launch<9>(ax, mode, in, out, sc, st); break;
+    }
+}
+static_assert(kFftMinLog == 4 && kFftMaxLog == 9, "fft_transform instantiates 2^4 .. 2^9");
+
 hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, double *x, double *t0, double *t1,
                           hipStream_t st, std::string &err) {
     (void)err;
-    const int nx = S.n[0], ny = S.n[1], nz = S.dim == 3 ? S.n[2] : 1;
+    const int nx = S.n[0], ny = S.n[1], nz = S.dim == 3 ? S.n[2] : 1, last = S.dim - 1;
+    auto fft_on = [&](int ax) { return !S.dense && S.fft[ax] != 0; };
+    const bool fused = fft_on(last);   // forward, division and inverse along the last axis in one pass
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_prof) {
         const double N3 = (double)nx * ny * nz;
-        prof_slot(K_CH_SPECTRAL, 8.0 * N3 * 2.0 * (2 * S.dim + 1), &e0, &e1);
+        prof_slot(K_CH_SPECTRAL, 8.0 * N3 * 2.0 * (fused ? 2 * S.dim - 1 : 2 * S.dim + 1), &e0, &e1);
         (void)hipEventRecord(e0, st);
     }
-    // forward: x (rows), y (z slabs), z
-    axis_transform(S.Q[0], nx, 1, ny * nz, true, r, nullptr, t0, nullptr, 0, st);
-    axis_transform(S.Q[1], ny, nx, nz, true, t0, nullptr, t1, nullptr, 0, st);
-    double *cur = t1, *oth = t0;
-    if (S.dim == 3) {
-        axis_transform(S.Q[2], nz, nx * ny, 1, true, cur, nullptr, oth, nullptr, 0, st);
+    const FftScale none{0.0, 0.0, nullptr, nullptr, nullptr, 1};
+    auto transform = [&](int ax, bool fwd, const double *in, double *out) {
+        if (fft_on(ax)) {
+            fft_transform(S, ax, fwd ? 0 : 1, in, out, none, st);
+        } else if (ax == 0) {
+            axis_transform(S.Q[0], nx, 1, ny * nz, fwd, in, nullptr, out, nullptr, 0, st);
+        } else if (ax == 1) {
+            axis_transform(S.Q[1], ny, nx, nz, fwd, in, nullptr, out, nullptr, 0, st);
+        } else {
+            axis_transform(S.Q[2], nz, nx * ny, 1, fwd, in, nullptr, out, nullptr, 0, st);
+        }
+    };
+    // forward: x, then y (3D), into t0 / t1
+    transform(0, true, r, t0);
+    double *cur = t0, *oth = t1;
+    for (int ax = 1; ax < last; ++ax) {
+        transform(ax, true, cur, oth);
         std::swap(cur, oth);
     }
-    Geo g;
-    g.n[0] = nx;
-    g.n[1] = ny;
-    g.n[2] = nz;
-    g.per[0] = g.per[1] = g.per[2] = 1;
-    g.N = (long long)nx * ny * nz;
-    hipLaunchKernelGGL(k_spectral_scale, dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, (const double *)S.lam[0],
-                       (const double *)S.lam[1], (const double *)(S.dim == 3 ? S.lam[2] : nullptr), a, b, cur);
-    // inverse: z, y, x
-    if (S.dim == 3) {
-        axis_transform(S.Q[2], nz, nx * ny, 1, false, cur, nullptr, oth, nullptr, 0, st);
+    if (fused) {
+        const FftScale sc{a, b, (const double *)S.lam[0], S.dim == 3 ? (const double *)S.lam[1] : nullptr,
+                          (const double *)S.lam[last], nx};
+        fft_transform(S, last, 2, cur, oth, sc, st);
+        std::swap(cur, oth);
+    } else {
+        transform(last, true, cur, oth);
+        std::swap(cur, oth);
+        Geo g;
+        g.n[0] = nx;
+        g.n[1] = ny;
+        g.n[2] = nz;
+        g.per[0] = g.per[1] = g.per[2] = 1;
+        g.N = (long long)nx * ny * nz;
+        hipLaunchKernelGGL(k_spectral_scale, dim3(grid_for(g.N)), dim3(kBlock), 0, st, g, (const double *)S.lam[0],
+                           (const double *)S.lam[1], (const double *)(S.dim == 3 ? S.lam[2] : nullptr), a, b, cur);
+        transform(last, false, cur, oth);
         std::swap(cur, oth);
     }
-    axis_transform(S.Q[1], ny, nx, nz, false, cur, nullptr, oth, nullptr, 0, st);
-    std::swap(cur, oth);
-    axis_transform(S.Q[0], nx, 1, ny * nz, false, cur, nullptr, x, nullptr, 0, st);
+    // inverse: y (3D), then x into the result
+    for (int ax = last - 1; ax >= 1; --ax) {
+        transform(ax, false, cur, oth);
+        std::swap(cur, oth);
+    }
+    transform(0, false, cur, x);
     if (e1) (void)hipEventRecord(e1, st);
     return hipGetLastError();
 }

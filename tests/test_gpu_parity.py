@@ -365,6 +365,51 @@ def test_ch_direct_solve_matches_mg_pcg(case):
     assert relerr(pa - pa.mean(), pb - pb.mean()) < 1e-8
 
 
+def _fft_case(case):
+    drops = {"seed": 5, "count": 2, "rmin": 0.04, "rmax": 0.06, "gap": 0.05, "velocity": "stream",
+             "vseed": 9, "vamp": 0.05}
+    return {"drops3d_32": lambda: W.drops3d(32, steps=4),
+            "ternary_64x32x16": lambda: W.ternary_problem((64, 32, 16), "ternary_drops",
+                                                          dict(drops, velocity="potential3d"), steps=4),
+            "ternary_32x32x24": lambda: W.ternary_problem((32, 32, 24), "ternary_drops",
+                                                          dict(drops, velocity="potential3d"), steps=4),
+            "bubble2d_64": lambda: W.rising_bubble(64, steps=4),
+            "spinodal2d_128": lambda: W.spinodal(128, steps=4)}[case]()
+
+
+@pytest.mark.parametrize("case", ["drops3d_32", "ternary_64x32x16", "ternary_32x32x24", "bubble2d_64",
+                                  "spinodal2d_128"])
+def test_ch_fft_matches_dense_basis(case):
+    """The direct CH solve transforms periodic power-of-two axes by radix-2
+    FFT (the last axis with the division fused in, when it is one of them)
+    and every other axis by the product with the dense basis; forcing the
+    dense product on every axis (CHNS_CH_DIRECT_DENSE) must give the same
+    states to rounding after four steps.  Cases: every axis FFT (32^3; 64 x
+    32 x 16 with 16 on the fused axis; 2D 128^2), a non-power-of-two last
+    axis (32 x 32 x 24: FFT on x, y, dense z and the separate division), a
+    walled axis (bubble: FFT x, dense y)."""
+    P = _lib()
+    prob = _fft_case(case)
+    init = W.initial_state(prob)
+    out = []
+    for solver in (P.CHNS_CH_DIRECT, P.CHNS_CH_DIRECT_DENSE):
+        g = P.grid_for_problem(prob)
+        g.set_option(P.CHNS_OPT_CH_SOLVER, solver)
+        st = g.new_state(init)
+        stats = g.step(st, 4)
+        print("CH transform", case, solver, stats["iters_ch"], flush=True)
+        out.append(st)
+    a, b = out
+    phis = a["phi"] if isinstance(a["phi"], (list, tuple)) else [a["phi"]]
+    phib = b["phi"] if isinstance(b["phi"], (list, tuple)) else [b["phi"]]
+    for x, y in zip(phis, phib):
+        assert relerr(to_np(x), to_np(y)) < 1e-11
+    for d in range(len(a["u"])):
+        assert relerr(to_np(a["u"][d]), to_np(b["u"][d])) < 1e-10, d
+    pa, pb = to_np(a["p"]), to_np(b["p"])
+    assert relerr(pa - pa.mean(), pb - pb.mean()) < 1e-10
+
+
 @pytest.mark.parametrize("case", ["bubble2d", "drops3d"])
 def test_concurrent_momentum_matches_serial_bitwise(case):
     """The momentum components run on their own streams and host threads; with
