@@ -466,7 +466,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
         // residual of the previous iteration, stored before q is overwritten
         if (rpend) rpend[c] = (T)cg_residual((double)rpend[c], (double)q[c], alpha_prev);
         const double pc = pv(c);
-        double qc = (double)L.s[c] * pc;
+        // a singular (pressure) operator has s = +0: not read
+        double sv = 0.0;
+        if (!singular) sv = (double)L.s[c];
+        double qc = sv * pc;
 #pragma unroll
         for (int b = 0; b < DIM; ++b) {   // branch-free: a missing neighbour is c itself with weight 0
             const int lo = nb_lo(L.g, c, ia[b], b);
@@ -584,7 +587,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply3_march(Level<T> L, const T
                 nbr[2][0] = Rm[li];
                 nbr[2][1] = Rp[li];
             }
-            double qc = RHO ? 0.0 * pc : (double)L.s[c] * pc;
+            // s = +0 on a singular (pressure) operator: not read
+            double sv = 0.0;
+            if (!RHO && !singular) sv = (double)L.s[c];
+            double qc = sv * pc;
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const int lo = nb_lo(g, c, ia[b], b);

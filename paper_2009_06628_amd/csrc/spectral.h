@@ -47,5 +47,11 @@ void spectral_release(Spectral &S);
 // Returns hipSuccess or the launch error.
 hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, double *x, double *t0, double *t1,
                           hipStream_t st, std::string &err);
+// Whether every axis is transformed by FFT (then spectral_solve2 applies).
+bool spectral_all_fft(const Spectral &S);
+// The same for two right-hand sides, both in every launch (every axis an
+// FFT axis); t0[i], t1[i]: scratch of N doubles per field.
+hipError_t spectral_solve2(Spectral &S, double a, double b, const double *const r[2], double *const x[2],
+                           double *const t0[2], double *const t1[2], hipStream_t st);
 
 }  // namespace chns

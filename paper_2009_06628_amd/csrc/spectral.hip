@@ -586,9 +586,16 @@ __device__ inline void fft_run(double *re, double *im, const double *tw, double 
     }
 }
 
+// the fields of one launch (blockIdx.y): up to two solves with the same operator
+struct FftIo {
+    const double *in[2];
+    double *out[2];
+};
+
 template <int LOGN, int MODE>
-__global__ void __launch_bounds__(kBlock) k_axis_fft(FftAxis ax, const double *__restrict__ in,
-                                                     double *__restrict__ out, FftScale sc) {
+__global__ void __launch_bounds__(kBlock) k_axis_fft(FftAxis ax, FftIo io, FftScale sc) {
+    const double *__restrict__ in = io.in[blockIdx.y];
+    double *__restrict__ out = io.out[blockIdx.y];
     using L = FftLds<LOGN>;
     constexpr int n = L::n, m = n / 2, P = L::P;
     __shared__ double re[P * L::W], im[P * L::W], tws[2 * n];
@@ -701,29 +708,66 @@ static FftAxis fft_axis_of(const Spectral &S, int a) {
 }
 
 template <int LOGN>
-static void fft_launch(const FftAxis &ax, int mode, const double *in, double *out, const FftScale &sc,
-                       hipStream_t st) {
+static void fft_launch(const FftAxis &ax, int mode, const FftIo &io, int nf, const FftScale &sc, hipStream_t st) {
     constexpr int P = 2048 >> LOGN;
-    const dim3 grid((ax.npen + P - 1) / P);
+    const dim3 grid((ax.npen + P - 1) / P, nf);
     if (mode == 0)
-        hipLaunchKernelGGL((k_axis_fft<LOGN, 0>), grid, dim3(kBlock), 0, st, ax, in, out, sc);
+        hipLaunchKernelGGL((k_axis_fft<LOGN, 0>), grid, dim3(kBlock), 0, st, ax, io, sc);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_axis_fft<LOGN, 1>), grid, dim3(kBlock), 0, st, ax, in, out, sc);
+        hipLaunchKernelGGL((k_axis_fft<LOGN, 1>), grid, dim3(kBlock), 0, st, ax, io, sc);
     else
-        hipLaunchKernelGGL((k_axis_fft<LOGN, 2>), grid, dim3(kBlock), 0, st, ax, in, out, sc);
+        hipLaunchKernelGGL((k_axis_fft<LOGN, 2>), grid, dim3(kBlock), 0, st, ax, io, sc);
 }
 
-static void fft_transform(const Spectral &S, int a, int mode, const double *in, double *out, const FftScale &sc,
+// transform along axis a of nf fields (io.in / io.out [0, nf))
+static void fft_transform(const Spectral &S, int a, int mode, const FftIo &io, int nf, const FftScale &sc,
                           hipStream_t st) {
     const FftAxis ax = fft_axis_of(S, a);
     switch (S.fft[a]) {
-        case 4: fft_launch<4>(ax, mode, in, out, sc, st); break;
-        case 5: fft_launch<5>(ax, mode, in, out, sc, st); break;
-        case 6: fft_launch<6>(ax, mode, in, out, sc, st); break;
-        case 7: fft_launch<7>(ax, mode, in, out, sc, st); break;
-        case 8: fft_launch<8>(ax, mode, in, out, sc, st); break;
-        default: fft_launch<9>(ax, mode, in, out, sc, st); break;
+        case 4: fft_launch<4>(ax, mode, io, nf, sc, st); break;
+        case 5: fft_launch<5>(ax, mode, io, nf, sc, st); break;
+        case 6: fft_launch<6>(ax, mode, io, nf, sc, st); break;
+        case 7: fft_launch<7>(ax, mode, io, nf, sc, st); break;
+        case 8: fft_launch<8>(ax, mode, io, nf, sc, st); break;
+        default: fft_launch<9>(ax, mode, io, nf, sc, st); break;
     }
+}
+
+bool spectral_all_fft(const Spectral &S) {
+    if (!S.on || S.dense) return false;
+    for (int a = 0; a < S.dim; ++a)
+        if (!S.fft[a]) return false;
+    return true;
+}
+
+// Both fields in every launch: every axis is an FFT axis.
+hipError_t spectral_solve2(Spectral &S, double a, double b, const double *const r[2], double *const x[2],
+                           double *const t0[2], double *const t1[2], hipStream_t st) {
+    const int nx = S.n[0], ny = S.n[1], nz = S.dim == 3 ? S.n[2] : 1, last = S.dim - 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_prof) {
+        prof_slot(K_CH_SPECTRAL, 2.0 * 8.0 * nx * ny * nz * 2.0 * (2 * S.dim - 1), &e0, &e1);
+        (void)hipEventRecord(e0, st);
+    }
+    const FftScale none{0.0, 0.0, nullptr, nullptr, nullptr, 1};
+    FftIo io{{r[0], r[1]}, {t0[0], t0[1]}};
+    fft_transform(S, 0, 0, io, 2, none, st);
+    double *cur[2] = {t0[0], t0[1]}, *oth[2] = {t1[0], t1[1]};
+    auto step = [&](int ax, int mode, const FftScale &sc) {
+        const FftIo f{{cur[0], cur[1]}, {oth[0], oth[1]}};
+        fft_transform(S, ax, mode, f, 2, sc, st);
+        std::swap(cur[0], oth[0]);
+        std::swap(cur[1], oth[1]);
+    };
+    for (int ax = 1; ax < last; ++ax) step(ax, 0, none);
+    const FftScale sc{a, b, (const double *)S.lam[0], S.dim == 3 ? (const double *)S.lam[1] : nullptr,
+                      (const double *)S.lam[last], nx};
+    step(last, 2, sc);
+    for (int ax = last - 1; ax >= 1; --ax) step(ax, 1, none);
+    const FftIo fin{{cur[0], cur[1]}, {x[0], x[1]}};
+    fft_transform(S, 0, 1, fin, 2, none, st);
+    if (e1) (void)hipEventRecord(e1, st);
+    return hipGetLastError();
 }
 static_assert(kFftMinLog == 4 && kFftMaxLog == 9, "fft_transform instantiates 2^4 .. 2^9");
 
@@ -742,7 +786,7 @@ hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, doub
     const FftScale none{0.0, 0.0, nullptr, nullptr, nullptr, 1};
     auto transform = [&](int ax, bool fwd, const double *in, double *out) {
         if (fft_on(ax)) {
-            fft_transform(S, ax, fwd ? 0 : 1, in, out, none, st);
+            fft_transform(S, ax, fwd ? 0 : 1, FftIo{{in, in}, {out, out}}, 1, none, st);
         } else if (ax == 0) {
             axis_transform(S.Q[0], nx, 1, ny * nz, fwd, in, nullptr, out, nullptr, 0, st);
         } else if (ax == 1) {
@@ -761,7 +805,7 @@ hipError_t spectral_solve(Spectral &S, double a, double b, const double *r, doub
     if (fused) {
         const FftScale sc{a, b, (const double *)S.lam[0], S.dim == 3 ? (const double *)S.lam[1] : nullptr,
                           (const double *)S.lam[last], nx};
-        fft_transform(S, last, 2, cur, oth, sc, st);
+        fft_transform(S, last, 2, FftIo{{cur, cur}, {oth, oth}}, 1, sc, st);
         std::swap(cur, oth);
     } else {
         transform(last, true, cur, oth);
