@@ -302,7 +302,7 @@ static void hierarchy_setup(chns_grid *g, const SolveCtx &c) {
         mg_setup(*c.S64, g->dim, c.s);
     } else {
         convert_level0(*c.S64, *c.S32, g->dim, c.s);
-        mg_setup(*c.S32, g->dim, c.s);
+        mg_setup(*c.S32, g->dim, c.s, false);
     }
 }
 
@@ -863,7 +863,7 @@ int chns_set_properties(chns_grid *g, const chns_props *p) {
     mg_setup(g->ch, g->dim, g->stream);
     if (g->prec == CHNS_FP32_REFINE) {
         convert_level0(g->ch, g->ch32, g->dim, g->stream);
-        mg_setup(g->ch32, g->dim, g->stream);
+        mg_setup(g->ch32, g->dim, g->stream, false);
     }
     HIPCHK(hipGetLastError());
     return CHNS_OK;

@@ -1294,11 +1294,13 @@ __global__ void __launch_bounds__(kBlock) k_gs_red_rz(Level<T> L, const TB *__re
     }
 }
 
-// r = b - A x (slot operator); partials of b.b and r.r
-template <typename T, int DIM>
+// r = b - A x (slot operator); partials of b.b and r.r; rp (when given):
+// r rounded to the preconditioner's precision
+template <typename T, int DIM, typename TP = T>
 __global__ void __launch_bounds__(kBlock) k_pcg_init_slot(Level<T> L, const T *__restrict__ b,
                                                           const T *__restrict__ x, T *__restrict__ r,
-                                                          double *__restrict__ p0, double *__restrict__ p1) {
+                                                          double *__restrict__ p0, double *__restrict__ p1,
+                                                          TP *__restrict__ rp) {
     __shared__ double lds[kBlock / kWave];
     double bb = 0.0, rr = 0.0;
     GRID_LOOP(L.g.N) {
@@ -1307,6 +1309,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init_slot(Level<T> L, const T *_
         const double bc = (double)b[c];
         const double rc = bc - apply_at<T, DIM>(L, x, c, ia);
         r[c] = (T)rc;
+        if (rp) rp[c] = (TP)(T)rc;   // the preconditioner's copy (k_round_vec's value)
         bb += bc * bc;
         rr += rc * rc;
     }
@@ -1456,12 +1459,13 @@ static int trunc_level(const Slot<T> &S, int dim) {
 }
 
 template <typename T, int DIM>
-static void mg_setup_d(Slot<T> &S, hipStream_t st) {
+static void mg_setup_d(Slot<T> &S, hipStream_t st, bool invd0) {
     constexpr double W = sizeof(T);
     S.lsb = single_block_level(S);
     const int lsb = S.lsb;
     const int lt = trunc_level(S, DIM);
-    if (lsb > 0) LAUNCH(K_MG_SETUP, W * (2 + DIM) * S.lev[0].g.N, (k_invd<T, DIM>), S.lev[0].g.N, st, S.lev[0]);
+    if (lsb > 0 && invd0)
+        LAUNCH(K_MG_SETUP, W * (2 + DIM) * S.lev[0].g.N, (k_invd<T, DIM>), S.lev[0].g.N, st, S.lev[0]);
     for (int l = 1; l < (lt >= 0 ? lt + 1 : lsb); ++l) {
         LAUNCH(K_MG_SETUP, W * (1 + DIM) * (S.lev[l - 1].g.N + S.lev[l].g.N), (k_coarsen<T, DIM>), S.lev[l].g.N, st,
                S.lev[l - 1], S.lev[l]);
@@ -1475,11 +1479,11 @@ static void mg_setup_d(Slot<T> &S, hipStream_t st) {
 }
 
 template <typename T>
-void mg_setup(Slot<T> &S, int dim, hipStream_t st) {
+void mg_setup(Slot<T> &S, int dim, hipStream_t st, bool invd0) {
     if (dim == 2)
-        mg_setup_d<T, 2>(S, st);
+        mg_setup_d<T, 2>(S, st, invd0);
     else
-        mg_setup_d<T, 3>(S, st);
+        mg_setup_d<T, 3>(S, st, invd0);
 }
 
 // 2D tile grid of a level: tiles along x, rounded up to whole XCD groups
@@ -1772,8 +1776,9 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
     if (zero_guess) {
         LAUNCHR(K_PCG_INIT, W * 3 * N, (k_pcg_init_zero<T>), N, st, N, b, x, v.r, red.part0, red.part1);
     } else if (kind == OP_SLOT) {
-        LAUNCHR(K_PCG_INIT, W * (4 + DIM) * N, (k_pcg_init_slot<T, DIM>), N, st, L0, b, (const T *)x, v.r, red.part0,
-               red.part1);
+        constexpr bool split = !std::is_same<T, TP>::value;
+        LAUNCHR(K_PCG_INIT, W * (4 + DIM) * N + (split ? WP * N : 0.0), (k_pcg_init_slot<T, DIM, TP>), N, st, L0, b,
+                (const T *)x, v.r, red.part0, red.part1, split ? (TP *)v.rp : (TP *)nullptr);
     } else {
         LAUNCH(K_PCG_INIT, W * 2 * N, (k_ch_lap_plain<T, DIM>), N, st, g, ch.ih2, (const T *)x, v.t);
         LAUNCHR(K_PCG_INIT, W * 4 * N, (k_pcg_init_ch<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, b, (const T *)x,
@@ -1787,7 +1792,8 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
     // to), so the level-0 passes read 4 instead of 8 bytes per cell of it.
     constexpr bool split = !std::is_same<T, TP>::value;
     const TP *rpre = split ? (const TP *)v.rp : (const TP *)(const void *)v.r;
-    if (split) LAUNCH(K_PCG_INIT, (W + WP) * N, (k_round_vec<T, TP>), N, st, N, (const T *)v.r, v.rp);
+    if (split && !(kind == OP_SLOT && !zero_guess))   // (the slot init writes rp itself)
+        LAUNCH(K_PCG_INIT, (W + WP) * N, (k_round_vec<T, TP>), N, st, N, (const T *)v.r, v.rp);
     // preconditioner, then the r.z partials (in 3D with the slot operator
     // they ride on the preconditioner's last pass where that can take them)
     auto precond_rz = [&]() {
@@ -1916,17 +1922,31 @@ hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x
 // form's test, ||r||_2 <= rtol max(||b||_2, ||r_0||_2).
 // ---------------------------------------------------------------------------
 template <int DIM>
+// FP32 copy of the level-0 coefficients and their 1 / diag (invd_cell's
+// sum, in FP32, of the rounded values: the upper faces' coefficients are
+// read from the neighbours' FP64 entries and rounded the same way)
 __global__ void __launch_bounds__(kBlock) k_conv_coef(Level<double> A, Level<float> B) {
     GRID_LOOP(A.g.N) {
-        B.s[c] = (float)A.s[c];
+        int ia[3];
+        coords_of<DIM>(A.g, c, ia);
+        const float sc = (float)A.s[c];
+        B.s[c] = sc;
+        float d = sc;
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) B.cs[b][c] = (float)A.cs[b][c];
+        for (int b = 0; b < DIM; ++b) {
+            const float w = (float)A.cs[b][c];
+            B.cs[b][c] = w;
+            if (nb_lo(A.g, c, ia[b], b) >= 0) d += w;
+            const int hi = nb_hi(A.g, c, ia[b], b);
+            if (hi >= 0) d += (float)A.cs[b][hi];
+        }
+        B.invd[c] = 1.0f / d;
     }
 }
 
 void convert_level0(const Slot<double> &A, Slot<float> &B, int dim, hipStream_t st) {
     const int N = A.lev[0].g.N;
-    const double bytes = (8.0 + 4.0) * (1 + dim) * N;
+    const double bytes = (8.0 + 4.0) * (1 + dim) * N + 4.0 * N;
     if (dim == 2)
         LAUNCH(K_MG_SETUP, bytes, (k_conv_coef<2>), N, st, A.lev[0], B.lev[0]);
     else
@@ -1968,11 +1988,11 @@ void slot_apply(Slot<T> &S, int dim, const T *x, T *y, hipStream_t st) {
         LAUNCH(K_PCG_APPLY, 0, (k_slot_apply<T, 3>), S.lev[0].g.N, st, S.lev[0], x, y);
 }
 
-template void mg_setup<double>(Slot<double> &, int, hipStream_t);
+template void mg_setup<double>(Slot<double> &, int, hipStream_t, bool);
 template void mg_vcycle<double>(Slot<double> &, int, const double *, double *, const int *, hipStream_t);
 template hipError_t pcg_solve<double>(Slot<double> &, int, OpKind, ChOp, const double *, double *, double, int, int,
                                       Red &, PcgVecs<double> &, hipStream_t, SolveOut *, int);
-template void mg_setup<float>(Slot<float> &, int, hipStream_t);
+template void mg_setup<float>(Slot<float> &, int, hipStream_t, bool);
 template hipError_t pcg_solve<float>(Slot<float> &, int, OpKind, ChOp, const float *, float *, double, int, int,
                                      Red &, PcgVecs<float> &, hipStream_t, SolveOut *, int);
 template void remove_mean<double>(const Geo &, double *, Red &, hipStream_t);

@@ -145,7 +145,7 @@ int chns_solve_pressure_noalloc(const chns_grid_desc *desc, const void *rho, con
                       &o);
     } else {
         convert_level0(S.p64, S.p32, dim, s);
-        mg_setup(S.p32, dim, s);
+        mg_setup(S.p32, dim, s, false);
         const PcgVecs2<double, float> v2{S.vr, S.vp0, S.vp1, S.vq, S.vt, S.f_z, S.f_t, S.f_r};
         int predict = 4;
         e = refine_solve(S.p64, S.p32, dim, OP_SLOT, none, (const double *)S.rhs, (double *)p, rtol, max_iter,

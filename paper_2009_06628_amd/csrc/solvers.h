@@ -39,9 +39,10 @@ struct ChOp {
 };
 
 // Coarsen the slot's level-0 coefficients onto every level and invert the
-// coarsest operator (deterministic, on the stream).
+// coarsest operator (deterministic, on the stream).  invd0 = false: the
+// level-0 1 / diag is already in place (convert_level0 writes it).
 template <typename T>
-void mg_setup(Slot<T> &S, int dim, hipStream_t st);
+void mg_setup(Slot<T> &S, int dim, hipStream_t st, bool invd0 = true);
 
 // One symmetric V(1,1) cycle with red-black Gauss-Seidel: x0 ~ A^{-1} b0.
 template <typename T>
@@ -65,6 +66,8 @@ hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x
 // convert_level0 and coarsened by mg_setup<float> beforehand).
 // FP64 refinement rounds of the batched precision form (at most).
 constexpr int kMaxRefine = 4;
+// FP32 copy of the level-0 coefficients of A into B, with B's level-0
+// 1 / diag (then mg_setup(B, dim, st, false)).
 void convert_level0(const Slot<double> &A, Slot<float> &B, int dim, hipStream_t st);
 hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kind, ChOp ch, const double *b,
                         double *x, double rtol, int max_iter, int *predict, Red &red,
