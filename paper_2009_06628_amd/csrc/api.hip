@@ -206,6 +206,8 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
         g->cn_phim = g->cn_phimid = g->cn_dp = nullptr;
         for (int a = 0; a < 3; ++a) g->cn_vt[a] = nullptr;
     }
+    g->pext[0] = B.take<double>(N);
+    g->pext[1] = B.take<double>(N);
     g->vr = B.take<double>(N);
     g->vz = B.take<double>(N);
     g->vp0 = B.take<double>(N);
@@ -419,7 +421,7 @@ static bool serial_momentum(const chns_grid *g) { return g->serial_components !=
 // S1..S8 of one step from (phi, u) with the pressure initial guess in pr:
 // phihat, mu, phi_new, ustar and p; solver statistics into last.
 int forward_core(chns_grid *g, const double *phi, const double *const uc[3], double *mu, double *pr,
-                 chns_step_stats &last, const double *phi2 = nullptr, double *mu2 = nullptr) {
+                 chns_step_stats &last, const double *phi2 = nullptr, double *mu2 = nullptr, bool pguess = false) {
     const int dim = g->dim;
     const Geo &geo = g->geo;
     const StepConst k = step_const(g);
@@ -563,12 +565,16 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs,
                        g->prho);
     remove_mean(geo, g->rhs, g->red, s);
+    // initial guess: 2 p^n - p^(n-1) where this handle's previous step
+    // produced the incoming p^n (per cell), else p^n
+    if (pguess) launch_pressure_guess(geo, pr, g->pext[0], g->pext[1], s);
     HIPCHK(run_solve_ctx(g, main_ctx(g, 2), !concurrent, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
     if (int rc = check_solve(o, "pressure")) return rc;
     last.iters_p = o.iters;
     last.res_p = o.rel_res;
     last.unconverged |= o.unconverged ? 16 : 0;
     remove_mean(geo, pr, g->red, s);
+    if (pguess) HIPCHK(hipMemcpyAsync(g->pext[0], pr, sizeof(double) * geo.N, hipMemcpyDeviceToDevice, s));
     return CHNS_OK;
 }
 
@@ -742,6 +748,7 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     }
     for (int k = 0; k < 12; ++k) g->last_iters[k] = g->last_inner[k] = 4;
     g->adj_ready = 0;
+    g->in_record = 0;
     // streams (default priority) and events of the momentum components and
     // of the pressure set-up
     g->mc_ready = 0;
@@ -774,6 +781,7 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     g->serial_components = 0;
     g->scheme = CHNS_SCHEME_SPLIT;
     g->picard = 3;
+    g->pguess = 1;
     memset(g->wall_u, 0, sizeof g->wall_u);
     g->walls_move = 0;
     if (g->spec.carved) {
@@ -788,6 +796,8 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     memset(&g->last, 0, sizeof g->last);
     hipError_t e = hipMemsetAsync(g->red.counter, 0, 64 * sizeof(unsigned int), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->red.scal, 0, sizeof(Scal), g->stream);
+    // no pressure history yet: all-ones bytes are a NaN, equal to no pressure
+    if (e == hipSuccess) e = hipMemsetAsync(g->pext[0], 0xFF, sizeof(double) * (size_t)g->geo.N, g->stream);
     for (int a = 1; a < P.dim && e == hipSuccess; ++a) {
         e = hipMemsetAsync(g->mc[a - 1].red.counter, 0, 64 * sizeof(unsigned int), g->stream);
         if (e == hipSuccess) e = hipMemsetAsync(g->mc[a - 1].red.scal, 0, sizeof(Scal), g->stream);
@@ -897,7 +907,7 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
             unconv_any |= last.unconverged;
             continue;
         }
-        if (int rc = forward_core(g, phi, uc, mu, pr, last, phi2, mu2)) return rc;
+        if (int rc = forward_core(g, phi, uc, mu, pr, last, phi2, mu2, g->pguess && !g->in_record)) return rc;
         // S9
         if (g->nph == 3) {
             const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2},
@@ -1228,7 +1238,11 @@ int chns_step_record(chns_grid *g, chns_state *st, const chns_record *rec) {
     if (g->nph != 2) return fail(CHNS_EINVAL, "step records cover the two-phase step");
     if (g->scheme != CHNS_SCHEME_SPLIT) return fail(CHNS_EINVAL, "step records cover the split step");
     if (int rc = check_record(g, rec)) return rc;
+    // a recorded step starts its pressure solve from the state's p, as the
+    // adjoint's recomputation of the step does
+    g->in_record = 1;
     const int rc = chns_step(g, st, 1, nullptr);
+    g->in_record = 0;
     if (rc != CHNS_OK && rc != CHNS_ENOCONV) return rc;
     hipStream_t s = g->stream;
     const size_t bytes = sizeof(double) * g->geo.N;
@@ -1354,6 +1368,10 @@ int chns_set_option(chns_grid *g, int option, int value) {
         case CHNS_OPT_PICARD_ITERATIONS:
             if (value < 1 || value > 1000) return fail(CHNS_EINVAL, "Picard iterations must be in 1..1000");
             g->picard = value;
+            return CHNS_OK;
+        case CHNS_OPT_PRESSURE_GUESS:
+            if (value != 0 && value != 1) return fail(CHNS_EINVAL, "pressure-guess value must be 0 or 1");
+            g->pguess = value;
             return CHNS_OK;
         case CHNS_OPT_SERIAL_COMPONENTS:
             if (value != 0 && value != 1) return fail(CHNS_EINVAL, "serial-components value must be 0 or 1");

@@ -130,6 +130,9 @@ void launch_project(int dim, const Geo &g, const StepConst &k, const double *phi
                     const double *p, double *phi, double *const u[3], hipStream_t st);
 // CH slot level-0 coefficients: s = 1, cs = c / h^2.
 void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *const cs[3], hipStream_t st);
+// S8 initial guess: p = 2 p - prev where p equals last (the handle's previous
+// solution), else p unchanged; prev = the incoming p.
+void launch_pressure_guess(const Geo &g, double *p, const double *last, double *prev, hipStream_t st);
 // Diagnostics into out[0..6] = mass+, mass-, kinetic, free, gravity, umax, divmax.
 void launch_diagnostics(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
                         double *part, unsigned int *counter, double *out, hipStream_t st);

@@ -249,6 +249,23 @@ void launch_project(int dim, const Geo &g, const StepConst &k, const double *phi
                     const double *p, double *phi, double *const u[3], hipStream_t st) {
     DISPATCH(K_PROJECT, 3 + 2 * dim, dim, k_project, g.N, st, g, k, phi_new, mk_u3(ustar), p, phi, mk_w3(u));
 }
+// Linear extrapolation of the pressure in time as the S8 initial guess,
+// cell by cell only where the incoming p^n is the handle's previous
+// solution (a state edited or swapped by the caller keeps its own p there).
+__global__ void __launch_bounds__(kBlock) k_pressure_guess(int N, double *__restrict__ p,
+                                                           const double *__restrict__ last,
+                                                           double *__restrict__ prev) {
+    for (int c = xcd_block() * kBlock + (int)threadIdx.x; c < N; c += (int)gridDim.x * kBlock) {
+        const double pc = p[c];
+        if (pc == last[c]) p[c] = 2.0 * pc - prev[c];
+        prev[c] = pc;
+    }
+}
+
+void launch_pressure_guess(const Geo &g, double *p, const double *last, double *prev, hipStream_t st) {
+    TLAUNCH(K_P_SETUP, 32.0 * g.N, k_pressure_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, p, last, prev);
+}
+
 void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *const cs[3], hipStream_t st) {
     DISPATCH(K_MG_SETUP, 1 + dim, dim, k_fill_ch, g.N, st, g, csval, s, mk_w3(cs));
 }
