@@ -520,15 +520,18 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  *                               instead of three grid-wide launches (default
  *                               262144: 64^3 cells and below; 0: never).
  *                               Same per-cell arithmetic, bit for bit.
- *   CHNS_OPT_PRESSURE_GUESS     1 (default): the S8 pressure solve of a split
- *                               step starts from 2 p^n - p^(n-1), extrapolated
- *                               in time, in every cell where the incoming p^n
- *                               is this handle's previous solution (else
- *                               from p^n); 0: from p^n.  The converged
- *                               pressure meets the same tolerance either way
- *                               (three-phase drops at 128^3: 9 -> 7 CG
- *                               iterations).  chns_step_record and the
- *                               adjoint's recomputation start from p^n, so
+ *   CHNS_OPT_TIME_GUESS         1 (default): the S7 and S8 solves of a split
+ *                               step start from their solutions of the
+ *                               handle's two previous steps extrapolated in
+ *                               time (2 x^n - x^(n-1); x^n alone after one
+ *                               step), in every cell where the incoming p^n
+ *                               is this handle's previous pressure; else from
+ *                               the step's own guess (u^n, p^n).  0: never.
+ *                               The solutions meet the same tolerances either
+ *                               way (three-phase drops at 128^3: 9 -> 7
+ *                               pressure and 4 -> 2 momentum CG iterations).
+ *                               chns_step_record and the adjoint's
+ *                               recomputation use the step's own guesses, so
  *                               an adjoint rollout that must repeat its
  *                               forward steps bit for bit sets 0.
  * Results do not depend on CHNS_OPT_SERIAL_COMPONENTS; the two S2 solvers
@@ -554,7 +557,7 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  * and the energy monitor cover the split step only.                        */
 enum { CHNS_OPT_CH_SOLVER = 1, CHNS_OPT_SERIAL_COMPONENTS = 2, CHNS_OPT_TIME_SCHEME = 3,
        CHNS_OPT_PICARD_ITERATIONS = 4, CHNS_OPT_MARCH_SWEEP_CELLS = 5, CHNS_OPT_TILE_CYCLE_CELLS = 6,
-       CHNS_OPT_PRESSURE_GUESS = 7 };
+       CHNS_OPT_TIME_GUESS = 7 };
 enum { CHNS_CH_DIRECT = 0, CHNS_CH_PCG = 1, CHNS_CH_DIRECT_DENSE = 2 };
 enum { CHNS_SCHEME_SPLIT = 0, CHNS_SCHEME_CN = 1 };
 int chns_set_option(struct chns_grid *g, int option, int value);

@@ -26,7 +26,7 @@ CHNS_FP64, CHNS_FP32_REFINE = 0, 1
 CHNS_OPT_CH_SOLVER, CHNS_OPT_SERIAL_COMPONENTS, CHNS_OPT_TIME_SCHEME, CHNS_OPT_PICARD_ITERATIONS = 1, 2, 3, 4
 CHNS_OPT_MARCH_SWEEP_CELLS = 5
 CHNS_OPT_TILE_CYCLE_CELLS = 6
-CHNS_OPT_PRESSURE_GUESS = 7
+CHNS_OPT_TIME_GUESS = 7
 CHNS_CH_DIRECT, CHNS_CH_PCG, CHNS_CH_DIRECT_DENSE = 0, 1, 2
 CHNS_SCHEME_SPLIT, CHNS_SCHEME_CN = 0, 1
 
@@ -440,7 +440,7 @@ class Grid:
         CHNS_OPT_SERIAL_COMPONENTS (0 / 1), CHNS_OPT_TIME_SCHEME
         (CHNS_SCHEME_SPLIT / CHNS_SCHEME_CN), CHNS_OPT_PICARD_ITERATIONS (>= 1),
         CHNS_OPT_MARCH_SWEEP_CELLS (>= 1), CHNS_OPT_TILE_CYCLE_CELLS (>= 0),
-        CHNS_OPT_PRESSURE_GUESS (0 / 1)."""
+        CHNS_OPT_TIME_GUESS (0 / 1)."""
         _check(self._lib.chns_set_option(self._h, int(option), int(value)), "chns_set_option")
 
     # -- per-kernel timing ------------------------------------------------------

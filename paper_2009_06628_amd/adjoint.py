@@ -22,7 +22,7 @@ from __future__ import annotations
 import ctypes
 from typing import Dict, List, Sequence, Tuple
 
-from . import CHNS_OPT_PRESSURE_GUESS, Grid, _torch
+from . import CHNS_OPT_TIME_GUESS, Grid, _torch
 
 
 def props_for(props, sigma: float, mobility: float):
@@ -47,7 +47,7 @@ def _run(grid: Grid, props, sigma: float, mobility: float, phi0, u0: Sequence, n
     # the reverse sweep recomputes segments from checkpoints with step
     # records, which start the pressure solve from the stored p: the forward
     # steps do the same, so that the recomputation repeats them bit for bit
-    grid.set_option(CHNS_OPT_PRESSURE_GUESS, 0)
+    grid.set_option(CHNS_OPT_TIME_GUESS, 0)
     st = {"phi": phi0.detach().clone().contiguous(), "u": [x.detach().clone().contiguous() for x in u0],
           "p": torch.zeros_like(phi0), "mu": torch.zeros_like(phi0)}
     checkpoints: List[Dict] = []

@@ -208,6 +208,8 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
     }
     g->pext[0] = B.take<double>(N);
     g->pext[1] = B.take<double>(N);
+    for (int a = 0; a < 3; ++a)
+        for (int h = 0; h < 2; ++h) g->uext[a][h] = a < P.dim ? B.take<double>(N) : nullptr;
     g->vr = B.take<double>(N);
     g->vz = B.take<double>(N);
     g->vp0 = B.take<double>(N);
@@ -499,7 +501,14 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
             if (em[a] != hipSuccess) return;
         }
         double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
+        // extrapolated guess; after the solve the history moves one step
+        // (the older buffer takes the new solution)
+        if (pguess) launch_velocity_guess(geo, g->ustar[a], g->uext[a][0], g->uext[a][1], pr, g->pext[0], c.s);
         em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
+        if (pguess && em[a] == hipSuccess) {
+            std::swap(g->uext[a][0], g->uext[a][1]);
+            em[a] = hipMemcpyAsync(g->uext[a][0], g->ustar[a], sizeof(double) * geo.N, hipMemcpyDeviceToDevice, c.s);
+        }
         if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
     };
     // S5..S7 set-up of every component in one pass on the handle's stream
@@ -798,6 +807,9 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     if (e == hipSuccess) e = hipMemsetAsync(g->red.scal, 0, sizeof(Scal), g->stream);
     // no pressure history yet: all-ones bytes are a NaN, equal to no pressure
     if (e == hipSuccess) e = hipMemsetAsync(g->pext[0], 0xFF, sizeof(double) * (size_t)g->geo.N, g->stream);
+    for (int a = 0; a < P.dim && e == hipSuccess; ++a)
+        for (int h = 0; h < 2 && e == hipSuccess; ++h)
+            e = hipMemsetAsync(g->uext[a][h], 0xFF, sizeof(double) * (size_t)g->geo.N, g->stream);
     for (int a = 1; a < P.dim && e == hipSuccess; ++a) {
         e = hipMemsetAsync(g->mc[a - 1].red.counter, 0, 64 * sizeof(unsigned int), g->stream);
         if (e == hipSuccess) e = hipMemsetAsync(g->mc[a - 1].red.scal, 0, sizeof(Scal), g->stream);
@@ -1369,7 +1381,7 @@ int chns_set_option(chns_grid *g, int option, int value) {
             if (value < 1 || value > 1000) return fail(CHNS_EINVAL, "Picard iterations must be in 1..1000");
             g->picard = value;
             return CHNS_OK;
-        case CHNS_OPT_PRESSURE_GUESS:
+        case CHNS_OPT_TIME_GUESS:
             if (value != 0 && value != 1) return fail(CHNS_EINVAL, "pressure-guess value must be 0 or 1");
             g->pguess = value;
             return CHNS_OK;

@@ -266,6 +266,27 @@ void launch_pressure_guess(const Geo &g, double *p, const double *last, double *
     TLAUNCH(K_P_SETUP, 32.0 * g.N, k_pressure_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, p, last, prev);
 }
 
+// The same for a velocity component of S7 from its last two solutions (the
+// incoming pressure stands for the state: where it is the handle's previous
+// solution, the velocity is too)
+__global__ void __launch_bounds__(kBlock) k_velocity_guess(int N, double *__restrict__ u,
+                                                           const double *__restrict__ h0,
+                                                           const double *__restrict__ h1,
+                                                           const double *__restrict__ p,
+                                                           const double *__restrict__ plast) {
+    for (int c = xcd_block() * kBlock + (int)threadIdx.x; c < N; c += (int)gridDim.x * kBlock) {
+        if (p[c] != plast[c]) continue;
+        const double a = h0[c], b = h1[c];
+        u[c] = isfinite(b) ? 2.0 * a - b : a;
+    }
+}
+
+void launch_velocity_guess(const Geo &g, double *u, const double *h0, const double *h1, const double *p,
+                           const double *plast, hipStream_t st) {
+    TLAUNCH(K_MOM_SETUP, 40.0 * g.N, k_velocity_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, u, h0, h1, p,
+            plast);
+}
+
 void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *const cs[3], hipStream_t st) {
     DISPATCH(K_MG_SETUP, 1 + dim, dim, k_fill_ch, g.N, st, g, csval, s, mk_w3(cs));
 }
