@@ -522,14 +522,16 @@ int chns_set_wall_velocity(struct chns_grid *g, int axis, int side, int componen
  *                               Same per-cell arithmetic, bit for bit.
  *   CHNS_OPT_TIME_GUESS         1 (default): the S7 and S8 solves of a split
  *                               step start from their solutions of the
- *                               handle's two previous steps extrapolated in
- *                               time (2 x^n - x^(n-1); x^n alone after one
- *                               step), in every cell where the incoming p^n
- *                               is this handle's previous pressure; else from
- *                               the step's own guess (u^n, p^n).  0: never.
- *                               The solutions meet the same tolerances either
- *                               way (three-phase drops at 128^3: 9 -> 7
- *                               pressure and 4 -> 2 momentum CG iterations).
+ *                               handle's three previous steps extrapolated in
+ *                               time (3 x^n - 3 x^(n-1) + x^(n-2); linear or
+ *                               x^n while fewer exist), in every cell where
+ *                               the incoming p^n is this handle's previous
+ *                               pressure (elsewhere the history restarts);
+ *                               else from the step's own guess (u^n, p^n).
+ *                               0: never.  The solutions meet the same
+ *                               tolerances either way (three-phase drops at
+ *                               128^3: 9 -> 6 pressure and 4 -> 2 momentum
+ *                               CG iterations).
  *                               chns_step_record and the adjoint's
  *                               recomputation use the step's own guesses, so
  *                               an adjoint rollout that must repeat its

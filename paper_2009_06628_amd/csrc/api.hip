@@ -206,10 +206,9 @@ void layout(Bump &B, const Plan &P, chns_grid *g, int prec) {
         g->cn_phim = g->cn_phimid = g->cn_dp = nullptr;
         for (int a = 0; a < 3; ++a) g->cn_vt[a] = nullptr;
     }
-    g->pext[0] = B.take<double>(N);
-    g->pext[1] = B.take<double>(N);
+    for (int h = 0; h < 3; ++h) g->pext[h] = B.take<double>(N);
     for (int a = 0; a < 3; ++a)
-        for (int h = 0; h < 2; ++h) g->uext[a][h] = a < P.dim ? B.take<double>(N) : nullptr;
+        for (int h = 0; h < 3; ++h) g->uext[a][h] = a < P.dim ? B.take<double>(N) : nullptr;
     g->vr = B.take<double>(N);
     g->vz = B.take<double>(N);
     g->vp0 = B.take<double>(N);
@@ -503,11 +502,15 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
         // extrapolated guess; after the solve the history moves one step
         // (the older buffer takes the new solution)
-        if (pguess) launch_velocity_guess(geo, g->ustar[a], g->uext[a][0], g->uext[a][1], pr, g->pext[0], c.s);
+        double **h = g->uext[a];
+        if (pguess) launch_velocity_guess(geo, g->ustar[a], h, pr, g->pext[0], c.s);
         em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
         if (pguess && em[a] == hipSuccess) {
-            std::swap(g->uext[a][0], g->uext[a][1]);
-            em[a] = hipMemcpyAsync(g->uext[a][0], g->ustar[a], sizeof(double) * geo.N, hipMemcpyDeviceToDevice, c.s);
+            double *oldest = h[2];
+            h[2] = h[1];
+            h[1] = h[0];
+            h[0] = oldest;
+            em[a] = hipMemcpyAsync(h[0], g->ustar[a], sizeof(double) * geo.N, hipMemcpyDeviceToDevice, c.s);
         }
         if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
     };
@@ -576,7 +579,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     remove_mean(geo, g->rhs, g->red, s);
     // initial guess: 2 p^n - p^(n-1) where this handle's previous step
     // produced the incoming p^n (per cell), else p^n
-    if (pguess) launch_pressure_guess(geo, pr, g->pext[0], g->pext[1], s);
+    if (pguess) launch_pressure_guess(geo, pr, g->pext, s);
     HIPCHK(run_solve_ctx(g, main_ctx(g, 2), !concurrent, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
     if (int rc = check_solve(o, "pressure")) return rc;
     last.iters_p = o.iters;
@@ -806,9 +809,10 @@ int chns_create_grid(const chns_grid_desc *desc, void *workspace, size_t bytes, 
     hipError_t e = hipMemsetAsync(g->red.counter, 0, 64 * sizeof(unsigned int), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->red.scal, 0, sizeof(Scal), g->stream);
     // no pressure history yet: all-ones bytes are a NaN, equal to no pressure
-    if (e == hipSuccess) e = hipMemsetAsync(g->pext[0], 0xFF, sizeof(double) * (size_t)g->geo.N, g->stream);
+    for (int h = 0; h < 3 && e == hipSuccess; ++h)
+        e = hipMemsetAsync(g->pext[h], 0xFF, sizeof(double) * (size_t)g->geo.N, g->stream);
     for (int a = 0; a < P.dim && e == hipSuccess; ++a)
-        for (int h = 0; h < 2 && e == hipSuccess; ++h)
+        for (int h = 0; h < 3 && e == hipSuccess; ++h)
             e = hipMemsetAsync(g->uext[a][h], 0xFF, sizeof(double) * (size_t)g->geo.N, g->stream);
     for (int a = 1; a < P.dim && e == hipSuccess; ++a) {
         e = hipMemsetAsync(g->mc[a - 1].red.counter, 0, 64 * sizeof(unsigned int), g->stream);

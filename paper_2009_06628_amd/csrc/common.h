@@ -388,8 +388,8 @@ struct chns_grid {
     int scheme, picard;                      // CHNS_OPT_TIME_SCHEME, CHNS_OPT_PICARD_ITERATIONS
     int pguess;                              // CHNS_OPT_TIME_GUESS
     int in_record;                           // inside chns_step_record (no extrapolated guesses)
-    double *pext[2];                         // S8 guess history: [0] the last step's pressure, [1] the one before
-    double *uext[3][2];                      // S7 guess history per component: [0] the last u*, [1] the one before
+    double *pext[3];                         // S8 guess history: the last three steps' pressures, newest first
+    double *uext[3][3];                      // S7 guess history per component: the last three u*, newest first
     double *cn_phim, *cn_phimid, *cn_dp, *cn_vt[3];   // Crank-Nicolson iterates (two-phase grids)
     const double *wall_u[3][2][3];           // moving-wall data [axis][side][component] (caller-owned)
     int walls_move;                          // any of them set

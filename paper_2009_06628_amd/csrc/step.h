@@ -130,13 +130,16 @@ void launch_project(int dim, const Geo &g, const StepConst &k, const double *phi
                     const double *p, double *phi, double *const u[3], hipStream_t st);
 // CH slot level-0 coefficients: s = 1, cs = c / h^2.
 void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *const cs[3], hipStream_t st);
-// S8 initial guess: p = 2 p - prev where p equals last (the handle's previous
-// solution), else p unchanged; prev = the incoming p.
-void launch_pressure_guess(const Geo &g, double *p, const double *last, double *prev, hipStream_t st);
-// S7 initial guess of one component: u = 2 h0 - h1 (h0 alone where h1 is not
-// finite: one step of history) where p equals plast, else u unchanged.
-void launch_velocity_guess(const Geo &g, double *u, const double *h0, const double *h1, const double *p,
-                           const double *plast, hipStream_t st);
+// S8 initial guess: where p equals h[0] (the handle's previous solution), p
+// extrapolated in time from p and the older pressures h[1], h[2] (as many
+// as are finite: quadratic, linear or p itself); then h[2] = h[1],
+// h[1] = the incoming p.
+void launch_pressure_guess(const Geo &g, double *p, double *const h[3], hipStream_t st);
+// S7 initial guess of one component: where p equals plast, u extrapolated
+// from its last solutions h[0], h[1], h[2] (as many as are finite), else u
+// unchanged.
+void launch_velocity_guess(const Geo &g, double *u, double *const h[3], const double *p, const double *plast,
+                           hipStream_t st);
 // Diagnostics into out[0..6] = mass+, mass-, kinetic, free, gravity, umax, divmax.
 void launch_diagnostics(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
                         double *part, unsigned int *counter, double *out, hipStream_t st);

@@ -249,42 +249,53 @@ void launch_project(int dim, const Geo &g, const StepConst &k, const double *phi
                     const double *p, double *phi, double *const u[3], hipStream_t st) {
     DISPATCH(K_PROJECT, 3 + 2 * dim, dim, k_project, g.N, st, g, k, phi_new, mk_u3(ustar), p, phi, mk_w3(u));
 }
-// Linear extrapolation of the pressure in time as the S8 initial guess,
-// cell by cell only where the incoming p^n is the handle's previous
-// solution (a state edited or swapped by the caller keeps its own p there).
-__global__ void __launch_bounds__(kBlock) k_pressure_guess(int N, double *__restrict__ p,
-                                                           const double *__restrict__ last,
-                                                           double *__restrict__ prev) {
+// Extrapolation in time from x^n = a and the older solutions b, c as far as
+// they are finite (no history yet: NaN): 3a - 3b + c, 2a - b or a.
+__device__ inline double time_extrap(double a, double b, double c) {
+    return isfinite(c) ? 3.0 * a - 3.0 * b + c : (isfinite(b) ? 2.0 * a - b : a);
+}
+
+// S8 initial guess, cell by cell only where the incoming p^n is the handle's
+// previous solution (a state edited or swapped by the caller keeps its own p
+// there, and its history restarts); the history moves one step.
+__global__ void __launch_bounds__(kBlock) k_pressure_guess(int N, double *__restrict__ p, const double *__restrict__ h0,
+                                                           double *__restrict__ h1, double *__restrict__ h2) {
     for (int c = xcd_block() * kBlock + (int)threadIdx.x; c < N; c += (int)gridDim.x * kBlock) {
-        const double pc = p[c];
-        if (pc == last[c]) p[c] = 2.0 * pc - prev[c];
-        prev[c] = pc;
+        const double pc = p[c], b = h1[c];
+        const bool cont = pc == h0[c];
+        if (cont) p[c] = time_extrap(pc, b, h2[c]);
+        h2[c] = cont ? b : __longlong_as_double(-1LL);   // all-ones bytes: NaN, no history
+        h1[c] = pc;
     }
 }
 
-void launch_pressure_guess(const Geo &g, double *p, const double *last, double *prev, hipStream_t st) {
-    TLAUNCH(K_P_SETUP, 32.0 * g.N, k_pressure_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, p, last, prev);
+void launch_pressure_guess(const Geo &g, double *p, double *const h[3], hipStream_t st) {
+    TLAUNCH(K_P_SETUP, 48.0 * g.N, k_pressure_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, p,
+            (const double *)h[0], h[1], h[2]);
 }
 
-// The same for a velocity component of S7 from its last two solutions (the
-// incoming pressure stands for the state: where it is the handle's previous
-// solution, the velocity is too)
-__global__ void __launch_bounds__(kBlock) k_velocity_guess(int N, double *__restrict__ u,
-                                                           const double *__restrict__ h0,
-                                                           const double *__restrict__ h1,
+// The same for a velocity component of S7 from its last three solutions
+// (the incoming pressure stands for the state: where it is the handle's
+// previous solution, the velocity is too)
+__global__ void __launch_bounds__(kBlock) k_velocity_guess(int N, double *__restrict__ u, double *__restrict__ h0,
+                                                           double *__restrict__ h1, const double *__restrict__ h2,
                                                            const double *__restrict__ p,
                                                            const double *__restrict__ plast) {
     for (int c = xcd_block() * kBlock + (int)threadIdx.x; c < N; c += (int)gridDim.x * kBlock) {
-        if (p[c] != plast[c]) continue;
-        const double a = h0[c], b = h1[c];
-        u[c] = isfinite(b) ? 2.0 * a - b : a;
+        if (p[c] == plast[c]) {
+            u[c] = time_extrap(h0[c], h1[c], h2[c]);
+        } else {
+            // another trajectory: its history restarts with this step's solution
+            h0[c] = __longlong_as_double(-1LL);
+            h1[c] = __longlong_as_double(-1LL);
+        }
     }
 }
 
-void launch_velocity_guess(const Geo &g, double *u, const double *h0, const double *h1, const double *p,
-                           const double *plast, hipStream_t st) {
-    TLAUNCH(K_MOM_SETUP, 40.0 * g.N, k_velocity_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, u, h0, h1, p,
-            plast);
+void launch_velocity_guess(const Geo &g, double *u, double *const h[3], const double *p, const double *plast,
+                           hipStream_t st) {
+    TLAUNCH(K_MOM_SETUP, 48.0 * g.N, k_velocity_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, u, h[0], h[1],
+            (const double *)h[2], p, plast);
 }
 
 void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *const cs[3], hipStream_t st) {

@@ -411,6 +411,54 @@ def test_ch_fft_matches_dense_basis(case):
 
 
 @pytest.mark.parametrize("case", ["bubble2d", "drops3d"])
+def test_time_guess_meets_the_tolerances(case):
+    """CHNS_OPT_TIME_GUESS (default on) starts the momentum and pressure
+    solves from their last solutions extrapolated in time: after 10 steps
+    the state agrees with the plain guesses (u^n, p^n) to the solver
+    tolerances, with no more CG iterations in the last step."""
+    P = _lib()
+    prob = W.rising_bubble(64, steps=10) if case == "bubble2d" else W.drop3d(32, steps=10)
+    init = W.initial_state(prob)
+    out = []
+    for guess in (1, 0):
+        g = P.grid_for_problem(prob)
+        g.set_option(P.CHNS_OPT_TIME_GUESS, guess)
+        st = g.new_state(init)
+        g.step(st, 9)
+        stats = g.step(st, 1)
+        print("time guess", case, guess, stats["iters_p"], stats["iters_mom"], flush=True)
+        out.append((st, stats))
+    (a, sa), (b, sb) = out
+    assert sa["iters_p"] <= sb["iters_p"] and sum(sa["iters_mom"]) <= sum(sb["iters_mom"])
+    assert relerr(to_np(a["phi"]), to_np(b["phi"])) < 1e-9
+    for d in range(len(a["u"])):
+        assert relerr(to_np(a["u"][d]), to_np(b["u"][d])) < 1e-8, d
+    pa, pb = to_np(a["p"]), to_np(b["p"])
+    assert relerr(pa - pa.mean(), pb - pb.mean()) < 1e-8
+
+
+def test_time_guess_restarts_on_another_state():
+    """A handle that stepped one state and is then given another (whose
+    pressure is not the handle's last solution) restarts its guess history
+    there: the new state's steps are bit for bit those of a fresh handle."""
+    P = _lib()
+    pa, pb = W.drop3d(32, steps=3), W.drop3d(32, steps=2, Re=20.0)
+    g = P.grid_for_problem(pa)
+    sa = g.new_state(W.initial_state(pa))
+    g.step(sa, 3)
+    g.set_properties(pb.props)
+    sb = g.new_state(W.initial_state(pb))
+    g.step(sb, 2)
+    f = P.grid_for_problem(pb)
+    sf = f.new_state(W.initial_state(pb))
+    f.step(sf, 2)
+    for k in ("phi", "p", "mu"):
+        assert torch.equal(sb[k], sf[k]), k
+    for d in range(3):
+        assert torch.equal(sb["u"][d], sf["u"][d]), d
+
+
+@pytest.mark.parametrize("case", ["bubble2d", "drops3d"])
 def test_concurrent_momentum_matches_serial_bitwise(case):
     """The momentum components run on their own streams and host threads; with
     the per-kernel timing on, or with CHNS_OPT_SERIAL_COMPONENTS, they run one
