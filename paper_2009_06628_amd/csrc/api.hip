@@ -503,7 +503,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         // extrapolated guess; after the solve the history moves one step
         // (the older buffer takes the new solution)
         double **h = g->uext[a];
-        if (pguess) launch_velocity_guess(geo, g->ustar[a], h, pr, g->pext[0], c.s);
+        if (pguess) launch_velocity_guess(geo, g->ustar[a], h, uc[a], pr, g->pext[0], c.s);
         em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
         if (pguess && em[a] == hipSuccess) {
             double *oldest = h[2];
@@ -524,7 +524,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
             mo.s[a] = L0.s;
             for (int b = 0; b < 3; ++b) mo.cs[a][b] = L0.cs[b];
             mo.rhs[a] = a == 0 ? g->rhs : g->mc[a - 1].rhs;
-            mo.ustar[a] = g->ustar[a];
+            mo.ustar[a] = pguess ? nullptr : g->ustar[a];   // with the time guess written by k_velocity_guess
         }
         WallVel wv;
         memcpy(wv.v, g->wall_u, sizeof wv.v);
@@ -577,8 +577,9 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
         launch_p_setup(dim, geo, k, g->phi_new, usc, P0.s, pcs, g->rhs, s, concurrent ? kPRhs : kPCoef | kPRhs,
                        g->prho);
     remove_mean(geo, g->rhs, g->red, s);
-    // initial guess: 2 p^n - p^(n-1) where this handle's previous step
-    // produced the incoming p^n (per cell), else p^n
+    // initial guess: p extrapolated in time from this handle's previous
+    // solutions where its last step produced the incoming p^n (per cell),
+    // else p^n
     if (pguess) launch_pressure_guess(geo, pr, g->pext, s);
     HIPCHK(run_solve_ctx(g, main_ctx(g, 2), !concurrent, OP_SLOT, ch, (const double *)g->rhs, pr, p.rtol_p, 4, &o));
     if (int rc = check_solve(o, "pressure")) return rc;

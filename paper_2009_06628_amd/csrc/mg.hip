@@ -489,8 +489,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply_slot(Level<T> L, const TZ 
 }
 
 // The same apply on a 3D grid (no pending residual), marching along z:
-// block b owns the kMX x kMY x zc cells of column tile b mod ncol and z chunk
-// b / ncol, one cell per thread and plane.  p = (z - zmean) + beta p_old of
+// logical block b owns the kMX x kMY x zc cells of column tile b mod ncol and
+// z chunk b / ncol, one cell per thread and plane.  p = (z - zmean) + beta p_old of
 // the column and a one-cell halo is formed once per plane into a ring of
 // three LDS planes, where the grid-stride form above evaluates it at all
 // seven stencil points of every cell (128^3: 4 TB/s).  q, p_new and the
@@ -526,7 +526,10 @@ __global__ void __launch_bounds__(kBlock) k_pcg_apply3_march(Level<T> L, const T
     const double beta = it.beta, zm = it.zm;
     const Geo &g = L.g;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    const int col = (int)blockIdx.x % ncol, z0 = ((int)blockIdx.x / ncol) * zc;
+    // XCD-contiguous numbering: the column tiles of a z chunk, whose halos
+    // overlap, run on the same XCD and share its L2 (128^3: 32 -> 28 us)
+    const int lb = xcd_block();
+    const int col = lb % ncol, z0 = (lb / ncol) * zc;
     const int x0 = (col % ncolx) * kMX, y0 = (col / ncolx) * kMY;
     const int z1 = z0 + zc < nz ? z0 + zc : nz;
     // coordinate of a halo position on one axis (wrapped on a periodic axis);

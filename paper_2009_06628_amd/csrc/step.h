@@ -22,7 +22,8 @@ struct WallVel {
 };
 
 // Outputs of the set-up of every momentum component (component a: level-0
-// coefficients s, cs[b] of its hierarchy, right-hand side, initial guess).
+// coefficients s, cs[b] of its hierarchy, right-hand side, initial guess
+// u_a; ustar null: the guess is left to the time-guess kernel).
 struct MomOut {
     double *s[3];
     double *cs[3][3];   // [component][direction]
@@ -136,10 +137,10 @@ void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *cons
 // h[1] = the incoming p.
 void launch_pressure_guess(const Geo &g, double *p, double *const h[3], hipStream_t st);
 // S7 initial guess of one component: where p equals plast, u extrapolated
-// from its last solutions h[0], h[1], h[2] (as many as are finite), else u
-// unchanged.
-void launch_velocity_guess(const Geo &g, double *u, double *const h[3], const double *p, const double *plast,
-                           hipStream_t st);
+// from its last solutions h[0], h[1], h[2] (as many as are finite), else u^n
+// (un).  Writes every cell of u: the momentum set-up is then given no ustar.
+void launch_velocity_guess(const Geo &g, double *u, double *const h[3], const double *un, const double *p,
+                           const double *plast, hipStream_t st);
 // Diagnostics into out[0..6] = mass+, mass-, kinetic, free, gravity, umax, divmax.
 void launch_diagnostics(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
                         double *part, unsigned int *counter, double *out, hipStream_t st);

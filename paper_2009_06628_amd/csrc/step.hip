@@ -218,7 +218,7 @@ void launch_mom_setup_all(int dim, const Geo &g, const StepConst &k, const doubl
     WallVel w{};
     if (wv) w = *wv;
     // phi, phi_new, mu and u[d] read; s, cs[d], rhs, ustar written per component
-    const double bytes = 8.0 * (3 + dim + dim * (3 + dim)) * g.N;
+    const double bytes = 8.0 * (3 + dim + dim * (3 + dim) - (o.ustar[0] ? 0 : dim)) * g.N;
     const dim3 grid(grid_for(g.N)), block(kBlock);
     if (dim == 2) {
         if (wv)
@@ -276,9 +276,11 @@ void launch_pressure_guess(const Geo &g, double *p, double *const h[3], hipStrea
 
 // The same for a velocity component of S7 from its last three solutions
 // (the incoming pressure stands for the state: where it is the handle's
-// previous solution, the velocity is too)
+// previous solution, the velocity is too), else u^n (un); every cell of u is
+// written (the set-up leaves it to this kernel)
 __global__ void __launch_bounds__(kBlock) k_velocity_guess(int N, double *__restrict__ u, double *__restrict__ h0,
                                                            double *__restrict__ h1, const double *__restrict__ h2,
+                                                           const double *__restrict__ un,
                                                            const double *__restrict__ p,
                                                            const double *__restrict__ plast) {
     for (int c = xcd_block() * kBlock + (int)threadIdx.x; c < N; c += (int)gridDim.x * kBlock) {
@@ -286,16 +288,17 @@ __global__ void __launch_bounds__(kBlock) k_velocity_guess(int N, double *__rest
             u[c] = time_extrap(h0[c], h1[c], h2[c]);
         } else {
             // another trajectory: its history restarts with this step's solution
+            u[c] = un[c];
             h0[c] = __longlong_as_double(-1LL);
             h1[c] = __longlong_as_double(-1LL);
         }
     }
 }
 
-void launch_velocity_guess(const Geo &g, double *u, double *const h[3], const double *p, const double *plast,
-                           hipStream_t st) {
+void launch_velocity_guess(const Geo &g, double *u, double *const h[3], const double *un, const double *p,
+                           const double *plast, hipStream_t st) {
     TLAUNCH(K_MOM_SETUP, 48.0 * g.N, k_velocity_guess, dim3(grid_for(g.N)), dim3(kBlock), st, (int)g.N, u, h[0], h[1],
-            (const double *)h[2], p, plast);
+            (const double *)h[2], un, p, plast);
 }
 
 void launch_fill_ch(int dim, const Geo &g, double csval, double *s, double *const cs[3], hipStream_t st) {

@@ -196,7 +196,7 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
         for (int b = 0; b < DIM; ++b) cs.a[b][c] = 0.0;
         if (!coef_only) {
             rhs[c] = 0.0;
-            ustar[c] = 0.0;
+            if (ustar) ustar[c] = 0.0;
         }
         return;
     }
@@ -269,7 +269,7 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
     s[c] = sd;
     if (!coef_only) {
         rhs[c] = f;
-        ustar[c] = ua[c];
+        if (ustar) ustar[c] = ua[c];   // null: the guess is written by k_velocity_guess
     }
 }
 

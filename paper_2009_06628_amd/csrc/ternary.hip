@@ -426,7 +426,7 @@ void launch_mom_setup3_all(int dim, const Geo &g, const StepConst &k, const Tern
     for (int b = 0; b < 3; ++b) mx.m[b] = m[b];
     // rho^{n+1}, rho^n, eta^{n+1}, phi_1, phi_2, mu_1, mu_2, m[d] and u[d] read; s, cs[d], rhs, ustar written
     // per component
-    const double bytes = 8.0 * (7 + 2 * dim + dim * (3 + dim)) * g.N;
+    const double bytes = 8.0 * (7 + 2 * dim + dim * (3 + dim) - (o.ustar[0] ? 0 : dim)) * g.N;
     if (dim == 2) {
         if (wv)
             TLAUNCH(K_MOM_SETUP, bytes, (k_mom_setup3_all<2, true>), grid, block, st, g, k, mx, mk_u3(u), o, w);
