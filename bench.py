@@ -10,11 +10,14 @@ input:
                tests use (CH 1e-15, momentum 1e-13, pressure 1e-12)
   fp32_refine  the precision form: FP32 multigrid preconditioner inside FP64
                CG (FP64 vectors, operator apply and dots), at its own tolerances
-               (1e-10 / 1e-10 / 1e-9)
+               (1e-10 / 1e-9 / 1e-8; its state stays within 1.5e-8 of the FP64
+               run over the configuration's 500 steps, budget 1e-5)
 A step is one full pass T1..T9 (two CH solves, three momentum components,
-pressure projection).  Inputs are synthetic and already resident in device
-memory when the timed region starts.  `value` is the precision form's
-throughput; the FP64 form's and the ratio are in `config`.
+pressure projection).  By default each form runs the configuration's 500
+steps from the initial state, 10 untimed and 490 timed.  Inputs are
+synthetic and already resident in device memory when the timed region
+starts.  `value` is the precision form's throughput; the FP64 form's and the
+ratio are in `config`.
 
 Secondary measurements (key "secondary", each on its own workload, skipped
 with --no-extras):
@@ -60,13 +63,16 @@ EXTRAS = ("bubble", "hbm_sweeps", "batched", "adjoint")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    # default: the headline configuration's 500 steps, 10 untimed and 490 timed
+    ap.add_argument("--steps", type=int, default=490)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-headline", action="store_true", help="skip the headline legs (profiling runs of extras)")
+    ap.add_argument("--headline-forms", default="fp64,fp32_refine",
+                    help="headline forms to run (profiling runs take one form each)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extra-steps", type=int, default=20)
     ap.add_argument("--extras", default=",".join(EXTRAS),
@@ -137,21 +143,35 @@ KERNEL_CLASSES = {
     "t_phase": ("k_t_phase",),
     "ch_spectral": ("k_axis_mfma64", "k_axis_gemm", "k_axis_gemm16s", "k_spectral_scale_batch", "k_spectral_scale",
                     "k_axis_fft"),
+    # the step's own passes and the solver set-ups
+    "ch_rhs": ("k_ch_rhs", "k_ch_rhs3", "k_cn_ch_rhs"),
+    "mu": ("k_mu", "k_mu3"),
+    "phi_update": ("k_phi_update", "k_phi_update3", "k_cn_phi_update"),
+    "mom_setup": ("k_mom_setup", "k_mom_setup_all", "k_mom_setup3_all", "k_mom_setup_walls", "k_mflux3",
+                  "k_velocity_guess", "k_cn_mom_setup"),
+    "p_setup": ("k_p_setup", "k_p_setup3", "k_p_coef_rho", "k_pressure_guess"),
+    "project": ("k_project", "k_project3", "k_cn_project", "k_cn_finish"),
+    "mg_setup": ("k_coarsen", "k_conv_coef", "k_fill_ch", "k_invd", "k_setup_block"),
+    "pcg_init": ("k_pcg_init_slot", "k_pcg_init_zero", "k_pcg_init_ch", "k_pcg_fin_init", "k_round_vec",
+                 "k_ch_lap_plain", "k_cn_zero"),
+    "mean": ("k_sum", "k_sub_mean"),
 }
 
-# Which dispatches of a profiled bench.py run belong to a workload: the
-# headline legs run in one process and differ in the multigrid precision
-# (template arguments); the other workloads are profiled in runs of their own.
+# Which dispatches of a profiled bench.py run belong to a workload: every
+# workload, each headline form included (--headline-forms), is profiled in a
+# bench.py run of its own.
 WORKLOAD_FILTERS = {
-    "ternary_drops3d_128^3_fp32_refine": lambda args: "float" in args,
-    "ternary_drops3d_128^3_fp64": lambda args: bool(args) and "float" not in args,
+    "ternary_drops3d_128^3_fp32_refine": lambda args: True,
+    "ternary_drops3d_128^3_fp64": lambda args: True,
     "rising_bubble_256x512_fp64": lambda args: True,
     "pressure_512^3_fp64": lambda args: True,
     "pressure_8192^2_fp64": lambda args: True,
     "ensemble_512_fp32_refine": lambda args: True,
 }
-TRAFFIC_SOURCES = ["paper_2009_06628_amd/csrc/mg.hip", "paper_2009_06628_amd/csrc/mgdev.h",
-                   "paper_2009_06628_amd/csrc/common.h", "paper_2009_06628_amd/csrc/tile2d.h"]
+# the counter record stands for the library built from these sources
+TRAFFIC_SOURCES = sorted("paper_2009_06628_amd/csrc/" + f for f in os.listdir(os.path.join(ROOT, "paper_2009_06628_amd",
+                                                                                          "csrc"))
+                         if f.endswith((".hip", ".h")))
 
 
 def _class_of(kernel_name):
@@ -601,9 +621,12 @@ def main():
         prob = W.ternary_drops3d(128, steps=500)
         legs = {}
         states = {}
+        forms = [f for f in args.headline_forms.split(",") if f]
         for name, prec, pr in (("fp64", P.CHNS_FP64, prob),
                                ("fp32_refine", P.CHNS_FP32_REFINE,
                                 W.ternary_drops3d(128, steps=500, **W.PRECISION_FORM_TOLERANCES))):
+            if name not in forms:
+                continue
             g, st, t = timed_run(P, pr, prec, args.warmup, args.steps, args.serial_components)
             stats = g.step(st, 1)     # outside the timed region: solver statistics and diagnostics
             legs[name] = {"value": round(prob.cells * args.steps / t["wall"], 1),
@@ -620,22 +643,27 @@ def main():
             states[name] = st
             del g
             torch.cuda.empty_cache()
-        a, b = states["fp32_refine"], states["fp64"]
-        diff = 0.0
-        for i in range(2):
-            diff = max(diff, float((a["phi"][i] - b["phi"][i]).abs().max() / b["phi"][i].abs().max()))
-        for d in range(3):
-            diff = max(diff, float((a["u"][d] - b["u"][d]).abs().max() / b["u"][d].abs().max().clamp_min(1e-300)))
-        del states, a, b
+        diff = None
+        if len(states) == 2:
+            a, b = states["fp32_refine"], states["fp64"]
+            diff = 0.0
+            for i in range(2):
+                diff = max(diff, float((a["phi"][i] - b["phi"][i]).abs().max() / b["phi"][i].abs().max()))
+            for d in range(3):
+                diff = max(diff,
+                           float((a["u"][d] - b["u"][d]).abs().max() / b["u"][d].abs().max().clamp_min(1e-300)))
+            del a, b
+        del states
         torch.cuda.empty_cache()
-        f64, f32 = legs["fp64"], legs["fp32_refine"]
-        out.update(value=f32["value"], ms_per_step=f32["ms_per_step"], roofline=f32.pop("roofline", None))
+        f64, f32 = legs.get("fp64"), legs.get("fp32_refine")
+        head = f32 if f32 is not None else f64
+        out.update(value=head["value"], ms_per_step=head["ms_per_step"], roofline=head.pop("roofline", None))
         out["config"] = {"workload": workload, "grid": list(prob.n), "cells": prob.cells, "bc": list(prob.bc),
                          "nphases": 3, "densities": list(prob.props.rho3), "viscosities": list(prob.props.eta3),
                          "surface_tensions": [round(x, 6) for x in prob.props.sigma3], "Re": prob.props.Re,
-                         "dt": prob.props.dt, "form": "fp32_refine",
+                         "dt": prob.props.dt, "form": "fp32_refine" if f32 is not None else "fp64",
                          "fp32_refine": f32, "fp64": f64,
-                         "speedup_fp32_refine_vs_fp64": round(f32["value"] / f64["value"], 3),
+                         "speedup_fp32_refine_vs_fp64": round(f32["value"] / f64["value"], 3) if f32 and f64 else None,
                          "max_rel_state_diff_fp32_refine_vs_fp64": diff,
                          "serial_components": bool(args.serial_components)}
         if not args.no_cpu_baseline and args.cpu_steps > 0:

@@ -125,6 +125,26 @@ def test_third_phase_absent_gpu_matches_binary_gpu():
     assert relerr(to_np(s3["p"]), to_np(s2["p"])) <= 1e-10
 
 
+def test_ternary_precision_form_128_vs_fp64_500_steps():
+    """The 128^3 three-phase drops over the configuration's 500 steps: the
+    precision form at its own tolerances stays within its 1e-5 budget of the
+    FP64 path at the parity tolerances (which the 32^3 tests pin to the
+    oracle), and every phase mass agrees to 1e-12."""
+    P = _lib()
+    print("ternary 128^3, 500 steps: FP64 and the precision form", flush=True)
+    _, s64, st64 = run_gpu(W.ternary_drops3d(128, steps=500), 500)
+    ref = {"phi": [to_np(x) for x in s64["phi"]], "mu": [to_np(x) for x in s64["mu"]],
+           "u": [to_np(x) for x in s64["u"]], "p": to_np(s64["p"])}
+    del s64
+    _, s32, st32 = run_gpu(W.ternary_drops3d(128, steps=500, **W.PRECISION_FORM_TOLERANCES), 500,
+                           precision=P.CHNS_FP32_REFINE)
+    errs = compare(s32, ref, 3)
+    print({k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert max(errs.values()) <= 1e-5, errs
+    for i in range(3):
+        assert abs(st32["mass_phase"][i] - st64["mass_phase"][i]) <= 1e-12 * st64["mass_phase"][i]
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_ternary_full_size_invariants(precision):
     """The 128^3 three-phase drop configuration in the launch shape the

@@ -604,8 +604,11 @@ def ensemble_stratified(per_size: int = 3, seed: int = 4, sizes=(64, 96, 128, 19
 
 # Solver tolerances of the precision form (FP64 CG with the FP32 multigrid
 # preconditioner): its budget is 1e-5 relative to the FP64 oracle, so the solves
-# stop at these looser relative residuals (measured error ~2e-7).
-PRECISION_FORM_TOLERANCES = dict(rtol_ch=1e-10, rtol_mom=1e-10, rtol_p=1e-9)
+# stop at these looser relative residuals.  Over the 500 steps of the 128^3
+# three-phase drops the state stays within 1.5e-8 of the FP64 run at the
+# parity tolerances (1e-9 / 1e-8 for momentum / pressure: 2.3e-7 with 1e-8 /
+# 1e-7, 1.3e-5 with 1e-8 / 1e-6), three orders of magnitude inside the budget.
+PRECISION_FORM_TOLERANCES = dict(rtol_ch=1e-10, rtol_mom=1e-9, rtol_p=1e-8)
 
 
 def problem_by_name(name: str) -> Problem:
