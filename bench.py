@@ -425,6 +425,7 @@ def bench_hbm_sweeps(P, W, hbm_shapes):
         del phi
         p = torch.zeros_like(rho)
         g.solve_pressure(rho, rhs, p, rtol=1e-10, max_iter=200)    # warm-up (first-use costs)
+        _progress("hbm_sweeps %s: warm-up solve done" % key)
         p.zero_()
         _sync()
         g.set_timing(True)
@@ -441,6 +442,12 @@ def bench_hbm_sweeps(P, W, hbm_shapes):
     return out
 
 
+def _progress(msg):
+    """One line on stderr when a phase of the run ends (profiled runs are slow
+    and print their JSON line only at the end)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def bench_batched(P, W, steps, form="auto", cpu_problems=0):
     """Batched ensemble: 512 problems, precision form; autotuned form and
     launch shape (or a fixed one); timed eagerly (solves run to convergence
@@ -450,6 +457,7 @@ def bench_batched(P, W, steps, form="auto", cpu_problems=0):
     probs = W.ensemble(count=512, seed=4, steps=200, **W.PRECISION_FORM_TOLERANCES)
     b = P.create_batch(probs, P.CHNS_FP32_REFINE, device="cuda:0")
     st = b.new_state([W.initial_state(p) for p in probs])
+    _progress("batched: %d problems created" % len(probs))
     out = {"workload": "ensemble_512_oscillating_drops_fp32_refine", "problems": len(probs),
            "cells": b.total_cells, "steps": steps}
     if form == "auto":
@@ -467,9 +475,11 @@ def bench_batched(P, W, steps, form="auto", cpu_problems=0):
     for label, graph in (("eager", False), ("graph", True)):
         b.step(st, steps, use_graph=graph, stats=False)     # warm-up (and capture)
         _sync()
+        _progress("batched: %s warm-up done" % label)
         t0 = time.perf_counter()
         stats = b.step(st, steps, use_graph=graph, stats=True)
         dt = time.perf_counter() - t0
+        _progress("batched: %s steps done" % label)
         tot = sum(s["total_iters"] for s in stats)
         out[label] = {"value": round(b.total_cells * steps / dt, 1), "ms_per_step": round(dt / steps * 1e3, 3),
                       "pcg_iterations_per_problem_step": round(tot / (len(probs) * steps), 2),
@@ -628,6 +638,7 @@ def main():
             if name not in forms:
                 continue
             g, st, t = timed_run(P, pr, prec, args.warmup, args.steps, args.serial_components)
+            _progress("headline %s: timed steps done" % name)
             stats = g.step(st, 1)     # outside the timed region: solver statistics and diagnostics
             legs[name] = {"value": round(prob.cells * args.steps / t["wall"], 1),
                           "ms_per_step": round(t["wall"] / args.steps * 1e3, 4),
@@ -682,6 +693,7 @@ def main():
             if name in extras:
                 torch.cuda.empty_cache()
                 secondary[name] = runs[name]()
+                _progress("%s done" % name)
         out["secondary"] = secondary
     print(json.dumps(out), flush=True)
 
