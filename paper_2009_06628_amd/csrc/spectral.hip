@@ -471,10 +471,10 @@ __global__ void __launch_bounds__(kBlock) k_spectral_scale(Geo g, const double *
 // and back x_j = Re sum_{k <= m} c_k e^{+2 pi i k j / n} with
 // c_0 = mode 0 / sqrt(n), c_k = sqrt(2/n) (mode 2k-1 - i mode 2k),
 // c_m = mode n-1 / sqrt(n): O(log n) operations per value where the basis
-// product takes O(n).  A 256-thread workgroup takes P = 2048 / n pencils into
-// LDS and runs the log2 n radix-2 stages: decimation in time on
-// bit-reversed input for the forward transform, decimation in frequency
-// with bit-reversed output for the inverse.
+// product takes O(n).  A 256-thread workgroup takes P = 2048 / n complex
+// pencils (each two real ones) into LDS and runs the log2 n radix-2 stages:
+// decimation in time on bit-reversed input for the forward transform,
+// decimation in frequency with bit-reversed output for the inverse.
 // MODE 0: forward; 1: inverse; 2: forward, division by 1 - a lam + b lam^2,
 // inverse (the last axis of the solve, whose pencils carry every mode of the
 // other axes).  Pencil q of an axis: element j at
@@ -592,94 +592,138 @@ struct FftIo {
     double *out[2];
 };
 
+// Two real pencils share one complex transform: pencil p of the workgroup's
+// first half is the real part and pencil p + P the imaginary part of complex
+// slot p, so a workgroup transforms 2P = 4096 / n real pencils with P complex
+// ones.  Forward, the spectra separate as X_k = (Z_k + conj Z_(n-k)) / 2 and
+// Y_k = (Z_k - conj Z_(n-k)) / 2i; backward, the two Hermitian spectra are
+// joined as Z = X + i Y and the real and imaginary parts of the result are
+// the two pencils.
 template <int LOGN, int MODE>
 __global__ void __launch_bounds__(kBlock) k_axis_fft(FftAxis ax, FftIo io, FftScale sc) {
     const double *__restrict__ in = io.in[blockIdx.y];
     double *__restrict__ out = io.out[blockIdx.y];
     using L = FftLds<LOGN>;
-    constexpr int n = L::n, m = n / 2, P = L::P;
+    constexpr int n = L::n, m = n / 2, P = L::P, P2 = 2 * P;
     __shared__ double re[P * L::W], im[P * L::W], tws[2 * n];
-    __shared__ long long base[P];
-    const int tid = (int)threadIdx.x, q0 = (int)blockIdx.x * P;
+    __shared__ long long base[P2];
+    const int tid = (int)threadIdx.x, q0 = (int)blockIdx.x * P2;
     const double s0 = 1.0 / sqrt((double)n), s1 = sqrt(2.0 / (double)n);
     for (int i = tid; i < 2 * n; i += kBlock) tws[i] = ax.tw[i];
-    if (tid < P) {
+    if (tid < P2) {
         const int q = q0 + tid;
         base[tid] = (long long)(q / ax.nin) * ax.ostride + q % ax.nin;
     }
     __syncthreads();
-    auto at = [&](int p, int j) { return base[p] + (long long)j * ax.nb; };
-    // element e of the workgroup's pencils: the index contiguous in memory
+    auto at = [&](int pp, int j) { return base[pp] + (long long)j * ax.nb; };
+    auto valid = [&](int pp) { return q0 + pp < ax.npen; };
+    // element e of the workgroup's 2P pencils: the index contiguous in memory
     // runs fastest across the threads
-    auto split = [&](int e, int &p, int &j) {
+    auto split = [&](int e, int &pp, int &j) {
         if (ax.nb == 1) {
-            p = e / n;
+            pp = e / n;
             j = e % n;
         } else {
-            j = e / P;
-            p = e % P;
+            j = e / P2;
+            pp = e % P2;
         }
     };
     auto brev = [](int j) { return (int)(__brev((unsigned)j) >> (32 - LOGN)); };
-    for (int e = tid; e < P * n; e += kBlock) {
-        int p, j;
-        split(e, p, j);
-        const bool ok = q0 + p < ax.npen;
-        double vr = 0.0, vi = 0.0;
-        if (MODE != 1) {
-            if (ok) vr = in[at(p, j)];
-            re[L::at(p, brev(j))] = vr;
-            im[L::at(p, brev(j))] = 0.0;
-        } else {
-            if (ok && j <= m) {   // j is the frequency k
-                if (j == 0) {
-                    vr = s0 * in[at(p, 0)];
-                } else if (j == m) {
-                    vr = s0 * in[at(p, n - 1)];
+    if (MODE != 1) {
+        // pencil pp into the real (pp < P) or imaginary part of slot pp mod P,
+        // bit-reversed for the decimation-in-time forward transform
+        for (int e = tid; e < P2 * n; e += kBlock) {
+            int pp, j;
+            split(e, pp, j);
+            const double v = valid(pp) ? in[at(pp, j)] : 0.0;
+            double *part = pp < P ? re : im;
+            part[L::at(pp < P ? pp : pp - P, brev(j))] = v;
+        }
+    } else {
+        // the half spectra c_k, d_k of pencils p and p + P (c_0, c_m real;
+        // c_k = s1 (mode 2k-1 - i mode 2k)) as the full spectrum
+        // Z_k = C_k + i D_k, with C_k = c_k / 2 and C_(n-k) = conj(c_k) / 2
+        // for 0 < k < m
+        for (int e = tid; e < P * (m + 1); e += kBlock) {
+            const int p = e % P, k = e / P;
+            double cr = 0.0, ci = 0.0, dr = 0.0, di = 0.0;
+            auto coef = [&](int pp, double &vr, double &vi) {
+                if (!valid(pp)) return;
+                if (k == 0) {
+                    vr = s0 * in[at(pp, 0)];
+                } else if (k == m) {
+                    vr = s0 * in[at(pp, n - 1)];
                 } else {
-                    vr = s1 * in[at(p, 2 * j - 1)];
-                    vi = -s1 * in[at(p, 2 * j)];
+                    vr = s1 * in[at(pp, 2 * k - 1)];
+                    vi = -s1 * in[at(pp, 2 * k)];
                 }
+            };
+            coef(p, cr, ci);
+            coef(p + P, dr, di);
+            if (k == 0 || k == m) {
+                re[L::at(p, k)] = cr;
+                im[L::at(p, k)] = dr;
+            } else {
+                re[L::at(p, k)] = 0.5 * (cr - di);
+                im[L::at(p, k)] = 0.5 * (ci + dr);
+                re[L::at(p, n - k)] = 0.5 * (cr + di);
+                im[L::at(p, n - k)] = 0.5 * (dr - ci);
             }
-            re[L::at(p, j)] = vr;
-            im[L::at(p, j)] = vi;
         }
     }
     __syncthreads();
     if (MODE != 1) fft_run<LOGN, true>(re, im, tws, -1.0);
     if (MODE == 0) {
-        for (int e = tid; e < P * n; e += kBlock) {
-            int p, c;
-            split(e, p, c);
-            if (q0 + p >= ax.npen) continue;
-            const int k = c == n - 1 ? m : (c + 1) / 2;
-            const double v = c == 0 || c == n - 1 ? s0 * re[L::at(p, k)]
-                                                  : ((c & 1) ? s1 * re[L::at(p, k)] : -s1 * im[L::at(p, k)]);
-            out[at(p, c)] = v;
+        for (int e = tid; e < P2 * n; e += kBlock) {
+            int pp, c;
+            split(e, pp, c);
+            if (!valid(pp)) continue;
+            const int p = pp < P ? pp : pp - P, k = c == n - 1 ? m : (c + 1) / 2, kn = (n - k) & (n - 1);
+            const double zr = re[L::at(p, k)], zi = im[L::at(p, k)];
+            const double wr = re[L::at(p, kn)], wi = im[L::at(p, kn)];
+            // X_k of pencil p (pp < P) or Y_k of pencil p + P
+            const double xr = pp < P ? 0.5 * (zr + wr) : 0.5 * (zi + wi);
+            const double xi = pp < P ? 0.5 * (zi - wi) : 0.5 * (wr - zr);
+            const double v = c == 0 || c == n - 1 ? s0 * xr : ((c & 1) ? s1 * xr : -s1 * xi);
+            out[at(pp, c)] = v;
         }
         return;
     }
     if (MODE == 2) {
-        // c_k = f_k X_k / (1 - a lam + b lam^2), f = 1 / n at k = 0, m, else 2 / n
+        // X_k, Y_k of the slot's two pencils divided by 1 - a lam + b lam^2
+        // (with the inverse's 1 / n), joined again as Z_k = X_k + i Y_k and
+        // Z_(n-k) = conj X_k + i conj Y_k
         const double inv_n = 1.0 / (double)n;
-        for (int e = tid; e < P * n; e += kBlock) {
-            const int p = e / n, k = e % n, q = q0 + p;
-            double f = 0.0;
-            if (k <= m && q < ax.npen) {
-                const double lxy = sc.ly ? sc.lx[q % sc.nx] + sc.ly[q / sc.nx] : sc.lx[q];
-                const double lam = lxy + sc.lz[k == 0 ? 0 : (k == m ? n - 1 : 2 * k - 1)];
-                f = (k == 0 || k == m ? inv_n : 2.0 * inv_n) / (1.0 - sc.a * lam + sc.b * lam * lam);
+        auto gain = [&](int pp, int k) {
+            const int q = q0 + pp;
+            if (q >= ax.npen) return 0.0;
+            const double lxy = sc.ly ? sc.lx[q % sc.nx] + sc.ly[q / sc.nx] : sc.lx[q];
+            const double lam = lxy + sc.lz[k == 0 ? 0 : (k == m ? n - 1 : 2 * k - 1)];
+            return inv_n / (1.0 - sc.a * lam + sc.b * lam * lam);
+        };
+        for (int e = tid; e < P * (m + 1); e += kBlock) {
+            const int p = e % P, k = e / P, kn = (n - k) & (n - 1);
+            const double zr = re[L::at(p, k)], zi = im[L::at(p, k)];
+            const double wr = re[L::at(p, kn)], wi = im[L::at(p, kn)];
+            const double gx = gain(p, k), gy = gain(p + P, k);
+            const double xr = gx * (0.5 * (zr + wr)), xi = gx * (0.5 * (zi - wi));
+            const double yr = gy * (0.5 * (zi + wi)), yi = gy * (0.5 * (wr - zr));
+            re[L::at(p, k)] = xr - yi;
+            im[L::at(p, k)] = xi + yr;
+            if (kn != k) {
+                re[L::at(p, kn)] = xr + yi;
+                im[L::at(p, kn)] = yr - xi;
             }
-            re[L::at(p, k)] *= f;
-            im[L::at(p, k)] *= f;
         }
         __syncthreads();
     }
     fft_run<LOGN, false>(re, im, tws, 1.0);
-    for (int e = tid; e < P * n; e += kBlock) {
-        int p, j;
-        split(e, p, j);
-        if (q0 + p < ax.npen) out[at(p, j)] = re[L::at(p, brev(j))];
+    for (int e = tid; e < P2 * n; e += kBlock) {
+        int pp, j;
+        split(e, pp, j);
+        if (!valid(pp)) continue;
+        const int p = pp < P ? pp : pp - P;
+        out[at(pp, j)] = pp < P ? re[L::at(p, brev(j))] : im[L::at(p, brev(j))];
     }
 }
 
@@ -709,8 +753,8 @@ static FftAxis fft_axis_of(const Spectral &S, int a) {
 
 template <int LOGN>
 static void fft_launch(const FftAxis &ax, int mode, const FftIo &io, int nf, const FftScale &sc, hipStream_t st) {
-    constexpr int P = 2048 >> LOGN;
-    const dim3 grid((ax.npen + P - 1) / P, nf);
+    constexpr int P2 = 4096 >> LOGN;   // real pencils per workgroup
+    const dim3 grid((ax.npen + P2 - 1) / P2, nf);
     if (mode == 0)
         hipLaunchKernelGGL((k_axis_fft<LOGN, 0>), grid, dim3(kBlock), 0, st, ax, io, sc);
     else if (mode == 1)

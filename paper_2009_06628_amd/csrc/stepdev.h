@@ -19,6 +19,15 @@ __device__ inline double pullback(double p) { return fabs(p) <= 1.0 ? p : copysi
 // derivative of the pull-back (1 inside (-1, 1), 0 outside)
 __device__ inline double dpullback(double p) { return fabs(p) < 1.0 ? 1.0 : 0.0; }
 
+// Store marked non-temporal (streamed past the L2): a pass that writes
+// many arrays which no kernel reads back while they would still be in the
+// L2 keeps the L2 for the input planes its stencils read again (the
+// momentum set-up writes 15 arrays per cell: 198 -> 163 us at 128^3).
+template <typename T>
+__device__ inline void st_nt(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+
 #define CELL_LOOP(N) \
     for (int c = xcd_block() * (int)blockDim.x + (int)threadIdx.x; c < (int)(N); c += (int)(gridDim.x * blockDim.x))
 
@@ -191,12 +200,12 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
     const double *ua = u.a[a];
     if (!g.per[a] && ia[a] == 0) {
         // wall face of a walled axis: decoupled identity row, u = 0
-        s[c] = 1.0;
+        st_nt(&s[c], 1.0);
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) cs.a[b][c] = 0.0;
+        for (int b = 0; b < DIM; ++b) st_nt(&cs.a[b][c], 0.0);
         if (!coef_only) {
-            rhs[c] = 0.0;
-            if (ustar) ustar[c] = 0.0;
+            st_nt(&rhs[c], 0.0);
+            if (ustar) st_nt(&ustar[c], 0.0);
         }
         return;
     }
@@ -220,7 +229,7 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
                 w = 0.0;
             }
             if (!g.per[a] && ia[a] == g.n[a] - 1) sd += e_c * rvis;   // upper wall face
-            cs.a[b][c] = w;
+            st_nt(&cs.a[b][c], w);
             // skew advection, b == a
             const double m_c = mflux_mix<DIM>(g, mx, u.a[a], a, c, ia[a]);
             const double m_hi = hi >= 0 ? mflux_mix<DIM>(g, mx, u.a[a], a, hi, wrap_next(ia[a], g.n[a])) : 0.0;
@@ -234,9 +243,9 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
             if (lo >= 0) {
                 const int lam = nb_lo(g, lo, ia[a], a);   // c - e_b - e_a
                 const double ee = 0.25 * (((e_c + e_am) + eta_of(lo)) + eta_of(lam));
-                cs.a[b][c] = (!g.per[b] && ia[b] == 0) ? 0.0 : ee * rvis;
+                st_nt(&cs.a[b][c], (!g.per[b] && ia[b] == 0) ? 0.0 : ee * rvis);
             } else {
-                cs.a[b][c] = 0.0;
+                st_nt(&cs.a[b][c], 0.0);
             }
             if (!g.per[b] && ia[b] == 0) {
                 sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
@@ -266,10 +275,10 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
                   : (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
     if (a == 1 && k.inv_Fr != 0.0) f -= rf_new * k.inv_Fr;     // g_hat = (0, -1, 0)
     if (WALLS) f += fwall;
-    s[c] = sd;
+    st_nt(&s[c], sd);
     if (!coef_only) {
-        rhs[c] = f;
-        if (ustar) ustar[c] = ua[c];   // null: the guess is written by k_velocity_guess
+        st_nt(&rhs[c], f);
+        if (ustar) st_nt(&ustar[c], ua[c]);   // null: the guess is written by k_velocity_guess
     }
 }
 

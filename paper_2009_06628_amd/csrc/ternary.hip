@@ -230,15 +230,16 @@ __global__ void __launch_bounds__(kBlock) k_phi_update3(Geo g, StepConst k, cons
             }
         }
         const double q1 = p1 - k.dt * (div1 * k.ih), q2 = p2 - k.dt * (div2 * k.ih);
-        pn1[c] = q1;
-        pn2[c] = q2;
+        // seven arrays written past the L2 (128^3: 71 -> 55 us)
+        st_nt(&pn1[c], q1);
+        st_nt(&pn2[c], q2);
         // the cell fields of MixPre: rho^{n+1}, rho^n (pull-back), eta^{n+1},
         // rho_lin^n and chi = (kM/2) sum_{i=1,2} (rho_i - rho_3) mu~_i
-        fields.a[0][c] = Mix3::mixc(mx.rho, q1, q2);
-        fields.a[1][c] = Mix3::mixc(mx.rho, p1, p2);
-        fields.a[2][c] = Mix3::mixc(mx.eta, q1, q2);
-        fields.a[3][c] = mx.rho_lin(c);
-        fields.a[4][c] = mx.jc[0] * m1 + mx.jc[1] * m2;
+        st_nt(&fields.a[0][c], Mix3::mixc(mx.rho, q1, q2));
+        st_nt(&fields.a[1][c], Mix3::mixc(mx.rho, p1, p2));
+        st_nt(&fields.a[2][c], Mix3::mixc(mx.eta, q1, q2));
+        st_nt(&fields.a[3][c], mx.rho_lin(c));
+        st_nt(&fields.a[4][c], mx.jc[0] * m1 + mx.jc[1] * m2);
     }
 }
 

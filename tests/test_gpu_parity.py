@@ -373,12 +373,13 @@ def _fft_case(case):
                                                           dict(drops, velocity="potential3d"), steps=4),
             "ternary_32x32x24": lambda: W.ternary_problem((32, 32, 24), "ternary_drops",
                                                           dict(drops, velocity="potential3d"), steps=4),
+            "ternary2d_32x16": lambda: W.ternary_problem((32, 16), "ternary_drops", drops, steps=4),
             "bubble2d_64": lambda: W.rising_bubble(64, steps=4),
             "spinodal2d_128": lambda: W.spinodal(128, steps=4)}[case]()
 
 
-@pytest.mark.parametrize("case", ["drops3d_32", "ternary_64x32x16", "ternary_32x32x24", "bubble2d_64",
-                                  "spinodal2d_128"])
+@pytest.mark.parametrize("case", ["drops3d_32", "ternary_64x32x16", "ternary_32x32x24", "ternary2d_32x16",
+                                  "bubble2d_64", "spinodal2d_128"])
 def test_ch_fft_matches_dense_basis(case):
     """The direct CH solve transforms periodic power-of-two axes by radix-2
     FFT (the last axis with the division fused in, when it is one of them)
@@ -387,7 +388,8 @@ def test_ch_fft_matches_dense_basis(case):
     states to rounding after four steps.  Cases: every axis FFT (32^3; 64 x
     32 x 16 with 16 on the fused axis; 2D 128^2), a non-power-of-two last
     axis (32 x 32 x 24: FFT on x, y, dense z and the separate division), a
-    walled axis (bubble: FFT x, dense y)."""
+    walled axis (bubble: FFT x, dense y), and workgroups with fewer pencils
+    than they pair (2D 32 x 16: 16 of 128 and 32 of 256)."""
     P = _lib()
     prob = _fft_case(case)
     init = W.initial_state(prob)
