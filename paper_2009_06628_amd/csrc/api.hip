@@ -428,6 +428,19 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     const StepConst k = step_const(g);
     const chns_props &p = g->props;
     hipStream_t s = g->stream;
+    if (pguess) {
+        // u*^n, component a's last solution, stays in its buffer and becomes
+        // the newest history entry; the oldest entry's buffer takes this
+        // step's solve (the history moves without a copy)
+        for (int a = 0; a < dim; ++a) {
+            double **h = g->uext[a];
+            double *fresh = h[2];
+            h[2] = h[1];
+            h[1] = h[0];
+            h[0] = g->ustar[a];
+            g->ustar[a] = fresh;
+        }
+    }
     const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
     const ChOp ch{p.dt * k.kM * p.S, p.dt * k.kM * p.Cn * p.Cn, k.ih2};
     SolveOut o;
@@ -436,11 +449,13 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     const bool tern = g->nph == 3;
     const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2},
                      {g->mix3[0], g->mix3[1], g->mix3[2], g->mix3[3], g->mix3[4]}};
-    // S1, S2
+    // S1, S2 (a direct S2 solve needs no initial guess phihat = phi)
+    const bool ch_guess = !g->spec.on;
     if (tern)
-        launch_ch_rhs3(dim, geo, k, g->tern, ph, uc, g->rch, g->rch2, g->phihat, g->phihat2, s);
+        launch_ch_rhs3(dim, geo, k, g->tern, ph, uc, g->rch, g->rch2, ch_guess ? g->phihat : nullptr,
+                       ch_guess ? g->phihat2 : nullptr, s);
     else
-        launch_ch_rhs(dim, geo, k, phi, uc, g->rch, g->phihat, s);
+        launch_ch_rhs(dim, geo, k, phi, uc, g->rch, ch_guess ? g->phihat : nullptr, s);
     if (tern && spectral_all_fft(g->spec)) {
         // the two phases' systems share the operator: both go through one
         // set of transform launches (the CG vectors are free until S7)
@@ -500,18 +515,9 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
             if (em[a] != hipSuccess) return;
         }
         double *rhs = a == 0 ? g->rhs : g->mc[a - 1].rhs;
-        // extrapolated guess; after the solve the history moves one step
-        // (the older buffer takes the new solution)
-        double **h = g->uext[a];
-        if (pguess) launch_velocity_guess(geo, g->ustar[a], h, uc[a], pr, g->pext[0], c.s);
+        // extrapolated guess from the history (moved at the top of the step)
+        if (pguess) launch_velocity_guess(geo, g->ustar[a], g->uext[a], uc[a], pr, g->pext[0], c.s);
         em[a] = run_solve_ctx(g, c, 1, OP_SLOT, ch, (const double *)rhs, g->ustar[a], p.rtol_mom, 1 + a, &om[a]);
-        if (pguess && em[a] == hipSuccess) {
-            double *oldest = h[2];
-            h[2] = h[1];
-            h[1] = h[0];
-            h[0] = oldest;
-            em[a] = hipMemcpyAsync(h[0], g->ustar[a], sizeof(double) * geo.N, hipMemcpyDeviceToDevice, c.s);
-        }
         if (em[a] == hipSuccess && a > 0 && concurrent) em[a] = hipEventRecord(g->mc[a - 1].done_ev, c.s);
     };
     // S5..S7 set-up of every component in one pass on the handle's stream
@@ -586,8 +592,7 @@ int forward_core(chns_grid *g, const double *phi, const double *const uc[3], dou
     last.iters_p = o.iters;
     last.res_p = o.rel_res;
     last.unconverged |= o.unconverged ? 16 : 0;
-    remove_mean(geo, pr, g->red, s);
-    if (pguess) HIPCHK(hipMemcpyAsync(g->pext[0], pr, sizeof(double) * geo.N, hipMemcpyDeviceToDevice, s));
+    remove_mean(geo, pr, g->red, s, pguess ? g->pext[0] : nullptr);   // and the newest history entry
     return CHNS_OK;
 }
 
@@ -914,7 +919,6 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
     double *phi2 = g->nph == 3 ? (double *)st->phi2 : nullptr, *mu2 = g->nph == 3 ? (double *)st->mu2 : nullptr;
     double *u[3] = {(double *)st->u[0], (double *)st->u[1], dim == 3 ? (double *)st->u[2] : nullptr};
     const double *uc[3] = {u[0], u[1], u[2]};
-    const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
     int unconv_any = 0;
     chns_step_stats last;
     memset(&last, 0, sizeof last);
@@ -925,6 +929,8 @@ int chns_step(chns_grid *g, chns_state *st, int nsteps, chns_step_stats *stats) 
             continue;
         }
         if (int rc = forward_core(g, phi, uc, mu, pr, last, phi2, mu2, g->pguess && !g->in_record)) return rc;
+        // this step's u* buffers (forward_core may move them with the time guesses)
+        const double *usc[3] = {g->ustar[0], g->ustar[1], g->ustar[2]};
         // S9
         if (g->nph == 3) {
             const Phases3 ph{{phi, phi2}, {g->phi_new, g->phi_new2}, {mu, mu2},

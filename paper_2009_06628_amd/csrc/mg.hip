@@ -1421,12 +1421,17 @@ __global__ void __launch_bounds__(kBlock) k_sum(int N, const T *__restrict__ x, 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// x -= mean(x); copy (when given) receives the same values
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_sub_mean(int N, T *__restrict__ x, const double *__restrict__ part,
-                                                     int nparts) {
+                                                     int nparts, T *__restrict__ copy) {
     __shared__ double lds[kBlock / kWave];
     const double m = sum_parts_all(part, nparts, lds) / (double)N;
-    GRID_LOOP(N) x[c] = (T)((double)x[c] - m);
+    GRID_LOOP(N) {
+        const T v = (T)((double)x[c] - m);
+        x[c] = v;
+        if (copy) copy[c] = v;
+    }
 }
 
 template <typename T, int DIM>
@@ -1976,11 +1981,12 @@ hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kin
 }
 
 template <typename T>
-void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st) {
+void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st, T *copy) {
     const int N = (int)g.N;
     const int nb = grid_red(N);
     LAUNCHR(K_MEAN, sizeof(T) * N, (k_sum<T>), N, st, N, (const T *)x, red.part0);
-    LAUNCHR(K_MEAN, 2.0 * sizeof(T) * N, (k_sub_mean<T>), N, st, N, x, (const double *)red.part0, nb);
+    LAUNCHR(K_MEAN, (copy ? 3.0 : 2.0) * sizeof(T) * N, (k_sub_mean<T>), N, st, N, x, (const double *)red.part0, nb,
+            copy);
 }
 
 template <typename T>
@@ -1998,7 +2004,7 @@ template hipError_t pcg_solve<double>(Slot<double> &, int, OpKind, ChOp, const d
 template void mg_setup<float>(Slot<float> &, int, hipStream_t, bool);
 template hipError_t pcg_solve<float>(Slot<float> &, int, OpKind, ChOp, const float *, float *, double, int, int,
                                      Red &, PcgVecs<float> &, hipStream_t, SolveOut *, int);
-template void remove_mean<double>(const Geo &, double *, Red &, hipStream_t);
+template void remove_mean<double>(const Geo &, double *, Red &, hipStream_t, double *);
 template void slot_apply<double>(Slot<double> &, int, const double *, double *, hipStream_t);
 
 }  // namespace chns

@@ -75,8 +75,9 @@ hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kin
 
 // Subtract the mean of a cell array (deterministic).  Used for the
 // singular pressure system (right-hand side, then the solution gauge).
+// copy (when given) receives the result as well.
 template <typename T>
-void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st);
+void remove_mean(const Geo &g, T *x, Red &red, hipStream_t st, T *copy = nullptr);
 
 // Apply the slot operator at level 0: y = A x (tests / residual checks).
 template <typename T>

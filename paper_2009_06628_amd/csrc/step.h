@@ -43,7 +43,7 @@ struct Phases3 {
     double *mix[5];   // per-step mixture fields: rho^{n+1}, rho^n, eta^{n+1}, rho_lin^n, chi
 };
 
-// T1: r_i and phihat_i = phi_i for i = 1, 2.
+// T1: r_i and phihat_i = phi_i for i = 1, 2 (hat1 / hat2 null: not written).
 void launch_ch_rhs3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                     const double *const u[3], double *r1, double *r2, double *hat1, double *hat2, hipStream_t st);
 // T3: mu~_i from phihat_i.
@@ -95,7 +95,8 @@ void launch_cn_finish(int dim, const Geo &g, const double *const vt[3], double *
                       const double *phin, hipStream_t st);
 void launch_cn_zero(const Geo &g, double *x, hipStream_t st);
 
-// S1: r = phi - dt D(u A phi) + dt kM L(psi'(phi) - S phi); phihat = phi.
+// S1: r = phi - dt D(u A phi) + dt kM L(psi'(phi) - S phi); phihat = phi
+// (phihat null: not written).
 void launch_ch_rhs(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3],
                    double *r, double *phihat, hipStream_t st);
 // S3: mu = psi'(phi) + S (phihat - phi) - Cn^2 L phihat.

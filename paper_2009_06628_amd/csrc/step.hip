@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geo g, StepConst k, const doubl
 
 void launch_ch_rhs(int dim, const Geo &g, const StepConst &k, const double *phi, const double *const u[3], double *r,
                    double *phihat, hipStream_t st) {
-    DISPATCH(K_CH_RHS, 3 + dim, dim, k_ch_rhs, g.N, st, g, k, phi, mk_u3(u), r, phihat);
+    DISPATCH(K_CH_RHS, (phihat ? 3 : 2) + dim, dim, k_ch_rhs, g.N, st, g, k, phi, mk_u3(u), r, phihat);
 }
 void launch_mu(int dim, const Geo &g, const StepConst &k, const double *phi, const double *phihat, double *mu,
                hipStream_t st) {

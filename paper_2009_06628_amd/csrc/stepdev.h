@@ -128,7 +128,7 @@ __device__ inline void ch_rhs_cell(const Geo &g, const StepConst &k, const doubl
         div += fhi - flo;
     }
     r[c] = pc - k.dt * (div * k.ih) + k.dt * k.kM * (lap * k.ih2);
-    phihat[c] = pc;
+    if (phihat) phihat[c] = pc;   // the guess of an iterative S2 solve (null: direct solve)
 }
 
 // S3: mu = psi'(phi) + S (phihat - phi) - Cn^2 L phihat

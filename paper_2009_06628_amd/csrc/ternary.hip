@@ -162,8 +162,10 @@ __global__ void __launch_bounds__(kBlock) k_ch_rhs3(Geo g, StepConst k, TernCons
         }
         r1[c] = p1 - k.dt * (div1 * k.ih) + k.dt * k.kM * (lap1 * k.ih2);
         r2[c] = p2 - k.dt * (div2 * k.ih) + k.dt * k.kM * (lap2 * k.ih2);
-        ph1[c] = p1;
-        ph2[c] = p2;
+        if (ph1) {   // the guesses of iterative T2 solves (null: direct solve)
+            ph1[c] = p1;
+            ph2[c] = p2;
+        }
     }
 }
 
@@ -374,7 +376,8 @@ TernConst tern_const_of(const chns_props &p) {
 
 void launch_ch_rhs3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph,
                     const double *const u[3], double *r1, double *r2, double *hat1, double *hat2, hipStream_t st) {
-    DISPATCH(K_CH_RHS, 6 + dim, dim, k_ch_rhs3, g.N, st, g, k, t, ph.phi[0], ph.phi[1], mk_u3(u), r1, r2, hat1, hat2);
+    DISPATCH(K_CH_RHS, (hat1 ? 6 : 4) + dim, dim, k_ch_rhs3, g.N, st, g, k, t, ph.phi[0], ph.phi[1], mk_u3(u), r1, r2,
+             hat1, hat2);
 }
 
 void launch_mu3(int dim, const Geo &g, const StepConst &k, const TernConst &t, const Phases3 &ph, const double *hat1,
