@@ -299,12 +299,14 @@ struct SolveCtx {
 };
 
 // Rebuild the hierarchy of a solve from the level-0 coefficients just
-// written by the set-up kernels (momentum, pressure), on c.s.
-static void hierarchy_setup(chns_grid *g, const SolveCtx &c) {
+// written by the set-up kernels (momentum, pressure), on c.s.  skip0: the
+// level-0 arrays of the preconditioner (1 / diag, the FP32 copies) are
+// written by the CG init pass instead.
+static void hierarchy_setup(chns_grid *g, const SolveCtx &c, bool skip0 = false) {
     if (g->prec == CHNS_FP64) {
-        mg_setup(*c.S64, g->dim, c.s);
+        mg_setup(*c.S64, g->dim, c.s, !skip0);
     } else {
-        convert_level0(*c.S64, *c.S32, g->dim, c.s);
+        if (!skip0) convert_level0(*c.S64, *c.S32, g->dim, c.s);
         mg_setup(*c.S32, g->dim, c.s, false);
     }
 }
@@ -330,17 +332,21 @@ hipError_t run_solve_ctx(chns_grid *g, const SolveCtx &c, int setup, OpKind kind
     Slot<double> &S64 = *c.S64;
     PcgVecs<double> v = c.v;
     Red red = c.red;
-    if (setup) hierarchy_setup(g, c);
+    // a cycle that ends on the grid itself (the momentum operator when its
+    // shift dominates) needs only the level-0 arrays, which the CG init pass
+    // writes from the coefficients it reads anyway
+    const int conv0 = setup && kind == OP_SLOT && S64.ltrunc == 0 ? 1 : 0;
+    if (setup) hierarchy_setup(g, c, conv0 != 0);
     if (g->prec == CHNS_FP64) {
         hipError_t e = pcg_solve(S64, g->dim, kind, ch, b, x, rtol, g->props.max_iter, next_predict(g->last_iters[pidx]),
-                                 red, v, c.s, o);
+                                 red, v, c.s, o, 0, conv0);
         g->last_iters[pidx] = o->iters;
         return e;
     }
     Slot<float> &S32 = *c.S32;
     const PcgVecs2<double, float> v2{v.r, v.p0, v.p1, v.q, v.t, c.f_z, c.f_t, c.f_r};
     return refine_solve(S64, S32, g->dim, kind, ch, b, x, rtol, g->props.max_iter, &g->last_inner[pidx], red, v2,
-                        c.s, o);
+                        c.s, o, conv0);
 }
 
 // The handle's own buffers; which: 0 CH, 1 momentum, 2 pressure.

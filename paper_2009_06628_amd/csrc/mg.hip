@@ -1298,12 +1298,17 @@ __global__ void __launch_bounds__(kBlock) k_gs_red_rz(Level<T> L, const TB *__re
 }
 
 // r = b - A x (slot operator); partials of b.b and r.r; rp (when given):
-// r rounded to the preconditioner's precision
+// r rounded to the preconditioner's precision.  conv: also the level-0
+// arrays of the preconditioner's hierarchy B that the set-up would write
+// (a cycle that ends on the grid needs nothing else): 1 / diag, and for a
+// lower precision the rounded s and cs[b], with the arithmetic and order of
+// k_invd / k_conv_coef (bit for bit).
 template <typename T, int DIM, typename TP = T>
 __global__ void __launch_bounds__(kBlock) k_pcg_init_slot(Level<T> L, const T *__restrict__ b,
                                                           const T *__restrict__ x, T *__restrict__ r,
                                                           double *__restrict__ p0, double *__restrict__ p1,
-                                                          TP *__restrict__ rp) {
+                                                          TP *__restrict__ rp, Level<TP> B, int conv) {
+    constexpr bool kSame = std::is_same<T, TP>::value;
     __shared__ double lds[kBlock / kWave];
     double bb = 0.0, rr = 0.0;
     GRID_LOOP(L.g.N) {
@@ -1315,6 +1320,20 @@ __global__ void __launch_bounds__(kBlock) k_pcg_init_slot(Level<T> L, const T *_
         if (rp) rp[c] = (TP)(T)rc;   // the preconditioner's copy (k_round_vec's value)
         bb += bc * bc;
         rr += rc * rc;
+        if (conv) {
+            const TP sv = (TP)L.s[c];
+            if (!kSame) B.s[c] = sv;
+            TP d = sv;
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) {
+                const TP w = (TP)L.cs[q][c];
+                if (!kSame) B.cs[q][c] = w;
+                if (nb_lo(L.g, c, ia[q], q) >= 0) d += w;
+                const int hi = nb_hi(L.g, c, ia[q], q);
+                if (hi >= 0) d += (TP)L.cs[q][hi];
+            }
+            B.invd[c] = (TP)1 / d;
+        }
     }
     const double s0 = block_sum(bb, lds);
     const double s1 = block_sum(rr, lds);
@@ -1771,7 +1790,7 @@ static void precond_cg_d(Slot<TP> &SP, OpKind kind, const TP *r, TP *z, TP *w, c
 template <typename T, typename TP, int DIM>
 static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T *b, T *x, double rtol, int max_iter,
                         int predict, Red &red, const PcgVecs2<T, TP> &v, hipStream_t st, SolveOut *out,
-                        int zero_guess) {
+                        int zero_guess, int conv0 = 0) {
     constexpr double W = sizeof(T);
     constexpr double WP = sizeof(TP);
     const Level<T> &L0 = SA.lev[0];
@@ -1785,8 +1804,11 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
         LAUNCHR(K_PCG_INIT, W * 3 * N, (k_pcg_init_zero<T>), N, st, N, b, x, v.r, red.part0, red.part1);
     } else if (kind == OP_SLOT) {
         constexpr bool split = !std::is_same<T, TP>::value;
-        LAUNCHR(K_PCG_INIT, W * (4 + DIM) * N + (split ? WP * N : 0.0), (k_pcg_init_slot<T, DIM, TP>), N, st, L0, b,
-                (const T *)x, v.r, red.part0, red.part1, split ? (TP *)v.rp : (TP *)nullptr);
+        // conv0: the level-0 set-up of SP's cycle rides on this pass
+        const double conv_bytes = conv0 ? (split ? WP * (2 + DIM) : WP) * N : 0.0;
+        LAUNCHR(K_PCG_INIT, W * (4 + DIM) * N + (split ? WP * N : 0.0) + conv_bytes, (k_pcg_init_slot<T, DIM, TP>), N,
+                st, L0, b, (const T *)x, v.r, red.part0, red.part1, split ? (TP *)v.rp : (TP *)nullptr, SP.lev[0],
+                conv0);
     } else {
         LAUNCH(K_PCG_INIT, W * 2 * N, (k_ch_lap_plain<T, DIM>), N, st, g, ch.ih2, (const T *)x, v.t);
         LAUNCHR(K_PCG_INIT, W * 4 * N, (k_pcg_init_ch<T, DIM>), N, st, g, ch.ih2, ch.a, ch.b, b, (const T *)x,
@@ -1914,10 +1936,12 @@ static hipError_t pcg_d(Slot<T> &SA, Slot<TP> &SP, OpKind kind, ChOp ch, const T
 
 template <typename T>
 hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x, double rtol, int max_iter,
-                     int predict, Red &red, PcgVecs<T> &v, hipStream_t st, SolveOut *out, int zero_guess) {
+                     int predict, Red &red, PcgVecs<T> &v, hipStream_t st, SolveOut *out, int zero_guess,
+                     int conv0) {
     const PcgVecs2<T, T> v2{v.r, v.p0, v.p1, v.q, v.t, v.z, v.t, nullptr};
-    if (dim == 2) return pcg_d<T, T, 2>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess);
-    return pcg_d<T, T, 3>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess);
+    if (dim == 2)
+        return pcg_d<T, T, 2>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess, conv0);
+    return pcg_d<T, T, 3>(S, S, kind, ch, b, x, rtol, max_iter, predict, red, v2, st, out, zero_guess, conv0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1964,9 +1988,10 @@ void convert_level0(const Slot<double> &A, Slot<float> &B, int dim, hipStream_t 
 template <int DIM>
 static hipError_t refine_d(Slot<double> &S64, Slot<float> &S32, OpKind kind, ChOp ch, const double *b, double *x,
                            double rtol, int max_iter, int *predict, Red &red, const PcgVecs2<double, float> &v,
-                           hipStream_t st, SolveOut *out) {
+                           hipStream_t st, SolveOut *out, int conv0) {
     SolveOut o;
-    hipError_t e = pcg_d<double, float, DIM>(S64, S32, kind, ch, b, x, rtol, max_iter, *predict, red, v, st, &o, 0);
+    hipError_t e =
+        pcg_d<double, float, DIM>(S64, S32, kind, ch, b, x, rtol, max_iter, *predict, red, v, st, &o, 0, conv0);
     if (e != hipSuccess) return e;
     if (o.iters > 0) *predict = o.iters;
     if (out) *out = o;
@@ -1975,9 +2000,9 @@ static hipError_t refine_d(Slot<double> &S64, Slot<float> &S32, OpKind kind, ChO
 
 hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kind, ChOp ch, const double *b,
                         double *x, double rtol, int max_iter, int *predict, Red &red,
-                        const PcgVecs2<double, float> &v, hipStream_t st, SolveOut *out) {
-    if (dim == 2) return refine_d<2>(S64, S32, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out);
-    return refine_d<3>(S64, S32, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out);
+                        const PcgVecs2<double, float> &v, hipStream_t st, SolveOut *out, int conv0) {
+    if (dim == 2) return refine_d<2>(S64, S32, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out, conv0);
+    return refine_d<3>(S64, S32, kind, ch, b, x, rtol, max_iter, predict, red, v, st, out, conv0);
 }
 
 template <typename T>
@@ -2000,10 +2025,10 @@ void slot_apply(Slot<T> &S, int dim, const T *x, T *y, hipStream_t st) {
 template void mg_setup<double>(Slot<double> &, int, hipStream_t, bool);
 template void mg_vcycle<double>(Slot<double> &, int, const double *, double *, const int *, hipStream_t);
 template hipError_t pcg_solve<double>(Slot<double> &, int, OpKind, ChOp, const double *, double *, double, int, int,
-                                      Red &, PcgVecs<double> &, hipStream_t, SolveOut *, int);
+                                      Red &, PcgVecs<double> &, hipStream_t, SolveOut *, int, int);
 template void mg_setup<float>(Slot<float> &, int, hipStream_t, bool);
 template hipError_t pcg_solve<float>(Slot<float> &, int, OpKind, ChOp, const float *, float *, double, int, int,
-                                     Red &, PcgVecs<float> &, hipStream_t, SolveOut *, int);
+                                     Red &, PcgVecs<float> &, hipStream_t, SolveOut *, int, int);
 template void remove_mean<double>(const Geo &, double *, Red &, hipStream_t, double *);
 template void slot_apply<double>(Slot<double> &, int, const double *, double *, hipStream_t);
 

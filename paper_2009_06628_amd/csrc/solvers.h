@@ -51,11 +51,14 @@ void mg_vcycle(Slot<T> &S, int dim, const T *b0, T *x0, const int *done, hipStre
 // PCG on A x = b (A = slot operator, or the CH operator preconditioned by
 // two V-cycles of the slot).  x is the initial guess on entry.  predict is
 // the number of iterations launched before the first host check.
-// Returns hipSuccess or the first HIP error.
+// Returns hipSuccess or the first HIP error.  conv0: the hierarchy's cycle
+// ends on the grid and its level-0 1 / diag (and, in refine_solve, the FP32
+// copies of s and cs) are written by the CG init pass; the caller skips them
+// in the set-up.
 template <typename T>
 hipError_t pcg_solve(Slot<T> &S, int dim, OpKind kind, ChOp ch, const T *b, T *x, double rtol,
                      int max_iter, int predict, Red &red, PcgVecs<T> &v, hipStream_t st,
-                     SolveOut *out, int zero_guess = 0);
+                     SolveOut *out, int zero_guess = 0, int conv0 = 0);
 
 // Precision form: FP64 conjugate gradients (residual recurrence, operator
 // apply, updates and dot products in FP64) preconditioned by FP32 V-cycles
@@ -71,7 +74,7 @@ constexpr int kMaxRefine = 4;
 void convert_level0(const Slot<double> &A, Slot<float> &B, int dim, hipStream_t st);
 hipError_t refine_solve(Slot<double> &S64, Slot<float> &S32, int dim, OpKind kind, ChOp ch, const double *b,
                         double *x, double rtol, int max_iter, int *predict, Red &red,
-                        const PcgVecs2<double, float> &v, hipStream_t st, SolveOut *out);
+                        const PcgVecs2<double, float> &v, hipStream_t st, SolveOut *out, int conv0 = 0);
 
 // Subtract the mean of a cell array (deterministic).  Used for the
 // singular pressure system (right-hand side, then the solution gauge).
