@@ -187,7 +187,9 @@ __device__ inline void phi_update_cell(const Geo &g, const StepConst &k, const d
 // - (1/We) G p~m (pm) + gravity, where u holds v~m and mx the midpoint
 // mixture; the advection is the advective form (the advective half of the
 // skew-symmetric operator) instead of the skew-symmetric one.
-template <int DIM, typename Mix, bool WALLS = false, bool CN = false>
+// NT: the stores are non-temporal (the grid-wide set-up of every component,
+// whose outputs are read only by later kernels).
+template <int DIM, typename Mix, bool WALLS = false, bool CN = false, bool NT = false>
 __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, const Mix &mx, const U3 &u,
                                       double *__restrict__ s, const W3 &cs, double *__restrict__ rhs,
                                       double *__restrict__ ustar, int coef_only, int c,
@@ -198,14 +200,20 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
     if (DIM == 2) cell_coords2(g, c, i, j, kk); else cell_coords(g, c, i, j, kk);
     const int ia[3] = {i, j, kk};
     const double *ua = u.a[a];
+    auto put = [](double *q, double v) {
+        if (NT)
+            st_nt(q, v);
+        else
+            *q = v;
+    };
     if (!g.per[a] && ia[a] == 0) {
         // wall face of a walled axis: decoupled identity row, u = 0
-        st_nt(&s[c], 1.0);
+        put(&s[c], 1.0);
 #pragma unroll
-        for (int b = 0; b < DIM; ++b) st_nt(&cs.a[b][c], 0.0);
+        for (int b = 0; b < DIM; ++b) put(&cs.a[b][c], 0.0);
         if (!coef_only) {
-            st_nt(&rhs[c], 0.0);
-            if (ustar) st_nt(&ustar[c], 0.0);
+            put(&rhs[c], 0.0);
+            if (ustar) put(&ustar[c], 0.0);
         }
         return;
     }
@@ -229,7 +237,7 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
                 w = 0.0;
             }
             if (!g.per[a] && ia[a] == g.n[a] - 1) sd += e_c * rvis;   // upper wall face
-            st_nt(&cs.a[b][c], w);
+            put(&cs.a[b][c], w);
             // skew advection, b == a
             const double m_c = mflux_mix<DIM>(g, mx, u.a[a], a, c, ia[a]);
             const double m_hi = hi >= 0 ? mflux_mix<DIM>(g, mx, u.a[a], a, hi, wrap_next(ia[a], g.n[a])) : 0.0;
@@ -243,9 +251,9 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
             if (lo >= 0) {
                 const int lam = nb_lo(g, lo, ia[a], a);   // c - e_b - e_a
                 const double ee = 0.25 * (((e_c + e_am) + eta_of(lo)) + eta_of(lam));
-                st_nt(&cs.a[b][c], (!g.per[b] && ia[b] == 0) ? 0.0 : ee * rvis);
+                put(&cs.a[b][c], (!g.per[b] && ia[b] == 0) ? 0.0 : ee * rvis);
             } else {
-                st_nt(&cs.a[b][c], 0.0);
+                put(&cs.a[b][c], 0.0);
             }
             if (!g.per[b] && ia[b] == 0) {
                 sd += 2.0 * (0.5 * (e_c + e_am)) * rvis;
@@ -275,10 +283,10 @@ __device__ inline void mom_setup_body(const Geo &g, const StepConst &k, int a, c
                   : (0.5 * (rf_new + rf_old)) / k.dt * ua[c] - nadv - st;
     if (a == 1 && k.inv_Fr != 0.0) f -= rf_new * k.inv_Fr;     // g_hat = (0, -1, 0)
     if (WALLS) f += fwall;
-    st_nt(&s[c], sd);
+    put(&s[c], sd);
     if (!coef_only) {
-        st_nt(&rhs[c], f);
-        if (ustar) st_nt(&ustar[c], ua[c]);   // null: the guess is written by k_velocity_guess
+        put(&rhs[c], f);
+        if (ustar) put(&ustar[c], ua[c]);   // null: the guess is written by k_velocity_guess
     }
 }
 
@@ -290,7 +298,7 @@ __device__ inline void mom_setup_all_body(const Geo &g, const StepConst &k, cons
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const W3 cs{{o.cs[a][0], o.cs[a][1], o.cs[a][2]}};
-        mom_setup_body<DIM, Mix, WALLS>(g, k, a, mx, u, o.s[a], cs, o.rhs[a], o.ustar[a], 0, c, wv);
+        mom_setup_body<DIM, Mix, WALLS, false, true>(g, k, a, mx, u, o.s[a], cs, o.rhs[a], o.ustar[a], 0, c, wv);
     }
 }
 
